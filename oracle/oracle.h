@@ -1,0 +1,73 @@
+/* Oracle of the Cartesian cut-cell discrete-velocity method
+ * (Dechriste & Mieussens, "A Cartesian cut cell method for rarefied flow
+ * simulations around moving obstacles", 2015).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, serial-order FP64 CPU
+ * implementation that follows the paper's steps in the paper's order.  Only
+ * the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * may load it.  It shares no code, header, table or helper with the solver
+ * library; the two meet only through the seeded inputs.
+ *
+ * Layout of the oracle's own arrays: cell c = (k*ny + j)*nx + i, velocity
+ * p = (p3*N + p2)*N + p1, f[c*nvel + p].  2D carries f and g; 3D carries F.
+ *
+ * Status codes: 0 ok, -1 bad argument, -3 geometry rejected (saddle cell,
+ * master search cycle or no gas neighbour), -2 out of memory.
+ */
+#ifndef CCDVM_ORACLE_H
+#define CCDVM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int dim;                 /* 2 or 3 */
+  int n[3];                /* cells per axis (n[2] = 1 in 2D) */
+  double lo[3], hi[3];     /* domain box */
+  int nv;                  /* velocity nodes per axis */
+  double vmin, vmax;       /* velocity box, same on every axis */
+  double kn, lref;         /* Knudsen number (<= 0: collisionless), length */
+  double cfl, dt;          /* dt <= 0: dt from cfl */
+  double inflow[5];        /* rho, ux, uy, uz, T of the farfield Maxwellian */
+  int body_kind;           /* 0 none 1 circle 2 ellipse 3 cavity 4 halfplane 5 sphere */
+  double center[3], axes[3], theta, t_wall;
+  double mass, inertia;
+  int motion;              /* 0 fixed 1 free rotation 2 imposed */
+  double vel[3], omega;    /* rigid body velocity at t = 0 */
+} orc_cfg;
+
+typedef struct orc2d orc2d;
+
+int  orc2d_create(const orc_cfg *cfg, orc2d **out);
+void orc2d_destroy(orc2d *o);
+double orc2d_dt(const orc2d *o);
+void orc2d_velocity(const orc2d *o, double *v);     /* N nodes */
+/* geometry export: per-cell arrays of length ncell */
+void orc2d_geometry(const orc2d *o, int *type, int *master, double *lxm,
+                    double *lxp, double *lym, double *lyp, double *lw,
+                    double *nwx, double *nwy, double *rwx, double *rwy,
+                    double *sbar, double *scv);
+void orc2d_init(const orc2d *o, double *f, double *g);
+/* in-place merge over control volumes (FusionDD) */
+void orc2d_merge(const orc2d *o, double *f, double *g);
+/* scheme + redistribution for the listed cells (their control volumes);
+   input must be merged.  Output rows are written for the listed cells only,
+   in list order: fo[k*nvel + p]. */
+void orc2d_update_cells(const orc2d *o, const double *fm, const double *gm,
+                        const int *cells, int ncells, double *fo, double *go);
+/* one complete fixed-geometry step: merge, scheme, redistribution.
+   diag (nullable) receives Fx, Fy, torque, mass of the state at t^n. */
+int  orc2d_step(orc2d *o, const double *f, const double *g, double *fo,
+                double *go, double *diag);
+/* force, torque and mass of a merged state */
+void orc2d_force(const orc2d *o, const double *fm, const double *gm, double *diag);
+/* per-cell moments rho, ux, uy, T, Sxx, Sxy, Syy, qx, qy (9 per cell) */
+void orc2d_moments(const orc2d *o, const double *f, const double *g, double *out);
+/* body state: centre (2), theta, velocity (2), omega */
+void orc2d_body_state(const orc2d *o, double *state);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,178 @@
+"""ctypes front of the oracle library (test infrastructure only).
+
+Arrays on this side are numpy float64 of shape (ncell, nvel), the oracle's
+own layout (cell index fastest in x, velocity index fastest in p1).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import build as _build
+
+_BODY = {"none": 0, "circle": 1, "ellipse": 2, "cavity": 3, "halfplane": 4, "sphere": 5}
+_MOTION = {"fixed": 0, "free_rotation": 1, "imposed": 2}
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class _Cfg(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3), ("nv", C.c_int), ("vmin", C.c_double),
+                ("vmax", C.c_double), ("kn", C.c_double), ("lref", C.c_double),
+                ("cfl", C.c_double), ("dt", C.c_double), ("inflow", C.c_double * 5),
+                ("body_kind", C.c_int), ("center", C.c_double * 3),
+                ("axes", C.c_double * 3), ("theta", C.c_double), ("t_wall", C.c_double),
+                ("mass", C.c_double), ("inertia", C.c_double), ("motion", C.c_int),
+                ("vel", C.c_double * 3), ("omega", C.c_double)]
+
+
+def cfg_struct(cfg) -> _Cfg:
+    b = cfg.body
+    s = _Cfg()
+    s.dim = cfg.dim
+    s.n[:] = list(cfg.n)
+    s.lo[:] = list(cfg.lo)
+    s.hi[:] = list(cfg.hi)
+    s.nv = cfg.nv
+    s.vmin, s.vmax = cfg.vmin, cfg.vmax
+    s.kn, s.lref, s.cfl, s.dt = cfg.kn, cfg.lref, cfg.cfl, cfg.dt
+    s.inflow[:] = list(cfg.inflow)
+    s.body_kind = _BODY[b.kind]
+    s.center[:] = list(b.center)
+    s.axes[:] = list(b.axes)
+    s.theta, s.t_wall, s.mass, s.inertia = b.theta, b.t_wall, b.mass, b.inertia
+    s.motion = _MOTION[b.motion]
+    s.vel[:] = list(b.vel)
+    s.omega = b.omega
+    return s
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(_build.ensure_built())
+        P = C.c_void_p
+        _lib.orc2d_create.argtypes = [C.POINTER(_Cfg), C.POINTER(P)]
+        _lib.orc2d_destroy.argtypes = [P]
+        _lib.orc2d_dt.argtypes = [P]
+        _lib.orc2d_dt.restype = C.c_double
+        for name in ("orc2d_velocity", "orc2d_body_state"):
+            getattr(_lib, name).argtypes = [P, P]
+        _lib.orc2d_geometry.argtypes = [P] + [P] * 13
+        _lib.orc2d_init.argtypes = [P, P, P]
+        _lib.orc2d_merge.argtypes = [P, P, P]
+        _lib.orc2d_update_cells.argtypes = [P, P, P, P, C.c_int, P, P]
+        _lib.orc2d_step.argtypes = [P, P, P, P, P, P]
+        _lib.orc2d_force.argtypes = [P, P, P, P]
+        _lib.orc2d_moments.argtypes = [P, P, P, P]
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Oracle2D:
+    """Reduced 2D model: state (f, g), each (ncell, N*N) float64."""
+
+    def __init__(self, cfg):
+        assert cfg.dim == 2
+        self.cfg = cfg
+        self._s = cfg_struct(cfg)
+        h = C.c_void_p()
+        st = lib().orc2d_create(C.byref(self._s), C.byref(h))
+        if st != 0:
+            raise OracleError(f"oracle create failed with status {st}")
+        self._h = h
+        self.nx, self.ny = cfg.n[0], cfg.n[1]
+        self.ncell = self.nx * self.ny
+        self.N = cfg.nv
+        self.nvel = cfg.nv * cfg.nv
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().orc2d_destroy(h)
+            self._h = None
+
+    @property
+    def dt(self) -> float:
+        return lib().orc2d_dt(self._h)
+
+    def velocity(self):
+        v = np.zeros(self.N)
+        lib().orc2d_velocity(self._h, _p(v))
+        return v
+
+    def body_state(self):
+        s = np.zeros(6)
+        lib().orc2d_body_state(self._h, _p(s))
+        return s
+
+    def geometry(self):
+        n = self.ncell
+        out = {"type": np.zeros(n, np.int32), "master": np.zeros(n, np.int32)}
+        names = ["lxm", "lxp", "lym", "lyp", "lw", "nwx", "nwy", "rwx", "rwy", "sbar", "scv"]
+        for k in names:
+            out[k] = np.zeros(n)
+        lib().orc2d_geometry(self._h, _p(out["type"]), _p(out["master"]),
+                             *[_p(out[k]) for k in names])
+        return out
+
+    def _zeros(self):
+        return np.zeros((self.ncell, self.nvel))
+
+    def init(self):
+        f, g = self._zeros(), self._zeros()
+        lib().orc2d_init(self._h, _p(f), _p(g))
+        return f, g
+
+    def merge(self, f, g):
+        f = np.ascontiguousarray(f, dtype=np.float64).copy()
+        g = np.ascontiguousarray(g, dtype=np.float64).copy()
+        lib().orc2d_merge(self._h, _p(f), _p(g))
+        return f, g
+
+    def update_cells(self, fm, gm, cells):
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        fo = np.zeros((cells.size, self.nvel))
+        go = np.zeros((cells.size, self.nvel))
+        lib().orc2d_update_cells(self._h, _p(np.ascontiguousarray(fm)),
+                                 _p(np.ascontiguousarray(gm)), _p(cells),
+                                 int(cells.size), _p(fo), _p(go))
+        return fo, go
+
+    def step(self, f, g):
+        """One step; returns (f1, g1, diag) with diag = (Fx, Fy, torque, mass) of f^n."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        fo, go = self._zeros(), self._zeros()
+        d = np.zeros(4)
+        st = lib().orc2d_step(self._h, _p(f), _p(g), _p(fo), _p(go), _p(d))
+        if st != 0:
+            raise OracleError(f"oracle step failed with status {st}")
+        return fo, go, d
+
+    def run(self, f, g, nsteps):
+        diags = []
+        for _ in range(nsteps):
+            f, g, d = self.step(f, g)
+            diags.append(d)
+        return f, g, np.array(diags).reshape(-1, 4)
+
+    def force(self, fm, gm):
+        d = np.zeros(4)
+        lib().orc2d_force(self._h, _p(np.ascontiguousarray(fm)), _p(np.ascontiguousarray(gm)), _p(d))
+        return d
+
+    def moments(self, f, g):
+        out = np.zeros((self.ncell, 9))
+        lib().orc2d_moments(self._h, _p(np.ascontiguousarray(f)), _p(np.ascontiguousarray(g)), _p(out))
+        return out

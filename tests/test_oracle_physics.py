@@ -1,0 +1,192 @@
+"""Pins of the oracle's step against what the paper and mathematics fix.
+
+* Discrete moments of a sampled Maxwellian reproduce its parameters within
+  the quadrature error of the midpoint velocity grid (Section 3.1).
+* Pure transport without a body is the textbook first-order upwind scheme:
+  f_new = (1 - a - b) f + a f_upwind_x + b f_upwind_y with a = |v_x| dt/dx,
+  b = |v_y| dt/dy, checked per velocity (catches a swapped velocity index).
+* A gas at rest with a wall at the same temperature stays at rest (diffuse
+  wall with zero net mass flux, Section 3.3.1) to round-off without
+  collisions, and to quadrature error with BGK.
+* Mass in a closed cavity with diffuse walls is conserved exactly without
+  collisions (Section 3.4.2) and the BGK relaxation conserves mass,
+  momentum and energy to quadrature error.
+* One full step equals a brute-force face-loop formulation on tiny grids
+  with cut and merged cells.
+* The force on a cylinder in a uniform state (first step) tends to the
+  free-molecular force obtained by integrating the continuous half-range
+  fluxes around the exact circle, and the force of a gas at rest is zero.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import ndtr
+
+from ccdvm_inputs import Body, Config, random_state, small_2d
+from oracle import Oracle2D
+from tests.brute import brute_step
+
+
+def test_moments_of_sampled_maxwellian():
+    for nv, mach, tol in ((16, 0.0, 3e-8), (16, 0.5, 5e-7), (32, 0.8, 5e-6)):
+        cfg = small_2d(4, 4, nv, mach=mach, body=Body("none"))
+        o = Oracle2D(cfg)
+        f, g = o.init()
+        m = o.moments(f, g)
+        rho, ux, uy, T = m[0, :4]
+        assert abs(rho - 1.0) < tol
+        assert abs(ux - cfg.inflow[1]) < tol
+        assert abs(uy) < 1e-15
+        assert abs(T - 1.0) < tol
+        # pressure tensor of a Maxwellian: Sigma = rho T I ; heat flux 0
+        assert abs(m[0, 4] - 1.0) < 5 * tol and abs(m[0, 6] - 1.0) < 5 * tol
+        assert abs(m[0, 5]) < 1e-14 and abs(m[0, 8]) < 1e-14
+        assert abs(m[0, 7]) < 10 * tol
+
+
+def test_pure_upwind_transport_closed_form():
+    nx, ny = 6, 5
+    cfg = Config(dim=2, n=(nx, ny, 1), lo=(0, 0, 0), hi=(1, 1, 1), nv=2, vmin=-2.0,
+                 vmax=2.0, kn=0.0, dt=0.04, body=Body("none"))
+    o = Oracle2D(cfg)
+    v = o.velocity()
+    assert np.allclose(v, [-1.0, 1.0])
+    f, g = random_state(nx * ny, 2, 2, seed=3)
+    f1, g1, _ = o.step(f, g)
+    a, b = 0.04 * nx, 0.04 * ny
+    for j in range(1, ny - 1):
+        for i in range(1, nx - 1):
+            c = j * nx + i
+            for p in range(4):
+                vx, vy = v[p % 2], v[p // 2]
+                cx = c - 1 if vx > 0 else c + 1
+                cy = c - nx if vy > 0 else c + nx
+                for arr, new in ((f, f1), (g, g1)):
+                    expect = (1 - a - b) * arr[c, p] + a * arr[cx, p] + b * arr[cy, p]
+                    assert new[c, p] == pytest.approx(expect, rel=1e-14, abs=1e-17)
+
+
+@pytest.mark.parametrize("kn,tol", [(0.0, 1e-14), (0.1, 2e-9)])
+def test_rest_state_with_isothermal_wall_is_stationary(kn, tol):
+    cfg = small_2d(32, 32, 16, kn=kn, mach=0.0)
+    o = Oracle2D(cfg)
+    f, g = o.init()
+    f1, g1, d = o.step(f, g)
+    assert np.max(np.abs(f1 - f)) / np.max(f) < tol
+    assert np.max(np.abs(g1 - g)) / np.max(g) < tol
+    # zero force and torque at rest (closure of every virtual cell and of the
+    # polygon of wall chords)
+    assert abs(d[0]) < 1e-14 and abs(d[1]) < 1e-14 and abs(d[2]) < 1e-15
+
+
+def _cavity(nv=8, kn=0.0, n=16):
+    return small_2d(n, n, nv, kn=kn, mach=0.0,
+                    body=Body("cavity", (0.5, 0.5, 0.0), (0.43, 0.43, 0.0), t_wall=1.3))
+
+
+def test_cavity_mass_conserved_without_collisions():
+    cfg = _cavity()
+    o = Oracle2D(cfg)
+    f, g = random_state(cfg.ncell, cfg.nv, 2, seed=11)
+    f, g, d = o.run(f, g, 12)
+    mass = d[:, 3]
+    assert np.max(np.abs(mass - mass[0])) / mass[0] < 1e-13
+    assert np.all(f >= 0.0)   # positivity under the CFL condition
+
+
+def test_bgk_conserves_to_quadrature_error():
+    # interior cells of a uniform state see no net transport, so only the
+    # relaxation acts; it must conserve rho, rho u and E of (f, g)
+    nx = ny = 5
+    cfg = Config(dim=2, n=(nx, ny, 1), lo=(0, 0, 0), hi=(1, 1, 1), nv=24, kn=0.05,
+                 body=Body("none"), inflow=(1.0, 0.3, -0.2, 0.0, 1.1))
+    o = Oracle2D(cfg)
+    v = o.velocity()
+    vx = np.tile(v, 24)
+    vy = np.repeat(v, 24)
+    w = (12.0 / 24) ** 2
+    # a bimodal (two-beam) state well inside the velocity box, g from a
+    # third temperature: far from equilibrium, yet its fitted Maxwellian is
+    # resolved by the grid
+    def gauss(ax, ay, T):
+        return np.exp(-((vx - ax) ** 2 + (vy - ay) ** 2) / (2 * T)) / (2 * np.pi * T)
+    f0 = 0.6 * gauss(0.9, 0.2, 0.5) + 0.5 * gauss(-0.7, -0.4, 0.7)
+    g0 = 0.4 * f0 + 0.2 * gauss(0.0, 0.3, 0.9)
+    f = np.repeat(f0[None], nx * ny, axis=0)
+    g = np.repeat(g0[None], nx * ny, axis=0)
+    f1, g1, _ = o.step(f, g)
+    c = 2 * nx + 2
+    def mom(ff, gg):
+        return np.array([ff.sum() * w, (vx * ff).sum() * w, (vy * ff).sum() * w,
+                         (0.5 * (vx ** 2 + vy ** 2) * ff + gg).sum() * w])
+    m0, m1 = mom(f[c], g[c]), mom(f1[c], g1[c])
+    # the state is far from equilibrium: the update must be large ...
+    assert np.max(np.abs(f1[c] - f[c])) > 1e-3 * np.max(f[c])
+    # ... while the collision invariants move only by quadrature error
+    assert np.all(np.abs(m1 - m0) < 2e-7 * np.abs(m0).max())
+
+
+TINY = [
+    small_2d(6, 6, 4, kn=0.07, mach=0.4, body=Body("circle", (0.5, 0.52, 0), (0.19, 0.19, 0))),
+    small_2d(6, 6, 4, kn=0.2, mach=0.7, body=Body("circle", (0.47, 0.52, 0), (0.18, 0.18, 0), t_wall=1.7)),
+    small_2d(8, 8, 4, kn=0.0, mach=0.3, body=Body("ellipse", (0.5, 0.5, 0), (0.3, 0.12, 0), theta=0.4)),
+    small_2d(8, 6, 6, kn=0.5, mach=0.0, body=Body("cavity", (0.5, 0.5, 0), (0.41, 0.41, 0), t_wall=0.8)),
+]
+
+
+@pytest.mark.parametrize("k", range(len(TINY)))
+def test_step_equals_brute_force(k):
+    cfg = TINY[k]
+    o = Oracle2D(cfg)
+    geo = o.geometry()
+    merged = np.sum((geo["master"] >= 0) & (geo["master"] != np.arange(cfg.ncell)))
+    if k < 2:
+        assert merged > 0 and np.sum(geo["type"] == 1) > 0
+    f, g = random_state(cfg.ncell, cfg.nv, 2, seed=100 + k)
+    f1, g1, _ = o.step(f, g)
+    bf, bg = brute_step(cfg, geo, o.velocity(), o.dt, f, g, collide=cfg.kn > 0)
+    scale = np.max(np.abs(f1))
+    assert np.max(np.abs(f1 - bf)) / scale < 1e-13
+    assert np.max(np.abs(g1 - bg)) / np.max(np.abs(g1)) < 1e-13
+
+
+def free_molecular_force(r, U, T=1.0, Tw=1.0, n=4096):
+    """Force per unit length on a circle of radius r in a free stream
+    (rho = 1, u = (U, 0), T) with diffuse re-emission at Tw, from the
+    continuous half-range fluxes integrated over the exact circle."""
+    s = math.sqrt(T)
+    Fx = Fy = 0.0
+    for k in range(n):
+        a = 2 * math.pi * (k + 0.5) / n
+        nw = (-math.cos(a), -math.sin(a))            # into the wall
+        tw = (-nw[1], nw[0])
+        Un = U * nw[0]
+        Ut = U * tw[0]
+        z = Un / s
+        pdf = math.exp(-0.5 * z * z) / math.sqrt(2 * math.pi)
+        cdf = ndtr(z)
+        n_in = Un * cdf + s * pdf                      # int_{c_n>0} c_n g
+        p_n = (Un * Un + T) * cdf + Un * s * pdf       # int_{c_n>0} c_n^2 g
+        phi_w = n_in / math.sqrt(Tw / (2 * math.pi))
+        pn_tot = p_n + phi_w * Tw / 2.0
+        pt_tot = Ut * n_in
+        Fx += (pn_tot * nw[0] + pt_tot * tw[0]) * r * 2 * math.pi / n
+        Fy += (pn_tot * nw[1] + pt_tot * tw[1]) * r * 2 * math.pi / n
+    return Fx, Fy
+
+
+def test_first_step_drag_tends_to_free_molecular():
+    U = 0.8 * math.sqrt(5.0 / 3.0)
+    exact, _ = free_molecular_force(0.2, U, Tw=1.5)
+    errs = []
+    for n, nv in ((32, 16), (64, 32), (128, 48)):
+        cfg = small_2d(n, n, nv, mach=0.8,
+                       body=Body("circle", (0.5, 0.5, 0), (0.2, 0.2, 0), t_wall=1.5))
+        o = Oracle2D(cfg)
+        f, g = o.init()
+        d = o.force(f, g)
+        errs.append(abs(d[0] - exact) / exact)
+        assert abs(d[1]) < 1e-12
+    assert errs[0] < 5e-3 and errs[-1] < 3e-4
+    assert errs[2] < errs[1] < errs[0]
