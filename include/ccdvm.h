@@ -1,0 +1,186 @@
+/* ccdvm -- Cartesian cut-cell discrete-velocity solver for rarefied gas flow
+ * around obstacles, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Dechriste & Mieussens, "A Cartesian cut cell method for rarefied
+ * flow simulations around moving obstacles" (2015).  One time step is the
+ * sweep over cells x discrete velocities of Section 3.3: merge of small
+ * virtual cells into control volumes (eq. FusionDD), first-order explicit
+ * scheme with upwind fluxes on Cartesian and wall edges (eqs. ExSchemeDD,
+ * FluxDD), diffuse-reflection wall distribution whose density makes the net
+ * mass flux zero (eq. BoundaryDDv), BGK relaxation toward the local
+ * Maxwellian built from the discrete moments (eqs. MacroscopicDDv, BGKDD),
+ * redistribution to the virtual cells (eq. UpdateDD); the force and torque
+ * on the body from the wall stress (eqs. eq-force, eq-torque,
+ * StressTensorDD); the rigid-body update (eqs. motionDD_posit, motionDD_vit,
+ * uwDD).  The 3D variant follows Section 5.1 (eq. eq-schema3D).
+ *
+ * Units: nondimensional, R = T0 = rho0 = 1.  All floating point is FP64.
+ *
+ * Memory ownership: the caller owns every device buffer.  It queries sizes
+ * with cc_workspace_bytes, allocates them (for example as torch tensors on
+ * the GPU) and hands them to cc_bind together with the HIP stream to use.
+ * The library keeps only host metadata and never allocates device memory
+ * after cc_bind; cc_step launches kernels only (no host synchronisation
+ * unless a status flag is read back).
+ *
+ * Device layouts (velocity innermost, so consecutive lanes read consecutive
+ * addresses):
+ *   cell index   c = (k*ny + j)*nx + i          (i fastest)
+ *   velocity     p = p2*N + p1 (2D), p = (p3*N + p2)*N + p1 (3D), p1 fastest;
+ *                node v = vmin + (idx + 1/2) dv, dv = (vmax - vmin)/N
+ *   2D state     double2 state[c][p] = {f, g} (16 bytes per cell-velocity)
+ *   3D state     double  state[c][p] = F      (8 bytes per cell-velocity)
+ *   "plane" arrays used by cc_load_state / cc_store_state: double f[c][p]
+ *   (and g[c][p] in 2D), 8-byte aligned device pointers.
+ *
+ * Errors: every call returns a cc_status; no exception crosses the ABI.
+ * cc_last_error returns a message for the last failure on that context.
+ * Threading: one context per host thread at a time; a context is bound to
+ * one stream.
+ */
+#ifndef CCDVM_H
+#define CCDVM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cc_ctx cc_ctx;
+
+typedef enum {
+  CC_OK = 0,
+  CC_EINVAL = -1,     /* bad argument or unsupported size */
+  CC_ENOMEM = -2,     /* host allocation failed or a workspace is too small */
+  CC_EGEOM = -3,      /* geometry rejected: a cell cut twice by the boundary,
+                         a master search that cycles or needs more than 4 hops */
+  CC_ECFL = -4,       /* positivity condition (eq-CFL) violated in strict mode */
+  CC_EHIP = -5,       /* a HIP runtime call failed */
+  CC_ESTATE = -6,     /* call out of order (e.g. cc_step before cc_bind) */
+  CC_ENUMERIC = -7    /* non-finite or negative value detected by a check */
+} cc_status;
+
+enum { CC_BODY_NONE = 0, CC_BODY_CIRCLE = 1, CC_BODY_ELLIPSE = 2,
+       CC_BODY_CAVITY = 3, CC_BODY_HALFPLANE = 4, CC_BODY_SPHERE = 5 };
+enum { CC_MOTION_FIXED = 0, CC_MOTION_FREE_ROTATION = 1, CC_MOTION_IMPOSED = 2 };
+
+/* Flow set-up.  dim = 2 selects the reduced plane-flow model with the two
+ * distributions f, g (Section 2.2); dim = 3 the full model with F
+ * (Section 2.1).  n[2] = 1 in 2D.  kn <= 0 selects pure transport (no
+ * collisions).  dt <= 0: dt = cfl / sum_d (max_p |v_d| / dx_d).  inflow =
+ * (rho, ux, uy, uz, T) of the Maxwellian carried by every outer face (farfield)
+ * and used as the initial state. */
+typedef struct {
+  int dim;
+  int n[3];
+  double lo[3], hi[3];
+  int nv;                 /* velocity nodes per axis, N */
+  double vmin, vmax;
+  double kn, lref;
+  double cfl, dt;
+  double inflow[5];
+} cc_config;
+
+/* Obstacle given by an analytic signed distance, gas side positive
+ * (Appendix A).  circle: axes[0] = radius; ellipse: semi-axes axes[0],
+ * axes[1], rotated by theta about center; cavity: gas inside a circle of
+ * radius axes[0]; halfplane: gas where (x - center).(cos theta, sin theta) > 0;
+ * sphere (3D): axes[0] = radius.  t_wall: wall temperature.  motion:
+ * fixed, free rotation about the centre driven by the gas torque (inertia),
+ * or imposed constant velocity vel / angular velocity omega. */
+typedef struct {
+  int kind;
+  double center[3], axes[3], theta, t_wall;
+  double mass, inertia;
+  int motion;
+  double vel[3], omega;
+} cc_body;
+
+/* Validates the set-up, computes dt and the sizes of the device buffers.
+ * No device work.  *out receives a new context (free with cc_destroy). */
+cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out);
+void cc_destroy(cc_ctx* ctx);
+const char* cc_last_error(const cc_ctx* ctx);
+
+/* Bytes of the two state buffers (each), of the geometry buffer and of the
+ * scratch buffer.  All must be 256-byte aligned device allocations. */
+cc_status cc_workspace_bytes(const cc_ctx* ctx, size_t* state_bytes,
+                             size_t* geom_bytes, size_t* scratch_bytes);
+
+/* Binds caller-owned device buffers and a HIP stream (hipStream_t passed as
+ * void*, NULL = default stream), then builds the geometry on the device
+ * (Appendix A: level set, cell types, edge lengths, wall normal, areas,
+ * master search, control volumes).  Synchronises the stream once to read
+ * the geometry status; returns CC_EGEOM when the geometry is rejected. */
+cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom,
+                  void* scratch, void* hip_stream);
+
+/* Fills the current state with the inflow Maxwellian in every non-solid
+ * cell (g = T/2 f in 2D), zero in solid cells.  Asynchronous. */
+cc_status cc_init_maxwellian(cc_ctx* ctx);
+
+/* Copies a state given as plane arrays (device pointers, layout above; g is
+ * ignored in 3D) into the current state, sets solid cells to zero and merges
+ * every control volume (eq. FusionDD).  Asynchronous. */
+cc_status cc_load_state(cc_ctx* ctx, const double* f, const double* g);
+
+/* Copies the current state out as plane arrays (device pointers). */
+cc_status cc_store_state(const cc_ctx* ctx, double* f, double* g);
+
+/* Advances nsteps time steps.  diag (nullable device pointer, nsteps*4
+ * doubles) receives, for each step n, the force (Fx, Fy), the torque about
+ * the body centre and the total mass, all of the state at t^n (eqs.
+ * eq-force, eq-torque, def-masse); in 3D the entries are (Fx, Fy, Fz, mass).
+ * Asynchronous for fixed bodies; for a moving body the rigid-body update of
+ * every step runs on the device as well. */
+cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag);
+
+/* Moments of every cell of the current state, eq. (MacroscopicDDv):
+ * 2D: out[c][9] = rho, ux, uy, T, Sxx, Sxy, Syy, qx, qy;
+ * 3D: out[c][14] = rho, ux, uy, uz, T, Sxx, Sxy, Sxz, Syy, Syz, Szz, qx, qy, qz.
+ * Solid cells get zeros.  out is a device pointer.  Asynchronous. */
+cc_status cc_moments(cc_ctx* ctx, double* out);
+
+/* Force and torque on the body for the current state (synchronous):
+ * out[0..3] = Fx, Fy, torque, mass (2D) or Fx, Fy, Fz, mass (3D). */
+cc_status cc_body_force(cc_ctx* ctx, double out[4]);
+
+/* Rigid-body state at the current time (synchronous): centre x, y,
+ * angle, velocity x, y, angular velocity. */
+cc_status cc_body_state(cc_ctx* ctx, double out[6]);
+
+/* Applies one explicit Euler update of the body velocity with a given
+ * force and torque, eq. (motionDD_vit), honouring the motion mode (free
+ * rotation updates only the angular velocity).  Synchronous. */
+cc_status cc_rigid_update(cc_ctx* ctx, const double force[3], double torque);
+
+/* Time step in use. */
+cc_status cc_dt(const cc_ctx* ctx, double* dt);
+
+/* Copies the geometry tables to host arrays of ncell entries each (any
+ * pointer may be NULL): type (0 gas, 1 cut, 2 solid), master (-1 for solid),
+ * then 2D: lxm, lxp, lym, lyp, lw, nwx, nwy, rwx, rwy, sbar, scv.
+ * Synchronous.  3D: see cc_geometry_export3d. */
+cc_status cc_geometry_export(cc_ctx* ctx, int* type, int* master,
+                             double* lxm, double* lxp, double* lym, double* lyp,
+                             double* lw, double* nwx, double* nwy, double* rwx,
+                             double* rwy, double* sbar, double* scv);
+
+/* Number of control volumes handled by the cut-cell kernel (masters that
+ * are cut cells or own merged cells) and of non-master non-solid cells. */
+cc_status cc_geometry_counts(cc_ctx* ctx, int* n_irregular, int* n_members,
+                             int* n_solid);
+
+/* Per-kernel timing with HIP events recorded on the bound stream.
+ * cc_profile_enable(ctx, 1) starts recording (cleared); cc_profile_read
+ * returns, for kernel id k (0 = regular-cell step, 1 = cut-cell step,
+ * 2 = force reduction, 3 = merge), the summed milliseconds and the number of
+ * launches since enabling.  Reading synchronises the stream. */
+cc_status cc_profile_enable(cc_ctx* ctx, int on);
+cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCDVM_H */

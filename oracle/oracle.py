@@ -72,7 +72,12 @@ def lib():
         _lib.orc2d_step.argtypes = [P, P, P, P, P, P]
         _lib.orc2d_force.argtypes = [P, P, P, P]
         _lib.orc2d_moments.argtypes = [P, P, P, P]
+        _lib.orc_threads.restype = C.c_int
     return _lib
+
+
+def threads() -> int:
+    return lib().orc_threads()
 
 
 def _p(a):

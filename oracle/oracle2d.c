@@ -739,3 +739,15 @@ void orc2d_moments(const orc2d *o, const double *f, const double *g, double *out
     q[4] = sxx; q[5] = sxy; q[6] = syy; q[7] = qx; q[8] = qy;
   }
 }
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* number of threads the oracle's parallel loops use */
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

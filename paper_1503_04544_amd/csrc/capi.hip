@@ -1,0 +1,460 @@
+// C-ABI of the ccdvm library: validation, buffer layout, orchestration of the
+// device kernels on the caller's stream.  The declarations and their
+// contracts are in include/ccdvm.h.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ccdvm_impl.h"
+
+using namespace ccdvm;
+
+namespace ccdvm {
+bool regular_supported_2d(int nvel);
+bool regular_supported_3d(int nvel);
+hipError_t launch_force_only_2d(cc_ctx* ctx, double* out4);
+hipError_t launch_force_only_3d(cc_ctx* ctx, double* out4);
+hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_row);
+}  // namespace ccdvm
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Bump allocator over a caller buffer; with base == nullptr it only sizes.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+void layout_geo2d(cc_ctx* ctx, char* base, size_t* bytes) {
+  Carver cv{base};
+  Geo2D& G = ctx->g2;
+  G.nx = ctx->nx; G.ny = ctx->ny; G.ncell = ctx->ncell; G.N = ctx->N; G.nvel = ctx->nvel;
+  G.x0 = ctx->cfg.lo[0]; G.y0 = ctx->cfg.lo[1]; G.dx = ctx->dx; G.dy = ctx->dy;
+  size_t n = ctx->ncell;
+  G.phi = cv.take<double>((size_t)(ctx->nx + 1) * (ctx->ny + 1));
+  G.type = cv.take<int>(n); G.master = cv.take<int>(n); G.kind = cv.take<int>(n);
+  G.flags = cv.take<int>(n);
+  G.lxm = cv.take<double>(n); G.lxp = cv.take<double>(n);
+  G.lym = cv.take<double>(n); G.lyp = cv.take<double>(n);
+  G.lw = cv.take<double>(n); G.nwx = cv.take<double>(n); G.nwy = cv.take<double>(n);
+  G.rwx = cv.take<double>(n); G.rwy = cv.take<double>(n);
+  G.sbar = cv.take<double>(n); G.scv = cv.take<double>(n);
+  G.irr = cv.take<int>(n); G.mptr = cv.take<int>(n + 1); G.mem = cv.take<int>(n);
+  G.counts = cv.take<int>(4);
+  G.vnode = cv.take<double>(ctx->N);
+  G.ghost = cv.take<double2>(ctx->nvel);
+  G.wden = nullptr;
+  *bytes = cv.off;
+}
+
+void layout_geo3d(cc_ctx* ctx, char* base, size_t* bytes) {
+  Carver cv{base};
+  Geo3D& G = ctx->g3;
+  G.nx = ctx->nx; G.ny = ctx->ny; G.nz = ctx->nz; G.ncell = ctx->ncell; G.N = ctx->N;
+  G.nvel = ctx->nvel;
+  G.x0 = ctx->cfg.lo[0]; G.y0 = ctx->cfg.lo[1]; G.z0 = ctx->cfg.lo[2];
+  G.dx = ctx->dx; G.dy = ctx->dy; G.dz = ctx->dz;
+  size_t n = ctx->ncell;
+  G.phi = cv.take<double>((size_t)(ctx->nx + 1) * (ctx->ny + 1) * (ctx->nz + 1));
+  G.type = cv.take<int>(n); G.master = cv.take<int>(n); G.kind = cv.take<int>(n);
+  G.flags = cv.take<int>(n);
+  G.sxm = cv.take<double>(n); G.sxp = cv.take<double>(n); G.sym = cv.take<double>(n);
+  G.syp = cv.take<double>(n); G.szm = cv.take<double>(n); G.szp = cv.take<double>(n);
+  G.aw = cv.take<double>(n); G.nwx = cv.take<double>(n); G.nwy = cv.take<double>(n);
+  G.nwz = cv.take<double>(n); G.rwx = cv.take<double>(n); G.rwy = cv.take<double>(n);
+  G.rwz = cv.take<double>(n);
+  G.vbar = cv.take<double>(n); G.vcv = cv.take<double>(n);
+  G.irr = cv.take<int>(n); G.mptr = cv.take<int>(n + 1); G.mem = cv.take<int>(n);
+  G.counts = cv.take<int>(4);
+  G.vnode = cv.take<double>(ctx->N);
+  G.ghost = cv.take<double>(ctx->nvel);
+  *bytes = cv.off;
+}
+
+void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
+  Carver cv{base};
+  size_t n = ctx->ncell;
+  int nm = ctx->dim == 2 ? 4 : 5;
+  ctx->s.mom = cv.take<double>(n * nm);
+  ctx->s.fslot = cv.take<double>(n * 3);
+  ctx->s.body = cv.take<double>(16);
+  ctx->s.red = cv.take<double>(4 * 128 + 8);
+  *bytes = cv.off;
+}
+
+cc_status fail(cc_ctx* ctx, cc_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+cc_status hip_fail(cc_ctx* ctx, hipError_t e, const char* where) {
+  return fail(ctx, CC_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr, where)                      \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+  } while (0)
+
+}  // namespace
+
+namespace ccdvm {
+
+void prof_begin(cc_ctx* ctx, int k) {
+  Prof& P = ctx->prof;
+  if (!P.on || P.count[k] >= (int)P.start[k].size()) return;
+  hipEventRecord(P.start[k][P.count[k]], ctx->stream);
+}
+
+void prof_end(cc_ctx* ctx, int k) {
+  Prof& P = ctx->prof;
+  if (!P.on || P.count[k] >= (int)P.stop[k].size()) return;
+  hipEventRecord(P.stop[k][P.count[k]], ctx->stream);
+  P.count[k] += 1;
+}
+
+}  // namespace ccdvm
+
+extern "C" {
+
+cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
+  if (!cfg || !body || !out) return CC_EINVAL;
+  *out = nullptr;
+  cc_ctx* ctx = new (std::nothrow) cc_ctx();
+  if (!ctx) return CC_ENOMEM;
+  ctx->cfg = *cfg;
+  ctx->body = *body;
+  const cc_config& c = *cfg;
+  auto reject = [&](const std::string& msg) {
+    fprintf(stderr, "ccdvm: %s\n", msg.c_str());
+    delete ctx;
+    return CC_EINVAL;
+  };
+  if (c.dim != 2 && c.dim != 3) return reject("dim must be 2 or 3");
+  for (int d = 0; d < c.dim; ++d) {
+    if (c.n[d] < 1) return reject("grid size must be >= 1");
+    if (!(c.hi[d] > c.lo[d])) return reject("empty domain");
+  }
+  if (c.dim == 2 && c.n[2] != 1) return reject("n[2] must be 1 in 2D");
+  if (c.nv < 1 || c.nv > 64) return reject("nv must be in [1, 64]");
+  if (!(c.vmax > c.vmin)) return reject("empty velocity box");
+  if (!(c.cfl > 0.0) && !(c.dt > 0.0)) return reject("need cfl > 0 or dt > 0");
+  if (!(c.inflow[0] > 0.0) || !(c.inflow[4] > 0.0)) return reject("inflow rho and T must be > 0");
+  if (c.kn > 0.0 && !(c.lref > 0.0)) return reject("lref must be > 0");
+  if (body->kind < CC_BODY_NONE || body->kind > CC_BODY_SPHERE) return reject("unknown body kind");
+  if (c.dim == 2 && body->kind == CC_BODY_SPHERE) return reject("sphere is 3D only");
+  if (c.dim == 3 && body->kind != CC_BODY_SPHERE && body->kind != CC_BODY_NONE)
+    return reject("3D supports sphere or no body");
+  if (body->kind != CC_BODY_NONE && !(body->t_wall > 0.0)) return reject("t_wall must be > 0");
+  if (body->kind == CC_BODY_ELLIPSE && !(body->axes[0] > 0.0 && body->axes[1] > 0.0))
+    return reject("ellipse semi-axes must be > 0");
+  if ((body->kind == CC_BODY_CIRCLE || body->kind == CC_BODY_CAVITY || body->kind == CC_BODY_SPHERE) &&
+      !(body->axes[0] > 0.0))
+    return reject("radius must be > 0");
+  if (body->motion < CC_MOTION_FIXED || body->motion > CC_MOTION_IMPOSED) return reject("unknown motion");
+  if (body->motion != CC_MOTION_FIXED && c.dim == 3) return reject("moving bodies are 2D only");
+  if (body->motion == CC_MOTION_FREE_ROTATION && !(body->inertia > 0.0))
+    return reject("inertia must be > 0");
+  ctx->dim = c.dim;
+  ctx->nx = c.n[0]; ctx->ny = c.n[1]; ctx->nz = c.dim == 3 ? c.n[2] : 1;
+  long long ncell = (long long)ctx->nx * ctx->ny * ctx->nz;
+  if (ncell > (1LL << 30)) return reject("too many cells");
+  ctx->ncell = (int)ncell;
+  ctx->N = c.nv;
+  ctx->nvel = c.dim == 2 ? c.nv * c.nv : c.nv * c.nv * c.nv;
+  if (c.dim == 2 && !regular_supported_2d(ctx->nvel)) return reject("unsupported velocity grid size");
+  if (c.dim == 3 && !regular_supported_3d(ctx->nvel)) return reject("unsupported velocity grid size");
+  ctx->dx = (c.hi[0] - c.lo[0]) / ctx->nx;
+  ctx->dy = (c.hi[1] - c.lo[1]) / ctx->ny;
+  ctx->dz = c.dim == 3 ? (c.hi[2] - c.lo[2]) / ctx->nz : 1.0;
+  ctx->dv = (c.vmax - c.vmin) / c.nv;
+  double vm = 0.0;
+  for (int p = 0; p < c.nv; ++p) vm = fmax(vm, fabs(c.vmin + (p + 0.5) * ctx->dv));
+  ctx->vmax_abs = vm;
+  // dt = CFL / sum_d max|v_d| / dx_d (simple form of the positivity condition)
+  double rate = vm / ctx->dx + vm / ctx->dy + (c.dim == 3 ? vm / ctx->dz : 0.0);
+  ctx->dt = c.dt > 0.0 ? c.dt : c.cfl / rate;
+  size_t per = c.dim == 2 ? 16 : 8;
+  ctx->state_bytes = align_up((size_t)ctx->ncell * ctx->nvel * per);
+  if (c.dim == 2) layout_geo2d(ctx, nullptr, &ctx->geom_bytes);
+  else layout_geo3d(ctx, nullptr, &ctx->geom_bytes);
+  layout_scratch(ctx, nullptr, &ctx->scratch_bytes);
+  ctx->body_state[0] = body->center[0];
+  ctx->body_state[1] = body->center[1];
+  ctx->body_state[2] = body->theta;
+  if (body->motion != CC_MOTION_FIXED) {
+    ctx->body_state[3] = body->vel[0];
+    ctx->body_state[4] = body->vel[1];
+    ctx->body_state[5] = body->omega;
+  }
+  *out = ctx;
+  return CC_OK;
+}
+
+void cc_destroy(cc_ctx* ctx) {
+  if (!ctx) return;
+  for (int k = 0; k < kProfKernels; ++k) {
+    for (hipEvent_t e : ctx->prof.start[k]) hipEventDestroy(e);
+    for (hipEvent_t e : ctx->prof.stop[k]) hipEventDestroy(e);
+  }
+  delete ctx;
+}
+
+const char* cc_last_error(const cc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+cc_status cc_workspace_bytes(const cc_ctx* ctx, size_t* state_bytes, size_t* geom_bytes,
+                             size_t* scratch_bytes) {
+  if (!ctx) return CC_EINVAL;
+  if (state_bytes) *state_bytes = ctx->state_bytes;
+  if (geom_bytes) *geom_bytes = ctx->geom_bytes;
+  if (scratch_bytes) *scratch_bytes = ctx->scratch_bytes;
+  return CC_OK;
+}
+
+cc_status cc_dt(const cc_ctx* ctx, double* dt) {
+  if (!ctx || !dt) return CC_EINVAL;
+  *dt = ctx->dt;
+  return CC_OK;
+}
+
+static cc_status read_geometry_status(cc_ctx* ctx) {
+  int counts[4] = {0, 0, 0, 0};
+  int* dcounts = ctx->dim == 2 ? ctx->g2.counts : ctx->g3.counts;
+  HIPCHK(ctx, hipMemcpyAsync(counts, dcounts, sizeof(counts), hipMemcpyDeviceToHost, ctx->stream),
+         "geometry status copy");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "geometry build");
+  if (counts[3] & 2) return fail(ctx, CC_EGEOM, "a cell is cut twice by the boundary");
+  if (counts[3] & 1) return fail(ctx, CC_EGEOM, "master search cycles, leaves the domain or needs more than 4 hops");
+  if (counts[3] & 4) return fail(ctx, CC_EGEOM, "a control volume has more members than supported");
+  ctx->n_irr = counts[0];
+  ctx->n_members = counts[1];
+  ctx->n_solid = counts[2];
+  return CC_OK;
+}
+
+cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scratch,
+                  void* hip_stream) {
+  if (!ctx) return CC_EINVAL;
+  if (!state0 || !state1 || !geom || !scratch) return fail(ctx, CC_EINVAL, "null buffer");
+  for (void* p : {state0, state1, geom, scratch})
+    if ((uintptr_t)p % kAlign) return fail(ctx, CC_EINVAL, "buffers must be 256-byte aligned");
+  ctx->state[0] = state0;
+  ctx->state[1] = state1;
+  ctx->cur = 0;
+  ctx->geom = geom;
+  ctx->scratch = scratch;
+  ctx->stream = (hipStream_t)hip_stream;
+  size_t b;
+  if (ctx->dim == 2) layout_geo2d(ctx, (char*)geom, &b);
+  else layout_geo3d(ctx, (char*)geom, &b);
+  layout_scratch(ctx, (char*)scratch, &b);
+  HIPCHK(ctx, hipMemsetAsync(scratch, 0, ctx->scratch_bytes, ctx->stream), "scratch clear");
+  // solid cells are never written by a fixed-geometry step: both buffers
+  // start at zero so that they read as empty on either side of the ping-pong
+  HIPCHK(ctx, hipMemsetAsync(state0, 0, ctx->state_bytes, ctx->stream), "state clear");
+  HIPCHK(ctx, hipMemsetAsync(state1, 0, ctx->state_bytes, ctx->stream), "state clear");
+  HIPCHK(ctx, hipMemcpyAsync(ctx->s.body, ctx->body_state, 6 * sizeof(double),
+                             hipMemcpyHostToDevice, ctx->stream), "body state upload");
+  hipError_t e = ctx->dim == 2
+                     ? build_geometry_2d(ctx, ctx->body_state[0], ctx->body_state[1], ctx->body_state[2])
+                     : build_geometry_3d(ctx);
+  if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernels");
+  cc_status st = read_geometry_status(ctx);
+  if (st != CC_OK) return st;
+  ctx->bound = true;
+  ctx->merged = false;
+  ctx->mom_valid = false;
+  return CC_OK;
+}
+
+// make the current state ready for a step: moments valid, control volumes merged
+static cc_status prepare(cc_ctx* ctx) {
+  if (!ctx->mom_valid) {
+    HIPCHK(ctx, ctx->dim == 2 ? launch_moments_all_2d(ctx) : launch_moments_all_3d(ctx), "moments");
+    ctx->mom_valid = true;
+  }
+  if (!ctx->merged) {
+    HIPCHK(ctx, ctx->dim == 2 ? launch_merge_2d(ctx) : launch_merge_3d(ctx), "merge");
+    ctx->merged = true;
+  }
+  return CC_OK;
+}
+
+cc_status cc_init_maxwellian(cc_ctx* ctx) {
+  if (!ctx) return CC_EINVAL;
+  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  HIPCHK(ctx, ctx->dim == 2 ? launch_init_maxwellian_2d(ctx) : launch_init_maxwellian_3d(ctx), "init");
+  ctx->mom_valid = false;
+  ctx->merged = false;
+  return prepare(ctx);
+}
+
+cc_status cc_load_state(cc_ctx* ctx, const double* f, const double* g) {
+  if (!ctx || !f) return CC_EINVAL;
+  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (ctx->dim == 2 && !g) return fail(ctx, CC_EINVAL, "g is required in 2D");
+  HIPCHK(ctx, ctx->dim == 2 ? launch_load_state_2d(ctx, f, g) : launch_load_state_3d(ctx, f), "load");
+  ctx->mom_valid = false;
+  ctx->merged = false;
+  return prepare(ctx);
+}
+
+cc_status cc_store_state(const cc_ctx* ctx, double* f, double* g) {
+  if (!ctx || !f) return CC_EINVAL;
+  if (!ctx->bound) return CC_ESTATE;
+  hipError_t e = ctx->dim == 2 ? launch_store_state_2d(ctx, f, g) : launch_store_state_3d(ctx, f);
+  return e == hipSuccess ? CC_OK : CC_EHIP;
+}
+
+cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
+  if (!ctx || nsteps < 0) return CC_EINVAL;
+  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  cc_status st = prepare(ctx);
+  if (st != CC_OK) return st;
+  if (nsteps == 0) return CC_OK;
+  bool moving = ctx->body.motion != CC_MOTION_FIXED && ctx->body.kind != CC_BODY_NONE;
+  if (diag) {
+    HIPCHK(ctx, ctx->dim == 2 ? launch_mass_2d(ctx, diag + 3) : launch_mass_3d(ctx, diag + 3), "mass");
+  }
+  for (int n = 0; n < nsteps; ++n) {
+    double* frow = diag ? diag + 4 * (size_t)n : nullptr;
+    double* mrow = (diag && n + 1 < nsteps) ? diag + 4 * (size_t)(n + 1) + 3 : nullptr;
+    hipError_t e;
+    if (ctx->dim == 3) e = launch_step_3d(ctx, frow, mrow);
+    else if (moving) e = launch_moving_step_2d(ctx, frow, mrow);
+    else e = launch_step_2d(ctx, frow, mrow);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step");
+  }
+  return CC_OK;
+}
+
+cc_status cc_moments(cc_ctx* ctx, double* out) {
+  if (!ctx || !out) return CC_EINVAL;
+  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  HIPCHK(ctx, ctx->dim == 2 ? launch_moments_out_2d(ctx, out) : launch_moments_out_3d(ctx, out), "moments");
+  return CC_OK;
+}
+
+cc_status cc_body_force(cc_ctx* ctx, double out[4]) {
+  if (!ctx || !out) return CC_EINVAL;
+  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  cc_status st = prepare(ctx);
+  if (st != CC_OK) return st;
+  double* dev = ctx->s.red + 4 * 128 + 4;
+  HIPCHK(ctx, ctx->dim == 2 ? launch_force_only_2d(ctx, dev) : launch_force_only_3d(ctx, dev), "force");
+  HIPCHK(ctx, hipMemcpyAsync(out, dev, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "force copy");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "force sync");
+  return CC_OK;
+}
+
+cc_status cc_body_state(cc_ctx* ctx, double out[6]) {
+  if (!ctx || !out) return CC_EINVAL;
+  if (!ctx->bound) {
+    memcpy(out, ctx->body_state, 6 * sizeof(double));
+    return CC_OK;
+  }
+  HIPCHK(ctx, hipMemcpyAsync(ctx->body_state, ctx->s.body, 6 * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx->stream), "body copy");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "body sync");
+  memcpy(out, ctx->body_state, 6 * sizeof(double));
+  return CC_OK;
+}
+
+cc_status cc_rigid_update(cc_ctx* ctx, const double force[3], double torque) {
+  if (!ctx || !force) return CC_EINVAL;
+  double s[6];
+  cc_status st = cc_body_state(ctx, s);
+  if (st != CC_OK) return st;
+  // eq. (motionDD_vit): explicit Euler on the velocities
+  if (ctx->body.motion == CC_MOTION_FREE_ROTATION) {
+    s[5] += ctx->dt * torque / ctx->body.inertia;
+  } else if (ctx->body.motion == CC_MOTION_FIXED) {
+    return fail(ctx, CC_EINVAL, "fixed body");
+  }
+  memcpy(ctx->body_state, s, sizeof(s));
+  if (ctx->bound) {
+    HIPCHK(ctx, hipMemcpyAsync(ctx->s.body, ctx->body_state, 6 * sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream), "body upload");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "body sync");
+  }
+  return CC_OK;
+}
+
+cc_status cc_geometry_export(cc_ctx* ctx, int* type, int* master, double* lxm, double* lxp,
+                             double* lym, double* lyp, double* lw, double* nwx, double* nwy,
+                             double* rwx, double* rwy, double* sbar, double* scv) {
+  if (!ctx) return CC_EINVAL;
+  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (ctx->dim != 2) return fail(ctx, CC_EINVAL, "2D only");
+  const Geo2D& G = ctx->g2;
+  size_t n = ctx->ncell;
+  struct { void* dst; const void* src; size_t sz; } cp[] = {
+      {type, G.type, 4}, {master, G.master, 4}, {lxm, G.lxm, 8}, {lxp, G.lxp, 8},
+      {lym, G.lym, 8}, {lyp, G.lyp, 8}, {lw, G.lw, 8}, {nwx, G.nwx, 8}, {nwy, G.nwy, 8},
+      {rwx, G.rwx, 8}, {rwy, G.rwy, 8}, {sbar, G.sbar, 8}, {scv, G.scv, 8}};
+  for (auto& c : cp)
+    if (c.dst) HIPCHK(ctx, hipMemcpyAsync(c.dst, c.src, n * c.sz, hipMemcpyDeviceToHost, ctx->stream), "export");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "export sync");
+  return CC_OK;
+}
+
+cc_status cc_geometry_counts(cc_ctx* ctx, int* n_irregular, int* n_members, int* n_solid) {
+  if (!ctx) return CC_EINVAL;
+  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (n_irregular) *n_irregular = ctx->n_irr;
+  if (n_members) *n_members = ctx->n_members;
+  if (n_solid) *n_solid = ctx->n_solid;
+  return CC_OK;
+}
+
+cc_status cc_profile_enable(cc_ctx* ctx, int on) {
+  if (!ctx) return CC_EINVAL;
+  Prof& P = ctx->prof;
+  if (on && P.start[0].empty()) {
+    for (int k = 0; k < kProfKernels; ++k) {
+      P.start[k].resize(kProfCap);
+      P.stop[k].resize(kProfCap);
+      for (int e = 0; e < kProfCap; ++e) {
+        HIPCHK(ctx, hipEventCreate(&P.start[k][e]), "event create");
+        HIPCHK(ctx, hipEventCreate(&P.stop[k][e]), "event create");
+      }
+    }
+  }
+  P.on = on != 0;
+  for (int k = 0; k < kProfKernels; ++k) P.count[k] = 0;
+  return CC_OK;
+}
+
+cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launches) {
+  if (!ctx || kernel < 0 || kernel >= kProfKernels) return CC_EINVAL;
+  Prof& P = ctx->prof;
+  double tot = 0.0;
+  if (P.count[kernel] > 0) HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "profile sync");
+  for (int e = 0; e < P.count[kernel]; ++e) {
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, P.start[kernel][e], P.stop[kernel][e]), "elapsed");
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = P.count[kernel];
+  return CC_OK;
+}
+
+}  // extern "C"

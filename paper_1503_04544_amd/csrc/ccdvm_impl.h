@@ -1,0 +1,149 @@
+// Internal declarations of the ccdvm library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "ccdvm.h"
+
+namespace ccdvm {
+
+// Per-cell kind used to dispatch the step.
+enum CellKind : int {
+  KIND_REGULAR = 0,    // gas cell, control volume of one cell: fused stencil kernel
+  KIND_IRREGULAR = 1,  // master of a control volume that is cut or owns merged cells
+  KIND_MEMBER = 2,     // non-master virtual cell: receives its master's value
+  KIND_SOLID = 3
+};
+
+enum CellType : int { TYPE_GAS = 0, TYPE_CUT = 1, TYPE_SOLID = 2 };
+
+// Maximum number of virtual cells merged into one control volume that the
+// cut-cell kernel handles (the master search stops after 4 hops, and in the
+// workloads a control volume holds at most 3 cells).
+constexpr int kMaxMembers = 8;
+// Window half-width scanned for members of a control volume (hop cap).
+constexpr int kHopCap = 4;
+
+// Body parameters as seen by device code.
+struct BodyDev {
+  int kind;
+  double cx, cy, cz;
+  double a, b, c;
+  double theta;
+  double t_wall;
+};
+
+// Geometry tables of a 2D grid, all in the caller's geometry buffer.
+struct Geo2D {
+  int nx, ny, ncell, N, nvel;
+  double x0, y0, dx, dy;
+  double* phi;       // (nx+1)*(ny+1) vertex level set
+  int* type;         // CellType
+  int* master;       // master cell, -1 for solid
+  int* kind;         // CellKind
+  int* flags;        // bit0: centre in gas (eq. ii); bit1: two boundary pieces
+  double* lxm; double* lxp; double* lym; double* lyp;
+  double* lw; double* nwx; double* nwy; double* rwx; double* rwy;
+  double* sbar; double* scv;
+  int* irr;          // irregular masters, ascending cell index
+  int* mptr;         // CSR pointers (n_irr + 1) into mem
+  int* mem;          // members of each irregular master, ascending
+  int* counts;       // [0] n_irr, [1] n_members, [2] n_solid, [3] error bits
+  double* vnode;     // N velocity nodes
+  double2* ghost;    // nvel farfield values (f, g)
+  double* wden;      // per irregular-list slot and member: wall-density denominator
+};
+
+struct Geo3D {
+  int nx, ny, nz, ncell, N, nvel;
+  double x0, y0, z0, dx, dy, dz;
+  double* phi;       // (nx+1)*(ny+1)*(nz+1)
+  int* type; int* master; int* kind; int* flags;
+  double* sxm; double* sxp; double* sym; double* syp; double* szm; double* szp;
+  double* aw; double* nwx; double* nwy; double* nwz; double* rwx; double* rwy; double* rwz;
+  double* vbar; double* vcv;
+  int* irr; int* mptr; int* mem; int* counts;
+  double* vnode;
+  double* ghost;     // nvel farfield values (F)
+};
+
+// Scratch layout (caller's scratch buffer).
+struct Scratch {
+  double* mom;       // ncell * 4 (2D: rho, ux, uy, T) or ncell * 5 (3D: rho, u, T)
+  double* fslot;     // per irregular master: Fx, Fy, torque (2D) / Fx, Fy, Fz (3D)
+  double* body;      // rigid body state on device: cx, cy, theta, ux, uy, omega
+  double* red;       // small reduction buffer
+};
+
+// Per-kernel HIP events recorded around every launch while profiling is on;
+// elapsed times are summed when read.
+constexpr int kProfKernels = 4;
+constexpr int kProfCap = 4096;
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> start[kProfKernels], stop[kProfKernels];
+  int count[kProfKernels] = {0, 0, 0, 0};
+};
+
+}  // namespace ccdvm
+
+struct cc_ctx {
+  cc_config cfg;
+  cc_body body;
+  int dim;
+  int nx, ny, nz, ncell, N, nvel;
+  double dx, dy, dz, dv, dt;
+  double vmax_abs;
+  size_t state_bytes, geom_bytes, scratch_bytes;
+  void* state[2] = {nullptr, nullptr};
+  int cur = 0;
+  void* geom = nullptr;
+  void* scratch = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  bool merged = false;     // members hold their control-volume value
+  bool mom_valid = false;  // scratch.mom holds the moments of the current state
+  ccdvm::Geo2D g2;
+  ccdvm::Geo3D g3;
+  ccdvm::Scratch s;
+  int n_irr = 0, n_members = 0, n_solid = 0;
+  // host mirror of the rigid body (kept in sync with the device copy)
+  double body_state[6] = {0, 0, 0, 0, 0, 0};
+  ccdvm::Prof prof;
+  std::string err;
+};
+
+namespace ccdvm {
+
+// geometry (geom2d.hip / geom3d.hip)
+hipError_t build_geometry_2d(cc_ctx* ctx, double cx, double cy, double theta);
+hipError_t build_geometry_3d(cc_ctx* ctx);
+
+// step and helpers (step2d.hip / step3d.hip)
+hipError_t launch_init_maxwellian_2d(cc_ctx* ctx);
+hipError_t launch_load_state_2d(cc_ctx* ctx, const double* f, const double* g);
+hipError_t launch_store_state_2d(const cc_ctx* ctx, double* f, double* g);
+hipError_t launch_merge_2d(cc_ctx* ctx);
+hipError_t launch_moments_all_2d(cc_ctx* ctx);
+hipError_t launch_step_2d(cc_ctx* ctx, double* force_row, double* mass_row);
+hipError_t launch_mass_2d(cc_ctx* ctx, double* mass_row);
+hipError_t launch_moments_out_2d(cc_ctx* ctx, double* out);
+
+hipError_t launch_init_maxwellian_3d(cc_ctx* ctx);
+hipError_t launch_load_state_3d(cc_ctx* ctx, const double* f);
+hipError_t launch_store_state_3d(const cc_ctx* ctx, double* f);
+hipError_t launch_merge_3d(cc_ctx* ctx);
+hipError_t launch_moments_all_3d(cc_ctx* ctx);
+hipError_t launch_step_3d(cc_ctx* ctx, double* force_row, double* mass_row);
+hipError_t launch_mass_3d(cc_ctx* ctx, double* mass_row);
+hipError_t launch_moments_out_3d(cc_ctx* ctx, double* out);
+
+// profiling hooks (capi.cpp)
+void prof_begin(cc_ctx* ctx, int k);
+void prof_end(cc_ctx* ctx, int k);
+
+}  // namespace ccdvm

@@ -1,0 +1,346 @@
+// Device construction of the 2D cut-cell geometry (Appendix A of the paper):
+// vertex level set with the 1e-10 dx clamp (A.1), cell types from the sign
+// pattern (A.1), gas lengths of the Cartesian edges by linear interpolation of
+// the crossing points (A.2), wall edge by closure of the virtual cell with the
+// normal pointing into the solid (A.2), virtual-cell area (A.4), master search
+// with test (ii) and algorithm (fusion) (A.3), control-volume areas (A.4) and
+// the compact list of control volumes handled by the cut-cell kernel.
+//
+// Everything is a pure function of the level set, so building it on the GPU
+// costs a handful of small launches; a moving body rebuilds it every step.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "ccdvm_impl.h"
+
+namespace ccdvm {
+namespace {
+
+// Signed distance to the ellipse X^2/a^2 + Y^2/b^2 = 1 (negative inside).
+// The nearest point is (a^2 X/(a^2+t), b^2 Y/(b^2+t)), t the unique root of
+// G(t) = (aX/(a^2+t))^2 + (bY/(b^2+t))^2 - 1 on t > -min(a, b)^2, G
+// decreasing and convex there: Newton from the right of the root converges
+// monotonically; a bracket guards against round-off.
+__device__ double ellipse_signed_distance(double a, double b, double x, double y) {
+  double X = fabs(x), Y = fabs(y);
+  if (b > a) { double t = a; a = b; b = t; t = X; X = Y; Y = t; }
+  const double a2 = a * a, b2 = b * b;
+  const double q = X * X / a2 + Y * Y / b2 - 1.0;
+  double px, py;
+  if (Y == 0.0) {
+    // on the major axis: interior points may have their nearest point off-axis
+    double lim = (a2 - b2) / a;
+    if (X < lim) {
+      double xs = a2 * X / (a2 - b2);
+      px = xs;
+      double r = 1.0 - (xs / a) * (xs / a);
+      py = b * sqrt(r > 0.0 ? r : 0.0);
+    } else {
+      px = a; py = 0.0;
+    }
+  } else if (X == 0.0) {
+    px = 0.0; py = b;
+  } else {
+    double lo = -b2;                               // G(lo+) = +inf
+    double t = fmax(a * X, b * Y) - b2;            // G(t) <= 0 here
+    if (t < lo) t = lo;
+    double hi = t + a * X + b * Y + 1.0;           // G(hi) < 0 surely
+    // start from the right end of the bracket
+    t = hi;
+    for (int it = 0; it < 200; ++it) {
+      double ra = a * X / (a2 + t), rb = b * Y / (b2 + t);
+      double G = ra * ra + rb * rb - 1.0;
+      if (G > 0.0) lo = t; else hi = t;
+      double dG = -2.0 * (ra * ra / (a2 + t) + rb * rb / (b2 + t));
+      double tn = t - G / dG;
+      if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+      if (tn == t || hi - lo <= 1e-17 * fabs(hi)) { t = tn; break; }
+      t = tn;
+    }
+    px = a2 * X / (a2 + t);
+    py = b2 * Y / (b2 + t);
+  }
+  double d = hypot(px - X, py - Y);
+  return q < 0.0 ? -d : d;
+}
+
+__device__ double level_set_2d(const BodyDev& B, double x, double y, double cx,
+                               double cy, double th) {
+  double ex = x - cx, ey = y - cy;
+  switch (B.kind) {
+    case CC_BODY_CIRCLE: return hypot(ex, ey) - B.a;
+    case CC_BODY_CAVITY: return B.a - hypot(ex, ey);
+    case CC_BODY_HALFPLANE: return ex * cos(th) + ey * sin(th);
+    case CC_BODY_ELLIPSE: {
+      double c = cos(th), s = sin(th);
+      return ellipse_signed_distance(B.a, B.b, c * ex + s * ey, -s * ex + c * ey);
+    }
+    default: return 1.0e300;
+  }
+}
+
+__global__ void k_phi2d(Geo2D G, BodyDev B, double cx, double cy, double th) {
+  int nvx = G.nx + 1, nvy = G.ny + 1;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nvx * nvy) return;
+  int a = t % nvx, b = t / nvx;
+  double p = level_set_2d(B, G.x0 + a * G.dx, G.y0 + b * G.dy, cx, cy, th);
+  double floor_ = 1e-10 * G.dx;
+  double m = fabs(p) > floor_ ? fabs(p) : floor_;
+  G.phi[t] = p >= 0.0 ? m : -m;
+}
+
+// gas length of an edge of length h whose ends carry level-set values pa
+// (s = 0) and pb (s = h); *s receives the crossing abscissa on a mixed edge
+__device__ inline double gas_len(double pa, double pb, double h, bool* mixed, double* s) {
+  bool ga = pa > 0.0, gb = pb > 0.0;
+  *mixed = ga != gb;
+  if (ga && gb) return h;
+  if (!ga && !gb) return 0.0;
+  double sc = h * pa / (pa - pb);
+  *s = sc;
+  return ga ? sc : h - sc;
+}
+
+__global__ void k_cell2d(Geo2D G) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.ncell) return;
+  int i = c % G.nx, j = c / G.nx;
+  int nvx = G.nx + 1;
+  double p00 = G.phi[j * nvx + i], p10 = G.phi[j * nvx + i + 1];
+  double p11 = G.phi[(j + 1) * nvx + i + 1], p01 = G.phi[(j + 1) * nvx + i];
+  double mn = fmin(fmin(p00, p10), fmin(p11, p01));
+  double mx = fmax(fmax(p00, p10), fmax(p11, p01));
+  int type = mn > 0.0 ? TYPE_GAS : (mx < 0.0 ? TYPE_SOLID : TYPE_CUT);
+  const double dx = G.dx, dy = G.dy;
+  bool mr, ml, mt, mb;
+  double sr = 0, sl = 0, st = 0, sb = 0;
+  double Lr = gas_len(p10, p11, dy, &mr, &sr);   // right edge, bottom -> top
+  double Ll = gas_len(p00, p01, dy, &ml, &sl);   // left edge
+  double Lt = gas_len(p01, p11, dx, &mt, &st);   // top edge, left -> right
+  double Lb = gas_len(p00, p10, dx, &mb, &sb);   // bottom edge
+  int nmix = (int)mr + (int)ml + (int)mt + (int)mb;
+  int flags = 0;
+  if (0.25 * (p00 + p10 + p11 + p01) > 1e-12 * dx) flags |= 1;
+  if (nmix == 4) flags |= 2;
+  // polygon of the virtual cell, counter-clockwise from the lower-left
+  // corner, in coordinates relative to that corner
+  double vx[8], vy[8];
+  int nvtx = 0;
+  if (p00 > 0.0) { vx[nvtx] = 0.0; vy[nvtx] = 0.0; ++nvtx; }
+  if (mb) { vx[nvtx] = sb; vy[nvtx] = 0.0; ++nvtx; }
+  if (p10 > 0.0) { vx[nvtx] = dx; vy[nvtx] = 0.0; ++nvtx; }
+  if (mr) { vx[nvtx] = dx; vy[nvtx] = sr; ++nvtx; }
+  if (p11 > 0.0) { vx[nvtx] = dx; vy[nvtx] = dy; ++nvtx; }
+  if (mt) { vx[nvtx] = st; vy[nvtx] = dy; ++nvtx; }
+  if (p01 > 0.0) { vx[nvtx] = 0.0; vy[nvtx] = dy; ++nvtx; }
+  if (ml) { vx[nvtx] = 0.0; vy[nvtx] = sl; ++nvtx; }
+  double area = 0.0;
+  for (int k = 0; k < nvtx; ++k) {
+    int k1 = k + 1 == nvtx ? 0 : k + 1;
+    area += vx[k] * vy[k1] - vx[k1] * vy[k];
+  }
+  area *= 0.5;
+  // wall edge: |L_w| n_w closes the polygon of Cartesian edges
+  double ddx = Lr - Ll, ddy = Lt - Lb;
+  double lw = 0.0, nx_ = 0.0, ny_ = 0.0, rx = 0.0, ry = 0.0;
+  if (type == TYPE_CUT && nmix == 2) {
+    lw = sqrt(ddx * ddx + ddy * ddy);
+    if (lw > 0.0) {
+      nx_ = -ddx / lw; ny_ = -ddy / lw;
+      double cxs = 0.0, cys = 0.0;
+      if (mr) { cxs += dx; cys += sr; }
+      if (ml) { cxs += 0.0; cys += sl; }
+      if (mt) { cxs += st; cys += dy; }
+      if (mb) { cxs += sb; cys += 0.0; }
+      rx = 0.5 * cxs; ry = 0.5 * cys;
+    }
+  }
+  G.type[c] = type;
+  G.flags[c] = flags;
+  G.lxp[c] = Lr; G.lxm[c] = Ll; G.lyp[c] = Lt; G.lym[c] = Lb;
+  G.lw[c] = lw; G.nwx[c] = nx_; G.nwy[c] = ny_;
+  G.rwx[c] = G.x0 + i * dx + rx;
+  G.rwy[c] = G.y0 + j * dy + ry;
+  G.sbar[c] = type == TYPE_SOLID ? 0.0 : (type == TYPE_GAS ? dx * dy : area);
+}
+
+// One hop of the master search from cell (i, j): across the largest gas edge
+// shared with a cell of the domain, ties (within 1e-12 of the largest) broken
+// in the order x+, x-, y+, y-.  Returns false when no edge qualifies.
+__device__ inline bool hop2d(const Geo2D& G, const double* lxp, const double* lxm,
+                             const double* lyp, const double* lym, int& i, int& j) {
+  int c = j * G.nx + i;
+  double r = i + 1 < G.nx ? lxp[c] : 0.0;
+  double l = i > 0 ? lxm[c] : 0.0;
+  double t = j + 1 < G.ny ? lyp[c] : 0.0;
+  double b = j > 0 ? lym[c] : 0.0;
+  double M = fmax(fmax(r, l), fmax(t, b));
+  if (!(M > 0.0)) return false;
+  double tie = M * (1.0 - 1e-12);
+  if (r >= tie) i += 1;
+  else if (l >= tie) i -= 1;
+  else if (t >= tie) j += 1;
+  else j -= 1;
+  return true;
+}
+
+__global__ void k_master2d(Geo2D G) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.ncell) return;
+  if (G.type[c] == TYPE_SOLID) { G.master[c] = -1; return; }
+  int i = c % G.nx, j = c / G.nx;
+  int seen[kHopCap + 1];
+  seen[0] = c;
+  int hops = 0;
+  bool bad = false;
+  while (!(G.flags[j * G.nx + i] & 1)) {
+    if (hops == kHopCap || !hop2d(G, G.lxp, G.lxm, G.lyp, G.lym, i, j)) { bad = true; break; }
+    ++hops;
+    int nc = j * G.nx + i;
+    for (int h = 0; h < hops; ++h) bad |= seen[h] == nc;
+    if (bad) break;
+    seen[hops] = nc;
+  }
+  G.master[c] = j * G.nx + i;
+  if (bad) atomicOr(&G.counts[3], 1);
+  if (G.flags[c] & 2) atomicOr(&G.counts[3], 2);
+}
+
+// control-volume area and kind; members of a control volume are cut cells
+// within kHopCap cells of their master, and a master owning members touches
+// a cut cell
+__global__ void k_cv2d(Geo2D G) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.ncell) return;
+  int m = G.master[c];
+  if (m < 0) { G.kind[c] = KIND_SOLID; G.scv[c] = 0.0; return; }
+  if (m != c) { G.kind[c] = KIND_MEMBER; G.scv[c] = 0.0; return; }
+  int i = c % G.nx, j = c / G.nx;
+  bool near_cut = false;
+  for (int dj = -1; dj <= 1; ++dj)
+    for (int di = -1; di <= 1; ++di) {
+      int ii = i + di, jj = j + dj;
+      if (ii >= 0 && jj >= 0 && ii < G.nx && jj < G.ny) near_cut |= G.type[jj * G.nx + ii] == TYPE_CUT;
+    }
+  double S = 0.0;
+  int cnt = 0;
+  if (!near_cut) {
+    S = G.sbar[c]; cnt = 1;
+  } else {
+    for (int jj = max(j - kHopCap, 0); jj <= min(j + kHopCap, G.ny - 1); ++jj)
+      for (int ii = max(i - kHopCap, 0); ii <= min(i + kHopCap, G.nx - 1); ++ii) {
+        int k = jj * G.nx + ii;
+        if (G.master[k] == c) { S += G.sbar[k]; ++cnt; }
+      }
+  }
+  G.scv[c] = S;
+  G.kind[c] = (G.type[c] == TYPE_GAS && cnt == 1) ? KIND_REGULAR : KIND_IRREGULAR;
+  if (cnt > kMaxMembers) atomicOr(&G.counts[3], 4);
+}
+
+// Block-wide exclusive scan of 1024 ints held one per thread; returns the
+// exclusive prefix and writes the block total to *total.
+__device__ int block_exclusive_scan(int v, int* sh, int* total) {
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    int add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int incl = sh[t];
+  *total = sh[blockDim.x - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// Single-block deterministic compaction: list of irregular masters in
+// ascending cell order, CSR of their members, population counts.
+__global__ void __launch_bounds__(1024) k_compact2d(Geo2D G) {
+  __shared__ int sh[1024];
+  int t = threadIdx.x;
+  int per = (G.ncell + blockDim.x - 1) / blockDim.x;
+  int b = t * per, e = min(b + per, G.ncell);
+  int nirr = 0, nmem = 0, nsol = 0;
+  for (int c = b; c < e; ++c) {
+    int k = G.kind[c];
+    nirr += k == KIND_IRREGULAR;
+    nmem += k == KIND_MEMBER;
+    nsol += k == KIND_SOLID;
+  }
+  int tot_irr, tot_mem, tot_sol;
+  int off = block_exclusive_scan(nirr, sh, &tot_irr);
+  block_exclusive_scan(nmem, sh, &tot_mem);
+  block_exclusive_scan(nsol, sh, &tot_sol);
+  for (int c = b; c < e; ++c)
+    if (G.kind[c] == KIND_IRREGULAR) G.irr[off++] = c;
+  if (t == 0) { G.counts[0] = tot_irr; G.counts[1] = tot_mem; G.counts[2] = tot_sol; }
+  __syncthreads();
+  // member counts per listed master, then CSR pointers by a chunked scan
+  int carry = 0;
+  for (int base = 0; base < tot_irr; base += blockDim.x) {
+    int q = base + t, cnt = 0;
+    if (q < tot_irr) {
+      int m = G.irr[q], i = m % G.nx, j = m / G.nx;
+      for (int jj = max(j - kHopCap, 0); jj <= min(j + kHopCap, G.ny - 1); ++jj)
+        for (int ii = max(i - kHopCap, 0); ii <= min(i + kHopCap, G.nx - 1); ++ii)
+          cnt += G.master[jj * G.nx + ii] == m;
+    }
+    int tot;
+    int ex = block_exclusive_scan(cnt, sh, &tot);
+    if (q < tot_irr) G.mptr[q] = carry + ex;
+    carry += tot;
+  }
+  if (t == 0) G.mptr[tot_irr] = carry;
+  __syncthreads();
+  for (int q = t; q < tot_irr; q += blockDim.x) {
+    int m = G.irr[q], i = m % G.nx, j = m / G.nx, w = G.mptr[q];
+    for (int jj = max(j - kHopCap, 0); jj <= min(j + kHopCap, G.ny - 1); ++jj)
+      for (int ii = max(i - kHopCap, 0); ii <= min(i + kHopCap, G.nx - 1); ++ii) {
+        int k = jj * G.nx + ii;
+        if (G.master[k] == m) G.mem[w++] = k;
+      }
+  }
+}
+
+// velocity nodes (midpoints of the velocity box) and farfield table
+__global__ void k_tables2d(Geo2D G, double vmin, double dv, double rho, double ux,
+                           double uy, double T) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < G.N) G.vnode[p] = vmin + (p + 0.5) * dv;
+  if (p >= G.nvel) return;
+  double vx = vmin + (p % G.N + 0.5) * dv, vy = vmin + (p / G.N + 0.5) * dv;
+  double ex = vx - ux, ey = vy - uy;
+  double f = rho / (2.0 * M_PI * T) * exp(-(ex * ex + ey * ey) / (2.0 * T));
+  G.ghost[p] = make_double2(f, 0.5 * T * f);
+}
+
+}  // namespace
+
+hipError_t build_geometry_2d(cc_ctx* ctx, double cx, double cy, double theta) {
+  Geo2D& G = ctx->g2;
+  BodyDev B{};
+  B.kind = ctx->body.kind;
+  B.a = ctx->body.axes[0]; B.b = ctx->body.axes[1];
+  B.t_wall = ctx->body.t_wall;
+  hipStream_t s = ctx->stream;
+  hipError_t e = hipMemsetAsync(G.counts, 0, 4 * sizeof(int), s);
+  if (e != hipSuccess) return e;
+  int nv = (G.nx + 1) * (G.ny + 1);
+  k_phi2d<<<(nv + 255) / 256, 256, 0, s>>>(G, B, cx, cy, theta);
+  k_cell2d<<<(G.ncell + 255) / 256, 256, 0, s>>>(G);
+  k_master2d<<<(G.ncell + 255) / 256, 256, 0, s>>>(G);
+  k_cv2d<<<(G.ncell + 255) / 256, 256, 0, s>>>(G);
+  k_compact2d<<<1, 1024, 0, s>>>(G);
+  const double* in = ctx->cfg.inflow;
+  int nt = G.nvel > G.N ? G.nvel : G.N;
+  k_tables2d<<<(nt + 255) / 256, 256, 0, s>>>(G, ctx->cfg.vmin, ctx->dv, in[0], in[1],
+                                              in[2], in[4]);
+  return hipGetLastError();
+}
+
+}  // namespace ccdvm

@@ -1,0 +1,145 @@
+"""Python front of the ccdvm C-ABI.
+
+PyTorch only provides device memory and the stream: every step of the method
+runs in the HIP kernels of libccdvm.so, reached through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from ._capi import CCError, lib, make_body, make_config
+
+
+def _ptr(t: torch.Tensor | None):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+class Solver:
+    """One flow problem bound to one stream of one GPU."""
+
+    def __init__(self, cfg, device: str | torch.device = "cuda", stream: torch.cuda.Stream | None = None):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self._cfg = make_config(cfg)
+        self._body = make_body(cfg.body)
+        h = C.c_void_p()
+        st = lib().cc_create(C.byref(self._cfg), C.byref(self._body), C.byref(h))
+        if st != 0:
+            raise CCError(st, "cc_create rejected the configuration")
+        self._h = h
+        sb, gb, xb = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        self._check(lib().cc_workspace_bytes(h, C.byref(sb), C.byref(gb), C.byref(xb)))
+        self.dim = cfg.dim
+        self.ncell = cfg.n[0] * cfg.n[1] * cfg.n[2]
+        self.nvel = cfg.nv ** cfg.dim
+        with torch.cuda.device(self.device):
+            # caller-owned device buffers (uint8 tensors; 256-byte aligned by the caching allocator)
+            self.state = [torch.empty(sb.value, dtype=torch.uint8, device=self.device) for _ in range(2)]
+            self.geom = torch.empty(gb.value, dtype=torch.uint8, device=self.device)
+            self.scratch = torch.empty(xb.value, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self._check(lib().cc_bind(h, _ptr(self.state[0]), _ptr(self.state[1]), _ptr(self.geom),
+                                      _ptr(self.scratch), C.c_void_p(self.stream.cuda_stream)))
+
+    def _check(self, st):
+        if st != 0:
+            msg = lib().cc_last_error(self._h) if getattr(self, "_h", None) else b""
+            raise CCError(st, (msg or b"").decode())
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().cc_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- state
+    @property
+    def dt(self) -> float:
+        d = C.c_double()
+        self._check(lib().cc_dt(self._h, C.byref(d)))
+        return d.value
+
+    def init_maxwellian(self):
+        self._check(lib().cc_init_maxwellian(self._h))
+
+    def load_state(self, f: torch.Tensor, g: torch.Tensor | None = None):
+        f = f.to(self.device, torch.float64).contiguous()
+        if g is not None:
+            g = g.to(self.device, torch.float64).contiguous()
+        assert f.numel() == self.ncell * self.nvel
+        self._check(lib().cc_load_state(self._h, _ptr(f), _ptr(g)))
+        self.stream.synchronize()
+
+    def store_state(self):
+        f = torch.empty((self.ncell, self.nvel), dtype=torch.float64, device=self.device)
+        g = torch.empty_like(f) if self.dim == 2 else None
+        self._check(lib().cc_store_state(self._h, _ptr(f), _ptr(g)))
+        self.stream.synchronize()
+        return f, g
+
+    # ---------------------------------------------------------------- stepping
+    def step(self, nsteps: int = 1, diag: torch.Tensor | bool | None = None):
+        """Advance nsteps; with diag=True returns a (nsteps, 4) device tensor of
+        (Fx, Fy, torque, mass) of the state at the start of each step."""
+        d = None
+        if diag is True:
+            d = torch.empty((nsteps, 4), dtype=torch.float64, device=self.device)
+        elif isinstance(diag, torch.Tensor):
+            d = diag
+        self._check(lib().cc_step(self._h, int(nsteps), _ptr(d)))
+        return d
+
+    def moments(self) -> torch.Tensor:
+        k = 9 if self.dim == 2 else 14
+        out = torch.empty((self.ncell, k), dtype=torch.float64, device=self.device)
+        self._check(lib().cc_moments(self._h, _ptr(out)))
+        return out
+
+    def body_force(self) -> np.ndarray:
+        out = (C.c_double * 4)()
+        self._check(lib().cc_body_force(self._h, out))
+        return np.array(out[:])
+
+    def body_state(self) -> np.ndarray:
+        out = (C.c_double * 6)()
+        self._check(lib().cc_body_state(self._h, out))
+        return np.array(out[:])
+
+    def rigid_update(self, force, torque: float):
+        f = (C.c_double * 3)(*[float(x) for x in force])
+        self._check(lib().cc_rigid_update(self._h, f, float(torque)))
+
+    # ---------------------------------------------------------------- geometry
+    def geometry(self) -> dict:
+        n = self.ncell
+        out = {"type": np.zeros(n, np.int32), "master": np.zeros(n, np.int32)}
+        names = ["lxm", "lxp", "lym", "lyp", "lw", "nwx", "nwy", "rwx", "rwy", "sbar", "scv"]
+        for k in names:
+            out[k] = np.zeros(n)
+        P = lambda a: a.ctypes.data_as(C.c_void_p)
+        self._check(lib().cc_geometry_export(self._h, P(out["type"]), P(out["master"]),
+                                             *[P(out[k]) for k in names]))
+        return out
+
+    def counts(self):
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        self._check(lib().cc_geometry_counts(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    # ---------------------------------------------------------------- profiling
+    def profile_enable(self, on: bool = True):
+        self._check(lib().cc_profile_enable(self._h, int(on)))
+
+    def profile_read(self, kernel: int):
+        ms, n = C.c_double(), C.c_int()
+        self._check(lib().cc_profile_read(self._h, kernel, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
