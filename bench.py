@@ -7,7 +7,7 @@ step.  Inputs are synthetic (the flow set-up itself) and resident in HBM
 before timing starts.
 
 Prints one JSON line: whole-job cell-velocity updates per second, the
-roofline position of the dominant kernel (regular-cell stencil) measured
+roofline position of the dominant kernel (k_step2d, regular-cell stencil) measured
 with HIP events on the solver's stream, and the oracle timed on the host.
 """
 from __future__ import annotations
@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--kn", type=float, default=0.1)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy 10 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the "
@@ -82,6 +84,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calib:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": a.numel() * 8,
+                          "copy_bytes_written_per_launch": a.numel() * 8, "launches": 10}))
+        return
     from ccdvm_inputs import workload
     from paper_1503_04544_amd.solver import Solver
 
@@ -140,7 +151,7 @@ def main():
                    "cells": cfg.ncell, "active_cells": active, "velocities": nvel,
                    "cut_control_volumes": n_irr, "merged_cells": n_mem, "dt": s.dt,
                    "drag_last_step": drag_last},
-        "roofline": {"bound": "hbm", "kernel": "k_regular2d",
+        "roofline": {"bound": "hbm", "kernel": "k_step2d",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "avg_launch_us": round(avg_s * 1e6, 2),

@@ -172,11 +172,17 @@ cc_status cc_geometry_export(cc_ctx* ctx, int* type, int* master,
 cc_status cc_geometry_counts(cc_ctx* ctx, int* n_irregular, int* n_members,
                              int* n_solid);
 
+/* Rows of cells per tile of the regular-cell pass (each tile is 4 adjacent
+ * columns; one wave per column marches up the rows).  0 = automatic.
+ * Changes performance only, never results. */
+cc_status cc_set_tile_rows(cc_ctx* ctx, int rows);
+
 /* Per-kernel timing with HIP events recorded on the bound stream.
  * cc_profile_enable(ctx, 1) starts recording (cleared); cc_profile_read
- * returns, for kernel id k (0 = regular-cell step, 1 = cut-cell step,
- * 2 = force reduction, 3 = merge), the summed milliseconds and the number of
- * launches since enabling.  Reading synchronises the stream. */
+ * returns, for kernel id k (0 = fused step kernel, 1 = force-only cut-cell
+ * kernel, 2 = final reduction of a stepping call, 3 = merge), the summed
+ * milliseconds and the number of launches since enabling (at most 4096
+ * launches per kernel are recorded).  Reading synchronises the stream. */
 cc_status cc_profile_enable(cc_ctx* ctx, int on);
 cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launches);
 

@@ -92,7 +92,9 @@ void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
   size_t n = ctx->ncell;
   int nm = ctx->dim == 2 ? 4 : 5;
   ctx->s.mom = cv.take<double>(n * nm);
-  ctx->s.fslot = cv.take<double>(n * 3);
+  ctx->s.fslot = cv.take<double>(n * 3 * 2);
+  ctx->s.mpart_cap = (int)((size_t)((ctx->nx + 3) / 4) * ctx->ny * ctx->nz + n);
+  ctx->s.mpart = cv.take<double>((size_t)ctx->s.mpart_cap * 2);
   ctx->s.body = cv.take<double>(16);
   ctx->s.red = cv.take<double>(4 * 128 + 8);
   *bytes = cv.off;
@@ -333,15 +335,31 @@ cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
   if (diag) {
     HIPCHK(ctx, ctx->dim == 2 ? launch_mass_2d(ctx, diag + 3) : launch_mass_3d(ctx, diag + 3), "mass");
   }
+  if (ctx->dim == 2 && !moving) {
+    // fused step; the force/mass partials of step n are reduced by step n+1
+    for (int n = 0; n < nsteps; ++n) {
+      bool red = diag && n > 0;
+      hipError_t e = launch_step_2d_fused(ctx, red, red ? diag + 4 * (size_t)(n - 1) : nullptr,
+                                          red ? diag + 4 * (size_t)n + 3 : nullptr, diag != nullptr);
+      if (e != hipSuccess) return hip_fail(ctx, e, "step");
+    }
+    if (diag) HIPCHK(ctx, launch_step_2d_flush(ctx, diag + 4 * (size_t)(nsteps - 1), nullptr), "reduce");
+    return CC_OK;
+  }
   for (int n = 0; n < nsteps; ++n) {
     double* frow = diag ? diag + 4 * (size_t)n : nullptr;
     double* mrow = (diag && n + 1 < nsteps) ? diag + 4 * (size_t)(n + 1) + 3 : nullptr;
     hipError_t e;
     if (ctx->dim == 3) e = launch_step_3d(ctx, frow, mrow);
-    else if (moving) e = launch_moving_step_2d(ctx, frow, mrow);
-    else e = launch_step_2d(ctx, frow, mrow);
+    else e = launch_moving_step_2d(ctx, frow, mrow);
     if (e != hipSuccess) return hip_fail(ctx, e, "step");
   }
+  return CC_OK;
+}
+
+cc_status cc_set_tile_rows(cc_ctx* ctx, int rows) {
+  if (!ctx || rows < 0) return CC_EINVAL;
+  ctx->seglen = rows;
   return CC_OK;
 }
 

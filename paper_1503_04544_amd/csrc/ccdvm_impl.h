@@ -74,7 +74,9 @@ struct Geo3D {
 // Scratch layout (caller's scratch buffer).
 struct Scratch {
   double* mom;       // ncell * 4 (2D: rho, ux, uy, T) or ncell * 5 (3D: rho, u, T)
-  double* fslot;     // per irregular master: Fx, Fy, torque (2D) / Fx, Fy, Fz (3D)
+  double* fslot;     // 2 x per irregular master: Fx, Fy, torque (2D) / Fx, Fy, Fz (3D)
+  double* mpart;     // 2 x mass partials (regular tiles, then control volumes)
+  int mpart_cap;
   double* body;      // rigid body state on device: cx, cy, theta, ux, uy, omega
   double* red;       // small reduction buffer
 };
@@ -107,6 +109,9 @@ struct cc_ctx {
   bool bound = false;
   bool merged = false;     // members hold their control-volume value
   bool mom_valid = false;  // scratch.mom holds the moments of the current state
+  int step_parity = 0;     // which half of the double-buffered partials the next step writes
+  int last_args_ntiles = 0;
+  int seglen = 0;          // rows per regular-cell tile (0: automatic)
   ccdvm::Geo2D g2;
   ccdvm::Geo3D g3;
   ccdvm::Scratch s;
@@ -129,7 +134,9 @@ hipError_t launch_load_state_2d(cc_ctx* ctx, const double* f, const double* g);
 hipError_t launch_store_state_2d(const cc_ctx* ctx, double* f, double* g);
 hipError_t launch_merge_2d(cc_ctx* ctx);
 hipError_t launch_moments_all_2d(cc_ctx* ctx);
-hipError_t launch_step_2d(cc_ctx* ctx, double* force_row, double* mass_row);
+hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_force_row,
+                                double* cur_mass_row, bool record);
+hipError_t launch_step_2d_flush(cc_ctx* ctx, double* force_row, double* mass_row);
 hipError_t launch_mass_2d(cc_ctx* ctx, double* mass_row);
 hipError_t launch_moments_out_2d(cc_ctx* ctx, double* out);
 

@@ -47,71 +47,6 @@ struct StepParams {
   int write_state;        // 0: cut-cell kernel only computes the wall forces
 };
 
-// ---------------------------------------------------------------------
-// Regular gas cells: fused transport + relaxation + moments of the result.
-// NCH = number of 64-velocity chunks per cell (ceil(N^2 / 64)).
-// ---------------------------------------------------------------------
-template <int NCH>
-__global__ void __launch_bounds__(256) k_regular2d(Geo2D G, const double2* __restrict__ in,
-                                                   double2* __restrict__ out,
-                                                   double* __restrict__ mom, StepParams P) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int c = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
-  if (c >= G.ncell) return;
-  if (G.kind[c] != KIND_REGULAR) return;
-  const int N = G.N, nvel = G.nvel, nx = G.nx;
-  const int i = c % nx, j = c / nx;
-  const double rho = mom[4 * c + 0], ux = mom[4 * c + 1], uy = mom[4 * c + 2], T = mom[4 * c + 3];
-  const double inv2T = 0.5 / T;
-  const double A = rho / (2.0 * M_PI * T);
-  const double dtau = P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
-  // separable Maxwellian: lane l < N holds exp(-(v_l - u)^2 / 2T) per axis
-  double tx = 0.0, ty = 0.0;
-  if (lane < N) {
-    double v = vnode(P.vmin, P.dv, lane);
-    tx = exp(-(v - ux) * (v - ux) * inv2T);
-    ty = exp(-(v - uy) * (v - uy) * inv2T);
-  }
-  const double S = G.dx * G.dy;
-  const double cxf = P.dt / S * G.dy, cyf = P.dt / S * G.dx;
-  const double2* incell = in + (size_t)c * nvel;
-  double2* outcell = out + (size_t)c * nvel;
-  double sr = 0.0, smx = 0.0, smy = 0.0, se = 0.0;
-#pragma unroll 4
-  for (int k = 0; k < NCH; ++k) {
-    const int p = k * kWave + lane;
-    const bool ok = p < nvel;
-    const int pp = ok ? p : 0;
-    const int p1 = pp % N, p2 = pp / N;
-    const double vx = vnode(P.vmin, P.dv, p1), vy = vnode(P.vmin, P.dv, p2);
-    const double2 own = incell[pp];
-    double2 xu, yu;
-    if (vx > 0.0) xu = i > 0 ? incell[pp - (ptrdiff_t)nvel] : G.ghost[pp];
-    else xu = i + 1 < nx ? incell[pp + (ptrdiff_t)nvel] : G.ghost[pp];
-    if (vy > 0.0) yu = j > 0 ? incell[pp - (ptrdiff_t)nx * nvel] : G.ghost[pp];
-    else yu = j + 1 < G.ny ? incell[pp + (ptrdiff_t)nx * nvel] : G.ghost[pp];
-    const double ax = cxf * fabs(vx), ay = cyf * fabs(vy);
-    const double E = A * __shfl(tx, p1, kWave) * __shfl(ty, p2, kWave);
-    double fn = own.x - ax * (own.x - xu.x) - ay * (own.x - yu.x) + dtau * (E - own.x);
-    double gn = own.y - ax * (own.y - xu.y) - ay * (own.y - yu.y) + dtau * (0.5 * T * E - own.y);
-    if (ok) {
-      outcell[p] = make_double2(fn, gn);
-      sr += fn;
-      smx += vx * fn;
-      smy += vy * fn;
-      se += 0.5 * (vx * vx + vy * vy) * fn + gn;
-    }
-  }
-  sr = wave_sum(sr); smx = wave_sum(smx); smy = wave_sum(smy); se = wave_sum(se);
-  if (lane == 0) {
-    double r = sr * P.w, mx = smx * P.w / r, my = smy * P.w / r, e = se * P.w;
-    mom[4 * c + 0] = r;
-    mom[4 * c + 1] = mx;
-    mom[4 * c + 2] = my;
-    mom[4 * c + 3] = (2.0 * e / r - (mx * mx + my * my)) / 3.0;
-  }
-}
-
 __device__ inline void wall_velocity(const double* body, double rx, double ry, double* uwx,
                                      double* uwy) {
   // u_w = u_sol + (r - c)^perp omega, a^perp = (-a_y, a_x)
@@ -124,18 +59,31 @@ __device__ inline double maxw_wall(double vx, double vy, double uwx, double uwy,
   return exp(-(ex * ex + ey * ey) / (2.0 * Tw)) / (2.0 * M_PI * Tw);
 }
 
+// Block-wide sum over the 4 waves of a 256-thread block; every thread gets
+// the total.  Waves are added in wave order (deterministic).
+__device__ inline double block_sum4(double v, double* lds) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[wave] = v;
+  __syncthreads();
+  return ((lds[0] + lds[1]) + lds[2]) + lds[3];
+}
+
 // ---------------------------------------------------------------------
-// Control volumes that are cut or own merged cells: one wave each.
-// fslot[q] receives (Fx, Fy, torque) of the wall edges of the control volume
-// from the state being advanced (eqs. StressTensorDD, eq-force, eq-torque).
+// One control volume that is cut or owns merged cells, by a block of 256
+// threads (velocities strided over the block).  Wall density of each wall
+// edge (eq. BoundaryDDv), fluxes of all members' edges (eq. FluxDD), the
+// explicit update with relaxation (eq. ExSchemeDD), redistribution to all
+// members (eq. UpdateDD), wall stress -> force and torque of the state at
+// t^n (eqs. StressTensorDD, eq-force, eq-torque), moments and mass of the
+// new value.  With write_state == 0 only the force is produced.
 // ---------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_cut2d(Geo2D G, const double2* __restrict__ in,
-                                              double2* __restrict__ out,
-                                              double* __restrict__ mom,
-                                              double* __restrict__ fslot,
-                                              const double* __restrict__ body, StepParams P) {
-  const int q = blockIdx.x;
-  const int lane = threadIdx.x;
+__device__ void cut_cv(const Geo2D& G, const double2* __restrict__ in, double2* __restrict__ out,
+                       double* __restrict__ mom, double* __restrict__ fslot,
+                       double* __restrict__ mpart, const double* __restrict__ body,
+                       const StepParams& P, int q, double* lds) {
+  const int tid = threadIdx.x, nth = blockDim.x;
   const int m = G.irr[q];
   const int b = G.mptr[q], e = G.mptr[q + 1];
   const int nm = e - b;
@@ -146,7 +94,6 @@ __global__ void __launch_bounds__(64) k_cut2d(Geo2D G, const double2* __restrict
   const double S = G.scv[m];
   const double2* own = in + (size_t)m * nvel;
   const double Tw = P.t_wall;
-  // wall density of every wall edge of the control volume
   double phiw[kMaxMembers], uwx[kMaxMembers], uwy[kMaxMembers];
   for (int t = 0; t < nm; ++t) {
     const int k = G.mem[b + t];
@@ -155,20 +102,20 @@ __global__ void __launch_bounds__(64) k_cut2d(Geo2D G, const double2* __restrict
     wall_velocity(body, G.rwx[k], G.rwy[k], &uwx[t], &uwy[t]);
     const double nwx = G.nwx[k], nwy = G.nwy[k];
     double num = 0.0, den = 0.0;
-    for (int p = lane; p < nvel; p += kWave) {
+    for (int p = tid; p < nvel; p += nth) {
       const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
       const double cn = (vx - uwx[t]) * nwx + (vy - uwy[t]) * nwy;
       if (cn > 0.0) num += cn * own[p].x;
       else if (cn < 0.0) den += cn * maxw_wall(vx, vy, uwx[t], uwy[t], Tw);
     }
-    num = wave_sum(num);
-    den = wave_sum(den);
+    num = block_sum4(num, lds);
+    den = block_sum4(den, lds);
     phiw[t] = den != 0.0 ? -num / den : 0.0;
   }
   double sx[kMaxMembers], sy[kMaxMembers];
   for (int t = 0; t < kMaxMembers; ++t) { sx[t] = 0.0; sy[t] = 0.0; }
   double sr = 0.0, smx = 0.0, smy = 0.0, se = 0.0;
-  for (int p = lane; p < nvel; p += kWave) {
+  for (int p = tid; p < nvel; p += nth) {
     const int p1 = p % N, p2 = p / N;
     const double vx = vnode(P.vmin, P.dv, p1), vy = vnode(P.vmin, P.dv, p2);
     const double vxm = fmin(vx, 0.0), vxp = fmax(vx, 0.0);
@@ -180,22 +127,22 @@ __global__ void __launch_bounds__(64) k_cut2d(Geo2D G, const double2* __restrict
       const int i = k % nx, j = k / nx;
       const double Lr = G.lxp[k], Ll = G.lxm[k], Lt = G.lyp[k], Lb = G.lym[k];
       if (Lr > 0.0) {
-        double2 nb = i + 1 < nx ? in[(size_t)(k + 1) * nvel + p] : G.ghost[p];
+        const double2 nb = i + 1 < nx ? in[(size_t)(k + 1) * nvel + p] : G.ghost[p];
         Rf += Lr * (vxm * nb.x + vxp * o.x);
         Rg += Lr * (vxm * nb.y + vxp * o.y);
       }
       if (Ll > 0.0) {
-        double2 nb = i > 0 ? in[(size_t)(k - 1) * nvel + p] : G.ghost[p];
+        const double2 nb = i > 0 ? in[(size_t)(k - 1) * nvel + p] : G.ghost[p];
         Rf -= Ll * (vxm * o.x + vxp * nb.x);
         Rg -= Ll * (vxm * o.y + vxp * nb.y);
       }
       if (Lt > 0.0) {
-        double2 nb = j + 1 < ny ? in[(size_t)(k + nx) * nvel + p] : G.ghost[p];
+        const double2 nb = j + 1 < ny ? in[(size_t)(k + nx) * nvel + p] : G.ghost[p];
         Rf += Lt * (vym * nb.x + vyp * o.x);
         Rg += Lt * (vym * nb.y + vyp * o.y);
       }
       if (Lb > 0.0) {
-        double2 nb = j > 0 ? in[(size_t)(k - nx) * nvel + p] : G.ghost[p];
+        const double2 nb = j > 0 ? in[(size_t)(k - nx) * nvel + p] : G.ghost[p];
         Rf -= Lb * (vym * o.x + vyp * nb.x);
         Rg -= Lb * (vym * o.y + vyp * nb.y);
       }
@@ -227,17 +174,17 @@ __global__ void __launch_bounds__(64) k_cut2d(Geo2D G, const double2* __restrict
   double Fx = 0.0, Fy = 0.0, Tq = 0.0;
   for (int t = 0; t < nm; ++t) {
     const int k = G.mem[b + t];
-    const double ax = wave_sum(sx[t]) * P.w, ay = wave_sum(sy[t]) * P.w;
-    if (G.lw[k] > 0.0) {
-      Fx += ax * G.lw[k];
-      Fy += ay * G.lw[k];
-      Tq += ((G.rwx[k] - body[0]) * ay - (G.rwy[k] - body[1]) * ax) * G.lw[k];
-    }
+    if (!(G.lw[k] > 0.0)) continue;
+    const double ax = block_sum4(sx[t], lds) * P.w, ay = block_sum4(sy[t], lds) * P.w;
+    Fx += ax * G.lw[k];
+    Fy += ay * G.lw[k];
+    Tq += ((G.rwx[k] - body[0]) * ay - (G.rwy[k] - body[1]) * ax) * G.lw[k];
   }
-  sr = wave_sum(sr); smx = wave_sum(smx); smy = wave_sum(smy); se = wave_sum(se);
-  if (lane == 0) {
-    double r = sr * P.w, mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
-    double Tn = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
+  sr = block_sum4(sr, lds); smx = block_sum4(smx, lds);
+  smy = block_sum4(smy, lds); se = block_sum4(se, lds);
+  if (tid == 0) {
+    const double r = sr * P.w, mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
+    const double Tn = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
     if (P.write_state)
       for (int t = 0; t < nm; ++t) {
         const int k = G.mem[b + t];
@@ -246,7 +193,251 @@ __global__ void __launch_bounds__(64) k_cut2d(Geo2D G, const double2* __restrict
     fslot[3 * q + 0] = Fx;
     fslot[3 * q + 1] = Fy;
     fslot[3 * q + 2] = Tq;
+    if (mpart) *mpart = S * r;
   }
+}
+
+__global__ void __launch_bounds__(256) k_cut_force2d(Geo2D G, const double2* __restrict__ in,
+                                                     double* __restrict__ mom,
+                                                     double* __restrict__ fslot,
+                                                     const double* __restrict__ body,
+                                                     StepParams P) {
+  __shared__ double lds[8];
+  cut_cv(G, in, nullptr, mom, fslot, nullptr, body, P, blockIdx.x, lds);
+}
+
+// ---------------------------------------------------------------------
+// The fused step: one launch per time step.
+// Two launches per time step.  k_cutstep2d: one 256-thread block per cut /
+// merged control volume (kept apart so that its per-member bookkeeping does
+// not set the register budget of the streaming kernel).  k_step2d:
+//   block 0           deferred deterministic reduction of the previous
+//                     step's force slots and mass partials into diag
+//   blocks 8..        regular-cell tiles: kTileW adjacent columns x a
+//                     segment of rows, one wave per column marching up
+//                     the rows.  The wave keeps in registers the upper
+//                     velocity half (v_y > 0) of the cell below and the
+//                     lower half (v_y < 0) of the current cell, so every
+//                     value of the state is loaded from HBM once; the x
+//                     upwind neighbour comes from the adjacent wave's loads
+//                     through L2.  Tiles are mapped so that the tiles of
+//                     one XCD are adjacent columns of the same rows.
+// ---------------------------------------------------------------------
+constexpr int kTileW = 4;   // columns (waves) per tile
+#ifndef CCDVM_PREFETCH
+#define CCDVM_PREFETCH 4
+#endif
+// Chunks loaded ahead of the one computed.  Each chunk in flight costs 16
+// VGPRs and the row window 8 per chunk; the depth is capped so that a wave
+// stays within 256 VGPRs (2 waves per SIMD) without spilling.
+constexpr int prefetch_depth(int nch) {
+  int cap = (138 - 8 * nch) / 16;
+  int d = CCDVM_PREFETCH < cap ? CCDVM_PREFETCH : cap;
+  d = d < 1 ? 1 : d;
+  return d < nch - 1 ? d : (nch - 1 > 0 ? nch - 1 : 0);
+}
+
+struct FusedArgs {
+  const double2* in;
+  double2* out;
+  double* mom;
+  double* fslot;            // this step: 3 per control volume
+  double* mpart;            // this step: ntiles tile partials, then n_irr
+  const double* prev_fslot; // previous step (deferred reduction), may be null
+  const double* prev_mpart;
+  double* red_force;        // diag row of the previous step (force, torque)
+  double* red_mass;         // diag mass of the state entering this step
+  const double* body;
+  int n_cut, cut_base;      // cut blocks start at block cut_base
+  int ntiles, tile_base, ntiles_pad;
+  int ngroups, seglen;
+  int split;                // number of velocity rows with v_y < 0
+};
+
+__device__ void deferred_reduce(const Geo2D& G, const FusedArgs& A, double* lds) {
+  const int nparts = A.ntiles + A.n_cut;
+  double ms = 0.0, fx = 0.0, fy = 0.0, tq = 0.0;
+  for (int t = threadIdx.x; t < nparts; t += blockDim.x) ms += A.prev_mpart[t];
+  for (int q = threadIdx.x; q < A.n_cut; q += blockDim.x) {
+    fx += A.prev_fslot[3 * q]; fy += A.prev_fslot[3 * q + 1]; tq += A.prev_fslot[3 * q + 2];
+  }
+  ms = block_sum4(ms, lds); fx = block_sum4(fx, lds);
+  fy = block_sum4(fy, lds); tq = block_sum4(tq, lds);
+  if (threadIdx.x == 0) {
+    if (A.red_force) { A.red_force[0] = fx; A.red_force[1] = fy; A.red_force[2] = tq; }
+    if (A.red_mass) A.red_mass[0] = ms;
+  }
+}
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// load one velocity half of a cell row (or of the farfield table)
+template <int NCH>
+__device__ inline void load_half(d2v (&dst)[NCH], const d2v* __restrict__ row, int base,
+                                 int count, int lane) {
+#pragma unroll
+  for (int k = 0; k < NCH; ++k) {
+    const int o = k * 64 + lane;
+    dst[k] = o < count ? row[base + o] : d2v{0.0, 0.0};
+  }
+}
+
+// One tile of regular cells.  Velocity rows [0, split) have v_y < 0 (lower
+// half, y-upwind neighbour above), rows [split, N) have v_y >= 0 (upper
+// half, y-upwind neighbour below).  Both halves are walked together, chunk
+// by chunk: chunk k of either half holds the same p1 for a given lane, so
+// the x-upwind cell and the x part of the Maxwellian are shared.
+template <int NCH>
+__device__ void regular_tile(const Geo2D& G, const FusedArgs& A, const StepParams& P, int tile,
+                             double* lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gi = tile % A.ngroups, seg = tile / A.ngroups;
+  const int i = gi * kTileW + wave;
+  const int nx = G.nx, ny = G.ny, N = G.N, nvel = G.nvel;
+  const int j0 = seg * A.seglen, j1 = min(j0 + A.seglen, ny);
+  const int split = A.split;
+  const int lo_n = split * N, hi_n = nvel - lo_n;   // sizes of the two halves
+  const d2v* in = reinterpret_cast<const d2v*>(A.in);
+  d2v* out = reinterpret_cast<d2v*>(A.out);
+  const d2v* ghost = reinterpret_cast<const d2v*>(G.ghost);
+  double msum = 0.0;
+  if (i < nx && j0 < j1) {
+    const double S = G.dx * G.dy;
+    const double cxf = P.dt / S * G.dy, cyf = P.dt / S * G.dx;
+    d2v prevU[NCH], curL[NCH];
+    load_half<NCH>(prevU, j0 > 0 ? in + (size_t)((j0 - 1) * nx + i) * nvel : ghost, lo_n, hi_n, lane);
+    load_half<NCH>(curL, in + (size_t)(j0 * nx + i) * nvel, 0, lo_n, lane);
+    for (int j = j0; j < j1; ++j) {
+      const int c = j * nx + i;
+      const d2v* row = in + (size_t)c * nvel;
+      const d2v* nrow = j + 1 < ny ? row + (size_t)nx * nvel : ghost;
+      const bool reg = G.kind[c] == KIND_REGULAR;   // uniform over the wave
+      double Am = 0.0, T = 1.0, dtau = 0.0, tx = 0.0, ty = 0.0;
+      if (reg) {
+        const double* mc = A.mom + 4 * c;
+        const double rho = mc[0], ux = mc[1], uy = mc[2];
+        T = mc[3];
+        const double inv2T = 0.5 / T;
+        Am = rho / (2.0 * M_PI * T);
+        dtau = P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
+        if (lane < N) {
+          const double v = vnode(P.vmin, P.dv, lane);
+          tx = exp(-(v - ux) * (v - ux) * inv2T);
+          ty = exp(-(v - uy) * (v - uy) * inv2T);
+        }
+      }
+      const d2v* xl = i > 0 ? row - nvel : ghost;        // x-upwind for v_x > 0
+      const d2v* xr = i + 1 < nx ? row + nvel : ghost;   // x-upwind for v_x < 0
+      d2v* orow = out + (size_t)c * nvel;
+      double sr = 0.0, smx = 0.0, smy = 0.0, se = 0.0;
+      // software pipeline over the chunks: the loads of chunk k+PD are issued
+      // before chunk k is computed; a scheduling barrier between chunks keeps
+      // the live set to the window plus PD+1 chunks.
+      // The per-chunk velocity constants are the same for every row; they are
+      // recomputed per row (a few ALU ops) instead of being held in registers
+      // across the row loop, which would cost ~10 VGPRs per chunk.
+      int lv = lane;
+      asm volatile("" : "+v"(lv));
+      constexpr int PD = prefetch_depth(NCH);
+      d2v bN[NCH], bU[NCH], bXa[NCH], bXb[NCH];
+      auto issue = [&](int k) {
+        const int o = k * 64 + lv;
+        const int lp1 = o % N;
+        const d2v* xrow = vnode(P.vmin, P.dv, lp1) > 0.0 ? xl : xr;
+        bN[k] = o < lo_n ? nrow[o] : d2v{0.0, 0.0};
+        bU[k] = o < hi_n ? row[lo_n + o] : d2v{0.0, 0.0};
+        bXa[k] = reg && o < lo_n ? xrow[o] : d2v{0.0, 0.0};
+        bXb[k] = reg && o < hi_n ? xrow[lo_n + o] : d2v{0.0, 0.0};
+      };
+#pragma unroll
+      for (int k = 0; k < PD; ++k) issue(k);
+#pragma unroll
+      for (int k = 0; k < NCH; ++k) {
+        if (k + PD < NCH) issue(k + PD);
+        const int o = k * 64 + lv;
+        const d2v nL = bN[k], cU = bU[k], xa = bXa[k], xb = bXb[k];
+        if (reg) {
+          const int p1 = o % N, q2 = o / N;
+          const double vx = vnode(P.vmin, P.dv, p1);
+          const double ax = cxf * fabs(vx);
+          const double ex = Am * __shfl(tx, p1, 64);
+          const double tyl = __shfl(ty, q2 < N ? q2 : 0, 64);
+          const double tyu = __shfl(ty, split + q2 < N ? split + q2 : 0, 64);
+          if (o < lo_n) {   // lower half: v_y < 0, y-upwind is the cell above
+            const double vy = vnode(P.vmin, P.dv, q2);
+            const double ay = cyf * fabs(vy), E = ex * tyl;
+            const d2v own = curL[k];
+            const double fn = own.x - ax * (own.x - xa.x) - ay * (own.x - nL.x) + dtau * (E - own.x);
+            const double gn = own.y - ax * (own.y - xa.y) - ay * (own.y - nL.y) +
+                              dtau * (0.5 * T * E - own.y);
+            __builtin_nontemporal_store(d2v{fn, gn}, &orow[o]);
+            sr += fn; smx += vx * fn; smy += vy * fn;
+            se += 0.5 * (vx * vx + vy * vy) * fn + gn;
+          }
+          if (o < hi_n) {   // upper half: v_y >= 0, y-upwind is the cell below
+            const double vy = vnode(P.vmin, P.dv, split + q2);
+            const double ay = cyf * fabs(vy), E = ex * tyu;
+            const d2v own = cU, yu = prevU[k];
+            const double fn = own.x - ax * (own.x - xb.x) - ay * (own.x - yu.x) + dtau * (E - own.x);
+            const double gn = own.y - ax * (own.y - xb.y) - ay * (own.y - yu.y) +
+                              dtau * (0.5 * T * E - own.y);
+            __builtin_nontemporal_store(d2v{fn, gn}, &orow[lo_n + o]);
+            sr += fn; smx += vx * fn; smy += vy * fn;
+            se += 0.5 * (vx * vx + vy * vy) * fn + gn;
+          }
+        }
+        prevU[k] = cU;
+        curL[k] = nL;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (reg) {
+        sr = wave_sum(sr); smx = wave_sum(smx); smy = wave_sum(smy); se = wave_sum(se);
+        const double r = sr * P.w;
+        if (lane == 0) {
+          const double mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
+          double* mo = A.mom + 4 * c;
+          mo[0] = r; mo[1] = mx; mo[2] = my;
+          mo[3] = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
+        }
+        msum += S * r;
+      }
+    }
+  }
+  __syncthreads();
+  if (lane == 0) lds[wave] = msum;
+  __syncthreads();
+  if (threadIdx.x == 0) A.mpart[tile] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+}
+
+// regular-cell tiles (+ block 0: deferred reduction of the previous step)
+template <int NCH>
+__global__ void __launch_bounds__(256) k_step2d(Geo2D G, FusedArgs A, StepParams P) {
+  __shared__ double lds[8];
+  const int bid = blockIdx.x;
+  if (bid < A.tile_base) {
+    if (bid == 0 && A.prev_mpart) deferred_reduce(G, A, lds);
+    return;
+  }
+  // XCD-aware order: block b runs on XCD b % 8; the tiles of one XCD are
+  // contiguous in the tile order (adjacent columns, same rows)
+  const int b = bid - A.tile_base;
+  const int per = A.ntiles_pad / 8;
+  const int tile = (b % 8) * per + b / 8;
+  if (tile >= A.ntiles) return;
+  regular_tile<NCH>(G, A, P, tile, lds);
+}
+
+// cut / merged control volumes of one step, one 256-thread block each
+__global__ void __launch_bounds__(256) k_cutstep2d(Geo2D G, FusedArgs A, StepParams P) {
+  __shared__ double lds[8];
+  const int q = blockIdx.x;
+  cut_cv(G, A.in, A.out, A.mom, A.fslot, A.mpart + A.ntiles + q, A.body, P, q, lds);
+}
+
+// final reduction of the last step of a call (same code as the deferred one)
+__global__ void __launch_bounds__(256) k_final_reduce2d(Geo2D G, FusedArgs A) {
+  __shared__ double lds[8];
+  deferred_reduce(G, A, lds);
 }
 
 // ---------------------------------------------------------------------
@@ -443,56 +634,73 @@ StepParams params2d(const cc_ctx* ctx) {
   return P;
 }
 
+typedef void (*fused_fn)(const cc_ctx*, dim3, const FusedArgs&, const StepParams&);
+
 template <int NCH>
-void launch_regular(const cc_ctx* ctx, const double2* in, double2* out, double* mom,
-                    const StepParams& P) {
-  const int cells_per_block = 4;
-  dim3 grid((ctx->ncell + cells_per_block - 1) / cells_per_block);
-  k_regular2d<NCH><<<grid, 256, 0, ctx->stream>>>(ctx->g2, in, out, mom, P);
+void launch_fused(const cc_ctx* ctx, dim3 grid, const FusedArgs& A, const StepParams& P) {
+  k_step2d<NCH><<<grid, 256, 0, ctx->stream>>>(ctx->g2, A, P);
 }
 
-typedef void (*regular_fn)(const cc_ctx*, const double2*, double2*, double*, const StepParams&);
-
-regular_fn pick_regular(int nch) {
+fused_fn pick_fused(int nch) {
   switch (nch) {
-    case 1: return launch_regular<1>;
-    case 2: return launch_regular<2>;
-    case 3: return launch_regular<3>;
-    case 4: return launch_regular<4>;
-    case 5: return launch_regular<5>;
-    case 6: return launch_regular<6>;
-    case 7: return launch_regular<7>;
-    case 8: return launch_regular<8>;
-    case 9: return launch_regular<9>;
-    case 10: return launch_regular<10>;
-    case 12: return launch_regular<12>;
-    case 16: return launch_regular<16>;
-    case 20: return launch_regular<20>;
-    case 25: return launch_regular<25>;
-    case 32: return launch_regular<32>;
-    case 36: return launch_regular<36>;
-    case 49: return launch_regular<49>;
-    case 64: return launch_regular<64>;
+    case 1: return launch_fused<1>;
+    case 2: return launch_fused<2>;
+    case 3: return launch_fused<3>;
+    case 4: return launch_fused<4>;
+    case 5: return launch_fused<5>;
+    case 6: return launch_fused<6>;
+    case 7: return launch_fused<7>;
+    case 8: return launch_fused<8>;
+    case 9: return launch_fused<9>;
+    case 10: return launch_fused<10>;
+    case 11: return launch_fused<11>;
+    case 12: return launch_fused<12>;
+    case 13: return launch_fused<13>;
+    case 14: return launch_fused<14>;
+    case 16: return launch_fused<16>;
+    case 18: return launch_fused<18>;
+    case 20: return launch_fused<20>;
+    case 24: return launch_fused<24>;
+    case 28: return launch_fused<28>;
+    case 32: return launch_fused<32>;
     default: return nullptr;
   }
 }
 
+// rows of the velocity grid with v_y < 0 (the lower half of a cell row)
+int split_rows(const cc_ctx* ctx) {
+  int s = 0;
+  for (int p = 0; p < ctx->N; ++p) s += (ctx->cfg.vmin + (p + 0.5) * ctx->dv) < 0.0;
+  return s;
+}
+
+int chunks_per_half(const cc_ctx* ctx) {
+  int s = split_rows(ctx);
+  int rows = s > ctx->N - s ? s : ctx->N - s;
+  return (rows * ctx->N + 63) / 64;
+}
+
 }  // namespace
 
-bool regular_supported_2d(int nvel) { return pick_regular((nvel + 63) / 64) != nullptr; }
+bool regular_supported_2d(int nvel) {
+  // the half-row window holds at most 32 chunks of 64 velocities per half
+  int n = (int)lround(sqrt((double)nvel));
+  return pick_fused((((n + 1) / 2) * n + 63) / 64) != nullptr;
+}
 
 hipError_t launch_force_only_2d(cc_ctx* ctx, double* out4) {
   StepParams P = params2d(ctx);
   P.write_state = 0;
   const double2* in = (const double2*)ctx->state[ctx->cur];
   if (ctx->n_irr > 0)
-    k_cut2d<<<ctx->n_irr, 64, 0, ctx->stream>>>(ctx->g2, in, (double2*)ctx->state[1 - ctx->cur],
-                                                 ctx->s.mom, ctx->s.fslot, ctx->s.body, P);
+    k_cut_force2d<<<ctx->n_irr, 256, 0, ctx->stream>>>(ctx->g2, in, ctx->s.mom, ctx->s.fslot,
+                                                       ctx->s.body, P);
   k_reduce2d<<<kRedBlocks, 256, 0, ctx->stream>>>(
       ctx->g2, ctx->s.mom, ctx->s.fslot, ctx->s.red,
       reinterpret_cast<unsigned int*>(ctx->s.red + 4 * kRedBlocks), out4, out4 + 3);
   return hipGetLastError();
 }
+
 
 hipError_t launch_init_maxwellian_2d(cc_ctx* ctx) {
   size_t tot = (size_t)ctx->ncell * ctx->nvel;
@@ -547,37 +755,84 @@ hipError_t launch_mass_2d(cc_ctx* ctx, double* mass_row) {
   return hipGetLastError();
 }
 
-// One step: state[cur] -> state[1-cur].  force_row (nullable) receives the
-// force and torque of the state at t^n; mass_row (nullable) the mass of the
-// state at t^{n+1}.
-hipError_t launch_step_2d(cc_ctx* ctx, double* force_row, double* mass_row) {
+// Tile shape of the regular-cell pass: kTileW columns x seglen rows.
+int tile_rows(const cc_ctx* ctx) {
+  if (ctx->seglen > 0) return ctx->seglen;
+  // aim for ~4 resident tiles per CU on 256 CUs
+  const int groups = (ctx->nx + kTileW - 1) / kTileW;
+  int segs = (1024 + groups - 1) / groups;
+  if (segs < 1) segs = 1;
+  int rows = (ctx->ny + segs - 1) / segs;
+  return rows < 1 ? 1 : rows;
+}
+
+// One step: state[cur] -> state[1-cur].  When diag is requested, this
+// launch also reduces the previous step's partials (deferred) into
+// diag rows; the last step's are reduced by cc_step through
+// launch_step_2d_flush.
+hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_force_row,
+                                double* cur_mass_row, bool record) {
   StepParams P = params2d(ctx);
-  const double2* in = (const double2*)ctx->state[ctx->cur];
-  double2* out = (double2*)ctx->state[1 - ctx->cur];
-  int nch = (ctx->nvel + 63) / 64;
-  regular_fn fn = pick_regular(nch);
+  fused_fn fn = pick_fused(chunks_per_half(ctx));
   if (!fn) return hipErrorInvalidValue;
-  prof_begin(ctx, 0);
-  fn(ctx, in, out, ctx->s.mom, P);
-  prof_end(ctx, 0);
-  if (ctx->n_irr > 0) {
+  const int par = ctx->step_parity;
+  FusedArgs A;
+  A.in = (const double2*)ctx->state[ctx->cur];
+  A.out = (double2*)ctx->state[1 - ctx->cur];
+  A.mom = ctx->s.mom;
+  A.body = ctx->s.body;
+  A.ngroups = (ctx->nx + kTileW - 1) / kTileW;
+  A.seglen = tile_rows(ctx);
+  const int nseg = (ctx->ny + A.seglen - 1) / A.seglen;
+  A.ntiles = A.ngroups * nseg;
+  A.ntiles_pad = (A.ntiles + 7) / 8 * 8;
+  A.n_cut = ctx->n_irr;
+  A.cut_base = 0;
+  A.tile_base = 8;
+  A.split = split_rows(ctx);
+  const int nparts = A.ntiles + A.n_cut;
+  double* fs[2] = {ctx->s.fslot, ctx->s.fslot + 3 * (size_t)ctx->ncell};
+  double* mp[2] = {ctx->s.mpart, ctx->s.mpart + (size_t)ctx->s.mpart_cap};
+  if (nparts > ctx->s.mpart_cap) return hipErrorInvalidValue;
+  A.fslot = fs[par];
+  A.mpart = mp[par];
+  A.prev_fslot = reduce_prev ? fs[1 - par] : nullptr;
+  A.prev_mpart = reduce_prev ? mp[1 - par] : nullptr;
+  A.red_force = prev_force_row;
+  A.red_mass = cur_mass_row;
+  dim3 grid(A.tile_base + A.ntiles_pad);
+  if (A.n_cut > 0) {
     prof_begin(ctx, 1);
-    k_cut2d<<<ctx->n_irr, 64, 0, ctx->stream>>>(ctx->g2, in, out, ctx->s.mom, ctx->s.fslot,
-                                                 ctx->s.body, P);
+    k_cutstep2d<<<A.n_cut, 256, 0, ctx->stream>>>(ctx->g2, A, P);
     prof_end(ctx, 1);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (force_row || mass_row) {
-    prof_begin(ctx, 2);
-    k_reduce2d<<<kRedBlocks, 256, 0, ctx->stream>>>(
-        ctx->g2, ctx->s.mom, ctx->s.fslot, ctx->s.red,
-        reinterpret_cast<unsigned int*>(ctx->s.red + 4 * kRedBlocks), force_row, mass_row);
-    prof_end(ctx, 2);
-    e = hipGetLastError();
-  }
+  prof_begin(ctx, 0);
+  fn(ctx, grid, A, P);
+  prof_end(ctx, 0);
+  ctx->last_args_ntiles = A.ntiles;
   ctx->cur = 1 - ctx->cur;
-  return e;
+  ctx->step_parity = 1 - par;
+  (void)record;
+  return hipGetLastError();
+}
+
+// reduce the partials of the step that just ran into its force row and the
+// mass row of the state it produced
+hipError_t launch_step_2d_flush(cc_ctx* ctx, double* force_row, double* mass_row) {
+  const int par = 1 - ctx->step_parity;   // parity of the last launched step
+  FusedArgs A{};
+  A.ntiles = ctx->last_args_ntiles;
+  A.n_cut = ctx->n_irr;
+  double* fs[2] = {ctx->s.fslot, ctx->s.fslot + 3 * (size_t)ctx->ncell};
+  double* mp[2] = {ctx->s.mpart, ctx->s.mpart + (size_t)ctx->s.mpart_cap};
+  A.prev_fslot = fs[par];
+  A.prev_mpart = mp[par];
+  A.red_force = force_row;
+  A.red_mass = mass_row;
+  prof_begin(ctx, 2);
+  k_final_reduce2d<<<1, 256, 0, ctx->stream>>>(ctx->g2, A);
+  prof_end(ctx, 2);
+  return hipGetLastError();
 }
 
 

@@ -135,6 +135,9 @@ class Solver:
         self._check(lib().cc_geometry_counts(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
 
+    def set_tile_rows(self, rows: int):
+        self._check(lib().cc_set_tile_rows(self._h, int(rows)))
+
     # ---------------------------------------------------------------- profiling
     def profile_enable(self, on: bool = True):
         self._check(lib().cc_profile_enable(self._h, int(on)))

@@ -111,7 +111,8 @@ def test_body_force_call_matches_step_diag():
     s.step(5)
     F = s.body_force()
     d = s.step(1, diag=True).cpu().numpy()[0]
-    assert np.allclose(F, d, rtol=1e-14, atol=0)
+    # same force through two reduction orders: equal to round-off of |F|
+    assert np.all(np.abs(F - d) <= 1e-14 * np.max(np.abs(F)))
 
 
 def test_cyl512_full_size_sampled_cells():
