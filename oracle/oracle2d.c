@@ -653,7 +653,7 @@ int orc2d_step(orc2d *o, const double *f, const double *g, double *fo,
     for (int c = 0; c < n; ++c) {
       if (!(Gn->type[c] == SOLID && G1->type[c] != SOLID)) continue;
       int cc = c, hops = 0;
-      while (Gn->master[cc] < 0 && hops <= 4) {
+      while (Gn->master[cc] < 0 && hops < 4) {
         int i = cc % nx, j = cc / nx;
         double Lxp = i + 1 < nx ? G1->lxp[cc] : 0.0, Lxm = i > 0 ? G1->lxm[cc] : 0.0;
         double Lyp = j + 1 < o->ny ? G1->lyp[cc] : 0.0, Lym = j > 0 ? G1->lym[cc] : 0.0;

@@ -21,7 +21,12 @@ bool regular_supported_3d(int nvel);
 hipError_t launch_force_only_2d(cc_ctx* ctx, double* out4);
 hipError_t launch_force_only_3d(cc_ctx* ctx, double* out4);
 hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_row);
+hipError_t launch_moving_init_2d(cc_ctx* ctx);
 }  // namespace ccdvm
+
+static bool is_moving(const cc_ctx* ctx) {
+  return ctx->body.motion != CC_MOTION_FIXED && ctx->body.kind != CC_BODY_NONE;
+}
 
 namespace {
 
@@ -41,9 +46,8 @@ struct Carver {
   }
 };
 
-void layout_geo2d(cc_ctx* ctx, char* base, size_t* bytes) {
+void layout_geo2d_one(cc_ctx* ctx, Geo2D& G, char* base, size_t* bytes) {
   Carver cv{base};
-  Geo2D& G = ctx->g2;
   G.nx = ctx->nx; G.ny = ctx->ny; G.ncell = ctx->ncell; G.N = ctx->N; G.nvel = ctx->nvel;
   G.x0 = ctx->cfg.lo[0]; G.y0 = ctx->cfg.lo[1]; G.dx = ctx->dx; G.dy = ctx->dy;
   size_t n = ctx->ncell;
@@ -61,6 +65,17 @@ void layout_geo2d(cc_ctx* ctx, char* base, size_t* bytes) {
   G.ghost = cv.take<double2>(ctx->nvel);
   G.wden = nullptr;
   *bytes = cv.off;
+}
+
+// one geometry level for a fixed body, two (t^n, t^{n+1}) for a moving one
+void layout_geo2d(cc_ctx* ctx, char* base, size_t* bytes) {
+  size_t one = 0;
+  layout_geo2d_one(ctx, ctx->g2, base, &one);
+  *bytes = one;
+  if (is_moving(ctx)) {
+    layout_geo2d_one(ctx, ctx->g2n, base ? base + one : nullptr, &one);
+    *bytes = 2 * one;
+  }
 }
 
 void layout_geo3d(cc_ctx* ctx, char* base, size_t* bytes) {
@@ -91,6 +106,15 @@ void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
   Carver cv{base};
   size_t n = ctx->ncell;
   int nm = ctx->dim == 2 ? 4 : 5;
+  ctx->s.skind = cv.take<int>(n);
+  ctx->s.target = cv.take<int>(n);
+  ctx->s.rcnt = cv.take<int>(n);
+  ctx->s.age = cv.take<int>(n);
+  ctx->s.gl = cv.take<int>(n);
+  ctx->s.gptr = cv.take<int>(n + 1);
+  ctx->s.gmem = cv.take<int>(n);
+  ctx->s.gcount = cv.take<int>(4);
+  ctx->s.pose = cv.take<double>(4);
   ctx->s.mom = cv.take<double>(n * nm);
   ctx->s.fslot = cv.take<double>(n * 3 * 2);
   ctx->s.mpart_cap = (int)((size_t)((ctx->nx + 3) / 4) * ctx->ny * ctx->nz + n);
@@ -172,6 +196,9 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
     return reject("radius must be > 0");
   if (body->motion < CC_MOTION_FIXED || body->motion > CC_MOTION_IMPOSED) return reject("unknown motion");
   if (body->motion != CC_MOTION_FIXED && c.dim == 3) return reject("moving bodies are 2D only");
+  if (body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_CIRCLE && body->kind != CC_BODY_ELLIPSE &&
+      body->kind != CC_BODY_NONE)
+    return reject("moving bodies must be circles or ellipses");
   if (body->motion == CC_MOTION_FREE_ROTATION && !(body->inertia > 0.0))
     return reject("inertia must be > 0");
   ctx->dim = c.dim;
@@ -274,12 +301,17 @@ cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scr
   HIPCHK(ctx, hipMemsetAsync(state1, 0, ctx->state_bytes, ctx->stream), "state clear");
   HIPCHK(ctx, hipMemcpyAsync(ctx->s.body, ctx->body_state, 6 * sizeof(double),
                              hipMemcpyHostToDevice, ctx->stream), "body state upload");
-  hipError_t e = ctx->dim == 2
-                     ? build_geometry_2d(ctx, ctx->body_state[0], ctx->body_state[1], ctx->body_state[2])
-                     : build_geometry_3d(ctx);
+  hipError_t e = ctx->dim == 2 ? build_geometry_2d(ctx, ctx->g2, ctx->s.body) : build_geometry_3d(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernels");
+  if (ctx->dim == 2 && is_moving(ctx)) {
+    e = build_geometry_2d(ctx, ctx->g2n, ctx->s.body);
+    if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernels");
+    e = launch_moving_init_2d(ctx);
+    if (e != hipSuccess) return hip_fail(ctx, e, "moving init");
+  }
   cc_status st = read_geometry_status(ctx);
   if (st != CC_OK) return st;
+  ctx->nstep = 0;
   ctx->bound = true;
   ctx->merged = false;
   ctx->mom_valid = false;
@@ -353,6 +385,17 @@ cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
     if (ctx->dim == 3) e = launch_step_3d(ctx, frow, mrow);
     else e = launch_moving_step_2d(ctx, frow, mrow);
     if (e != hipSuccess) return hip_fail(ctx, e, "step");
+  }
+  if (moving) {
+    // a moving body rebuilds its geometry every step: report a rejected
+    // geometry (one synchronisation per call)
+    int bits[3] = {0, 0, 0};
+    HIPCHK(ctx, hipMemcpyAsync(&bits[0], ctx->g2.counts + 3, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "status");
+    HIPCHK(ctx, hipMemcpyAsync(&bits[1], ctx->g2n.counts + 3, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "status");
+    HIPCHK(ctx, hipMemcpyAsync(&bits[2], ctx->s.gcount + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "status");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "step sync");
+    if (bits[0] | bits[1]) return fail(ctx, CC_EGEOM, "moving geometry rejected (cut twice, master search, members)");
+    if (bits[2]) return fail(ctx, CC_EGEOM, "a cell appearing at the new time found no control volume");
   }
   return CC_OK;
 }

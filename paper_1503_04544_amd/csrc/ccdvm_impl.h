@@ -37,7 +37,13 @@ struct BodyDev {
   double t_wall;
 };
 
+// A box of cells [i0, i0+ni) x [j0, j0+nj).
+struct Box2D {
+  int i0, j0, ni, nj;
+};
+
 // Geometry tables of a 2D grid, all in the caller's geometry buffer.
+struct Geo2D;
 struct Geo2D {
   int nx, ny, ncell, N, nvel;
   double x0, y0, dx, dy;
@@ -58,6 +64,26 @@ struct Geo2D {
   double* wden;      // per irregular-list slot and member: wall-density denominator
 };
 
+// One hop of the master search (algorithm (fusion), Appendix A.3) from cell
+// (i, j): across the largest gas edge shared with a cell of the domain, ties
+// (lengths within 1e-12 of the largest) broken in the order x+, x-, y+, y-.
+// Returns false when no edge qualifies.
+__device__ inline bool hop2d(const Geo2D& G, int& i, int& j) {
+  int c = j * G.nx + i;
+  double r = i + 1 < G.nx ? G.lxp[c] : 0.0;
+  double l = i > 0 ? G.lxm[c] : 0.0;
+  double t = j + 1 < G.ny ? G.lyp[c] : 0.0;
+  double b = j > 0 ? G.lym[c] : 0.0;
+  double M = fmax(fmax(r, l), fmax(t, b));
+  if (!(M > 0.0)) return false;
+  double tie = M * (1.0 - 1e-12);
+  if (r >= tie) i += 1;
+  else if (l >= tie) i -= 1;
+  else if (t >= tie) j += 1;
+  else j -= 1;
+  return true;
+}
+
 struct Geo3D {
   int nx, ny, nz, ncell, N, nvel;
   double x0, y0, z0, dx, dy, dz;
@@ -73,6 +99,16 @@ struct Geo3D {
 
 // Scratch layout (caller's scratch buffer).
 struct Scratch {
+  // moving bodies: per-step dispatch and receiving control volumes
+  int* skind;        // per-cell kind for this step
+  int* target;       // per cell: master at t^n of the control volume it receives from, -1 none
+  int* rcnt;         // per master: receivers other than itself
+  int* age;          // consecutive time levels a cell has been solid (saturates at 2)
+  int* gl;           // general control volumes (master) or -1-c (cell to zero)
+  int* gptr;         // receivers CSR pointers
+  int* gmem;         // receivers
+  int* gcount;       // [0] entries in gl, [1] error bits
+  double* pose;      // pose at t^{n+1}: cx, cy, theta
   double* mom;       // ncell * 4 (2D: rho, ux, uy, T) or ncell * 5 (3D: rho, u, T)
   double* fslot;     // 2 x per irregular master: Fx, Fy, torque (2D) / Fx, Fy, Fz (3D)
   double* mpart;     // 2 x mass partials (regular tiles, then control volumes)
@@ -112,7 +148,9 @@ struct cc_ctx {
   int step_parity = 0;     // which half of the double-buffered partials the next step writes
   int last_args_ntiles = 0;
   int seglen = 0;          // rows per regular-cell tile (0: automatic)
-  ccdvm::Geo2D g2;
+  ccdvm::Geo2D g2;          // geometry at the current time
+  ccdvm::Geo2D g2n;         // moving bodies: geometry at the next time level
+  long long nstep = 0;      // steps taken since binding
   ccdvm::Geo3D g3;
   ccdvm::Scratch s;
   int n_irr = 0, n_members = 0, n_solid = 0;
@@ -125,7 +163,8 @@ struct cc_ctx {
 namespace ccdvm {
 
 // geometry (geom2d.hip / geom3d.hip)
-hipError_t build_geometry_2d(cc_ctx* ctx, double cx, double cy, double theta);
+hipError_t build_geometry_2d(cc_ctx* ctx, Geo2D& G, const double* pose);
+hipError_t build_geometry_box_2d(cc_ctx* ctx, Geo2D& G, const double* pose, Box2D bx);
 hipError_t build_geometry_3d(cc_ctx* ctx);
 
 // step and helpers (step2d.hip / step3d.hip)

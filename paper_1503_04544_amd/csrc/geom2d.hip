@@ -80,12 +80,14 @@ __device__ double level_set_2d(const BodyDev& B, double x, double y, double cx,
   }
 }
 
-__global__ void k_phi2d(Geo2D G, BodyDev B, double cx, double cy, double th) {
-  int nvx = G.nx + 1, nvy = G.ny + 1;
+// vertices [i0, i0+ni] x [j0, j0+nj] of a box of cells; pose = (cx, cy, theta)
+__global__ void k_phi2d(Geo2D G, BodyDev B, const double* __restrict__ pose, Box2D bx) {
+  int nvx = G.nx + 1;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nvx * nvy) return;
-  int a = t % nvx, b = t / nvx;
-  double p = level_set_2d(B, G.x0 + a * G.dx, G.y0 + b * G.dy, cx, cy, th);
+  if (t >= (bx.ni + 1) * (bx.nj + 1)) return;
+  int a = bx.i0 + t % (bx.ni + 1), b = bx.j0 + t / (bx.ni + 1);
+  double p = level_set_2d(B, G.x0 + a * G.dx, G.y0 + b * G.dy, pose[0], pose[1], pose[2]);
+  t = b * nvx + a;
   double floor_ = 1e-10 * G.dx;
   double m = fabs(p) > floor_ ? fabs(p) : floor_;
   G.phi[t] = p >= 0.0 ? m : -m;
@@ -103,10 +105,11 @@ __device__ inline double gas_len(double pa, double pb, double h, bool* mixed, do
   return ga ? sc : h - sc;
 }
 
-__global__ void k_cell2d(Geo2D G) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= G.ncell) return;
-  int i = c % G.nx, j = c / G.nx;
+__global__ void k_cell2d(Geo2D G, Box2D bx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bx.ni * bx.nj) return;
+  int i = bx.i0 + t % bx.ni, j = bx.j0 + t / bx.ni;
+  int c = j * G.nx + i;
   int nvx = G.nx + 1;
   double p00 = G.phi[j * nvx + i], p10 = G.phi[j * nvx + i + 1];
   double p11 = G.phi[(j + 1) * nvx + i + 1], p01 = G.phi[(j + 1) * nvx + i];
@@ -166,37 +169,18 @@ __global__ void k_cell2d(Geo2D G) {
   G.sbar[c] = type == TYPE_SOLID ? 0.0 : (type == TYPE_GAS ? dx * dy : area);
 }
 
-// One hop of the master search from cell (i, j): across the largest gas edge
-// shared with a cell of the domain, ties (within 1e-12 of the largest) broken
-// in the order x+, x-, y+, y-.  Returns false when no edge qualifies.
-__device__ inline bool hop2d(const Geo2D& G, const double* lxp, const double* lxm,
-                             const double* lyp, const double* lym, int& i, int& j) {
+__global__ void k_master2d(Geo2D G, Box2D bx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bx.ni * bx.nj) return;
+  int i = bx.i0 + t % bx.ni, j = bx.j0 + t / bx.ni;
   int c = j * G.nx + i;
-  double r = i + 1 < G.nx ? lxp[c] : 0.0;
-  double l = i > 0 ? lxm[c] : 0.0;
-  double t = j + 1 < G.ny ? lyp[c] : 0.0;
-  double b = j > 0 ? lym[c] : 0.0;
-  double M = fmax(fmax(r, l), fmax(t, b));
-  if (!(M > 0.0)) return false;
-  double tie = M * (1.0 - 1e-12);
-  if (r >= tie) i += 1;
-  else if (l >= tie) i -= 1;
-  else if (t >= tie) j += 1;
-  else j -= 1;
-  return true;
-}
-
-__global__ void k_master2d(Geo2D G) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= G.ncell) return;
   if (G.type[c] == TYPE_SOLID) { G.master[c] = -1; return; }
-  int i = c % G.nx, j = c / G.nx;
   int seen[kHopCap + 1];
   seen[0] = c;
   int hops = 0;
   bool bad = false;
   while (!(G.flags[j * G.nx + i] & 1)) {
-    if (hops == kHopCap || !hop2d(G, G.lxp, G.lxm, G.lyp, G.lym, i, j)) { bad = true; break; }
+    if (hops == kHopCap || !hop2d(G, i, j)) { bad = true; break; }
     ++hops;
     int nc = j * G.nx + i;
     for (int h = 0; h < hops; ++h) bad |= seen[h] == nc;
@@ -211,9 +195,10 @@ __global__ void k_master2d(Geo2D G) {
 // control-volume area and kind; members of a control volume are cut cells
 // within kHopCap cells of their master, and a master owning members touches
 // a cut cell
-__global__ void k_cv2d(Geo2D G) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= G.ncell) return;
+__global__ void k_cv2d(Geo2D G, Box2D bx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bx.ni * bx.nj) return;
+  int c = (bx.j0 + t / bx.ni) * G.nx + bx.i0 + t % bx.ni;
   int m = G.master[c];
   if (m < 0) { G.kind[c] = KIND_SOLID; G.scv[c] = 0.0; return; }
   if (m != c) { G.kind[c] = KIND_MEMBER; G.scv[c] = 0.0; return; }
@@ -260,14 +245,17 @@ __device__ int block_exclusive_scan(int v, int* sh, int* total) {
 
 // Single-block deterministic compaction: list of irregular masters in
 // ascending cell order, CSR of their members, population counts.
-__global__ void __launch_bounds__(1024) k_compact2d(Geo2D G) {
+__global__ void __launch_bounds__(1024) k_compact2d(Geo2D G, Box2D bx) {
   __shared__ int sh[1024];
   int t = threadIdx.x;
-  int per = (G.ncell + blockDim.x - 1) / blockDim.x;
-  int b = t * per, e = min(b + per, G.ncell);
+  const int nbox = bx.ni * bx.nj;
+  int per = (nbox + blockDim.x - 1) / blockDim.x;
+  int b = t * per, e = min(b + per, nbox);
+  // box index -> cell index, ascending in the cell order
+  auto cell = [&](int u) { return (bx.j0 + u / bx.ni) * G.nx + bx.i0 + u % bx.ni; };
   int nirr = 0, nmem = 0, nsol = 0;
-  for (int c = b; c < e; ++c) {
-    int k = G.kind[c];
+  for (int u = b; u < e; ++u) {
+    int k = G.kind[cell(u)];
     nirr += k == KIND_IRREGULAR;
     nmem += k == KIND_MEMBER;
     nsol += k == KIND_SOLID;
@@ -276,8 +264,8 @@ __global__ void __launch_bounds__(1024) k_compact2d(Geo2D G) {
   int off = block_exclusive_scan(nirr, sh, &tot_irr);
   block_exclusive_scan(nmem, sh, &tot_mem);
   block_exclusive_scan(nsol, sh, &tot_sol);
-  for (int c = b; c < e; ++c)
-    if (G.kind[c] == KIND_IRREGULAR) G.irr[off++] = c;
+  for (int u = b; u < e; ++u)
+    if (G.kind[cell(u)] == KIND_IRREGULAR) G.irr[off++] = cell(u);
   if (t == 0) { G.counts[0] = tot_irr; G.counts[1] = tot_mem; G.counts[2] = tot_sol; }
   __syncthreads();
   // member counts per listed master, then CSR pointers by a chunked scan
@@ -321,25 +309,40 @@ __global__ void k_tables2d(Geo2D G, double vmin, double dv, double rho, double u
 
 }  // namespace
 
-hipError_t build_geometry_2d(cc_ctx* ctx, double cx, double cy, double theta) {
-  Geo2D& G = ctx->g2;
+BodyDev body_dev(const cc_ctx* ctx) {
   BodyDev B{};
   B.kind = ctx->body.kind;
   B.a = ctx->body.axes[0]; B.b = ctx->body.axes[1];
   B.t_wall = ctx->body.t_wall;
+  return B;
+}
+
+// Geometry of G for the pose stored at `pose` (device), inside box bx (the
+// cells outside it are gas cells of unchanged geometry).
+hipError_t build_geometry_box_2d(cc_ctx* ctx, Geo2D& G, const double* pose, Box2D bx) {
+  BodyDev B = body_dev(ctx);
   hipStream_t s = ctx->stream;
-  hipError_t e = hipMemsetAsync(G.counts, 0, 4 * sizeof(int), s);
+  hipError_t e = hipMemsetAsync(G.counts, 0, 3 * sizeof(int), s);
   if (e != hipSuccess) return e;
-  int nv = (G.nx + 1) * (G.ny + 1);
-  k_phi2d<<<(nv + 255) / 256, 256, 0, s>>>(G, B, cx, cy, theta);
-  k_cell2d<<<(G.ncell + 255) / 256, 256, 0, s>>>(G);
-  k_master2d<<<(G.ncell + 255) / 256, 256, 0, s>>>(G);
-  k_cv2d<<<(G.ncell + 255) / 256, 256, 0, s>>>(G);
-  k_compact2d<<<1, 1024, 0, s>>>(G);
+  int nv = (bx.ni + 1) * (bx.nj + 1), nc = bx.ni * bx.nj;
+  k_phi2d<<<(nv + 255) / 256, 256, 0, s>>>(G, B, pose, bx);
+  k_cell2d<<<(nc + 255) / 256, 256, 0, s>>>(G, bx);
+  k_master2d<<<(nc + 255) / 256, 256, 0, s>>>(G, bx);
+  k_cv2d<<<(nc + 255) / 256, 256, 0, s>>>(G, bx);
+  k_compact2d<<<1, 1024, 0, s>>>(G, bx);
+  return hipGetLastError();
+}
+
+hipError_t build_geometry_2d(cc_ctx* ctx, Geo2D& G, const double* pose) {
+  hipError_t e = hipMemsetAsync(G.counts, 0, 4 * sizeof(int), ctx->stream);
+  if (e != hipSuccess) return e;
+  Box2D all{0, 0, G.nx, G.ny};
+  e = build_geometry_box_2d(ctx, G, pose, all);
+  if (e != hipSuccess) return e;
   const double* in = ctx->cfg.inflow;
   int nt = G.nvel > G.N ? G.nvel : G.N;
-  k_tables2d<<<(nt + 255) / 256, 256, 0, s>>>(G, ctx->cfg.vmin, ctx->dv, in[0], in[1],
-                                              in[2], in[4]);
+  k_tables2d<<<(nt + 255) / 256, 256, 0, ctx->stream>>>(G, ctx->cfg.vmin, ctx->dv, in[0], in[1],
+                                                       in[2], in[4]);
   return hipGetLastError();
 }
 

@@ -17,6 +17,5 @@ hipError_t launch_step_3d(cc_ctx*, double*, double*) { return hipErrorNotSupport
 hipError_t launch_mass_3d(cc_ctx*, double*) { return hipErrorNotSupported; }
 hipError_t launch_moments_out_3d(cc_ctx*, double*) { return hipErrorNotSupported; }
 hipError_t launch_force_only_3d(cc_ctx*, double*) { return hipErrorNotSupported; }
-hipError_t launch_moving_step_2d(cc_ctx*, double*, double*) { return hipErrorNotSupported; }
 
 }  // namespace ccdvm

@@ -59,6 +59,24 @@ __device__ inline double maxw_wall(double vx, double vy, double uwx, double uwy,
   return exp(-(ex * ex + ey * ey) / (2.0 * Tw)) / (2.0 * M_PI * Tw);
 }
 
+// Block-wide exclusive scan of one int per thread (any block size up to
+// 1024); returns the exclusive prefix and the block total.
+__device__ int block_exclusive_scan_int(int v, int* sh, int* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const int incl = sh[t];
+  *total = sh[blockDim.x - 1];
+  __syncthreads();
+  return incl - v;
+}
+
 // Block-wide sum over the 4 waves of a 256-thread block; every thread gets
 // the total.  Waves are added in wave order (deterministic).
 __device__ inline double block_sum4(double v, double* lds) {
@@ -203,7 +221,8 @@ __global__ void __launch_bounds__(256) k_cut_force2d(Geo2D G, const double2* __r
                                                      const double* __restrict__ body,
                                                      StepParams P) {
   __shared__ double lds[8];
-  cut_cv(G, in, nullptr, mom, fslot, nullptr, body, P, blockIdx.x, lds);
+  for (int q = blockIdx.x; q < G.counts[0]; q += gridDim.x)
+    cut_cv(G, in, nullptr, mom, fslot, nullptr, body, P, q, lds);
 }
 
 // ---------------------------------------------------------------------
@@ -224,6 +243,7 @@ __global__ void __launch_bounds__(256) k_cut_force2d(Geo2D G, const double2* __r
 //                     one XCD are adjacent columns of the same rows.
 // ---------------------------------------------------------------------
 constexpr int kTileW = 4;   // columns (waves) per tile
+constexpr int kListBlocks = 512;   // grid of kernels that walk a list whose length is on the device
 #ifndef CCDVM_PREFETCH
 #define CCDVM_PREFETCH 4
 #endif
@@ -238,6 +258,7 @@ constexpr int prefetch_depth(int nch) {
 }
 
 struct FusedArgs {
+  const int* kind;          // per-cell dispatch kind (KIND_REGULAR cells are streamed)
   const double2* in;
   double2* out;
   double* mom;
@@ -311,7 +332,7 @@ __device__ void regular_tile(const Geo2D& G, const FusedArgs& A, const StepParam
       const int c = j * nx + i;
       const d2v* row = in + (size_t)c * nvel;
       const d2v* nrow = j + 1 < ny ? row + (size_t)nx * nvel : ghost;
-      const bool reg = G.kind[c] == KIND_REGULAR;   // uniform over the wave
+      const bool reg = A.kind[c] == KIND_REGULAR;   // uniform over the wave
       double Am = 0.0, T = 1.0, dtau = 0.0, tx = 0.0, ty = 0.0;
       if (reg) {
         const double* mc = A.mom + 4 * c;
@@ -444,9 +465,9 @@ __global__ void __launch_bounds__(256) k_final_reduce2d(Geo2D G, FusedArgs A) {
 // Merge (eq. FusionDD) of control volumes with several members, in place,
 // followed by the moments of the merged value.
 // ---------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_merge2d(Geo2D G, double2* __restrict__ st,
-                                                double* __restrict__ mom, StepParams P) {
-  const int q = blockIdx.x, lane = threadIdx.x;
+__device__ void merge_cv(Geo2D G, double2* __restrict__ st, double* __restrict__ mom,
+                         const StepParams& P, int q) {
+  const int lane = threadIdx.x;
   const int m = G.irr[q];
   const int b = G.mptr[q], e = G.mptr[q + 1];
   const int N = G.N, nvel = G.nvel;
@@ -480,6 +501,11 @@ __global__ void __launch_bounds__(64) k_merge2d(Geo2D G, double2* __restrict__ s
       mom[4 * k + 0] = r; mom[4 * k + 1] = mx; mom[4 * k + 2] = my; mom[4 * k + 3] = Tn;
     }
   }
+}
+
+__global__ void __launch_bounds__(64) k_merge2d(Geo2D G, double2* __restrict__ st,
+                                                double* __restrict__ mom, StepParams P) {
+  for (int q = blockIdx.x; q < G.counts[0]; q += gridDim.x) merge_cv(G, st, mom, P, q);
 }
 
 // moments (rho, u, T) of every non-solid cell, one wave per cell
@@ -634,6 +660,318 @@ StepParams params2d(const cc_ctx* ctx) {
   return P;
 }
 
+// =====================================================================
+// Moving body (seven-step summary of Section 3.3.4).  With G0 the geometry
+// at t^n and G1 the geometry at t^{n+1} (built inside a box around the body
+// from the pose at t^{n+1}), one step is:
+//   merge over the control volumes sigma^n of G0 (eq. FusionDD),
+//   k_steplist2d: the control volume of t^n that each cell of t^{n+1}
+//     receives from (cells appearing at t^{n+1} hop across their largest
+//     new edge into a cell of sigma^n), the control volumes whose update
+//     differs from a plain gas cell (cut, merged, receiving an appearing
+//     cell, or changing area), and the cells left holding stale values,
+//   k_genstep2d: those control volumes, with the area ratio S^n/S^{n+1,*}
+//     of eq. (ExSchemeDD) and the wall velocity of eq. (uwDD) at t^n,
+//   k_step2d: every other cell (plain gas cell at both times),
+//   k_rigid2d: force and torque of t^n, then the body velocity at t^{n+1}
+//     (eq. motionDD_vit) and the pose at t^{n+1} (eq. motionDD_posit).
+// =====================================================================
+
+struct MoveArgs {
+  Geo2D G0, G1;
+  int* skind;
+  int* target;
+  int* rcnt;
+  int* age;
+  int* gl;
+  int* gptr;
+  int* gmem;
+  int* gcount;
+  Box2D bx;
+};
+
+// pose at t^{n+1} from the state at t^n (position updated with the old
+// velocity, eq. motionDD_posit)
+__global__ void k_pose_next2d(const double* __restrict__ body, double* __restrict__ pose,
+                              double dt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    pose[0] = body[0] + dt * body[3];
+    pose[1] = body[1] + dt * body[4];
+    pose[2] = body[2] + dt * body[5];
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_steplist2d(MoveArgs M) {
+  __shared__ int sh[1024];
+  const Geo2D& G0 = M.G0;
+  const Geo2D& G1 = M.G1;
+  const int nx = G0.nx;
+  const int nbox = M.bx.ni * M.bx.nj;
+  auto cell = [&](int u) { return (M.bx.j0 + u / M.bx.ni) * nx + M.bx.i0 + u % M.bx.ni; };
+  const int t = threadIdx.x;
+  const int per = (nbox + blockDim.x - 1) / blockDim.x;
+  const int ub = t * per, ue = min(ub + per, nbox);
+  const int R = 2 * kHopCap;   // a receiver is at most 2 x 4 hops from its master
+  int bad = 0;
+  // receiving control volume of every cell of t^{n+1}
+  for (int u = ub; u < ue; ++u) {
+    const int c = cell(u);
+    int tg = G0.master[c];
+    if (tg < 0 && G1.type[c] != TYPE_SOLID) {
+      // appearing cell: hop across its largest edge of t^{n+1} into sigma^n
+      int i = c % nx, j = c / nx, hops = 0;
+      while (G0.master[j * nx + i] < 0) {
+        if (hops == kHopCap || !hop2d(G1, i, j)) { bad = 1; break; }
+        ++hops;
+      }
+      tg = G0.master[j * nx + i];
+    }
+    M.target[c] = tg;
+    M.rcnt[c] = 0;
+  }
+  __syncthreads();
+  // receivers other than the master itself, counted per master (integer
+  // atomics: the count does not depend on their order)
+  for (int u = ub; u < ue; ++u) {
+    const int c = cell(u);
+    const int tg = M.target[c];
+    if (tg >= 0 && tg != c) atomicAdd(&M.rcnt[tg], 1);
+  }
+  __syncthreads();
+  // control volumes that need the general update, per-cell kinds, cells to zero
+  int ngen = 0, nzero = 0;
+  for (int u = ub; u < ue; ++u) {
+    const int c = cell(u);
+    const int tg = M.target[c];
+    int kind = KIND_SOLID;
+    if (tg == c) {
+      const bool general = G0.kind[c] != KIND_REGULAR || M.rcnt[c] != 0 || G1.type[c] != TYPE_GAS;
+      kind = general ? KIND_IRREGULAR : KIND_REGULAR;
+      ngen += general;
+    } else if (tg >= 0) {
+      kind = KIND_MEMBER;
+    }
+    M.skind[c] = kind;
+    // solid at t^n and t^{n+1} but not at t^{n-1}: its entry in the output
+    // buffer (the state of t^{n-1}) is stale
+    if (G1.type[c] == TYPE_SOLID && M.age[c] == 1) ++nzero;
+  }
+  int tot_gen, tot_zero;
+  int off_gen = block_exclusive_scan_int(ngen, sh, &tot_gen);
+  int off_zero = block_exclusive_scan_int(nzero, sh, &tot_zero);
+  for (int u = ub; u < ue; ++u) {
+    const int c = cell(u);
+    if (M.skind[c] == KIND_IRREGULAR) M.gl[off_gen++] = c;
+    const int a = M.age[c];
+    if (G1.type[c] == TYPE_SOLID && a == 1) M.gl[tot_gen + off_zero++] = -1 - c;
+    M.age[c] = G1.type[c] == TYPE_SOLID ? min(a + 1, 2) : 0;
+  }
+  __syncthreads();
+  // receivers of each general control volume, in ascending cell order
+  int carry = 0;
+  for (int base = 0; base < tot_gen; base += blockDim.x) {
+    const int q = base + t;
+    int cnt = 0;
+    if (q < tot_gen) {
+      cnt = 1 + M.rcnt[M.gl[q]];
+      if (cnt > kMaxMembers) bad |= 2;
+    }
+    int tot;
+    const int ex = block_exclusive_scan_int(cnt, sh, &tot);
+    if (q < tot_gen) {
+      const int m = M.gl[q];
+      M.gptr[q] = carry + ex;
+      int w = carry + ex, lim = carry + ex + cnt;
+      const int i = m % nx, j = m / nx;
+      for (int jj = max(j - R, 0); jj <= min(j + R, G0.ny - 1); ++jj)
+        for (int ii = max(i - R, 0); ii <= min(i + R, nx - 1); ++ii)
+          if (M.target[jj * nx + ii] == m && w < lim) M.gmem[w++] = jj * nx + ii;
+      if (w != lim) bad |= 4;
+    }
+    carry += tot;
+  }
+  if (t == 0) {
+    M.gptr[tot_gen] = carry;
+    M.gcount[0] = tot_gen + tot_zero;
+    M.gcount[2] = tot_gen;
+  }
+  if (bad) atomicOr(&M.gcount[1], bad);
+}
+
+// One general control volume (or one stale cell to zero) per block.
+__device__ void general_cv(const MoveArgs& M, const double2* __restrict__ in,
+                           double2* __restrict__ out, double* __restrict__ mom,
+                           double* __restrict__ fslot, double* __restrict__ mpart,
+                           const double* __restrict__ body, const StepParams& P, int q,
+                           double* lds) {
+  const Geo2D& G0 = M.G0;
+  const Geo2D& G1 = M.G1;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int N = G0.N, nvel = G0.nvel, nx = G0.nx, ny = G0.ny;
+  const int e0 = M.gl[q];
+  if (e0 < 0) {
+    const int c = -1 - e0;
+    for (int p = tid; p < nvel; p += nth) out[(size_t)c * nvel + p] = make_double2(0.0, 0.0);
+    if (tid == 0) { fslot[3 * q] = 0.0; fslot[3 * q + 1] = 0.0; fslot[3 * q + 2] = 0.0; *mpart = 0.0; }
+    return;
+  }
+  const int m = e0;
+  const int b = M.gptr[q];
+  // more receivers than supported is reported by k_steplist2d; never index past the arrays
+  const int nm = min(M.gptr[q + 1] - b, kMaxMembers);
+  const double rho = mom[4 * m + 0], ux = mom[4 * m + 1], uy = mom[4 * m + 2], T = mom[4 * m + 3];
+  const double inv2T = 0.5 / T, A = rho / (2.0 * M_PI * T);
+  const double dtau = P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
+  const double Sn = G0.scv[m];
+  double Snew = 0.0;
+  for (int t = 0; t < nm; ++t) Snew += G1.sbar[M.gmem[b + t]];
+  const double2* own = in + (size_t)m * nvel;
+  const double Tw = P.t_wall;
+  double phiw[kMaxMembers], uwx[kMaxMembers], uwy[kMaxMembers];
+  for (int t = 0; t < nm; ++t) {
+    const int k = M.gmem[b + t];
+    phiw[t] = 0.0; uwx[t] = 0.0; uwy[t] = 0.0;
+    if (!(G0.lw[k] > 0.0)) continue;
+    wall_velocity(body, G0.rwx[k], G0.rwy[k], &uwx[t], &uwy[t]);
+    const double nwx = G0.nwx[k], nwy = G0.nwy[k];
+    double num = 0.0, den = 0.0;
+    for (int p = tid; p < nvel; p += nth) {
+      const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
+      const double cn = (vx - uwx[t]) * nwx + (vy - uwy[t]) * nwy;
+      if (cn > 0.0) num += cn * own[p].x;
+      else if (cn < 0.0) den += cn * maxw_wall(vx, vy, uwx[t], uwy[t], Tw);
+    }
+    num = block_sum4(num, lds);
+    den = block_sum4(den, lds);
+    phiw[t] = den != 0.0 ? -num / den : 0.0;
+  }
+  double sx[kMaxMembers], sy[kMaxMembers];
+  for (int t = 0; t < kMaxMembers; ++t) { sx[t] = 0.0; sy[t] = 0.0; }
+  double sr = 0.0, smx = 0.0, smy = 0.0, se = 0.0;
+  const double ratio = Snew > 0.0 ? Sn / Snew : 0.0;
+  const double dts = Snew > 0.0 ? P.dt / Snew : 0.0;
+  for (int p = tid; p < nvel; p += nth) {
+    const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
+    const double vxm = fmin(vx, 0.0), vxp = fmax(vx, 0.0);
+    const double vym = fmin(vy, 0.0), vyp = fmax(vy, 0.0);
+    const double2 o = own[p];
+    double Rf = 0.0, Rg = 0.0;
+    for (int t = 0; t < nm; ++t) {
+      const int k = M.gmem[b + t];
+      const int i = k % nx, j = k / nx;
+      const double Lr = G0.lxp[k], Ll = G0.lxm[k], Lt = G0.lyp[k], Lb = G0.lym[k];
+      if (Lr > 0.0) {
+        const double2 nb = i + 1 < nx ? in[(size_t)(k + 1) * nvel + p] : G0.ghost[p];
+        Rf += Lr * (vxm * nb.x + vxp * o.x);
+        Rg += Lr * (vxm * nb.y + vxp * o.y);
+      }
+      if (Ll > 0.0) {
+        const double2 nb = i > 0 ? in[(size_t)(k - 1) * nvel + p] : G0.ghost[p];
+        Rf -= Ll * (vxm * o.x + vxp * nb.x);
+        Rg -= Ll * (vxm * o.y + vxp * nb.y);
+      }
+      if (Lt > 0.0) {
+        const double2 nb = j + 1 < ny ? in[(size_t)(k + nx) * nvel + p] : G0.ghost[p];
+        Rf += Lt * (vym * nb.x + vyp * o.x);
+        Rg += Lt * (vym * nb.y + vyp * o.y);
+      }
+      if (Lb > 0.0) {
+        const double2 nb = j > 0 ? in[(size_t)(k - nx) * nvel + p] : G0.ghost[p];
+        Rf -= Lb * (vym * o.x + vyp * nb.x);
+        Rg -= Lb * (vym * o.y + vyp * nb.y);
+      }
+      const double Lw = G0.lw[k];
+      if (Lw > 0.0) {
+        const double cx_ = vx - uwx[t], cy_ = vy - uwy[t];
+        const double cn = cx_ * G0.nwx[k] + cy_ * G0.nwy[k];
+        const double Mw = maxw_wall(vx, vy, uwx[t], uwy[t], Tw);
+        const double fw = phiw[t] * Mw, gw = phiw[t] * 0.5 * Tw * Mw;
+        Rf += Lw * (fmin(cn, 0.0) * fw + fmax(cn, 0.0) * o.x);
+        Rg += Lw * (fmin(cn, 0.0) * gw + fmax(cn, 0.0) * o.y);
+        const double fv = cn < 0.0 ? fw : (cn > 0.0 ? o.x : 0.0);
+        sx[t] += cx_ * cn * fv;
+        sy[t] += cy_ * cn * fv;
+      }
+    }
+    double E = 0.0;
+    if (dtau != 0.0) {
+      const double ex = vx - ux, ey = vy - uy;
+      E = A * exp(-ex * ex * inv2T) * exp(-ey * ey * inv2T);
+    }
+    const double fn = ratio * o.x - dts * Rf + ratio * dtau * (E - o.x);
+    const double gn = ratio * o.y - dts * Rg + ratio * dtau * (0.5 * T * E - o.y);
+    for (int t = 0; t < nm; ++t) {
+      const int k = M.gmem[b + t];
+      const bool live = G1.type[k] != TYPE_SOLID && Snew > 0.0;
+      out[(size_t)k * nvel + p] = live ? make_double2(fn, gn) : make_double2(0.0, 0.0);
+    }
+    sr += fn; smx += vx * fn; smy += vy * fn;
+    se += 0.5 * (vx * vx + vy * vy) * fn + gn;
+  }
+  double Fx = 0.0, Fy = 0.0, Tq = 0.0;
+  for (int t = 0; t < nm; ++t) {
+    const int k = M.gmem[b + t];
+    if (!(G0.lw[k] > 0.0)) continue;
+    const double ax = block_sum4(sx[t], lds) * P.w, ay = block_sum4(sy[t], lds) * P.w;
+    Fx += ax * G0.lw[k];
+    Fy += ay * G0.lw[k];
+    Tq += ((G0.rwx[k] - body[0]) * ay - (G0.rwy[k] - body[1]) * ax) * G0.lw[k];
+  }
+  sr = block_sum4(sr, lds); smx = block_sum4(smx, lds);
+  smy = block_sum4(smy, lds); se = block_sum4(se, lds);
+  if (tid == 0) {
+    const double r = sr * P.w, mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
+    const double Tn = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
+    for (int t = 0; t < nm; ++t) {
+      const int k = M.gmem[b + t];
+      mom[4 * k + 0] = r; mom[4 * k + 1] = mx; mom[4 * k + 2] = my; mom[4 * k + 3] = Tn;
+    }
+    fslot[3 * q + 0] = Fx;
+    fslot[3 * q + 1] = Fy;
+    fslot[3 * q + 2] = Tq;
+    *mpart = Snew > 0.0 ? Snew * r : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_genstep2d(MoveArgs M, const double2* __restrict__ in,
+                                                   double2* __restrict__ out,
+                                                   double* __restrict__ mom,
+                                                   double* __restrict__ fslot,
+                                                   double* __restrict__ mpart, int ntiles,
+                                                   const double* __restrict__ body, StepParams P) {
+  __shared__ double lds[8];
+  const int cnt = M.gcount[0];
+  for (int q = blockIdx.x; q < cnt; q += gridDim.x)
+    general_cv(M, in, out, mom, fslot, mpart + ntiles + q, body, P, q, lds);
+}
+
+// Force, torque (t^n) and mass (t^{n+1}) in fixed order; then the rigid
+// body: pose at t^{n+1} and, for free rotation, the angular velocity at
+// t^{n+1} from the torque of t^n (eq. motionDD_vit).
+__global__ void __launch_bounds__(256) k_rigid2d(const int* __restrict__ gcount,
+                                                 const double* __restrict__ fslot,
+                                                 const double* __restrict__ mpart, int ntiles,
+                                                 double* __restrict__ body,
+                                                 const double* __restrict__ pose, double dt,
+                                                 double inv_inertia, int free_rotation,
+                                                 double* force_row, double* mass_row) {
+  __shared__ double lds[8];
+  const int ng = gcount[0];
+  double ms = 0.0, fx = 0.0, fy = 0.0, tq = 0.0;
+  for (int t = threadIdx.x; t < ntiles + ng; t += blockDim.x) ms += mpart[t];
+  for (int q = threadIdx.x; q < ng; q += blockDim.x) {
+    fx += fslot[3 * q]; fy += fslot[3 * q + 1]; tq += fslot[3 * q + 2];
+  }
+  ms = block_sum4(ms, lds); fx = block_sum4(fx, lds);
+  fy = block_sum4(fy, lds); tq = block_sum4(tq, lds);
+  if (threadIdx.x == 0) {
+    if (force_row) { force_row[0] = fx; force_row[1] = fy; force_row[2] = tq; }
+    if (mass_row) mass_row[0] = ms;
+    body[0] = pose[0]; body[1] = pose[1]; body[2] = pose[2];
+    if (free_rotation) body[5] = body[5] + dt * tq * inv_inertia;
+  }
+}
+
 typedef void (*fused_fn)(const cc_ctx*, dim3, const FusedArgs&, const StepParams&);
 
 template <int NCH>
@@ -692,9 +1030,8 @@ hipError_t launch_force_only_2d(cc_ctx* ctx, double* out4) {
   StepParams P = params2d(ctx);
   P.write_state = 0;
   const double2* in = (const double2*)ctx->state[ctx->cur];
-  if (ctx->n_irr > 0)
-    k_cut_force2d<<<ctx->n_irr, 256, 0, ctx->stream>>>(ctx->g2, in, ctx->s.mom, ctx->s.fslot,
-                                                       ctx->s.body, P);
+  k_cut_force2d<<<kListBlocks, 256, 0, ctx->stream>>>(ctx->g2, in, ctx->s.mom, ctx->s.fslot,
+                                                      ctx->s.body, P);
   k_reduce2d<<<kRedBlocks, 256, 0, ctx->stream>>>(
       ctx->g2, ctx->s.mom, ctx->s.fslot, ctx->s.red,
       reinterpret_cast<unsigned int*>(ctx->s.red + 4 * kRedBlocks), out4, out4 + 3);
@@ -724,11 +1061,10 @@ hipError_t launch_store_state_2d(const cc_ctx* ctx, double* f, double* g) {
 }
 
 hipError_t launch_merge_2d(cc_ctx* ctx) {
-  if (ctx->n_irr == 0) return hipSuccess;
   StepParams P = params2d(ctx);
   prof_begin(ctx, 3);
-  k_merge2d<<<ctx->n_irr, 64, 0, ctx->stream>>>(ctx->g2, (double2*)ctx->state[ctx->cur],
-                                                 ctx->s.mom, P);
+  k_merge2d<<<kListBlocks, 64, 0, ctx->stream>>>(ctx->g2, (double2*)ctx->state[ctx->cur],
+                                                  ctx->s.mom, P);
   prof_end(ctx, 3);
   return hipGetLastError();
 }
@@ -777,6 +1113,7 @@ hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_forc
   if (!fn) return hipErrorInvalidValue;
   const int par = ctx->step_parity;
   FusedArgs A;
+  A.kind = ctx->g2.kind;
   A.in = (const double2*)ctx->state[ctx->cur];
   A.out = (double2*)ctx->state[1 - ctx->cur];
   A.mom = ctx->s.mom;
@@ -814,6 +1151,110 @@ hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_forc
   ctx->step_parity = 1 - par;
   (void)record;
   return hipGetLastError();
+}
+
+__global__ void k_moving_init2d(Geo2D G, int* __restrict__ skind, int* __restrict__ target,
+                                int* __restrict__ age) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.ncell) return;
+  skind[c] = G.kind[c];
+  target[c] = G.master[c];
+  age[c] = G.type[c] == TYPE_SOLID ? 2 : 0;
+}
+
+hipError_t launch_moving_init_2d(cc_ctx* ctx) {
+  k_moving_init2d<<<(ctx->ncell + 255) / 256, 256, 0, ctx->stream>>>(ctx->g2, ctx->s.skind,
+                                                                      ctx->s.target, ctx->s.age);
+  return hipGetLastError();
+}
+
+// Box of cells that can change between t^n and t^{n+1}: the body's extent
+// at both times plus a margin covering master searches and receivers.
+Box2D moving_box(const cc_ctx* ctx) {
+  const cc_body& b = ctx->body;
+  double R = b.axes[0] > b.axes[1] ? b.axes[0] : b.axes[1];
+  if (b.kind == CC_BODY_CIRCLE) R = b.axes[0];
+  double t0 = ctx->nstep * ctx->dt, t1 = t0 + ctx->dt;
+  double vx = b.motion == CC_MOTION_IMPOSED ? b.vel[0] : 0.0;
+  double vy = b.motion == CC_MOTION_IMPOSED ? b.vel[1] : 0.0;
+  double xa = b.center[0] + vx * t0, xb = b.center[0] + vx * t1;
+  double ya = b.center[1] + vy * t0, yb = b.center[1] + vy * t1;
+  double xmin = fmin(xa, xb) - R, xmax = fmax(xa, xb) + R;
+  double ymin = fmin(ya, yb) - R, ymax = fmax(ya, yb) + R;
+  const int margin = 2 * kHopCap + 3;
+  int i0 = (int)floor((xmin - ctx->cfg.lo[0]) / ctx->dx) - margin;
+  int i1 = (int)ceil((xmax - ctx->cfg.lo[0]) / ctx->dx) + margin;
+  int j0 = (int)floor((ymin - ctx->cfg.lo[1]) / ctx->dy) - margin;
+  int j1 = (int)ceil((ymax - ctx->cfg.lo[1]) / ctx->dy) + margin;
+  i0 = i0 < 0 ? 0 : i0; j0 = j0 < 0 ? 0 : j0;
+  i1 = i1 > ctx->nx ? ctx->nx : i1; j1 = j1 > ctx->ny ? ctx->ny : j1;
+  return Box2D{i0, j0, i1 - i0, j1 - j0};
+}
+
+hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_row) {
+  StepParams P = params2d(ctx);
+  fused_fn fn = pick_fused(chunks_per_half(ctx));
+  if (!fn) return hipErrorInvalidValue;
+  hipStream_t st = ctx->stream;
+  const int par = ctx->step_parity;
+  // 1. pose at t^{n+1}; 3. geometry at t^{n+1} inside the box
+  k_pose_next2d<<<1, 64, 0, st>>>(ctx->s.body, ctx->s.pose, ctx->dt);
+  Box2D bx = moving_box(ctx);
+  hipError_t e = build_geometry_box_2d(ctx, ctx->g2n, ctx->s.pose, bx);
+  if (e != hipSuccess) return e;
+  // 2. merge over the control volumes of t^n
+  prof_begin(ctx, 3);
+  k_merge2d<<<kListBlocks, 64, 0, st>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom, P);
+  prof_end(ctx, 3);
+  MoveArgs M;
+  M.G0 = ctx->g2; M.G1 = ctx->g2n;
+  M.skind = ctx->s.skind; M.target = ctx->s.target; M.rcnt = ctx->s.rcnt; M.age = ctx->s.age;
+  M.gl = ctx->s.gl; M.gptr = ctx->s.gptr; M.gmem = ctx->s.gmem; M.gcount = ctx->s.gcount;
+  M.bx = bx;
+  k_steplist2d<<<1, 1024, 0, st>>>(M);
+  FusedArgs A;
+  A.kind = ctx->s.skind;
+  A.in = (const double2*)ctx->state[ctx->cur];
+  A.out = (double2*)ctx->state[1 - ctx->cur];
+  A.mom = ctx->s.mom;
+  A.body = ctx->s.body;
+  A.ngroups = (ctx->nx + kTileW - 1) / kTileW;
+  A.seglen = tile_rows(ctx);
+  const int nseg = (ctx->ny + A.seglen - 1) / A.seglen;
+  A.ntiles = A.ngroups * nseg;
+  A.ntiles_pad = (A.ntiles + 7) / 8 * 8;
+  A.n_cut = 0;
+  A.cut_base = 0;
+  A.tile_base = 8;
+  A.split = split_rows(ctx);
+  double* fs = ctx->s.fslot + (size_t)par * 3 * ctx->ncell;
+  double* mp = ctx->s.mpart + (size_t)par * ctx->s.mpart_cap;
+  A.fslot = fs;
+  A.mpart = mp;
+  A.prev_fslot = nullptr;
+  A.prev_mpart = nullptr;
+  A.red_force = nullptr;
+  A.red_mass = nullptr;
+  // 4-6. wall condition, scheme and redistribution
+  prof_begin(ctx, 1);
+  k_genstep2d<<<kListBlocks, 256, 0, st>>>(M, A.in, A.out, A.mom, fs, mp, A.ntiles, ctx->s.body, P);
+  prof_end(ctx, 1);
+  prof_begin(ctx, 0);
+  fn(ctx, dim3(A.tile_base + A.ntiles_pad), A, P);
+  prof_end(ctx, 0);
+  // 5/1. force and torque of t^n, body velocity and pose at t^{n+1}
+  const bool free_rot = ctx->body.motion == CC_MOTION_FREE_ROTATION;
+  prof_begin(ctx, 2);
+  k_rigid2d<<<1, 256, 0, st>>>(ctx->s.gcount, fs, mp, A.ntiles, ctx->s.body, ctx->s.pose, ctx->dt,
+                               free_rot ? 1.0 / ctx->body.inertia : 0.0, free_rot ? 1 : 0,
+                               force_row, mass_row);
+  prof_end(ctx, 2);
+  e = hipGetLastError();
+  Geo2D tmp = ctx->g2; ctx->g2 = ctx->g2n; ctx->g2n = tmp;
+  ctx->cur = 1 - ctx->cur;
+  ctx->step_parity = 1 - par;
+  ctx->nstep += 1;
+  return e;
 }
 
 // reduce the partials of the step that just ran into its force row and the
