@@ -23,6 +23,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOAD_TEXT = {
+    "cyl512": "cyl512: 2D 512x256 cells, 32x32 velocities on [-6,6]^2, cylinder r=0.05, "
+              "Kn {kn}, Mach 0.8, T_w 1, CFL 0.5, drag every step",
+    "ellipse256": "ellipse256: 2D 256x256 cells, 40x40 velocities on [-6,6]^2, ellipse 0.2x0.04 "
+                  "free to rotate (J=0.01), Kn {kn}, Mach 0.5, geometry rebuilt every step, "
+                  "torque every step",
+    "cyl32": "cyl32: 2D 32x32 cells, 16x16 velocities, cylinder r=0.2, Kn {kn}, Mach 0.5",
+}
 KERNEL_SRC = os.path.join(ROOT, "paper_1503_04544_amd", "csrc", "step2d.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_regular2d_cyl512.json")
 
@@ -72,7 +80,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--kn", type=float, default=0.1)
+    ap.add_argument("--kn", type=float, default=None)
+    ap.add_argument("--workload", default="cyl512", choices=["cyl512", "ellipse256", "cyl32"],
+                    help="cyl512 (default, the headline line) | ellipse256 (moving body) | cyl32")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
@@ -96,7 +106,7 @@ def main():
     from ccdvm_inputs import workload
     from paper_1503_04544_amd.solver import Solver
 
-    cfg = workload("cyl512", kn=args.kn)
+    cfg = workload(args.workload, kn=args.kn)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     s = Solver(cfg, device=dev)
@@ -125,12 +135,13 @@ def main():
     reg_ms, reg_n = s.profile_read(0)
     cut_ms, cut_n = s.profile_read(1)
     red_ms, red_n = s.profile_read(2)
+    mrg_ms, mrg_n = s.profile_read(3)
     s.profile_enable(False)
     n_regular = active - n_irr - n_mem
     bytes_per_launch = n_regular * nvel * 32        # read f,g + write f,g, FP64
     avg_s = reg_ms / max(reg_n, 1) / 1e3
     achieved = bytes_per_launch / avg_s / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic() if args.workload == "cyl512" else None
 
     out = {
         "metric": "cell-velocity updates/s",
@@ -145,9 +156,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "cyl512: 2D 512x256 cells, 32x32 velocities on [-6,6]^2, "
-                               f"cylinder r=0.05, Kn {args.kn}, Mach 0.8, T_w 1, CFL 0.5, "
-                               "drag every step",
+        "config": {"workload": WORKLOAD_TEXT[args.workload].format(kn=cfg.kn),
                    "cells": cfg.ncell, "active_cells": active, "velocities": nvel,
                    "cut_control_volumes": n_irr, "merged_cells": n_mem, "dt": s.dt,
                    "drag_last_step": drag_last},
@@ -157,12 +166,13 @@ def main():
                      "avg_launch_us": round(avg_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "cut_kernel_avg_us": round(cut_ms / max(cut_n, 1) * 1e3, 2),
-                     "reduce_kernel_avg_us": round(red_ms / max(red_n, 1) * 1e3, 2)},
+                     "reduce_kernel_avg_us": round(red_ms / max(red_n, 1) * 1e3, 2),
+                     "merge_kernel_avg_us": round(mrg_ms / max(mrg_n, 1) * 1e3, 2)},
     }
     s.close()
     del s
     torch.cuda.empty_cache()
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "cyl512":
         log(f"bench: oracle on the host, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -186,6 +186,38 @@ cc_status cc_set_tile_rows(cc_ctx* ctx, int rows);
 cc_status cc_profile_enable(cc_ctx* ctx, int on);
 cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launches);
 
+/* ------------------------------------------------------------------ */
+/* Batched instances.  Many independent 2D fixed-body problems (each its own
+ * context: grid, velocity grid, Kn, T_w, inflow), all bound to the same
+ * stream, advanced together: per step one kernel walks the cut/merged
+ * control volumes of every instance and one kernel per velocity-grid size
+ * walks the regular-cell tiles of every instance of that size.  A step is
+ * captured once as a HIP graph (one per ping-pong parity), so cc_batch_step
+ * issues one graph launch per step.  Results are bitwise identical to
+ * stepping each context with cc_step. */
+typedef struct cc_batch cc_batch;
+
+/* ctxs: n distinct bound 2D fixed-body contexts on the same stream.  The
+ * batch refers to them; they must outlive it. */
+cc_status cc_batch_create(cc_ctx* const* ctxs, int n, cc_batch** out);
+/* Bytes of the device workspace (descriptor tables and work lists). */
+cc_status cc_batch_workspace_bytes(const cc_batch* b, size_t* bytes);
+/* Binds a caller-owned 256-byte aligned device workspace, builds the tables
+ * and captures the step graphs.  Synchronises the stream. */
+cc_status cc_batch_bind(cc_batch* b, void* workspace);
+/* Picks, for each velocity-grid size, the tile height (rows) with the
+ * fastest tile kernel over trial_steps timed launches; rows_out (nullable)
+ * receives one entry per group.  The states are not advanced.  Synchronous. */
+cc_status cc_batch_autotune(cc_batch* b, int trial_steps, int* rows_out);
+/* Groups (velocity-grid sizes): count, chunks of 64 velocities per half-row
+ * and tile rows in use, arrays of ngroups entries (at most 16 groups). */
+cc_status cc_batch_groups(const cc_batch* b, int* ngroups, int* chunks, int* rows);
+/* Advances every instance by nsteps (asynchronous).  Stepping an instance
+ * on its own in between is allowed; the tables are rebuilt when needed. */
+cc_status cc_batch_step(cc_batch* b, int nsteps);
+const char* cc_batch_last_error(const cc_batch* b);
+void cc_batch_destroy(cc_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

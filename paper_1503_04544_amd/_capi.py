@@ -55,6 +55,14 @@ SYMBOLS = {
     "cc_set_tile_rows": (C.c_int, [C.c_void_p, C.c_int]),
     "cc_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "cc_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "cc_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p)]),
+    "cc_batch_workspace_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "cc_batch_bind": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "cc_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    "cc_batch_groups": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "cc_batch_step": (C.c_int, [C.c_void_p, C.c_int]),
+    "cc_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "cc_batch_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -516,6 +517,206 @@ cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launch
   if (total_ms) *total_ms = tot;
   if (launches) *launches = P.count[kernel];
   return CC_OK;
+}
+
+// ---------------------------------------------------------------------
+// batched instances
+// ---------------------------------------------------------------------
+static const int kBatchMinRows = 4;
+static const int kBatchRows[] = {8, 16, 32, 64, 128};
+
+static cc_status batch_fail(cc_batch* b, cc_status st, const std::string& msg) {
+  if (b) b->err = msg;
+  return st;
+}
+
+static cc_status batch_upload_and_capture(cc_batch* b) {
+  std::vector<char> d0, d1;
+  std::vector<int2> tiles, cuts;
+  batch_fill(b, d0, d1, tiles, cuts);
+  if (tiles.size() > b->tile_cap || cuts.size() > b->cut_cap)
+    return batch_fail(b, CC_ENOMEM, "batch work lists exceed the workspace");
+  b->ncut = (int)cuts.size();
+  hipError_t e;
+  if ((e = hipMemcpyAsync(b->d_desc0, d0.data(), d0.size(), hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(b->d_desc1, d1.data(), d1.size(), hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+      (tiles.size() && (e = hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(int2),
+                                           hipMemcpyHostToDevice, b->stream)) != hipSuccess) ||
+      (cuts.size() && (e = hipMemcpyAsync(b->d_cuts, cuts.data(), cuts.size() * sizeof(int2),
+                                          hipMemcpyHostToDevice, b->stream)) != hipSuccess) ||
+      (e = hipStreamSynchronize(b->stream)) != hipSuccess)
+    return batch_fail(b, CC_EHIP, std::string("batch upload: ") + hipGetErrorString(e));
+  // one step per ping-pong parity, recorded on a private capture stream
+  hipStream_t cap;
+  if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess)
+    return batch_fail(b, CC_EHIP, "capture stream");
+  hipStream_t user = b->stream;
+  for (int par = 0; par < 2; ++par) {
+    if (b->exec[par]) { hipGraphExecDestroy(b->exec[par]); b->exec[par] = nullptr; }
+    if (b->graph[par]) { hipGraphDestroy(b->graph[par]); b->graph[par] = nullptr; }
+    b->stream = cap;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t le = batch_launch_step(b, par);
+      e = hipStreamEndCapture(cap, &b->graph[par]);
+      if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[par], b->graph[par], nullptr, nullptr, 0);
+    b->stream = user;
+    if (e != hipSuccess) {
+      hipStreamDestroy(cap);
+      return batch_fail(b, CC_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+  }
+  hipStreamDestroy(cap);
+  b->base_cur.resize(b->ctx.size());
+  for (size_t i = 0; i < b->ctx.size(); ++i) b->base_cur[i] = b->ctx[i]->cur;
+  b->steps = 0;
+  return CC_OK;
+}
+
+cc_status cc_batch_create(cc_ctx* const* ctxs, int n, cc_batch** out) {
+  if (!ctxs || n < 1 || !out) return CC_EINVAL;
+  *out = nullptr;
+  cc_batch* b = new (std::nothrow) cc_batch();
+  if (!b) return CC_ENOMEM;
+  for (int i = 0; i < n; ++i) {
+    cc_ctx* c = ctxs[i];
+    bool ok = c && c->bound && c->dim == 2 && !is_moving(c) && batch_supported_nch(batch_group_nch(c));
+    for (int k = 0; k < i && ok; ++k) ok = ctxs[k] != c;
+    if (ok && i > 0) ok = c->stream == ctxs[0]->stream;
+    if (!ok) {
+      fprintf(stderr, "ccdvm: batch instance %d must be a distinct bound 2D fixed-body context on the "
+                      "stream of instance 0\n", i);
+      delete b;
+      return CC_EINVAL;
+    }
+    b->ctx.push_back(c);
+    int g = batch_group_nch(c);
+    bool seen = false;
+    for (int x : b->group_nch) seen |= x == g;
+    if (!seen) b->group_nch.push_back(g);
+  }
+  std::sort(b->group_nch.begin(), b->group_nch.end());
+  b->group_rows.assign(b->group_nch.size(), 16);   // until cc_batch_autotune picks per group
+  b->stream = ctxs[0]->stream;
+  for (cc_ctx* c : b->ctx) {
+    b->tile_cap += (size_t)((c->nx + 3) / 4) * ((c->ny + kBatchMinRows - 1) / kBatchMinRows);
+    b->cut_cap += c->n_irr;
+  }
+  size_t desc = align_up(n * batch_desc_bytes());
+  b->dev_bytes = 2 * desc + align_up(b->tile_cap * sizeof(int2)) + align_up((b->cut_cap + 1) * sizeof(int2));
+  *out = b;
+  return CC_OK;
+}
+
+cc_status cc_batch_workspace_bytes(const cc_batch* b, size_t* bytes) {
+  if (!b || !bytes) return CC_EINVAL;
+  *bytes = b->dev_bytes;
+  return CC_OK;
+}
+
+cc_status cc_batch_bind(cc_batch* b, void* workspace) {
+  if (!b || !workspace) return CC_EINVAL;
+  if ((uintptr_t)workspace % kAlign) return batch_fail(b, CC_EINVAL, "workspace must be 256-byte aligned");
+  b->dev = (char*)workspace;
+  size_t desc = align_up(b->ctx.size() * batch_desc_bytes());
+  b->d_desc0 = b->dev;
+  b->d_desc1 = b->dev + desc;
+  b->d_tiles = (int2*)(b->dev + 2 * desc);
+  b->d_cuts = (int2*)(b->dev + 2 * desc + align_up(b->tile_cap * sizeof(int2)));
+  for (cc_ctx* c : b->ctx) {
+    cc_status st = prepare(c);
+    if (st != CC_OK) return batch_fail(b, st, "instance preparation failed: " + c->err);
+  }
+  cc_status st = batch_upload_and_capture(b);
+  if (st != CC_OK) return st;
+  b->bound = true;
+  return CC_OK;
+}
+
+cc_status cc_batch_autotune(cc_batch* b, int trial_steps, int* rows_out) {
+  if (!b || trial_steps < 1) return CC_EINVAL;
+  if (!b->bound) return batch_fail(b, CC_ESTATE, "cc_batch_bind first");
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return batch_fail(b, CC_EHIP, "events");
+  for (size_t g = 0; g < b->group_nch.size(); ++g) {
+    double best = 1e300;
+    int best_rows = 0;
+    for (int rows : kBatchRows) {
+      b->group_rows[g] = rows;
+      cc_status st = batch_upload_and_capture(b);
+      if (st != CC_OK) return st;
+      batch_launch_group(b, (int)g);   // warm-up
+      hipEventRecord(e0, b->stream);
+      for (int k = 0; k < trial_steps; ++k) batch_launch_group(b, (int)g);
+      hipEventRecord(e1, b->stream);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; best_rows = rows; }
+    }
+    b->group_rows[g] = best_rows;
+    if (rows_out) rows_out[g] = best_rows;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  // the trials advanced the regular cells of the ping-pong targets only, but
+  // rewrote the stored moments: recompute them from the current states
+  for (cc_ctx* c : b->ctx) c->mom_valid = false;
+  for (cc_ctx* c : b->ctx) {
+    cc_status st = prepare(c);
+    if (st != CC_OK) return batch_fail(b, st, "instance preparation failed");
+  }
+  return batch_upload_and_capture(b);
+}
+
+cc_status cc_batch_groups(const cc_batch* b, int* ngroups, int* chunks, int* rows) {
+  if (!b || !ngroups) return CC_EINVAL;
+  *ngroups = (int)b->group_nch.size();
+  for (size_t g = 0; g < b->group_nch.size(); ++g) {
+    if (chunks) chunks[g] = b->group_nch[g];
+    if (rows) rows[g] = b->group_rows[g];
+  }
+  return CC_OK;
+}
+
+cc_status cc_batch_step(cc_batch* b, int nsteps) {
+  if (!b || nsteps < 0) return CC_EINVAL;
+  if (!b->bound) return batch_fail(b, CC_ESTATE, "cc_batch_bind first");
+  bool stale = false;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    cc_ctx* c = b->ctx[i];
+    stale |= c->cur != (b->base_cur[i] ^ (int)(b->steps & 1));
+    cc_status st = prepare(c);
+    if (st != CC_OK) return batch_fail(b, st, "instance preparation failed");
+  }
+  if (stale) {
+    cc_status st = batch_upload_and_capture(b);
+    if (st != CC_OK) return st;
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    hipError_t e = hipGraphLaunch(b->exec[(b->steps + k) & 1], b->stream);
+    if (e != hipSuccess) return batch_fail(b, CC_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+  }
+  b->steps += nsteps;
+  for (cc_ctx* c : b->ctx) {
+    c->cur ^= nsteps & 1;
+    c->nstep += nsteps;
+  }
+  return CC_OK;
+}
+
+const char* cc_batch_last_error(const cc_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+void cc_batch_destroy(cc_batch* b) {
+  if (!b) return;
+  for (int par = 0; par < 2; ++par) {
+    if (b->exec[par]) hipGraphExecDestroy(b->exec[par]);
+    if (b->graph[par]) hipGraphDestroy(b->graph[par]);
+  }
+  delete b;
 }
 
 }  // extern "C"

@@ -160,7 +160,37 @@ struct cc_ctx {
   std::string err;
 };
 
+struct cc_batch {
+  std::vector<cc_ctx*> ctx;
+  std::vector<int> base_cur;        // each instance's current buffer when the tables were built
+  hipStream_t stream = nullptr;
+  char* dev = nullptr;              // caller-owned workspace
+  size_t dev_bytes = 0;
+  void* d_desc0 = nullptr;
+  void* d_desc1 = nullptr;
+  int2* d_tiles = nullptr;
+  int2* d_cuts = nullptr;
+  size_t tile_cap = 0, cut_cap = 0;
+  int ncut = 0;
+  std::vector<int> group_nch, group_rows, group_off, group_cnt;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  long long steps = 0;              // batched steps since the tables were built
+  bool bound = false;
+  std::string err;
+};
+
 namespace ccdvm {
+
+// batched step (step2d.hip)
+int batch_group_nch(const cc_ctx* ctx);
+bool batch_supported_nch(int nch);
+size_t batch_desc_bytes();
+void batch_fill(cc_batch* B, std::vector<char>& desc0, std::vector<char>& desc1,
+                std::vector<int2>& tiles, std::vector<int2>& cuts);
+hipError_t batch_launch_step(cc_batch* B, int par);
+hipError_t batch_launch_group(cc_batch* B, int g);
+int tile_rows(const cc_ctx* ctx);
 
 // geometry (geom2d.hip / geom3d.hip)
 hipError_t build_geometry_2d(cc_ctx* ctx, Geo2D& G, const double* pose);

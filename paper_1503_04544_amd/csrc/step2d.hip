@@ -22,6 +22,9 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <string.h>
+
+#include <vector>
 
 #include "ccdvm_impl.h"
 
@@ -972,6 +975,74 @@ __global__ void __launch_bounds__(256) k_rigid2d(const int* __restrict__ gcount,
   }
 }
 
+
+// =====================================================================
+// Batched step: many independent instances (each its own grid, velocity
+// grid, Kn, T_w, Mach) advanced together.  One kernel walks the cut/merged
+// control volumes of every instance, and one kernel per velocity-grid size
+// walks the regular-cell tiles of every instance of that size, in an
+// XCD-aware order; a step is captured once as a hipGraph.
+// =====================================================================
+struct BatchInst {
+  Geo2D G;
+  FusedArgs A;
+  StepParams P;
+};
+
+template <int NCH>
+__global__ void __launch_bounds__(256) k_batch_tiles2d(const BatchInst* __restrict__ D,
+                                                       const int2* __restrict__ items, int nitems,
+                                                       int nitems_pad) {
+  __shared__ double lds[8];
+  const int b = blockIdx.x;
+  const int per = nitems_pad / 8;
+  const int w = (b % 8) * per + b / 8;
+  if (w >= nitems) return;
+  const int2 it = items[w];
+  const BatchInst& d = D[it.x];
+  regular_tile<NCH>(d.G, d.A, d.P, it.y, lds);
+}
+
+__global__ void __launch_bounds__(256) k_batch_cut2d(const BatchInst* __restrict__ D,
+                                                     const int2* __restrict__ items, int nitems) {
+  __shared__ double lds[8];
+  const int w = blockIdx.x;
+  if (w >= nitems) return;
+  const int2 it = items[w];
+  const BatchInst& d = D[it.x];
+  cut_cv(d.G, d.A.in, d.A.out, d.A.mom, d.A.fslot, d.A.mpart + d.A.ntiles + it.y, d.A.body, d.P,
+         it.y, lds);
+}
+
+typedef void (*batch_tiles_fn)(hipStream_t, const BatchInst*, const int2*, int);
+
+template <int NCH>
+void launch_batch_tiles(hipStream_t st, const BatchInst* D, const int2* items, int n) {
+  const int pad = (n + 7) / 8 * 8;
+  k_batch_tiles2d<NCH><<<pad, 256, 0, st>>>(D, items, n, pad);
+}
+
+batch_tiles_fn pick_batch_tiles(int nch) {
+  switch (nch) {
+    case 1: return launch_batch_tiles<1>;
+    case 2: return launch_batch_tiles<2>;
+    case 3: return launch_batch_tiles<3>;
+    case 4: return launch_batch_tiles<4>;
+    case 5: return launch_batch_tiles<5>;
+    case 6: return launch_batch_tiles<6>;
+    case 7: return launch_batch_tiles<7>;
+    case 8: return launch_batch_tiles<8>;
+    case 9: return launch_batch_tiles<9>;
+    case 10: return launch_batch_tiles<10>;
+    case 11: return launch_batch_tiles<11>;
+    case 12: return launch_batch_tiles<12>;
+    case 13: return launch_batch_tiles<13>;
+    case 14: return launch_batch_tiles<14>;
+    case 16: return launch_batch_tiles<16>;
+    default: return nullptr;
+  }
+}
+
 typedef void (*fused_fn)(const cc_ctx*, dim3, const FusedArgs&, const StepParams&);
 
 template <int NCH>
@@ -1255,6 +1326,93 @@ hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_ro
   ctx->step_parity = 1 - par;
   ctx->nstep += 1;
   return e;
+}
+
+
+// ---------------------------------------------------------------------
+// batch host side
+// ---------------------------------------------------------------------
+static FusedArgs fused_args_for(const cc_ctx* ctx, int in_buf, int rows) {
+  FusedArgs A;
+  A.kind = ctx->g2.kind;
+  A.in = (const double2*)ctx->state[in_buf];
+  A.out = (double2*)ctx->state[1 - in_buf];
+  A.mom = ctx->s.mom;
+  A.body = ctx->s.body;
+  A.ngroups = (ctx->nx + kTileW - 1) / kTileW;
+  A.seglen = rows;
+  const int nseg = (ctx->ny + rows - 1) / rows;
+  A.ntiles = A.ngroups * nseg;
+  A.ntiles_pad = (A.ntiles + 7) / 8 * 8;
+  A.n_cut = ctx->n_irr;
+  A.cut_base = 0;
+  A.tile_base = 0;
+  A.split = split_rows(ctx);
+  A.fslot = ctx->s.fslot;
+  A.mpart = ctx->s.mpart;
+  A.prev_fslot = nullptr;
+  A.prev_mpart = nullptr;
+  A.red_force = nullptr;
+  A.red_mass = nullptr;
+  return A;
+}
+
+int batch_group_nch(const cc_ctx* ctx) { return chunks_per_half(ctx); }
+bool batch_supported_nch(int nch) { return pick_batch_tiles(nch) != nullptr; }
+
+size_t batch_desc_bytes() { return sizeof(BatchInst); }
+
+// Host images of the descriptors (parity 0: each instance reads its current
+// buffer; parity 1: the other one) and of the work lists.
+void batch_fill(cc_batch* B, std::vector<char>& desc0, std::vector<char>& desc1,
+                std::vector<int2>& tiles, std::vector<int2>& cuts) {
+  const int n = (int)B->ctx.size();
+  desc0.assign(n * sizeof(BatchInst), 0);
+  desc1.assign(n * sizeof(BatchInst), 0);
+  tiles.clear();
+  cuts.clear();
+  B->group_off.assign(B->group_nch.size(), 0);
+  B->group_cnt.assign(B->group_nch.size(), 0);
+  for (size_t g = 0; g < B->group_nch.size(); ++g) {
+    B->group_off[g] = (int)tiles.size();
+    for (int i = 0; i < n; ++i) {
+      cc_ctx* c = B->ctx[i];
+      if (batch_group_nch(c) != B->group_nch[g]) continue;
+      const int rows = B->group_rows[g] > 0 ? B->group_rows[g] : tile_rows(c);
+      for (int par = 0; par < 2; ++par) {
+        BatchInst d;
+        d.G = c->g2;
+        d.A = fused_args_for(c, c->cur ^ par, rows);
+        d.P = params2d(c);
+        memcpy((par ? desc1 : desc0).data() + i * sizeof(BatchInst), &d, sizeof(d));
+      }
+      BatchInst d0;
+      memcpy(&d0, desc0.data() + i * sizeof(BatchInst), sizeof(d0));
+      for (int t = 0; t < d0.A.ntiles; ++t) tiles.push_back(make_int2(i, t));
+    }
+    B->group_cnt[g] = (int)tiles.size() - B->group_off[g];
+  }
+  for (int i = 0; i < n; ++i)
+    for (int q = 0; q < B->ctx[i]->n_irr; ++q) cuts.push_back(make_int2(i, q));
+}
+
+// launch one batched step (parity 0 or 1) on the batch stream
+hipError_t batch_launch_step(cc_batch* B, int par) {
+  const BatchInst* D = (const BatchInst*)(par ? B->d_desc1 : B->d_desc0);
+  if (B->ncut > 0)
+    k_batch_cut2d<<<B->ncut, 256, 0, B->stream>>>(D, B->d_cuts, B->ncut);
+  for (size_t g = 0; g < B->group_nch.size(); ++g) {
+    if (B->group_cnt[g] == 0) continue;
+    pick_batch_tiles(B->group_nch[g])(B->stream, D, B->d_tiles + B->group_off[g], B->group_cnt[g]);
+  }
+  return hipGetLastError();
+}
+
+// tile kernel of one group only (autotuning)
+hipError_t batch_launch_group(cc_batch* B, int g) {
+  const BatchInst* D = (const BatchInst*)B->d_desc0;
+  pick_batch_tiles(B->group_nch[g])(B->stream, D, B->d_tiles + B->group_off[g], B->group_cnt[g]);
+  return hipGetLastError();
 }
 
 // reduce the partials of the step that just ran into its force row and the

@@ -146,3 +146,54 @@ class Solver:
         ms, n = C.c_double(), C.c_int()
         self._check(lib().cc_profile_read(self._h, kernel, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+
+class Batch:
+    """Several Solvers on the same stream advanced together (cc_batch_*)."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        arr = (C.c_void_p * len(self.solvers))(*[s._h.value for s in self.solvers])
+        h = C.c_void_p()
+        st = lib().cc_batch_create(arr, len(self.solvers), C.byref(h))
+        if st != 0:
+            raise CCError(st, "cc_batch_create rejected the instances")
+        self._h = h
+        nb = C.c_size_t()
+        self._check(lib().cc_batch_workspace_bytes(h, C.byref(nb)))
+        dev = self.solvers[0].device
+        self.workspace = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=dev)
+        self._check(lib().cc_batch_bind(h, _ptr(self.workspace)))
+
+    def _check(self, st):
+        if st != 0:
+            msg = lib().cc_batch_last_error(self._h) if getattr(self, "_h", None) else b""
+            raise CCError(st, (msg or b"").decode())
+
+    def groups(self):
+        n = C.c_int()
+        ch = (C.c_int * 16)()
+        rows = (C.c_int * 16)()
+        self._check(lib().cc_batch_groups(self._h, C.byref(n), ch, rows))
+        return [(ch[i], rows[i]) for i in range(n.value)]
+
+    def autotune(self, trial_steps: int = 5):
+        n = len(self.groups())
+        out = (C.c_int * max(n, 1))()
+        self._check(lib().cc_batch_autotune(self._h, int(trial_steps), out))
+        return list(out[:n])
+
+    def step(self, nsteps: int = 1):
+        self._check(lib().cc_batch_step(self._h, int(nsteps)))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().cc_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,90 @@
+"""Batched step (one graph launch per step over heterogeneous instances):
+bitwise identical to stepping each instance alone, and equal to the oracle."""
+import numpy as np
+import pytest
+
+from ccdvm_inputs import Body, batch_instances, small_2d
+from oracle import Oracle2D
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _cfgs():
+    return [
+        small_2d(24, 20, 8, kn=0.1, mach=0.4, body=Body("circle", (0.5, 0.5, 0), (0.2, 0.2, 0), t_wall=0.8)),
+        small_2d(32, 32, 12, kn=0.02, mach=0.9, body=Body("circle", (0.45, 0.55, 0), (0.18, 0.18, 0), t_wall=1.7)),
+        small_2d(16, 40, 16, kn=0.5, mach=0.3, body=Body("ellipse", (0.5, 0.5, 0), (0.3, 0.1, 0), theta=0.3)),
+        small_2d(20, 20, 8, kn=0.0, mach=0.6, body=Body("none")),
+        small_2d(40, 28, 12, kn=0.3, mach=0.5, body=Body("circle", (0.5, 0.5, 0), (0.25, 0.25, 0))),
+    ]
+
+
+def _solvers(cfgs, stream):
+    from paper_1503_04544_amd.solver import Solver
+    out = []
+    for c in cfgs:
+        s = Solver(c, device="cuda:0", stream=stream)
+        s.init_maxwellian()
+        out.append(s)
+    return out
+
+
+def _states(solvers):
+    return [tuple(t.cpu().numpy() for t in s.store_state()) for s in solvers]
+
+
+def test_batch_equals_sequential_and_oracle():
+    from paper_1503_04544_amd.solver import Batch
+    cfgs = _cfgs()
+    stream = torch.cuda.Stream()
+    seq = _solvers(cfgs, stream)
+    for s in seq:
+        s.step(15)
+    ref = _states(seq)
+    bat = _solvers(cfgs, stream)
+    b = Batch(bat)
+    assert len(b.groups()) == 2    # chunks per half-row: N=8 -> 1, N=12 and N=16 -> 2
+    b.step(15)
+    got = _states(bat)
+    for (f0, g0), (f1, g1) in zip(ref, got):
+        assert np.array_equal(f0, f1) and np.array_equal(g0, g1)
+    o = Oracle2D(cfgs[1])
+    f, g = o.init()
+    fo, go, _ = o.run(f, g, 15)
+    assert np.max(np.abs(got[1][0] - fo)) / np.max(fo) < 1e-10
+
+
+def test_batch_autotune_and_interleaving_keep_results():
+    from paper_1503_04544_amd.solver import Batch
+    cfgs = _cfgs()
+    stream = torch.cuda.Stream()
+    seq = _solvers(cfgs, stream)
+    for s in seq:
+        s.step(9)
+    ref = _states(seq)
+    bat = _solvers(cfgs, stream)
+    b = Batch(bat)
+    rows = b.autotune(3)
+    assert all(r in (8, 16, 32, 64, 128) for r in rows)
+    b.step(4)
+    for s in bat:          # step every instance alone once: the batch tables must follow
+        s.step(1)
+    b.step(4)
+    got = _states(bat)
+    for (f0, g0), (f1, g1) in zip(ref, got):
+        assert np.array_equal(f0, f1) and np.array_equal(g0, g1)
+
+
+def test_batch_instances_recipe():
+    inst = batch_instances()
+    assert len(inst) == 64
+    assert {c.n[0] for c in inst} <= {64, 128, 256}
+    assert {c.nv for c in inst} <= {16, 24, 32}
+    assert all(0.01 <= c.kn <= 1.0 and 0.5 <= c.body.t_wall <= 2.0 for c in inst)
