@@ -75,13 +75,62 @@ def cpu_baseline(cfg, nsteps):
                       f"Maxwellian ({dt:.1f} s)"}
 
 
+def bench_batch(args):
+    """64 heterogeneous 2D fixed-cylinder instances (seeded recipe): batched
+    step (one graph launch per step) against the same instances stepped one
+    after the other with their own launches."""
+    import torch
+    from ccdvm_inputs import batch_instances
+    from paper_1503_04544_amd.solver import Batch, Solver
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    cfgs = batch_instances()
+    solvers = []
+    for c in cfgs:
+        s = Solver(c, device=dev, stream=stream)
+        s.init_maxwellian()
+        solvers.append(s)
+    upd = sum((c.ncell - s.counts()[2]) * c.nv ** 2 for c, s in zip(cfgs, solvers))
+    steps = args.steps
+    log(f"bench batch: {len(cfgs)} instances, {upd / 1e6:.1f} M cell-velocity updates per step")
+    for s in solvers:
+        s.step(args.warmup)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(steps)
+    stream.synchronize()
+    t_seq = time.perf_counter() - t0
+    b = Batch(solvers)
+    rows = b.autotune(5)
+    b.step(args.warmup)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    stream.synchronize()
+    t_bat = time.perf_counter() - t0
+    out = {
+        "metric": "cell-velocity updates/s", "value": round(upd * steps / t_bat / 1e9, 3),
+        "unit": "G cell-velocity updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(t_bat / steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch: 64 2D fixed-cylinder instances, n in {64,128,256}^2, "
+                               "N in {16,24,32}^2, Kn 10^U(-2,0), T_w U(0.5,2), Mach U(0.3,1), seed 20150316",
+                   "updates_per_step": upd,
+                   "sequential_ms_per_step": round(t_seq / steps * 1e3, 4),
+                   "batched_over_sequential": round(t_seq / t_bat, 3),
+                   "groups_chunks_rows": b.groups(), "autotuned_rows": rows},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kn", type=float, default=None)
-    ap.add_argument("--workload", default="cyl512", choices=["cyl512", "ellipse256", "cyl32"],
+    ap.add_argument("--workload", default="cyl512", choices=["cyl512", "ellipse256", "cyl32", "batch"],
                     help="cyl512 (default, the headline line) | ellipse256 (moving body) | cyl32")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
@@ -105,6 +154,8 @@ def main():
         return
     from ccdvm_inputs import workload
     from paper_1503_04544_amd.solver import Solver
+    if args.workload == "batch":
+        return bench_batch(args)
 
     cfg = workload(args.workload, kn=args.kn)
     dev = torch.device("cuda:0")

@@ -188,7 +188,7 @@ bool batch_supported_nch(int nch);
 size_t batch_desc_bytes();
 void batch_fill(cc_batch* B, std::vector<char>& desc0, std::vector<char>& desc1,
                 std::vector<int2>& tiles, std::vector<int2>& cuts);
-hipError_t batch_launch_step(cc_batch* B, int par);
+hipError_t batch_launch_step(cc_batch* B, int par, hipStream_t* side, int nside);
 hipError_t batch_launch_group(cc_batch* B, int g);
 int tile_rows(const cc_ctx* ctx);
 

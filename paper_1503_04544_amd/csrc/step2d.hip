@@ -311,23 +311,45 @@ __device__ inline void load_half(d2v (&dst)[NCH], const d2v* __restrict__ row, i
 // half, y-upwind neighbour below).  Both halves are walked together, chunk
 // by chunk: chunk k of either half holds the same p1 for a given lane, so
 // the x-upwind cell and the x part of the Maxwellian are shared.
+// Everything the regular-cell tile needs, passed by value so that it lives
+// in scalar registers.
+struct TileArgs {
+  const int* kind;
+  const double2* in;
+  double2* out;
+  double* mom;
+  double* mpart;
+  const double2* ghost;
+  int nx, ny, N, nvel, ngroups, seglen, split;
+  double dx, dy;
+};
+
+__host__ __device__ inline TileArgs tile_args(const Geo2D& G, const FusedArgs& A) {
+  TileArgs T;
+  T.kind = A.kind; T.in = A.in; T.out = A.out; T.mom = A.mom; T.mpart = A.mpart;
+  T.ghost = G.ghost;
+  T.nx = G.nx; T.ny = G.ny; T.N = G.N; T.nvel = G.nvel;
+  T.ngroups = A.ngroups; T.seglen = A.seglen; T.split = A.split;
+  T.dx = G.dx; T.dy = G.dy;
+  return T;
+}
+
 template <int NCH>
-__device__ void regular_tile(const Geo2D& G, const FusedArgs& A, const StepParams& P, int tile,
-                             double* lds) {
+__device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, double* lds) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int gi = tile % A.ngroups, seg = tile / A.ngroups;
+  const int gi = tile % Ta.ngroups, seg = tile / Ta.ngroups;
   const int i = gi * kTileW + wave;
-  const int nx = G.nx, ny = G.ny, N = G.N, nvel = G.nvel;
-  const int j0 = seg * A.seglen, j1 = min(j0 + A.seglen, ny);
-  const int split = A.split;
+  const int nx = Ta.nx, ny = Ta.ny, N = Ta.N, nvel = Ta.nvel;
+  const int j0 = seg * Ta.seglen, j1 = min(j0 + Ta.seglen, ny);
+  const int split = Ta.split;
   const int lo_n = split * N, hi_n = nvel - lo_n;   // sizes of the two halves
-  const d2v* in = reinterpret_cast<const d2v*>(A.in);
-  d2v* out = reinterpret_cast<d2v*>(A.out);
-  const d2v* ghost = reinterpret_cast<const d2v*>(G.ghost);
+  const d2v* in = reinterpret_cast<const d2v*>(Ta.in);
+  d2v* out = reinterpret_cast<d2v*>(Ta.out);
+  const d2v* ghost = reinterpret_cast<const d2v*>(Ta.ghost);
   double msum = 0.0;
   if (i < nx && j0 < j1) {
-    const double S = G.dx * G.dy;
-    const double cxf = P.dt / S * G.dy, cyf = P.dt / S * G.dx;
+    const double S = Ta.dx * Ta.dy;
+    const double cxf = P.dt / S * Ta.dy, cyf = P.dt / S * Ta.dx;
     d2v prevU[NCH], curL[NCH];
     load_half<NCH>(prevU, j0 > 0 ? in + (size_t)((j0 - 1) * nx + i) * nvel : ghost, lo_n, hi_n, lane);
     load_half<NCH>(curL, in + (size_t)(j0 * nx + i) * nvel, 0, lo_n, lane);
@@ -335,10 +357,10 @@ __device__ void regular_tile(const Geo2D& G, const FusedArgs& A, const StepParam
       const int c = j * nx + i;
       const d2v* row = in + (size_t)c * nvel;
       const d2v* nrow = j + 1 < ny ? row + (size_t)nx * nvel : ghost;
-      const bool reg = A.kind[c] == KIND_REGULAR;   // uniform over the wave
+      const bool reg = Ta.kind[c] == KIND_REGULAR;   // uniform over the wave
       double Am = 0.0, T = 1.0, dtau = 0.0, tx = 0.0, ty = 0.0;
       if (reg) {
-        const double* mc = A.mom + 4 * c;
+        const double* mc = Ta.mom + 4 * c;
         const double rho = mc[0], ux = mc[1], uy = mc[2];
         T = mc[3];
         const double inv2T = 0.5 / T;
@@ -419,7 +441,7 @@ __device__ void regular_tile(const Geo2D& G, const FusedArgs& A, const StepParam
         const double r = sr * P.w;
         if (lane == 0) {
           const double mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
-          double* mo = A.mom + 4 * c;
+          double* mo = Ta.mom + 4 * c;
           mo[0] = r; mo[1] = mx; mo[2] = my;
           mo[3] = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
         }
@@ -430,7 +452,7 @@ __device__ void regular_tile(const Geo2D& G, const FusedArgs& A, const StepParam
   __syncthreads();
   if (lane == 0) lds[wave] = msum;
   __syncthreads();
-  if (threadIdx.x == 0) A.mpart[tile] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+  if (threadIdx.x == 0) Ta.mpart[tile] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
 }
 
 // regular-cell tiles (+ block 0: deferred reduction of the previous step)
@@ -448,7 +470,7 @@ __global__ void __launch_bounds__(256) k_step2d(Geo2D G, FusedArgs A, StepParams
   const int per = A.ntiles_pad / 8;
   const int tile = (b % 8) * per + b / 8;
   if (tile >= A.ntiles) return;
-  regular_tile<NCH>(G, A, P, tile, lds);
+  regular_tile<NCH>(tile_args(G, A), P, tile, lds);
 }
 
 // cut / merged control volumes of one step, one 256-thread block each
@@ -987,6 +1009,7 @@ struct BatchInst {
   Geo2D G;
   FusedArgs A;
   StepParams P;
+  TileArgs T;
 };
 
 template <int NCH>
@@ -999,8 +1022,9 @@ __global__ void __launch_bounds__(256) k_batch_tiles2d(const BatchInst* __restri
   const int w = (b % 8) * per + b / 8;
   if (w >= nitems) return;
   const int2 it = items[w];
-  const BatchInst& d = D[it.x];
-  regular_tile<NCH>(d.G, d.A, d.P, it.y, lds);
+  const int inst = __builtin_amdgcn_readfirstlane(it.x);
+  const int tile = __builtin_amdgcn_readfirstlane(it.y);
+  regular_tile<NCH>(D[inst].T, D[inst].P, tile, lds);
 }
 
 __global__ void __launch_bounds__(256) k_batch_cut2d(const BatchInst* __restrict__ D,
@@ -1009,9 +1033,11 @@ __global__ void __launch_bounds__(256) k_batch_cut2d(const BatchInst* __restrict
   const int w = blockIdx.x;
   if (w >= nitems) return;
   const int2 it = items[w];
-  const BatchInst& d = D[it.x];
-  cut_cv(d.G, d.A.in, d.A.out, d.A.mom, d.A.fslot, d.A.mpart + d.A.ntiles + it.y, d.A.body, d.P,
-         it.y, lds);
+  const int inst = __builtin_amdgcn_readfirstlane(it.x);
+  const int q = __builtin_amdgcn_readfirstlane(it.y);
+  const Geo2D G = D[inst].G;
+  const FusedArgs A = D[inst].A;
+  cut_cv(G, A.in, A.out, A.mom, A.fslot, A.mpart + A.ntiles + q, A.body, D[inst].P, q, lds);
 }
 
 typedef void (*batch_tiles_fn)(hipStream_t, const BatchInst*, const int2*, int);
@@ -1384,6 +1410,7 @@ void batch_fill(cc_batch* B, std::vector<char>& desc0, std::vector<char>& desc1,
         d.G = c->g2;
         d.A = fused_args_for(c, c->cur ^ par, rows);
         d.P = params2d(c);
+        d.T = tile_args(d.G, d.A);
         memcpy((par ? desc1 : desc0).data() + i * sizeof(BatchInst), &d, sizeof(d));
       }
       BatchInst d0;
@@ -1396,16 +1423,48 @@ void batch_fill(cc_batch* B, std::vector<char>& desc0, std::vector<char>& desc1,
     for (int q = 0; q < B->ctx[i]->n_irr; ++q) cuts.push_back(make_int2(i, q));
 }
 
-// launch one batched step (parity 0 or 1) on the batch stream
-hipError_t batch_launch_step(cc_batch* B, int par) {
+// launch one batched step (parity 0 or 1) on the batch stream; with side
+// streams (graph capture), the cut-cell kernel and each group's tile kernel
+// are recorded on their own branch so the graph may run them concurrently
+hipError_t batch_launch_step(cc_batch* B, int par, hipStream_t* side, int nside) {
   const BatchInst* D = (const BatchInst*)(par ? B->d_desc1 : B->d_desc0);
-  if (B->ncut > 0)
-    k_batch_cut2d<<<B->ncut, 256, 0, B->stream>>>(D, B->d_cuts, B->ncut);
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;
+  if (nside > 0) {
+    hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    hipEventRecord(fork, B->stream);
+  }
+  int branch = 0;
+  auto on_branch = [&]() -> hipStream_t {
+    if (nside == 0) return B->stream;
+    hipStream_t s = side[branch % nside];
+    ++branch;
+    hipStreamWaitEvent(s, fork, 0);
+    return s;
+  };
+  auto close_branch = [&](hipStream_t s) {
+    if (nside == 0) return;
+    hipEvent_t j;
+    hipEventCreateWithFlags(&j, hipEventDisableTiming);
+    hipEventRecord(j, s);
+    joins.push_back(j);
+  };
+  if (B->ncut > 0) {
+    hipStream_t s = on_branch();
+    k_batch_cut2d<<<B->ncut, 256, 0, s>>>(D, B->d_cuts, B->ncut);
+    close_branch(s);
+  }
   for (size_t g = 0; g < B->group_nch.size(); ++g) {
     if (B->group_cnt[g] == 0) continue;
-    pick_batch_tiles(B->group_nch[g])(B->stream, D, B->d_tiles + B->group_off[g], B->group_cnt[g]);
+    hipStream_t s = on_branch();
+    pick_batch_tiles(B->group_nch[g])(s, D, B->d_tiles + B->group_off[g], B->group_cnt[g]);
+    close_branch(s);
   }
-  return hipGetLastError();
+  for (hipEvent_t j : joins) hipStreamWaitEvent(B->stream, j, 0);
+  hipError_t e = hipGetLastError();
+  for (hipEvent_t j : joins) hipEventDestroy(j);
+  if (fork) hipEventDestroy(fork);
+  return e;
 }
 
 // tile kernel of one group only (autotuning)
