@@ -66,6 +66,11 @@ void orc2d_force(const orc2d *o, const double *fm, const double *gm, double *dia
 void orc2d_moments(const orc2d *o, const double *f, const double *g, double *out);
 /* body state: centre (2), theta, velocity (2), omega */
 void orc2d_body_state(const orc2d *o, double *state);
+/* adjoint (fixed bodies): nsteps from the inflow Maxwellian, objective
+   0 = drag, 1 = torque of the final state; out = J, dJ/dT_w, dJ/dKn,
+   dJ/du_x, dJ/du_y of the farfield velocity */
+int  orc2d_adjoint(orc2d *o, int nsteps, int objective, double *out);
+int  orc_threads(void);
 
 #ifdef __cplusplus
 }

@@ -73,6 +73,7 @@ def lib():
         _lib.orc2d_force.argtypes = [P, P, P, P]
         _lib.orc2d_moments.argtypes = [P, P, P, P]
         _lib.orc_threads.restype = C.c_int
+        _lib.orc2d_adjoint.argtypes = [P, C.c_int, C.c_int, P]
     return _lib
 
 
@@ -176,6 +177,14 @@ class Oracle2D:
         d = np.zeros(4)
         lib().orc2d_force(self._h, _p(np.ascontiguousarray(fm)), _p(np.ascontiguousarray(gm)), _p(d))
         return d
+
+    def adjoint(self, nsteps, objective="drag"):
+        """J and dJ/d(T_w, Kn, u_x, u_y) after nsteps from the inflow Maxwellian."""
+        out = np.zeros(5)
+        st = lib().orc2d_adjoint(self._h, int(nsteps), 0 if objective == "drag" else 1, _p(out))
+        if st != 0:
+            raise OracleError(f"oracle adjoint failed with status {st}")
+        return out[0], out[1:]
 
     def moments(self, f, g):
         out = np.zeros((self.ncell, 9))

@@ -751,3 +751,258 @@ int orc_threads(void) {
   return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* Adjoint of the fixed-geometry step (not in the paper: the transpose  */
+/* of the scheme above, written out term by term).                     */
+/*                                                                     */
+/* With x^n the merged state entering step n and Lambda^{n+1}_m the    */
+/* sensitivity of the objective to the value that control volume m     */
+/* writes to its members, the adjoint step accumulates                 */
+/*   a^n = sum_m (d Phi_m / d x^n)^T Lambda^{n+1}_m                     */
+/* per cell, and Lambda^n_m = sum over the members j of m of a^n[j]    */
+/* (the merge and the redistribution transpose into that sum).          */
+/* Terms: identity and relaxation (1 - beta) with beta = dt rho / kappa;*/
+/* the Jacobian of the Maxwellian through (rho, rho u, E); the upwind   */
+/* fluxes transposed (outflow on the own value, inflow gathered onto    */
+/* the upwind cell); the wall flux with its density phi_w linear in the */
+/* outgoing part of x (rank one per wall edge).  Parameter partials     */
+/* accumulate into dJ/dT_w, dJ/dKn and dJ/du (farfield faces and the    */
+/* initial state).                                                      */
+/* ------------------------------------------------------------------ */
+
+/* weights of the objective per wall edge: drag (1, 0), torque (-a_y, a_x) */
+static void obj_weights(const orc2d *o, const geo2d *G, int k, int objective,
+                        double *al, double *ga) {
+  if (objective == 0) { *al = 1.0; *ga = 0.0; return; }
+  double ax = G->rwx[k] - o->c[0], ay = G->rwy[k] - o->c[1];
+  *al = -ay; *ga = ax;
+}
+
+/* dJ/dx of the objective at a merged state, per cell (f only), plus dJ/dT_w */
+static void objective_adjoint(const orc2d *o, const geo2d *G, const double *fm, int objective,
+                              double *af, double *dTw) {
+  int nvel = o->nvel, N = o->N;
+  double Tw = o->cfg.t_wall, w = o->w;
+  for (int k = 0; k < o->ncell; ++k) {
+    if (G->lw[k] <= 0.0) continue;
+    int m = G->master[k];
+    const double *fc = fm + (size_t)m * nvel;
+    double al, ga;
+    obj_weights(o, G, k, objective, &al, &ga);
+    double num = 0.0, den = 0.0, dden = 0.0;
+    for (int p = 0; p < nvel; ++p) {
+      double vx = o->v[p % N], vy = o->v[p / N];
+      double cn = vx * G->nwx[k] + vy * G->nwy[k];
+      double Mw = maxw2(1.0, 0.0, 0.0, Tw, vx, vy);
+      if (cn > 0.0) num += cn * fc[p] * w;
+      else if (cn < 0.0) {
+        den += cn * Mw * w;
+        dden += cn * Mw * ((vx * vx + vy * vy) / (2.0 * Tw * Tw) - 1.0 / Tw) * w;
+      }
+    }
+    double phi = den != 0.0 ? -num / den : 0.0;
+    double dphi = den != 0.0 ? num / (den * den) * dden : 0.0;
+    /* sum over incoming velocities of psi c M_w w, and its T_w derivative */
+    double sin_ = 0.0, sdT = 0.0;
+    for (int p = 0; p < nvel; ++p) {
+      double vx = o->v[p % N], vy = o->v[p / N];
+      double cn = vx * G->nwx[k] + vy * G->nwy[k];
+      if (cn >= 0.0) continue;
+      double psi = al * vx + ga * vy;
+      double Mw = maxw2(1.0, 0.0, 0.0, Tw, vx, vy);
+      double dMw = Mw * ((vx * vx + vy * vy) / (2.0 * Tw * Tw) - 1.0 / Tw);
+      sin_ += psi * cn * Mw * w;
+      sdT += psi * cn * (dphi * Mw + phi * dMw) * w;
+    }
+    *dTw += G->lw[k] * sdT;
+    for (int q = 0; q < nvel; ++q) {
+      double vx = o->v[q % N], vy = o->v[q / N];
+      double cn = vx * G->nwx[k] + vy * G->nwy[k];
+      if (cn <= 0.0) continue;
+      double psi = al * vx + ga * vy;
+      af[(size_t)m * nvel + q] += G->lw[k] * (psi * cn * w + sin_ * (-cn * w / den));
+    }
+  }
+}
+
+/* one adjoint step: Lf, Lg = Lambda^{n+1} stored at master indices;
+   af, ag (zeroed by the caller) receive a^n per cell; gp += partials
+   (0: T_w, 1: Kn, 2: u_x, 3: u_y of the farfield) */
+static void adjoint_step(const orc2d *o, const geo2d *G, const double *fm, const double *gm,
+                         const double *Lf, const double *Lg, double *af, double *ag,
+                         double *gp) {
+  int nvel = o->nvel, N = o->N, nx = o->nx, ny = o->ny;
+  double dt = o->dt, w = o->w, Tw = o->cfg.t_wall;
+  const double *in = o->cfg.inflow;
+  int collide = o->cfg.kn > 0.0;
+  double kappa = sqrt(M_PI) / 2.0 * o->cfg.kn * o->cfg.lref / sqrt(2.0);
+  for (int m = 0; m < o->ncell; ++m) {
+    if (G->master[m] != m) continue;
+    const double *lf = Lf + (size_t)m * nvel, *lg = Lg + (size_t)m * nvel;
+    const double *fc = fm + (size_t)m * nvel, *gc = gm + (size_t)m * nvel;
+    double S = G->scv[m];
+    double rho, ux, uy, T;
+    cell_moments(o, fc, gc, &rho, &ux, &uy, &T);
+    double beta = collide ? dt * rho / kappa : 0.0;
+    /* (i) identity, relaxation and the Maxwellian's Jacobian */
+    for (int q = 0; q < nvel; ++q) {
+      af[(size_t)m * nvel + q] += (1.0 - beta) * lf[q];
+      ag[(size_t)m * nvel + q] += (1.0 - beta) * lg[q];
+    }
+    if (collide) {
+      double s_r = 0, s_ux = 0, s_uy = 0, s_T = 0, C = 0;
+      for (int p = 0; p < nvel; ++p) {
+        double vx = o->v[p % N], vy = o->v[p / N];
+        double cx = vx - ux, cy = vy - uy, c2 = cx * cx + cy * cy;
+        double E = maxw2(rho, ux, uy, T, vx, vy);
+        double dEr = E / rho, dEux = E * cx / T, dEuy = E * cy / T;
+        double dET = E * (c2 / (2.0 * T * T) - 1.0 / T);
+        s_r += lf[p] * dEr + lg[p] * 0.5 * T * dEr;
+        s_ux += lf[p] * dEux + lg[p] * 0.5 * T * dEux;
+        s_uy += lf[p] * dEuy + lg[p] * 0.5 * T * dEuy;
+        s_T += lf[p] * dET + lg[p] * (0.5 * E + 0.5 * T * dET);
+        C += lf[p] * (E - fc[p]) + lg[p] * (0.5 * T * E - gc[p]);
+      }
+      /* (rho, u, T) -> (rho, rho u, E) */
+      double u2 = ux * ux + uy * uy;
+      double A_r = s_r + s_ux * (-ux / rho) + s_uy * (-uy / rho) + s_T * (u2 - 3.0 * T) / (3.0 * rho);
+      double A_px = s_ux / rho + s_T * (-2.0 * ux / (3.0 * rho));
+      double A_py = s_uy / rho + s_T * (-2.0 * uy / (3.0 * rho));
+      double A_e = s_T * 2.0 / (3.0 * rho);
+      for (int q = 0; q < nvel; ++q) {
+        double vx = o->v[q % N], vy = o->v[q / N];
+        af[(size_t)m * nvel + q] += beta * w * (A_r + A_px * vx + A_py * vy + A_e * 0.5 * (vx * vx + vy * vy))
+                                    + dt * w / kappa * C;
+        ag[(size_t)m * nvel + q] += beta * w * A_e;
+      }
+      gp[1] += C * (-beta / o->cfg.kn);
+    }
+    /* (ii) fluxes of every edge of every member; (iii) wall edges */
+    for (int kk = G->mptr[m]; kk < G->mptr[m + 1]; ++kk) {
+      int k = G->midx[kk];
+      int i = k % nx, j = k / nx;
+      struct { double L; int nb; int axis; double sgn; } e[4] = {
+          {G->lxp[k], i + 1 < nx ? k + 1 : -1, 0, 1.0},
+          {G->lxm[k], i > 0 ? k - 1 : -1, 0, -1.0},
+          {G->lyp[k], j + 1 < ny ? k + nx : -1, 1, 1.0},
+          {G->lym[k], j > 0 ? k - nx : -1, 1, -1.0}};
+      for (int f = 0; f < 4; ++f) {
+        if (e[f].L == 0.0) continue;
+        for (int q = 0; q < nvel; ++q) {
+          double vd = e[f].axis == 0 ? o->v[q % N] : o->v[q / N];
+          double c = e[f].sgn * vd;
+          double cp = dmax(c, 0.0), cm = dmin(c, 0.0);
+          double co = -dt / S * e[f].L;
+          af[(size_t)k * nvel + q] += co * cp * lf[q];
+          ag[(size_t)k * nvel + q] += co * cp * lg[q];
+          if (e[f].nb >= 0) {
+            af[(size_t)e[f].nb * nvel + q] += co * cm * lf[q];
+            ag[(size_t)e[f].nb * nvel + q] += co * cm * lg[q];
+          } else if (cm != 0.0) {
+            /* farfield ghost M[rho, u, T] and T/2 of it: d/du_d = M (v_d - u_d)/T */
+            double vx = o->v[q % N], vy = o->v[q / N];
+            double M = maxw2(in[0], in[1], in[2], in[4], vx, vy);
+            double t = co * cm * (lf[q] + 0.5 * in[4] * lg[q]);
+            gp[2] += t * M * (vx - in[1]) / in[4];
+            gp[3] += t * M * (vy - in[2]) / in[4];
+          }
+        }
+      }
+      if (G->lw[k] > 0.0) {
+        double Lw = G->lw[k], co = -dt / S * Lw;
+        double num = 0.0, den = 0.0, dden = 0.0;
+        for (int p = 0; p < nvel; ++p) {
+          double vx = o->v[p % N], vy = o->v[p / N];
+          double cn = vx * G->nwx[k] + vy * G->nwy[k];
+          double Mw = maxw2(1.0, 0.0, 0.0, Tw, vx, vy);
+          if (cn > 0.0) num += cn * fc[p] * w;
+          else if (cn < 0.0) {
+            den += cn * Mw * w;
+            dden += cn * Mw * ((vx * vx + vy * vy) / (2.0 * Tw * Tw) - 1.0 / Tw) * w;
+          }
+        }
+        double phi = den != 0.0 ? -num / den : 0.0;
+        double dphi = den != 0.0 ? num / (den * den) * dden : 0.0;
+        double Lam = 0.0, dT = 0.0;
+        for (int p = 0; p < nvel; ++p) {
+          double vx = o->v[p % N], vy = o->v[p / N];
+          double cn = vx * G->nwx[k] + vy * G->nwy[k];
+          if (cn >= 0.0) continue;
+          double Mw = maxw2(1.0, 0.0, 0.0, Tw, vx, vy);
+          double dMw = Mw * ((vx * vx + vy * vy) / (2.0 * Tw * Tw) - 1.0 / Tw);
+          Lam += cn * Mw * (lf[p] + 0.5 * Tw * lg[p]);
+          double dfw = dphi * Mw + phi * dMw;
+          double dgw = dphi * 0.5 * Tw * Mw + phi * (0.5 * Mw + 0.5 * Tw * dMw);
+          dT += cn * (lf[p] * dfw + lg[p] * dgw);
+        }
+        gp[0] += co * dT;
+        for (int q = 0; q < nvel; ++q) {
+          double vx = o->v[q % N], vy = o->v[q / N];
+          double cn = vx * G->nwx[k] + vy * G->nwy[k];
+          if (cn <= 0.0) continue;
+          af[(size_t)k * nvel + q] += co * cn * lf[q];
+          ag[(size_t)k * nvel + q] += co * cn * lg[q];
+          af[(size_t)m * nvel + q] += co * Lam * (-cn * w / den);
+        }
+      }
+    }
+  }
+}
+
+/* Lambda_m = sum over the members j of m of a[j], stored at m */
+static void cv_sum(const orc2d *o, const geo2d *G, const double *a, double *L) {
+  int nvel = o->nvel;
+  memset(L, 0, (size_t)o->ncell * nvel * sizeof(double));
+  for (int c = 0; c < o->ncell; ++c) {
+    int m = G->master[c];
+    if (m < 0) continue;
+    for (int p = 0; p < nvel; ++p) L[(size_t)m * nvel + p] += a[(size_t)c * nvel + p];
+  }
+}
+
+/* Runs nsteps from the inflow Maxwellian, J = objective (0 drag, 1 torque)
+   of the final state, and its gradient: out = J, dJ/dT_w, dJ/dKn, dJ/du_x,
+   dJ/du_y (u = farfield velocity). Fixed bodies only. */
+int orc2d_adjoint(orc2d *o, int nsteps, int objective, double *out) {
+  if (o->cfg.motion != 0 && o->cfg.body_kind != 0) return -1;
+  int nvel = o->nvel, N = o->N;
+  size_t tot = (size_t)o->ncell * nvel;
+  const geo2d *G = &o->g[o->cur];
+  double **F = malloc((nsteps + 1) * sizeof(double *)), **Gs = malloc((nsteps + 1) * sizeof(double *));
+  for (int n = 0; n <= nsteps; ++n) { F[n] = malloc(tot * 8); Gs[n] = malloc(tot * 8); }
+  orc2d_init(o, F[0], Gs[0]);
+  for (int n = 0; n < nsteps; ++n) orc2d_step(o, F[n], Gs[n], F[n + 1], Gs[n + 1], NULL);
+  /* merged states x^n */
+  for (int n = 0; n <= nsteps; ++n) merge_with(o, G, F[n], Gs[n]);
+  double diag[4];
+  force_with(o, G, F[nsteps], Gs[nsteps], diag);
+  double J = objective == 0 ? diag[0] : diag[2];
+  double *af = calloc(tot, 8), *ag = calloc(tot, 8), *Lf = calloc(tot, 8), *Lg = calloc(tot, 8);
+  double gp[4] = {0, 0, 0, 0};
+  objective_adjoint(o, G, F[nsteps], objective, af, &gp[0]);
+  for (int n = nsteps - 1; n >= 0; --n) {
+    cv_sum(o, G, af, Lf);
+    cv_sum(o, G, ag, Lg);
+    memset(af, 0, tot * 8); memset(ag, 0, tot * 8);
+    adjoint_step(o, G, F[n], Gs[n], Lf, Lg, af, ag, gp);
+  }
+  /* initial state: every non-solid cell holds M[rho, u, T] (and T/2 of it) */
+  cv_sum(o, G, af, Lf);
+  cv_sum(o, G, ag, Lg);
+  const double *in = o->cfg.inflow;
+  for (int m = 0; m < o->ncell; ++m) {
+    if (G->master[m] != m) continue;
+    for (int p = 0; p < nvel; ++p) {
+      double vx = o->v[p % N], vy = o->v[p / N];
+      double M = maxw2(in[0], in[1], in[2], in[4], vx, vy);
+      double t = Lf[(size_t)m * nvel + p] + 0.5 * in[4] * Lg[(size_t)m * nvel + p];
+      gp[2] += t * M * (vx - in[1]) / in[4];
+      gp[3] += t * M * (vy - in[2]) / in[4];
+    }
+  }
+  out[0] = J; out[1] = gp[0]; out[2] = gp[1]; out[3] = gp[2]; out[4] = gp[3];
+  for (int n = 0; n <= nsteps; ++n) { free(F[n]); free(Gs[n]); }
+  free(F); free(Gs); free(af); free(ag); free(Lf); free(Lg);
+  return 0;
+}
