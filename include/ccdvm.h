@@ -187,6 +187,22 @@ cc_status cc_profile_enable(cc_ctx* ctx, int on);
 cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launches);
 
 /* ------------------------------------------------------------------ */
+/* Adjoint (2D fixed bodies).  Starting from the inflow Maxwellian, runs
+ * nsteps and returns out = {J, dJ/dT_w, dJ/dKn, dJ/dMa}, J = drag
+ * (objective 0) or torque (objective 1) of the final state, by a
+ * hand-written adjoint of every step (transposed upwind fluxes, wall density,
+ * BGK Jacobian) with checkpointed recomputation: the state is saved every
+ * ckpt_every steps and each segment is recomputed once during the backward
+ * sweep.  Mach derivative: u_inflow = Ma sqrt(gamma T_inflow) along the
+ * inflow direction, gamma = 5/3.  pool: caller-owned 256-byte aligned device
+ * buffer of cc_adjoint_workspace_bytes bytes (checkpoints, one segment of
+ * states and moments, two sensitivity buffers, partial sums).  Leaves the
+ * context at the final state.  Synchronous. */
+cc_status cc_adjoint_workspace_bytes(const cc_ctx* ctx, int nsteps, int ckpt_every, size_t* bytes);
+cc_status cc_adjoint(cc_ctx* ctx, int nsteps, int ckpt_every, int objective, void* pool,
+                     double out[4]);
+
+/* ------------------------------------------------------------------ */
 /* Batched instances.  Many independent 2D fixed-body problems (each its own
  * context: grid, velocity grid, Kn, T_w, inflow), all bound to the same
  * stream, advanced together: per step one kernel walks the cut/merged

@@ -55,6 +55,8 @@ SYMBOLS = {
     "cc_set_tile_rows": (C.c_int, [C.c_void_p, C.c_int]),
     "cc_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "cc_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "cc_adjoint_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
+    "cc_adjoint": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
     "cc_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p)]),
     "cc_batch_workspace_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "cc_batch_bind": (C.c_int, [C.c_void_p, C.c_void_p]),

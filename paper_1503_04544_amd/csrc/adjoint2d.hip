@@ -1,0 +1,561 @@
+// Hand-written adjoint of the fixed-geometry 2D step (not in the paper: the
+// transpose of the scheme of Section 3.3 written out term by term), and the
+// checkpointed driver that returns the gradient of the drag or the torque of
+// the final state with respect to the wall temperature, the Knudsen number
+// and the inflow Mach number.
+//
+// Notation.  x^n is the merged state entering step n; Lambda^{n+1}_m is the
+// sensitivity of the objective to the value that control volume m writes to
+// its members at step n.  The kernels store mu_k = Lambda_{master(k)} / S_m
+// at every member cell k (zero in solid cells), so that an upwind cell
+// gathers its downwind neighbours' sensitivities as a plain stencil:
+//   Lambda^n_m = (1 - beta) Lambda + (BGK Jacobian)^T Lambda
+//              - dt/S_m sum_edges L c+ Lambda          (own outflow)
+//              + dt sum_edges L c+ mu_downwind          (inflow into the neighbour)
+//              + wall terms (own outflow, rank one through phi_w).
+// beta = dt rho / kappa; the Maxwellian's Jacobian goes through (rho, rho u,
+// E) with four reductions per cell of Lambda against dE/d(rho, u, T).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "ccdvm_impl.h"
+
+namespace ccdvm {
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// sum over the 4 waves of a 256-thread block, in wave order
+__device__ inline double bsum(double v, double* lds) {
+  v = wsum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return ((lds[0] + lds[1]) + lds[2]) + lds[3];
+}
+
+__device__ inline double vnd(double vmin, double dv, int idx) { return vmin + (idx + 0.5) * dv; }
+
+struct AdjParams {
+  double vmin, dv, w, dt;
+  double kappa;      // tau = kappa / rho; 0: no collisions
+  double kn;
+  double t_wall;
+  double rho_in, ux_in, uy_in, t_in;   // farfield Maxwellian
+  int objective;     // 0 drag, 1 torque
+};
+
+struct AdjBufs {
+  const double2* x;      // x^n (merged state entering the step)
+  const double* mom;     // rho, ux, uy, T of x^n per cell
+  const double2* mu_in;  // mu^{n+1}
+  double2* mu_out;       // mu^n
+  double* part;          // per-block partials (accumulated across steps): T_w, Kn, ux, uy
+  const double* body;    // body state (centre for the torque arm)
+};
+
+__device__ inline double maxw(double rho, double ux, double uy, double T, double vx, double vy) {
+  const double cx = vx - ux, cy = vy - uy;
+  return rho / (2.0 * M_PI * T) * exp(-(cx * cx + cy * cy) / (2.0 * T));
+}
+
+// reductions of Lambda against the derivatives of the relaxation term:
+// A = (A_rho, A_px, A_py, A_E) in (rho, rho u, E) and C = sum Lambda.(Q - x)
+struct BgkSums { double Ar, Apx, Apy, Ae, C; };
+
+__device__ inline void bgk_terms(double rho, double ux, double uy, double T, double vx, double vy,
+                                 double lf, double lg, double f, double g, double* s) {
+  const double cx = vx - ux, cy = vy - uy, c2 = cx * cx + cy * cy;
+  const double E = maxw(rho, ux, uy, T, vx, vy);
+  const double dEr = E / rho, dEux = E * cx / T, dEuy = E * cy / T;
+  const double dET = E * (c2 / (2.0 * T * T) - 1.0 / T);
+  s[0] += lf * dEr + lg * 0.5 * T * dEr;
+  s[1] += lf * dEux + lg * 0.5 * T * dEux;
+  s[2] += lf * dEuy + lg * 0.5 * T * dEuy;
+  s[3] += lf * dET + lg * (0.5 * E + 0.5 * T * dET);
+  s[4] += lf * (E - f) + lg * (0.5 * T * E - g);
+}
+
+__device__ inline BgkSums chain(double rho, double ux, double uy, double T, const double* s) {
+  const double u2 = ux * ux + uy * uy;
+  BgkSums b;
+  b.Ar = s[0] + s[1] * (-ux / rho) + s[2] * (-uy / rho) + s[3] * (u2 - 3.0 * T) / (3.0 * rho);
+  b.Apx = s[1] / rho + s[3] * (-2.0 * ux / (3.0 * rho));
+  b.Apy = s[2] / rho + s[3] * (-2.0 * uy / (3.0 * rho));
+  b.Ae = s[3] * 2.0 / (3.0 * rho);
+  b.C = s[4];
+  return b;
+}
+
+// ---------------------------------------------------------------------
+// regular gas cells: one wave per cell
+// ---------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_adj_regular2d(Geo2D G, AdjBufs B, AdjParams P) {
+  __shared__ double lds[4][4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + wave;
+  double pk = 0.0, pux = 0.0, puy = 0.0;
+  if (c < G.ncell && G.kind[c] == KIND_REGULAR) {
+    const int nx = G.nx, ny = G.ny, N = G.N, nvel = G.nvel;
+    const int i = c % nx, j = c / nx;
+    const double S = G.dx * G.dy;
+    const double rho = B.mom[4 * c], ux = B.mom[4 * c + 1], uy = B.mom[4 * c + 2], T = B.mom[4 * c + 3];
+    const bool collide = P.kappa > 0.0;
+    const double beta = collide ? P.dt * rho / P.kappa : 0.0;
+    const double2* mu = B.mu_in + (size_t)c * nvel;
+    const double2* xc = B.x + (size_t)c * nvel;
+    BgkSums A{0, 0, 0, 0, 0};
+    if (collide) {
+      double s[5] = {0, 0, 0, 0, 0};
+      for (int p = lane; p < nvel; p += kWave) {
+        const double2 m = mu[p], x = xc[p];
+        bgk_terms(rho, ux, uy, T, vnd(P.vmin, P.dv, p % N), vnd(P.vmin, P.dv, p / N), S * m.x, S * m.y,
+                  x.x, x.y, s);
+      }
+      for (int k = 0; k < 5; ++k) s[k] = wsum(s[k]);
+      A = chain(rho, ux, uy, T, s);
+      pk = A.C * (-beta / P.kn);
+    }
+    const double ca = P.dt / G.dx, cb = P.dt / G.dy;
+    const double2* xr = i + 1 < nx ? mu + nvel : nullptr;
+    const double2* xl = i > 0 ? mu - nvel : nullptr;
+    const double2* yu = j + 1 < ny ? mu + (size_t)nx * nvel : nullptr;
+    const double2* yd = j > 0 ? mu - (size_t)nx * nvel : nullptr;
+    double2* out = B.mu_out + (size_t)c * nvel;
+    for (int p = lane; p < nvel; p += kWave) {
+      const double vx = vnd(P.vmin, P.dv, p % N), vy = vnd(P.vmin, P.dv, p / N);
+      const double a = ca * fabs(vx), b = cb * fabs(vy);
+      const double2 m = mu[p];
+      // downwind neighbours (none past an outer face: the farfield is fixed)
+      const double2* dx_ = vx > 0.0 ? xr : xl;
+      const double2* dy_ = vy > 0.0 ? yu : yd;
+      const double2 mdx = dx_ ? dx_[p] : make_double2(0.0, 0.0);
+      const double2 mdy = dy_ ? dy_[p] : make_double2(0.0, 0.0);
+      double of = (1.0 - beta - a - b) * m.x + a * mdx.x + b * mdy.x;
+      double og = (1.0 - beta - a - b) * m.y + a * mdx.y + b * mdy.y;
+      if (collide) {
+        of += (beta * P.w * (A.Ar + A.Apx * vx + A.Apy * vy + A.Ae * 0.5 * (vx * vx + vy * vy)) +
+               P.dt * P.w / P.kappa * A.C) / S;
+        og += beta * P.w * A.Ae / S;
+      }
+      out[p] = make_double2(of, og);
+      // farfield faces upwind of the cell: d ghost / d u
+      const bool ghost_x = (vx > 0.0 && i == 0) || (vx < 0.0 && i == nx - 1);
+      const bool ghost_y = (vy > 0.0 && j == 0) || (vy < 0.0 && j == ny - 1);
+      if (ghost_x || ghost_y) {
+        const double M = maxw(P.rho_in, P.ux_in, P.uy_in, P.t_in, vx, vy);
+        const double coef = (ghost_x ? P.dt * G.dy * fabs(vx) : 0.0) + (ghost_y ? P.dt * G.dx * fabs(vy) : 0.0);
+        const double t = coef * (m.x + 0.5 * P.t_in * m.y) * M / P.t_in;
+        pux += t * (vx - P.ux_in);
+        puy += t * (vy - P.uy_in);
+      }
+    }
+  }
+  // pk is one value per cell, identical on every lane; the farfield terms are per lane
+  pux = wsum(pux);
+  puy = wsum(puy);
+  if (lane == 0) { lds[wave][0] = pk; lds[wave][1] = pux; lds[wave][2] = puy; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* pt = B.part + 4 * (size_t)blockIdx.x;
+    pt[1] += ((lds[0][0] + lds[1][0]) + lds[2][0]) + lds[3][0];
+    pt[2] += ((lds[0][1] + lds[1][1]) + lds[2][1]) + lds[3][1];
+    pt[3] += ((lds[0][2] + lds[1][2]) + lds[2][2]) + lds[3][2];
+  }
+}
+
+// ---------------------------------------------------------------------
+// cut / merged control volumes: one 256-thread block each
+// ---------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_adj_cut2d(Geo2D G, AdjBufs B, AdjParams P, int part_base) {
+  __shared__ double lds[8];
+  const int q = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
+  const int m = G.irr[q];
+  const int b0 = G.mptr[q];
+  const int nm = min(G.mptr[q + 1] - b0, kMaxMembers);
+  const int nx = G.nx, ny = G.ny, N = G.N, nvel = G.nvel;
+  const double S = G.scv[m];
+  const double rho = B.mom[4 * m], ux = B.mom[4 * m + 1], uy = B.mom[4 * m + 2], T = B.mom[4 * m + 3];
+  const bool collide = P.kappa > 0.0;
+  const double beta = collide ? P.dt * rho / P.kappa : 0.0;
+  const double2* mu = B.mu_in + (size_t)m * nvel;
+  const double2* xc = B.x + (size_t)m * nvel;
+  const double Tw = P.t_wall;
+  // reductions: relaxation, and per wall edge phi_w, d phi_w/dT_w, Lambda_k
+  BgkSums A{0, 0, 0, 0, 0};
+  double s[5] = {0, 0, 0, 0, 0};
+  if (collide) {
+    for (int p = tid; p < nvel; p += nth) {
+      const double2 mm = mu[p], x = xc[p];
+      bgk_terms(rho, ux, uy, T, vnd(P.vmin, P.dv, p % N), vnd(P.vmin, P.dv, p / N), S * mm.x, S * mm.y,
+                x.x, x.y, s);
+    }
+    for (int k = 0; k < 5; ++k) s[k] = bsum(s[k], lds);
+    A = chain(rho, ux, uy, T, s);
+  }
+  double den[kMaxMembers], lam[kMaxMembers];
+  double pTw = 0.0;
+  for (int t = 0; t < nm; ++t) {
+    const int k = G.mem[b0 + t];
+    den[t] = 0.0; lam[t] = 0.0;
+    if (!(G.lw[k] > 0.0)) continue;
+    double num = 0.0, dn = 0.0, dd = 0.0;
+    for (int p = tid; p < nvel; p += nth) {
+      const double vx = vnd(P.vmin, P.dv, p % N), vy = vnd(P.vmin, P.dv, p / N);
+      const double cn = vx * G.nwx[k] + vy * G.nwy[k];
+      if (cn > 0.0) num += cn * xc[p].x * P.w;
+      else if (cn < 0.0) {
+        const double Mw = maxw(1.0, 0.0, 0.0, Tw, vx, vy);
+        dn += cn * Mw * P.w;
+        dd += cn * Mw * ((vx * vx + vy * vy) / (2.0 * Tw * Tw) - 1.0 / Tw) * P.w;
+      }
+    }
+    num = bsum(num, lds); dn = bsum(dn, lds); dd = bsum(dd, lds);
+    const double phi = dn != 0.0 ? -num / dn : 0.0;
+    const double dphi = dn != 0.0 ? num / (dn * dn) * dd : 0.0;
+    double L = 0.0, dT = 0.0;
+    for (int p = tid; p < nvel; p += nth) {
+      const double vx = vnd(P.vmin, P.dv, p % N), vy = vnd(P.vmin, P.dv, p / N);
+      const double cn = vx * G.nwx[k] + vy * G.nwy[k];
+      if (cn >= 0.0) continue;
+      const double Mw = maxw(1.0, 0.0, 0.0, Tw, vx, vy);
+      const double dMw = Mw * ((vx * vx + vy * vy) / (2.0 * Tw * Tw) - 1.0 / Tw);
+      const double2 mm = mu[p];
+      const double lf = S * mm.x, lg = S * mm.y;
+      L += cn * Mw * (lf + 0.5 * Tw * lg);
+      const double dfw = dphi * Mw + phi * dMw;
+      const double dgw = dphi * 0.5 * Tw * Mw + phi * (0.5 * Mw + 0.5 * Tw * dMw);
+      dT += cn * (lf * dfw + lg * dgw);
+    }
+    L = bsum(L, lds);
+    dT = bsum(dT, lds);
+    den[t] = dn;
+    lam[t] = L;
+    pTw += -P.dt / S * G.lw[k] * dT;
+  }
+  double pux = 0.0, puy = 0.0;
+  for (int p = tid; p < nvel; p += nth) {
+    const double vx = vnd(P.vmin, P.dv, p % N), vy = vnd(P.vmin, P.dv, p / N);
+    const double2 mm = mu[p];
+    const double lf = S * mm.x, lg = S * mm.y;
+    double of = (1.0 - beta) * lf, og = (1.0 - beta) * lg;
+    if (collide) {
+      of += beta * P.w * (A.Ar + A.Apx * vx + A.Apy * vy + A.Ae * 0.5 * (vx * vx + vy * vy)) +
+            P.dt * P.w / P.kappa * A.C;
+      og += beta * P.w * A.Ae;
+    }
+    for (int t = 0; t < nm; ++t) {
+      const int k = G.mem[b0 + t];
+      const int i = k % nx, j = k / nx;
+      const double Le[4] = {G.lxp[k], G.lxm[k], G.lyp[k], G.lym[k]};
+      const int nb[4] = {i + 1 < nx ? k + 1 : -1, i > 0 ? k - 1 : -1, j + 1 < ny ? k + nx : -1,
+                         j > 0 ? k - nx : -1};
+      const double cf[4] = {vx, -vx, vy, -vy};   // outward normal velocity of each edge
+      for (int e = 0; e < 4; ++e) {
+        if (Le[e] == 0.0) continue;
+        if (nb[e] >= 0 && G.master[nb[e]] == m) continue;   // inside the control volume
+        const double c = cf[e], cp = fmax(c, 0.0), cm = fmin(c, 0.0);
+        of -= P.dt / S * Le[e] * cp * lf;
+        og -= P.dt / S * Le[e] * cp * lg;
+        if (nb[e] >= 0) {
+          const double2 mn = B.mu_in[(size_t)nb[e] * nvel + p];
+          of += P.dt * Le[e] * cp * mn.x;
+          og += P.dt * Le[e] * cp * mn.y;
+        } else if (cm != 0.0) {
+          const double M = maxw(P.rho_in, P.ux_in, P.uy_in, P.t_in, vx, vy);
+          const double tt = -P.dt / S * Le[e] * cm * (lf + 0.5 * P.t_in * lg) * M / P.t_in;
+          pux += tt * (vx - P.ux_in);
+          puy += tt * (vy - P.uy_in);
+        }
+      }
+      const double Lw = G.lw[k];
+      if (Lw > 0.0) {
+        const double cn = vx * G.nwx[k] + vy * G.nwy[k];
+        if (cn > 0.0) {
+          of += -P.dt / S * Lw * cn * lf + P.dt / S * Lw * lam[t] * cn * P.w / den[t];
+          og += -P.dt / S * Lw * cn * lg;
+        }
+      }
+    }
+    for (int t = 0; t < nm; ++t)
+      B.mu_out[(size_t)G.mem[b0 + t] * nvel + p] = make_double2(of / S, og / S);
+  }
+  pux = bsum(pux, lds);
+  puy = bsum(puy, lds);
+  if (tid == 0) {
+    double* pt = B.part + 4 * (size_t)(part_base + q);
+    pt[0] += pTw;
+    pt[1] += collide ? A.C * (-beta / P.kn) : 0.0;
+    pt[2] += pux;
+    pt[3] += puy;
+  }
+}
+
+// objective (drag or torque of the final state): mu^N at the members of every
+// control volume with wall edges, and dJ/dT_w
+__global__ void __launch_bounds__(256) k_adj_objective2d(Geo2D G, AdjBufs B, AdjParams P,
+                                                         int part_base) {
+  __shared__ double lds[8];
+  const int q = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
+  const int m = G.irr[q];
+  const int b0 = G.mptr[q];
+  const int nm = min(G.mptr[q + 1] - b0, kMaxMembers);
+  const int N = G.N, nvel = G.nvel;
+  const double S = G.scv[m];
+  const double Tw = P.t_wall;
+  const double2* xc = B.x + (size_t)m * nvel;
+  double den[kMaxMembers], sin_[kMaxMembers], al[kMaxMembers], ga[kMaxMembers];
+  double pTw = 0.0;
+  for (int t = 0; t < nm; ++t) {
+    const int k = G.mem[b0 + t];
+    den[t] = 0.0; sin_[t] = 0.0; al[t] = 1.0; ga[t] = 0.0;
+    if (!(G.lw[k] > 0.0)) continue;
+    if (P.objective == 1) { al[t] = -(G.rwy[k] - B.body[1]); ga[t] = G.rwx[k] - B.body[0]; }
+    double num = 0.0, dn = 0.0, dd = 0.0;
+    for (int p = tid; p < nvel; p += nth) {
+      const double vx = vnd(P.vmin, P.dv, p % N), vy = vnd(P.vmin, P.dv, p / N);
+      const double cn = vx * G.nwx[k] + vy * G.nwy[k];
+      if (cn > 0.0) num += cn * xc[p].x * P.w;
+      else if (cn < 0.0) {
+        const double Mw = maxw(1.0, 0.0, 0.0, Tw, vx, vy);
+        dn += cn * Mw * P.w;
+        dd += cn * Mw * ((vx * vx + vy * vy) / (2.0 * Tw * Tw) - 1.0 / Tw) * P.w;
+      }
+    }
+    num = bsum(num, lds); dn = bsum(dn, lds); dd = bsum(dd, lds);
+    const double phi = dn != 0.0 ? -num / dn : 0.0;
+    const double dphi = dn != 0.0 ? num / (dn * dn) * dd : 0.0;
+    double si = 0.0, sdT = 0.0;
+    for (int p = tid; p < nvel; p += nth) {
+      const double vx = vnd(P.vmin, P.dv, p % N), vy = vnd(P.vmin, P.dv, p / N);
+      const double cn = vx * G.nwx[k] + vy * G.nwy[k];
+      if (cn >= 0.0) continue;
+      const double psi = al[t] * vx + ga[t] * vy;
+      const double Mw = maxw(1.0, 0.0, 0.0, Tw, vx, vy);
+      const double dMw = Mw * ((vx * vx + vy * vy) / (2.0 * Tw * Tw) - 1.0 / Tw);
+      si += psi * cn * Mw * P.w;
+      sdT += psi * cn * (dphi * Mw + phi * dMw) * P.w;
+    }
+    si = bsum(si, lds);
+    sdT = bsum(sdT, lds);
+    den[t] = dn;
+    sin_[t] = si;
+    pTw += G.lw[k] * sdT;
+  }
+  for (int p = tid; p < nvel; p += nth) {
+    const double vx = vnd(P.vmin, P.dv, p % N), vy = vnd(P.vmin, P.dv, p / N);
+    double of = 0.0;
+    for (int t = 0; t < nm; ++t) {
+      const int k = G.mem[b0 + t];
+      if (!(G.lw[k] > 0.0)) continue;
+      const double cn = vx * G.nwx[k] + vy * G.nwy[k];
+      if (cn <= 0.0) continue;
+      const double psi = al[t] * vx + ga[t] * vy;
+      of += G.lw[k] * (psi * cn * P.w + sin_[t] * (-cn * P.w / den[t]));
+    }
+    for (int t = 0; t < nm; ++t)
+      B.mu_out[(size_t)G.mem[b0 + t] * nvel + p] = make_double2(of / S, 0.0);
+  }
+  if (tid == 0) B.part[4 * (size_t)(part_base + q)] += pTw;
+}
+
+// initial state (inflow Maxwellian in every cell): sum_m S_m mu^0_m . dM/du
+__global__ void __launch_bounds__(256) k_adj_initial2d(Geo2D G, AdjBufs B, AdjParams P, int part_base) {
+  __shared__ double lds[8];
+  const int c = blockIdx.x;
+  const int m = G.master[c];
+  if (m != c) return;                      // uniform over the block
+  const int N = G.N, nvel = G.nvel;
+  const double S = G.scv[m];
+  const double2* mu = B.mu_in + (size_t)m * nvel;
+  double pux = 0.0, puy = 0.0;
+  for (int p = threadIdx.x; p < nvel; p += blockDim.x) {
+    const double vx = vnd(P.vmin, P.dv, p % N), vy = vnd(P.vmin, P.dv, p / N);
+    const double M = maxw(P.rho_in, P.ux_in, P.uy_in, P.t_in, vx, vy);
+    const double t = S * (mu[p].x + 0.5 * P.t_in * mu[p].y) * M / P.t_in;
+    pux += t * (vx - P.ux_in);
+    puy += t * (vy - P.uy_in);
+  }
+  pux = bsum(pux, lds);
+  puy = bsum(puy, lds);
+  if (threadIdx.x == 0) {
+    B.part[4 * (size_t)(part_base + c) + 2] += pux;
+    B.part[4 * (size_t)(part_base + c) + 3] += puy;
+  }
+}
+
+__global__ void k_fill0(double* __restrict__ p, size_t n) {
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+    p[t] = 0.0;
+}
+
+// fixed-order sum of the partial arrays into out[4]
+__global__ void __launch_bounds__(256) k_adj_sum(const double* __restrict__ part, int nparts,
+                                                 double* __restrict__ out) {
+  __shared__ double lds[8];
+  for (int r = 0; r < 4; ++r) {
+    double s = 0.0;
+    for (int t = threadIdx.x; t < nparts; t += blockDim.x) s += part[4 * (size_t)t + r];
+    s = bsum(s, lds);
+    if (threadIdx.x == 0) out[r] = s;
+  }
+}
+
+AdjParams adj_params(const cc_ctx* ctx, int objective) {
+  AdjParams P;
+  P.vmin = ctx->cfg.vmin;
+  P.dv = ctx->dv;
+  P.w = ctx->dv * ctx->dv;
+  P.dt = ctx->dt;
+  P.kappa = ctx->cfg.kn > 0.0 ? sqrt(M_PI) / 2.0 * ctx->cfg.kn * ctx->cfg.lref / sqrt(2.0) : 0.0;
+  P.kn = ctx->cfg.kn;
+  P.t_wall = ctx->body.t_wall;
+  P.rho_in = ctx->cfg.inflow[0];
+  P.ux_in = ctx->cfg.inflow[1];
+  P.uy_in = ctx->cfg.inflow[2];
+  P.t_in = ctx->cfg.inflow[4];
+  P.objective = objective;
+  return P;
+}
+
+}  // namespace
+
+// Pool layout for the adjoint of nsteps steps with a checkpoint every K.
+struct AdjLayout {
+  size_t ckpt, ckmom, seg, segmom, mu0, mu1, part, out, total;
+  int nckpt, K, nparts, nreg_blocks;
+};
+
+static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+static AdjLayout adj_layout(const cc_ctx* ctx, int nsteps, int K) {
+  AdjLayout L;
+  L.K = K;
+  L.nckpt = (nsteps + K - 1) / K;
+  const size_t st = ctx->state_bytes, mb = al256((size_t)ctx->ncell * 4 * sizeof(double));
+  L.nreg_blocks = (ctx->ncell + 3) / 4;
+  L.nparts = L.nreg_blocks + 2 * ctx->ncell + ctx->ncell;   // regular blocks, cut CVs, objective, initial
+  size_t off = 0;
+  L.ckpt = off; off += st * (size_t)L.nckpt;
+  L.ckmom = off; off += mb * (size_t)L.nckpt;
+  L.seg = off; off += st * (size_t)K;
+  L.segmom = off; off += mb * (size_t)K;
+  L.mu0 = off; off += st;
+  L.mu1 = off; off += st;
+  L.part = off; off += al256((size_t)L.nparts * 4 * sizeof(double));
+  L.out = off; off += 256;
+  L.total = off;
+  return L;
+}
+
+size_t adjoint_workspace_bytes(const cc_ctx* ctx, int nsteps, int K) {
+  return adj_layout(ctx, nsteps, K).total;
+}
+
+hipError_t launch_step_2d_ptrs(cc_ctx* ctx, const double2* in, double2* out, double* mom);
+hipError_t launch_force_only_2d(cc_ctx* ctx, double* out4);
+
+// Forward nsteps from the current state with checkpoints, objective of the
+// final state, then the adjoint sweep segment by segment (restore, recompute
+// the segment keeping every state and its moments, adjoint steps backwards).
+// out (host) = J, dJ/dT_w, dJ/dKn, dJ/du_x, dJ/du_y.
+hipError_t adjoint_run_2d(cc_ctx* ctx, int nsteps, int K, int objective, char* pool, double* out) {
+  AdjLayout L = adj_layout(ctx, nsteps, K);
+  hipStream_t s = ctx->stream;
+  const size_t st = ctx->state_bytes;
+  const size_t mb = al256((size_t)ctx->ncell * 4 * sizeof(double));
+  AdjParams P = adj_params(ctx, objective);
+  hipError_t e;
+  double* part = (double*)(pool + L.part);
+  k_fill0<<<512, 256, 0, s>>>(part, (size_t)L.nparts * 4);
+  k_fill0<<<1024, 256, 0, s>>>((double*)(pool + L.mu0), st / 8);
+  k_fill0<<<1024, 256, 0, s>>>((double*)(pool + L.mu1), st / 8);
+  // forward with checkpoints
+  for (int n = 0; n < nsteps; ++n) {
+    if (n % K == 0) {
+      // the state and the moments the next step will use, so that the
+      // recomputation replays the forward bit for bit
+      e = hipMemcpyAsync(pool + L.ckpt + st * (size_t)(n / K), ctx->state[ctx->cur], st,
+                         hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return e;
+      e = hipMemcpyAsync(pool + L.ckmom + mb * (size_t)(n / K), ctx->s.mom,
+                         (size_t)ctx->ncell * 4 * sizeof(double), hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return e;
+    }
+    e = launch_step_2d_fused(ctx, false, nullptr, nullptr, false);
+    if (e != hipSuccess) return e;
+  }
+  // objective value and its sensitivity mu^N
+  double* dev_out = (double*)(pool + L.out);
+  e = launch_force_only_2d(ctx, dev_out);
+  if (e != hipSuccess) return e;
+  AdjBufs B;
+  B.body = ctx->s.body;
+  B.part = part;
+  B.x = (const double2*)ctx->state[ctx->cur];
+  B.mom = ctx->s.mom;
+  B.mu_in = nullptr;
+  B.mu_out = (double2*)(pool + L.mu0);
+  const int cut_base = L.nreg_blocks, obj_base = L.nreg_blocks + ctx->ncell;
+  if (ctx->n_irr > 0) k_adj_objective2d<<<ctx->n_irr, 256, 0, s>>>(ctx->g2, B, P, obj_base);
+  int cur_mu = 0;   // mu^{n+1} lives in mu[cur_mu]
+  char* mu[2] = {pool + L.mu0, pool + L.mu1};
+  double* host_j = out;
+  // backward over the segments
+  for (int sg = L.nckpt - 1; sg >= 0; --sg) {
+    const int n0 = sg * K, n1 = nsteps < n0 + K ? nsteps : n0 + K, len = n1 - n0;
+    char* seg = pool + L.seg;
+    char* segmom = pool + L.segmom;
+    e = hipMemcpyAsync(seg, pool + L.ckpt + st * (size_t)sg, st, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(segmom, pool + L.ckmom + mb * (size_t)sg, (size_t)ctx->ncell * 4 * sizeof(double),
+                       hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i + 1 < len; ++i) {
+      e = hipMemcpyAsync(segmom + mb * (i + 1), segmom + mb * i, (size_t)ctx->ncell * 4 * sizeof(double),
+                         hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return e;
+      e = launch_step_2d_ptrs(ctx, (const double2*)(seg + st * i), (double2*)(seg + st * (i + 1)),
+                              (double*)(segmom + mb * (i + 1)));
+      if (e != hipSuccess) return e;
+    }
+    for (int i = len - 1; i >= 0; --i) {
+      B.x = (const double2*)(seg + st * i);
+      B.mom = (const double*)(segmom + mb * i);
+      B.mu_in = (const double2*)mu[cur_mu];
+      B.mu_out = (double2*)mu[1 - cur_mu];
+      prof_begin(ctx, 1);
+      if (ctx->n_irr > 0) k_adj_cut2d<<<ctx->n_irr, 256, 0, s>>>(ctx->g2, B, P, cut_base);
+      prof_end(ctx, 1);
+      prof_begin(ctx, 0);
+      k_adj_regular2d<<<L.nreg_blocks, 256, 0, s>>>(ctx->g2, B, P);
+      prof_end(ctx, 0);
+      cur_mu = 1 - cur_mu;
+    }
+  }
+  B.mu_in = (const double2*)mu[cur_mu];
+  k_adj_initial2d<<<ctx->ncell, 256, 0, s>>>(ctx->g2, B, P, L.nreg_blocks + 2 * ctx->ncell);
+  k_adj_sum<<<1, 256, 0, s>>>(part, L.nparts, dev_out + 4);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  double h[8];
+  e = hipMemcpyAsync(h, dev_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  host_j[0] = objective == 0 ? h[0] : h[2];
+  host_j[1] = h[4];
+  host_j[2] = h[5];
+  host_j[3] = h[6];
+  host_j[4] = h[7];
+  return hipSuccess;
+}
+
+}  // namespace ccdvm

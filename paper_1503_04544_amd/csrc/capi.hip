@@ -23,6 +23,8 @@ hipError_t launch_force_only_2d(cc_ctx* ctx, double* out4);
 hipError_t launch_force_only_3d(cc_ctx* ctx, double* out4);
 hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_row);
 hipError_t launch_moving_init_2d(cc_ctx* ctx);
+size_t adjoint_workspace_bytes(const cc_ctx* ctx, int nsteps, int K);
+hipError_t adjoint_run_2d(cc_ctx* ctx, int nsteps, int K, int objective, char* pool, double* out);
 }  // namespace ccdvm
 
 static bool is_moving(const cc_ctx* ctx) {
@@ -516,6 +518,39 @@ cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launch
   }
   if (total_ms) *total_ms = tot;
   if (launches) *launches = P.count[kernel];
+  return CC_OK;
+}
+
+// ---------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------
+static const double kGamma = 5.0 / 3.0;
+
+cc_status cc_adjoint_workspace_bytes(const cc_ctx* ctx, int nsteps, int ckpt_every, size_t* bytes) {
+  if (!ctx || !bytes || nsteps < 1 || ckpt_every < 1) return CC_EINVAL;
+  if (ctx->dim != 2 || is_moving(ctx)) return CC_EINVAL;
+  *bytes = adjoint_workspace_bytes(ctx, nsteps, ckpt_every);
+  return CC_OK;
+}
+
+cc_status cc_adjoint(cc_ctx* ctx, int nsteps, int ckpt_every, int objective, void* pool, double out[4]) {
+  if (!ctx || !out || !pool || nsteps < 1 || ckpt_every < 1 || (objective != 0 && objective != 1))
+    return CC_EINVAL;
+  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (ctx->dim != 2 || is_moving(ctx)) return fail(ctx, CC_EINVAL, "the adjoint covers 2D fixed bodies");
+  if ((uintptr_t)pool % kAlign) return fail(ctx, CC_EINVAL, "pool must be 256-byte aligned");
+  cc_status st = cc_init_maxwellian(ctx);
+  if (st != CC_OK) return st;
+  double r[5];
+  hipError_t e = adjoint_run_2d(ctx, nsteps, ckpt_every, objective, (char*)pool, r);
+  if (e != hipSuccess) return hip_fail(ctx, e, "adjoint");
+  // Mach number along the inflow direction: u = Ma sqrt(gamma T) e
+  const double ux = ctx->cfg.inflow[1], uy = ctx->cfg.inflow[2], un = sqrt(ux * ux + uy * uy);
+  const double ex = un > 0.0 ? ux / un : 1.0, ey = un > 0.0 ? uy / un : 0.0;
+  out[0] = r[0];
+  out[1] = r[1];
+  out[2] = r[2];
+  out[3] = sqrt(kGamma * ctx->cfg.inflow[4]) * (ex * r[3] + ey * r[4]);
   return CC_OK;
 }
 

@@ -1474,6 +1474,44 @@ hipError_t batch_launch_group(cc_batch* B, int g) {
   return hipGetLastError();
 }
 
+// one fixed-geometry step with explicit state and moment buffers (no
+// reductions): recomputation inside the adjoint
+hipError_t launch_step_2d_ptrs(cc_ctx* ctx, const double2* in, double2* out, double* mom) {
+  StepParams P = params2d(ctx);
+  fused_fn fn = pick_fused(chunks_per_half(ctx));
+  if (!fn) return hipErrorInvalidValue;
+  FusedArgs A;
+  A.kind = ctx->g2.kind;
+  A.in = in;
+  A.out = out;
+  A.mom = mom;
+  A.body = ctx->s.body;
+  A.ngroups = (ctx->nx + kTileW - 1) / kTileW;
+  A.seglen = tile_rows(ctx);
+  const int nseg = (ctx->ny + A.seglen - 1) / A.seglen;
+  A.ntiles = A.ngroups * nseg;
+  A.ntiles_pad = (A.ntiles + 7) / 8 * 8;
+  A.n_cut = ctx->n_irr;
+  A.cut_base = 0;
+  A.tile_base = 8;
+  A.split = split_rows(ctx);
+  A.fslot = ctx->s.fslot;
+  A.mpart = ctx->s.mpart;
+  A.prev_fslot = nullptr;
+  A.prev_mpart = nullptr;
+  A.red_force = nullptr;
+  A.red_mass = nullptr;
+  if (A.n_cut > 0) k_cutstep2d<<<A.n_cut, 256, 0, ctx->stream>>>(ctx->g2, A, P);
+  fn(ctx, dim3(A.tile_base + A.ntiles_pad), A, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_ptr_2d(cc_ctx* ctx, const double2* st, double* mom) {
+  StepParams P = params2d(ctx);
+  k_mom2d<<<(ctx->ncell + 3) / 4, 256, 0, ctx->stream>>>(ctx->g2, st, mom, P);
+  return hipGetLastError();
+}
+
 // reduce the partials of the step that just ran into its force row and the
 // mass row of the state it produced
 hipError_t launch_step_2d_flush(cc_ctx* ctx, double* force_row, double* mass_row) {

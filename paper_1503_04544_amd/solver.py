@@ -135,6 +135,18 @@ class Solver:
         self._check(lib().cc_geometry_counts(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
 
+    def adjoint(self, nsteps: int, ckpt_every: int = 16, objective: str = "drag"):
+        """J and dJ/d(T_w, Kn, Ma) of the drag or torque after nsteps from the
+        inflow Maxwellian (hand-written adjoint with checkpointing)."""
+        nb = C.c_size_t()
+        self._check(lib().cc_adjoint_workspace_bytes(self._h, int(nsteps), int(ckpt_every), C.byref(nb)))
+        pool = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        out = (C.c_double * 4)()
+        self._check(lib().cc_adjoint(self._h, int(nsteps), int(ckpt_every),
+                                     0 if objective == "drag" else 1, _ptr(pool), out))
+        del pool
+        return out[0], np.array(out[1:])
+
     def set_tile_rows(self, rows: int):
         self._check(lib().cc_set_tile_rows(self._h, int(rows)))
 

@@ -1,0 +1,86 @@
+"""GPU adjoint (hand-written, checkpointed) against the oracle's FP64 adjoint
+and against central finite differences of the GPU forward."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from ccdvm_inputs import Body, mach_to_speed, small_2d, workload
+from oracle import Oracle2D
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def solver(cfg):
+    from paper_1503_04544_amd.solver import Solver
+    return Solver(cfg, device="cuda:0")
+
+
+CASES = {
+    "ellipse_drag": ("drag", small_2d(12, 10, 8, kn=0.1, mach=0.5, body=Body(
+        "ellipse", (0.47, 0.52, 0), (0.22, 0.12, 0), theta=0.4, t_wall=1.3))),
+    "ellipse_torque": ("torque", small_2d(12, 10, 8, kn=0.1, mach=0.5, body=Body(
+        "ellipse", (0.47, 0.52, 0), (0.22, 0.12, 0), theta=0.4, t_wall=1.3))),
+    "merged_ragged": ("drag", small_2d(20, 14, 12, kn=0.3, mach=0.6, body=Body(
+        "circle", (0.45, 0.5, 0), (0.22, 0.22, 0), t_wall=1.4))),
+    "cyl32": ("drag", workload("cyl32")),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_adjoint_matches_oracle_adjoint(name):
+    obj, cfg = CASES[name]
+    nsteps, every = 11, 4          # segments of 4, 4 and 3 steps
+    J, g = solver(cfg).adjoint(nsteps, every, obj)
+    Jo, go = Oracle2D(cfg).adjoint(nsteps, obj)
+    # oracle returns d/du_x, d/du_y; the library returns d/dMa along the inflow
+    dma = math.sqrt(5.0 / 3.0 * cfg.inflow[4]) * go[2]
+    ref = np.array([go[0], go[1], dma])
+    assert J == pytest.approx(Jo, rel=1e-11, abs=1e-15)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(g - ref)) <= 1e-9 * scale, (g, ref)
+
+
+def test_adjoint_checkpoint_interval_does_not_change_result():
+    obj, cfg = CASES["merged_ragged"]
+    a = solver(cfg).adjoint(12, 1, obj)[1]
+    b = solver(cfg).adjoint(12, 5, obj)[1]
+    c = solver(cfg).adjoint(12, 12, obj)[1]
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def _drag(cfg, n):
+    s = solver(cfg)
+    s.init_maxwellian()
+    s.step(n)
+    return s.body_force()[0]
+
+
+def test_cyl512_gradient_against_central_differences():
+    """Full-size workload, 6 steps: adjoint vs central differences (GPU forward)."""
+    cfg = workload("cyl512")
+    n = 6
+    J, g = solver(cfg).adjoint(n, 3, "drag")
+    assert J == pytest.approx(_drag(cfg, n), rel=1e-12)
+    b = cfg.body
+    h = 1e-5
+    fd_tw = (_drag(cfg.with_(body=dataclasses.replace(b, t_wall=b.t_wall + h)), n)
+             - _drag(cfg.with_(body=dataclasses.replace(b, t_wall=b.t_wall - h)), n)) / (2 * h)
+    fd_kn = (_drag(cfg.with_(kn=cfg.kn * (1 + h)), n) - _drag(cfg.with_(kn=cfg.kn * (1 - h)), n)) / (2 * h * cfg.kn)
+    ma = 0.8
+
+    def with_ma(m):
+        inf = list(cfg.inflow)
+        inf[1] = mach_to_speed(m)
+        return cfg.with_(inflow=tuple(inf))
+    fd_ma = (_drag(with_ma(ma + h), n) - _drag(with_ma(ma - h), n)) / (2 * h)
+    fd = np.array([fd_tw, fd_kn, fd_ma])
+    assert np.all(np.abs(g - fd) <= 1e-6 * np.abs(fd)), (g, fd)
