@@ -134,6 +134,9 @@ def main():
                     help="cyl512 (default, the headline line) | ellipse256 (moving body) | cyl32")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=40,
+                    help="steps of the adjoint/forward time ratio measurement (0: skip)")
+    ap.add_argument("--adjoint-ckpt", type=int, default=8)
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -220,6 +223,25 @@ def main():
                      "reduce_kernel_avg_us": round(red_ms / max(red_n, 1) * 1e3, 2),
                      "merge_kernel_avg_us": round(mrg_ms / max(mrg_n, 1) * 1e3, 2)},
     }
+    if args.workload == "cyl512" and args.adjoint_steps > 0:
+        # adjoint over the same workload: forward alone vs forward with
+        # checkpoints + recomputation + adjoint sweep (cc_adjoint)
+        na, ka = args.adjoint_steps, args.adjoint_ckpt
+        log(f"bench: adjoint over {na} steps, checkpoint every {ka}")
+        s.init_maxwellian()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(na)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        J, grad = s.adjoint(na, ka, "drag")
+        t_adj = time.perf_counter() - t0
+        out["adjoint"] = {"steps": na, "ckpt_every": ka, "forward_s": round(t_fwd, 4),
+                          "adjoint_total_s": round(t_adj, 4),
+                          "backward_over_forward": round((t_adj - t_fwd) / t_fwd, 3),
+                          "adjoint_total_over_forward": round(t_adj / t_fwd, 3),
+                          "drag": J, "d_drag_d_Tw_Kn_Ma": [float(x) for x in grad]}
     s.close()
     del s
     torch.cuda.empty_cache()

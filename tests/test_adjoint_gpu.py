@@ -84,3 +84,16 @@ def test_cyl512_gradient_against_central_differences():
     fd_ma = (_drag(with_ma(ma + h), n) - _drag(with_ma(ma - h), n)) / (2 * h)
     fd = np.array([fd_tw, fd_kn, fd_ma])
     assert np.all(np.abs(g - fd) <= 1e-6 * np.abs(fd)), (g, fd)
+
+
+def test_autograd_function_returns_the_adjoint_gradient():
+    from paper_1503_04544_amd.autograd import drag
+    obj, cfg = CASES["ellipse_drag"]
+    ma = cfg.inflow[1] / math.sqrt(5.0 / 3.0)
+    p = torch.tensor([cfg.body.t_wall, cfg.kn, ma], dtype=torch.float64, requires_grad=True)
+    J = drag(p, cfg, 9, 4)
+    (g,) = torch.autograd.grad(3.0 * J, p)
+    Jo, go = Oracle2D(cfg).adjoint(9, "drag")
+    assert float(J) == pytest.approx(Jo, rel=1e-11)
+    ref = 3.0 * np.array([go[0], go[1], math.sqrt(5.0 / 3.0) * go[2]])
+    assert np.max(np.abs(g.numpy() - ref)) <= 1e-9 * np.max(np.abs(ref))
