@@ -72,6 +72,26 @@ void orc2d_body_state(const orc2d *o, double *state);
 int  orc2d_adjoint(orc2d *o, int nsteps, int objective, double *out);
 int  orc_threads(void);
 
+typedef struct orc3d orc3d;
+int  orc3d_create(const orc_cfg *cfg, orc3d **out);
+void orc3d_destroy(orc3d *o);
+double orc3d_dt(const orc3d *o);
+void orc3d_velocity(const orc3d *o, double *v);
+/* geometry export: type, master, S (6 per cell: x-, x+, y-, y+, z-, z+ gas
+   areas), wall area, wall normal (3 per cell, into the solid), wall centre
+   (3 per cell), virtual-cell volume, control-volume volume */
+void orc3d_geometry(const orc3d *o, int *type, int *master, double *S6, double *sw,
+                    double *nw3, double *rw3, double *vbar, double *vcv);
+void orc3d_init(const orc3d *o, double *F);
+void orc3d_merge(const orc3d *o, double *F);
+void orc3d_update_cells(const orc3d *o, const double *Fm, const int *cells, int ncells,
+                        double *out);
+/* one fixed-geometry step; diag (nullable) = Fx, Fy, Fz, mass of F^n */
+int  orc3d_step(orc3d *o, const double *F, double *Fo, double *diag);
+void orc3d_force(const orc3d *o, const double *Fm, double *diag);
+/* 14 moments per cell (see orc3d_moments) */
+void orc3d_moments(const orc3d *o, const double *F, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -190,3 +190,109 @@ class Oracle2D:
         out = np.zeros((self.ncell, 9))
         lib().orc2d_moments(self._h, _p(np.ascontiguousarray(f)), _p(np.ascontiguousarray(g)), _p(out))
         return out
+
+
+def _lib3():
+    L = lib()
+    if not getattr(L, "_has3", False):
+        P = C.c_void_p
+        L.orc3d_create.argtypes = [C.POINTER(_Cfg), C.POINTER(P)]
+        L.orc3d_destroy.argtypes = [P]
+        L.orc3d_dt.argtypes = [P]
+        L.orc3d_dt.restype = C.c_double
+        L.orc3d_velocity.argtypes = [P, P]
+        L.orc3d_geometry.argtypes = [P] + [P] * 8
+        L.orc3d_init.argtypes = [P, P]
+        L.orc3d_merge.argtypes = [P, P]
+        L.orc3d_update_cells.argtypes = [P, P, P, C.c_int, P]
+        L.orc3d_step.argtypes = [P, P, P, P]
+        L.orc3d_force.argtypes = [P, P, P]
+        L.orc3d_moments.argtypes = [P, P, P]
+        L._has3 = True
+    return L
+
+
+class Oracle3D:
+    """Three-dimensional model: state F of shape (ncell, N**3)."""
+
+    def __init__(self, cfg):
+        assert cfg.dim == 3
+        self.cfg = cfg
+        self._s = cfg_struct(cfg)
+        h = C.c_void_p()
+        st = _lib3().orc3d_create(C.byref(self._s), C.byref(h))
+        if st != 0:
+            raise OracleError(f"oracle create failed with status {st}")
+        self._h = h
+        self.nx, self.ny, self.nz = cfg.n
+        self.ncell = self.nx * self.ny * self.nz
+        self.N = cfg.nv
+        self.nvel = cfg.nv ** 3
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib3().orc3d_destroy(h)
+            self._h = None
+
+    @property
+    def dt(self) -> float:
+        return _lib3().orc3d_dt(self._h)
+
+    def velocity(self):
+        v = np.zeros(self.N)
+        _lib3().orc3d_velocity(self._h, _p(v))
+        return v
+
+    def geometry(self):
+        n = self.ncell
+        out = {"type": np.zeros(n, np.int32), "master": np.zeros(n, np.int32),
+               "S": np.zeros((n, 6)), "sw": np.zeros(n), "nw": np.zeros((n, 3)),
+               "rw": np.zeros((n, 3)), "vbar": np.zeros(n), "vcv": np.zeros(n)}
+        _lib3().orc3d_geometry(self._h, *[_p(out[k]) for k in
+                                          ("type", "master", "S", "sw", "nw", "rw", "vbar", "vcv")])
+        return out
+
+    def init(self):
+        F = np.zeros((self.ncell, self.nvel))
+        _lib3().orc3d_init(self._h, _p(F))
+        return F
+
+    def merge(self, F):
+        F = np.ascontiguousarray(F, dtype=np.float64).copy()
+        _lib3().orc3d_merge(self._h, _p(F))
+        return F
+
+    def update_cells(self, Fm, cells):
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        out = np.zeros((cells.size, self.nvel))
+        _lib3().orc3d_update_cells(self._h, _p(np.ascontiguousarray(Fm)), _p(cells),
+                                   int(cells.size), _p(out))
+        return out
+
+    def step(self, F):
+        """One step; returns (F1, diag) with diag = (Fx, Fy, Fz, mass) of F^n."""
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        Fo = np.zeros_like(F)
+        d = np.zeros(4)
+        st = _lib3().orc3d_step(self._h, _p(F), _p(Fo), _p(d))
+        if st != 0:
+            raise OracleError(f"oracle step failed with status {st}")
+        return Fo, d
+
+    def run(self, F, nsteps):
+        diags = []
+        for _ in range(nsteps):
+            F, d = self.step(F)
+            diags.append(d)
+        return F, np.array(diags).reshape(-1, 4)
+
+    def force(self, Fm):
+        d = np.zeros(4)
+        _lib3().orc3d_force(self._h, _p(np.ascontiguousarray(Fm)), _p(d))
+        return d
+
+    def moments(self, F):
+        out = np.zeros((self.ncell, 14))
+        _lib3().orc3d_moments(self._h, _p(np.ascontiguousarray(F)), _p(out))
+        return out

@@ -1,0 +1,494 @@
+/* Oracle, three-dimensional model (F) -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain serial-order FP64 implementation of the 3D cut-cell method of
+ * Dechriste & Mieussens (2015), Section 5.1 (fixed body):
+ *   moments and Maxwellian ........................ Section 2.1, eqs. (MacroscopicTD), (MaxwellianTD)
+ *   diffuse wall with zero net mass flux ........... Section 5.1 step 4
+ *   explicit scheme with seven virtual faces ....... eq. (eq-schema3D)
+ *   control volumes, merge, redistribution ......... Section 5.1 steps 2, 6, 7
+ * READING (the paper leaves the 3D geometry "to the reader"): the gas area
+ * of a Cartesian face is the 2D virtual-cell polygon of that face's four
+ * vertices (linear crossings on mixed edges); the wall face closes the cell,
+ * |S_w| n_w = -sum_k |S_k| n_k, n_w pointing into the solid; its centre is
+ * the mean of the cell's edge crossings; the volume follows from the
+ * divergence theorem, V = 1/3 sum_faces |S| (m . n).  READING (printed
+ * typos of eq. eq-schema3D): the y and z fluxes use v_{p2} and v_{p3}, the
+ * collision term carries dt, tau is per cell.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+#define GAS 0
+#define CUT 1
+#define SOLID 2
+
+struct orc3d {
+  orc_cfg cfg;
+  int nx, ny, nz, ncell, N, nvel;
+  double dx, dy, dz, dv, w, dt;
+  double *v;
+  double *phi;                    /* (nx+1)(ny+1)(nz+1) */
+  int *type, *master, *mptr, *midx;
+  double *S[6];                   /* gas areas of the faces x-, x+, y-, y+, z-, z+ */
+  double *sw, *nw[3], *rw[3];     /* wall area, normal into the solid, centre */
+  double *vbar, *vcv;             /* virtual-cell volume, control-volume volume */
+};
+
+static double mn(double a, double b) { return a < b ? a : b; }
+static double mx(double a, double b) { return a > b ? a : b; }
+
+/* 3D Maxwellian rho/(2 pi R T)^{3/2} exp(-|v-u|^2/(2 R T)), R = 1 */
+static double maxw3(double rho, const double *u, double T, double vx, double vy, double vz) {
+  double cx = vx - u[0], cy = vy - u[1], cz = vz - u[2];
+  return rho / pow(2.0 * M_PI * T, 1.5) * exp(-(cx * cx + cy * cy + cz * cz) / (2.0 * T));
+}
+
+/* gas polygon of a rectangle [0,h1]x[0,h2] whose corners (0,0), (h1,0),
+   (h1,h2), (0,h2) carry level-set values q[0..3]: area and centroid;
+   *saddle set when all four edges are crossed */
+static void face_polygon(const double *q, double h1, double h2, double *area, double *cs,
+                         double *ct, int *saddle, int *ncross, double *xs, double *xt) {
+  double cx[4] = {0, h1, h1, 0}, cy[4] = {0, 0, h2, h2};
+  double ps[8], pt[8];
+  int np = 0, nc = 0;
+  for (int e = 0; e < 4; ++e) {
+    int e1 = (e + 1) % 4;
+    if (q[e] > 0.0) { ps[np] = cx[e]; pt[np] = cy[e]; ++np; }
+    if ((q[e] > 0.0) != (q[e1] > 0.0)) {
+      double t = q[e] / (q[e] - q[e1]);
+      double s_ = cx[e] + t * (cx[e1] - cx[e]), t_ = cy[e] + t * (cy[e1] - cy[e]);
+      ps[np] = s_; pt[np] = t_; ++np;
+      xs[nc] = s_; xt[nc] = t_; ++nc;
+    }
+  }
+  *saddle = nc == 4;
+  *ncross = nc;
+  double A = 0.0, Cs = 0.0, Ct = 0.0;
+  for (int k = 0; k < np; ++k) {
+    int k1 = (k + 1) % np;
+    double cr = ps[k] * pt[k1] - ps[k1] * pt[k];
+    A += cr;
+    Cs += (ps[k] + ps[k1]) * cr;
+    Ct += (pt[k] + pt[k1]) * cr;
+  }
+  A *= 0.5;
+  *area = A;
+  if (A > 0.0) { *cs = Cs / (6.0 * A); *ct = Ct / (6.0 * A); }
+  else { *cs = 0.0; *ct = 0.0; }
+}
+
+static double levelset3(const orc_cfg *cf, double x, double y, double z) {
+  if (cf->body_kind == 5) {
+    double a = x - cf->center[0], b = y - cf->center[1], c = z - cf->center[2];
+    return sqrt(a * a + b * b + c * c) - cf->axes[0];
+  }
+  return 1.0e300;
+}
+
+static int build3(orc3d *o) {
+  const orc_cfg *cf = &o->cfg;
+  int nx = o->nx, ny = o->ny, nz = o->nz;
+  int vx = nx + 1, vy = ny + 1;
+  double eps = 1e-10 * o->dx;
+  for (int c = 0; c <= nz; ++c)
+    for (int b = 0; b <= ny; ++b)
+      for (int a = 0; a <= nx; ++a) {
+        double p = levelset3(cf, cf->lo[0] + a * o->dx, cf->lo[1] + b * o->dy, cf->lo[2] + c * o->dz);
+        double s = p >= 0.0 ? 1.0 : -1.0;
+        o->phi[((size_t)c * vy + b) * vx + a] = s * mx(fabs(p), eps);
+      }
+#define PH(a, b, c) o->phi[((size_t)(c) * vy + (b)) * vx + (a)]
+  int bad = 0;
+  double h[3] = {o->dx, o->dy, o->dz};
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        int cc = (k * ny + j) * nx + i;
+        double q8[8];
+        double qmin = 1e300, qmax = -1e300;
+        for (int t = 0; t < 8; ++t) {
+          q8[t] = PH(i + (t & 1), j + ((t >> 1) & 1), k + ((t >> 2) & 1));
+          qmin = mn(qmin, q8[t]); qmax = mx(qmax, q8[t]);
+        }
+        int type = qmin > 0.0 ? GAS : (qmax < 0.0 ? SOLID : CUT);
+        o->type[cc] = type;
+        /* faces: axis d, side s (0: at 0, 1: at h_d); local axes (d1, d2) */
+        double V = 0.0;
+        double Aw[3] = {0, 0, 0};
+        for (int d = 0; d < 3; ++d) {
+          int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+          for (int sd = 0; sd < 2; ++sd) {
+            double q[4];
+            /* corners in the order (0,0), (h1,0), (h1,h2), (0,h2) of (d1, d2) */
+            int co[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+            for (int t = 0; t < 4; ++t) {
+              int idx[3];
+              idx[d] = sd; idx[d1] = co[t][0]; idx[d2] = co[t][1];
+              q[t] = q8[idx[0] | (idx[1] << 1) | (idx[2] << 2)];
+            }
+            double area, cs, ct, xs[4], xt[4];
+            int saddle, ncr;
+            face_polygon(q, h[d1], h[d2], &area, &cs, &ct, &saddle, &ncr, xs, xt);
+            if (saddle) bad = 1;
+            o->S[2 * d + sd][cc] = type == SOLID ? 0.0 : area;
+            /* outward normal: -e_d on side 0, +e_d on side 1; m.n = sd*h_d */
+            double sgn = sd ? 1.0 : -1.0;
+            Aw[d] -= sgn * area;
+            V += area * (sd ? h[d] : 0.0) / 3.0;
+          }
+        }
+        /* edge crossings of the cell (12 edges) -> wall centre */
+        double rs[3] = {0, 0, 0};
+        int ncx = 0;
+        for (int d = 0; d < 3; ++d)
+          for (int t = 0; t < 4; ++t) {
+            int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+            int idx0[3], idx1[3];
+            idx0[d] = 0; idx1[d] = 1;
+            idx0[d1] = idx1[d1] = t & 1;
+            idx0[d2] = idx1[d2] = (t >> 1) & 1;
+            double qa = q8[idx0[0] | (idx0[1] << 1) | (idx0[2] << 2)];
+            double qb = q8[idx1[0] | (idx1[1] << 1) | (idx1[2] << 2)];
+            if ((qa > 0.0) != (qb > 0.0)) {
+              double tt = qa / (qa - qb);
+              double p3[3];
+              p3[d] = tt * h[d]; p3[d1] = idx0[d1] * h[d1]; p3[d2] = idx0[d2] * h[d2];
+              rs[0] += p3[0]; rs[1] += p3[1]; rs[2] += p3[2];
+              ++ncx;
+            }
+          }
+        double Sw = sqrt(Aw[0] * Aw[0] + Aw[1] * Aw[1] + Aw[2] * Aw[2]);
+        if (type == CUT && ncx > 0 && Sw > 0.0) {
+          double r[3] = {rs[0] / ncx, rs[1] / ncx, rs[2] / ncx};
+          o->sw[cc] = Sw;
+          for (int d = 0; d < 3; ++d) o->nw[d][cc] = Aw[d] / Sw;
+          V += (r[0] * Aw[0] + r[1] * Aw[1] + r[2] * Aw[2]) / 3.0;
+          o->rw[0][cc] = cf->lo[0] + i * o->dx + r[0];
+          o->rw[1][cc] = cf->lo[1] + j * o->dy + r[1];
+          o->rw[2][cc] = cf->lo[2] + k * o->dz + r[2];
+        } else {
+          o->sw[cc] = 0.0;
+          for (int d = 0; d < 3; ++d) { o->nw[d][cc] = 0.0; o->rw[d][cc] = 0.0; }
+        }
+        o->vbar[cc] = type == SOLID ? 0.0 : (type == GAS ? o->dx * o->dy * o->dz : V);
+      }
+  /* masters: centre in gas = mean of the 8 vertex values > 1e-12 dx; hop
+     across the largest face shared with a cell of the domain, order
+     x+, x-, y+, y-, z+, z- */
+  double thr = 1e-12 * o->dx;
+  for (int cc = 0; cc < o->ncell; ++cc) {
+    if (o->type[cc] == SOLID) { o->master[cc] = -1; continue; }
+    int i = cc % nx, j = (cc / nx) % ny, k = cc / (nx * ny), hops = 0;
+    int seen[5];
+    seen[0] = cc;
+    for (;;) {
+      int c2 = (k * ny + j) * nx + i;
+      double avg = 0.0;
+      for (int t = 0; t < 8; ++t) avg += PH(i + (t & 1), j + ((t >> 1) & 1), k + ((t >> 2) & 1));
+      if (avg / 8.0 > thr) break;
+      double L[6] = {i + 1 < nx ? o->S[1][c2] : 0.0, i > 0 ? o->S[0][c2] : 0.0,
+                     j + 1 < ny ? o->S[3][c2] : 0.0, j > 0 ? o->S[2][c2] : 0.0,
+                     k + 1 < nz ? o->S[5][c2] : 0.0, k > 0 ? o->S[4][c2] : 0.0};
+      double M = 0.0;
+      for (int t = 0; t < 6; ++t) M = mx(M, L[t]);
+      if (!(M > 0.0) || hops == 4) { bad = 1; break; }
+      double tie = M * (1.0 - 1e-12);
+      int t = 0;
+      while (L[t] < tie) ++t;
+      if (t == 0) i += 1; else if (t == 1) i -= 1; else if (t == 2) j += 1;
+      else if (t == 3) j -= 1; else if (t == 4) k += 1; else k -= 1;
+      ++hops;
+      int nc = (k * ny + j) * nx + i;
+      for (int hh = 0; hh < hops; ++hh) if (seen[hh] == nc) bad = 1;
+      if (bad) break;
+      seen[hops] = nc;
+    }
+    o->master[cc] = (k * ny + j) * nx + i;
+  }
+#undef PH
+  if (bad) return -3;
+  int n = o->ncell;
+  memset(o->mptr, 0, (n + 1) * sizeof(int));
+  for (int c = 0; c < n; ++c) if (o->master[c] >= 0) o->mptr[o->master[c] + 1]++;
+  for (int c = 0; c < n; ++c) o->mptr[c + 1] += o->mptr[c];
+  int *fill = calloc(n, sizeof(int));
+  for (int c = 0; c < n; ++c) {
+    int m = o->master[c];
+    if (m >= 0) o->midx[o->mptr[m] + fill[m]++] = c;
+  }
+  free(fill);
+  for (int c = 0; c < n; ++c) {
+    o->vcv[c] = 0.0;
+    for (int q = o->mptr[c]; q < o->mptr[c + 1]; ++q) o->vcv[c] += o->vbar[o->midx[q]];
+  }
+  for (int c = 0; c < n; ++c) {
+    int m = o->master[c];
+    if (m >= 0 && o->master[m] != m) return -3;
+  }
+  return 0;
+}
+
+void orc3d_destroy(orc3d *o);
+
+int orc3d_create(const orc_cfg *cfg, orc3d **out) {
+  if (!cfg || cfg->dim != 3 || cfg->n[0] < 1 || cfg->n[1] < 1 || cfg->n[2] < 1 || cfg->nv < 1 ||
+      !(cfg->vmax > cfg->vmin))
+    return -1;
+  orc3d *o = calloc(1, sizeof(orc3d));
+  o->cfg = *cfg;
+  o->nx = cfg->n[0]; o->ny = cfg->n[1]; o->nz = cfg->n[2];
+  o->ncell = o->nx * o->ny * o->nz;
+  o->N = cfg->nv; o->nvel = o->N * o->N * o->N;
+  o->dx = (cfg->hi[0] - cfg->lo[0]) / o->nx;
+  o->dy = (cfg->hi[1] - cfg->lo[1]) / o->ny;
+  o->dz = (cfg->hi[2] - cfg->lo[2]) / o->nz;
+  o->dv = (cfg->vmax - cfg->vmin) / o->N;
+  o->w = o->dv * o->dv * o->dv;
+  o->v = malloc(o->N * sizeof(double));
+  for (int p = 0; p < o->N; ++p) o->v[p] = cfg->vmin + (p + 0.5) * o->dv;
+  double vm = 0.0;
+  for (int p = 0; p < o->N; ++p) vm = mx(vm, fabs(o->v[p]));
+  o->dt = cfg->dt > 0.0 ? cfg->dt : cfg->cfl / (vm / o->dx + vm / o->dy + vm / o->dz);
+  size_t n = o->ncell;
+  o->phi = malloc((size_t)(o->nx + 1) * (o->ny + 1) * (o->nz + 1) * sizeof(double));
+  o->type = calloc(n, sizeof(int)); o->master = calloc(n, sizeof(int));
+  o->mptr = calloc(n + 1, sizeof(int)); o->midx = calloc(n, sizeof(int));
+  for (int f = 0; f < 6; ++f) o->S[f] = calloc(n, sizeof(double));
+  o->sw = calloc(n, sizeof(double));
+  for (int d = 0; d < 3; ++d) { o->nw[d] = calloc(n, sizeof(double)); o->rw[d] = calloc(n, sizeof(double)); }
+  o->vbar = calloc(n, sizeof(double)); o->vcv = calloc(n, sizeof(double));
+  int st = build3(o);
+  if (st) { orc3d_destroy(o); return st; }
+  *out = o;
+  return 0;
+}
+
+void orc3d_destroy(orc3d *o) {
+  if (!o) return;
+  free(o->v); free(o->phi); free(o->type); free(o->master); free(o->mptr); free(o->midx);
+  for (int f = 0; f < 6; ++f) free(o->S[f]);
+  free(o->sw);
+  for (int d = 0; d < 3; ++d) { free(o->nw[d]); free(o->rw[d]); }
+  free(o->vbar); free(o->vcv);
+  free(o);
+}
+
+double orc3d_dt(const orc3d *o) { return o->dt; }
+
+/* geometry export: type, master, S (6 per cell, x-,x+,y-,y+,z-,z+), sw,
+   nw (3 per cell), rw (3 per cell), vbar, vcv */
+void orc3d_geometry(const orc3d *o, int *type, int *master, double *S6, double *sw, double *nw3,
+                    double *rw3, double *vbar, double *vcv) {
+  size_t n = o->ncell;
+  memcpy(type, o->type, n * sizeof(int));
+  memcpy(master, o->master, n * sizeof(int));
+  for (size_t c = 0; c < n; ++c) {
+    for (int f = 0; f < 6; ++f) S6[6 * c + f] = o->S[f][c];
+    for (int d = 0; d < 3; ++d) { nw3[3 * c + d] = o->nw[d][c]; rw3[3 * c + d] = o->rw[d][c]; }
+  }
+  memcpy(sw, o->sw, n * 8); memcpy(vbar, o->vbar, n * 8); memcpy(vcv, o->vcv, n * 8);
+}
+
+void orc3d_init(const orc3d *o, double *F) {
+  const double *in = o->cfg.inflow;
+  double u[3] = {in[1], in[2], in[3]};
+  int N = o->N;
+  for (int c = 0; c < o->ncell; ++c)
+    for (int p = 0; p < o->nvel; ++p) {
+      double M = maxw3(in[0], u, in[4], o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]);
+      F[(size_t)c * o->nvel + p] = o->type[c] == SOLID ? 0.0 : M;
+    }
+}
+
+static void merge3(const orc3d *o, double *F) {
+  int nvel = o->nvel;
+  double *acc = malloc(nvel * sizeof(double));
+  for (int m = 0; m < o->ncell; ++m) {
+    if (o->master[m] != m || o->mptr[m + 1] - o->mptr[m] <= 1) continue;
+    for (int p = 0; p < nvel; ++p) acc[p] = 0.0;
+    for (int q = o->mptr[m]; q < o->mptr[m + 1]; ++q) {
+      int c = o->midx[q];
+      for (int p = 0; p < nvel; ++p) acc[p] += o->vbar[c] * F[(size_t)c * nvel + p];
+    }
+    for (int q = o->mptr[m]; q < o->mptr[m + 1]; ++q) {
+      int c = o->midx[q];
+      for (int p = 0; p < nvel; ++p) F[(size_t)c * nvel + p] = acc[p] / o->vcv[m];
+    }
+  }
+  free(acc);
+}
+
+void orc3d_merge(const orc3d *o, double *F) { merge3(o, F); }
+
+static void moments3(const orc3d *o, const double *F, double *rho, double *u, double *T) {
+  int N = o->N;
+  double r = 0, m[3] = {0, 0, 0}, E = 0;
+  for (int p = 0; p < o->nvel; ++p) {
+    double vx = o->v[p % N], vy = o->v[(p / N) % N], vz = o->v[p / (N * N)];
+    r += F[p] * o->w;
+    m[0] += vx * F[p] * o->w; m[1] += vy * F[p] * o->w; m[2] += vz * F[p] * o->w;
+    E += 0.5 * (vx * vx + vy * vy + vz * vz) * F[p] * o->w;
+  }
+  *rho = r;
+  for (int d = 0; d < 3; ++d) u[d] = m[d] / r;
+  /* E = rho |u|^2/2 + 3/2 rho R T */
+  *T = (2.0 * E / r - (u[0] * u[0] + u[1] * u[1] + u[2] * u[2])) / 3.0;
+}
+
+/* scheme (eq-schema3D) for control volume m, fixed geometry */
+static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
+  int nvel = o->nvel, N = o->N, nx = o->nx, ny = o->ny, nz = o->nz;
+  const double *fc = Fm + (size_t)m * nvel;
+  const double *in = o->cfg.inflow;
+  double uin[3] = {in[1], in[2], in[3]};
+  double Tw = o->cfg.t_wall, zero[3] = {0, 0, 0};
+  double rho, u[3], T;
+  moments3(o, fc, &rho, u, &T);
+  int collide = o->cfg.kn > 0.0;
+  double tau = collide ? sqrt(M_PI) / 2.0 * (1.0 / rho) * o->cfg.kn * o->cfg.lref / sqrt(2.0) : 1.0;
+  double V = o->vcv[m];
+  double *R = calloc(nvel, sizeof(double));
+  double *fw = malloc(nvel * sizeof(double));
+  for (int q = o->mptr[m]; q < o->mptr[m + 1]; ++q) {
+    int k = o->midx[q];
+    int i = k % nx, j = (k / nx) % ny, kk = k / (nx * ny);
+    const double *fk = Fm + (size_t)k * nvel;
+    int nb[6] = {i > 0 ? k - 1 : -1, i + 1 < nx ? k + 1 : -1, j > 0 ? k - nx : -1,
+                 j + 1 < ny ? k + nx : -1, kk > 0 ? k - nx * ny : -1, kk + 1 < nz ? k + nx * ny : -1};
+    int has_wall = o->sw[k] > 0.0;
+    if (has_wall) {
+      /* wall density (Section 5.1 step 4), fixed wall u_w = 0 */
+      double num = 0.0, den = 0.0;
+      for (int p = 0; p < nvel; ++p) {
+        double vx = o->v[p % N], vy = o->v[(p / N) % N], vz = o->v[p / (N * N)];
+        double cn = vx * o->nw[0][k] + vy * o->nw[1][k] + vz * o->nw[2][k];
+        if (cn > 0.0) num += cn * fc[p] * o->w;
+        else if (cn < 0.0) den += cn * maxw3(1.0, zero, Tw, vx, vy, vz) * o->w;
+      }
+      double phi = den != 0.0 ? -num / den : 0.0;
+      for (int p = 0; p < nvel; ++p)
+        fw[p] = phi * maxw3(1.0, zero, Tw, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]);
+    }
+    for (int p = 0; p < nvel; ++p) {
+      double vv[3] = {o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]};
+      double r = 0.0;
+      for (int f = 0; f < 6; ++f) {
+        double A = o->S[f][k];
+        if (A == 0.0) continue;
+        /* outward normal velocity of face f */
+        double c = (f & 1) ? vv[f / 2] : -vv[f / 2];
+        double fn = nb[f] >= 0 ? Fm[(size_t)nb[f] * nvel + p] : maxw3(in[0], uin, in[4], vv[0], vv[1], vv[2]);
+        r += A * (mx(c, 0.0) * fk[p] + mn(c, 0.0) * fn);
+      }
+      if (has_wall) {
+        double cn = vv[0] * o->nw[0][k] + vv[1] * o->nw[1][k] + vv[2] * o->nw[2][k];
+        r += o->sw[k] * (mn(cn, 0.0) * fw[p] + mx(cn, 0.0) * fk[p]);
+      }
+      R[p] += r;
+    }
+  }
+  for (int p = 0; p < nvel; ++p) {
+    double E = collide ? maxw3(rho, u, T, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]) : 0.0;
+    double fnew = fc[p] - o->dt / V * R[p];
+    if (collide) fnew += o->dt / tau * (E - fc[p]);
+    out[p] = fnew;
+  }
+  free(R); free(fw);
+}
+
+static void force3(const orc3d *o, const double *Fm, double *diag) {
+  int nvel = o->nvel, N = o->N;
+  double Tw = o->cfg.t_wall, zero[3] = {0, 0, 0};
+  double F[3] = {0, 0, 0}, mass = 0.0;
+  for (int k = 0; k < o->ncell; ++k) {
+    if (o->sw[k] <= 0.0) continue;
+    const double *fc = Fm + (size_t)o->master[k] * nvel;
+    double num = 0.0, den = 0.0;
+    for (int p = 0; p < nvel; ++p) {
+      double vx = o->v[p % N], vy = o->v[(p / N) % N], vz = o->v[p / (N * N)];
+      double cn = vx * o->nw[0][k] + vy * o->nw[1][k] + vz * o->nw[2][k];
+      if (cn > 0.0) num += cn * fc[p] * o->w;
+      else if (cn < 0.0) den += cn * maxw3(1.0, zero, Tw, vx, vy, vz) * o->w;
+    }
+    double phi = den != 0.0 ? -num / den : 0.0;
+    double s[3] = {0, 0, 0};
+    for (int p = 0; p < nvel; ++p) {
+      double vv[3] = {o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]};
+      double cn = vv[0] * o->nw[0][k] + vv[1] * o->nw[1][k] + vv[2] * o->nw[2][k];
+      double fv = cn < 0.0 ? phi * maxw3(1.0, zero, Tw, vv[0], vv[1], vv[2]) : (cn > 0.0 ? fc[p] : 0.0);
+      for (int d = 0; d < 3; ++d) s[d] += vv[d] * cn * fv * o->w;
+    }
+    for (int d = 0; d < 3; ++d) F[d] += s[d] * o->sw[k];
+  }
+  for (int m = 0; m < o->ncell; ++m) {
+    if (o->master[m] != m) continue;
+    double sm = 0.0;
+    for (int p = 0; p < nvel; ++p) sm += Fm[(size_t)m * nvel + p] * o->w;
+    mass += o->vcv[m] * sm;
+  }
+  diag[0] = F[0]; diag[1] = F[1]; diag[2] = F[2]; diag[3] = mass;
+}
+
+void orc3d_force(const orc3d *o, const double *Fm, double *diag) { force3(o, Fm, diag); }
+
+void orc3d_update_cells(const orc3d *o, const double *Fm, const int *cells, int ncells, double *out) {
+  int nvel = o->nvel;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int q = 0; q < ncells; ++q) {
+    int m = o->master[cells[q]];
+    double *dst = out + (size_t)q * nvel;
+    if (m < 0) { memset(dst, 0, nvel * sizeof(double)); continue; }
+    scheme3(o, Fm, m, dst);
+  }
+}
+
+int orc3d_step(orc3d *o, const double *F, double *Fo, double *diag) {
+  int nvel = o->nvel;
+  size_t tot = (size_t)o->ncell * nvel;
+  double *Fm = malloc(tot * sizeof(double));
+  memcpy(Fm, F, tot * sizeof(double));
+  merge3(o, Fm);
+  if (diag) force3(o, Fm, diag);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int m = 0; m < o->ncell; ++m) {
+    if (o->master[m] != m) continue;
+    scheme3(o, Fm, m, Fo + (size_t)m * nvel);
+  }
+  for (int c = 0; c < o->ncell; ++c) {
+    int m = o->master[c];
+    if (m < 0) memset(Fo + (size_t)c * nvel, 0, nvel * sizeof(double));
+    else if (m != c) memcpy(Fo + (size_t)c * nvel, Fo + (size_t)m * nvel, nvel * sizeof(double));
+  }
+  free(Fm);
+  return 0;
+}
+
+/* moments per cell, eq. (MacroscopicTD): rho, ux, uy, uz, T, Sxx, Sxy, Sxz,
+   Syy, Syz, Szz, qx, qy, qz (14 per cell) */
+void orc3d_moments(const orc3d *o, const double *F, double *out) {
+  int N = o->N;
+  for (int c = 0; c < o->ncell; ++c) {
+    double *q = out + (size_t)c * 14;
+    if (o->type[c] == SOLID) { for (int k = 0; k < 14; ++k) q[k] = 0.0; continue; }
+    const double *fc = F + (size_t)c * o->nvel;
+    double rho, u[3], T;
+    moments3(o, fc, &rho, u, &T);
+    double S[6] = {0, 0, 0, 0, 0, 0}, h[3] = {0, 0, 0};
+    for (int p = 0; p < o->nvel; ++p) {
+      double cx = o->v[p % N] - u[0], cy = o->v[(p / N) % N] - u[1], cz = o->v[p / (N * N)] - u[2];
+      double fw = fc[p] * o->w;
+      S[0] += cx * cx * fw; S[1] += cx * cy * fw; S[2] += cx * cz * fw;
+      S[3] += cy * cy * fw; S[4] += cy * cz * fw; S[5] += cz * cz * fw;
+      double e = 0.5 * (cx * cx + cy * cy + cz * cz) * fw;
+      h[0] += cx * e; h[1] += cy * e; h[2] += cz * e;
+    }
+    q[0] = rho; q[1] = u[0]; q[2] = u[1]; q[3] = u[2]; q[4] = T;
+    for (int k = 0; k < 6; ++k) q[5 + k] = S[k];
+    for (int k = 0; k < 3; ++k) q[11 + k] = h[k];
+  }
+}
+
+void orc3d_velocity(const orc3d *o, double *v) { memcpy(v, o->v, o->N * sizeof(double)); }

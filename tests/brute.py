@@ -123,3 +123,95 @@ def brute_step(cfg, geo, v, dt, f, g, collide=True):
             out_f[c] = newf
             out_g[c] = newg
     return out_f, out_g
+
+
+def maxwellian3(rho, u, T, v):
+    c2 = (v[0] - u[0]) ** 2 + (v[1] - u[1]) ** 2 + (v[2] - u[2]) ** 2
+    return rho / (2 * math.pi * T) ** 1.5 * math.exp(-c2 / (2 * T))
+
+
+def brute_step_3d(cfg, geo, v, dt, F, collide=True):
+    """Face-loop formulation of one fixed-geometry 3D step (eq. eq-schema3D):
+    every Cartesian face is visited once, its upwind flux added to the control
+    volume below it and subtracted from the one above; wall faces add their
+    flux to their own control volume."""
+    nx, ny, nz = cfg.n
+    N = cfg.nv
+    nvel = N ** 3
+    dv = (cfg.vmax - cfg.vmin) / N
+    w = dv ** 3
+    rho_in, ux, uy, uz, T_in = cfg.inflow
+    Tw = cfg.body.t_wall
+    vel = [(v[p % N], v[(p // N) % N], v[p // (N * N)]) for p in range(nvel)]
+    ghost = np.array([maxwellian3(rho_in, (ux, uy, uz), T_in, q) for q in vel])
+    master = geo["master"]
+    S, vbar, vcv = geo["S"], geo["vbar"], geo["vcv"]
+    ncell = nx * ny * nz
+    F = F.copy()
+    groups = {}
+    for c in range(ncell):
+        if master[c] >= 0:
+            groups.setdefault(int(master[c]), []).append(c)
+    for m, mem in groups.items():
+        if len(mem) > 1:
+            fc = sum(vbar[c] * F[c] for c in mem) / vcv[m]
+            for c in mem:
+                F[c] = fc
+    R = {m: np.zeros(nvel) for m in groups}
+    n3 = (nx, ny, nz)
+    stride = (1, nx, nx * ny)
+    vd = [np.array([q[d] for q in vel]) for d in range(3)]
+
+    def cell(idx):
+        return idx[0] + nx * (idx[1] + ny * idx[2])
+
+    for d in range(3):
+        others = [e for e in range(3) if e != d]
+        for a in range(n3[others[0]]):
+            for b in range(n3[others[1]]):
+                for s in range(n3[d] + 1):
+                    lo = [0, 0, 0]
+                    lo[others[0]] = a
+                    lo[others[1]] = b
+                    lo[d] = s - 1
+                    hi = list(lo)
+                    hi[d] = s
+                    has_lo, has_hi = s - 1 >= 0, s < n3[d]
+                    A = S[cell(hi), 2 * d] if has_hi else S[cell(lo), 2 * d + 1]
+                    if has_lo and has_hi:
+                        assert S[cell(lo), 2 * d + 1] == A
+                    if A == 0.0:
+                        continue
+                    f_lo = F[cell(lo)] if has_lo else ghost
+                    f_hi = F[cell(hi)] if has_hi else ghost
+                    flux = A * (np.minimum(vd[d], 0) * f_hi + np.maximum(vd[d], 0) * f_lo)
+                    if has_lo:
+                        R[int(master[cell(lo)])] += flux
+                    if has_hi:
+                        R[int(master[cell(hi)])] -= flux
+    for k in range(ncell):
+        A = geo["sw"][k]
+        if A <= 0.0:
+            continue
+        n = geo["nw"][k]
+        cn = vd[0] * n[0] + vd[1] * n[1] + vd[2] * n[2]
+        Mw = np.array([maxwellian3(1.0, (0, 0, 0), Tw, q) for q in vel])
+        num = np.sum(np.where(cn > 0, cn * F[k], 0.0)) * w
+        den = np.sum(np.where(cn < 0, cn * Mw, 0.0)) * w
+        phi = -num / den
+        R[int(master[k])] += A * np.where(cn < 0, cn * phi * Mw, cn * F[k])
+    out = np.zeros_like(F)
+    tau_c = math.sqrt(math.pi) / 2 * cfg.kn * cfg.lref / math.sqrt(2.0)
+    for m, mem in groups.items():
+        fm = F[m]
+        new = fm - dt / vcv[m] * R[m]
+        if collide:
+            rho = fm.sum() * w
+            u = [float((vd[d] * fm).sum() * w / rho) for d in range(3)]
+            E = float((0.5 * (vd[0] ** 2 + vd[1] ** 2 + vd[2] ** 2) * fm).sum() * w)
+            T = (2 * E / rho - u[0] ** 2 - u[1] ** 2 - u[2] ** 2) / 3
+            Eq = np.array([maxwellian3(rho, u, T, q) for q in vel])
+            new = new + dt / (tau_c / rho) * (Eq - fm)
+        for c in mem:
+            out[c] = new
+    return out
