@@ -30,6 +30,8 @@ WORKLOAD_TEXT = {
                   "free to rotate (J=0.01), Kn {kn}, Mach 0.5, geometry rebuilt every step, "
                   "torque every step",
     "cyl32": "cyl32: 2D 32x32 cells, 16x16 velocities, cylinder r=0.2, Kn {kn}, Mach 0.5",
+    "sphere128": "sphere128: 3D 128x64x64 cells on [0,1]x[0,0.5]^2, 16^3 velocities on [-6,6]^3, "
+                 "sphere r=0.1, Kn {kn}, Mach 0.5, T_w 1, CFL 0.5, force every step",
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_1503_04544_amd", "csrc", "step2d.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_regular2d_cyl512.json")
@@ -130,8 +132,9 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kn", type=float, default=None)
-    ap.add_argument("--workload", default="cyl512", choices=["cyl512", "ellipse256", "cyl32", "batch"],
-                    help="cyl512 (default, the headline line) | ellipse256 (moving body) | cyl32")
+    ap.add_argument("--workload", default="cyl512", choices=["cyl512", "ellipse256", "cyl32", "sphere128", "batch"],
+                    help="cyl512 (default, the headline line) | ellipse256 (moving body) | cyl32 | "
+                         "sphere128 (3D)")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=40,
@@ -166,7 +169,7 @@ def main():
     s = Solver(cfg, device=dev)
     n_irr, n_mem, n_solid = s.counts()
     active = cfg.ncell - n_solid
-    nvel = cfg.nv ** 2
+    nvel = cfg.nv ** cfg.dim
     s.init_maxwellian()
     diag = torch.empty((max(args.steps, args.warmup, 1), 4), dtype=torch.float64, device=dev)
     log(f"bench: warmup {args.warmup} steps")
@@ -190,9 +193,11 @@ def main():
     cut_ms, cut_n = s.profile_read(1)
     red_ms, red_n = s.profile_read(2)
     mrg_ms, mrg_n = s.profile_read(3)
+    mom_ms, mom_n = s.profile_read(4)
     s.profile_enable(False)
     n_regular = active - n_irr - n_mem
-    bytes_per_launch = n_regular * nvel * 32        # read f,g + write f,g, FP64
+    # read + write of the state, FP64: f,g in 2D (32 B), F in 3D (16 B)
+    bytes_per_launch = n_regular * nvel * (32 if cfg.dim == 2 else 16)
     avg_s = reg_ms / max(reg_n, 1) / 1e3
     achieved = bytes_per_launch / avg_s / 1e9
     traffic = measured_traffic() if args.workload == "cyl512" else None
@@ -214,7 +219,7 @@ def main():
                    "cells": cfg.ncell, "active_cells": active, "velocities": nvel,
                    "cut_control_volumes": n_irr, "merged_cells": n_mem, "dt": s.dt,
                    "drag_last_step": drag_last},
-        "roofline": {"bound": "hbm", "kernel": "k_step2d",
+        "roofline": {"bound": "hbm", "kernel": "k_step2d" if cfg.dim == 2 else "k_step3d",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "avg_launch_us": round(avg_s * 1e6, 2),
@@ -223,6 +228,8 @@ def main():
                      "reduce_kernel_avg_us": round(red_ms / max(red_n, 1) * 1e3, 2),
                      "merge_kernel_avg_us": round(mrg_ms / max(mrg_n, 1) * 1e3, 2)},
     }
+    if cfg.dim == 3:
+        out["roofline"]["moment_kernel_avg_us"] = round(mom_ms / max(mom_n, 1) * 1e3, 2)
     if args.workload == "cyl512" and args.adjoint_steps > 0:
         # adjoint over the same workload: forward alone vs forward with
         # checkpoints + recomputation + adjoint sweep (cc_adjoint)

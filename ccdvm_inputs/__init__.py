@@ -8,7 +8,8 @@ structures.
 """
 from .configs import (Body, Config, mach_to_speed, workload, WORKLOADS,
                       small_2d, small_3d, batch_instances)
-from .states import random_state
+from .states import random_state, tiled_random_state
 
 __all__ = ["Body", "Config", "mach_to_speed", "workload", "WORKLOADS",
-           "small_2d", "small_3d", "batch_instances", "random_state"]
+           "small_2d", "small_3d", "batch_instances", "random_state",
+           "tiled_random_state"]

@@ -98,7 +98,10 @@ typedef struct {
 } cc_body;
 
 /* Validates the set-up, computes dt and the sizes of the device buffers.
- * No device work.  *out receives a new context (free with cc_destroy). */
+ * No device work.  *out receives a new context (free with cc_destroy).
+ * Returns CC_EINVAL for an unsupported set-up; in 3D the velocity box must
+ * be symmetric about 0 and N one of 4, 6, 8, 12, 16, and the body a fixed
+ * sphere (or none). */
 cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out);
 void cc_destroy(cc_ctx* ctx);
 const char* cc_last_error(const cc_ctx* ctx);
@@ -167,6 +170,16 @@ cc_status cc_geometry_export(cc_ctx* ctx, int* type, int* master,
                              double* lw, double* nwx, double* nwy, double* rwx,
                              double* rwy, double* sbar, double* scv);
 
+/* 3D geometry tables (Section 5.1 with the face, wall and volume rules
+ * stated in the library's geometry source) to host arrays of ncell entries
+ * each (any pointer may be NULL): type, master, gas areas of the faces x-,
+ * x+, y-, y+, z-, z+, wall area, wall normal (into the solid), wall centre,
+ * virtual-cell volume, control-volume volume.  Synchronous. */
+cc_status cc_geometry_export3d(cc_ctx* ctx, int* type, int* master, double* sxm, double* sxp,
+                               double* sym, double* syp, double* szm, double* szp, double* aw,
+                               double* nwx, double* nwy, double* nwz, double* rwx, double* rwy,
+                               double* rwz, double* vbar, double* vcv);
+
 /* Number of control volumes handled by the cut-cell kernel (masters that
  * are cut cells or own merged cells) and of non-master non-solid cells. */
 cc_status cc_geometry_counts(cc_ctx* ctx, int* n_irregular, int* n_members,
@@ -179,8 +192,9 @@ cc_status cc_set_tile_rows(cc_ctx* ctx, int rows);
 
 /* Per-kernel timing with HIP events recorded on the bound stream.
  * cc_profile_enable(ctx, 1) starts recording (cleared); cc_profile_read
- * returns, for kernel id k (0 = fused step kernel, 1 = force-only cut-cell
- * kernel, 2 = final reduction of a stepping call, 3 = merge), the summed
+ * returns, for kernel id k (0 = regular-cell step kernel, 1 = cut-cell
+ * kernel, 2 = force/mass reduction, 3 = merge, 4 = 3D moment reduction
+ * between steps), the summed
  * milliseconds and the number of launches since enabling (at most 4096
  * launches per kernel are recorded).  Reading synchronises the stream. */
 cc_status cc_profile_enable(cc_ctx* ctx, int on);

@@ -51,6 +51,7 @@ SYMBOLS = {
     "cc_rigid_update": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_double]),
     "cc_dt": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "cc_geometry_export": (C.c_int, [C.c_void_p] + [C.c_void_p] * 13),
+    "cc_geometry_export3d": (C.c_int, [C.c_void_p] + [C.c_void_p] * 17),
     "cc_geometry_counts": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int)] * 3),
     "cc_set_tile_rows": (C.c_int, [C.c_void_p, C.c_int]),
     "cc_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),

@@ -108,7 +108,7 @@ void layout_geo3d(cc_ctx* ctx, char* base, size_t* bytes) {
 void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
   Carver cv{base};
   size_t n = ctx->ncell;
-  int nm = ctx->dim == 2 ? 4 : 5;
+  int nm = ctx->dim == 2 ? 4 : 8;
   ctx->s.skind = cv.take<int>(n);
   ctx->s.target = cv.take<int>(n);
   ctx->s.rcnt = cv.take<int>(n);
@@ -119,6 +119,7 @@ void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
   ctx->s.gcount = cv.take<int>(4);
   ctx->s.pose = cv.take<double>(4);
   ctx->s.mom = cv.take<double>(n * nm);
+  ctx->s.part = ctx->dim == 3 ? cv.take<double>(n * (size_t)chunks3d(ctx->N) * 5) : nullptr;
   ctx->s.fslot = cv.take<double>(n * 3 * 2);
   ctx->s.mpart_cap = (int)((size_t)((ctx->nx + 3) / 4) * ctx->ny * ctx->nz + n);
   ctx->s.mpart = cv.take<double>((size_t)ctx->s.mpart_cap * 2);
@@ -212,7 +213,10 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   ctx->N = c.nv;
   ctx->nvel = c.dim == 2 ? c.nv * c.nv : c.nv * c.nv * c.nv;
   if (c.dim == 2 && !regular_supported_2d(ctx->nvel)) return reject("unsupported velocity grid size");
-  if (c.dim == 3 && !regular_supported_3d(ctx->nvel)) return reject("unsupported velocity grid size");
+  if (c.dim == 3 && !regular_supported_3d(ctx->nvel))
+    return reject("unsupported velocity grid size (3D: N in {4, 6, 8, 12, 16})");
+  if (c.dim == 3 && fabs(c.vmin + c.vmax) > 1e-12 * fabs(c.vmax))
+    return reject("3D needs a velocity box symmetric about 0");
   ctx->dx = (c.hi[0] - c.lo[0]) / ctx->nx;
   ctx->dy = (c.hi[1] - c.lo[1]) / ctx->ny;
   ctx->dz = c.dim == 3 ? (c.hi[2] - c.lo[2]) / ctx->nz : 1.0;
@@ -367,10 +371,16 @@ cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
   if (st != CC_OK) return st;
   if (nsteps == 0) return CC_OK;
   bool moving = ctx->body.motion != CC_MOTION_FIXED && ctx->body.kind != CC_BODY_NONE;
-  if (diag) {
-    HIPCHK(ctx, ctx->dim == 2 ? launch_mass_2d(ctx, diag + 3) : launch_mass_3d(ctx, diag + 3), "mass");
+  if (ctx->dim == 3) {
+    // every step reduces its own force and mass rows
+    for (int n = 0; n < nsteps; ++n) {
+      hipError_t e = launch_step_3d(ctx, diag ? diag + 4 * (size_t)n : nullptr, nullptr);
+      if (e != hipSuccess) return hip_fail(ctx, e, "step");
+    }
+    return CC_OK;
   }
-  if (ctx->dim == 2 && !moving) {
+  if (diag) HIPCHK(ctx, launch_mass_2d(ctx, diag + 3), "mass");
+  if (!moving) {
     // fused step; the force/mass partials of step n are reduced by step n+1
     for (int n = 0; n < nsteps; ++n) {
       bool red = diag && n > 0;
@@ -384,9 +394,7 @@ cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
   for (int n = 0; n < nsteps; ++n) {
     double* frow = diag ? diag + 4 * (size_t)n : nullptr;
     double* mrow = (diag && n + 1 < nsteps) ? diag + 4 * (size_t)(n + 1) + 3 : nullptr;
-    hipError_t e;
-    if (ctx->dim == 3) e = launch_step_3d(ctx, frow, mrow);
-    else e = launch_moving_step_2d(ctx, frow, mrow);
+    hipError_t e = launch_moving_step_2d(ctx, frow, mrow);
     if (e != hipSuccess) return hip_fail(ctx, e, "step");
   }
   if (moving) {
@@ -473,6 +481,26 @@ cc_status cc_geometry_export(cc_ctx* ctx, int* type, int* master, double* lxm, d
       {type, G.type, 4}, {master, G.master, 4}, {lxm, G.lxm, 8}, {lxp, G.lxp, 8},
       {lym, G.lym, 8}, {lyp, G.lyp, 8}, {lw, G.lw, 8}, {nwx, G.nwx, 8}, {nwy, G.nwy, 8},
       {rwx, G.rwx, 8}, {rwy, G.rwy, 8}, {sbar, G.sbar, 8}, {scv, G.scv, 8}};
+  for (auto& c : cp)
+    if (c.dst) HIPCHK(ctx, hipMemcpyAsync(c.dst, c.src, n * c.sz, hipMemcpyDeviceToHost, ctx->stream), "export");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "export sync");
+  return CC_OK;
+}
+
+cc_status cc_geometry_export3d(cc_ctx* ctx, int* type, int* master, double* sxm, double* sxp,
+                               double* sym, double* syp, double* szm, double* szp, double* aw,
+                               double* nwx, double* nwy, double* nwz, double* rwx, double* rwy,
+                               double* rwz, double* vbar, double* vcv) {
+  if (!ctx) return CC_EINVAL;
+  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (ctx->dim != 3) return fail(ctx, CC_EINVAL, "3D only");
+  const Geo3D& G = ctx->g3;
+  size_t n = ctx->ncell;
+  struct { void* dst; const void* src; size_t sz; } cp[] = {
+      {type, G.type, 4}, {master, G.master, 4}, {sxm, G.sxm, 8}, {sxp, G.sxp, 8},
+      {sym, G.sym, 8}, {syp, G.syp, 8}, {szm, G.szm, 8}, {szp, G.szp, 8}, {aw, G.aw, 8},
+      {nwx, G.nwx, 8}, {nwy, G.nwy, 8}, {nwz, G.nwz, 8}, {rwx, G.rwx, 8}, {rwy, G.rwy, 8},
+      {rwz, G.rwz, 8}, {vbar, G.vbar, 8}, {vcv, G.vcv, 8}};
   for (auto& c : cp)
     if (c.dst) HIPCHK(ctx, hipMemcpyAsync(c.dst, c.src, n * c.sz, hipMemcpyDeviceToHost, ctx->stream), "export");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "export sync");

@@ -109,7 +109,9 @@ struct Scratch {
   int* gmem;         // receivers
   int* gcount;       // [0] entries in gl, [1] error bits
   double* pose;      // pose at t^{n+1}: cx, cy, theta
-  double* mom;       // ncell * 4 (2D: rho, ux, uy, T) or ncell * 5 (3D: rho, u, T)
+  double* mom;       // 2D: ncell * 4 (rho, ux, uy, T); 3D: ncell * 8 (Maxwellian factor, u,
+                     // 1/(2T), dt/tau, rho)
+  double* part;      // 3D: per cell and velocity chunk, sums of F, v F, |v|^2 F
   double* fslot;     // 2 x per irregular master: Fx, Fy, torque (2D) / Fx, Fy, Fz (3D)
   double* mpart;     // 2 x mass partials (regular tiles, then control volumes)
   int mpart_cap;
@@ -119,12 +121,12 @@ struct Scratch {
 
 // Per-kernel HIP events recorded around every launch while profiling is on;
 // elapsed times are summed when read.
-constexpr int kProfKernels = 4;
+constexpr int kProfKernels = 5;
 constexpr int kProfCap = 4096;
 struct Prof {
   bool on = false;
   std::vector<hipEvent_t> start[kProfKernels], stop[kProfKernels];
-  int count[kProfKernels] = {0, 0, 0, 0};
+  int count[kProfKernels] = {0, 0, 0, 0, 0};
 };
 
 }  // namespace ccdvm
@@ -217,6 +219,7 @@ hipError_t launch_moments_all_3d(cc_ctx* ctx);
 hipError_t launch_step_3d(cc_ctx* ctx, double* force_row, double* mass_row);
 hipError_t launch_mass_3d(cc_ctx* ctx, double* mass_row);
 hipError_t launch_moments_out_3d(cc_ctx* ctx, double* out);
+int chunks3d(int N);   // velocity chunks of the 3D regular-cell pass (0: unsupported N)
 
 // profiling hooks (capi.cpp)
 void prof_begin(cc_ctx* ctx, int k);

@@ -120,14 +120,29 @@ class Solver:
 
     # ---------------------------------------------------------------- geometry
     def geometry(self) -> dict:
+        """Geometry tables as host arrays.  3D: 'S' (ncell, 6) gas areas of
+        the faces x-, x+, y-, y+, z-, z+; 'sw' wall area; 'nw', 'rw' (ncell, 3)
+        wall normal and centre; 'vbar', 'vcv' volumes."""
         n = self.ncell
         out = {"type": np.zeros(n, np.int32), "master": np.zeros(n, np.int32)}
-        names = ["lxm", "lxp", "lym", "lyp", "lw", "nwx", "nwy", "rwx", "rwy", "sbar", "scv"]
-        for k in names:
-            out[k] = np.zeros(n)
         P = lambda a: a.ctypes.data_as(C.c_void_p)
-        self._check(lib().cc_geometry_export(self._h, P(out["type"]), P(out["master"]),
-                                             *[P(out[k]) for k in names]))
+        if self.dim == 2:
+            names = ["lxm", "lxp", "lym", "lyp", "lw", "nwx", "nwy", "rwx", "rwy", "sbar", "scv"]
+            for k in names:
+                out[k] = np.zeros(n)
+            self._check(lib().cc_geometry_export(self._h, P(out["type"]), P(out["master"]),
+                                                 *[P(out[k]) for k in names]))
+            return out
+        names = ["sxm", "sxp", "sym", "syp", "szm", "szp", "aw", "nwx", "nwy", "nwz",
+                 "rwx", "rwy", "rwz", "vbar", "vcv"]
+        raw = {k: np.zeros(n) for k in names}
+        self._check(lib().cc_geometry_export3d(self._h, P(out["type"]), P(out["master"]),
+                                               *[P(raw[k]) for k in names]))
+        out["S"] = np.stack([raw[k] for k in names[:6]], axis=1)
+        out["sw"] = raw["aw"]
+        out["nw"] = np.stack([raw["nwx"], raw["nwy"], raw["nwz"]], axis=1)
+        out["rw"] = np.stack([raw["rwx"], raw["rwy"], raw["rwz"]], axis=1)
+        out["vbar"], out["vcv"] = raw["vbar"], raw["vcv"]
         return out
 
     def counts(self):
