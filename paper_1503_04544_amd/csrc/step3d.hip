@@ -31,7 +31,18 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kTY = 4, kTZ = 4, kTileWaves = kTY * kTZ;
-constexpr int kPD3 = 2;   // cells prefetched ahead of the next one
+#ifndef CCDVM_PD3
+#define CCDVM_PD3 2
+#endif
+#ifndef CCDVM_HALO_PD
+#define CCDVM_HALO_PD 0
+#endif
+// Own cells are loaded kPD3 + 2 x-steps before they are updated, halo cells
+// kHaloPD x-steps before.  Vector-memory completions are waited for in issue
+// order, so each x-step issues the halo loads (needed soonest) before the own
+// prefetch.
+constexpr int kPD3 = CCDVM_PD3;
+constexpr int kHaloPD = CCDVM_HALO_PD;
 
 __device__ inline double wave_sum3(double v) {
 #pragma unroll
@@ -130,6 +141,23 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A) {
   auto own_row = [&](int i) -> const double* {
     return i < nx ? own_base + (size_t)i * nvel : A.ghost;
   };
+  auto load_halo = [&](double (&hy)[R], double (&hz)[R], int i, int lv) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool a = active(lv, r);
+      const int o = offset(lv, r);
+      hy[r] = y_glob && a ? y_base[(size_t)i * y_step + o] : 0.0;
+      hz[r] = z_glob && a ? z_base[(size_t)i * z_step + o] : 0.0;
+    }
+  };
+  double hqy[kHaloPD + 1][R], hqz[kHaloPD + 1][R];
+#pragma unroll
+  for (int d = 0; d < kHaloPD; ++d) {
+    if (d < nx) load_halo(hqy[d], hqz[d], d, lane);
+    else
+#pragma unroll
+      for (int r = 0; r < R; ++r) { hqy[d][r] = 0.0; hqz[d][r] = 0.0; }
+  }
   double prv[R], cur[R], q[kPD3 + 1][R];
   load_row(prv, A.ghost, lane);
   load_row(cur, own_base, lane);
@@ -144,21 +172,18 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A) {
   for (int i = 0; i < nx; ++i) {
     int lv = lane;
     asm volatile("" : "+v"(lv));
-    // prefetch: own cell i+kPD3+2 (the farfield past the end); the halo of
-    // cell i is read now and waited for after the exchange barrier
-    double qn[R], hy[R], hz[R];
+    // prefetch: halos of cell i+kHaloPD, then own cell i+kPD3+2 (the
+    // farfield past the end)
+    if (i + kHaloPD < nx) load_halo(hqy[kHaloPD], hqz[kHaloPD], i + kHaloPD, lv);
+    else
+#pragma unroll
+      for (int r = 0; r < R; ++r) { hqy[kHaloPD][r] = 0.0; hqz[kHaloPD][r] = 0.0; }
+    double qn[R];
     const int ia = i + kPD3 + 2;
     if (ia <= nx) load_row(qn, own_row(ia), lv);
     else
 #pragma unroll
       for (int r = 0; r < R; ++r) qn[r] = 0.0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const bool a = active(lv, r);
-      const int o = offset(lv, r);
-      hy[r] = y_glob && a ? y_base[(size_t)i * y_step + o] : 0.0;
-      hz[r] = z_glob && a ? z_base[(size_t)i * z_step + o] : 0.0;
-    }
     const int s = i & 1;
 #pragma unroll
     for (int r = 0; r < R; ++r) xch[s][wave][r][lv] = cur[r];
@@ -183,8 +208,8 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A) {
         const int p1 = rem % N, p2 = sy * C::H + rem / N, p3 = p3b + e / C::E1;
         const double vx = vnode3(vmin, dv, p1), vy = vnode3(vmin, dv, p2), vz = vnode3(vmin, dv, p3);
         const double E = Am * __shfl(tx, p1, kWave) * __shfl(tyy, p2, kWave) * __shfl(tzz, p3, kWave);
-        const double yv = y_lds ? xch[s][wy][r][lv] : hy[r];
-        const double zv = z_lds ? xch[s][wz][r][lv] : hz[r];
+        const double yv = y_lds ? xch[s][wy][r][lv] : hqy[0][r];
+        const double zv = z_lds ? xch[s][wz][r][lv] : hqz[0][r];
         const double f = cur[r];
         const double fxu = p1 >= C::H ? prv[r] : q[0][r];
         const double fn = f - A.cxf * fabs(vx) * (f - fxu) - A.cyf * fabs(vy) * (f - yv) -
@@ -209,7 +234,206 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A) {
 #pragma unroll
       for (int d = 0; d < kPD3; ++d) q[d][r] = q[d + 1][r];
       q[kPD3][r] = qn[r];
+#pragma unroll
+      for (int d = 0; d < kHaloPD; ++d) { hqy[d][r] = hqy[d + 1][r]; hqz[d][r] = hqz[d + 1][r]; }
     }
+  }
+}
+
+// ---------------------------------------------------------------------
+// N = 16 regular-cell kernel.  Same chunks as Chunk3<16> (R = 4 slots per
+// lane, 16 chunks), with the index structure made explicit: slot r of lane
+// l holds p1 = l % 16, p2 = 8 sy + l / 16 + 4 (r & 1), p3 = p3b + r / 2, at
+// offset (p3b + r/2) 256 + 128 sy + 64 (r & 1) + l in the cell.  Per x-step
+// and wave: one exp per lane (lanes 0-15, 16-31, 32-47 build the x, y, z
+// factors of the separable Maxwellian), the update written as
+// c0 f + a_x f_x + a_y f_y + a_z f_z + (dt/tau) E, the five moment sums
+// reduced by a reduce-scatter butterfly.  The previous cell (x-upwind for
+// v_x > 0) is read back from the wave's own LDS slot of the last x-step.
+// The x loop is unrolled by the 4-slot rotation of the own-cell prefetch
+// (slot (i+3) % 4 receives cell i+3), so no registers are moved.
+// ---------------------------------------------------------------------
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sums of v[0..4] over the wave: on return lanes 8q .. 8q+7 hold the sum
+// of quantity q (q < 5).
+__device__ inline double reduce5(const double (&v)[5], int lv) {
+  const bool b5 = lv & 32, b4 = lv & 16, b3 = lv & 8;
+  double w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double a = v[k], b = k == 0 ? v[4] : 0.0;   // quantities k and k+4
+    const double keep = b5 ? b : a, send = b5 ? a : b;
+    w[k] = keep + __shfl_xor(send, 32, kWave);
+  }
+  double x[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double keep = b4 ? w[k + 2] : w[k], send = b4 ? w[k] : w[k + 2];
+    x[k] = keep + __shfl_xor(send, 16, kWave);
+  }
+  double y;
+  {
+    const double keep = b3 ? x[1] : x[0], send = b3 ? x[0] : x[1];
+    y = keep + __shfl_xor(send, 8, kWave);
+  }
+  y += __shfl_xor(y, 4, kWave);
+  y += __shfl_xor(y, 2, kWave);
+  y += __shfl_xor(y, 1, kWave);
+  return y;
+}
+
+struct Ctx16 {
+  size_t pencil;          // cell index of the pencil's first cell
+  const double* own_base;
+  const double* y_base;
+  const double* z_base;
+  size_t y_step, z_step;
+  int cbase, wy, wz, wave, p3b, sy, ch;
+  bool valid, y_lds, z_lds, y_glob, z_glob;
+};
+
+template <int U>
+__device__ __forceinline__ void step16(const Step3Args& A, const Ctx16& X, int i,
+                                       double (&S)[4][4], double (*xch)[kTileWaves][4][kWave]) {
+  constexpr int R = 4;
+  constexpr int rof[4] = {0, 64, 256, 320};   // (r >> 1) * 256 + (r & 1) * 64
+  const int nx = A.nx, nvel = A.nvel;
+  int lv = threadIdx.x & 63;
+  asm volatile("" : "+v"(lv));
+  // halos of cell i (needed first), then own cell i+3 (the farfield past
+  // the end)
+  double hy[4], hz[4];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int o = X.cbase + rof[r] + lv;
+    hy[r] = X.y_glob ? X.y_base[(size_t)i * X.y_step + o] : 0.0;
+    hz[r] = X.z_glob ? X.z_base[(size_t)i * X.z_step + o] : 0.0;
+  }
+  double (&tgt)[4] = S[(U + 3) & 3];
+  if (i + 3 <= nx && X.valid) {
+    const double* row = i + 3 < nx ? X.own_base + (size_t)(i + 3) * nvel : A.ghost;
+#pragma unroll
+    for (int r = 0; r < R; ++r) tgt[r] = row[X.cbase + rof[r] + lv];
+  }
+  const double (&cur)[4] = S[U & 3];
+  const double (&nxt)[4] = S[(U + 1) & 3];
+  const int s = i & 1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) xch[s][X.wave][r][lv] = cur[r];
+  __syncthreads();
+  const int c = (int)(X.pencil + i);
+  if (X.valid && A.kind[c] == KIND_REGULAR) {
+    const double* mc = A.mom + 8 * (size_t)c;
+    const double Am = mc[0], inv2T = mc[4], nu = mc[5];
+    const double vmin = A.vmin, dv = A.dv;
+    const int g = lv >> 4;
+    const double ug = g == 0 ? mc[1] : (g == 1 ? mc[2] : mc[3]);
+    const double vt = vnode3(vmin, dv, lv & 15) - ug;
+    const double t = exp(-vt * vt * inv2T);
+    const int p2a = X.sy * 8 + (lv >> 4);
+    const double ex = __shfl(t, lv & 15, kWave);
+    const double eya = __shfl(t, 16 + p2a, kWave), eyb = __shfl(t, 20 + p2a, kWave);
+    const double ez0 = readlane_d(t, 32 + X.p3b), ez1 = readlane_d(t, 33 + X.p3b);
+    const double vx = vnode3(vmin, dv, lv & 15);
+    const double vya = vnode3(vmin, dv, p2a), vyb = vnode3(vmin, dv, p2a + 4);
+    const double vz0 = vnode3(vmin, dv, X.p3b), vz1 = vnode3(vmin, dv, X.p3b + 1);
+    const double ax = A.cxf * fabs(vx), aya = A.cyf * fabs(vya), ayb = A.cyf * fabs(vyb);
+    const double az0 = A.czf * fabs(vz0), az1 = A.czf * fabs(vz1);
+    const double base = 1.0 - nu - ax;
+    const double Ax = Am * ex;
+    const double Exa = Ax * eya, Exb = Ax * eyb;
+    const bool xpos = (lv & 15) >= 8;
+    double fn[4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double ay = (r & 1) ? ayb : aya, az = (r >> 1) ? az1 : az0;
+      const double E = ((r & 1) ? Exb : Exa) * ((r >> 1) ? ez1 : ez0);
+      const double fx = xpos ? xch[s ^ 1][X.wave][r][lv] : nxt[r];
+      const double fy = X.y_lds ? xch[s][X.wy][r][lv] : hy[r];
+      const double fz = X.z_lds ? xch[s][X.wz][r][lv] : hz[r];
+      const double c0 = base - ay - az;
+      fn[r] = c0 * cur[r] + ax * fx + ay * fy + az * fz + nu * E;
+    }
+    double* orow = A.out + (size_t)c * nvel + X.cbase + lv;
+#pragma unroll
+    for (int r = 0; r < R; ++r) __builtin_nontemporal_store(fn[r], orow + rof[r]);
+    const double A0 = fn[0] + fn[2], A1 = fn[1] + fn[3];
+    const double B0 = fn[0] + fn[1], B1 = fn[2] + fn[3];
+    const double s0 = A0 + A1;
+    double m[5];
+    m[0] = s0;
+    m[1] = vx * s0;
+    m[2] = vya * A0 + vyb * A1;
+    m[3] = vz0 * B0 + vz1 * B1;
+    m[4] = vx * vx * s0 + (vya * vya * A0 + vyb * vyb * A1) + (vz0 * vz0 * B0 + vz1 * vz1 * B1);
+    const double tot = reduce5(m, lv);
+    if ((lv & 7) == 0 && lv < 40) A.part[((size_t)c * 16 + X.ch) * 5 + (lv >> 3)] = tot;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_step3d16(const Step3Args A) {
+  __shared__ double xch[2][kTileWaves][4][kWave];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x;
+  const int logical = (b & 7) * A.per + (b >> 3);
+  if (logical >= A.nblk) return;
+  Ctx16 X;
+  X.ch = logical / A.ntiles;
+  const int tile = logical - X.ch * A.ntiles;
+  const int ty = wave & 3, tz = wave >> 2;
+  const int tj = tile % A.ntj, tk = tile / A.ntj;
+  const int j = tj * kTY + ty, k = tk * kTZ + tz;
+  X.valid = j < A.ny && k < A.nz;
+  X.sy = X.ch & 1;
+  X.p3b = (X.ch >> 1) * 2;
+  X.wave = wave;
+  X.cbase = X.p3b * 256 + X.sy * 128;
+  const int dyu = X.sy ? -1 : 1, dzu = X.p3b >= 8 ? -1 : 1;
+  const int jy = j + dyu, kz = k + dzu, tyu = ty + dyu, tzu = tz + dzu;
+  const bool y_dom = jy >= 0 && jy < A.ny, z_dom = kz >= 0 && kz < A.nz;
+  X.y_lds = y_dom && tyu >= 0 && tyu < kTY;
+  X.z_lds = z_dom && tzu >= 0 && tzu < kTZ;
+  X.wy = X.y_lds ? tz * kTY + tyu : 0;
+  X.wz = X.z_lds ? tzu * kTY + ty : 0;
+  const int nx = A.nx, nvel = A.nvel;
+  const size_t pencil = (size_t)((X.valid ? k : 0) * A.ny + (X.valid ? j : 0)) * nx;
+  X.pencil = pencil;
+  X.own_base = A.in + pencil * nvel;
+  X.y_base = y_dom && X.valid ? A.in + (size_t)(k * A.ny + jy) * nx * nvel : A.ghost;
+  X.z_base = z_dom && X.valid ? A.in + (size_t)(kz * A.ny + j) * nx * nvel : A.ghost;
+  X.y_step = y_dom && X.valid ? nvel : 0;
+  X.z_step = z_dom && X.valid ? nvel : 0;
+  X.y_glob = X.valid && !X.y_lds;
+  X.z_glob = X.valid && !X.z_lds;
+  constexpr int rof[4] = {0, 64, 256, 320};
+  double S[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { S[u][r] = 0.0; }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int o = X.cbase + rof[r] + lane;
+    // cells 0, 1, 2 (the farfield past the end); x-upwind of cell 0 is the farfield
+    if (X.valid) {
+      S[0][r] = X.own_base[o];
+      S[1][r] = 1 < nx ? X.own_base[(size_t)nvel + o] : A.ghost[o];
+      if (2 <= nx) S[2][r] = 2 < nx ? X.own_base[(size_t)2 * nvel + o] : A.ghost[o];
+    }
+    xch[1][wave][r][lane] = X.valid ? A.ghost[o] : 0.0;
+  }
+  for (int i = 0; i < nx; i += 4) {
+    step16<0>(A, X, i, S, xch);
+    if (i + 1 < nx) step16<1>(A, X, i + 1, S, xch);
+    if (i + 2 < nx) step16<2>(A, X, i + 2, S, xch);
+    if (i + 3 < nx) step16<3>(A, X, i + 3, S, xch);
   }
 }
 
@@ -519,7 +743,7 @@ typedef void (*part3_fn)(Geo3D, const double*, double*, double, double);
 
 template <int N>
 void pick3(step3_fn* s, part3_fn* p, int* nch) {
-  if (s) *s = k_step3d<N>;
+  if (s) *s = N == 16 ? k_step3d16 : k_step3d<N>;
   if (p) *p = k_part3d<N>;
   if (nch) *nch = Chunk3<N>::NCH;
 }
