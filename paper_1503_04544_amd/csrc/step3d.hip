@@ -34,6 +34,12 @@ constexpr int kTY = 4, kTZ = 4, kTileWaves = kTY * kTZ;
 #ifndef CCDVM_PD3
 #define CCDVM_PD3 2
 #endif
+#ifndef CCDVM_CHUNK_LAUNCH
+#define CCDVM_CHUNK_LAUNCH 0
+#endif
+#ifndef CCDVM_R16
+#define CCDVM_R16 4   // velocities per lane of the N = 16 kernel: 4 or 8
+#endif
 #ifndef CCDVM_HALO_PD
 #define CCDVM_HALO_PD 0
 #endif
@@ -67,7 +73,8 @@ template <int N>
 struct Chunk3 {
   static constexpr int H = N / 2;                 // p2 (or p3) values of one sign
   static constexpr int E1 = H * N;                // velocities of one (p3, half of p2)
-  static constexpr int G3 = (H % 2 == 0) ? 2 : (H % 3 == 0 ? 3 : 1);  // p3 per chunk
+  // p3 per chunk (N = 16: as the dedicated kernel's chunks)
+  static constexpr int G3 = N == 16 ? CCDVM_R16 / 2 : ((H % 2 == 0) ? 2 : (H % 3 == 0 ? 3 : 1));
   static constexpr int CH = G3 * E1;              // velocities per chunk
   static constexpr int R = (CH + kWave - 1) / kWave;
   static constexpr int NCH = 4 * H / G3;          // chunks
@@ -90,11 +97,13 @@ struct Step3Args {
   const double* ghost;  // farfield values
   int nx, ny, nz, nvel;
   int ntj, ntiles, nblk, per;
+  int ch0;              // first chunk of this launch
   double vmin, dv, cxf, cyf, czf;   // dt/dx, dt/dy, dt/dz
 };
 
 template <int N>
-__global__ void __launch_bounds__(1024) k_step3d(const Step3Args A) {
+__global__ void __launch_bounds__(1024) k_step3d(const Step3Args A, const int* __restrict__ kind,
+                                                const double* __restrict__ mom) {
   using C = Chunk3<N>;
   constexpr int R = C::R;
   __shared__ double xch[2][kTileWaves][R][kWave];
@@ -106,7 +115,8 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A) {
   const int b = blockIdx.x;
   const int logical = (b & 7) * A.per + (b >> 3);
   if (logical >= A.nblk) return;
-  const int ch = logical / A.ntiles, tile = logical - ch * A.ntiles;
+  const int lch = logical / A.ntiles, tile = logical - lch * A.ntiles;
+  const int ch = A.ch0 + lch;
   const int ty = wave & 3, tz = wave >> 2;
   const int tj = tile % A.ntj, tk = tile / A.ntj;
   const int j = tj * kTY + ty, k = tk * kTZ + tz;
@@ -189,8 +199,8 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A) {
     for (int r = 0; r < R; ++r) xch[s][wave][r][lv] = cur[r];
     __syncthreads();
     const int c = (int)(pencil + i);
-    if (valid && A.kind[c] == KIND_REGULAR) {
-      const double* mc = A.mom + 8 * (size_t)c;
+    if (valid && kind[c] == KIND_REGULAR) {
+      const double* mc = mom + 8 * (size_t)c;
       const double Am = mc[0], ux = mc[1], uy = mc[2], uz = mc[3], inv2T = mc[4], nu = mc[5];
       double tx = 0.0, tyy = 0.0, tzz = 0.0;
       if (lv < N) {
@@ -241,18 +251,24 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A) {
 }
 
 // ---------------------------------------------------------------------
-// N = 16 regular-cell kernel.  Same chunks as Chunk3<16> (R = 4 slots per
-// lane, 16 chunks), with the index structure made explicit: slot r of lane
-// l holds p1 = l % 16, p2 = 8 sy + l / 16 + 4 (r & 1), p3 = p3b + r / 2, at
-// offset (p3b + r/2) 256 + 128 sy + 64 (r & 1) + l in the cell.  Per x-step
-// and wave: one exp per lane (lanes 0-15, 16-31, 32-47 build the x, y, z
-// factors of the separable Maxwellian), the update written as
-// c0 f + a_x f_x + a_y f_y + a_z f_z + (dt/tau) E, the five moment sums
-// reduced by a reduce-scatter butterfly.  The previous cell (x-upwind for
-// v_x > 0) is read back from the wave's own LDS slot of the last x-step.
-// The x loop is unrolled by the 4-slot rotation of the own-cell prefetch
-// (slot (i+3) % 4 receives cell i+3), so no registers are moved.
+// N = 16 regular-cell kernel.  Same chunks as Chunk3<16> (R = 4 or 8 slots
+// per lane, 16 or 8 chunks of 64 R velocities), with the index structure made
+// explicit: slot r of lane l holds p1 = l % 16, p2 = 8 sy + l / 16 +
+// 4 (r & 1), p3 = p3b + r / 2, at offset (p3b + r/2) 256 + 128 sy +
+// 64 (r & 1) + l in the cell.  Per x-step and wave: one exp per lane (lanes
+// 0-15, 16-31, 32-47 build the x, y, z factors of the separable
+// Maxwellian), the update written as c0 f + a_x f_x + a_y f_y + a_z f_z +
+// (dt/tau) E, the five moment sums reduced by a reduce-scatter butterfly.
+// Each wave publishes its cell in its LDS slot before the x-step barrier and
+// then reads it back from there, as it reads the previous cell (x-upwind for
+// v_x > 0) from its slot of the last x-step; so the own cells rotate through
+// two register slots (next, in flight) and the x loop is unrolled by two.
+// Halo cells of the next x-step are requested after the update.
 // ---------------------------------------------------------------------
+constexpr int kR16 = CCDVM_R16;          // slots per lane: 4 or 8
+constexpr int kG16 = kR16 / 2;           // p3 values per chunk
+constexpr int kNCH16 = 2 * 16 / kG16;    // chunks
+
 __device__ inline double readlane_d(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
@@ -298,101 +314,142 @@ struct Ctx16 {
   bool valid, y_lds, z_lds, y_glob, z_glob;
 };
 
+constexpr int rof16(int r) { return (r >> 1) * 256 + (r & 1) * 64; }
+
+// a double known to be the same in every lane, as a scalar value
+__device__ inline double uniform_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// load from a wave-uniform base plus a per-lane unsigned byte offset, so
+// that the address stays a scalar base + 32-bit lane offset
+__device__ inline double ld_u(const double* base, unsigned lane_bytes) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + lane_bytes);
+}
+
+// halo cells i of the neighbouring tiles (or the farfield), for the waves
+// on the upwind edges of the tile
+__device__ __forceinline__ void load_halos16(const Ctx16& X, int i, int nx, unsigned lb,
+                                             double (&hy)[kR16], double (&hz)[kR16]) {
+  if (i >= nx || !(X.y_glob || X.z_glob)) return;
+  // a wave on one edge only reads the farfield row for the other direction
+  // (L2-resident) so that both register sets are always written
+  const double* ry = X.y_base + (size_t)i * X.y_step + X.cbase;
+  const double* rz = X.z_base + (size_t)i * X.z_step + X.cbase;
+#pragma unroll
+  for (int r = 0; r < kR16; ++r) {
+    hy[r] = ld_u(ry + rof16(r), lb);
+    hz[r] = ld_u(rz + rof16(r), lb);
+  }
+}
+
 template <int U>
-__device__ __forceinline__ void step16(const Step3Args& A, const Ctx16& X, int i,
-                                       double (&S)[4][4], double (*xch)[kTileWaves][4][kWave]) {
-  constexpr int R = 4;
-  constexpr int rof[4] = {0, 64, 256, 320};   // (r >> 1) * 256 + (r & 1) * 64
+__device__ __forceinline__ void step16(const Step3Args& A, const int* __restrict__ kind,
+                                       const double* __restrict__ mom, const Ctx16& X, int i,
+                                       double (&S)[2][kR16], double (&hy)[kR16], double (&hz)[kR16],
+                                       double (*xch)[kTileWaves][kR16][kWave]) {
+  constexpr int R = kR16;
   const int nx = A.nx, nvel = A.nvel;
   int lv = threadIdx.x & 63;
   asm volatile("" : "+v"(lv));
-  // halos of cell i (needed first), then own cell i+3 (the farfield past
-  // the end)
-  double hy[4], hz[4];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int o = X.cbase + rof[r] + lv;
-    hy[r] = X.y_glob ? X.y_base[(size_t)i * X.y_step + o] : 0.0;
-    hz[r] = X.z_glob ? X.z_base[(size_t)i * X.z_step + o] : 0.0;
-  }
-  double (&tgt)[4] = S[(U + 3) & 3];
-  if (i + 3 <= nx && X.valid) {
-    const double* row = i + 3 < nx ? X.own_base + (size_t)(i + 3) * nvel : A.ghost;
-#pragma unroll
-    for (int r = 0; r < R; ++r) tgt[r] = row[X.cbase + rof[r] + lv];
-  }
-  const double (&cur)[4] = S[U & 3];
-  const double (&nxt)[4] = S[(U + 1) & 3];
+  // publish cell i, then reuse its registers for cell i+2 (the farfield
+  // past the end); the update reads cell i back from the wave's own slot
+  double (&cur)[R] = S[U & 1];
+  const double (&nxt)[R] = S[(U + 1) & 1];
   const int s = i & 1;
+  const unsigned lb = (unsigned)lv * 8u;
 #pragma unroll
   for (int r = 0; r < R; ++r) xch[s][X.wave][r][lv] = cur[r];
+  if (i + 2 <= nx && X.valid) {
+    const double* row = (i + 2 < nx ? X.own_base + (size_t)(i + 2) * nvel : A.ghost) + X.cbase;
+#pragma unroll
+    for (int r = 0; r < R; ++r) cur[r] = ld_u(row + rof16(r), lb);
+  }
   __syncthreads();
   const int c = (int)(X.pencil + i);
-  if (X.valid && A.kind[c] == KIND_REGULAR) {
-    const double* mc = A.mom + 8 * (size_t)c;
-    const double Am = mc[0], inv2T = mc[4], nu = mc[5];
+  if (X.valid && kind[c] == KIND_REGULAR) {
+    const double* mc = mom + 8 * (size_t)c;
+    const double Am = uniform_d(mc[0]), inv2T = uniform_d(mc[4]), nu = uniform_d(mc[5]);
+    const double ux = uniform_d(mc[1]), uy = uniform_d(mc[2]), uz = uniform_d(mc[3]);
     const double vmin = A.vmin, dv = A.dv;
     const int g = lv >> 4;
-    const double ug = g == 0 ? mc[1] : (g == 1 ? mc[2] : mc[3]);
+    const double ug = g == 0 ? ux : (g == 1 ? uy : uz);
     const double vt = vnode3(vmin, dv, lv & 15) - ug;
     const double t = exp(-vt * vt * inv2T);
     const int p2a = X.sy * 8 + (lv >> 4);
     const double ex = __shfl(t, lv & 15, kWave);
     const double eya = __shfl(t, 16 + p2a, kWave), eyb = __shfl(t, 20 + p2a, kWave);
-    const double ez0 = readlane_d(t, 32 + X.p3b), ez1 = readlane_d(t, 33 + X.p3b);
     const double vx = vnode3(vmin, dv, lv & 15);
     const double vya = vnode3(vmin, dv, p2a), vyb = vnode3(vmin, dv, p2a + 4);
-    const double vz0 = vnode3(vmin, dv, X.p3b), vz1 = vnode3(vmin, dv, X.p3b + 1);
     const double ax = A.cxf * fabs(vx), aya = A.cyf * fabs(vya), ayb = A.cyf * fabs(vyb);
-    const double az0 = A.czf * fabs(vz0), az1 = A.czf * fabs(vz1);
     const double base = 1.0 - nu - ax;
     const double Ax = Am * ex;
     const double Exa = Ax * eya, Exb = Ax * eyb;
     const bool xpos = (lv & 15) >= 8;
-    double fn[4];
+    double* orow = A.out + (size_t)c * nvel + X.cbase;
+    double Aa = 0.0, Ab = 0.0, m3 = 0.0, m4z = 0.0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double ay = (r & 1) ? ayb : aya, az = (r >> 1) ? az1 : az0;
-      const double E = ((r & 1) ? Exb : Exa) * ((r >> 1) ? ez1 : ez0);
-      const double fx = xpos ? xch[s ^ 1][X.wave][r][lv] : nxt[r];
-      const double fy = X.y_lds ? xch[s][X.wy][r][lv] : hy[r];
-      const double fz = X.z_lds ? xch[s][X.wz][r][lv] : hz[r];
-      const double c0 = base - ay - az;
-      fn[r] = c0 * cur[r] + ax * fx + ay * fy + az * fz + nu * E;
+    for (int q = 0; q < kG16; ++q) {
+      const double ez = readlane_d(t, 32 + X.p3b + q);
+      const double vz = vnode3(vmin, dv, X.p3b + q);
+      const double az = A.czf * fabs(vz);
+      double Bq = 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = 2 * q + h;
+        const double ay = h ? ayb : aya;
+        const double E = (h ? Exb : Exa) * ez;
+        const double fx = xpos ? xch[s ^ 1][X.wave][r][lv] : nxt[r];
+        const double fy = X.y_lds ? xch[s][X.wy][r][lv] : hy[r];
+        const double fz = X.z_lds ? xch[s][X.wz][r][lv] : hz[r];
+        const double c0 = base - ay - az;
+        const double fn = c0 * xch[s][X.wave][r][lv] + ax * fx + ay * fy + az * fz + nu * E;
+        __builtin_nontemporal_store(
+            fn, reinterpret_cast<double*>(reinterpret_cast<char*>(orow + rof16(r)) + lb));
+        if (h) Ab += fn; else Aa += fn;
+        Bq += fn;
+      }
+      m3 += vz * Bq;
+      m4z += vz * vz * Bq;
     }
-    double* orow = A.out + (size_t)c * nvel + X.cbase + lv;
-#pragma unroll
-    for (int r = 0; r < R; ++r) __builtin_nontemporal_store(fn[r], orow + rof[r]);
-    const double A0 = fn[0] + fn[2], A1 = fn[1] + fn[3];
-    const double B0 = fn[0] + fn[1], B1 = fn[2] + fn[3];
-    const double s0 = A0 + A1;
+    const double s0 = Aa + Ab;
     double m[5];
     m[0] = s0;
     m[1] = vx * s0;
-    m[2] = vya * A0 + vyb * A1;
-    m[3] = vz0 * B0 + vz1 * B1;
-    m[4] = vx * vx * s0 + (vya * vya * A0 + vyb * vyb * A1) + (vz0 * vz0 * B0 + vz1 * vz1 * B1);
+    m[2] = vya * Aa + vyb * Ab;
+    m[3] = m3;
+    m[4] = vx * vx * s0 + (vya * vya * Aa + vyb * vyb * Ab) + m4z;
+    // halos of cell i+1 before the reduction
+    load_halos16(X, i + 1, nx, lb, hy, hz);
     const double tot = reduce5(m, lv);
-    if ((lv & 7) == 0 && lv < 40) A.part[((size_t)c * 16 + X.ch) * 5 + (lv >> 3)] = tot;
+    if ((lv & 7) == 0 && lv < 40) A.part[((size_t)c * kNCH16 + X.ch) * 5 + (lv >> 3)] = tot;
+  } else {
+    load_halos16(X, i + 1, nx, lb, hy, hz);
   }
 }
 
-__global__ void __launch_bounds__(1024) k_step3d16(const Step3Args A) {
-  __shared__ double xch[2][kTileWaves][4][kWave];
+__global__ void __launch_bounds__(1024) k_step3d16(const Step3Args A, const int* __restrict__ kind,
+                                                  const double* __restrict__ mom) {
+  constexpr int R = kR16;
+  __shared__ double xch[2][kTileWaves][R][kWave];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int b = blockIdx.x;
   const int logical = (b & 7) * A.per + (b >> 3);
   if (logical >= A.nblk) return;
   Ctx16 X;
-  X.ch = logical / A.ntiles;
-  const int tile = logical - X.ch * A.ntiles;
+  const int lch = logical / A.ntiles;
+  const int tile = logical - lch * A.ntiles;
+  X.ch = A.ch0 + lch;
   const int ty = wave & 3, tz = wave >> 2;
   const int tj = tile % A.ntj, tk = tile / A.ntj;
   const int j = tj * kTY + ty, k = tk * kTZ + tz;
   X.valid = j < A.ny && k < A.nz;
   X.sy = X.ch & 1;
-  X.p3b = (X.ch >> 1) * 2;
+  X.p3b = (X.ch >> 1) * kG16;
   X.wave = wave;
   X.cbase = X.p3b * 256 + X.sy * 128;
   const int dyu = X.sy ? -1 : 1, dzu = X.p3b >= 8 ? -1 : 1;
@@ -406,34 +463,29 @@ __global__ void __launch_bounds__(1024) k_step3d16(const Step3Args A) {
   const size_t pencil = (size_t)((X.valid ? k : 0) * A.ny + (X.valid ? j : 0)) * nx;
   X.pencil = pencil;
   X.own_base = A.in + pencil * nvel;
-  X.y_base = y_dom && X.valid ? A.in + (size_t)(k * A.ny + jy) * nx * nvel : A.ghost;
-  X.z_base = z_dom && X.valid ? A.in + (size_t)(kz * A.ny + j) * nx * nvel : A.ghost;
-  X.y_step = y_dom && X.valid ? nvel : 0;
-  X.z_step = z_dom && X.valid ? nvel : 0;
   X.y_glob = X.valid && !X.y_lds;
   X.z_glob = X.valid && !X.z_lds;
-  constexpr int rof[4] = {0, 64, 256, 320};
-  double S[4][4];
+  const bool yg = X.y_glob && y_dom, zg = X.z_glob && z_dom;
+  X.y_base = yg ? A.in + (size_t)(k * A.ny + jy) * nx * nvel : A.ghost;
+  X.z_base = zg ? A.in + (size_t)(kz * A.ny + j) * nx * nvel : A.ghost;
+  X.y_step = yg ? nvel : 0;
+  X.z_step = zg ? nvel : 0;
+  double S[2][R], hy[R], hz[R];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) { S[u][r] = 0.0; }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int o = X.cbase + rof[r] + lane;
-    // cells 0, 1, 2 (the farfield past the end); x-upwind of cell 0 is the farfield
-    if (X.valid) {
-      S[0][r] = X.own_base[o];
-      S[1][r] = 1 < nx ? X.own_base[(size_t)nvel + o] : A.ghost[o];
-      if (2 <= nx) S[2][r] = 2 < nx ? X.own_base[(size_t)2 * nvel + o] : A.ghost[o];
-    }
+  for (int r = 0; r < R; ++r) {
+    const int o = X.cbase + rof16(r) + lane;
+    // cells 0 and 1 (the farfield past the end); x-upwind of cell 0 and the
+    // halos of cell 0
+    S[0][r] = X.valid ? X.own_base[o] : 0.0;
+    S[1][r] = X.valid ? (1 < nx ? X.own_base[(size_t)nvel + o] : A.ghost[o]) : 0.0;
     xch[1][wave][r][lane] = X.valid ? A.ghost[o] : 0.0;
+    hy[r] = 0.0;
+    hz[r] = 0.0;
   }
-  for (int i = 0; i < nx; i += 4) {
-    step16<0>(A, X, i, S, xch);
-    if (i + 1 < nx) step16<1>(A, X, i + 1, S, xch);
-    if (i + 2 < nx) step16<2>(A, X, i + 2, S, xch);
-    if (i + 3 < nx) step16<3>(A, X, i + 3, S, xch);
+  load_halos16(X, 0, nx, (unsigned)lane * 8u, hy, hz);
+  for (int i = 0; i < nx; i += 2) {
+    step16<0>(A, kind, mom, X, i, S, hy, hz, xch);
+    if (i + 1 < nx) step16<1>(A, kind, mom, X, i + 1, S, hy, hz, xch);
   }
 }
 
@@ -738,12 +790,16 @@ int node_count(int nvel) {
   return N * N * N == nvel ? N : 0;
 }
 
-typedef void (*step3_fn)(const Step3Args);
+typedef void (*step3_fn)(const Step3Args, const int*, const double*);
 typedef void (*part3_fn)(Geo3D, const double*, double*, double, double);
 
 template <int N>
 void pick3(step3_fn* s, part3_fn* p, int* nch) {
-  if (s) *s = N == 16 ? k_step3d16 : k_step3d<N>;
+  if constexpr (N == 16) {
+    if (s) *s = k_step3d16;
+  } else {
+    if (s) *s = k_step3d<N>;
+  }
   if (p) *p = k_part3d<N>;
   if (nch) *nch = Chunk3<N>::NCH;
 }
@@ -876,13 +932,25 @@ hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
   A.nx = ctx->nx; A.ny = ctx->ny; A.nz = ctx->nz; A.nvel = ctx->nvel;
   A.ntj = (ctx->ny + kTY - 1) / kTY;
   A.ntiles = A.ntj * ((ctx->nz + kTZ - 1) / kTZ);
+#if CCDVM_CHUNK_LAUNCH
+  // one launch per velocity chunk: the tiles of a chunk run together and
+  // march along x in step, so that the edge cells a tile reads from its
+  // neighbours (same XCD, adjacent in the tile order) are still in L2
+  A.nblk = A.ntiles;
+  const int nlaunch = chunks3d(ctx->N);
+#else
   A.nblk = A.ntiles * chunks3d(ctx->N);
+  const int nlaunch = 1;
+#endif
   A.per = (A.nblk + 7) / 8;
   A.vmin = ctx->cfg.vmin;
   A.dv = ctx->dv;
   A.cxf = ctx->dt / ctx->dx; A.cyf = ctx->dt / ctx->dy; A.czf = ctx->dt / ctx->dz;
   prof_begin(ctx, 0);
-  fn<<<A.per * 8, 1024, 0, ctx->stream>>>(A);
+  for (int l = 0; l < nlaunch; ++l) {
+    A.ch0 = l;
+    fn<<<A.per * 8, 1024, 0, ctx->stream>>>(A, A.kind, A.mom);
+  }
   prof_end(ctx, 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
