@@ -33,8 +33,11 @@ WORKLOAD_TEXT = {
     "sphere128": "sphere128: 3D 128x64x64 cells on [0,1]x[0,0.5]^2, 16^3 velocities on [-6,6]^3, "
                  "sphere r=0.1, Kn {kn}, Mach 0.5, T_w 1, CFL 0.5, force every step",
 }
-KERNEL_SRC = os.path.join(ROOT, "paper_1503_04544_amd", "csrc", "step2d.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_regular2d_cyl512.json")
+# committed rocprofv3 counter summaries: workload -> (kernel source, summary)
+TRAFFIC = {
+    "cyl512": ("step2d.hip", "traffic_regular2d_cyl512.json"),
+    "sphere128": ("step3d.hip", "traffic_regular3d_sphere128.json"),
+}
 
 
 def log(msg):
@@ -46,15 +49,18 @@ def src_hash(path):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(workload):
     """HBM bytes per launch of the regular-cell kernel from the committed
     rocprofv3 counter summary, valid only for the kernel source it was taken on."""
+    if workload not in TRAFFIC:
+        return None
+    src, summary = TRAFFIC[workload]
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(os.path.join(ROOT, "profiles", summary)) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != src_hash(KERNEL_SRC):
+    if t.get("kernel_source_sha256_16") != src_hash(os.path.join(ROOT, "paper_1503_04544_amd", "csrc", src)):
         return None
     return t.get("bytes_per_launch")
 
@@ -200,7 +206,7 @@ def main():
     bytes_per_launch = n_regular * nvel * (32 if cfg.dim == 2 else 16)
     avg_s = reg_ms / max(reg_n, 1) / 1e3
     achieved = bytes_per_launch / avg_s / 1e9
-    traffic = measured_traffic() if args.workload == "cyl512" else None
+    traffic = measured_traffic(args.workload)
 
     out = {
         "metric": "cell-velocity updates/s",
