@@ -71,6 +71,7 @@ class Config:
     body: Body = field(default_factory=Body)
     steps: int = 1
     name: str = ""
+    maxwellian: str = "direct"  # "direct" moments or "conservative" (Newton) equilibrium
 
     @property
     def ncell(self) -> int:

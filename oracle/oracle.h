@@ -35,6 +35,7 @@ typedef struct {
   double mass, inertia;
   int motion;              /* 0 fixed 1 free rotation 2 imposed */
   double vel[3], omega;    /* rigid body velocity at t = 0 */
+  int maxwellian;          /* 0 direct moments, 1 conservative (Newton) */
 } orc_cfg;
 
 typedef struct orc2d orc2d;
@@ -70,6 +71,10 @@ void orc2d_body_state(const orc2d *o, double *state);
    0 = drag, 1 = torque of the final state; out = J, dJ/dT_w, dJ/dKn,
    dJ/du_x, dJ/du_y of the farfield velocity */
 int  orc2d_adjoint(orc2d *o, int nsteps, int objective, double *out);
+/* triplet (rho, ux, uy, T) of the equilibrium used by the relaxation of
+   one cell's (f, g): the direct moments, or the conservative solution;
+   returns the Newton iterations taken (0 for direct), -1 if no convergence */
+int  orc2d_equilibrium(const orc2d *o, const double *f, const double *g, double *out);
 int  orc_threads(void);
 
 typedef struct orc3d orc3d;
@@ -91,6 +96,9 @@ int  orc3d_step(orc3d *o, const double *F, double *Fo, double *diag);
 void orc3d_force(const orc3d *o, const double *Fm, double *diag);
 /* 14 moments per cell (see orc3d_moments) */
 void orc3d_moments(const orc3d *o, const double *F, double *out);
+/* triplet (rho, ux, uy, uz, T) of the equilibrium of one cell's F (direct
+   or conservative); returns the Newton iterations, -1 if no convergence */
+int  orc3d_equilibrium(const orc3d *o, const double *F, double *out);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,7 @@ class _Cfg(C.Structure):
                 ("body_kind", C.c_int), ("center", C.c_double * 3),
                 ("axes", C.c_double * 3), ("theta", C.c_double), ("t_wall", C.c_double),
                 ("mass", C.c_double), ("inertia", C.c_double), ("motion", C.c_int),
-                ("vel", C.c_double * 3), ("omega", C.c_double)]
+                ("vel", C.c_double * 3), ("omega", C.c_double), ("maxwellian", C.c_int)]
 
 
 def cfg_struct(cfg) -> _Cfg:
@@ -48,6 +48,7 @@ def cfg_struct(cfg) -> _Cfg:
     s.motion = _MOTION[b.motion]
     s.vel[:] = list(b.vel)
     s.omega = b.omega
+    s.maxwellian = {"direct": 0, "conservative": 1}[getattr(cfg, "maxwellian", "direct")]
     return s
 
 
@@ -74,6 +75,7 @@ def lib():
         _lib.orc2d_moments.argtypes = [P, P, P, P]
         _lib.orc_threads.restype = C.c_int
         _lib.orc2d_adjoint.argtypes = [P, C.c_int, C.c_int, P]
+        _lib.orc2d_equilibrium.argtypes = [P, P, P, P]
     return _lib
 
 
@@ -186,6 +188,14 @@ class Oracle2D:
             raise OracleError(f"oracle adjoint failed with status {st}")
         return out[0], out[1:]
 
+    def equilibrium(self, f1, g1):
+        """(rho, ux, uy, T) of the relaxation for one cell's (f, g) and the
+        Newton iterations taken (0: direct moments)."""
+        out = np.zeros(4)
+        it = lib().orc2d_equilibrium(self._h, _p(np.ascontiguousarray(f1, dtype=np.float64)),
+                                     _p(np.ascontiguousarray(g1, dtype=np.float64)), _p(out))
+        return out, it
+
     def moments(self, f, g):
         out = np.zeros((self.ncell, 9))
         lib().orc2d_moments(self._h, _p(np.ascontiguousarray(f)), _p(np.ascontiguousarray(g)), _p(out))
@@ -208,6 +218,7 @@ def _lib3():
         L.orc3d_step.argtypes = [P, P, P, P]
         L.orc3d_force.argtypes = [P, P, P]
         L.orc3d_moments.argtypes = [P, P, P]
+        L.orc3d_equilibrium.argtypes = [P, P, P]
         L._has3 = True
     return L
 
@@ -291,6 +302,13 @@ class Oracle3D:
         d = np.zeros(4)
         _lib3().orc3d_force(self._h, _p(np.ascontiguousarray(Fm)), _p(d))
         return d
+
+    def equilibrium(self, F1):
+        """(rho, ux, uy, uz, T) of the relaxation for one cell's F and the
+        Newton iterations taken (0: direct moments)."""
+        out = np.zeros(5)
+        it = _lib3().orc3d_equilibrium(self._h, _p(np.ascontiguousarray(F1, dtype=np.float64)), _p(out))
+        return out, it
 
     def moments(self, F):
         out = np.zeros((self.ncell, 14))

@@ -439,6 +439,98 @@ static void cell_moments(const orc2d *o, const double *f, const double *g,
   *T = (2.0 * E / r - (*ux * *ux + *uy * *uy)) / 3.0;
 }
 
+/* Small dense solve A x = b (Gaussian elimination, partial pivoting); A and
+   b are overwritten, x returned in b.  n <= 5. */
+static int solve_small(int n, double A[5][5], double *b) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < n; ++r)
+      if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+    if (A[piv][k] == 0.0) return -1;
+    if (piv != k) {
+      for (int c = 0; c < n; ++c) { double t = A[k][c]; A[k][c] = A[piv][c]; A[piv][c] = t; }
+      double t = b[k]; b[k] = b[piv]; b[piv] = t;
+    }
+    for (int r = k + 1; r < n; ++r) {
+      double m = A[r][k] / A[k][k];
+      for (int c = k; c < n; ++c) A[r][c] -= m * A[k][c];
+      b[r] -= m * b[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double s = b[k];
+    for (int c = k + 1; c < n; ++c) s -= A[k][c] * b[c];
+    b[k] = s / A[k][k];
+  }
+  return 0;
+}
+
+/* Conservative equilibrium (Section 3.1, the Newton algorithm of Titarev):
+   the triplet (rho, u, T) of the equilibrium pair (M, G = T/2 M) is the root
+   of  sum_p psi_p (M_p, G_p) w = sum_p psi_p (f_p, g_p) w  for the
+   collision invariants psi = (1, v_x, v_y, |v|^2/2 for M and 1 for G),
+   so that the discrete relaxation term conserves mass, momentum and energy
+   exactly.  Newton from the directly computed triplet; the Jacobian is the
+   sum of psi times the derivatives of (M, G) in (rho, u_x, u_y, T).
+   Stops when the step is below 1e-15 of (rho, sqrt T, T).  Returns the
+   iterations taken, -1 without convergence in 30 iterations. */
+static int conservative_triplet2(const orc2d *o, const double *f, const double *g,
+                                 double *x /* rho, ux, uy, T in/out */) {
+  int N = o->N;
+  double target[4] = {0, 0, 0, 0};
+  for (int p = 0; p < o->nvel; ++p) {
+    double vx = o->v[p % N], vy = o->v[p / N];
+    target[0] += f[p] * o->w;
+    target[1] += vx * f[p] * o->w;
+    target[2] += vy * f[p] * o->w;
+    target[3] += (0.5 * (vx * vx + vy * vy) * f[p] + g[p]) * o->w;
+  }
+  for (int it = 1; it <= 30; ++it) {
+    double r = x[0], ux = x[1], uy = x[2], T = x[3];
+    double R[5] = {0, 0, 0, 0, 0}, J[5][5];
+    memset(J, 0, sizeof(J));
+    for (int p = 0; p < o->nvel; ++p) {
+      double vx = o->v[p % N], vy = o->v[p / N];
+      double cx = vx - ux, cy = vy - uy;
+      double M = maxw2(r, ux, uy, T, vx, vy);
+      double dM[4] = {M / r, M * cx / T, M * cy / T, M * ((cx * cx + cy * cy) / (2.0 * T * T) - 1.0 / T)};
+      double psi[4] = {1.0, vx, vy, 0.5 * (vx * vx + vy * vy)};
+      for (int i = 0; i < 4; ++i) {
+        R[i] += psi[i] * M * o->w;
+        for (int j = 0; j < 4; ++j) J[i][j] += psi[i] * dM[j] * o->w;
+      }
+      /* energy carried by G = T/2 M */
+      R[3] += 0.5 * T * M * o->w;
+      for (int j = 0; j < 4; ++j) J[3][j] += 0.5 * T * dM[j] * o->w;
+      J[3][3] += 0.5 * M * o->w;
+    }
+    for (int i = 0; i < 4; ++i) R[i] -= target[i];
+    if (solve_small(4, J, R)) return -1;
+    for (int i = 0; i < 4; ++i) x[i] -= R[i];
+    double su = sqrt(fabs(x[3]));
+    if (fabs(R[0]) <= 1e-15 * fabs(x[0]) && fabs(R[1]) <= 1e-15 * su &&
+        fabs(R[2]) <= 1e-15 * su && fabs(R[3]) <= 1e-15 * fabs(x[3]))
+      return it;
+  }
+  return -1;
+}
+
+/* triplet of the relaxation of one cell: direct moments, or conservative */
+static int equilibrium2(const orc2d *o, const double *f, const double *g, double *rho,
+                        double *ux, double *uy, double *T) {
+  cell_moments(o, f, g, rho, ux, uy, T);
+  if (!o->cfg.maxwellian) return 0;
+  double x[4] = {*rho, *ux, *uy, *T};
+  int it = conservative_triplet2(o, f, g, x);
+  *rho = x[0]; *ux = x[1]; *uy = x[2]; *T = x[3];
+  return it;
+}
+
+int orc2d_equilibrium(const orc2d *o, const double *f, const double *g, double *out) {
+  int it = equilibrium2(o, f, g, &out[0], &out[1], &out[2], &out[3]);
+  return it;
+}
+
 /* wall velocity of the boundary point r, eq. (uwDD) */
 static void wall_velocity(const orc2d *o, double rx, double ry, double *uwx, double *uwy) {
   double ax = rx - o->c[0], ay = ry - o->c[1];
@@ -487,7 +579,9 @@ static void scheme_cv(const orc2d *o, const geo2d *G, const double *fm,
   const double *fc = fm + (size_t)m * nvel, *gc = gm + (size_t)m * nvel;
   double S = G->scv[m];
   double rho, ux, uy, T;
-  cell_moments(o, fc, gc, &rho, &ux, &uy, &T);
+  /* READING: with the conservative equilibrium the whole triplet, rho in
+     the relaxation time included, comes from the Newton solution */
+  equilibrium2(o, fc, gc, &rho, &ux, &uy, &T);
   int collide = o->cfg.kn > 0.0;
   double tau = collide ? tau_of(o, rho) : 1.0;
   /* transport residual R_p = sum over members of (F_x+ - F_x-) + (F_y+ - F_y-) + F_w */
@@ -966,6 +1060,7 @@ static void cv_sum(const orc2d *o, const geo2d *G, const double *a, double *L) {
    dJ/du_y (u = farfield velocity). Fixed bodies only. */
 int orc2d_adjoint(orc2d *o, int nsteps, int objective, double *out) {
   if (o->cfg.motion != 0 && o->cfg.body_kind != 0) return -1;
+  if (o->cfg.maxwellian) return -1;   /* transpose written for the direct triplet */
   int nvel = o->nvel, N = o->N;
   size_t tot = (size_t)o->ncell * nvel;
   const geo2d *G = &o->g[o->cur];

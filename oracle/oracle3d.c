@@ -338,6 +338,88 @@ static void moments3(const orc3d *o, const double *F, double *rho, double *u, do
   *T = (2.0 * E / r - (u[0] * u[0] + u[1] * u[1] + u[2] * u[2])) / 3.0;
 }
 
+/* dense solve A x = b, n <= 5 (Gaussian elimination, partial pivoting) */
+static int solve5(int n, double A[5][5], double *b) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < n; ++r)
+      if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+    if (A[piv][k] == 0.0) return -1;
+    if (piv != k) {
+      for (int c = 0; c < n; ++c) { double t = A[k][c]; A[k][c] = A[piv][c]; A[piv][c] = t; }
+      double t = b[k]; b[k] = b[piv]; b[piv] = t;
+    }
+    for (int r = k + 1; r < n; ++r) {
+      double m = A[r][k] / A[k][k];
+      for (int c = k; c < n; ++c) A[r][c] -= m * A[k][c];
+      b[r] -= m * b[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double s = b[k];
+    for (int c = k + 1; c < n; ++c) s -= A[k][c] * b[c];
+    b[k] = s / A[k][k];
+  }
+  return 0;
+}
+
+/* Conservative equilibrium (Section 3.1, Newton algorithm of Titarev) in
+   3D: (rho, u, T) such that the discrete moments of the sampled Maxwellian
+   for psi = (1, v, |v|^2/2) equal those of F.  Newton from the direct
+   moments, stop when the step is below 1e-15 of (rho, sqrt T, T). */
+static int conservative_triplet3(const orc3d *o, const double *F, double *x /* rho u(3) T */) {
+  int N = o->N;
+  double target[5] = {0, 0, 0, 0, 0};
+  for (int p = 0; p < o->nvel; ++p) {
+    double v[3] = {o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]};
+    target[0] += F[p] * o->w;
+    for (int d = 0; d < 3; ++d) target[1 + d] += v[d] * F[p] * o->w;
+    target[4] += 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) * F[p] * o->w;
+  }
+  for (int it = 1; it <= 30; ++it) {
+    double R[5] = {0, 0, 0, 0, 0}, J[5][5];
+    memset(J, 0, sizeof(J));
+    double u[3] = {x[1], x[2], x[3]}, T = x[4];
+    for (int p = 0; p < o->nvel; ++p) {
+      double v[3] = {o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]};
+      double c[3] = {v[0] - u[0], v[1] - u[1], v[2] - u[2]};
+      double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+      double M = maxw3(x[0], u, T, v[0], v[1], v[2]);
+      double dM[5] = {M / x[0], M * c[0] / T, M * c[1] / T, M * c[2] / T,
+                      M * (c2 / (2.0 * T * T) - 1.5 / T)};
+      double psi[5] = {1.0, v[0], v[1], v[2], 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2])};
+      for (int i = 0; i < 5; ++i) {
+        R[i] += psi[i] * M * o->w;
+        for (int j = 0; j < 5; ++j) J[i][j] += psi[i] * dM[j] * o->w;
+      }
+    }
+    for (int i = 0; i < 5; ++i) R[i] -= target[i];
+    if (solve5(5, J, R)) return -1;
+    for (int i = 0; i < 5; ++i) x[i] -= R[i];
+    double su = sqrt(fabs(x[4]));
+    if (fabs(R[0]) <= 1e-15 * fabs(x[0]) && fabs(R[1]) <= 1e-15 * su && fabs(R[2]) <= 1e-15 * su &&
+        fabs(R[3]) <= 1e-15 * su && fabs(R[4]) <= 1e-15 * fabs(x[4]))
+      return it;
+  }
+  return -1;
+}
+
+static int equilibrium3(const orc3d *o, const double *F, double *rho, double *u, double *T) {
+  moments3(o, F, rho, u, T);
+  if (!o->cfg.maxwellian) return 0;
+  double x[5] = {*rho, u[0], u[1], u[2], *T};
+  int it = conservative_triplet3(o, F, x);
+  *rho = x[0]; u[0] = x[1]; u[1] = x[2]; u[2] = x[3]; *T = x[4];
+  return it;
+}
+
+int orc3d_equilibrium(const orc3d *o, const double *F, double *out) {
+  double u[3];
+  int it = equilibrium3(o, F, &out[0], u, &out[4]);
+  out[1] = u[0]; out[2] = u[1]; out[3] = u[2];
+  return it;
+}
+
 /* scheme (eq-schema3D) for control volume m, fixed geometry */
 static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
   int nvel = o->nvel, N = o->N, nx = o->nx, ny = o->ny, nz = o->nz;
@@ -346,7 +428,9 @@ static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
   double uin[3] = {in[1], in[2], in[3]};
   double Tw = o->cfg.t_wall, zero[3] = {0, 0, 0};
   double rho, u[3], T;
-  moments3(o, fc, &rho, u, &T);
+  /* READING: conservative equilibrium -> the whole triplet, rho in tau
+     included, from the Newton solution */
+  equilibrium3(o, fc, &rho, u, &T);
   int collide = o->cfg.kn > 0.0;
   double tau = collide ? sqrt(M_PI) / 2.0 * (1.0 / rho) * o->cfg.kn * o->cfg.lref / sqrt(2.0) : 1.0;
   double V = o->vcv[m];
