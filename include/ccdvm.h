@@ -64,6 +64,15 @@ typedef enum {
 enum { CC_BODY_NONE = 0, CC_BODY_CIRCLE = 1, CC_BODY_ELLIPSE = 2,
        CC_BODY_CAVITY = 3, CC_BODY_HALFPLANE = 4, CC_BODY_SPHERE = 5 };
 enum { CC_MOTION_FIXED = 0, CC_MOTION_FREE_ROTATION = 1, CC_MOTION_IMPOSED = 2 };
+/* Equilibrium of the relaxation term: the Maxwellian of the directly
+ * computed moments (eq. MacroscopicDDv), or the conservative one of
+ * Section 3.1, whose triplet (rho, u, T) solves, by Newton iterations from
+ * the direct moments, "discrete mass, momentum and energy of the sampled
+ * Maxwellian (and of T/2 M in 2D) = those of the state", so that the
+ * discrete relaxation conserves them exactly.  The whole triplet, rho in the
+ * relaxation time included, comes from that solution.  A cell whose
+ * iteration does not converge in 50 steps keeps the direct triplet. */
+enum { CC_MAXW_DIRECT = 0, CC_MAXW_CONSERVATIVE = 1 };
 
 /* Flow set-up.  dim = 2 selects the reduced plane-flow model with the two
  * distributions f, g (Section 2.2); dim = 3 the full model with F
@@ -80,6 +89,8 @@ typedef struct {
   double kn, lref;
   double cfl, dt;
   double inflow[5];
+  int maxwellian;         /* CC_MAXW_DIRECT or CC_MAXW_CONSERVATIVE (fixed bodies,
+                             no adjoint or batch) */
 } cc_config;
 
 /* Obstacle given by an analytic signed distance, gas side positive

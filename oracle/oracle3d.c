@@ -366,7 +366,8 @@ static int solve5(int n, double A[5][5], double *b) {
 /* Conservative equilibrium (Section 3.1, Newton algorithm of Titarev) in
    3D: (rho, u, T) such that the discrete moments of the sampled Maxwellian
    for psi = (1, v, |v|^2/2) equal those of F.  Newton from the direct
-   moments, stop when the step is below 1e-15 of (rho, sqrt T, T). */
+   moments; once a step is below 1e-13 of (rho, sqrt T, T) one more step is
+   taken and the iteration stops; -1 without convergence in 50 iterations. */
 static int conservative_triplet3(const orc3d *o, const double *F, double *x /* rho u(3) T */) {
   int N = o->N;
   double target[5] = {0, 0, 0, 0, 0};
@@ -376,7 +377,8 @@ static int conservative_triplet3(const orc3d *o, const double *F, double *x /* r
     for (int d = 0; d < 3; ++d) target[1 + d] += v[d] * F[p] * o->w;
     target[4] += 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) * F[p] * o->w;
   }
-  for (int it = 1; it <= 30; ++it) {
+  int polish = 0;
+  for (int it = 1; it <= 50; ++it) {
     double R[5] = {0, 0, 0, 0, 0}, J[5][5];
     memset(J, 0, sizeof(J));
     double u[3] = {x[1], x[2], x[3]}, T = x[4];
@@ -396,10 +398,11 @@ static int conservative_triplet3(const orc3d *o, const double *F, double *x /* r
     for (int i = 0; i < 5; ++i) R[i] -= target[i];
     if (solve5(5, J, R)) return -1;
     for (int i = 0; i < 5; ++i) x[i] -= R[i];
+    if (polish) return it;
     double su = sqrt(fabs(x[4]));
-    if (fabs(R[0]) <= 1e-15 * fabs(x[0]) && fabs(R[1]) <= 1e-15 * su && fabs(R[2]) <= 1e-15 * su &&
-        fabs(R[3]) <= 1e-15 * su && fabs(R[4]) <= 1e-15 * fabs(x[4]))
-      return it;
+    if (fabs(R[0]) <= 1e-13 * fabs(x[0]) && fabs(R[1]) <= 1e-13 * su && fabs(R[2]) <= 1e-13 * su &&
+        fabs(R[3]) <= 1e-13 * su && fabs(R[4]) <= 1e-13 * fabs(x[4]))
+      polish = 1;
   }
   return -1;
 }
@@ -409,7 +412,8 @@ static int equilibrium3(const orc3d *o, const double *F, double *rho, double *u,
   if (!o->cfg.maxwellian) return 0;
   double x[5] = {*rho, u[0], u[1], u[2], *T};
   int it = conservative_triplet3(o, F, x);
-  *rho = x[0]; u[0] = x[1]; u[1] = x[2]; u[2] = x[3]; *T = x[4];
+  /* READING: a cell whose iteration does not converge keeps the direct triplet */
+  if (it > 0) { *rho = x[0]; u[0] = x[1]; u[1] = x[2]; u[2] = x[3]; *T = x[4]; }
   return it;
 }
 

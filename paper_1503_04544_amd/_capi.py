@@ -23,7 +23,8 @@ class cc_config(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("lo", C.c_double * 3),
                 ("hi", C.c_double * 3), ("nv", C.c_int), ("vmin", C.c_double),
                 ("vmax", C.c_double), ("kn", C.c_double), ("lref", C.c_double),
-                ("cfl", C.c_double), ("dt", C.c_double), ("inflow", C.c_double * 5)]
+                ("cfl", C.c_double), ("dt", C.c_double), ("inflow", C.c_double * 5),
+                ("maxwellian", C.c_int)]
 
 
 class cc_body(C.Structure):
@@ -97,6 +98,7 @@ def make_config(cfg) -> cc_config:
     c.vmin, c.vmax = cfg.vmin, cfg.vmax
     c.kn, c.lref, c.cfl, c.dt = cfg.kn, cfg.lref, cfg.cfl, cfg.dt
     c.inflow[:] = [float(x) for x in cfg.inflow]
+    c.maxwellian = {"direct": 0, "conservative": 1}[getattr(cfg, "maxwellian", "direct")]
     return c
 
 

@@ -205,6 +205,10 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
     return reject("moving bodies must be circles or ellipses");
   if (body->motion == CC_MOTION_FREE_ROTATION && !(body->inertia > 0.0))
     return reject("inertia must be > 0");
+  if (c.maxwellian != CC_MAXW_DIRECT && c.maxwellian != CC_MAXW_CONSERVATIVE)
+    return reject("unknown maxwellian mode");
+  if (c.maxwellian == CC_MAXW_CONSERVATIVE && body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_NONE)
+    return reject("the conservative equilibrium is available for fixed bodies");
   ctx->dim = c.dim;
   ctx->nx = c.n[0]; ctx->ny = c.n[1]; ctx->nz = c.dim == 3 ? c.n[2] : 1;
   long long ncell = (long long)ctx->nx * ctx->ny * ctx->nz;
@@ -566,6 +570,8 @@ cc_status cc_adjoint(cc_ctx* ctx, int nsteps, int ckpt_every, int objective, voi
     return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   if (ctx->dim != 2 || is_moving(ctx)) return fail(ctx, CC_EINVAL, "the adjoint covers 2D fixed bodies");
+  if (ctx->cfg.maxwellian != CC_MAXW_DIRECT)
+    return fail(ctx, CC_EINVAL, "the adjoint is written for the direct equilibrium");
   if ((uintptr_t)pool % kAlign) return fail(ctx, CC_EINVAL, "pool must be 256-byte aligned");
   cc_status st = cc_init_maxwellian(ctx);
   if (st != CC_OK) return st;
@@ -651,12 +657,13 @@ cc_status cc_batch_create(cc_ctx* const* ctxs, int n, cc_batch** out) {
   if (!b) return CC_ENOMEM;
   for (int i = 0; i < n; ++i) {
     cc_ctx* c = ctxs[i];
-    bool ok = c && c->bound && c->dim == 2 && !is_moving(c) && batch_supported_nch(batch_group_nch(c));
+    bool ok = c && c->bound && c->dim == 2 && !is_moving(c) && c->cfg.maxwellian == CC_MAXW_DIRECT &&
+              batch_supported_nch(batch_group_nch(c));
     for (int k = 0; k < i && ok; ++k) ok = ctxs[k] != c;
     if (ok && i > 0) ok = c->stream == ctxs[0]->stream;
     if (!ok) {
-      fprintf(stderr, "ccdvm: batch instance %d must be a distinct bound 2D fixed-body context on the "
-                      "stream of instance 0\n", i);
+      fprintf(stderr, "ccdvm: batch instance %d must be a distinct bound 2D fixed-body context "
+                      "(direct equilibrium) on the stream of instance 0\n", i);
       delete b;
       return CC_EINVAL;
     }

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "ccdvm_impl.h"
+#include "equilibrium.h"
 
 namespace ccdvm {
 namespace {
@@ -672,6 +673,24 @@ __global__ void __launch_bounds__(256) k_reduce2d(Geo2D G, const double* __restr
   }
 }
 
+// Conservative equilibrium (Section 3.1) of every control volume of the
+// current state: replaces the direct moments (rho, u, T) held for the next
+// relaxation by the Newton solution; one thread per cell.
+__global__ void __launch_bounds__(256) k_newton2d(Geo2D G, double* __restrict__ mom, double vmin,
+                                                 double dv) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.ncell) return;
+  const int kd = G.kind[c];
+  if (kd != KIND_REGULAR && kd != KIND_IRREGULAR) return;
+  double* m = mom + 4 * (size_t)c;
+  const double rho = m[0], ux = m[1], uy = m[2], T = m[3];
+  const double target[4] = {rho, rho * ux, rho * uy, 0.5 * rho * (3.0 * T + ux * ux + uy * uy)};
+  double x[4] = {rho, ux, uy, T};
+  if (conservative_triplet_2d(x, target, vmin, dv, G.N)) {
+    m[0] = x[0]; m[1] = x[1]; m[2] = x[2]; m[3] = x[3];
+  }
+}
+
 StepParams params2d(const cc_ctx* ctx) {
   StepParams P;
   P.vmin = ctx->cfg.vmin;
@@ -1235,6 +1254,11 @@ hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_forc
   A.red_force = prev_force_row;
   A.red_mass = cur_mass_row;
   dim3 grid(A.tile_base + A.ntiles_pad);
+  if (ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE) {
+    prof_begin(ctx, 4);
+    k_newton2d<<<(ctx->ncell + 255) / 256, 256, 0, ctx->stream>>>(ctx->g2, ctx->s.mom, P.vmin, P.dv);
+    prof_end(ctx, 4);
+  }
   if (A.n_cut > 0) {
     prof_begin(ctx, 1);
     k_cutstep2d<<<A.n_cut, 256, 0, ctx->stream>>>(ctx->g2, A, P);

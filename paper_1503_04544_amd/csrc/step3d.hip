@@ -25,6 +25,7 @@
 #include <math.h>
 
 #include "ccdvm_impl.h"
+#include "equilibrium.h"
 
 namespace ccdvm {
 namespace {
@@ -523,7 +524,9 @@ __global__ void __launch_bounds__(256) k_part3d(Geo3D G, const double* __restric
 
 struct Mom3Params {
   double w, dt, tau_coef, vol;
-  int nch;
+  double vmin, dv;
+  int nch, N;
+  int conservative;     // conservative equilibrium (Section 3.1)
 };
 
 // moments of the regular cells from the chunk sums (eq. MacroscopicTD):
@@ -544,11 +547,18 @@ __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict
     const double ux = s[1] * P.w / rho, uy = s[2] * P.w / rho, uz = s[3] * P.w / rho;
     const double en = 0.5 * s[4] * P.w;
     const double T = (2.0 * en / rho - (ux * ux + uy * uy + uz * uz)) / 3.0;
+    double x[5] = {rho, ux, uy, uz, T};
+    if (P.conservative) {
+      const double target[5] = {rho, s[1] * P.w, s[2] * P.w, s[3] * P.w, en};
+      if (!conservative_triplet_3d(x, target, P.vmin, P.dv, P.N)) {
+        x[0] = rho; x[1] = ux; x[2] = uy; x[3] = uz; x[4] = T;
+      }
+    }
     double* mo = mom + 8 * (size_t)c;
-    mo[0] = rho / pow(2.0 * M_PI * T, 1.5);
-    mo[1] = ux; mo[2] = uy; mo[3] = uz;
-    mo[4] = 0.5 / T;
-    mo[5] = P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
+    mo[0] = x[0] / pow(2.0 * M_PI * x[4], 1.5);
+    mo[1] = x[1]; mo[2] = x[2]; mo[3] = x[3];
+    mo[4] = 0.5 / x[4];
+    mo[5] = P.tau_coef > 0.0 ? P.dt * x[0] / P.tau_coef : 0.0;
     mo[6] = rho;
     ms = P.vol * rho;
   }
@@ -559,6 +569,7 @@ __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict
 struct Cut3Params {
   double vmin, dv, w, dt, tau_coef, t_wall;
   int write_state;
+  int conservative;     // conservative equilibrium (Section 3.1)
 };
 
 __device__ inline double maxw3(double rho, double ux, double uy, double uz, double T, double vx,
@@ -593,9 +604,17 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
   }
   s0 = block_sum(s0, lds); s1 = block_sum(s1, lds); s2 = block_sum(s2, lds);
   s3 = block_sum(s3, lds); s4 = block_sum(s4, lds);
-  const double rho = s0 * P.w, ux = s1 * P.w / rho, uy = s2 * P.w / rho, uz = s3 * P.w / rho;
-  const double T = (2.0 * (0.5 * s4 * P.w) / rho - (ux * ux + uy * uy + uz * uz)) / 3.0;
-  const double nu = P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
+  const double rho = s0 * P.w;
+  double eq[5] = {rho, s1 * P.w / rho, s2 * P.w / rho, s3 * P.w / rho, 0.0};
+  eq[4] = (2.0 * (0.5 * s4 * P.w) / rho - (eq[1] * eq[1] + eq[2] * eq[2] + eq[3] * eq[3])) / 3.0;
+  if (P.conservative) {
+    const double target[5] = {rho, s1 * P.w, s2 * P.w, s3 * P.w, 0.5 * s4 * P.w};
+    double x[5] = {eq[0], eq[1], eq[2], eq[3], eq[4]};
+    if (conservative_triplet_3d(x, target, P.vmin, P.dv, N))
+      for (int k = 0; k < 5; ++k) eq[k] = x[k];
+  }
+  const double ux = eq[1], uy = eq[2], uz = eq[3], T = eq[4];
+  const double nu = P.tau_coef > 0.0 ? P.dt * eq[0] / P.tau_coef : 0.0;
   const double V = G.vcv[m];
   const double Tw = P.t_wall;
   double phiw[kMaxMembers];
@@ -649,7 +668,7 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
       }
     }
     if (P.write_state) {
-      const double E = nu != 0.0 ? maxw3(rho, ux, uy, uz, T, v[0], v[1], v[2]) : 0.0;
+      const double E = nu != 0.0 ? maxw3(eq[0], ux, uy, uz, T, v[0], v[1], v[2]) : 0.0;
       const double fn = fo - P.dt / V * Rs + nu * (E - fo);
       for (int t = 0; t < nm; ++t) out[(size_t)G.mem[b + t] * nvel + p] = fn;
     }
@@ -829,7 +848,11 @@ hipError_t run_mom3d(cc_ctx* ctx) {
   P.dt = ctx->dt;
   P.tau_coef = tau_coef(ctx);
   P.vol = ctx->dx * ctx->dy * ctx->dz;
+  P.vmin = ctx->cfg.vmin;
+  P.dv = ctx->dv;
   P.nch = chunks3d(ctx->N);
+  P.N = ctx->N;
+  P.conservative = ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE;
   prof_begin(ctx, 4);
   k_mom3d<<<mom_blocks(ctx), 256, 0, ctx->stream>>>(ctx->g3, ctx->s.part, ctx->s.mom, ctx->s.mpart, P);
   prof_end(ctx, 4);
@@ -845,6 +868,7 @@ Cut3Params cut_params(const cc_ctx* ctx, int write) {
   P.tau_coef = tau_coef(ctx);
   P.t_wall = ctx->body.t_wall;
   P.write_state = write;
+  P.conservative = ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE;
   return P;
 }
 
