@@ -141,6 +141,9 @@ def main():
     ap.add_argument("--workload", default="cyl512", choices=["cyl512", "ellipse256", "cyl32", "sphere128", "batch"],
                     help="cyl512 (default, the headline line) | ellipse256 (moving body) | cyl32 | "
                          "sphere128 (3D)")
+    ap.add_argument("--maxwellian", default="direct", choices=["direct", "conservative"],
+                    help="equilibrium of the relaxation: direct moments (default) or the conservative "
+                         "Newton triplet")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=40,
@@ -169,7 +172,7 @@ def main():
     if args.workload == "batch":
         return bench_batch(args)
 
-    cfg = workload(args.workload, kn=args.kn)
+    cfg = workload(args.workload, kn=args.kn).with_(maxwellian=args.maxwellian)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     s = Solver(cfg, device=dev)
@@ -224,6 +227,7 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload].format(kn=cfg.kn),
                    "cells": cfg.ncell, "active_cells": active, "velocities": nvel,
                    "cut_control_volumes": n_irr, "merged_cells": n_mem, "dt": s.dt,
+                   "maxwellian": args.maxwellian,
                    "drag_last_step": drag_last},
         "roofline": {"bound": "hbm", "kernel": "k_step2d" if cfg.dim == 2 else "k_step3d",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -234,9 +238,11 @@ def main():
                      "reduce_kernel_avg_us": round(red_ms / max(red_n, 1) * 1e3, 2),
                      "merge_kernel_avg_us": round(mrg_ms / max(mrg_n, 1) * 1e3, 2)},
     }
-    if cfg.dim == 3:
-        out["roofline"]["moment_kernel_avg_us"] = round(mom_ms / max(mom_n, 1) * 1e3, 2)
-    if args.workload == "cyl512" and args.adjoint_steps > 0:
+    if cfg.dim == 3 or args.maxwellian == "conservative":
+        # 3D: moments from the chunk sums (and the Newton triplet);
+        # 2D conservative: the Newton pass between steps
+        out["roofline"]["between_steps_kernel_avg_us"] = round(mom_ms / max(mom_n, 1) * 1e3, 2)
+    if args.workload == "cyl512" and args.adjoint_steps > 0 and args.maxwellian == "direct":
         # adjoint over the same workload: forward alone vs forward with
         # checkpoints + recomputation + adjoint sweep (cc_adjoint)
         na, ka = args.adjoint_steps, args.adjoint_ckpt

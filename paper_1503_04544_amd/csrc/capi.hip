@@ -331,12 +331,25 @@ cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scr
 
 // make the current state ready for a step: moments valid, control volumes merged
 static cc_status prepare(cc_ctx* ctx) {
+  if (ctx->dim == 3) {
+    // 3D moment sums are taken of the merged control-volume values
+    if (!ctx->merged) {
+      HIPCHK(ctx, launch_merge_3d(ctx), "merge");
+      ctx->merged = true;
+      ctx->mom_valid = false;
+    }
+    if (!ctx->mom_valid) {
+      HIPCHK(ctx, launch_moments_all_3d(ctx), "moments");
+      ctx->mom_valid = true;
+    }
+    return CC_OK;
+  }
   if (!ctx->mom_valid) {
-    HIPCHK(ctx, ctx->dim == 2 ? launch_moments_all_2d(ctx) : launch_moments_all_3d(ctx), "moments");
+    HIPCHK(ctx, launch_moments_all_2d(ctx), "moments");
     ctx->mom_valid = true;
   }
   if (!ctx->merged) {
-    HIPCHK(ctx, ctx->dim == 2 ? launch_merge_2d(ctx) : launch_merge_3d(ctx), "merge");
+    HIPCHK(ctx, launch_merge_2d(ctx), "merge");
     ctx->merged = true;
   }
   return CC_OK;

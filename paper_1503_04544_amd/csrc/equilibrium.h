@@ -25,18 +25,41 @@ struct AxisSums {
   double dT[3];   // dP_k/dT, k = 0..2
 };
 
+// Along the uniform grid X_p = exp(-(v_p - u)^2/(2T)) obeys X_{p+1} = X_p r_p
+// with r_{p+1} = r_p q, q = exp(-dv^2/T) (and the same downwards with the
+// mirrored ratio), so each axis needs four exponentials instead of N.  The
+// walk starts at the node nearest to u and goes outwards, where X only
+// decreases, so a cold gas underflows to zero without an overflowing ratio.
 __host__ __device__ inline void axis_sums(double vmin, double dv, int N, double u, double T, AxisSums& a) {
   double P[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const double inv2T = 0.5 / T;
-  for (int p = 0; p < N; ++p) {
+  int p0 = (int)floor((u - vmin) / dv);
+  p0 = p0 < 0 ? 0 : (p0 > N - 1 ? N - 1 : p0);
+  const double c0 = vmin + (p0 + 0.5) * dv - u;
+  const double X0 = exp(-c0 * c0 * inv2T);
+  const double q = exp(-dv * dv / T);
+  auto add = [&](int p, double X) {
     const double v = vmin + (p + 0.5) * dv;
-    const double c = v - u;
-    double t = exp(-c * c * inv2T) * dv;
+    double t = X * dv;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       P[k] += t;
       t *= v;
     }
+  };
+  add(p0, X0);
+  double X = X0, r = exp(-(2.0 * c0 * dv + dv * dv) * inv2T);
+  for (int p = p0 + 1; p < N; ++p) {
+    X *= r;
+    r *= q;
+    add(p, X);
+  }
+  X = X0;
+  r = exp((2.0 * c0 * dv - dv * dv) * inv2T);
+  for (int p = p0 - 1; p >= 0; --p) {
+    X *= r;
+    r *= q;
+    add(p, X);
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) a.P[k] = P[k];

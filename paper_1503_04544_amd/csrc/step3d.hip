@@ -490,15 +490,15 @@ __global__ void __launch_bounds__(1024) k_step3d16(const Step3Args A, const int*
   }
 }
 
-// partial moments of the current state, per regular cell and chunk (one
-// wave per cell)
+// partial moments of the current (merged) state, per control-volume master
+// and chunk (one wave per cell)
 template <int N>
 __global__ void __launch_bounds__(256) k_part3d(Geo3D G, const double* __restrict__ in,
                                                double* __restrict__ part, double vmin, double dv) {
   using C = Chunk3<N>;
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (c >= G.ncell || G.kind[c] != KIND_REGULAR) return;
+  if (c >= G.ncell || (G.kind[c] != KIND_REGULAR && G.kind[c] != KIND_IRREGULAR)) return;
   const double* row = in + (size_t)c * G.nvel;
   for (int ch = 0; ch < C::NCH; ++ch) {
     const int sy = ch & 1, p3b = (ch >> 1) * C::G3;
@@ -529,16 +529,18 @@ struct Mom3Params {
   int conservative;     // conservative equilibrium (Section 3.1)
 };
 
-// moments of the regular cells from the chunk sums (eq. MacroscopicTD):
-// rho, u, T = (2E/rho - |u|^2)/3, and the BGK coefficients; block partials
-// of the mass sum_c V_c rho_c
+// moments of every control volume from its chunk sums (eq. MacroscopicTD):
+// rho, u, T = (2E/rho - |u|^2)/3 (or the conservative triplet), the
+// relaxation record, and block partials of the mass sum_m V_m rho_m
+template <bool CONS>
 __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict__ part,
                                               double* __restrict__ mom, double* __restrict__ mpart,
                                               Mom3Params P) {
   __shared__ double lds[4];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   double ms = 0.0;
-  if (c < G.ncell && G.kind[c] == KIND_REGULAR) {
+  const int kd = c < G.ncell ? G.kind[c] : KIND_SOLID;
+  if (kd == KIND_REGULAR || kd == KIND_IRREGULAR) {
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double* pp = part + (size_t)c * P.nch * 5;
     for (int ch = 0; ch < P.nch; ++ch)
@@ -548,7 +550,7 @@ __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict
     const double en = 0.5 * s[4] * P.w;
     const double T = (2.0 * en / rho - (ux * ux + uy * uy + uz * uz)) / 3.0;
     double x[5] = {rho, ux, uy, uz, T};
-    if (P.conservative) {
+    if (CONS) {
       const double target[5] = {rho, s[1] * P.w, s[2] * P.w, s[3] * P.w, en};
       if (!conservative_triplet_3d(x, target, P.vmin, P.dv, P.N)) {
         x[0] = rho; x[1] = ux; x[2] = uy; x[3] = uz; x[4] = T;
@@ -560,7 +562,7 @@ __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict
     mo[4] = 0.5 / x[4];
     mo[5] = P.tau_coef > 0.0 ? P.dt * x[0] / P.tau_coef : 0.0;
     mo[6] = rho;
-    ms = P.vol * rho;
+    ms = (kd == KIND_REGULAR ? P.vol : G.vcv[c]) * rho;
   }
   ms = block_sum(ms, lds);
   if (threadIdx.x == 0) mpart[blockIdx.x] = ms;
@@ -581,11 +583,14 @@ __device__ inline double maxw3(double rho, double ux, double uy, double uz, doub
 // One control volume that is cut or owns merged cells: wall density of each
 // wall face (zero net mass flux, Section 5.1), fluxes through the six
 // Cartesian faces and the wall face of every member, explicit update with
-// relaxation, redistribution to the members; wall stress -> force and the
-// mass of the state at t^n.  write_state == 0: force and mass only.
+// relaxation toward the Maxwellian of the control volume's record (built by
+// k_mom3d), redistribution to the members, the moment sums of the new value
+// (chunk slot 0) for the next record; wall stress -> force of the state at
+// t^n.  write_state == 0: force only.
 __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict__ in,
                                               double* __restrict__ out, double* __restrict__ fslot,
-                                              double* __restrict__ mpart, Cut3Params P) {
+                                              const double* __restrict__ mom, double* __restrict__ part,
+                                              int nch, Cut3Params P) {
   __shared__ double lds[4];
   const int tid = threadIdx.x, nth = blockDim.x;
   const int q = blockIdx.x;
@@ -593,28 +598,8 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
   const int b = G.mptr[q], nm = G.mptr[q + 1] - b;
   const int N = G.N, nvel = G.nvel, nx = G.nx, ny = G.ny, nz = G.nz;
   const double* own = in + (size_t)m * nvel;
-  // moments of the control volume's value
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
-  for (int p = tid; p < nvel; p += nth) {
-    const double vx = vnode3(P.vmin, P.dv, p % N), vy = vnode3(P.vmin, P.dv, (p / N) % N),
-                 vz = vnode3(P.vmin, P.dv, p / (N * N));
-    const double f = own[p];
-    s0 += f; s1 += vx * f; s2 += vy * f; s3 += vz * f;
-    s4 += (vx * vx + vy * vy + vz * vz) * f;
-  }
-  s0 = block_sum(s0, lds); s1 = block_sum(s1, lds); s2 = block_sum(s2, lds);
-  s3 = block_sum(s3, lds); s4 = block_sum(s4, lds);
-  const double rho = s0 * P.w;
-  double eq[5] = {rho, s1 * P.w / rho, s2 * P.w / rho, s3 * P.w / rho, 0.0};
-  eq[4] = (2.0 * (0.5 * s4 * P.w) / rho - (eq[1] * eq[1] + eq[2] * eq[2] + eq[3] * eq[3])) / 3.0;
-  if (P.conservative) {
-    const double target[5] = {rho, s1 * P.w, s2 * P.w, s3 * P.w, 0.5 * s4 * P.w};
-    double x[5] = {eq[0], eq[1], eq[2], eq[3], eq[4]};
-    if (conservative_triplet_3d(x, target, P.vmin, P.dv, N))
-      for (int k = 0; k < 5; ++k) eq[k] = x[k];
-  }
-  const double ux = eq[1], uy = eq[2], uz = eq[3], T = eq[4];
-  const double nu = P.tau_coef > 0.0 ? P.dt * eq[0] / P.tau_coef : 0.0;
+  const double* rec = mom + 8 * (size_t)m;
+  const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4], nu = rec[5];
   const double V = G.vcv[m];
   const double Tw = P.t_wall;
   double phiw[kMaxMembers];
@@ -637,6 +622,7 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
   }
   double sx[kMaxMembers], sy[kMaxMembers], sz[kMaxMembers];
   for (int t = 0; t < kMaxMembers; ++t) { sx[t] = 0.0; sy[t] = 0.0; sz[t] = 0.0; }
+  double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0, n4 = 0.0;
   for (int p = tid; p < nvel; p += nth) {
     const double v[3] = {vnode3(P.vmin, P.dv, p % N), vnode3(P.vmin, P.dv, (p / N) % N),
                          vnode3(P.vmin, P.dv, p / (N * N))};
@@ -668,10 +654,21 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
       }
     }
     if (P.write_state) {
-      const double E = nu != 0.0 ? maxw3(eq[0], ux, uy, uz, T, v[0], v[1], v[2]) : 0.0;
+      const double cx = v[0] - ux, cy = v[1] - uy, cz = v[2] - uz;
+      const double E = nu != 0.0 ? Am * exp(-(cx * cx + cy * cy + cz * cz) * inv2T) : 0.0;
       const double fn = fo - P.dt / V * Rs + nu * (E - fo);
       for (int t = 0; t < nm; ++t) out[(size_t)G.mem[b + t] * nvel + p] = fn;
+      n0 += fn; n1 += v[0] * fn; n2 += v[1] * fn; n3 += v[2] * fn;
+      n4 += (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) * fn;
     }
+  }
+  if (P.write_state) {
+    n0 = block_sum(n0, lds); n1 = block_sum(n1, lds); n2 = block_sum(n2, lds);
+    n3 = block_sum(n3, lds); n4 = block_sum(n4, lds);
+    double* pp = part + (size_t)m * nch * 5;
+    for (int k = tid; k < nch * 5; k += nth) pp[k] = 0.0;
+    __syncthreads();
+    if (tid == 0) { pp[0] = n0; pp[1] = n1; pp[2] = n2; pp[3] = n3; pp[4] = n4; }
   }
   double Fx = 0.0, Fy = 0.0, Fz = 0.0;
   for (int t = 0; t < nm; ++t) {
@@ -687,28 +684,25 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
     fslot[3 * q + 0] = Fx;
     fslot[3 * q + 1] = Fy;
     fslot[3 * q + 2] = Fz;
-    mpart[q] = V * rho;
   }
 }
 
 // diag row: force summed over the control volumes in list order, mass over
-// the regular-cell block partials then the control volumes
+// the block partials of the moment pass
 __global__ void __launch_bounds__(256) k_reduce3d(const double* __restrict__ fslot, int ncv,
-                                                 const double* __restrict__ mreg, int nreg,
-                                                 const double* __restrict__ mcut,
+                                                 const double* __restrict__ mpart, int nmp,
                                                  double* __restrict__ row) {
   __shared__ double lds[4];
-  double fx = 0.0, fy = 0.0, fz = 0.0, ms = 0.0, mc = 0.0;
+  double fx = 0.0, fy = 0.0, fz = 0.0, ms = 0.0;
   for (int t = threadIdx.x; t < ncv; t += blockDim.x) {
     fx += fslot[3 * t]; fy += fslot[3 * t + 1]; fz += fslot[3 * t + 2];
-    mc += mcut[t];
   }
-  for (int t = threadIdx.x; t < nreg; t += blockDim.x) ms += mreg[t];
+  for (int t = threadIdx.x; t < nmp; t += blockDim.x) ms += mpart[t];
   fx = block_sum(fx, lds); fy = block_sum(fy, lds); fz = block_sum(fz, lds);
-  ms = block_sum(ms, lds); mc = block_sum(mc, lds);
+  ms = block_sum(ms, lds);
   if (threadIdx.x == 0) {
     row[0] = fx; row[1] = fy; row[2] = fz;
-    row[3] = ms + mc;
+    row[3] = ms;
   }
 }
 
@@ -854,7 +848,10 @@ hipError_t run_mom3d(cc_ctx* ctx) {
   P.N = ctx->N;
   P.conservative = ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE;
   prof_begin(ctx, 4);
-  k_mom3d<<<mom_blocks(ctx), 256, 0, ctx->stream>>>(ctx->g3, ctx->s.part, ctx->s.mom, ctx->s.mpart, P);
+  if (P.conservative)
+    k_mom3d<true><<<mom_blocks(ctx), 256, 0, ctx->stream>>>(ctx->g3, ctx->s.part, ctx->s.mom, ctx->s.mpart, P);
+  else
+    k_mom3d<false><<<mom_blocks(ctx), 256, 0, ctx->stream>>>(ctx->g3, ctx->s.part, ctx->s.mom, ctx->s.mpart, P);
   prof_end(ctx, 4);
   return hipGetLastError();
 }
@@ -875,16 +872,15 @@ Cut3Params cut_params(const cc_ctx* ctx, int write) {
 // force (and mass) slots of the current merged state into row[0..3]
 hipError_t cut_and_reduce(cc_ctx* ctx, const double* in, double* out, int write, double* row) {
   const int nb = mom_blocks(ctx);
-  double* mcut = ctx->s.mpart + nb;
   if (ctx->n_irr > 0) {
     prof_begin(ctx, 1);
-    k_cut3d<<<ctx->n_irr, 256, 0, ctx->stream>>>(ctx->g3, in, out, ctx->s.fslot, mcut,
-                                                 cut_params(ctx, write));
+    k_cut3d<<<ctx->n_irr, 256, 0, ctx->stream>>>(ctx->g3, in, out, ctx->s.fslot, ctx->s.mom, ctx->s.part,
+                                                 chunks3d(ctx->N), cut_params(ctx, write));
     prof_end(ctx, 1);
   }
   if (row) {
     prof_begin(ctx, 2);
-    k_reduce3d<<<1, 256, 0, ctx->stream>>>(ctx->s.fslot, ctx->n_irr, ctx->s.mpart, nb, mcut, row);
+    k_reduce3d<<<1, 256, 0, ctx->stream>>>(ctx->s.fslot, ctx->n_irr, ctx->s.mpart, nb, row);
     prof_end(ctx, 2);
   }
   return hipGetLastError();
@@ -989,7 +985,7 @@ hipError_t launch_mass_3d(cc_ctx* ctx, double* mass_row) {
   const int nb = (ctx->ncell + 3) / 4;
   k_mass3d<<<nb, 256, 0, ctx->stream>>>(ctx->g3, (const double*)ctx->state[ctx->cur], ctx->s.mpart,
                                          weight3(ctx));
-  k_reduce3d<<<1, 256, 0, ctx->stream>>>(ctx->s.fslot, 0, ctx->s.mpart, nb, ctx->s.mpart, ctx->s.red);
+  k_reduce3d<<<1, 256, 0, ctx->stream>>>(ctx->s.fslot, 0, ctx->s.mpart, nb, ctx->s.red);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return hipMemcpyAsync(mass_row, ctx->s.red + 3, sizeof(double), hipMemcpyDeviceToDevice,
