@@ -72,6 +72,7 @@ class Config:
     steps: int = 1
     name: str = ""
     maxwellian: str = "direct"  # "direct" moments or "conservative" (Newton) equilibrium
+    scheme: str = "explicit"    # "explicit" or "imex" (semi-implicit relaxation)
 
     @property
     def ncell(self) -> int:

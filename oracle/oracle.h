@@ -36,6 +36,7 @@ typedef struct {
   int motion;              /* 0 fixed 1 free rotation 2 imposed */
   double vel[3], omega;    /* rigid body velocity at t = 0 */
   int maxwellian;          /* 0 direct moments, 1 conservative (Newton) */
+  int scheme;              /* 0 explicit (ExSchemeDD), 1 semi-implicit (ImpSchemeDD) */
 } orc_cfg;
 
 typedef struct orc2d orc2d;

@@ -27,7 +27,8 @@ class _Cfg(C.Structure):
                 ("body_kind", C.c_int), ("center", C.c_double * 3),
                 ("axes", C.c_double * 3), ("theta", C.c_double), ("t_wall", C.c_double),
                 ("mass", C.c_double), ("inertia", C.c_double), ("motion", C.c_int),
-                ("vel", C.c_double * 3), ("omega", C.c_double), ("maxwellian", C.c_int)]
+                ("vel", C.c_double * 3), ("omega", C.c_double), ("maxwellian", C.c_int),
+                ("scheme", C.c_int)]
 
 
 def cfg_struct(cfg) -> _Cfg:
@@ -49,6 +50,7 @@ def cfg_struct(cfg) -> _Cfg:
     s.vel[:] = list(b.vel)
     s.omega = b.omega
     s.maxwellian = {"direct": 0, "conservative": 1}[getattr(cfg, "maxwellian", "direct")]
+    s.scheme = {"explicit": 0, "imex": 1}[getattr(cfg, "scheme", "explicit")]
     return s
 
 

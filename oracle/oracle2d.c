@@ -633,6 +633,32 @@ static void scheme_cv(const orc2d *o, const geo2d *G, const double *fm,
       Rg[p] += (Gxp - Gxm) + (Gyp - Gym) + Gw;
     }
   }
+  if (o->cfg.scheme == 1) {
+    /* Semi-implicit scheme (ImpSchemeDD): explicit transport, then the
+       relaxation toward the equilibrium of t^{n+1} taken implicitly.  Its
+       moments follow from summing the scheme over the velocities, where the
+       collision term vanishes: they are those of the transported value.
+       READING: tau^n comes from the directly computed density of the
+       control volume at t^n. */
+    double *fs = malloc(nvel * sizeof(double)), *gs = malloc(nvel * sizeof(double));
+    double ratio = S / snew;
+    for (int p = 0; p < nvel; ++p) {
+      fs[p] = ratio * fc[p] - dt / snew * R[p];
+      gs[p] = ratio * gc[p] - dt / snew * Rg[p];
+    }
+    double rn, uxn, uyn, Tn;
+    cell_moments(o, fc, gc, &rn, &uxn, &uyn, &Tn);
+    double nu = collide ? dt / tau_of(o, rn) : 0.0;
+    double r1, ux1, uy1, T1;
+    equilibrium2(o, fs, gs, &r1, &ux1, &uy1, &T1);
+    for (int p = 0; p < nvel; ++p) {
+      double E = collide ? maxw2(r1, ux1, uy1, T1, o->v[p % N], o->v[p / N]) : 0.0;
+      fo[p] = (fs[p] + nu * E) / (1.0 + nu);
+      go[p] = (gs[p] + nu * 0.5 * T1 * E) / (1.0 + nu);
+    }
+    free(fs); free(gs); free(R); free(Rg);
+    return;
+  }
   for (int p = 0; p < nvel; ++p) {
     double vx = o->v[p % N], vy = o->v[p / N];
     double E = 0.0, Ge = 0.0;
@@ -1065,7 +1091,7 @@ static void cv_sum(const orc2d *o, const geo2d *G, const double *a, double *L) {
    dJ/du_y (u = farfield velocity). Fixed bodies only. */
 int orc2d_adjoint(orc2d *o, int nsteps, int objective, double *out) {
   if (o->cfg.motion != 0 && o->cfg.body_kind != 0) return -1;
-  if (o->cfg.maxwellian) return -1;   /* transpose written for the direct triplet */
+  if (o->cfg.maxwellian || o->cfg.scheme) return -1;   /* transpose written for the explicit direct step */
   int nvel = o->nvel, N = o->N;
   size_t tot = (size_t)o->ncell * nvel;
   const geo2d *G = &o->g[o->cur];

@@ -478,6 +478,23 @@ static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
       R[p] += r;
     }
   }
+  if (o->cfg.scheme == 1) {
+    /* semi-implicit scheme (ImpSchemeDD in 3D): equilibrium of the
+       transported value, tau^n from the direct density at t^n (READING) */
+    double *fs = malloc(nvel * sizeof(double));
+    for (int p = 0; p < nvel; ++p) fs[p] = fc[p] - o->dt / V * R[p];
+    double rn, un[3], Tn;
+    moments3(o, fc, &rn, un, &Tn);
+    double nu = collide ? o->dt / (sqrt(M_PI) / 2.0 * (1.0 / rn) * o->cfg.kn * o->cfg.lref / sqrt(2.0)) : 0.0;
+    double r1, u1[3], T1;
+    equilibrium3(o, fs, &r1, u1, &T1);
+    for (int p = 0; p < nvel; ++p) {
+      double E = collide ? maxw3(r1, u1, T1, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]) : 0.0;
+      out[p] = (fs[p] + nu * E) / (1.0 + nu);
+    }
+    free(fs); free(R); free(fw);
+    return;
+  }
   for (int p = 0; p < nvel; ++p) {
     double E = collide ? maxw3(rho, u, T, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]) : 0.0;
     double fnew = fc[p] - o->dt / V * R[p];

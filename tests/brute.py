@@ -19,7 +19,7 @@ def maxwellian(rho, ux, uy, T, vx, vy):
     return rho / (2 * math.pi * T) * math.exp(-((vx - ux) ** 2 + (vy - uy) ** 2) / (2 * T))
 
 
-def brute_step(cfg, geo, v, dt, f, g, collide=True):
+def brute_step(cfg, geo, v, dt, f, g, collide=True, imex=False):
     nx, ny = cfg.n[0], cfg.n[1]
     N = cfg.nv
     nvel = N * N
@@ -109,7 +109,19 @@ def brute_step(cfg, geo, v, dt, f, g, collide=True):
         fm, gm = f[m], g[m]
         newf = fm - dt / S * Rf[m]
         newg = gm - dt / S * Rg[m]
-        if collide:
+        if collide and imex:
+            # implicit relaxation toward the equilibrium of the transported value
+            rho0 = sum(fm) * w
+            nu = dt / (tau_c / rho0)
+            rho = sum(newf) * w
+            ux = sum(vel[p][0] * newf[p] for p in range(nvel)) * w / rho
+            uy = sum(vel[p][1] * newf[p] for p in range(nvel)) * w / rho
+            E = sum((0.5 * (vel[p][0] ** 2 + vel[p][1] ** 2) * newf[p] + newg[p]) for p in range(nvel)) * w
+            T = (2 * E / rho - ux * ux - uy * uy) / 3
+            Eq = np.array([maxwellian(rho, ux, uy, T, vx, vy) for vx, vy in vel])
+            newf = (newf + nu * Eq) / (1 + nu)
+            newg = (newg + nu * 0.5 * T * Eq) / (1 + nu)
+        elif collide:
             rho = sum(fm) * w
             ux = sum(vel[p][0] * fm[p] for p in range(nvel)) * w / rho
             uy = sum(vel[p][1] * fm[p] for p in range(nvel)) * w / rho
@@ -130,7 +142,7 @@ def maxwellian3(rho, u, T, v):
     return rho / (2 * math.pi * T) ** 1.5 * math.exp(-c2 / (2 * T))
 
 
-def brute_step_3d(cfg, geo, v, dt, F, collide=True):
+def brute_step_3d(cfg, geo, v, dt, F, collide=True, imex=False):
     """Face-loop formulation of one fixed-geometry 3D step (eq. eq-schema3D):
     every Cartesian face is visited once, its upwind flux added to the control
     volume below it and subtracted from the one above; wall faces add their
@@ -205,7 +217,15 @@ def brute_step_3d(cfg, geo, v, dt, F, collide=True):
     for m, mem in groups.items():
         fm = F[m]
         new = fm - dt / vcv[m] * R[m]
-        if collide:
+        if collide and imex:
+            nu = dt / (tau_c / (fm.sum() * w))
+            rho = new.sum() * w
+            u = [float((vd[d] * new).sum() * w / rho) for d in range(3)]
+            E = float((0.5 * (vd[0] ** 2 + vd[1] ** 2 + vd[2] ** 2) * new).sum() * w)
+            T = (2 * E / rho - u[0] ** 2 - u[1] ** 2 - u[2] ** 2) / 3
+            Eq = np.array([maxwellian3(rho, u, T, q) for q in vel])
+            new = (new + nu * Eq) / (1 + nu)
+        elif collide:
             rho = fm.sum() * w
             u = [float((vd[d] * fm).sum() * w / rho) for d in range(3)]
             E = float((0.5 * (vd[0] ** 2 + vd[1] ** 2 + vd[2] ** 2) * fm).sum() * w)
