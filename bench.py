@@ -144,6 +144,9 @@ def main():
     ap.add_argument("--maxwellian", default="direct", choices=["direct", "conservative"],
                     help="equilibrium of the relaxation: direct moments (default) or the conservative "
                          "Newton triplet")
+    ap.add_argument("--scheme", default="explicit", choices=["explicit", "imex"],
+                    help="time scheme: explicit (default) or semi-implicit (transport explicit, "
+                         "relaxation implicit)")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=40,
@@ -172,7 +175,8 @@ def main():
     if args.workload == "batch":
         return bench_batch(args)
 
-    cfg = workload(args.workload, kn=args.kn).with_(maxwellian=args.maxwellian)
+    cfg = workload(args.workload, kn=args.kn).with_(maxwellian=args.maxwellian,
+                                                    scheme=args.scheme)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     s = Solver(cfg, device=dev)
@@ -203,6 +207,7 @@ def main():
     red_ms, red_n = s.profile_read(2)
     mrg_ms, mrg_n = s.profile_read(3)
     mom_ms, mom_n = s.profile_read(4)
+    rlx_ms, rlx_n = s.profile_read(5)
     s.profile_enable(False)
     n_regular = active - n_irr - n_mem
     # read + write of the state, FP64: f,g in 2D (32 B), F in 3D (16 B)
@@ -227,7 +232,7 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload].format(kn=cfg.kn),
                    "cells": cfg.ncell, "active_cells": active, "velocities": nvel,
                    "cut_control_volumes": n_irr, "merged_cells": n_mem, "dt": s.dt,
-                   "maxwellian": args.maxwellian,
+                   "maxwellian": args.maxwellian, "scheme": args.scheme,
                    "drag_last_step": drag_last},
         "roofline": {"bound": "hbm", "kernel": "k_step2d" if cfg.dim == 2 else "k_step3d",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -242,7 +247,10 @@ def main():
         # 3D: moments from the chunk sums (and the Newton triplet);
         # 2D conservative: the Newton pass between steps
         out["roofline"]["between_steps_kernel_avg_us"] = round(mom_ms / max(mom_n, 1) * 1e3, 2)
-    if args.workload == "cyl512" and args.adjoint_steps > 0 and args.maxwellian == "direct":
+    if args.scheme == "imex":
+        out["roofline"]["relax_kernel_avg_us"] = round(rlx_ms / max(rlx_n, 1) * 1e3, 2)
+    if (args.workload == "cyl512" and args.adjoint_steps > 0 and args.maxwellian == "direct"
+            and args.scheme == "explicit"):
         # adjoint over the same workload: forward alone vs forward with
         # checkpoints + recomputation + adjoint sweep (cc_adjoint)
         na, ka = args.adjoint_steps, args.adjoint_ckpt

@@ -73,6 +73,14 @@ enum { CC_MOTION_FIXED = 0, CC_MOTION_FREE_ROTATION = 1, CC_MOTION_IMPOSED = 2 }
  * relaxation time included, comes from that solution.  A cell whose
  * iteration does not converge in 50 steps keeps the direct triplet. */
 enum { CC_MAXW_DIRECT = 0, CC_MAXW_CONSERVATIVE = 1 };
+/* Time scheme: explicit (eq. ExSchemeDD) or the first-order semi-implicit
+ * scheme of eq. ImpSchemeDD: explicit transport, then the relaxation taken
+ * implicitly toward the equilibrium of the transported value,
+ * f^{n+1} = (f* + (dt/tau^n) E*)/(1 + dt/tau^n), tau^n from the density of
+ * the state at t^n.  The semi-implicit step reads and writes the state
+ * twice (about twice the time of an explicit step) and is stable for
+ * dt >> tau. */
+enum { CC_SCHEME_EXPLICIT = 0, CC_SCHEME_IMEX = 1 };
 
 /* Flow set-up.  dim = 2 selects the reduced plane-flow model with the two
  * distributions f, g (Section 2.2); dim = 3 the full model with F
@@ -90,6 +98,8 @@ typedef struct {
   double cfl, dt;
   double inflow[5];
   int maxwellian;         /* CC_MAXW_DIRECT or CC_MAXW_CONSERVATIVE (fixed bodies,
+                             no adjoint or batch) */
+  int scheme;             /* CC_SCHEME_EXPLICIT or CC_SCHEME_IMEX (fixed bodies,
                              no adjoint or batch) */
 } cc_config;
 
@@ -204,8 +214,9 @@ cc_status cc_set_tile_rows(cc_ctx* ctx, int rows);
 /* Per-kernel timing with HIP events recorded on the bound stream.
  * cc_profile_enable(ctx, 1) starts recording (cleared); cc_profile_read
  * returns, for kernel id k (0 = regular-cell step kernel, 1 = cut-cell
- * kernel, 2 = force/mass reduction, 3 = merge, 4 = 3D moment reduction
- * between steps), the summed
+ * kernel, 2 = force/mass reduction, 3 = merge, 4 = pass between steps:
+ * 3D moments and the conservative Newton solve, 5 = implicit relaxation of
+ * the semi-implicit scheme), the summed
  * milliseconds and the number of launches since enabling (at most 4096
  * launches per kernel are recorded).  Reading synchronises the stream. */
 cc_status cc_profile_enable(cc_ctx* ctx, int on);

@@ -25,6 +25,7 @@ hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_ro
 hipError_t launch_moving_init_2d(cc_ctx* ctx);
 size_t adjoint_workspace_bytes(const cc_ctx* ctx, int nsteps, int K);
 hipError_t adjoint_run_2d(cc_ctx* ctx, int nsteps, int K, int objective, char* pool, double* out);
+hipError_t launch_imex_step_2d(cc_ctx* ctx, double* row);
 }  // namespace ccdvm
 
 static bool is_moving(const cc_ctx* ctx) {
@@ -119,6 +120,8 @@ void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
   ctx->s.gcount = cv.take<int>(4);
   ctx->s.pose = cv.take<double>(4);
   ctx->s.mom = cv.take<double>(n * nm);
+  ctx->s.mom2 = cv.take<double>(ctx->dim == 2 ? n * 4 : 0);
+  ctx->s.nu = cv.take<double>(n);
   ctx->s.part = ctx->dim == 3 ? cv.take<double>(n * (size_t)chunks3d(ctx->N) * 5) : nullptr;
   ctx->s.fslot = cv.take<double>(n * 3 * 2);
   ctx->s.mpart_cap = (int)((size_t)((ctx->nx + 3) / 4) * ctx->ny * ctx->nz + n);
@@ -209,6 +212,9 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
     return reject("unknown maxwellian mode");
   if (c.maxwellian == CC_MAXW_CONSERVATIVE && body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_NONE)
     return reject("the conservative equilibrium is available for fixed bodies");
+  if (c.scheme != CC_SCHEME_EXPLICIT && c.scheme != CC_SCHEME_IMEX) return reject("unknown scheme");
+  if (c.scheme == CC_SCHEME_IMEX && body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_NONE)
+    return reject("the semi-implicit scheme is available for fixed bodies");
   ctx->dim = c.dim;
   ctx->nx = c.n[0]; ctx->ny = c.n[1]; ctx->nz = c.dim == 3 ? c.n[2] : 1;
   long long ncell = (long long)ctx->nx * ctx->ny * ctx->nz;
@@ -392,6 +398,13 @@ cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
     // every step reduces its own force and mass rows
     for (int n = 0; n < nsteps; ++n) {
       hipError_t e = launch_step_3d(ctx, diag ? diag + 4 * (size_t)n : nullptr, nullptr);
+      if (e != hipSuccess) return hip_fail(ctx, e, "step");
+    }
+    return CC_OK;
+  }
+  if (ctx->cfg.scheme == CC_SCHEME_IMEX) {
+    for (int n = 0; n < nsteps; ++n) {
+      hipError_t e = launch_imex_step_2d(ctx, diag ? diag + 4 * (size_t)n : nullptr);
       if (e != hipSuccess) return hip_fail(ctx, e, "step");
     }
     return CC_OK;
@@ -583,8 +596,8 @@ cc_status cc_adjoint(cc_ctx* ctx, int nsteps, int ckpt_every, int objective, voi
     return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   if (ctx->dim != 2 || is_moving(ctx)) return fail(ctx, CC_EINVAL, "the adjoint covers 2D fixed bodies");
-  if (ctx->cfg.maxwellian != CC_MAXW_DIRECT)
-    return fail(ctx, CC_EINVAL, "the adjoint is written for the direct equilibrium");
+  if (ctx->cfg.maxwellian != CC_MAXW_DIRECT || ctx->cfg.scheme != CC_SCHEME_EXPLICIT)
+    return fail(ctx, CC_EINVAL, "the adjoint is written for the explicit scheme with the direct equilibrium");
   if ((uintptr_t)pool % kAlign) return fail(ctx, CC_EINVAL, "pool must be 256-byte aligned");
   cc_status st = cc_init_maxwellian(ctx);
   if (st != CC_OK) return st;
@@ -671,12 +684,12 @@ cc_status cc_batch_create(cc_ctx* const* ctxs, int n, cc_batch** out) {
   for (int i = 0; i < n; ++i) {
     cc_ctx* c = ctxs[i];
     bool ok = c && c->bound && c->dim == 2 && !is_moving(c) && c->cfg.maxwellian == CC_MAXW_DIRECT &&
-              batch_supported_nch(batch_group_nch(c));
+              c->cfg.scheme == CC_SCHEME_EXPLICIT && batch_supported_nch(batch_group_nch(c));
     for (int k = 0; k < i && ok; ++k) ok = ctxs[k] != c;
     if (ok && i > 0) ok = c->stream == ctxs[0]->stream;
     if (!ok) {
       fprintf(stderr, "ccdvm: batch instance %d must be a distinct bound 2D fixed-body context "
-                      "(direct equilibrium) on the stream of instance 0\n", i);
+                      "(explicit, direct equilibrium) on the stream of instance 0\n", i);
       delete b;
       return CC_EINVAL;
     }

@@ -112,6 +112,8 @@ struct Scratch {
   double* mom;       // 2D: ncell * 4 (rho, ux, uy, T); 3D: ncell * 8 (Maxwellian factor, u,
                      // 1/(2T), dt/tau, rho)
   double* part;      // 3D: per cell and velocity chunk, sums of F, v F, |v|^2 F
+  double* mom2;      // 2D semi-implicit step: moments of the new state (ncell * 4)
+  double* nu;        // semi-implicit step: dt/tau of each control volume at t^n
   double* fslot;     // 2 x per irregular master: Fx, Fy, torque (2D) / Fx, Fy, Fz (3D)
   double* mpart;     // 2 x mass partials (regular tiles, then control volumes)
   int mpart_cap;
@@ -121,12 +123,12 @@ struct Scratch {
 
 // Per-kernel HIP events recorded around every launch while profiling is on;
 // elapsed times are summed when read.
-constexpr int kProfKernels = 5;
+constexpr int kProfKernels = 6;
 constexpr int kProfCap = 4096;
 struct Prof {
   bool on = false;
   std::vector<hipEvent_t> start[kProfKernels], stop[kProfKernels];
-  int count[kProfKernels] = {0, 0, 0, 0, 0};
+  int count[kProfKernels] = {0, 0, 0, 0, 0, 0};
 };
 
 }  // namespace ccdvm
@@ -206,7 +208,7 @@ hipError_t launch_store_state_2d(const cc_ctx* ctx, double* f, double* g);
 hipError_t launch_merge_2d(cc_ctx* ctx);
 hipError_t launch_moments_all_2d(cc_ctx* ctx);
 hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_force_row,
-                                double* cur_mass_row, bool record);
+                                double* cur_mass_row, bool record, bool relax = true);
 hipError_t launch_step_2d_flush(cc_ctx* ctx, double* force_row, double* mass_row);
 hipError_t launch_mass_2d(cc_ctx* ctx, double* mass_row);
 hipError_t launch_moments_out_2d(cc_ctx* ctx, double* out);

@@ -691,6 +691,59 @@ __global__ void __launch_bounds__(256) k_newton2d(Geo2D G, double* __restrict__ 
   }
 }
 
+// Semi-implicit step (ImpSchemeDD), first part: dt/tau^n of every control
+// volume from the directly computed density of the state at t^n.
+__global__ void __launch_bounds__(256) k_imex_nu2d(Geo2D G, const double* __restrict__ mom,
+                                                  double* __restrict__ nu, double dt, double tau_coef) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.ncell) return;
+  const int kd = G.kind[c];
+  if (kd != KIND_REGULAR && kd != KIND_IRREGULAR) return;
+  nu[c] = tau_coef > 0.0 ? dt * mom[4 * (size_t)c] / tau_coef : 0.0;
+}
+
+// Semi-implicit step, last part: the implicit relaxation of every non-solid
+// cell's transported value (f*, g*) toward the equilibrium of its control
+// volume's transported moments (direct or conservative triplet in mom):
+// f = (f* + nu E)/(1 + nu), g = (g* + nu T/2 E)/(1 + nu).  Masters also
+// write the direct moments of the new value to mom_next.  One wave per cell.
+__global__ void __launch_bounds__(256) k_relax2d(Geo2D G, double2* __restrict__ st,
+                                                const double* __restrict__ mom,
+                                                const double* __restrict__ nu,
+                                                double* __restrict__ mom_next, StepParams P) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= G.ncell) return;
+  const int m = G.master[c];
+  if (m < 0) return;
+  const int N = G.N, nvel = G.nvel;
+  const double* mc = mom + 4 * (size_t)m;
+  const double rho = mc[0], ux = mc[1], uy = mc[2], T = mc[3];
+  const double A = rho / (2.0 * M_PI * T), inv2T = 0.5 / T;
+  const double nv = nu[m], sc = 1.0 / (1.0 + nv);
+  double2* row = st + (size_t)c * nvel;
+  double sr = 0.0, smx = 0.0, smy = 0.0, se = 0.0;
+  for (int p = lane; p < nvel; p += kWave) {
+    const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
+    const double cx = vx - ux, cy = vy - uy;
+    const double E = A * exp(-(cx * cx + cy * cy) * inv2T);
+    const double2 o = row[p];
+    const double fn = (o.x + nv * E) * sc;
+    const double gn = (o.y + nv * 0.5 * T * E) * sc;
+    row[p] = make_double2(fn, gn);
+    sr += fn; smx += vx * fn; smy += vy * fn;
+    se += 0.5 * (vx * vx + vy * vy) * fn + gn;
+  }
+  if (c != m) return;
+  sr = wave_sum(sr); smx = wave_sum(smx); smy = wave_sum(smy); se = wave_sum(se);
+  if (lane == 0) {
+    const double r = sr * P.w, mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
+    double* mo = mom_next + 4 * (size_t)c;
+    mo[0] = r; mo[1] = mx; mo[2] = my;
+    mo[3] = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
+  }
+}
+
 StepParams params2d(const cc_ctx* ctx) {
   StepParams P;
   P.vmin = ctx->cfg.vmin;
@@ -1199,6 +1252,40 @@ hipError_t launch_moments_out_2d(cc_ctx* ctx, double* out) {
   return hipGetLastError();
 }
 
+// One semi-implicit step (ImpSchemeDD, fixed body); row (nullable) = force,
+// torque and mass of the state entering the step.
+hipError_t launch_imex_step_2d(cc_ctx* ctx, double* row) {
+  hipStream_t s = ctx->stream;
+  StepParams P = params2d(ctx);
+  unsigned int* ticket = reinterpret_cast<unsigned int*>(ctx->s.red + 4 * kRedBlocks);
+  if (row)   // mass of the state at t^n from its moments
+    k_reduce2d<<<kRedBlocks, 256, 0, s>>>(ctx->g2, ctx->s.mom, ctx->s.fslot, ctx->s.red, ticket,
+                                          nullptr, row + 3);
+  k_imex_nu2d<<<(ctx->ncell + 255) / 256, 256, 0, s>>>(ctx->g2, ctx->s.mom, ctx->s.nu, P.dt, P.tau_coef);
+  // transport: the step kernels without relaxation (the force of t^n is
+  // computed by the cut kernel into this parity's slots)
+  const int par = ctx->step_parity;
+  hipError_t e = launch_step_2d_fused(ctx, false, nullptr, nullptr, false, false);
+  if (e != hipSuccess) return e;
+  if (row) {
+    const double* fs = ctx->s.fslot + (par ? 3 * (size_t)ctx->ncell : 0);
+    k_reduce2d<<<kRedBlocks, 256, 0, s>>>(ctx->g2, ctx->s.mom, fs, ctx->s.red, ticket, row, nullptr);
+  }
+  if (ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE && P.tau_coef > 0.0) {
+    prof_begin(ctx, 4);
+    k_newton2d<<<(ctx->ncell + 255) / 256, 256, 0, s>>>(ctx->g2, ctx->s.mom, P.vmin, P.dv);
+    prof_end(ctx, 4);
+  }
+  prof_begin(ctx, 5);
+  k_relax2d<<<(ctx->ncell + 3) / 4, 256, 0, s>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
+                                                 ctx->s.nu, ctx->s.mom2, P);
+  prof_end(ctx, 5);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(ctx->s.mom, ctx->s.mom2, (size_t)ctx->ncell * 4 * sizeof(double),
+                        hipMemcpyDeviceToDevice, s);
+}
+
 // mass of the current state into mass_row (no force)
 hipError_t launch_mass_2d(cc_ctx* ctx, double* mass_row) {
   k_reduce2d<<<kRedBlocks, 256, 0, ctx->stream>>>(
@@ -1223,8 +1310,9 @@ int tile_rows(const cc_ctx* ctx) {
 // diag rows; the last step's are reduced by cc_step through
 // launch_step_2d_flush.
 hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_force_row,
-                                double* cur_mass_row, bool record) {
+                                double* cur_mass_row, bool record, bool relax) {
   StepParams P = params2d(ctx);
+  if (!relax) P.tau_coef = 0.0;   // transport only (first half of the semi-implicit step)
   fused_fn fn = pick_fused(chunks_per_half(ctx));
   if (!fn) return hipErrorInvalidValue;
   const int par = ctx->step_parity;
@@ -1254,7 +1342,7 @@ hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_forc
   A.red_force = prev_force_row;
   A.red_mass = cur_mass_row;
   dim3 grid(A.tile_base + A.ntiles_pad);
-  if (ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE) {
+  if (relax && ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE) {
     prof_begin(ctx, 4);
     k_newton2d<<<(ctx->ncell + 255) / 256, 256, 0, ctx->stream>>>(ctx->g2, ctx->s.mom, P.vmin, P.dv);
     prof_end(ctx, 4);

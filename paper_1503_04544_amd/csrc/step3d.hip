@@ -99,6 +99,7 @@ struct Step3Args {
   int nx, ny, nz, nvel;
   int ntj, ntiles, nblk, per;
   int ch0;              // first chunk of this launch
+  int relax;            // 0: transport only (semi-implicit step)
   double vmin, dv, cxf, cyf, czf;   // dt/dx, dt/dy, dt/dz
 };
 
@@ -202,7 +203,8 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A, const int* _
     const int c = (int)(pencil + i);
     if (valid && kind[c] == KIND_REGULAR) {
       const double* mc = mom + 8 * (size_t)c;
-      const double Am = mc[0], ux = mc[1], uy = mc[2], uz = mc[3], inv2T = mc[4], nu = mc[5];
+      const double Am = mc[0], ux = mc[1], uy = mc[2], uz = mc[3], inv2T = mc[4];
+      const double nu = A.relax ? mc[5] : 0.0;
       double tx = 0.0, tyy = 0.0, tzz = 0.0;
       if (lv < N) {
         const double v = vnode3(vmin, dv, lv);
@@ -373,7 +375,8 @@ __device__ __forceinline__ void step16(const Step3Args& A, const int* __restrict
   const int c = (int)(X.pencil + i);
   if (X.valid && kind[c] == KIND_REGULAR) {
     const double* mc = mom + 8 * (size_t)c;
-    const double Am = uniform_d(mc[0]), inv2T = uniform_d(mc[4]), nu = uniform_d(mc[5]);
+    const double Am = uniform_d(mc[0]), inv2T = uniform_d(mc[4]);
+    const double nu = A.relax ? uniform_d(mc[5]) : 0.0;
     const double ux = uniform_d(mc[1]), uy = uniform_d(mc[2]), uz = uniform_d(mc[3]);
     const double vmin = A.vmin, dv = A.dv;
     const int g = lv >> 4;
@@ -527,6 +530,11 @@ struct Mom3Params {
   double vmin, dv;
   int nch, N;
   int conservative;     // conservative equilibrium (Section 3.1)
+  // 0: explicit step (equilibrium and dt/tau from the same triplet);
+  // 1: semi-implicit step at t^n (dt/tau from the direct density only);
+  // 2: semi-implicit step, equilibrium of the transported value (dt/tau of
+  //    t^n kept)
+  int mode;
 };
 
 // moments of every control volume from its chunk sums (eq. MacroscopicTD):
@@ -550,7 +558,7 @@ __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict
     const double en = 0.5 * s[4] * P.w;
     const double T = (2.0 * en / rho - (ux * ux + uy * uy + uz * uz)) / 3.0;
     double x[5] = {rho, ux, uy, uz, T};
-    if (CONS) {
+    if (CONS && P.mode != 1) {
       const double target[5] = {rho, s[1] * P.w, s[2] * P.w, s[3] * P.w, en};
       if (!conservative_triplet_3d(x, target, P.vmin, P.dv, P.N)) {
         x[0] = rho; x[1] = ux; x[2] = uy; x[3] = uz; x[4] = T;
@@ -560,7 +568,7 @@ __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict
     mo[0] = x[0] / pow(2.0 * M_PI * x[4], 1.5);
     mo[1] = x[1]; mo[2] = x[2]; mo[3] = x[3];
     mo[4] = 0.5 / x[4];
-    mo[5] = P.tau_coef > 0.0 ? P.dt * x[0] / P.tau_coef : 0.0;
+    if (P.mode != 2) mo[5] = P.tau_coef > 0.0 ? P.dt * (P.mode == 1 ? rho : x[0]) / P.tau_coef : 0.0;
     mo[6] = rho;
     ms = (kd == KIND_REGULAR ? P.vol : G.vcv[c]) * rho;
   }
@@ -572,6 +580,7 @@ struct Cut3Params {
   double vmin, dv, w, dt, tau_coef, t_wall;
   int write_state;
   int conservative;     // conservative equilibrium (Section 3.1)
+  int relax;            // 0: transport only (semi-implicit step)
 };
 
 __device__ inline double maxw3(double rho, double ux, double uy, double uz, double T, double vx,
@@ -599,7 +608,8 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
   const int N = G.N, nvel = G.nvel, nx = G.nx, ny = G.ny, nz = G.nz;
   const double* own = in + (size_t)m * nvel;
   const double* rec = mom + 8 * (size_t)m;
-  const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4], nu = rec[5];
+  const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4];
+  const double nu = P.relax ? rec[5] : 0.0;
   const double V = G.vcv[m];
   const double Tw = P.t_wall;
   double phiw[kMaxMembers];
@@ -798,6 +808,59 @@ __global__ void __launch_bounds__(256) k_mass3d(Geo3D G, const double* __restric
   if (threadIdx.x == 0) mpart[blockIdx.x] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
 }
 
+// Semi-implicit step, last part: every non-solid cell's transported value
+// F* relaxes implicitly toward the equilibrium of its control volume's
+// transported moments, F = (F* + nu E)/(1 + nu) (nu = dt/tau^n from the
+// record), in place; masters also store the moment sums of the new value
+// (chunk slot 0, the other slots zero).  One wave per cell; the separable
+// Maxwellian is tabulated per axis in the first N lanes when the velocity
+// count is a multiple of the wave.
+__global__ void __launch_bounds__(256) k_relax3d(Geo3D G, double* __restrict__ st,
+                                                const double* __restrict__ mom,
+                                                double* __restrict__ part, int nch, double vmin,
+                                                double dv) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= G.ncell) return;
+  const int m = G.master[c];
+  if (m < 0) return;
+  const int N = G.N, nvel = G.nvel;
+  const double* rec = mom + 8 * (size_t)m;
+  const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4], nu = rec[5];
+  const double sc = 1.0 / (1.0 + nu);
+  double tx = 0.0, ty = 0.0, tz = 0.0;
+  if (lane < N) {
+    const double v = vnode3(vmin, dv, lane);
+    tx = exp(-(v - ux) * (v - ux) * inv2T);
+    ty = exp(-(v - uy) * (v - uy) * inv2T);
+    tz = exp(-(v - uz) * (v - uz) * inv2T);
+  }
+  const bool tables = nvel % kWave == 0;
+  double* row = st + (size_t)c * nvel;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+  for (int p = lane; p < nvel; p += kWave) {
+    const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
+    const double vx = vnode3(vmin, dv, p1), vy = vnode3(vmin, dv, p2), vz = vnode3(vmin, dv, p3);
+    double E;
+    if (tables) {
+      E = Am * __shfl(tx, p1, kWave) * __shfl(ty, p2, kWave) * __shfl(tz, p3, kWave);
+    } else {
+      const double cx = vx - ux, cy = vy - uy, cz = vz - uz;
+      E = Am * exp(-(cx * cx + cy * cy + cz * cz) * inv2T);
+    }
+    const double fn = (row[p] + nu * E) * sc;
+    row[p] = fn;
+    s0 += fn; s1 += vx * fn; s2 += vy * fn; s3 += vz * fn;
+    s4 += (vx * vx + vy * vy + vz * vz) * fn;
+  }
+  if (c != m) return;
+  s0 = wave_sum3(s0); s1 = wave_sum3(s1); s2 = wave_sum3(s2);
+  s3 = wave_sum3(s3); s4 = wave_sum3(s4);
+  double* pp = part + (size_t)c * nch * 5;
+  for (int k = lane; k < nch * 5; k += kWave) pp[k] = 0.0;
+  if (lane == 0) { pp[0] = s0; pp[1] = s1; pp[2] = s2; pp[3] = s3; pp[4] = s4; }
+}
+
 int node_count(int nvel) {
   int N = (int)llround(cbrt((double)nvel));
   return N * N * N == nvel ? N : 0;
@@ -836,7 +899,7 @@ double weight3(const cc_ctx* ctx) { return ctx->dv * ctx->dv * ctx->dv; }
 
 int mom_blocks(const cc_ctx* ctx) { return (ctx->ncell + 255) / 256; }
 
-hipError_t run_mom3d(cc_ctx* ctx) {
+hipError_t run_mom3d(cc_ctx* ctx, int mode = 0) {
   Mom3Params P;
   P.w = weight3(ctx);
   P.dt = ctx->dt;
@@ -847,6 +910,7 @@ hipError_t run_mom3d(cc_ctx* ctx) {
   P.nch = chunks3d(ctx->N);
   P.N = ctx->N;
   P.conservative = ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE;
+  P.mode = mode;
   prof_begin(ctx, 4);
   if (P.conservative)
     k_mom3d<true><<<mom_blocks(ctx), 256, 0, ctx->stream>>>(ctx->g3, ctx->s.part, ctx->s.mom, ctx->s.mpart, P);
@@ -856,7 +920,7 @@ hipError_t run_mom3d(cc_ctx* ctx) {
   return hipGetLastError();
 }
 
-Cut3Params cut_params(const cc_ctx* ctx, int write) {
+Cut3Params cut_params(const cc_ctx* ctx, int write, int relax = 1) {
   Cut3Params P;
   P.vmin = ctx->cfg.vmin;
   P.dv = ctx->dv;
@@ -866,16 +930,18 @@ Cut3Params cut_params(const cc_ctx* ctx, int write) {
   P.t_wall = ctx->body.t_wall;
   P.write_state = write;
   P.conservative = ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE;
+  P.relax = relax;
   return P;
 }
 
 // force (and mass) slots of the current merged state into row[0..3]
-hipError_t cut_and_reduce(cc_ctx* ctx, const double* in, double* out, int write, double* row) {
+hipError_t cut_and_reduce(cc_ctx* ctx, const double* in, double* out, int write, double* row,
+                          int relax = 1) {
   const int nb = mom_blocks(ctx);
   if (ctx->n_irr > 0) {
     prof_begin(ctx, 1);
     k_cut3d<<<ctx->n_irr, 256, 0, ctx->stream>>>(ctx->g3, in, out, ctx->s.fslot, ctx->s.mom, ctx->s.part,
-                                                 chunks3d(ctx->N), cut_params(ctx, write));
+                                                 chunks3d(ctx->N), cut_params(ctx, write, relax));
     prof_end(ctx, 1);
   }
   if (row) {
@@ -938,7 +1004,8 @@ hipError_t launch_moments_all_3d(cc_ctx* ctx) {
 hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
   step3_fn fn = nullptr;
   if (!select3(ctx->N, &fn, nullptr, nullptr)) return hipErrorNotSupported;
-  hipError_t e = run_mom3d(ctx);
+  const bool imex = ctx->cfg.scheme == CC_SCHEME_IMEX;
+  hipError_t e = run_mom3d(ctx, imex ? 1 : 0);
   if (e != hipSuccess) return e;
   const double* in = (const double*)ctx->state[ctx->cur];
   double* out = (double*)ctx->state[1 - ctx->cur];
@@ -966,6 +1033,7 @@ hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
   A.vmin = ctx->cfg.vmin;
   A.dv = ctx->dv;
   A.cxf = ctx->dt / ctx->dx; A.cyf = ctx->dt / ctx->dy; A.czf = ctx->dt / ctx->dz;
+  A.relax = imex ? 0 : 1;
   prof_begin(ctx, 0);
   for (int l = 0; l < nlaunch; ++l) {
     A.ch0 = l;
@@ -974,8 +1042,20 @@ hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
   prof_end(ctx, 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = cut_and_reduce(ctx, in, out, 1, row);
+  e = cut_and_reduce(ctx, in, out, 1, row, imex ? 0 : 1);
   if (e != hipSuccess) return e;
+  if (imex) {
+    // semi-implicit step (ImpSchemeDD): equilibrium of the transported
+    // value, then the implicit relaxation in place
+    e = run_mom3d(ctx, 2);
+    if (e != hipSuccess) return e;
+    prof_begin(ctx, 5);
+    k_relax3d<<<(ctx->ncell + 3) / 4, 256, 0, ctx->stream>>>(ctx->g3, out, ctx->s.mom, ctx->s.part,
+                                                             chunks3d(ctx->N), ctx->cfg.vmin, ctx->dv);
+    prof_end(ctx, 5);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   ctx->cur = 1 - ctx->cur;
   ctx->nstep += 1;
   return hipSuccess;

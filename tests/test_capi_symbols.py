@@ -81,3 +81,19 @@ def test_create_validates_maxwellian_mode():
     assert st == 0
     from paper_1503_04544_amd._capi import lib as L
     L().cc_destroy(h)
+
+
+def test_create_validates_scheme():
+    from paper_1503_04544_amd._capi import lib, make_body, make_config
+    cfg = small_2d(8, 8, 8)
+    c = make_config(cfg)
+    c.scheme = 2
+    h = C.c_void_p()
+    assert lib().cc_create(C.byref(c), C.byref(make_body(cfg.body)), C.byref(h)) == -1
+    moving = small_2d(8, 8, 8, body=Body("ellipse", (0.5, 0.5, 0), (0.2, 0.05, 0), motion="free_rotation",
+                                         inertia=0.01), scheme="imex")
+    st, h = _create(moving)
+    assert st == -1 and not h.value
+    st, h = _create(small_2d(8, 8, 8, scheme="imex"))
+    assert st == 0
+    lib().cc_destroy(h)

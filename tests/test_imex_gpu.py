@@ -1,0 +1,117 @@
+"""GPU parity of the semi-implicit scheme (eq. ImpSchemeDD) with the oracle,
+2D and 3D, with the direct and the conservative equilibrium, and its
+stability for dt >> tau on the GPU.
+
+Tolerances: one step <= 1e-12 of max|f|, ten or more steps <= 1e-9, force
+<= 1e-10 of |F|, mass <= 1e-12 relative.
+"""
+import numpy as np
+import pytest
+
+from ccdvm_inputs import Body, random_state, small_2d, small_3d
+from oracle import Oracle2D
+from oracle.oracle import Oracle3D
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_04544_amd.solver import Solver  # noqa: F401
+
+
+def solver(cfg):
+    from paper_1503_04544_amd.solver import Solver
+    return Solver(cfg, device="cuda:0")
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+I = "imex"
+CASES2 = {
+    "cyl32_n8_kn001": small_2d(32, 32, 8, kn=0.01, mach=0.9, scheme=I),
+    "tiny6_merge": small_2d(6, 6, 4, kn=0.002, mach=0.4, body=Body("circle", (0.5, 0.52, 0), (0.19, 0.19, 0)), scheme=I),
+    "ragged_n12_cons": small_2d(20, 14, 12, kn=0.005, mach=0.6, body=Body("circle", (0.45, 0.5, 0), (0.22, 0.22, 0), t_wall=1.4),
+                                scheme=I, maxwellian="conservative"),
+}
+CASES3 = {
+    "n16": small_3d(16, 8, 8, nv=16, kn=0.01, mach=0.5, scheme=I),
+    "ragged_n8_cons": small_3d(13, 7, 9, nv=8, kn=0.005, mach=0.9, body=Body("sphere", (0.45, 0.24, 0.26), (0.15,) * 3, t_wall=1.4),
+                               scheme=I, maxwellian="conservative"),
+    "n6_merge": small_3d(6, 5, 5, nv=6, kn=0.002, mach=0.4, body=Body("sphere", (0.5, 0.26, 0.24), (0.17,) * 3), scheme=I),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES2))
+def test_one_step_2d(name):
+    cfg = CASES2[name]
+    f0, g0 = random_state(cfg.ncell, cfg.nv, 2, seed=91)
+    s = solver(cfg)
+    s.load_state(torch.from_numpy(f0), torch.from_numpy(g0))
+    d = s.step(1, diag=True).cpu().numpy()
+    f1, g1 = (t.cpu().numpy() for t in s.store_state())
+    fo, go, do = Oracle2D(cfg).step(f0, g0)
+    assert relerr(f1, fo) < 1e-12
+    assert relerr(g1, go) < 1e-12
+    scale = max(abs(do[0]), abs(do[1]), 1e-12)
+    assert np.all(np.abs(d[0, :3] - do[:3]) <= 1e-10 * scale + 1e-15)
+    assert abs(d[0, 3] - do[3]) <= 1e-12 * abs(do[3])
+
+
+def test_twenty_steps_2d():
+    cfg = CASES2["cyl32_n8_kn001"]
+    s = solver(cfg)
+    s.init_maxwellian()
+    d = s.step(20, diag=True).cpu().numpy()
+    f1, g1 = (t.cpu().numpy() for t in s.store_state())
+    o = Oracle2D(cfg)
+    fo, go, do = o.run(*o.init(), 20)
+    assert relerr(f1, fo) < 1e-9
+    assert relerr(g1, go) < 1e-9
+    assert np.max(np.abs(d[:, 0] - do[:, 0]) / np.abs(do[:, 0])) < 1e-9
+    assert np.max(np.abs(d[:, 3] - do[:, 3]) / do[:, 3]) < 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(CASES3))
+def test_one_step_3d(name):
+    cfg = CASES3[name]
+    f0, _ = random_state(cfg.ncell, cfg.nv, 3, seed=92, with_g=False)
+    s = solver(cfg)
+    s.load_state(torch.from_numpy(f0))
+    d = s.step(1, diag=True).cpu().numpy()
+    f1 = s.store_state()[0].cpu().numpy()
+    fo, do = Oracle3D(cfg).step(f0)
+    assert relerr(f1, fo) < 1e-12
+    scale = max(np.max(np.abs(do[:3])), 1e-12)
+    assert np.all(np.abs(d[0, :3] - do[:3]) <= 1e-10 * scale + 1e-15)
+    assert abs(d[0, 3] - do[3]) <= 1e-12 * abs(do[3])
+
+
+def test_ten_steps_3d():
+    cfg = CASES3["ragged_n8_cons"]
+    s = solver(cfg)
+    s.init_maxwellian()
+    d = s.step(10, diag=True).cpu().numpy()
+    f1 = s.store_state()[0].cpu().numpy()
+    o = Oracle3D(cfg)
+    fo, do = o.run(o.init(), 10)
+    assert relerr(f1, fo) < 1e-9
+    assert np.max(np.abs(d[:, 3] - do[:, 3]) / do[:, 3]) < 1e-12
+
+
+def test_stiff_relaxation_stays_bounded_gpu():
+    cfg = small_2d(64, 64, 16, kn=1e-6, mach=0.8, scheme=I,
+                   body=Body("circle", (0.5, 0.5, 0), (0.2, 0.2, 0), t_wall=1.3))
+    s = solver(cfg)
+    s.init_maxwellian()
+    f0 = s.store_state()[0]
+    s.step(50)
+    f, g = s.store_state()
+    assert bool(torch.isfinite(f).all()) and float(f.min()) >= 0.0
+    assert float(f.abs().max()) < 10 * float(f0.abs().max())
