@@ -73,6 +73,8 @@ class Config:
     name: str = ""
     maxwellian: str = "direct"  # "direct" moments or "conservative" (Newton) equilibrium
     scheme: str = "explicit"    # "explicit" or "imex" (semi-implicit relaxation)
+    model: str = "bgk"          # relaxation model: "bgk" or "shakhov"
+    prandtl: float = 2.0 / 3.0  # Prandtl number of the Shakhov model
 
     @property
     def ncell(self) -> int:

@@ -37,6 +37,8 @@ typedef struct {
   double vel[3], omega;    /* rigid body velocity at t = 0 */
   int maxwellian;          /* 0 direct moments, 1 conservative (Newton) */
   int scheme;              /* 0 explicit (ExSchemeDD), 1 semi-implicit (ImpSchemeDD) */
+  int model;               /* 0 BGK, 1 Shakhov */
+  double prandtl;          /* Prandtl number of the Shakhov model */
 } orc_cfg;
 
 typedef struct orc2d orc2d;
@@ -76,6 +78,10 @@ int  orc2d_adjoint(orc2d *o, int nsteps, int objective, double *out);
    one cell's (f, g): the direct moments, or the conservative solution;
    returns the Newton iterations taken (0 for direct), -1 if no convergence */
 int  orc2d_equilibrium(const orc2d *o, const double *f, const double *g, double *out);
+/* equilibria (f_eq, g_eq) of one cell's (f, g) at every velocity: eq. (BGKDD)
+   or eq. (ShakhovDD), with the triplet of orc2d_equilibrium */
+void orc2d_equilibrium_values(const orc2d *o, const double *f, const double *g, double *fe,
+                              double *ge);
 int  orc_threads(void);
 
 typedef struct orc3d orc3d;
@@ -100,6 +106,9 @@ void orc3d_moments(const orc3d *o, const double *F, double *out);
 /* triplet (rho, ux, uy, uz, T) of the equilibrium of one cell's F (direct
    or conservative); returns the Newton iterations, -1 if no convergence */
 int  orc3d_equilibrium(const orc3d *o, const double *F, double *out);
+/* equilibrium of one cell's F at every velocity: the Maxwellian of Section
+   2.1, or the Shakhov equilibrium given there */
+void orc3d_equilibrium_values(const orc3d *o, const double *F, double *Fe);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,7 @@ class _Cfg(C.Structure):
                 ("axes", C.c_double * 3), ("theta", C.c_double), ("t_wall", C.c_double),
                 ("mass", C.c_double), ("inertia", C.c_double), ("motion", C.c_int),
                 ("vel", C.c_double * 3), ("omega", C.c_double), ("maxwellian", C.c_int),
-                ("scheme", C.c_int)]
+                ("scheme", C.c_int), ("model", C.c_int), ("prandtl", C.c_double)]
 
 
 def cfg_struct(cfg) -> _Cfg:
@@ -51,6 +51,8 @@ def cfg_struct(cfg) -> _Cfg:
     s.omega = b.omega
     s.maxwellian = {"direct": 0, "conservative": 1}[getattr(cfg, "maxwellian", "direct")]
     s.scheme = {"explicit": 0, "imex": 1}[getattr(cfg, "scheme", "explicit")]
+    s.model = {"bgk": 0, "shakhov": 1}[getattr(cfg, "model", "bgk")]
+    s.prandtl = getattr(cfg, "prandtl", 2.0 / 3.0)
     return s
 
 
@@ -78,6 +80,7 @@ def lib():
         _lib.orc_threads.restype = C.c_int
         _lib.orc2d_adjoint.argtypes = [P, C.c_int, C.c_int, P]
         _lib.orc2d_equilibrium.argtypes = [P, P, P, P]
+        _lib.orc2d_equilibrium_values.argtypes = [P, P, P, P, P]
     return _lib
 
 
@@ -198,6 +201,13 @@ class Oracle2D:
                                      _p(np.ascontiguousarray(g1, dtype=np.float64)), _p(out))
         return out, it
 
+    def equilibrium_values(self, f1, g1):
+        """(f_eq, g_eq) of one cell's (f, g) at every velocity."""
+        fe, ge = np.zeros(self.nvel), np.zeros(self.nvel)
+        lib().orc2d_equilibrium_values(self._h, _p(np.ascontiguousarray(f1, dtype=np.float64)),
+                                       _p(np.ascontiguousarray(g1, dtype=np.float64)), _p(fe), _p(ge))
+        return fe, ge
+
     def moments(self, f, g):
         out = np.zeros((self.ncell, 9))
         lib().orc2d_moments(self._h, _p(np.ascontiguousarray(f)), _p(np.ascontiguousarray(g)), _p(out))
@@ -221,6 +231,7 @@ def _lib3():
         L.orc3d_force.argtypes = [P, P, P]
         L.orc3d_moments.argtypes = [P, P, P]
         L.orc3d_equilibrium.argtypes = [P, P, P]
+        L.orc3d_equilibrium_values.argtypes = [P, P, P]
         L._has3 = True
     return L
 
@@ -311,6 +322,12 @@ class Oracle3D:
         out = np.zeros(5)
         it = _lib3().orc3d_equilibrium(self._h, _p(np.ascontiguousarray(F1, dtype=np.float64)), _p(out))
         return out, it
+
+    def equilibrium_values(self, F1):
+        """F_eq of one cell's F at every velocity."""
+        Fe = np.zeros(self.nvel)
+        _lib3().orc3d_equilibrium_values(self._h, _p(np.ascontiguousarray(F1, dtype=np.float64)), _p(Fe))
+        return Fe
 
     def moments(self, F):
         out = np.zeros((self.ncell, 14))

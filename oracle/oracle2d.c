@@ -4,6 +4,7 @@
  * Dechriste & Mieussens (2015), written from the paper:
  *   velocity grid and discrete moments ......... Section 3.1, eq. (MacroscopicDDv)
  *   reduced BGK equilibria ..................... Section 2.2, eq. (BGKDD)
+ *   reduced Shakhov equilibria ................. Section 2.2, eq. (ShakhovDD)
  *   level set, cell types, lengths, normal ..... Appendix A.1-A.2
  *   master search (fusion) and eq. (ii) ........ Appendix A.3
  *   virtual-cell and control-volume areas ...... Appendix A.4
@@ -536,6 +537,51 @@ int orc2d_equilibrium(const orc2d *o, const double *f, const double *g, double *
   return it;
 }
 
+/* What the relaxation of one cell relaxes toward: the triplet above and, for
+   the Shakhov model, the heat flux q of eq. (MacroscopicDDv).  READING: q is
+   taken about the directly computed mean velocity, as printed, also when the
+   conservative equilibrium supplies the triplet. */
+typedef struct { double rho, ux, uy, T, qx, qy; } relax2;
+
+static void relax_target2(const orc2d *o, const double *f, const double *g, relax2 *t) {
+  equilibrium2(o, f, g, &t->rho, &t->ux, &t->uy, &t->T);
+  t->qx = t->qy = 0.0;
+  if (o->cfg.model != 1) return;
+  double r, ux, uy, T;
+  cell_moments(o, f, g, &r, &ux, &uy, &T);
+  double qx = 0.0, qy = 0.0;
+  for (int p2 = 0; p2 < o->N; ++p2)
+    for (int p1 = 0; p1 < o->N; ++p1) {
+      int p = p2 * o->N + p1;
+      double cx = o->v[p1] - ux, cy = o->v[p2] - uy;
+      double h = 0.5 * (cx * cx + cy * cy) * f[p] + g[p];
+      qx += cx * h * o->w;
+      qy += cy * h * o->w;
+    }
+  t->qx = qx; t->qy = qy;
+}
+
+/* Reduced equilibria at (vx, vy): eq. (BGKDD), or eq. (ShakhovDD) with the
+   pressure P = rho R T, R = 1. */
+static void equilibrium_at2(const orc2d *o, const relax2 *t, double vx, double vy, double *fe,
+                            double *ge) {
+  double M = maxw2(t->rho, t->ux, t->uy, t->T, vx, vy);
+  if (o->cfg.model != 1) { *fe = M; *ge = 0.5 * t->T * M; return; }
+  double cx = vx - t->ux, cy = vy - t->uy, c2 = cx * cx + cy * cy;
+  double P = t->rho * t->T;
+  double s = (1.0 - o->cfg.prandtl) * (cx * t->qx + cy * t->qy) / (5.0 * P * t->T);
+  *fe = M * (1.0 + s * (c2 / t->T - 4.0));
+  *ge = 0.5 * t->T * M * (1.0 + s * (c2 / t->T - 2.0));
+}
+
+void orc2d_equilibrium_values(const orc2d *o, const double *f, const double *g, double *fe,
+                              double *ge) {
+  relax2 t;
+  relax_target2(o, f, g, &t);
+  for (int p = 0; p < o->nvel; ++p)
+    equilibrium_at2(o, &t, o->v[p % o->N], o->v[p / o->N], &fe[p], &ge[p]);
+}
+
 /* wall velocity of the boundary point r, eq. (uwDD) */
 static void wall_velocity(const orc2d *o, double rx, double ry, double *uwx, double *uwy) {
   double ax = rx - o->c[0], ay = ry - o->c[1];
@@ -583,10 +629,11 @@ static void scheme_cv(const orc2d *o, const geo2d *G, const double *fm,
   double dt = o->dt;
   const double *fc = fm + (size_t)m * nvel, *gc = gm + (size_t)m * nvel;
   double S = G->scv[m];
-  double rho, ux, uy, T;
   /* READING: with the conservative equilibrium the whole triplet, rho in
      the relaxation time included, comes from the Newton solution */
-  equilibrium2(o, fc, gc, &rho, &ux, &uy, &T);
+  relax2 tg;
+  relax_target2(o, fc, gc, &tg);
+  double rho = tg.rho;
   int collide = o->cfg.kn > 0.0;
   double tau = collide ? tau_of(o, rho) : 1.0;
   /* transport residual R_p = sum over members of (F_x+ - F_x-) + (F_y+ - F_y-) + F_w */
@@ -649,12 +696,13 @@ static void scheme_cv(const orc2d *o, const geo2d *G, const double *fm,
     double rn, uxn, uyn, Tn;
     cell_moments(o, fc, gc, &rn, &uxn, &uyn, &Tn);
     double nu = collide ? dt / tau_of(o, rn) : 0.0;
-    double r1, ux1, uy1, T1;
-    equilibrium2(o, fs, gs, &r1, &ux1, &uy1, &T1);
+    relax2 t1;
+    relax_target2(o, fs, gs, &t1);
     for (int p = 0; p < nvel; ++p) {
-      double E = collide ? maxw2(r1, ux1, uy1, T1, o->v[p % N], o->v[p / N]) : 0.0;
+      double E = 0.0, Ge = 0.0;
+      if (collide) equilibrium_at2(o, &t1, o->v[p % N], o->v[p / N], &E, &Ge);
       fo[p] = (fs[p] + nu * E) / (1.0 + nu);
-      go[p] = (gs[p] + nu * 0.5 * T1 * E) / (1.0 + nu);
+      go[p] = (gs[p] + nu * Ge) / (1.0 + nu);
     }
     free(fs); free(gs); free(R); free(Rg);
     return;
@@ -662,10 +710,7 @@ static void scheme_cv(const orc2d *o, const geo2d *G, const double *fm,
   for (int p = 0; p < nvel; ++p) {
     double vx = o->v[p % N], vy = o->v[p / N];
     double E = 0.0, Ge = 0.0;
-    if (collide) {
-      E = maxw2(rho, ux, uy, T, vx, vy);   /* eq. (BGKDD) */
-      Ge = 0.5 * T * E;
-    }
+    if (collide) equilibrium_at2(o, &tg, vx, vy, &E, &Ge);   /* eq. (BGKDD) / (ShakhovDD) */
     double ratio = S / snew;
     double fnew = ratio * fc[p] - dt / snew * R[p];
     double gnew = ratio * gc[p] - dt / snew * Rg[p];
@@ -1091,7 +1136,7 @@ static void cv_sum(const orc2d *o, const geo2d *G, const double *a, double *L) {
    dJ/du_y (u = farfield velocity). Fixed bodies only. */
 int orc2d_adjoint(orc2d *o, int nsteps, int objective, double *out) {
   if (o->cfg.motion != 0 && o->cfg.body_kind != 0) return -1;
-  if (o->cfg.maxwellian || o->cfg.scheme) return -1;   /* transpose written for the explicit direct step */
+  if (o->cfg.maxwellian || o->cfg.scheme || o->cfg.model) return -1;   /* transpose written for the explicit direct BGK step */
   int nvel = o->nvel, N = o->N;
   size_t tot = (size_t)o->ncell * nvel;
   const geo2d *G = &o->g[o->cur];

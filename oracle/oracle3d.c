@@ -3,6 +3,7 @@
  * Plain serial-order FP64 implementation of the 3D cut-cell method of
  * Dechriste & Mieussens (2015), Section 5.1 (fixed body):
  *   moments and Maxwellian ........................ Section 2.1, eqs. (MacroscopicTD), (MaxwellianTD)
+ *   Shakhov equilibrium ........................... Section 2.1
  *   diffuse wall with zero net mass flux ........... Section 5.1 step 4
  *   explicit scheme with seven virtual faces ....... eq. (eq-schema3D)
  *   control volumes, merge, redistribution ......... Section 5.1 steps 2, 6, 7
@@ -424,6 +425,46 @@ int orc3d_equilibrium(const orc3d *o, const double *F, double *out) {
   return it;
 }
 
+/* What the relaxation of one cell relaxes toward: the triplet and, for the
+   Shakhov model, the heat flux q of eq. (MacroscopicTD), taken about the
+   directly computed mean velocity (READING, as in 2D). */
+typedef struct { double rho, u[3], T, q[3]; } relax3;
+
+static void relax_target3(const orc3d *o, const double *F, relax3 *t) {
+  equilibrium3(o, F, &t->rho, t->u, &t->T);
+  t->q[0] = t->q[1] = t->q[2] = 0.0;
+  if (o->cfg.model != 1) return;
+  int N = o->N;
+  double r, u[3], T;
+  moments3(o, F, &r, u, &T);
+  for (int p = 0; p < o->nvel; ++p) {
+    double c[3] = {o->v[p % N] - u[0], o->v[(p / N) % N] - u[1], o->v[p / (N * N)] - u[2]};
+    double h = 0.5 * (c[0] * c[0] + c[1] * c[1] + c[2] * c[2]) * F[p] * o->w;
+    for (int d = 0; d < 3; ++d) t->q[d] += c[d] * h;
+  }
+}
+
+/* equilibrium at v: the Maxwellian (BGK) or the Shakhov function of Section
+   2.1, M [1 + (1 - Pr) (v - u).q (|v - u|^2/(R T) - 5) / (5 P R T)],
+   P = rho R T, R = 1 */
+static double equilibrium_at3(const orc3d *o, const relax3 *t, double vx, double vy, double vz) {
+  double M = maxw3(t->rho, t->u, t->T, vx, vy, vz);
+  if (o->cfg.model != 1) return M;
+  double c[3] = {vx - t->u[0], vy - t->u[1], vz - t->u[2]};
+  double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+  double cq = c[0] * t->q[0] + c[1] * t->q[1] + c[2] * t->q[2];
+  double P = t->rho * t->T;
+  return M * (1.0 + (1.0 - o->cfg.prandtl) * cq * (c2 / t->T - 5.0) / (5.0 * P * t->T));
+}
+
+void orc3d_equilibrium_values(const orc3d *o, const double *F, double *Fe) {
+  relax3 t;
+  relax_target3(o, F, &t);
+  int N = o->N;
+  for (int p = 0; p < o->nvel; ++p)
+    Fe[p] = equilibrium_at3(o, &t, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]);
+}
+
 /* scheme (eq-schema3D) for control volume m, fixed geometry */
 static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
   int nvel = o->nvel, N = o->N, nx = o->nx, ny = o->ny, nz = o->nz;
@@ -431,10 +472,11 @@ static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
   const double *in = o->cfg.inflow;
   double uin[3] = {in[1], in[2], in[3]};
   double Tw = o->cfg.t_wall, zero[3] = {0, 0, 0};
-  double rho, u[3], T;
   /* READING: conservative equilibrium -> the whole triplet, rho in tau
      included, from the Newton solution */
-  equilibrium3(o, fc, &rho, u, &T);
+  relax3 tg;
+  relax_target3(o, fc, &tg);
+  double rho = tg.rho;
   int collide = o->cfg.kn > 0.0;
   double tau = collide ? sqrt(M_PI) / 2.0 * (1.0 / rho) * o->cfg.kn * o->cfg.lref / sqrt(2.0) : 1.0;
   double V = o->vcv[m];
@@ -486,17 +528,17 @@ static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
     double rn, un[3], Tn;
     moments3(o, fc, &rn, un, &Tn);
     double nu = collide ? o->dt / (sqrt(M_PI) / 2.0 * (1.0 / rn) * o->cfg.kn * o->cfg.lref / sqrt(2.0)) : 0.0;
-    double r1, u1[3], T1;
-    equilibrium3(o, fs, &r1, u1, &T1);
+    relax3 t1;
+    relax_target3(o, fs, &t1);
     for (int p = 0; p < nvel; ++p) {
-      double E = collide ? maxw3(r1, u1, T1, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]) : 0.0;
+      double E = collide ? equilibrium_at3(o, &t1, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]) : 0.0;
       out[p] = (fs[p] + nu * E) / (1.0 + nu);
     }
     free(fs); free(R); free(fw);
     return;
   }
   for (int p = 0; p < nvel; ++p) {
-    double E = collide ? maxw3(rho, u, T, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]) : 0.0;
+    double E = collide ? equilibrium_at3(o, &tg, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]) : 0.0;
     double fnew = fc[p] - o->dt / V * R[p];
     if (collide) fnew += o->dt / tau * (E - fc[p]);
     out[p] = fnew;

@@ -19,6 +19,23 @@ def maxwellian(rho, ux, uy, T, vx, vy):
     return rho / (2 * math.pi * T) * math.exp(-((vx - ux) ** 2 + (vy - uy) ** 2) / (2 * T))
 
 
+def shakhov_2d(cfg, vel, w, rho, ux, uy, T, f, g, M):
+    """(f_eq, g_eq): eq. BGKDD, or eq. ShakhovDD when cfg.model is "shakhov",
+    with the heat flux of (f, g) about their own mean velocity."""
+    if getattr(cfg, "model", "bgk") != "shakhov":
+        return M, 0.5 * T * M
+    vx = np.array([a for a, _ in vel])
+    vy = np.array([b for _, b in vel])
+    mux, muy = (vx * f).sum() / f.sum(), (vy * f).sum() / f.sum()
+    cxd, cyd = vx - mux, vy - muy
+    h = 0.5 * (cxd ** 2 + cyd ** 2) * f + g
+    qx, qy = (cxd * h).sum() * w, (cyd * h).sum() * w
+    cx, cy = vx - ux, vy - uy
+    c2 = (cx ** 2 + cy ** 2) / T
+    s = (1 - cfg.prandtl) * (cx * qx + cy * qy) / (5 * rho * T * T)
+    return M * (1 + s * (c2 - 4)), 0.5 * T * M * (1 + s * (c2 - 2))
+
+
 def brute_step(cfg, geo, v, dt, f, g, collide=True, imex=False):
     nx, ny = cfg.n[0], cfg.n[1]
     N = cfg.nv
@@ -119,8 +136,9 @@ def brute_step(cfg, geo, v, dt, f, g, collide=True, imex=False):
             E = sum((0.5 * (vel[p][0] ** 2 + vel[p][1] ** 2) * newf[p] + newg[p]) for p in range(nvel)) * w
             T = (2 * E / rho - ux * ux - uy * uy) / 3
             Eq = np.array([maxwellian(rho, ux, uy, T, vx, vy) for vx, vy in vel])
-            newf = (newf + nu * Eq) / (1 + nu)
-            newg = (newg + nu * 0.5 * T * Eq) / (1 + nu)
+            Ef, Eg = shakhov_2d(cfg, vel, w, rho, ux, uy, T, newf, newg, Eq)
+            newf = (newf + nu * Ef) / (1 + nu)
+            newg = (newg + nu * Eg) / (1 + nu)
         elif collide:
             rho = sum(fm) * w
             ux = sum(vel[p][0] * fm[p] for p in range(nvel)) * w / rho
@@ -129,8 +147,9 @@ def brute_step(cfg, geo, v, dt, f, g, collide=True, imex=False):
             T = (2 * E / rho - ux * ux - uy * uy) / 3
             tau = tau_c / rho
             Eq = np.array([maxwellian(rho, ux, uy, T, vx, vy) for vx, vy in vel])
-            newf = newf + dt / tau * (Eq - fm)
-            newg = newg + dt / tau * (0.5 * T * Eq - gm)
+            Ef, Eg = shakhov_2d(cfg, vel, w, rho, ux, uy, T, fm, gm, Eq)
+            newf = newf + dt / tau * (Ef - fm)
+            newg = newg + dt / tau * (Eg - gm)
         for c in mem:
             out_f[c] = newf
             out_g[c] = newg
@@ -140,6 +159,21 @@ def brute_step(cfg, geo, v, dt, f, g, collide=True, imex=False):
 def maxwellian3(rho, u, T, v):
     c2 = (v[0] - u[0]) ** 2 + (v[1] - u[1]) ** 2 + (v[2] - u[2]) ** 2
     return rho / (2 * math.pi * T) ** 1.5 * math.exp(-c2 / (2 * T))
+
+
+def shakhov_3d(cfg, vd, w, rho, u, T, F, M):
+    """The Maxwellian M, or the 3D Shakhov equilibrium (Section 2.1) when
+    cfg.model is "shakhov", with the heat flux of F about its mean velocity."""
+    if getattr(cfg, "model", "bgk") != "shakhov":
+        return M
+    mu = [(vd[d] * F).sum() / F.sum() for d in range(3)]
+    cd = [vd[d] - mu[d] for d in range(3)]
+    h = 0.5 * (cd[0] ** 2 + cd[1] ** 2 + cd[2] ** 2) * F
+    q = [(cd[d] * h).sum() * w for d in range(3)]
+    c = [vd[d] - u[d] for d in range(3)]
+    c2 = (c[0] ** 2 + c[1] ** 2 + c[2] ** 2) / T
+    s = (1 - cfg.prandtl) * (c[0] * q[0] + c[1] * q[1] + c[2] * q[2]) / (5 * rho * T * T)
+    return M * (1 + s * (c2 - 5))
 
 
 def brute_step_3d(cfg, geo, v, dt, F, collide=True, imex=False):
@@ -223,14 +257,14 @@ def brute_step_3d(cfg, geo, v, dt, F, collide=True, imex=False):
             u = [float((vd[d] * new).sum() * w / rho) for d in range(3)]
             E = float((0.5 * (vd[0] ** 2 + vd[1] ** 2 + vd[2] ** 2) * new).sum() * w)
             T = (2 * E / rho - u[0] ** 2 - u[1] ** 2 - u[2] ** 2) / 3
-            Eq = np.array([maxwellian3(rho, u, T, q) for q in vel])
+            Eq = shakhov_3d(cfg, vd, w, rho, u, T, new, np.array([maxwellian3(rho, u, T, q) for q in vel]))
             new = (new + nu * Eq) / (1 + nu)
         elif collide:
             rho = fm.sum() * w
             u = [float((vd[d] * fm).sum() * w / rho) for d in range(3)]
             E = float((0.5 * (vd[0] ** 2 + vd[1] ** 2 + vd[2] ** 2) * fm).sum() * w)
             T = (2 * E / rho - u[0] ** 2 - u[1] ** 2 - u[2] ** 2) / 3
-            Eq = np.array([maxwellian3(rho, u, T, q) for q in vel])
+            Eq = shakhov_3d(cfg, vd, w, rho, u, T, fm, np.array([maxwellian3(rho, u, T, q) for q in vel]))
             new = new + dt / (tau_c / rho) * (Eq - fm)
         for c in mem:
             out[c] = new
