@@ -147,6 +147,9 @@ def main():
     ap.add_argument("--scheme", default="explicit", choices=["explicit", "imex"],
                     help="time scheme: explicit (default) or semi-implicit (transport explicit, "
                          "relaxation implicit)")
+    ap.add_argument("--model", default="bgk", choices=["bgk", "shakhov"],
+                    help="relaxation model: BGK (default) or Shakhov (Pr from --prandtl)")
+    ap.add_argument("--prandtl", type=float, default=2.0 / 3.0)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=40,
@@ -176,7 +179,8 @@ def main():
         return bench_batch(args)
 
     cfg = workload(args.workload, kn=args.kn).with_(maxwellian=args.maxwellian,
-                                                    scheme=args.scheme)
+                                                    scheme=args.scheme, model=args.model,
+                                                    prandtl=args.prandtl)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     s = Solver(cfg, device=dev)
@@ -232,7 +236,7 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload].format(kn=cfg.kn),
                    "cells": cfg.ncell, "active_cells": active, "velocities": nvel,
                    "cut_control_volumes": n_irr, "merged_cells": n_mem, "dt": s.dt,
-                   "maxwellian": args.maxwellian, "scheme": args.scheme,
+                   "maxwellian": args.maxwellian, "scheme": args.scheme, "model": args.model,
                    "drag_last_step": drag_last},
         "roofline": {"bound": "hbm", "kernel": "k_step2d" if cfg.dim == 2 else "k_step3d",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -250,7 +254,7 @@ def main():
     if args.scheme == "imex":
         out["roofline"]["relax_kernel_avg_us"] = round(rlx_ms / max(rlx_n, 1) * 1e3, 2)
     if (args.workload == "cyl512" and args.adjoint_steps > 0 and args.maxwellian == "direct"
-            and args.scheme == "explicit"):
+            and args.scheme == "explicit" and args.model == "bgk"):
         # adjoint over the same workload: forward alone vs forward with
         # checkpoints + recomputation + adjoint sweep (cc_adjoint)
         na, ka = args.adjoint_steps, args.adjoint_ckpt

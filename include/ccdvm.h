@@ -81,6 +81,14 @@ enum { CC_MAXW_DIRECT = 0, CC_MAXW_CONSERVATIVE = 1 };
  * twice (about twice the time of an explicit step) and is stable for
  * dt >> tau. */
 enum { CC_SCHEME_EXPLICIT = 0, CC_SCHEME_IMEX = 1 };
+/* Relaxation model: BGK (eq. BGKDD; 3D: the Maxwellian) or the Shakhov
+ * model (eq. ShakhovDD; 3D: the Shakhov equilibrium of Section 2.1), whose
+ * equilibrium multiplies the Maxwellian by a polynomial in v - u carrying
+ * the heat flux q of eq. MacroscopicDDv, so that the model has the Prandtl
+ * number `prandtl`.  q is taken about the directly computed mean velocity;
+ * with the conservative equilibrium the Newton triplet fills the rest of
+ * the formula.  Pr = 1 is BGK. */
+enum { CC_MODEL_BGK = 0, CC_MODEL_SHAKHOV = 1 };
 
 /* Flow set-up.  dim = 2 selects the reduced plane-flow model with the two
  * distributions f, g (Section 2.2); dim = 3 the full model with F
@@ -101,6 +109,8 @@ typedef struct {
                              no adjoint or batch) */
   int scheme;             /* CC_SCHEME_EXPLICIT or CC_SCHEME_IMEX (fixed bodies,
                              no adjoint or batch) */
+  int model;              /* CC_MODEL_BGK or CC_MODEL_SHAKHOV (no adjoint or batch) */
+  double prandtl;         /* Shakhov: Prandtl number, finite and > 0 */
 } cc_config;
 
 /* Obstacle given by an analytic signed distance, gas side positive

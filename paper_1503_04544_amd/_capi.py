@@ -24,7 +24,8 @@ class cc_config(C.Structure):
                 ("hi", C.c_double * 3), ("nv", C.c_int), ("vmin", C.c_double),
                 ("vmax", C.c_double), ("kn", C.c_double), ("lref", C.c_double),
                 ("cfl", C.c_double), ("dt", C.c_double), ("inflow", C.c_double * 5),
-                ("maxwellian", C.c_int), ("scheme", C.c_int)]
+                ("maxwellian", C.c_int), ("scheme", C.c_int), ("model", C.c_int),
+                ("prandtl", C.c_double)]
 
 
 class cc_body(C.Structure):
@@ -100,6 +101,8 @@ def make_config(cfg) -> cc_config:
     c.inflow[:] = [float(x) for x in cfg.inflow]
     c.maxwellian = {"direct": 0, "conservative": 1}[getattr(cfg, "maxwellian", "direct")]
     c.scheme = {"explicit": 0, "imex": 1}[getattr(cfg, "scheme", "explicit")]
+    c.model = {"bgk": 0, "shakhov": 1}[getattr(cfg, "model", "bgk")]
+    c.prandtl = getattr(cfg, "prandtl", 2.0 / 3.0)
     return c
 
 

@@ -121,6 +121,9 @@ void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
   ctx->s.pose = cv.take<double>(4);
   ctx->s.mom = cv.take<double>(n * nm);
   ctx->s.mom2 = cv.take<double>(ctx->dim == 2 ? n * 4 : 0);
+  const bool sk = ctx->cfg.model == CC_MODEL_SHAKHOV;
+  ctx->s.heat = sk ? cv.take<double>(n * (ctx->dim == 2 ? 2 : 3)) : nullptr;
+  ctx->s.heat2 = sk && ctx->dim == 2 ? cv.take<double>(n * 2) : nullptr;
   ctx->s.nu = cv.take<double>(n);
   ctx->s.part = ctx->dim == 3 ? cv.take<double>(n * (size_t)chunks3d(ctx->N) * 5) : nullptr;
   ctx->s.fslot = cv.take<double>(n * 3 * 2);
@@ -213,6 +216,10 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   if (c.maxwellian == CC_MAXW_CONSERVATIVE && body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_NONE)
     return reject("the conservative equilibrium is available for fixed bodies");
   if (c.scheme != CC_SCHEME_EXPLICIT && c.scheme != CC_SCHEME_IMEX) return reject("unknown scheme");
+  if (c.model != CC_MODEL_BGK && c.model != CC_MODEL_SHAKHOV) return reject("unknown relaxation model");
+  if (c.model == CC_MODEL_SHAKHOV && !(c.prandtl > 0.0 && isfinite(c.prandtl)))
+    return reject("the Shakhov model needs a finite Prandtl number > 0");
+  if (c.model == CC_MODEL_SHAKHOV && c.dim == 3) return reject("the Shakhov model is available in 2D");
   if (c.scheme == CC_SCHEME_IMEX && body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_NONE)
     return reject("the semi-implicit scheme is available for fixed bodies");
   ctx->dim = c.dim;
@@ -596,8 +603,9 @@ cc_status cc_adjoint(cc_ctx* ctx, int nsteps, int ckpt_every, int objective, voi
     return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   if (ctx->dim != 2 || is_moving(ctx)) return fail(ctx, CC_EINVAL, "the adjoint covers 2D fixed bodies");
-  if (ctx->cfg.maxwellian != CC_MAXW_DIRECT || ctx->cfg.scheme != CC_SCHEME_EXPLICIT)
-    return fail(ctx, CC_EINVAL, "the adjoint is written for the explicit scheme with the direct equilibrium");
+  if (ctx->cfg.maxwellian != CC_MAXW_DIRECT || ctx->cfg.scheme != CC_SCHEME_EXPLICIT ||
+      ctx->cfg.model != CC_MODEL_BGK)
+    return fail(ctx, CC_EINVAL, "the adjoint is written for the explicit BGK scheme with the direct equilibrium");
   if ((uintptr_t)pool % kAlign) return fail(ctx, CC_EINVAL, "pool must be 256-byte aligned");
   cc_status st = cc_init_maxwellian(ctx);
   if (st != CC_OK) return st;
@@ -684,7 +692,8 @@ cc_status cc_batch_create(cc_ctx* const* ctxs, int n, cc_batch** out) {
   for (int i = 0; i < n; ++i) {
     cc_ctx* c = ctxs[i];
     bool ok = c && c->bound && c->dim == 2 && !is_moving(c) && c->cfg.maxwellian == CC_MAXW_DIRECT &&
-              c->cfg.scheme == CC_SCHEME_EXPLICIT && batch_supported_nch(batch_group_nch(c));
+              c->cfg.scheme == CC_SCHEME_EXPLICIT && c->cfg.model == CC_MODEL_BGK &&
+              batch_supported_nch(batch_group_nch(c));
     for (int k = 0; k < i && ok; ++k) ok = ctxs[k] != c;
     if (ok && i > 0) ok = c->stream == ctxs[0]->stream;
     if (!ok) {

@@ -113,6 +113,8 @@ struct Scratch {
                      // 1/(2T), dt/tau, rho)
   double* part;      // 3D: per cell and velocity chunk, sums of F, v F, |v|^2 F
   double* mom2;      // 2D semi-implicit step: moments of the new state (ncell * 4)
+  double* heat;      // Shakhov: heat flux of each cell's control volume (2D: 2, 3D: 3 per cell)
+  double* heat2;     // 2D semi-implicit Shakhov step: heat flux of the new state
   double* nu;        // semi-implicit step: dt/tau of each control volume at t^n
   double* fslot;     // 2 x per irregular master: Fx, Fy, torque (2D) / Fx, Fy, Fz (3D)
   double* mpart;     // 2 x mass partials (regular tiles, then control volumes)

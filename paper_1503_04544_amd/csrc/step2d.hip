@@ -49,6 +49,8 @@ struct StepParams {
   double t_wall;
   int moving;
   int write_state;        // 0: cut-cell kernel only computes the wall forces
+  int shakhov;            // relaxation toward the Shakhov equilibria (eq. ShakhovDD)
+  double sk_coef;         // (1 - Pr)/5
 };
 
 __device__ inline void wall_velocity(const double* body, double rx, double ry, double* uwx,
@@ -61,6 +63,59 @@ __device__ inline void wall_velocity(const double* body, double rx, double ry, d
 __device__ inline double maxw_wall(double vx, double vy, double uwx, double uwy, double Tw) {
   double ex = vx - uwx, ey = vy - uwy;
   return exp(-(ex * ex + ey * ey) / (2.0 * Tw)) / (2.0 * M_PI * Tw);
+}
+
+// Velocity sums of one control volume's (f, g), from which eq.
+// (MacroscopicDDv) gives rho, u, T and, with SK, the heat flux.  q is
+// expanded in sums about v = 0 so that one pass over the values suffices:
+//   q = 1/2 [S3 - 2 S2 u - u tr S2 + 2 rho |u|^2 u] + G1 - u G0,
+// S2 = sum v v^T f, S3 = sum |v|^2 v f, G1 = sum v g, G0 = sum g.
+template <bool SK>
+struct Sums2 {
+  double r = 0.0, mx = 0.0, my = 0.0, e = 0.0;
+  double xx = 0.0, xy = 0.0, yy = 0.0, x3 = 0.0, y3 = 0.0, gx = 0.0, gy = 0.0;
+  __device__ inline void add(double vx, double vy, double f, double g) {
+    r += f; mx += vx * f; my += vy * f;
+    e += 0.5 * (vx * vx + vy * vy) * f + g;
+    if (SK) {
+      const double v2 = vx * vx + vy * vy;
+      xx += vx * vx * f; xy += vx * vy * f; yy += vy * vy * f;
+      x3 += vx * v2 * f; y3 += vy * v2 * f;
+      gx += vx * g; gy += vy * g;
+    }
+  }
+  template <class Red>
+  __device__ inline void reduce(Red red) {
+    r = red(r); mx = red(mx); my = red(my); e = red(e);
+    if (SK) {
+      xx = red(xx); xy = red(xy); yy = red(yy); x3 = red(x3); y3 = red(y3);
+      gx = red(gx); gy = red(gy);
+    }
+  }
+  // mo = (rho, ux, uy, T); with SK hq = (qx, qy).  w = dv^2.
+  __device__ inline void finish(double w, double* mo, double* hq) const {
+    const double rho = r * w, ux = mx * w / rho, uy = my * w / rho, en = e * w;
+    mo[0] = rho; mo[1] = ux; mo[2] = uy;
+    mo[3] = (2.0 * en / rho - (ux * ux + uy * uy)) / 3.0;
+    if (SK) {
+      const double sxx = xx * w, sxy = xy * w, syy = yy * w, tr = sxx + syy;
+      const double g0 = en - 0.5 * tr, u2 = ux * ux + uy * uy;
+      hq[0] = 0.5 * (x3 * w - 2.0 * (sxx * ux + sxy * uy) - ux * tr + 2.0 * rho * u2 * ux) + gx * w - ux * g0;
+      hq[1] = 0.5 * (y3 * w - 2.0 * (sxy * ux + syy * uy) - uy * tr + 2.0 * rho * u2 * uy) + gy * w - uy * g0;
+    }
+  }
+};
+
+// Reduced Shakhov equilibria (eq. ShakhovDD) from the Maxwellian value M at
+// v, with c = v - u:  f_eq = M [1 + s (|c|^2/T - 4)],
+// g_eq = T/2 M [1 + s (|c|^2/T - 2)],  s = (1 - Pr) c.q / (5 P T), P = rho T
+// (R = 1).  a = (1 - Pr)/(5 rho T^2), invT = 1/T.
+__device__ inline void shakhov2(double a, double qx, double qy, double T, double invT, double cx,
+                                double cy, double M, double& Ef, double& Eg) {
+  const double s = a * (cx * qx + cy * qy);
+  const double c2T = (cx * cx + cy * cy) * invT;
+  Ef = M * (1.0 + s * (c2T - 4.0));
+  Eg = 0.5 * T * M * (1.0 + s * (c2T - 2.0));
 }
 
 // Block-wide exclusive scan of one int per thread (any block size up to
@@ -101,8 +156,9 @@ __device__ inline double block_sum4(double v, double* lds) {
 // t^n (eqs. StressTensorDD, eq-force, eq-torque), moments and mass of the
 // new value.  With write_state == 0 only the force is produced.
 // ---------------------------------------------------------------------
+template <bool SK>
 __device__ void cut_cv(const Geo2D& G, const double2* __restrict__ in, double2* __restrict__ out,
-                       double* __restrict__ mom, double* __restrict__ fslot,
+                       double* __restrict__ mom, double* __restrict__ heat, double* __restrict__ fslot,
                        double* __restrict__ mpart, const double* __restrict__ body,
                        const StepParams& P, int q, double* lds) {
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -113,6 +169,8 @@ __device__ void cut_cv(const Geo2D& G, const double2* __restrict__ in, double2* 
   const double rho = mom[4 * m + 0], ux = mom[4 * m + 1], uy = mom[4 * m + 2], T = mom[4 * m + 3];
   const double inv2T = 0.5 / T, A = rho / (2.0 * M_PI * T);
   const double dtau = P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
+  const double qx = SK ? heat[2 * m] : 0.0, qy = SK ? heat[2 * m + 1] : 0.0;
+  const double ska = SK ? P.sk_coef / (rho * T * T) : 0.0;
   const double S = G.scv[m];
   const double2* own = in + (size_t)m * nvel;
   const double Tw = P.t_wall;
@@ -136,7 +194,7 @@ __device__ void cut_cv(const Geo2D& G, const double2* __restrict__ in, double2* 
   }
   double sx[kMaxMembers], sy[kMaxMembers];
   for (int t = 0; t < kMaxMembers; ++t) { sx[t] = 0.0; sy[t] = 0.0; }
-  double sr = 0.0, smx = 0.0, smy = 0.0, se = 0.0;
+  Sums2<SK> sm;
   for (int p = tid; p < nvel; p += nth) {
     const int p1 = p % N, p2 = p / N;
     const double vx = vnode(P.vmin, P.dv, p1), vy = vnode(P.vmin, P.dv, p2);
@@ -181,17 +239,18 @@ __device__ void cut_cv(const Geo2D& G, const double2* __restrict__ in, double2* 
         sy[t] += cy_ * cn * fv;
       }
     }
-    double E = 0.0;
+    double E = 0.0, Eg = 0.0;
     if (dtau != 0.0) {
       const double ex = vx - ux, ey = vy - uy;
       E = A * exp(-ex * ex * inv2T) * exp(-ey * ey * inv2T);
+      if (SK) shakhov2(ska, qx, qy, T, 1.0 / T, ex, ey, E, E, Eg);
+      else Eg = 0.5 * T * E;
     }
     const double fn = o.x - P.dt / S * Rf + dtau * (E - o.x);
-    const double gn = o.y - P.dt / S * Rg + dtau * (0.5 * T * E - o.y);
+    const double gn = o.y - P.dt / S * Rg + dtau * (Eg - o.y);
     if (P.write_state)
       for (int t = 0; t < nm; ++t) out[(size_t)G.mem[b + t] * nvel + p] = make_double2(fn, gn);
-    sr += fn; smx += vx * fn; smy += vy * fn;
-    se += 0.5 * (vx * vx + vy * vy) * fn + gn;
+    sm.add(vx, vy, fn, gn);
   }
   double Fx = 0.0, Fy = 0.0, Tq = 0.0;
   for (int t = 0; t < nm; ++t) {
@@ -202,20 +261,20 @@ __device__ void cut_cv(const Geo2D& G, const double2* __restrict__ in, double2* 
     Fy += ay * G.lw[k];
     Tq += ((G.rwx[k] - body[0]) * ay - (G.rwy[k] - body[1]) * ax) * G.lw[k];
   }
-  sr = block_sum4(sr, lds); smx = block_sum4(smx, lds);
-  smy = block_sum4(smy, lds); se = block_sum4(se, lds);
+  sm.reduce([&](double v) { return block_sum4(v, lds); });
   if (tid == 0) {
-    const double r = sr * P.w, mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
-    const double Tn = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
+    double mo[4], hq[2];
+    sm.finish(P.w, mo, hq);
     if (P.write_state)
       for (int t = 0; t < nm; ++t) {
         const int k = G.mem[b + t];
-        mom[4 * k + 0] = r; mom[4 * k + 1] = mx; mom[4 * k + 2] = my; mom[4 * k + 3] = Tn;
+        for (int i = 0; i < 4; ++i) mom[4 * k + i] = mo[i];
+        if (SK) { heat[2 * k] = hq[0]; heat[2 * k + 1] = hq[1]; }
       }
     fslot[3 * q + 0] = Fx;
     fslot[3 * q + 1] = Fy;
     fslot[3 * q + 2] = Tq;
-    if (mpart) *mpart = S * r;
+    if (mpart) *mpart = S * mo[0];
   }
 }
 
@@ -226,7 +285,7 @@ __global__ void __launch_bounds__(256) k_cut_force2d(Geo2D G, const double2* __r
                                                      StepParams P) {
   __shared__ double lds[8];
   for (int q = blockIdx.x; q < G.counts[0]; q += gridDim.x)
-    cut_cv(G, in, nullptr, mom, fslot, nullptr, body, P, q, lds);
+    cut_cv<false>(G, in, nullptr, mom, nullptr, fslot, nullptr, body, P, q, lds);
 }
 
 // ---------------------------------------------------------------------
@@ -251,11 +310,16 @@ constexpr int kListBlocks = 512;   // grid of kernels that walk a list whose len
 #ifndef CCDVM_PREFETCH
 #define CCDVM_PREFETCH 4
 #endif
+// VGPRs the Shakhov variant needs beyond the BGK one (heat-flux sums, q and
+// the velocity offsets), taken from the prefetch budget
+#ifndef CCDVM_SK_REGS
+#define CCDVM_SK_REGS 24
+#endif
 // Chunks loaded ahead of the one computed.  Each chunk in flight costs 16
 // VGPRs and the row window 8 per chunk; the depth is capped so that a wave
 // stays within 256 VGPRs (2 waves per SIMD) without spilling.
-constexpr int prefetch_depth(int nch) {
-  int cap = (138 - 8 * nch) / 16;
+constexpr int prefetch_depth(int nch, bool sk = false) {
+  int cap = (138 - (sk ? CCDVM_SK_REGS : 0) - 8 * nch) / 16;
   int d = CCDVM_PREFETCH < cap ? CCDVM_PREFETCH : cap;
   d = d < 1 ? 1 : d;
   return d < nch - 1 ? d : (nch - 1 > 0 ? nch - 1 : 0);
@@ -266,6 +330,7 @@ struct FusedArgs {
   const double2* in;
   double2* out;
   double* mom;
+  double* heat;             // Shakhov: heat flux (qx, qy) per cell, else unused
   double* fslot;            // this step: 3 per control volume
   double* mpart;            // this step: ntiles tile partials, then n_irr
   const double* prev_fslot; // previous step (deferred reduction), may be null
@@ -319,6 +384,7 @@ struct TileArgs {
   const double2* in;
   double2* out;
   double* mom;
+  double* heat;
   double* mpart;
   const double2* ghost;
   int nx, ny, N, nvel, ngroups, seglen, split;
@@ -327,7 +393,7 @@ struct TileArgs {
 
 __host__ __device__ inline TileArgs tile_args(const Geo2D& G, const FusedArgs& A) {
   TileArgs T;
-  T.kind = A.kind; T.in = A.in; T.out = A.out; T.mom = A.mom; T.mpart = A.mpart;
+  T.kind = A.kind; T.in = A.in; T.out = A.out; T.mom = A.mom; T.heat = A.heat; T.mpart = A.mpart;
   T.ghost = G.ghost;
   T.nx = G.nx; T.ny = G.ny; T.N = G.N; T.nvel = G.nvel;
   T.ngroups = A.ngroups; T.seglen = A.seglen; T.split = A.split;
@@ -335,7 +401,7 @@ __host__ __device__ inline TileArgs tile_args(const Geo2D& G, const FusedArgs& A
   return T;
 }
 
-template <int NCH>
+template <int NCH, bool SK>
 __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, double* lds) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gi = tile % Ta.ngroups, seg = tile / Ta.ngroups;
@@ -360,13 +426,20 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
       const d2v* nrow = j + 1 < ny ? row + (size_t)nx * nvel : ghost;
       const bool reg = Ta.kind[c] == KIND_REGULAR;   // uniform over the wave
       double Am = 0.0, T = 1.0, dtau = 0.0, tx = 0.0, ty = 0.0;
+      double ux = 0.0, uy = 0.0, qx = 0.0, qy = 0.0, ska = 0.0, invT = 1.0;   // SK only
       if (reg) {
         const double* mc = Ta.mom + 4 * c;
-        const double rho = mc[0], ux = mc[1], uy = mc[2];
+        const double rho = mc[0];
+        ux = mc[1]; uy = mc[2];
         T = mc[3];
         const double inv2T = 0.5 / T;
         Am = rho / (2.0 * M_PI * T);
         dtau = P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
+        if (SK) {
+          qx = Ta.heat[2 * c]; qy = Ta.heat[2 * c + 1];
+          ska = P.sk_coef / (rho * T * T);
+          invT = 1.0 / T;
+        }
         if (lane < N) {
           const double v = vnode(P.vmin, P.dv, lane);
           tx = exp(-(v - ux) * (v - ux) * inv2T);
@@ -376,7 +449,7 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
       const d2v* xl = i > 0 ? row - nvel : ghost;        // x-upwind for v_x > 0
       const d2v* xr = i + 1 < nx ? row + nvel : ghost;   // x-upwind for v_x < 0
       d2v* orow = out + (size_t)c * nvel;
-      double sr = 0.0, smx = 0.0, smy = 0.0, se = 0.0;
+      Sums2<SK> sm;
       // software pipeline over the chunks: the loads of chunk k+PD are issued
       // before chunk k is computed; a scheduling barrier between chunks keeps
       // the live set to the window plus PD+1 chunks.
@@ -385,7 +458,7 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
       // across the row loop, which would cost ~10 VGPRs per chunk.
       int lv = lane;
       asm volatile("" : "+v"(lv));
-      constexpr int PD = prefetch_depth(NCH);
+      constexpr int PD = prefetch_depth(NCH, SK);
       d2v bN[NCH], bU[NCH], bXa[NCH], bXb[NCH];
       auto issue = [&](int k) {
         const int o = k * 64 + lv;
@@ -412,25 +485,25 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
           const double tyu = __shfl(ty, split + q2 < N ? split + q2 : 0, 64);
           if (o < lo_n) {   // lower half: v_y < 0, y-upwind is the cell above
             const double vy = vnode(P.vmin, P.dv, q2);
-            const double ay = cyf * fabs(vy), E = ex * tyl;
+            const double ay = cyf * fabs(vy);
+            double E = ex * tyl, Eg = 0.5 * T * E;
+            if (SK) shakhov2(ska, qx, qy, T, invT, vx - ux, vy - uy, ex * tyl, E, Eg);
             const d2v own = curL[k];
             const double fn = own.x - ax * (own.x - xa.x) - ay * (own.x - nL.x) + dtau * (E - own.x);
-            const double gn = own.y - ax * (own.y - xa.y) - ay * (own.y - nL.y) +
-                              dtau * (0.5 * T * E - own.y);
+            const double gn = own.y - ax * (own.y - xa.y) - ay * (own.y - nL.y) + dtau * (Eg - own.y);
             __builtin_nontemporal_store(d2v{fn, gn}, &orow[o]);
-            sr += fn; smx += vx * fn; smy += vy * fn;
-            se += 0.5 * (vx * vx + vy * vy) * fn + gn;
+            sm.add(vx, vy, fn, gn);
           }
           if (o < hi_n) {   // upper half: v_y >= 0, y-upwind is the cell below
             const double vy = vnode(P.vmin, P.dv, split + q2);
-            const double ay = cyf * fabs(vy), E = ex * tyu;
+            const double ay = cyf * fabs(vy);
+            double E = ex * tyu, Eg = 0.5 * T * E;
+            if (SK) shakhov2(ska, qx, qy, T, invT, vx - ux, vy - uy, ex * tyu, E, Eg);
             const d2v own = cU, yu = prevU[k];
             const double fn = own.x - ax * (own.x - xb.x) - ay * (own.x - yu.x) + dtau * (E - own.x);
-            const double gn = own.y - ax * (own.y - xb.y) - ay * (own.y - yu.y) +
-                              dtau * (0.5 * T * E - own.y);
+            const double gn = own.y - ax * (own.y - xb.y) - ay * (own.y - yu.y) + dtau * (Eg - own.y);
             __builtin_nontemporal_store(d2v{fn, gn}, &orow[lo_n + o]);
-            sr += fn; smx += vx * fn; smy += vy * fn;
-            se += 0.5 * (vx * vx + vy * vy) * fn + gn;
+            sm.add(vx, vy, fn, gn);
           }
         }
         prevU[k] = cU;
@@ -438,15 +511,15 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
         __builtin_amdgcn_sched_barrier(0);
       }
       if (reg) {
-        sr = wave_sum(sr); smx = wave_sum(smx); smy = wave_sum(smy); se = wave_sum(se);
-        const double r = sr * P.w;
+        sm.reduce([](double v) { return wave_sum(v); });
         if (lane == 0) {
-          const double mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
-          double* mo = Ta.mom + 4 * c;
-          mo[0] = r; mo[1] = mx; mo[2] = my;
-          mo[3] = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
+          double mo[4], hq[2];
+          sm.finish(P.w, mo, hq);
+          double* dst = Ta.mom + 4 * c;
+          dst[0] = mo[0]; dst[1] = mo[1]; dst[2] = mo[2]; dst[3] = mo[3];
+          if (SK) { Ta.heat[2 * c] = hq[0]; Ta.heat[2 * c + 1] = hq[1]; }
         }
-        msum += S * r;
+        msum += S * (sm.r * P.w);
       }
     }
   }
@@ -457,7 +530,7 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
 }
 
 // regular-cell tiles (+ block 0: deferred reduction of the previous step)
-template <int NCH>
+template <int NCH, bool SK>
 __global__ void __launch_bounds__(256) k_step2d(Geo2D G, FusedArgs A, StepParams P) {
   __shared__ double lds[8];
   const int bid = blockIdx.x;
@@ -471,14 +544,17 @@ __global__ void __launch_bounds__(256) k_step2d(Geo2D G, FusedArgs A, StepParams
   const int per = A.ntiles_pad / 8;
   const int tile = (b % 8) * per + b / 8;
   if (tile >= A.ntiles) return;
-  regular_tile<NCH>(tile_args(G, A), P, tile, lds);
+  regular_tile<NCH, SK>(tile_args(G, A), P, tile, lds);
 }
 
 // cut / merged control volumes of one step, one 256-thread block each
 __global__ void __launch_bounds__(256) k_cutstep2d(Geo2D G, FusedArgs A, StepParams P) {
   __shared__ double lds[8];
   const int q = blockIdx.x;
-  cut_cv(G, A.in, A.out, A.mom, A.fslot, A.mpart + A.ntiles + q, A.body, P, q, lds);
+  if (P.shakhov)
+    cut_cv<true>(G, A.in, A.out, A.mom, A.heat, A.fslot, A.mpart + A.ntiles + q, A.body, P, q, lds);
+  else
+    cut_cv<false>(G, A.in, A.out, A.mom, nullptr, A.fslot, A.mpart + A.ntiles + q, A.body, P, q, lds);
 }
 
 // final reduction of the last step of a call (same code as the deferred one)
@@ -491,14 +567,15 @@ __global__ void __launch_bounds__(256) k_final_reduce2d(Geo2D G, FusedArgs A) {
 // Merge (eq. FusionDD) of control volumes with several members, in place,
 // followed by the moments of the merged value.
 // ---------------------------------------------------------------------
+template <bool SK>
 __device__ void merge_cv(Geo2D G, double2* __restrict__ st, double* __restrict__ mom,
-                         const StepParams& P, int q) {
+                         double* __restrict__ heat, const StepParams& P, int q) {
   const int lane = threadIdx.x;
   const int m = G.irr[q];
   const int b = G.mptr[q], e = G.mptr[q + 1];
   const int N = G.N, nvel = G.nvel;
   const double S = G.scv[m];
-  double sr = 0.0, smx = 0.0, smy = 0.0, se = 0.0;
+  Sums2<SK> sm;
   for (int p = lane; p < nvel; p += kWave) {
     double af = 0.0, ag = 0.0;
     if (e - b > 1) {
@@ -515,45 +592,57 @@ __device__ void merge_cv(Geo2D G, double2* __restrict__ st, double* __restrict__
       af = v.x; ag = v.y;
     }
     const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
-    sr += af; smx += vx * af; smy += vy * af;
-    se += 0.5 * (vx * vx + vy * vy) * af + ag;
+    sm.add(vx, vy, af, ag);
   }
-  sr = wave_sum(sr); smx = wave_sum(smx); smy = wave_sum(smy); se = wave_sum(se);
+  sm.reduce([](double v) { return wave_sum(v); });
   if (lane == 0) {
-    double r = sr * P.w, mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
-    double Tn = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
+    double mo[4], hq[2];
+    sm.finish(P.w, mo, hq);
     for (int t = b; t < e; ++t) {
       const int k = G.mem[t];
-      mom[4 * k + 0] = r; mom[4 * k + 1] = mx; mom[4 * k + 2] = my; mom[4 * k + 3] = Tn;
+      for (int i = 0; i < 4; ++i) mom[4 * k + i] = mo[i];
+      if (SK) { heat[2 * k] = hq[0]; heat[2 * k + 1] = hq[1]; }
     }
   }
 }
 
 __global__ void __launch_bounds__(64) k_merge2d(Geo2D G, double2* __restrict__ st,
-                                                double* __restrict__ mom, StepParams P) {
-  for (int q = blockIdx.x; q < G.counts[0]; q += gridDim.x) merge_cv(G, st, mom, P, q);
+                                                double* __restrict__ mom, double* __restrict__ heat,
+                                                StepParams P) {
+  for (int q = blockIdx.x; q < G.counts[0]; q += gridDim.x) {
+    if (P.shakhov) merge_cv<true>(G, st, mom, heat, P, q);
+    else merge_cv<false>(G, st, mom, nullptr, P, q);
+  }
 }
 
-// moments (rho, u, T) of every non-solid cell, one wave per cell
+// moments (rho, u, T; with SK the heat flux) of every non-solid cell, one
+// wave per cell
+template <bool SK>
+__device__ void cell_moments2d(const Geo2D& G, const double2* __restrict__ st, double* __restrict__ mom,
+                               double* __restrict__ heat, const StepParams& P, int c, int lane) {
+  const int N = G.N, nvel = G.nvel;
+  Sums2<SK> sm;
+  for (int p = lane; p < nvel; p += kWave) {
+    const double2 v = st[(size_t)c * nvel + p];
+    sm.add(vnode(P.vmin, P.dv, p % N), vnode(P.vmin, P.dv, p / N), v.x, v.y);
+  }
+  sm.reduce([](double v) { return wave_sum(v); });
+  if (lane == 0) {
+    double mo[4], hq[2];
+    sm.finish(P.w, mo, hq);
+    for (int i = 0; i < 4; ++i) mom[4 * c + i] = mo[i];
+    if (SK) { heat[2 * c] = hq[0]; heat[2 * c + 1] = hq[1]; }
+  }
+}
+
 __global__ void __launch_bounds__(256) k_mom2d(Geo2D G, const double2* __restrict__ st,
-                                               double* __restrict__ mom, StepParams P) {
+                                               double* __restrict__ mom, double* __restrict__ heat,
+                                               StepParams P) {
   const int lane = threadIdx.x & (kWave - 1);
   const int c = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
   if (c >= G.ncell || G.kind[c] == KIND_SOLID) return;
-  const int N = G.N, nvel = G.nvel;
-  double sr = 0.0, smx = 0.0, smy = 0.0, se = 0.0;
-  for (int p = lane; p < nvel; p += kWave) {
-    const double2 v = st[(size_t)c * nvel + p];
-    const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
-    sr += v.x; smx += vx * v.x; smy += vy * v.x;
-    se += 0.5 * (vx * vx + vy * vy) * v.x + v.y;
-  }
-  sr = wave_sum(sr); smx = wave_sum(smx); smy = wave_sum(smy); se = wave_sum(se);
-  if (lane == 0) {
-    double r = sr * P.w, mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
-    mom[4 * c + 0] = r; mom[4 * c + 1] = mx; mom[4 * c + 2] = my;
-    mom[4 * c + 3] = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
-  }
+  if (P.shakhov) cell_moments2d<true>(G, st, mom, heat, P, c, lane);
+  else cell_moments2d<false>(G, st, mom, nullptr, P, c, lane);
 }
 
 // full moments for output: rho, ux, uy, T, Sxx, Sxy, Syy, qx, qy
@@ -705,43 +794,56 @@ __global__ void __launch_bounds__(256) k_imex_nu2d(Geo2D G, const double* __rest
 // Semi-implicit step, last part: the implicit relaxation of every non-solid
 // cell's transported value (f*, g*) toward the equilibrium of its control
 // volume's transported moments (direct or conservative triplet in mom):
-// f = (f* + nu E)/(1 + nu), g = (g* + nu T/2 E)/(1 + nu).  Masters also
-// write the direct moments of the new value to mom_next.  One wave per cell.
+// f = (f* + nu f_eq)/(1 + nu), g = (g* + nu g_eq)/(1 + nu) (eq. BGKDD or
+// ShakhovDD).  Masters also write the direct moments (and the heat flux) of
+// the new value to mom_next (heat_next).  One wave per cell.
+template <bool SK>
+__device__ void relax_cell2d(const Geo2D& G, double2* __restrict__ st, const double* __restrict__ mom,
+                             const double* __restrict__ heat, const double* __restrict__ nu,
+                             double* __restrict__ mom_next, double* __restrict__ heat_next,
+                             const StepParams& P, int c, int m, int lane) {
+  const int N = G.N, nvel = G.nvel;
+  const double* mc = mom + 4 * (size_t)m;
+  const double rho = mc[0], ux = mc[1], uy = mc[2], T = mc[3];
+  const double A = rho / (2.0 * M_PI * T), inv2T = 0.5 / T;
+  const double qx = SK ? heat[2 * m] : 0.0, qy = SK ? heat[2 * m + 1] : 0.0;
+  const double ska = SK ? P.sk_coef / (rho * T * T) : 0.0, invT = 1.0 / T;
+  const double nv = nu[m], sc = 1.0 / (1.0 + nv);
+  double2* row = st + (size_t)c * nvel;
+  Sums2<SK> sm;
+  for (int p = lane; p < nvel; p += kWave) {
+    const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
+    const double cx = vx - ux, cy = vy - uy;
+    double E = A * exp(-(cx * cx + cy * cy) * inv2T), Eg = 0.5 * T * E;
+    if (SK) shakhov2(ska, qx, qy, T, invT, cx, cy, E, E, Eg);
+    const double2 o = row[p];
+    const double fn = (o.x + nv * E) * sc;
+    const double gn = (o.y + nv * Eg) * sc;
+    row[p] = make_double2(fn, gn);
+    sm.add(vx, vy, fn, gn);
+  }
+  if (c != m) return;
+  sm.reduce([](double v) { return wave_sum(v); });
+  if (lane == 0) {
+    double hq[2];
+    sm.finish(P.w, mom_next + 4 * (size_t)c, hq);
+    if (SK) { heat_next[2 * c] = hq[0]; heat_next[2 * c + 1] = hq[1]; }
+  }
+}
+
 __global__ void __launch_bounds__(256) k_relax2d(Geo2D G, double2* __restrict__ st,
                                                 const double* __restrict__ mom,
+                                                const double* __restrict__ heat,
                                                 const double* __restrict__ nu,
-                                                double* __restrict__ mom_next, StepParams P) {
+                                                double* __restrict__ mom_next,
+                                                double* __restrict__ heat_next, StepParams P) {
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= G.ncell) return;
   const int m = G.master[c];
   if (m < 0) return;
-  const int N = G.N, nvel = G.nvel;
-  const double* mc = mom + 4 * (size_t)m;
-  const double rho = mc[0], ux = mc[1], uy = mc[2], T = mc[3];
-  const double A = rho / (2.0 * M_PI * T), inv2T = 0.5 / T;
-  const double nv = nu[m], sc = 1.0 / (1.0 + nv);
-  double2* row = st + (size_t)c * nvel;
-  double sr = 0.0, smx = 0.0, smy = 0.0, se = 0.0;
-  for (int p = lane; p < nvel; p += kWave) {
-    const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
-    const double cx = vx - ux, cy = vy - uy;
-    const double E = A * exp(-(cx * cx + cy * cy) * inv2T);
-    const double2 o = row[p];
-    const double fn = (o.x + nv * E) * sc;
-    const double gn = (o.y + nv * 0.5 * T * E) * sc;
-    row[p] = make_double2(fn, gn);
-    sr += fn; smx += vx * fn; smy += vy * fn;
-    se += 0.5 * (vx * vx + vy * vy) * fn + gn;
-  }
-  if (c != m) return;
-  sr = wave_sum(sr); smx = wave_sum(smx); smy = wave_sum(smy); se = wave_sum(se);
-  if (lane == 0) {
-    const double r = sr * P.w, mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
-    double* mo = mom_next + 4 * (size_t)c;
-    mo[0] = r; mo[1] = mx; mo[2] = my;
-    mo[3] = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
-  }
+  if (P.shakhov) relax_cell2d<true>(G, st, mom, heat, nu, mom_next, heat_next, P, c, m, lane);
+  else relax_cell2d<false>(G, st, mom, nullptr, nu, mom_next, nullptr, P, c, m, lane);
 }
 
 StepParams params2d(const cc_ctx* ctx) {
@@ -754,6 +856,8 @@ StepParams params2d(const cc_ctx* ctx) {
   P.t_wall = ctx->body.t_wall;
   P.moving = ctx->body.motion != CC_MOTION_FIXED && ctx->body.kind != CC_BODY_NONE;
   P.write_state = 1;
+  P.shakhov = ctx->cfg.model == CC_MODEL_SHAKHOV;
+  P.sk_coef = (1.0 - ctx->cfg.prandtl) / 5.0;
   return P;
 }
 
@@ -896,8 +1000,9 @@ __global__ void __launch_bounds__(1024) k_steplist2d(MoveArgs M) {
 }
 
 // One general control volume (or one stale cell to zero) per block.
+template <bool SK>
 __device__ void general_cv(const MoveArgs& M, const double2* __restrict__ in,
-                           double2* __restrict__ out, double* __restrict__ mom,
+                           double2* __restrict__ out, double* __restrict__ mom, double* __restrict__ heat,
                            double* __restrict__ fslot, double* __restrict__ mpart,
                            const double* __restrict__ body, const StepParams& P, int q,
                            double* lds) {
@@ -919,6 +1024,8 @@ __device__ void general_cv(const MoveArgs& M, const double2* __restrict__ in,
   const double rho = mom[4 * m + 0], ux = mom[4 * m + 1], uy = mom[4 * m + 2], T = mom[4 * m + 3];
   const double inv2T = 0.5 / T, A = rho / (2.0 * M_PI * T);
   const double dtau = P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
+  const double qx = SK ? heat[2 * m] : 0.0, qy = SK ? heat[2 * m + 1] : 0.0;
+  const double ska = SK ? P.sk_coef / (rho * T * T) : 0.0;
   const double Sn = G0.scv[m];
   double Snew = 0.0;
   for (int t = 0; t < nm; ++t) Snew += G1.sbar[M.gmem[b + t]];
@@ -944,7 +1051,7 @@ __device__ void general_cv(const MoveArgs& M, const double2* __restrict__ in,
   }
   double sx[kMaxMembers], sy[kMaxMembers];
   for (int t = 0; t < kMaxMembers; ++t) { sx[t] = 0.0; sy[t] = 0.0; }
-  double sr = 0.0, smx = 0.0, smy = 0.0, se = 0.0;
+  Sums2<SK> sm;
   const double ratio = Snew > 0.0 ? Sn / Snew : 0.0;
   const double dts = Snew > 0.0 ? P.dt / Snew : 0.0;
   for (int p = tid; p < nvel; p += nth) {
@@ -990,20 +1097,21 @@ __device__ void general_cv(const MoveArgs& M, const double2* __restrict__ in,
         sy[t] += cy_ * cn * fv;
       }
     }
-    double E = 0.0;
+    double E = 0.0, Eg = 0.0;
     if (dtau != 0.0) {
       const double ex = vx - ux, ey = vy - uy;
       E = A * exp(-ex * ex * inv2T) * exp(-ey * ey * inv2T);
+      if (SK) shakhov2(ska, qx, qy, T, 1.0 / T, ex, ey, E, E, Eg);
+      else Eg = 0.5 * T * E;
     }
     const double fn = ratio * o.x - dts * Rf + ratio * dtau * (E - o.x);
-    const double gn = ratio * o.y - dts * Rg + ratio * dtau * (0.5 * T * E - o.y);
+    const double gn = ratio * o.y - dts * Rg + ratio * dtau * (Eg - o.y);
     for (int t = 0; t < nm; ++t) {
       const int k = M.gmem[b + t];
       const bool live = G1.type[k] != TYPE_SOLID && Snew > 0.0;
       out[(size_t)k * nvel + p] = live ? make_double2(fn, gn) : make_double2(0.0, 0.0);
     }
-    sr += fn; smx += vx * fn; smy += vy * fn;
-    se += 0.5 * (vx * vx + vy * vy) * fn + gn;
+    sm.add(vx, vy, fn, gn);
   }
   double Fx = 0.0, Fy = 0.0, Tq = 0.0;
   for (int t = 0; t < nm; ++t) {
@@ -1014,32 +1122,35 @@ __device__ void general_cv(const MoveArgs& M, const double2* __restrict__ in,
     Fy += ay * G0.lw[k];
     Tq += ((G0.rwx[k] - body[0]) * ay - (G0.rwy[k] - body[1]) * ax) * G0.lw[k];
   }
-  sr = block_sum4(sr, lds); smx = block_sum4(smx, lds);
-  smy = block_sum4(smy, lds); se = block_sum4(se, lds);
+  sm.reduce([&](double v) { return block_sum4(v, lds); });
   if (tid == 0) {
-    const double r = sr * P.w, mx = smx * P.w / r, my = smy * P.w / r, en = se * P.w;
-    const double Tn = (2.0 * en / r - (mx * mx + my * my)) / 3.0;
+    double mo[4], hq[2];
+    sm.finish(P.w, mo, hq);
     for (int t = 0; t < nm; ++t) {
       const int k = M.gmem[b + t];
-      mom[4 * k + 0] = r; mom[4 * k + 1] = mx; mom[4 * k + 2] = my; mom[4 * k + 3] = Tn;
+      for (int i = 0; i < 4; ++i) mom[4 * k + i] = mo[i];
+      if (SK) { heat[2 * k] = hq[0]; heat[2 * k + 1] = hq[1]; }
     }
     fslot[3 * q + 0] = Fx;
     fslot[3 * q + 1] = Fy;
     fslot[3 * q + 2] = Tq;
-    *mpart = Snew > 0.0 ? Snew * r : 0.0;
+    *mpart = Snew > 0.0 ? Snew * mo[0] : 0.0;
   }
 }
 
 __global__ void __launch_bounds__(256) k_genstep2d(MoveArgs M, const double2* __restrict__ in,
                                                    double2* __restrict__ out,
                                                    double* __restrict__ mom,
+                                                   double* __restrict__ heat,
                                                    double* __restrict__ fslot,
                                                    double* __restrict__ mpart, int ntiles,
                                                    const double* __restrict__ body, StepParams P) {
   __shared__ double lds[8];
   const int cnt = M.gcount[0];
-  for (int q = blockIdx.x; q < cnt; q += gridDim.x)
-    general_cv(M, in, out, mom, fslot, mpart + ntiles + q, body, P, q, lds);
+  for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
+    if (P.shakhov) general_cv<true>(M, in, out, mom, heat, fslot, mpart + ntiles + q, body, P, q, lds);
+    else general_cv<false>(M, in, out, mom, nullptr, fslot, mpart + ntiles + q, body, P, q, lds);
+  }
 }
 
 // Force, torque (t^n) and mass (t^{n+1}) in fixed order; then the rigid
@@ -1096,7 +1207,7 @@ __global__ void __launch_bounds__(256) k_batch_tiles2d(const BatchInst* __restri
   const int2 it = items[w];
   const int inst = __builtin_amdgcn_readfirstlane(it.x);
   const int tile = __builtin_amdgcn_readfirstlane(it.y);
-  regular_tile<NCH>(D[inst].T, D[inst].P, tile, lds);
+  regular_tile<NCH, false>(D[inst].T, D[inst].P, tile, lds);
 }
 
 __global__ void __launch_bounds__(256) k_batch_cut2d(const BatchInst* __restrict__ D,
@@ -1109,7 +1220,7 @@ __global__ void __launch_bounds__(256) k_batch_cut2d(const BatchInst* __restrict
   const int q = __builtin_amdgcn_readfirstlane(it.y);
   const Geo2D G = D[inst].G;
   const FusedArgs A = D[inst].A;
-  cut_cv(G, A.in, A.out, A.mom, A.fslot, A.mpart + A.ntiles + q, A.body, D[inst].P, q, lds);
+  cut_cv<false>(G, A.in, A.out, A.mom, nullptr, A.fslot, A.mpart + A.ntiles + q, A.body, D[inst].P, q, lds);
 }
 
 typedef void (*batch_tiles_fn)(hipStream_t, const BatchInst*, const int2*, int);
@@ -1143,35 +1254,40 @@ batch_tiles_fn pick_batch_tiles(int nch) {
 
 typedef void (*fused_fn)(const cc_ctx*, dim3, const FusedArgs&, const StepParams&);
 
-template <int NCH>
+template <int NCH, bool SK>
 void launch_fused(const cc_ctx* ctx, dim3 grid, const FusedArgs& A, const StepParams& P) {
-  k_step2d<NCH><<<grid, 256, 0, ctx->stream>>>(ctx->g2, A, P);
+  k_step2d<NCH, SK><<<grid, 256, 0, ctx->stream>>>(ctx->g2, A, P);
 }
 
-fused_fn pick_fused(int nch) {
+template <bool SK>
+fused_fn pick_fused_sk(int nch) {
   switch (nch) {
-    case 1: return launch_fused<1>;
-    case 2: return launch_fused<2>;
-    case 3: return launch_fused<3>;
-    case 4: return launch_fused<4>;
-    case 5: return launch_fused<5>;
-    case 6: return launch_fused<6>;
-    case 7: return launch_fused<7>;
-    case 8: return launch_fused<8>;
-    case 9: return launch_fused<9>;
-    case 10: return launch_fused<10>;
-    case 11: return launch_fused<11>;
-    case 12: return launch_fused<12>;
-    case 13: return launch_fused<13>;
-    case 14: return launch_fused<14>;
-    case 16: return launch_fused<16>;
-    case 18: return launch_fused<18>;
-    case 20: return launch_fused<20>;
-    case 24: return launch_fused<24>;
-    case 28: return launch_fused<28>;
-    case 32: return launch_fused<32>;
+    case 1: return launch_fused<1, SK>;
+    case 2: return launch_fused<2, SK>;
+    case 3: return launch_fused<3, SK>;
+    case 4: return launch_fused<4, SK>;
+    case 5: return launch_fused<5, SK>;
+    case 6: return launch_fused<6, SK>;
+    case 7: return launch_fused<7, SK>;
+    case 8: return launch_fused<8, SK>;
+    case 9: return launch_fused<9, SK>;
+    case 10: return launch_fused<10, SK>;
+    case 11: return launch_fused<11, SK>;
+    case 12: return launch_fused<12, SK>;
+    case 13: return launch_fused<13, SK>;
+    case 14: return launch_fused<14, SK>;
+    case 16: return launch_fused<16, SK>;
+    case 18: return launch_fused<18, SK>;
+    case 20: return launch_fused<20, SK>;
+    case 24: return launch_fused<24, SK>;
+    case 28: return launch_fused<28, SK>;
+    case 32: return launch_fused<32, SK>;
     default: return nullptr;
   }
+}
+
+fused_fn pick_fused(int nch, bool sk = false) {
+  return sk ? pick_fused_sk<true>(nch) : pick_fused_sk<false>(nch);
 }
 
 // rows of the velocity grid with v_y < 0 (the lower half of a cell row)
@@ -1233,7 +1349,7 @@ hipError_t launch_merge_2d(cc_ctx* ctx) {
   StepParams P = params2d(ctx);
   prof_begin(ctx, 3);
   k_merge2d<<<kListBlocks, 64, 0, ctx->stream>>>(ctx->g2, (double2*)ctx->state[ctx->cur],
-                                                  ctx->s.mom, P);
+                                                  ctx->s.mom, ctx->s.heat, P);
   prof_end(ctx, 3);
   return hipGetLastError();
 }
@@ -1241,7 +1357,7 @@ hipError_t launch_merge_2d(cc_ctx* ctx) {
 hipError_t launch_moments_all_2d(cc_ctx* ctx) {
   StepParams P = params2d(ctx);
   k_mom2d<<<(ctx->ncell + 3) / 4, 256, 0, ctx->stream>>>(
-      ctx->g2, (const double2*)ctx->state[ctx->cur], ctx->s.mom, P);
+      ctx->g2, (const double2*)ctx->state[ctx->cur], ctx->s.mom, ctx->s.heat, P);
   return hipGetLastError();
 }
 
@@ -1278,10 +1394,15 @@ hipError_t launch_imex_step_2d(cc_ctx* ctx, double* row) {
   }
   prof_begin(ctx, 5);
   k_relax2d<<<(ctx->ncell + 3) / 4, 256, 0, s>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
-                                                 ctx->s.nu, ctx->s.mom2, P);
+                                                 ctx->s.heat, ctx->s.nu, ctx->s.mom2, ctx->s.heat2, P);
   prof_end(ctx, 5);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (P.shakhov) {
+    e = hipMemcpyAsync(ctx->s.heat, ctx->s.heat2, (size_t)ctx->ncell * 2 * sizeof(double),
+                       hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
   return hipMemcpyAsync(ctx->s.mom, ctx->s.mom2, (size_t)ctx->ncell * 4 * sizeof(double),
                         hipMemcpyDeviceToDevice, s);
 }
@@ -1313,7 +1434,7 @@ hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_forc
                                 double* cur_mass_row, bool record, bool relax) {
   StepParams P = params2d(ctx);
   if (!relax) P.tau_coef = 0.0;   // transport only (first half of the semi-implicit step)
-  fused_fn fn = pick_fused(chunks_per_half(ctx));
+  fused_fn fn = pick_fused(chunks_per_half(ctx), P.shakhov);
   if (!fn) return hipErrorInvalidValue;
   const int par = ctx->step_parity;
   FusedArgs A;
@@ -1321,6 +1442,7 @@ hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_forc
   A.in = (const double2*)ctx->state[ctx->cur];
   A.out = (double2*)ctx->state[1 - ctx->cur];
   A.mom = ctx->s.mom;
+  A.heat = ctx->s.heat;
   A.body = ctx->s.body;
   A.ngroups = (ctx->nx + kTileW - 1) / kTileW;
   A.seglen = tile_rows(ctx);
@@ -1402,7 +1524,7 @@ Box2D moving_box(const cc_ctx* ctx) {
 
 hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_row) {
   StepParams P = params2d(ctx);
-  fused_fn fn = pick_fused(chunks_per_half(ctx));
+  fused_fn fn = pick_fused(chunks_per_half(ctx), P.shakhov);
   if (!fn) return hipErrorInvalidValue;
   hipStream_t st = ctx->stream;
   const int par = ctx->step_parity;
@@ -1413,7 +1535,8 @@ hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_ro
   if (e != hipSuccess) return e;
   // 2. merge over the control volumes of t^n
   prof_begin(ctx, 3);
-  k_merge2d<<<kListBlocks, 64, 0, st>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom, P);
+  k_merge2d<<<kListBlocks, 64, 0, st>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
+                                        ctx->s.heat, P);
   prof_end(ctx, 3);
   MoveArgs M;
   M.G0 = ctx->g2; M.G1 = ctx->g2n;
@@ -1426,6 +1549,7 @@ hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_ro
   A.in = (const double2*)ctx->state[ctx->cur];
   A.out = (double2*)ctx->state[1 - ctx->cur];
   A.mom = ctx->s.mom;
+  A.heat = ctx->s.heat;
   A.body = ctx->s.body;
   A.ngroups = (ctx->nx + kTileW - 1) / kTileW;
   A.seglen = tile_rows(ctx);
@@ -1446,7 +1570,7 @@ hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_ro
   A.red_mass = nullptr;
   // 4-6. wall condition, scheme and redistribution
   prof_begin(ctx, 1);
-  k_genstep2d<<<kListBlocks, 256, 0, st>>>(M, A.in, A.out, A.mom, fs, mp, A.ntiles, ctx->s.body, P);
+  k_genstep2d<<<kListBlocks, 256, 0, st>>>(M, A.in, A.out, A.mom, A.heat, fs, mp, A.ntiles, ctx->s.body, P);
   prof_end(ctx, 1);
   prof_begin(ctx, 0);
   fn(ctx, dim3(A.tile_base + A.ntiles_pad), A, P);
@@ -1476,6 +1600,7 @@ static FusedArgs fused_args_for(const cc_ctx* ctx, int in_buf, int rows) {
   A.in = (const double2*)ctx->state[in_buf];
   A.out = (double2*)ctx->state[1 - in_buf];
   A.mom = ctx->s.mom;
+  A.heat = nullptr;   // batched instances relax with BGK only
   A.body = ctx->s.body;
   A.ngroups = (ctx->nx + kTileW - 1) / kTileW;
   A.seglen = rows;
@@ -1590,6 +1715,7 @@ hipError_t batch_launch_group(cc_batch* B, int g) {
 // reductions): recomputation inside the adjoint
 hipError_t launch_step_2d_ptrs(cc_ctx* ctx, const double2* in, double2* out, double* mom) {
   StepParams P = params2d(ctx);
+  P.shakhov = 0;   // the adjoint is built for the BGK model only
   fused_fn fn = pick_fused(chunks_per_half(ctx));
   if (!fn) return hipErrorInvalidValue;
   FusedArgs A;
@@ -1597,6 +1723,7 @@ hipError_t launch_step_2d_ptrs(cc_ctx* ctx, const double2* in, double2* out, dou
   A.in = in;
   A.out = out;
   A.mom = mom;
+  A.heat = nullptr;
   A.body = ctx->s.body;
   A.ngroups = (ctx->nx + kTileW - 1) / kTileW;
   A.seglen = tile_rows(ctx);
@@ -1620,7 +1747,8 @@ hipError_t launch_step_2d_ptrs(cc_ctx* ctx, const double2* in, double2* out, dou
 
 hipError_t launch_moments_ptr_2d(cc_ctx* ctx, const double2* st, double* mom) {
   StepParams P = params2d(ctx);
-  k_mom2d<<<(ctx->ncell + 3) / 4, 256, 0, ctx->stream>>>(ctx->g2, st, mom, P);
+  P.shakhov = 0;
+  k_mom2d<<<(ctx->ncell + 3) / 4, 256, 0, ctx->stream>>>(ctx->g2, st, mom, nullptr, P);
   return hipGetLastError();
 }
 

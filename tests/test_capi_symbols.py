@@ -97,3 +97,17 @@ def test_create_validates_scheme():
     st, h = _create(small_2d(8, 8, 8, scheme="imex"))
     assert st == 0
     lib().cc_destroy(h)
+
+
+def test_create_validates_model():
+    from paper_1503_04544_amd._capi import lib, make_body, make_config
+    cfg = small_2d(8, 8, 8)
+    for model, pr in ((2, 0.5), (1, 0.0), (1, float("nan"))):
+        c = make_config(cfg)
+        c.model, c.prandtl = model, pr
+        h = C.c_void_p()
+        assert lib().cc_create(C.byref(c), C.byref(make_body(cfg.body)), C.byref(h)) == -1
+        assert not h.value
+    st, h = _create(small_2d(8, 8, 8, model="shakhov"))
+    assert st == 0
+    lib().cc_destroy(h)
