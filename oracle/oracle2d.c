@@ -687,7 +687,7 @@ static void scheme_cv(const orc2d *o, const geo2d *G, const double *fm,
        collision term vanishes: they are those of the transported value.
        READING: tau^n comes from the directly computed density of the
        control volume at t^n. */
-    double *fs = malloc(nvel * sizeof(double)), *gs = malloc(nvel * sizeof(double));
+    double *fs = calloc(nvel, sizeof(double)), *gs = calloc(nvel, sizeof(double));
     double ratio = S / snew;
     for (int p = 0; p < nvel; ++p) {
       fs[p] = ratio * fc[p] - dt / snew * R[p];
@@ -1137,6 +1137,7 @@ static void cv_sum(const orc2d *o, const geo2d *G, const double *a, double *L) {
 int orc2d_adjoint(orc2d *o, int nsteps, int objective, double *out) {
   if (o->cfg.motion != 0 && o->cfg.body_kind != 0) return -1;
   if (o->cfg.maxwellian || o->cfg.scheme || o->cfg.model) return -1;   /* transpose written for the explicit direct BGK step */
+  if (nsteps < 1) return -1;
   int nvel = o->nvel, N = o->N;
   size_t tot = (size_t)o->ncell * nvel;
   const geo2d *G = &o->g[o->cur];

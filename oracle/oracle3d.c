@@ -523,7 +523,7 @@ static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
   if (o->cfg.scheme == 1) {
     /* semi-implicit scheme (ImpSchemeDD in 3D): equilibrium of the
        transported value, tau^n from the direct density at t^n (READING) */
-    double *fs = malloc(nvel * sizeof(double));
+    double *fs = calloc(nvel, sizeof(double));
     for (int p = 0; p < nvel; ++p) fs[p] = fc[p] - o->dt / V * R[p];
     double rn, un[3], Tn;
     moments3(o, fc, &rn, un, &Tn);

@@ -125,7 +125,9 @@ void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
   ctx->s.heat = sk ? cv.take<double>(n * (ctx->dim == 2 ? 2 : 3)) : nullptr;
   ctx->s.heat2 = sk && ctx->dim == 2 ? cv.take<double>(n * 2) : nullptr;
   ctx->s.nu = cv.take<double>(n);
-  ctx->s.part = ctx->dim == 3 ? cv.take<double>(n * (size_t)chunks3d(ctx->N) * 5) : nullptr;
+  // 3D chunk sums: 5 per chunk, 14 with the Shakhov model (second and third moments)
+  const size_t nsum = ctx->cfg.model == CC_MODEL_SHAKHOV ? 14 : 5;
+  ctx->s.part = ctx->dim == 3 ? cv.take<double>(n * (size_t)chunks3d(ctx->N) * nsum) : nullptr;
   ctx->s.fslot = cv.take<double>(n * 3 * 2);
   ctx->s.mpart_cap = (int)((size_t)((ctx->nx + 3) / 4) * ctx->ny * ctx->nz + n);
   ctx->s.mpart = cv.take<double>((size_t)ctx->s.mpart_cap * 2);
@@ -219,7 +221,6 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   if (c.model != CC_MODEL_BGK && c.model != CC_MODEL_SHAKHOV) return reject("unknown relaxation model");
   if (c.model == CC_MODEL_SHAKHOV && !(c.prandtl > 0.0 && isfinite(c.prandtl)))
     return reject("the Shakhov model needs a finite Prandtl number > 0");
-  if (c.model == CC_MODEL_SHAKHOV && c.dim == 3) return reject("the Shakhov model is available in 2D");
   if (c.scheme == CC_SCHEME_IMEX && body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_NONE)
     return reject("the semi-implicit scheme is available for fixed bodies");
   ctx->dim = c.dim;

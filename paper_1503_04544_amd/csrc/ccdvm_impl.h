@@ -111,7 +111,8 @@ struct Scratch {
   double* pose;      // pose at t^{n+1}: cx, cy, theta
   double* mom;       // 2D: ncell * 4 (rho, ux, uy, T); 3D: ncell * 8 (Maxwellian factor, u,
                      // 1/(2T), dt/tau, rho)
-  double* part;      // 3D: per cell and velocity chunk, sums of F, v F, |v|^2 F
+  double* part;      // 3D: per cell and velocity chunk, sums of F, v F, |v|^2 F (Shakhov: and
+                     // v v^T F, |v|^2 v F)
   double* mom2;      // 2D semi-implicit step: moments of the new state (ncell * 4)
   double* heat;      // Shakhov: heat flux of each cell's control volume (2D: 2, 3D: 3 per cell)
   double* heat2;     // 2D semi-implicit Shakhov step: heat flux of the new state

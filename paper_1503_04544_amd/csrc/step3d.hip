@@ -69,6 +69,44 @@ __device__ inline double block_sum(double v, double* lds) {
 
 __device__ inline double vnode3(double vmin, double dv, int idx) { return vmin + (idx + 0.5) * dv; }
 
+// Velocity sums of F kept per control volume and chunk: F, v F, |v|^2 F
+// (kSums5) and, for the Shakhov model, v v^T F (xx, xy, xz, yy, yz, zz) and
+// |v|^2 v F, from which the heat flux follows in one pass (kSumsSK).
+constexpr int kSums5 = 5, kSumsSK = 14;
+template <bool SK>
+struct Sums3 {
+  static constexpr int K = SK ? kSumsSK : kSums5;
+  double s[K];
+  __device__ inline Sums3() {
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = 0.0;
+  }
+  __device__ inline void add(double vx, double vy, double vz, double f) {
+    const double v2 = vx * vx + vy * vy + vz * vz;
+    s[0] += f; s[1] += vx * f; s[2] += vy * f; s[3] += vz * f;
+    s[4] += v2 * f;
+    if (SK) {
+      s[5 + 0] += vx * vx * f; s[5 + 1] += vx * vy * f; s[5 + 2] += vx * vz * f;
+      s[5 + 3] += vy * vy * f; s[5 + 4] += vy * vz * f; s[5 + 5] += vz * vz * f;
+      s[11] += vx * v2 * f; s[12] += vy * v2 * f; s[13] += vz * v2 * f;
+    }
+  }
+  template <class Red>
+  __device__ inline void reduce(Red red) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = red(s[k]);
+  }
+};
+
+// 3D Shakhov equilibrium (Section 2.1) from the Maxwellian value M at v,
+// c = v - u: M [1 + (c.qt)(|c|^2/T - 5)], with the stored
+// qt = (1 - Pr) q / (5 P T), P = rho T (R = 1).
+__device__ inline double shakhov3(const double* __restrict__ qt, double invT, double cx, double cy,
+                                  double cz, double M) {
+  const double s = cx * qt[0] + cy * qt[1] + cz * qt[2];
+  return M * (1.0 + s * ((cx * cx + cy * cy + cz * cz) * invT - 5.0));
+}
+
 // Chunking of the velocity set for N nodes per axis (N even, symmetric box).
 template <int N>
 struct Chunk3 {
@@ -94,7 +132,8 @@ struct Step3Args {
   double* out;
   const int* kind;
   const double* mom;    // 8 per cell: A, ux, uy, uz, 1/(2T), dt/tau, rho, -
-  double* part;         // per cell and chunk: sums of F, v F, |v|^2 F (5)
+  double* part;         // per cell and chunk: the sums of Sums3 (5, Shakhov 14)
+  const double* heat;   // Shakhov: (1 - Pr) q / (5 P T) per cell (3)
   const double* ghost;  // farfield values
   int nx, ny, nz, nvel;
   int ntj, ntiles, nblk, per;
@@ -103,7 +142,7 @@ struct Step3Args {
   double vmin, dv, cxf, cyf, czf;   // dt/dx, dt/dy, dt/dz
 };
 
-template <int N>
+template <int N, bool SK>
 __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A, const int* __restrict__ kind,
                                                 const double* __restrict__ mom) {
   using C = Chunk3<N>;
@@ -205,6 +244,7 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A, const int* _
       const double* mc = mom + 8 * (size_t)c;
       const double Am = mc[0], ux = mc[1], uy = mc[2], uz = mc[3], inv2T = mc[4];
       const double nu = A.relax ? mc[5] : 0.0;
+      const double* qt = A.heat + 3 * (size_t)c;
       double tx = 0.0, tyy = 0.0, tzz = 0.0;
       if (lv < N) {
         const double v = vnode3(vmin, dv, lv);
@@ -212,7 +252,7 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A, const int* _
         tyy = exp(-(v - uy) * (v - uy) * inv2T);
         tzz = exp(-(v - uz) * (v - uz) * inv2T);
       }
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+      Sums3<SK> sm;
       double* orow = A.out + (pencil + i) * (size_t)nvel;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -220,7 +260,8 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A, const int* _
         const int rem = e % C::E1;
         const int p1 = rem % N, p2 = sy * C::H + rem / N, p3 = p3b + e / C::E1;
         const double vx = vnode3(vmin, dv, p1), vy = vnode3(vmin, dv, p2), vz = vnode3(vmin, dv, p3);
-        const double E = Am * __shfl(tx, p1, kWave) * __shfl(tyy, p2, kWave) * __shfl(tzz, p3, kWave);
+        double E = Am * __shfl(tx, p1, kWave) * __shfl(tyy, p2, kWave) * __shfl(tzz, p3, kWave);
+        if (SK) E = shakhov3(qt, 2.0 * inv2T, vx - ux, vy - uy, vz - uz, E);
         const double yv = y_lds ? xch[s][wy][r][lv] : hqy[0][r];
         const double zv = z_lds ? xch[s][wz][r][lv] : hqz[0][r];
         const double f = cur[r];
@@ -229,15 +270,14 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A, const int* _
                           A.czf * fabs(vz) * (f - zv) + nu * (E - f);
         if (active(lv, r)) {
           __builtin_nontemporal_store(fn, &orow[offset(lv, r)]);
-          s0 += fn; s1 += vx * fn; s2 += vy * fn; s3 += vz * fn;
-          s4 += (vx * vx + vy * vy + vz * vz) * fn;
+          sm.add(vx, vy, vz, fn);
         }
       }
-      s0 = wave_sum3(s0); s1 = wave_sum3(s1); s2 = wave_sum3(s2);
-      s3 = wave_sum3(s3); s4 = wave_sum3(s4);
+      sm.reduce([](double v) { return wave_sum3(v); });
       if (lv == 0) {
-        double* pp = A.part + ((size_t)c * C::NCH + ch) * 5;
-        pp[0] = s0; pp[1] = s1; pp[2] = s2; pp[3] = s3; pp[4] = s4;
+        double* pp = A.part + ((size_t)c * C::NCH + ch) * Sums3<SK>::K;
+#pragma unroll
+        for (int q2 = 0; q2 < Sums3<SK>::K; ++q2) pp[q2] = sm.s[q2];
       }
     }
 #pragma unroll
@@ -307,6 +347,36 @@ __device__ inline double reduce5(const double (&v)[5], int lv) {
   return y;
 }
 
+// Sums of v[0..15] over the wave: on return lanes 4q .. 4q+3 hold the sum
+// of quantity q.  Each level halves the quantities a lane keeps and adds its
+// partner's copy of them.
+__device__ inline double reduce16(const double (&v)[16], int lv) {
+  const bool b5 = lv & 32, b4 = lv & 16, b3 = lv & 8, b2 = lv & 4;
+  double a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double keep = b5 ? v[k + 8] : v[k], send = b5 ? v[k] : v[k + 8];
+    a[k] = keep + __shfl_xor(send, 32, kWave);
+  }
+  double b[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double keep = b4 ? a[k + 4] : a[k], send = b4 ? a[k] : a[k + 4];
+    b[k] = keep + __shfl_xor(send, 16, kWave);
+  }
+  double c[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double keep = b3 ? b[k + 2] : b[k], send = b3 ? b[k] : b[k + 2];
+    c[k] = keep + __shfl_xor(send, 8, kWave);
+  }
+  const double keep = b2 ? c[1] : c[0], send = b2 ? c[0] : c[1];
+  double d = keep + __shfl_xor(send, 4, kWave);
+  d += __shfl_xor(d, 2, kWave);
+  d += __shfl_xor(d, 1, kWave);
+  return d;
+}
+
 struct Ctx16 {
   size_t pencil;          // cell index of the pencil's first cell
   const double* own_base;
@@ -349,7 +419,7 @@ __device__ __forceinline__ void load_halos16(const Ctx16& X, int i, int nx, unsi
   }
 }
 
-template <int U>
+template <int U, bool SK>
 __device__ __forceinline__ void step16(const Step3Args& A, const int* __restrict__ kind,
                                        const double* __restrict__ mom, const Ctx16& X, int i,
                                        double (&S)[2][kR16], double (&hy)[kR16], double (&hz)[kR16],
@@ -394,6 +464,23 @@ __device__ __forceinline__ void step16(const Step3Args& A, const int* __restrict
     const double Exa = Ax * eya, Exb = Ax * eyb;
     const bool xpos = (lv & 15) >= 8;
     double* orow = A.out + (size_t)c * nvel + X.cbase;
+    // Shakhov: E *= 1 + (c.qt)(|c|^2/T - 5), split into the lane's x/y part
+    // and the wave-uniform z part
+    double qtz = 0.0, invT = 0.0, kxy[2] = {0.0, 0.0}, cxy2[2] = {0.0, 0.0};
+    if (SK) {
+      const double* qt = A.heat + 3 * (size_t)c;
+      const double qtx = uniform_d(qt[0]), qty = uniform_d(qt[1]);
+      qtz = uniform_d(qt[2]);
+      invT = 2.0 * inv2T;
+      const double cx = vx - ux;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double cy = (h ? vyb : vya) - uy;
+        kxy[h] = cx * qtx + cy * qty;
+        cxy2[h] = (cx * cx + cy * cy) * invT - 5.0;
+      }
+    }
+    double fnv[kR16];
     double Aa = 0.0, Ab = 0.0, m3 = 0.0, m4z = 0.0;
 #pragma unroll
     for (int q = 0; q < kG16; ++q) {
@@ -405,7 +492,11 @@ __device__ __forceinline__ void step16(const Step3Args& A, const int* __restrict
       for (int h = 0; h < 2; ++h) {
         const int r = 2 * q + h;
         const double ay = h ? ayb : aya;
-        const double E = (h ? Exb : Exa) * ez;
+        double E = (h ? Exb : Exa) * ez;
+        if (SK) {
+          const double cz = vz - uz;
+          E *= 1.0 + (kxy[h] + cz * qtz) * (cxy2[h] + cz * cz * invT);
+        }
         const double fx = xpos ? xch[s ^ 1][X.wave][r][lv] : nxt[r];
         const double fy = X.y_lds ? xch[s][X.wy][r][lv] : hy[r];
         const double fz = X.z_lds ? xch[s][X.wz][r][lv] : hz[r];
@@ -415,26 +506,67 @@ __device__ __forceinline__ void step16(const Step3Args& A, const int* __restrict
             fn, reinterpret_cast<double*>(reinterpret_cast<char*>(orow + rof16(r)) + lb));
         if (h) Ab += fn; else Aa += fn;
         Bq += fn;
+        fnv[r] = fn;
       }
       m3 += vz * Bq;
       m4z += vz * vz * Bq;
     }
     const double s0 = Aa + Ab;
-    double m[5];
-    m[0] = s0;
-    m[1] = vx * s0;
-    m[2] = vya * Aa + vyb * Ab;
-    m[3] = m3;
-    m[4] = vx * vx * s0 + (vya * vya * Aa + vyb * vyb * Ab) + m4z;
-    // halos of cell i+1 before the reduction
-    load_halos16(X, i + 1, nx, lb, hy, hz);
-    const double tot = reduce5(m, lv);
-    if ((lv & 7) == 0 && lv < 40) A.part[((size_t)c * kNCH16 + X.ch) * 5 + (lv >> 3)] = tot;
+    if (!SK) {
+      double m[5];
+      m[0] = s0;
+      m[1] = vx * s0;
+      m[2] = vya * Aa + vyb * Ab;
+      m[3] = m3;
+      m[4] = vx * vx * s0 + (vya * vya * Aa + vyb * vyb * Ab) + m4z;
+      // halos of cell i+1 before the reduction
+      load_halos16(X, i + 1, nx, lb, hy, hz);
+      const double tot = reduce5(m, lv);
+      if ((lv & 7) == 0 && lv < 40) A.part[((size_t)c * kNCH16 + X.ch) * kSums5 + (lv >> 3)] = tot;
+    } else {
+      // the 14 sums of Sums3 from the lane's values: v_x is the lane's, v_y
+      // takes two values (vya in even slots, vyb in odd), v_z one per pair
+      double yz = 0.0, y3z = 0.0, z3y = 0.0, z3 = 0.0;
+#pragma unroll
+      for (int q = 0; q < kG16; ++q) {
+        const double vz = vnode3(vmin, dv, X.p3b + q);
+        const double fa = fnv[2 * q], fb = fnv[2 * q + 1];
+        const double yq = vya * fa + vyb * fb;          // sum v_y F over the pair
+        yz += vz * yq;
+        y3z += vz * vz * yq;
+        z3y += vz * (vya * vya * fa + vyb * vyb * fb);
+        z3 += vz * vz * vz * (fa + fb);
+      }
+      const double sy = vya * Aa + vyb * Ab, yy = vya * vya * Aa + vyb * vyb * Ab;
+      const double vx2 = vx * vx;
+      double m[16];
+      m[0] = s0;
+      m[1] = vx * s0;
+      m[2] = sy;
+      m[3] = m3;
+      m[4] = vx2 * s0 + yy + m4z;
+      m[5] = vx2 * s0;
+      m[6] = vx * sy;
+      m[7] = vx * m3;
+      m[8] = yy;
+      m[9] = yz;
+      m[10] = m4z;
+      m[11] = vx * m[4];
+      m[12] = vx2 * sy + (vya * vya * vya * Aa + vyb * vyb * vyb * Ab) + y3z;
+      m[13] = vx2 * m3 + z3y + z3;
+      m[14] = 0.0;
+      m[15] = 0.0;
+      load_halos16(X, i + 1, nx, lb, hy, hz);
+      const double tot = reduce16(m, lv);
+      if ((lv & 3) == 0 && lv < 4 * kSumsSK)
+        A.part[((size_t)c * kNCH16 + X.ch) * kSumsSK + (lv >> 2)] = tot;
+    }
   } else {
     load_halos16(X, i + 1, nx, lb, hy, hz);
   }
 }
 
+template <bool SK>
 __global__ void __launch_bounds__(1024) k_step3d16(const Step3Args A, const int* __restrict__ kind,
                                                   const double* __restrict__ mom) {
   constexpr int R = kR16;
@@ -488,14 +620,14 @@ __global__ void __launch_bounds__(1024) k_step3d16(const Step3Args A, const int*
   }
   load_halos16(X, 0, nx, (unsigned)lane * 8u, hy, hz);
   for (int i = 0; i < nx; i += 2) {
-    step16<0>(A, kind, mom, X, i, S, hy, hz, xch);
-    if (i + 1 < nx) step16<1>(A, kind, mom, X, i + 1, S, hy, hz, xch);
+    step16<0, SK>(A, kind, mom, X, i, S, hy, hz, xch);
+    if (i + 1 < nx) step16<1, SK>(A, kind, mom, X, i + 1, S, hy, hz, xch);
   }
 }
 
 // partial moments of the current (merged) state, per control-volume master
 // and chunk (one wave per cell)
-template <int N>
+template <int N, bool SK>
 __global__ void __launch_bounds__(256) k_part3d(Geo3D G, const double* __restrict__ in,
                                                double* __restrict__ part, double vmin, double dv) {
   using C = Chunk3<N>;
@@ -505,22 +637,19 @@ __global__ void __launch_bounds__(256) k_part3d(Geo3D G, const double* __restric
   const double* row = in + (size_t)c * G.nvel;
   for (int ch = 0; ch < C::NCH; ++ch) {
     const int sy = ch & 1, p3b = (ch >> 1) * C::G3;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+    Sums3<SK> sm;
     for (int r = 0; r < C::R; ++r) {
       const int e = r * kWave + lane;
       if (e >= C::CH) continue;
       const int rem = e % C::E1;
       const double vx = vnode3(vmin, dv, rem % N), vy = vnode3(vmin, dv, sy * C::H + rem / N),
                    vz = vnode3(vmin, dv, p3b + e / C::E1);
-      const double f = row[chunk_offset<N>(ch, e)];
-      s0 += f; s1 += vx * f; s2 += vy * f; s3 += vz * f;
-      s4 += (vx * vx + vy * vy + vz * vz) * f;
+      sm.add(vx, vy, vz, row[chunk_offset<N>(ch, e)]);
     }
-    s0 = wave_sum3(s0); s1 = wave_sum3(s1); s2 = wave_sum3(s2);
-    s3 = wave_sum3(s3); s4 = wave_sum3(s4);
+    sm.reduce([](double v) { return wave_sum3(v); });
     if (lane == 0) {
-      double* pp = part + ((size_t)c * C::NCH + ch) * 5;
-      pp[0] = s0; pp[1] = s1; pp[2] = s2; pp[3] = s3; pp[4] = s4;
+      double* pp = part + ((size_t)c * C::NCH + ch) * Sums3<SK>::K;
+      for (int q = 0; q < Sums3<SK>::K; ++q) pp[q] = sm.s[q];
     }
   }
 }
@@ -535,24 +664,31 @@ struct Mom3Params {
   // 2: semi-implicit step, equilibrium of the transported value (dt/tau of
   //    t^n kept)
   int mode;
+  double sk_coef;       // Shakhov: (1 - Pr)/5
 };
 
 // moments of every control volume from its chunk sums (eq. MacroscopicTD):
 // rho, u, T = (2E/rho - |u|^2)/3 (or the conservative triplet), the
-// relaxation record, and block partials of the mass sum_m V_m rho_m
-template <bool CONS>
+// relaxation record, block partials of the mass sum_m V_m rho_m and, for
+// the Shakhov model, the heat flux about the direct mean velocity,
+//   q = 1/2 [S3 - 2 S2 u - u tr S2 + 2 rho |u|^2 u],
+// S2 = sum v v^T F w, S3 = sum |v|^2 v F w, stored as
+// (1 - Pr) q / (5 rho T^2) with the triplet of the record
+template <bool CONS, bool SK>
 __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict__ part,
-                                              double* __restrict__ mom, double* __restrict__ mpart,
-                                              Mom3Params P) {
+                                              double* __restrict__ mom, double* __restrict__ heat,
+                                              double* __restrict__ mpart, Mom3Params P) {
+  constexpr int K = Sums3<SK>::K;
   __shared__ double lds[4];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   double ms = 0.0;
   const int kd = c < G.ncell ? G.kind[c] : KIND_SOLID;
   if (kd == KIND_REGULAR || kd == KIND_IRREGULAR) {
-    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const double* pp = part + (size_t)c * P.nch * 5;
+    double s[K];
+    for (int q = 0; q < K; ++q) s[q] = 0.0;
+    const double* pp = part + (size_t)c * P.nch * K;
     for (int ch = 0; ch < P.nch; ++ch)
-      for (int q = 0; q < 5; ++q) s[q] += pp[5 * ch + q];
+      for (int q = 0; q < K; ++q) s[q] += pp[K * ch + q];
     const double rho = s[0] * P.w;
     const double ux = s[1] * P.w / rho, uy = s[2] * P.w / rho, uz = s[3] * P.w / rho;
     const double en = 0.5 * s[4] * P.w;
@@ -570,6 +706,19 @@ __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict
     mo[4] = 0.5 / x[4];
     if (P.mode != 2) mo[5] = P.tau_coef > 0.0 ? P.dt * (P.mode == 1 ? rho : x[0]) / P.tau_coef : 0.0;
     mo[6] = rho;
+    if (SK) {
+      const double w = P.w, u[3] = {ux, uy, uz}, u2 = ux * ux + uy * uy + uz * uz;
+      const double S2[3][3] = {{s[5] * w, s[6] * w, s[7] * w},
+                               {s[6] * w, s[8] * w, s[9] * w},
+                               {s[7] * w, s[9] * w, s[10] * w}};
+      const double tr = S2[0][0] + S2[1][1] + S2[2][2];
+      const double a = P.sk_coef / (x[0] * x[4] * x[4]);
+      for (int d = 0; d < 3; ++d) {
+        const double S2u = S2[d][0] * ux + S2[d][1] * uy + S2[d][2] * uz;
+        const double qd = 0.5 * (s[11 + d] * w - 2.0 * S2u - u[d] * tr + 2.0 * rho * u2 * u[d]);
+        heat[3 * (size_t)c + d] = a * qd;
+      }
+    }
     ms = (kd == KIND_REGULAR ? P.vol : G.vcv[c]) * rho;
   }
   ms = block_sum(ms, lds);
@@ -596,10 +745,12 @@ __device__ inline double maxw3(double rho, double ux, double uy, double uz, doub
 // k_mom3d), redistribution to the members, the moment sums of the new value
 // (chunk slot 0) for the next record; wall stress -> force of the state at
 // t^n.  write_state == 0: force only.
+template <bool SK>
 __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict__ in,
                                               double* __restrict__ out, double* __restrict__ fslot,
-                                              const double* __restrict__ mom, double* __restrict__ part,
-                                              int nch, Cut3Params P) {
+                                              const double* __restrict__ mom, const double* __restrict__ heat,
+                                              double* __restrict__ part, int nch, Cut3Params P) {
+  constexpr int K = Sums3<SK>::K;
   __shared__ double lds[4];
   const int tid = threadIdx.x, nth = blockDim.x;
   const int q = blockIdx.x;
@@ -610,6 +761,7 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
   const double* rec = mom + 8 * (size_t)m;
   const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4];
   const double nu = P.relax ? rec[5] : 0.0;
+  const double* qt = SK ? heat + 3 * (size_t)m : nullptr;
   const double V = G.vcv[m];
   const double Tw = P.t_wall;
   double phiw[kMaxMembers];
@@ -632,7 +784,7 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
   }
   double sx[kMaxMembers], sy[kMaxMembers], sz[kMaxMembers];
   for (int t = 0; t < kMaxMembers; ++t) { sx[t] = 0.0; sy[t] = 0.0; sz[t] = 0.0; }
-  double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0, n4 = 0.0;
+  Sums3<SK> sm;
   for (int p = tid; p < nvel; p += nth) {
     const double v[3] = {vnode3(P.vmin, P.dv, p % N), vnode3(P.vmin, P.dv, (p / N) % N),
                          vnode3(P.vmin, P.dv, p / (N * N))};
@@ -665,20 +817,20 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
     }
     if (P.write_state) {
       const double cx = v[0] - ux, cy = v[1] - uy, cz = v[2] - uz;
-      const double E = nu != 0.0 ? Am * exp(-(cx * cx + cy * cy + cz * cz) * inv2T) : 0.0;
+      double E = nu != 0.0 ? Am * exp(-(cx * cx + cy * cy + cz * cz) * inv2T) : 0.0;
+      if (SK && nu != 0.0) E = shakhov3(qt, 2.0 * inv2T, cx, cy, cz, E);
       const double fn = fo - P.dt / V * Rs + nu * (E - fo);
       for (int t = 0; t < nm; ++t) out[(size_t)G.mem[b + t] * nvel + p] = fn;
-      n0 += fn; n1 += v[0] * fn; n2 += v[1] * fn; n3 += v[2] * fn;
-      n4 += (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) * fn;
+      sm.add(v[0], v[1], v[2], fn);
     }
   }
   if (P.write_state) {
-    n0 = block_sum(n0, lds); n1 = block_sum(n1, lds); n2 = block_sum(n2, lds);
-    n3 = block_sum(n3, lds); n4 = block_sum(n4, lds);
-    double* pp = part + (size_t)m * nch * 5;
-    for (int k = tid; k < nch * 5; k += nth) pp[k] = 0.0;
+    sm.reduce([&](double x) { return block_sum(x, lds); });
+    double* pp = part + (size_t)m * nch * K;
+    for (int k = tid; k < nch * K; k += nth) pp[k] = 0.0;
     __syncthreads();
-    if (tid == 0) { pp[0] = n0; pp[1] = n1; pp[2] = n2; pp[3] = n3; pp[4] = n4; }
+    if (tid == 0)
+      for (int k = 0; k < K; ++k) pp[k] = sm.s[k];
   }
   double Fx = 0.0, Fy = 0.0, Fz = 0.0;
   for (int t = 0; t < nm; ++t) {
@@ -815,10 +967,13 @@ __global__ void __launch_bounds__(256) k_mass3d(Geo3D G, const double* __restric
 // (chunk slot 0, the other slots zero).  One wave per cell; the separable
 // Maxwellian is tabulated per axis in the first N lanes when the velocity
 // count is a multiple of the wave.
+template <bool SK>
 __global__ void __launch_bounds__(256) k_relax3d(Geo3D G, double* __restrict__ st,
                                                 const double* __restrict__ mom,
+                                                const double* __restrict__ heat,
                                                 double* __restrict__ part, int nch, double vmin,
                                                 double dv) {
+  constexpr int K = Sums3<SK>::K;
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= G.ncell) return;
@@ -827,6 +982,7 @@ __global__ void __launch_bounds__(256) k_relax3d(Geo3D G, double* __restrict__ s
   const int N = G.N, nvel = G.nvel;
   const double* rec = mom + 8 * (size_t)m;
   const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4], nu = rec[5];
+  const double* qt = SK ? heat + 3 * (size_t)m : nullptr;
   const double sc = 1.0 / (1.0 + nu);
   double tx = 0.0, ty = 0.0, tz = 0.0;
   if (lane < N) {
@@ -837,7 +993,7 @@ __global__ void __launch_bounds__(256) k_relax3d(Geo3D G, double* __restrict__ s
   }
   const bool tables = nvel % kWave == 0;
   double* row = st + (size_t)c * nvel;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+  Sums3<SK> sm;
   for (int p = lane; p < nvel; p += kWave) {
     const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
     const double vx = vnode3(vmin, dv, p1), vy = vnode3(vmin, dv, p2), vz = vnode3(vmin, dv, p3);
@@ -848,17 +1004,17 @@ __global__ void __launch_bounds__(256) k_relax3d(Geo3D G, double* __restrict__ s
       const double cx = vx - ux, cy = vy - uy, cz = vz - uz;
       E = Am * exp(-(cx * cx + cy * cy + cz * cz) * inv2T);
     }
+    if (SK) E = shakhov3(qt, 2.0 * inv2T, vx - ux, vy - uy, vz - uz, E);
     const double fn = (row[p] + nu * E) * sc;
     row[p] = fn;
-    s0 += fn; s1 += vx * fn; s2 += vy * fn; s3 += vz * fn;
-    s4 += (vx * vx + vy * vy + vz * vz) * fn;
+    sm.add(vx, vy, vz, fn);
   }
   if (c != m) return;
-  s0 = wave_sum3(s0); s1 = wave_sum3(s1); s2 = wave_sum3(s2);
-  s3 = wave_sum3(s3); s4 = wave_sum3(s4);
-  double* pp = part + (size_t)c * nch * 5;
-  for (int k = lane; k < nch * 5; k += kWave) pp[k] = 0.0;
-  if (lane == 0) { pp[0] = s0; pp[1] = s1; pp[2] = s2; pp[3] = s3; pp[4] = s4; }
+  sm.reduce([](double x) { return wave_sum3(x); });
+  double* pp = part + (size_t)c * nch * K;
+  for (int k = lane; k < nch * K; k += kWave) pp[k] = 0.0;
+  if (lane == 0)
+    for (int k = 0; k < K; ++k) pp[k] = sm.s[k];
 }
 
 int node_count(int nvel) {
@@ -869,27 +1025,33 @@ int node_count(int nvel) {
 typedef void (*step3_fn)(const Step3Args, const int*, const double*);
 typedef void (*part3_fn)(Geo3D, const double*, double*, double, double);
 
-template <int N>
+template <int N, bool SK>
 void pick3(step3_fn* s, part3_fn* p, int* nch) {
   if constexpr (N == 16) {
-    if (s) *s = k_step3d16;
+    if (s) *s = k_step3d16<SK>;
   } else {
-    if (s) *s = k_step3d<N>;
+    if (s) *s = k_step3d<N, SK>;
   }
-  if (p) *p = k_part3d<N>;
+  if (p) *p = k_part3d<N, SK>;
   if (nch) *nch = Chunk3<N>::NCH;
 }
 
-bool select3(int N, step3_fn* s, part3_fn* p, int* nch) {
+template <bool SK>
+bool select3_sk(int N, step3_fn* s, part3_fn* p, int* nch) {
   switch (N) {
-    case 4: pick3<4>(s, p, nch); return true;
-    case 6: pick3<6>(s, p, nch); return true;
-    case 8: pick3<8>(s, p, nch); return true;
-    case 12: pick3<12>(s, p, nch); return true;
-    case 16: pick3<16>(s, p, nch); return true;
+    case 4: pick3<4, SK>(s, p, nch); return true;
+    case 6: pick3<6, SK>(s, p, nch); return true;
+    case 8: pick3<8, SK>(s, p, nch); return true;
+    case 12: pick3<12, SK>(s, p, nch); return true;
+    case 16: pick3<16, SK>(s, p, nch); return true;
     default: return false;
   }
 }
+
+bool select3(int N, step3_fn* s, part3_fn* p, int* nch, bool sk = false) {
+  return sk ? select3_sk<true>(N, s, p, nch) : select3_sk<false>(N, s, p, nch);
+}
+
 
 double tau_coef(const cc_ctx* ctx) {
   return ctx->cfg.kn > 0.0 ? sqrt(M_PI) / 2.0 * ctx->cfg.kn * ctx->cfg.lref / sqrt(2.0) : 0.0;
@@ -911,11 +1073,12 @@ hipError_t run_mom3d(cc_ctx* ctx, int mode = 0) {
   P.N = ctx->N;
   P.conservative = ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE;
   P.mode = mode;
+  P.sk_coef = (1.0 - ctx->cfg.prandtl) / 5.0;
+  const bool sk = ctx->cfg.model == CC_MODEL_SHAKHOV;
+  auto fn = P.conservative ? (sk ? k_mom3d<true, true> : k_mom3d<true, false>)
+                           : (sk ? k_mom3d<false, true> : k_mom3d<false, false>);
   prof_begin(ctx, 4);
-  if (P.conservative)
-    k_mom3d<true><<<mom_blocks(ctx), 256, 0, ctx->stream>>>(ctx->g3, ctx->s.part, ctx->s.mom, ctx->s.mpart, P);
-  else
-    k_mom3d<false><<<mom_blocks(ctx), 256, 0, ctx->stream>>>(ctx->g3, ctx->s.part, ctx->s.mom, ctx->s.mpart, P);
+  fn<<<mom_blocks(ctx), 256, 0, ctx->stream>>>(ctx->g3, ctx->s.part, ctx->s.mom, ctx->s.heat, ctx->s.mpart, P);
   prof_end(ctx, 4);
   return hipGetLastError();
 }
@@ -940,8 +1103,9 @@ hipError_t cut_and_reduce(cc_ctx* ctx, const double* in, double* out, int write,
   const int nb = mom_blocks(ctx);
   if (ctx->n_irr > 0) {
     prof_begin(ctx, 1);
-    k_cut3d<<<ctx->n_irr, 256, 0, ctx->stream>>>(ctx->g3, in, out, ctx->s.fslot, ctx->s.mom, ctx->s.part,
-                                                 chunks3d(ctx->N), cut_params(ctx, write, relax));
+    auto fn = ctx->cfg.model == CC_MODEL_SHAKHOV ? k_cut3d<true> : k_cut3d<false>;
+    fn<<<ctx->n_irr, 256, 0, ctx->stream>>>(ctx->g3, in, out, ctx->s.fslot, ctx->s.mom, ctx->s.heat,
+                                            ctx->s.part, chunks3d(ctx->N), cut_params(ctx, write, relax));
     prof_end(ctx, 1);
   }
   if (row) {
@@ -993,7 +1157,7 @@ hipError_t launch_merge_3d(cc_ctx* ctx) {
 
 hipError_t launch_moments_all_3d(cc_ctx* ctx) {
   part3_fn fn = nullptr;
-  if (!select3(ctx->N, nullptr, &fn, nullptr)) return hipErrorNotSupported;
+  if (!select3(ctx->N, nullptr, &fn, nullptr, ctx->cfg.model == CC_MODEL_SHAKHOV)) return hipErrorNotSupported;
   fn<<<(ctx->ncell + 3) / 4, 256, 0, ctx->stream>>>(ctx->g3, (const double*)ctx->state[ctx->cur],
                                                      ctx->s.part, ctx->cfg.vmin, ctx->dv);
   return hipGetLastError();
@@ -1003,7 +1167,7 @@ hipError_t launch_moments_all_3d(cc_ctx* ctx) {
 // the state entering the step.
 hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
   step3_fn fn = nullptr;
-  if (!select3(ctx->N, &fn, nullptr, nullptr)) return hipErrorNotSupported;
+  if (!select3(ctx->N, &fn, nullptr, nullptr, ctx->cfg.model == CC_MODEL_SHAKHOV)) return hipErrorNotSupported;
   const bool imex = ctx->cfg.scheme == CC_SCHEME_IMEX;
   hipError_t e = run_mom3d(ctx, imex ? 1 : 0);
   if (e != hipSuccess) return e;
@@ -1015,6 +1179,7 @@ hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
   A.kind = ctx->g3.kind;
   A.mom = ctx->s.mom;
   A.part = ctx->s.part;
+  A.heat = ctx->s.heat;
   A.ghost = ctx->g3.ghost;
   A.nx = ctx->nx; A.ny = ctx->ny; A.nz = ctx->nz; A.nvel = ctx->nvel;
   A.ntj = (ctx->ny + kTY - 1) / kTY;
@@ -1050,8 +1215,9 @@ hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
     e = run_mom3d(ctx, 2);
     if (e != hipSuccess) return e;
     prof_begin(ctx, 5);
-    k_relax3d<<<(ctx->ncell + 3) / 4, 256, 0, ctx->stream>>>(ctx->g3, out, ctx->s.mom, ctx->s.part,
-                                                             chunks3d(ctx->N), ctx->cfg.vmin, ctx->dv);
+    auto rfn = ctx->cfg.model == CC_MODEL_SHAKHOV ? k_relax3d<true> : k_relax3d<false>;
+    rfn<<<(ctx->ncell + 3) / 4, 256, 0, ctx->stream>>>(ctx->g3, out, ctx->s.mom, ctx->s.heat, ctx->s.part,
+                                                       chunks3d(ctx->N), ctx->cfg.vmin, ctx->dv);
     prof_end(ctx, 5);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

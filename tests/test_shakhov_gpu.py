@@ -146,3 +146,79 @@ def test_adjoint_rejects_shakhov():
     s = solver(CASES["cyl32"])
     with pytest.raises(CCError):
         s.adjoint(2, 1)
+
+
+# ---------------------------------------------------------------- 3D
+from ccdvm_inputs import small_3d  # noqa: E402
+from oracle.oracle import Oracle3D  # noqa: E402
+
+CASES3 = {
+    "n16": small_3d(16, 8, 8, nv=16, kn=0.01, mach=0.5, **SK),
+    "ragged_n8_cons": small_3d(13, 7, 9, nv=8, kn=0.05, mach=0.9, body=Body("sphere", (0.45, 0.24, 0.26), (0.15,) * 3,
+                               t_wall=1.4), maxwellian="conservative", **SK),
+    "n6_merge_pr03": small_3d(6, 5, 5, nv=6, kn=0.02, mach=0.4, body=Body("sphere", (0.5, 0.26, 0.24), (0.17,) * 3),
+                              prandtl=0.3, **SK),
+    "n16_imex": small_3d(16, 8, 8, nv=16, kn=0.002, mach=0.5, scheme="imex", **SK),
+    "n12_imex_cons": small_3d(12, 9, 8, nv=12, kn=0.003, mach=0.7, body=Body("sphere", (0.5, 0.3, 0.25), (0.14,) * 3,
+                              t_wall=1.2), scheme="imex", maxwellian="conservative", **SK),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES3))
+def test_one_step_3d(name):
+    cfg = CASES3[name]
+    F0, _ = random_state(cfg.ncell, cfg.nv, 3, seed=79, with_g=False)
+    s = solver(cfg)
+    s.load_state(torch.from_numpy(F0))
+    d = s.step(1, diag=True).cpu().numpy()
+    F1 = s.store_state()[0].cpu().numpy()
+    Fo, do = Oracle3D(cfg).step(F0)
+    assert relerr(F1, Fo) < 1e-12
+    scale = max(np.max(np.abs(do[:3])), 1e-12)
+    assert np.all(np.abs(d[0, :3] - do[:3]) <= 1e-10 * scale + 1e-15)
+    assert abs(d[0, 3] - do[3]) <= 1e-12 * abs(do[3])
+    Fb = Oracle3D(cfg.with_(model="bgk")).step(F0)[0]
+    assert relerr(Fb, Fo) > 1e-9
+
+
+@pytest.mark.parametrize("name", ["n16", "ragged_n8_cons", "n16_imex"])
+def test_twenty_steps_3d(name):
+    cfg = CASES3[name]
+    s = solver(cfg)
+    s.init_maxwellian()
+    d = s.step(20, diag=True).cpu().numpy()
+    F1 = s.store_state()[0].cpu().numpy()
+    o = Oracle3D(cfg)
+    Fo, do = o.run(o.init(), 20)
+    assert relerr(F1, Fo) < 1e-9
+    assert np.max(np.abs(d[:, 3] - do[:, 3]) / do[:, 3]) < 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_sphere128_full_size_sampled_cells():
+    """Full sphere128 size (128 x 64 x 64 cells, 16^3 velocities) with the
+    Shakhov model: one step from a seeded state, sampled cells (cut and
+    merged control volumes, domain faces, random interior cells)
+    recomputed by the oracle."""
+    from ccdvm_inputs import tiled_random_state
+    cfg = workload("sphere128").with_(**SK)
+    f0 = tiled_random_state(cfg.ncell, cfg.nv, 3, seed=129)
+    s = solver(cfg)
+    s.load_state(torch.from_numpy(f0))
+    s.step(1)
+    f1 = s.store_state()[0]
+    o = Oracle3D(cfg)
+    geo = o.geometry()
+    nx, ny, nz = cfg.n
+    idx = np.arange(cfg.ncell)
+    ii, jj, kk = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    rng = np.random.default_rng(3)
+    cut = np.nonzero((geo["type"] == 1) | ((geo["master"] >= 0) & (geo["master"] != idx)))[0]
+    faces = idx[(ii == 0) | (ii == nx - 1) | (jj == 0) | (jj == ny - 1) | (kk == 0) | (kk == nz - 1)]
+    cells = np.unique(np.concatenate([cut, faces[::97], rng.integers(0, cfg.ncell, 300)])).astype(np.int32)
+    fm = o.merge(f0)
+    del f0
+    fo = o.update_cells(fm, cells)
+    del fm
+    sel = f1.index_select(0, torch.from_numpy(cells.astype(np.int64)).to(f1.device)).cpu().numpy()
+    assert relerr(sel, fo) < 1e-12
