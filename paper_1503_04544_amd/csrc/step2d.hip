@@ -310,10 +310,13 @@ constexpr int kListBlocks = 512;   // grid of kernels that walk a list whose len
 #ifndef CCDVM_PREFETCH
 #define CCDVM_PREFETCH 4
 #endif
+#ifndef CCDVM_XLDS
+#define CCDVM_XLDS 1
+#endif
 // VGPRs the Shakhov variant needs beyond the BGK one (heat-flux sums, q and
 // the velocity offsets), taken from the prefetch budget
 #ifndef CCDVM_SK_REGS
-#define CCDVM_SK_REGS 24
+#define CCDVM_SK_REGS 40
 #endif
 // Chunks loaded ahead of the one computed.  Each chunk in flight costs 16
 // VGPRs and the row window 8 per chunk; the depth is capped so that a wave
@@ -401,8 +404,15 @@ __host__ __device__ inline TileArgs tile_args(const Geo2D& G, const FusedArgs& A
   return T;
 }
 
+// xlo (nullable): LDS of kTileW x NCH x 64 values.  At each row every wave
+// publishes the lower half of its cell there, and the waves of the tile read
+// their x-upwind lower halves from it: that half was loaded by its owner one
+// row earlier (as the y-upwind of the row below), so its lines have left L2
+// by the time the neighbours need them.  (The upper half is loaded by its
+// owner in the same row and comes through L2.)
 template <int NCH, bool SK>
-__device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, double* lds) {
+__device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, double* lds,
+                             d2v* xlo = nullptr) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gi = tile % Ta.ngroups, seg = tile / Ta.ngroups;
   const int i = gi * kTileW + wave;
@@ -421,6 +431,12 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
     load_half<NCH>(prevU, j0 > 0 ? in + (size_t)((j0 - 1) * nx + i) * nvel : ghost, lo_n, hi_n, lane);
     load_half<NCH>(curL, in + (size_t)(j0 * nx + i) * nvel, 0, lo_n, lane);
     for (int j = j0; j < j1; ++j) {
+      if (xlo) {
+        __syncthreads();   // every wave is done with the previous row's halves
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) xlo[(wave * NCH + k) * kWave + lane] = curL[k];
+        __syncthreads();
+      }
       const int c = j * nx + i;
       const d2v* row = in + (size_t)c * nvel;
       const d2v* nrow = j + 1 < ny ? row + (size_t)nx * nvel : ghost;
@@ -460,13 +476,20 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
       asm volatile("" : "+v"(lv));
       constexpr int PD = prefetch_depth(NCH, SK);
       d2v bN[NCH], bU[NCH], bXa[NCH], bXb[NCH];
+      // lanes whose x-upwind cell is another wave of this tile read its
+      // lower half from xlo (v_x > 0: the wave to the left)
+      auto xwave = [&](int k) {
+        const bool pos = vnode(P.vmin, P.dv, (k * 64 + lv) % N) > 0.0;
+        const bool in_tile = pos ? wave > 0 : (wave + 1 < kTileW && i + 1 < nx);
+        return xlo && in_tile ? (pos ? wave - 1 : wave + 1) : -1;
+      };
       auto issue = [&](int k) {
         const int o = k * 64 + lv;
         const int lp1 = o % N;
         const d2v* xrow = vnode(P.vmin, P.dv, lp1) > 0.0 ? xl : xr;
         bN[k] = o < lo_n ? nrow[o] : d2v{0.0, 0.0};
         bU[k] = o < hi_n ? row[lo_n + o] : d2v{0.0, 0.0};
-        bXa[k] = reg && o < lo_n ? xrow[o] : d2v{0.0, 0.0};
+        bXa[k] = reg && o < lo_n && xwave(k) < 0 ? xrow[o] : d2v{0.0, 0.0};
         bXb[k] = reg && o < hi_n ? xrow[lo_n + o] : d2v{0.0, 0.0};
       };
 #pragma unroll
@@ -475,7 +498,9 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
       for (int k = 0; k < NCH; ++k) {
         if (k + PD < NCH) issue(k + PD);
         const int o = k * 64 + lv;
-        const d2v nL = bN[k], cU = bU[k], xa = bXa[k], xb = bXb[k];
+        const int xw = xwave(k);
+        const d2v nL = bN[k], cU = bU[k], xb = bXb[k];
+        const d2v xa = xw >= 0 && o < lo_n ? xlo[(xw * NCH + k) * kWave + lv] : bXa[k];
         if (reg) {
           const int p1 = o % N, q2 = o / N;
           const double vx = vnode(P.vmin, P.dv, p1);
@@ -523,6 +548,8 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
       }
     }
   }
+  if (xlo && !(i < nx) && j0 < j1)   // columns past the grid still take part in the row barriers
+    for (int j = j0; j < j1; ++j) { __syncthreads(); __syncthreads(); }
   __syncthreads();
   if (lane == 0) lds[wave] = msum;
   __syncthreads();
@@ -533,6 +560,8 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
 template <int NCH, bool SK>
 __global__ void __launch_bounds__(256) k_step2d(Geo2D G, FusedArgs A, StepParams P) {
   __shared__ double lds[8];
+  constexpr bool kX = CCDVM_XLDS && NCH <= 16;   // LDS lower halves (<= 64 KB per block)
+  __shared__ d2v xlo[kX ? kTileW * NCH * kWave : 1];
   const int bid = blockIdx.x;
   if (bid < A.tile_base) {
     if (bid == 0 && A.prev_mpart) deferred_reduce(G, A, lds);
@@ -544,7 +573,7 @@ __global__ void __launch_bounds__(256) k_step2d(Geo2D G, FusedArgs A, StepParams
   const int per = A.ntiles_pad / 8;
   const int tile = (b % 8) * per + b / 8;
   if (tile >= A.ntiles) return;
-  regular_tile<NCH, SK>(tile_args(G, A), P, tile, lds);
+  regular_tile<NCH, SK>(tile_args(G, A), P, tile, lds, kX ? xlo : nullptr);
 }
 
 // cut / merged control volumes of one step, one 256-thread block each
@@ -1418,9 +1447,9 @@ hipError_t launch_mass_2d(cc_ctx* ctx, double* mass_row) {
 // Tile shape of the regular-cell pass: kTileW columns x seglen rows.
 int tile_rows(const cc_ctx* ctx) {
   if (ctx->seglen > 0) return ctx->seglen;
-  // aim for ~4 resident tiles per CU on 256 CUs
+  // aim for ~2 tiles per CU on 256 CUs (as many as are resident at once)
   const int groups = (ctx->nx + kTileW - 1) / kTileW;
-  int segs = (1024 + groups - 1) / groups;
+  int segs = (512 + groups - 1) / groups;
   if (segs < 1) segs = 1;
   int rows = (ctx->ny + segs - 1) / segs;
   return rows < 1 ? 1 : rows;
