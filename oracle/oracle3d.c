@@ -89,6 +89,77 @@ static double levelset3(const orc_cfg *cf, double x, double y, double z) {
   return 1.0e300;
 }
 
+/* Geometry of one cell of sizes h[3] from its 8 clamped vertex values
+   q8[a | b << 1 | c << 2] (a, b, c = 0/1 along x, y, z): type, the gas
+   areas S6 of its faces (x-, x+, y-, y+, z-, z+), the wall area, its unit
+   normal into the solid and its centre relative to the cell's lower corner,
+   and the gas volume.  Returns 1 when a face is a saddle (four crossings). */
+static int cell_geom3(const double *q8, const double *h, int *type_out, double *S6, double *sw_out,
+                      double *nw_out, double *rloc, double *vbar) {
+  double qmin = 1e300, qmax = -1e300;
+  int bad = 0;
+  for (int t = 0; t < 8; ++t) { qmin = mn(qmin, q8[t]); qmax = mx(qmax, q8[t]); }
+  int type = qmin > 0.0 ? GAS : (qmax < 0.0 ? SOLID : CUT);
+  *type_out = type;
+  /* faces: axis d, side s (0: at 0, 1: at h_d); local axes (d1, d2) */
+  double V = 0.0;
+  double Aw[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d) {
+    int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+    for (int sd = 0; sd < 2; ++sd) {
+      double q[4];
+      /* corners in the order (0,0), (h1,0), (h1,h2), (0,h2) of (d1, d2) */
+      int co[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+      for (int t = 0; t < 4; ++t) {
+        int idx[3];
+        idx[d] = sd; idx[d1] = co[t][0]; idx[d2] = co[t][1];
+        q[t] = q8[idx[0] | (idx[1] << 1) | (idx[2] << 2)];
+      }
+      double area, cs, ct, xs[4], xt[4];
+      int saddle, ncr;
+      face_polygon(q, h[d1], h[d2], &area, &cs, &ct, &saddle, &ncr, xs, xt);
+      if (saddle) bad = 1;
+      S6[2 * d + sd] = type == SOLID ? 0.0 : area;
+      /* outward normal: -e_d on side 0, +e_d on side 1; m.n = sd*h_d */
+      double sgn = sd ? 1.0 : -1.0;
+      Aw[d] -= sgn * area;
+      V += area * (sd ? h[d] : 0.0) / 3.0;
+    }
+  }
+  /* edge crossings of the cell (12 edges) -> wall centre */
+  double rs[3] = {0, 0, 0};
+  int ncx = 0;
+  for (int d = 0; d < 3; ++d)
+    for (int t = 0; t < 4; ++t) {
+      int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+      int idx0[3], idx1[3];
+      idx0[d] = 0; idx1[d] = 1;
+      idx0[d1] = idx1[d1] = t & 1;
+      idx0[d2] = idx1[d2] = (t >> 1) & 1;
+      double qa = q8[idx0[0] | (idx0[1] << 1) | (idx0[2] << 2)];
+      double qb = q8[idx1[0] | (idx1[1] << 1) | (idx1[2] << 2)];
+      if ((qa > 0.0) != (qb > 0.0)) {
+        double tt = qa / (qa - qb);
+        double p3[3];
+        p3[d] = tt * h[d]; p3[d1] = idx0[d1] * h[d1]; p3[d2] = idx0[d2] * h[d2];
+        rs[0] += p3[0]; rs[1] += p3[1]; rs[2] += p3[2];
+        ++ncx;
+      }
+    }
+  double Sw = sqrt(Aw[0] * Aw[0] + Aw[1] * Aw[1] + Aw[2] * Aw[2]);
+  if (type == CUT && ncx > 0 && Sw > 0.0) {
+    double r[3] = {rs[0] / ncx, rs[1] / ncx, rs[2] / ncx};
+    *sw_out = Sw;
+    for (int d = 0; d < 3; ++d) { nw_out[d] = Aw[d] / Sw; rloc[d] = r[d]; }
+    V += (r[0] * Aw[0] + r[1] * Aw[1] + r[2] * Aw[2]) / 3.0;
+  } else {
+    *sw_out = 0.0;
+    for (int d = 0; d < 3; ++d) { nw_out[d] = 0.0; rloc[d] = 0.0; }
+  }
+  *vbar = type == SOLID ? 0.0 : (type == GAS ? h[0] * h[1] * h[2] : V);
+  return bad;
+}
+
 static int build3(orc3d *o) {
   const orc_cfg *cf = &o->cfg;
   int nx = o->nx, ny = o->ny, nz = o->nz;
@@ -109,72 +180,22 @@ static int build3(orc3d *o) {
       for (int i = 0; i < nx; ++i) {
         int cc = (k * ny + j) * nx + i;
         double q8[8];
-        double qmin = 1e300, qmax = -1e300;
-        for (int t = 0; t < 8; ++t) {
-          q8[t] = PH(i + (t & 1), j + ((t >> 1) & 1), k + ((t >> 2) & 1));
-          qmin = mn(qmin, q8[t]); qmax = mx(qmax, q8[t]);
-        }
-        int type = qmin > 0.0 ? GAS : (qmax < 0.0 ? SOLID : CUT);
+        for (int t = 0; t < 8; ++t) q8[t] = PH(i + (t & 1), j + ((t >> 1) & 1), k + ((t >> 2) & 1));
+        double S6[6], sw, nw[3], rl[3], vb;
+        int type;
+        if (cell_geom3(q8, h, &type, S6, &sw, nw, rl, &vb)) bad = 1;
         o->type[cc] = type;
-        /* faces: axis d, side s (0: at 0, 1: at h_d); local axes (d1, d2) */
-        double V = 0.0;
-        double Aw[3] = {0, 0, 0};
-        for (int d = 0; d < 3; ++d) {
-          int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
-          for (int sd = 0; sd < 2; ++sd) {
-            double q[4];
-            /* corners in the order (0,0), (h1,0), (h1,h2), (0,h2) of (d1, d2) */
-            int co[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
-            for (int t = 0; t < 4; ++t) {
-              int idx[3];
-              idx[d] = sd; idx[d1] = co[t][0]; idx[d2] = co[t][1];
-              q[t] = q8[idx[0] | (idx[1] << 1) | (idx[2] << 2)];
-            }
-            double area, cs, ct, xs[4], xt[4];
-            int saddle, ncr;
-            face_polygon(q, h[d1], h[d2], &area, &cs, &ct, &saddle, &ncr, xs, xt);
-            if (saddle) bad = 1;
-            o->S[2 * d + sd][cc] = type == SOLID ? 0.0 : area;
-            /* outward normal: -e_d on side 0, +e_d on side 1; m.n = sd*h_d */
-            double sgn = sd ? 1.0 : -1.0;
-            Aw[d] -= sgn * area;
-            V += area * (sd ? h[d] : 0.0) / 3.0;
-          }
-        }
-        /* edge crossings of the cell (12 edges) -> wall centre */
-        double rs[3] = {0, 0, 0};
-        int ncx = 0;
-        for (int d = 0; d < 3; ++d)
-          for (int t = 0; t < 4; ++t) {
-            int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
-            int idx0[3], idx1[3];
-            idx0[d] = 0; idx1[d] = 1;
-            idx0[d1] = idx1[d1] = t & 1;
-            idx0[d2] = idx1[d2] = (t >> 1) & 1;
-            double qa = q8[idx0[0] | (idx0[1] << 1) | (idx0[2] << 2)];
-            double qb = q8[idx1[0] | (idx1[1] << 1) | (idx1[2] << 2)];
-            if ((qa > 0.0) != (qb > 0.0)) {
-              double tt = qa / (qa - qb);
-              double p3[3];
-              p3[d] = tt * h[d]; p3[d1] = idx0[d1] * h[d1]; p3[d2] = idx0[d2] * h[d2];
-              rs[0] += p3[0]; rs[1] += p3[1]; rs[2] += p3[2];
-              ++ncx;
-            }
-          }
-        double Sw = sqrt(Aw[0] * Aw[0] + Aw[1] * Aw[1] + Aw[2] * Aw[2]);
-        if (type == CUT && ncx > 0 && Sw > 0.0) {
-          double r[3] = {rs[0] / ncx, rs[1] / ncx, rs[2] / ncx};
-          o->sw[cc] = Sw;
-          for (int d = 0; d < 3; ++d) o->nw[d][cc] = Aw[d] / Sw;
-          V += (r[0] * Aw[0] + r[1] * Aw[1] + r[2] * Aw[2]) / 3.0;
-          o->rw[0][cc] = cf->lo[0] + i * o->dx + r[0];
-          o->rw[1][cc] = cf->lo[1] + j * o->dy + r[1];
-          o->rw[2][cc] = cf->lo[2] + k * o->dz + r[2];
+        for (int f = 0; f < 6; ++f) o->S[f][cc] = S6[f];
+        o->sw[cc] = sw;
+        for (int d = 0; d < 3; ++d) o->nw[d][cc] = nw[d];
+        if (sw > 0.0) {
+          o->rw[0][cc] = cf->lo[0] + i * o->dx + rl[0];
+          o->rw[1][cc] = cf->lo[1] + j * o->dy + rl[1];
+          o->rw[2][cc] = cf->lo[2] + k * o->dz + rl[2];
         } else {
-          o->sw[cc] = 0.0;
-          for (int d = 0; d < 3; ++d) { o->nw[d][cc] = 0.0; o->rw[d][cc] = 0.0; }
+          for (int d = 0; d < 3; ++d) o->rw[d][cc] = 0.0;
         }
-        o->vbar[cc] = type == SOLID ? 0.0 : (type == GAS ? o->dx * o->dy * o->dz : V);
+        o->vbar[cc] = vb;
       }
   /* masters: centre in gas = mean of the 8 vertex values > 1e-12 dx; hop
      across the largest face shared with a cell of the domain, order
@@ -466,12 +487,12 @@ void orc3d_equilibrium_values(const orc3d *o, const double *F, double *Fe) {
 }
 
 /* scheme (eq-schema3D) for control volume m, fixed geometry */
-static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
-  int nvel = o->nvel, N = o->N, nx = o->nx, ny = o->ny, nz = o->nz;
-  const double *fc = Fm + (size_t)m * nvel;
-  const double *in = o->cfg.inflow;
-  double uin[3] = {in[1], in[2], in[3]};
-  double Tw = o->cfg.t_wall, zero[3] = {0, 0, 0};
+/* Update of one control volume from its transport residual R (the sum of
+   its members' face and wall fluxes, velocity by velocity) and volume V:
+   the explicit scheme with the relaxation of eq. (eq-schema3D), or the
+   semi-implicit scheme (ImpSchemeDD in 3D). */
+static void relax_update3(const orc3d *o, const double *fc, const double *R, double V, double *out) {
+  int nvel = o->nvel, N = o->N;
   /* READING: conservative equilibrium -> the whole triplet, rho in tau
      included, from the Newton solution */
   relax3 tg;
@@ -479,7 +500,54 @@ static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
   double rho = tg.rho;
   int collide = o->cfg.kn > 0.0;
   double tau = collide ? sqrt(M_PI) / 2.0 * (1.0 / rho) * o->cfg.kn * o->cfg.lref / sqrt(2.0) : 1.0;
-  double V = o->vcv[m];
+  if (o->cfg.scheme == 1) {
+    /* semi-implicit scheme (ImpSchemeDD in 3D): equilibrium of the
+       transported value, tau^n from the direct density at t^n (READING) */
+    double *fs = calloc(nvel, sizeof(double));
+    for (int p = 0; p < nvel; ++p) fs[p] = fc[p] - o->dt / V * R[p];
+    double rn, un[3], Tn;
+    moments3(o, fc, &rn, un, &Tn);
+    double nu = collide ? o->dt / (sqrt(M_PI) / 2.0 * (1.0 / rn) * o->cfg.kn * o->cfg.lref / sqrt(2.0)) : 0.0;
+    relax3 t1;
+    relax_target3(o, fs, &t1);
+    for (int p = 0; p < nvel; ++p) {
+      double E = collide ? equilibrium_at3(o, &t1, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]) : 0.0;
+      out[p] = (fs[p] + nu * E) / (1.0 + nu);
+    }
+    free(fs);
+    return;
+  }
+  for (int p = 0; p < nvel; ++p) {
+    double E = collide ? equilibrium_at3(o, &tg, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]) : 0.0;
+    double fnew = fc[p] - o->dt / V * R[p];
+    if (collide) fnew += o->dt / tau * (E - fc[p]);
+    out[p] = fnew;
+  }
+}
+
+/* Diffuse wall of zero net mass flux (Section 5.1 step 4), fixed wall
+   u_w = 0, normal nwk into the solid: fw = phi_w M[1, 0, T_w] at every
+   velocity, phi_w from the outgoing flux of the control-volume value fc. */
+static void wall_values3(const orc3d *o, const double *fc, const double *nwk, double *fw) {
+  int nvel = o->nvel, N = o->N;
+  double Tw = o->cfg.t_wall, zero[3] = {0, 0, 0};
+  double num = 0.0, den = 0.0;
+  for (int p = 0; p < nvel; ++p) {
+    double vx = o->v[p % N], vy = o->v[(p / N) % N], vz = o->v[p / (N * N)];
+    double cn = vx * nwk[0] + vy * nwk[1] + vz * nwk[2];
+    if (cn > 0.0) num += cn * fc[p] * o->w;
+    else if (cn < 0.0) den += cn * maxw3(1.0, zero, Tw, vx, vy, vz) * o->w;
+  }
+  double phi = den != 0.0 ? -num / den : 0.0;
+  for (int p = 0; p < nvel; ++p)
+    fw[p] = phi * maxw3(1.0, zero, Tw, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]);
+}
+
+static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
+  int nvel = o->nvel, N = o->N, nx = o->nx, ny = o->ny, nz = o->nz;
+  const double *fc = Fm + (size_t)m * nvel;
+  const double *in = o->cfg.inflow;
+  double uin[3] = {in[1], in[2], in[3]};
   double *R = calloc(nvel, sizeof(double));
   double *fw = malloc(nvel * sizeof(double));
   for (int q = o->mptr[m]; q < o->mptr[m + 1]; ++q) {
@@ -490,17 +558,8 @@ static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
                  j + 1 < ny ? k + nx : -1, kk > 0 ? k - nx * ny : -1, kk + 1 < nz ? k + nx * ny : -1};
     int has_wall = o->sw[k] > 0.0;
     if (has_wall) {
-      /* wall density (Section 5.1 step 4), fixed wall u_w = 0 */
-      double num = 0.0, den = 0.0;
-      for (int p = 0; p < nvel; ++p) {
-        double vx = o->v[p % N], vy = o->v[(p / N) % N], vz = o->v[p / (N * N)];
-        double cn = vx * o->nw[0][k] + vy * o->nw[1][k] + vz * o->nw[2][k];
-        if (cn > 0.0) num += cn * fc[p] * o->w;
-        else if (cn < 0.0) den += cn * maxw3(1.0, zero, Tw, vx, vy, vz) * o->w;
-      }
-      double phi = den != 0.0 ? -num / den : 0.0;
-      for (int p = 0; p < nvel; ++p)
-        fw[p] = phi * maxw3(1.0, zero, Tw, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]);
+      const double nwk[3] = {o->nw[0][k], o->nw[1][k], o->nw[2][k]};
+      wall_values3(o, fc, nwk, fw);
     }
     for (int p = 0; p < nvel; ++p) {
       double vv[3] = {o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]};
@@ -520,55 +579,40 @@ static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
       R[p] += r;
     }
   }
-  if (o->cfg.scheme == 1) {
-    /* semi-implicit scheme (ImpSchemeDD in 3D): equilibrium of the
-       transported value, tau^n from the direct density at t^n (READING) */
-    double *fs = calloc(nvel, sizeof(double));
-    for (int p = 0; p < nvel; ++p) fs[p] = fc[p] - o->dt / V * R[p];
-    double rn, un[3], Tn;
-    moments3(o, fc, &rn, un, &Tn);
-    double nu = collide ? o->dt / (sqrt(M_PI) / 2.0 * (1.0 / rn) * o->cfg.kn * o->cfg.lref / sqrt(2.0)) : 0.0;
-    relax3 t1;
-    relax_target3(o, fs, &t1);
-    for (int p = 0; p < nvel; ++p) {
-      double E = collide ? equilibrium_at3(o, &t1, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]) : 0.0;
-      out[p] = (fs[p] + nu * E) / (1.0 + nu);
-    }
-    free(fs); free(R); free(fw);
-    return;
-  }
-  for (int p = 0; p < nvel; ++p) {
-    double E = collide ? equilibrium_at3(o, &tg, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]) : 0.0;
-    double fnew = fc[p] - o->dt / V * R[p];
-    if (collide) fnew += o->dt / tau * (E - fc[p]);
-    out[p] = fnew;
-  }
+  relax_update3(o, fc, R, o->vcv[m], out);
   free(R); free(fw);
 }
 
-static void force3(const orc3d *o, const double *Fm, double *diag) {
+/* wall stress of one wall face (normal nwk into the solid, area swk) from
+   the control-volume value fc, added to the force F (Section 5.1 step 5) */
+static void wall_force3(const orc3d *o, const double *fc, const double *nwk, double swk, double *F) {
   int nvel = o->nvel, N = o->N;
   double Tw = o->cfg.t_wall, zero[3] = {0, 0, 0};
+  double num = 0.0, den = 0.0;
+  for (int p = 0; p < nvel; ++p) {
+    double vx = o->v[p % N], vy = o->v[(p / N) % N], vz = o->v[p / (N * N)];
+    double cn = vx * nwk[0] + vy * nwk[1] + vz * nwk[2];
+    if (cn > 0.0) num += cn * fc[p] * o->w;
+    else if (cn < 0.0) den += cn * maxw3(1.0, zero, Tw, vx, vy, vz) * o->w;
+  }
+  double phi = den != 0.0 ? -num / den : 0.0;
+  double s[3] = {0, 0, 0};
+  for (int p = 0; p < nvel; ++p) {
+    double vv[3] = {o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]};
+    double cn = vv[0] * nwk[0] + vv[1] * nwk[1] + vv[2] * nwk[2];
+    double fv = cn < 0.0 ? phi * maxw3(1.0, zero, Tw, vv[0], vv[1], vv[2]) : (cn > 0.0 ? fc[p] : 0.0);
+    for (int d = 0; d < 3; ++d) s[d] += vv[d] * cn * fv * o->w;
+  }
+  for (int d = 0; d < 3; ++d) F[d] += s[d] * swk;
+}
+
+static void force3(const orc3d *o, const double *Fm, double *diag) {
+  int nvel = o->nvel;
   double F[3] = {0, 0, 0}, mass = 0.0;
   for (int k = 0; k < o->ncell; ++k) {
     if (o->sw[k] <= 0.0) continue;
-    const double *fc = Fm + (size_t)o->master[k] * nvel;
-    double num = 0.0, den = 0.0;
-    for (int p = 0; p < nvel; ++p) {
-      double vx = o->v[p % N], vy = o->v[(p / N) % N], vz = o->v[p / (N * N)];
-      double cn = vx * o->nw[0][k] + vy * o->nw[1][k] + vz * o->nw[2][k];
-      if (cn > 0.0) num += cn * fc[p] * o->w;
-      else if (cn < 0.0) den += cn * maxw3(1.0, zero, Tw, vx, vy, vz) * o->w;
-    }
-    double phi = den != 0.0 ? -num / den : 0.0;
-    double s[3] = {0, 0, 0};
-    for (int p = 0; p < nvel; ++p) {
-      double vv[3] = {o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]};
-      double cn = vv[0] * o->nw[0][k] + vv[1] * o->nw[1][k] + vv[2] * o->nw[2][k];
-      double fv = cn < 0.0 ? phi * maxw3(1.0, zero, Tw, vv[0], vv[1], vv[2]) : (cn > 0.0 ? fc[p] : 0.0);
-      for (int d = 0; d < 3; ++d) s[d] += vv[d] * cn * fv * o->w;
-    }
-    for (int d = 0; d < 3; ++d) F[d] += s[d] * o->sw[k];
+    const double nwk[3] = {o->nw[0][k], o->nw[1][k], o->nw[2][k]};
+    wall_force3(o, Fm + (size_t)o->master[k] * nvel, nwk, o->sw[k], F);
   }
   for (int m = 0; m < o->ncell; ++m) {
     if (o->master[m] != m) continue;
