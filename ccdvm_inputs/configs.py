@@ -75,6 +75,8 @@ class Config:
     scheme: str = "explicit"    # "explicit" or "imex" (semi-implicit relaxation)
     model: str = "bgk"          # relaxation model: "bgk" or "shakhov"
     prandtl: float = 2.0 / 3.0  # Prandtl number of the Shakhov model
+    amr_depth: int = 0          # 3D octree: finest depth below the coarse grid n (0: uniform)
+    amr_band: float = 0.0       # octree refinement band in coarse spacings (<= 0: 2 sqrt 2)
 
     @property
     def ncell(self) -> int:

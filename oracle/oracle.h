@@ -39,6 +39,8 @@ typedef struct {
   int scheme;              /* 0 explicit (ExSchemeDD), 1 semi-implicit (ImpSchemeDD) */
   int model;               /* 0 BGK, 1 Shakhov */
   double prandtl;          /* Prandtl number of the Shakhov model */
+  int amr_depth;           /* octree (3D): finest depth below the coarse grid n, 0 = uniform */
+  double amr_band;         /* octree refinement band in coarse spacings (<= 0: 2 sqrt 2) */
 } orc_cfg;
 
 typedef struct orc2d orc2d;
@@ -109,6 +111,26 @@ int  orc3d_equilibrium(const orc3d *o, const double *F, double *out);
 /* equilibrium of one cell's F at every velocity: the Maxwellian of Section
    2.1, or the Shakhov equilibrium given there */
 void orc3d_equilibrium_values(const orc3d *o, const double *F, double *Fe);
+
+/* 3D octree mesh around a fixed body (Section 5, octree procedure):
+   leaves in Z-order; state F[leaf][p] */
+typedef struct orc3a orc3a;
+int  orc3a_create(const orc_cfg *cfg, orc3a **out);
+void orc3a_destroy(orc3a *o);
+double orc3a_dt(const orc3a *o);
+int  orc3a_nleaf(const orc3a *o);
+int  orc3a_nface(const orc3a *o);
+void orc3a_velocity(const orc3a *o, double *v);
+/* per leaf: depth, coordinates at that depth (3), type, master, gas volume,
+   control-volume volume, wall area, the 6 face gas areas */
+void orc3a_leaves(const orc3a *o, int *lvl, int *ijk, int *type, int *master, double *vbar,
+                  double *vcv, double *sw, double *S6);
+/* face lists: fptr (nleaf + 1), neighbour leaf or -1, direction 0..5
+   (x-, x+, y-, y+, z-, z+), gas area */
+void orc3a_faces(const orc3a *o, int *fptr, int *fnb, int *fdir, double *farea);
+void orc3a_init(const orc3a *o, double *F);
+void orc3a_merge(const orc3a *o, double *F);
+int  orc3a_step(orc3a *o, const double *F, double *Fo, double *diag);
 
 #ifdef __cplusplus
 }

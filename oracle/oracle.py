@@ -28,7 +28,8 @@ class _Cfg(C.Structure):
                 ("axes", C.c_double * 3), ("theta", C.c_double), ("t_wall", C.c_double),
                 ("mass", C.c_double), ("inertia", C.c_double), ("motion", C.c_int),
                 ("vel", C.c_double * 3), ("omega", C.c_double), ("maxwellian", C.c_int),
-                ("scheme", C.c_int), ("model", C.c_int), ("prandtl", C.c_double)]
+                ("scheme", C.c_int), ("model", C.c_int), ("prandtl", C.c_double),
+                ("amr_depth", C.c_int), ("amr_band", C.c_double)]
 
 
 def cfg_struct(cfg) -> _Cfg:
@@ -53,6 +54,8 @@ def cfg_struct(cfg) -> _Cfg:
     s.scheme = {"explicit": 0, "imex": 1}[getattr(cfg, "scheme", "explicit")]
     s.model = {"bgk": 0, "shakhov": 1}[getattr(cfg, "model", "bgk")]
     s.prandtl = getattr(cfg, "prandtl", 2.0 / 3.0)
+    s.amr_depth = getattr(cfg, "amr_depth", 0)
+    s.amr_band = getattr(cfg, "amr_band", 0.0)
     return s
 
 
@@ -333,3 +336,99 @@ class Oracle3D:
         out = np.zeros((self.ncell, 14))
         _lib3().orc3d_moments(self._h, _p(np.ascontiguousarray(F)), _p(out))
         return out
+
+
+def _lib3a():
+    L = _lib3()
+    if not getattr(L, "_has3a", False):
+        P = C.c_void_p
+        L.orc3a_create.argtypes = [C.POINTER(_Cfg), C.POINTER(P)]
+        L.orc3a_destroy.argtypes = [P]
+        L.orc3a_dt.argtypes = [P]
+        L.orc3a_dt.restype = C.c_double
+        L.orc3a_nleaf.argtypes = [P]
+        L.orc3a_nface.argtypes = [P]
+        L.orc3a_velocity.argtypes = [P, P]
+        L.orc3a_leaves.argtypes = [P] + [P] * 8
+        L.orc3a_faces.argtypes = [P] + [P] * 4
+        L.orc3a_init.argtypes = [P, P]
+        L.orc3a_merge.argtypes = [P, P]
+        L.orc3a_step.argtypes = [P, P, P, P]
+        L._has3a = True
+    return L
+
+
+class Oracle3A:
+    """3D octree mesh around a fixed body (Section 5): state F of shape
+    (nleaf, N**3), leaves in Z-order."""
+
+    def __init__(self, cfg):
+        assert cfg.dim == 3
+        self.cfg = cfg
+        self._s = cfg_struct(cfg)
+        h = C.c_void_p()
+        st = _lib3a().orc3a_create(C.byref(self._s), C.byref(h))
+        if st != 0:
+            raise OracleError(f"oracle create failed with status {st}")
+        self._h = h
+        self.nleaf = _lib3a().orc3a_nleaf(h)
+        self.nface = _lib3a().orc3a_nface(h)
+        self.N = cfg.nv
+        self.nvel = cfg.nv ** 3
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib3a().orc3a_destroy(h)
+            self._h = None
+
+    @property
+    def dt(self) -> float:
+        return _lib3a().orc3a_dt(self._h)
+
+    def velocity(self):
+        v = np.zeros(self.N)
+        _lib3a().orc3a_velocity(self._h, _p(v))
+        return v
+
+    def leaves(self):
+        n = self.nleaf
+        out = {"lvl": np.zeros(n, np.int32), "ijk": np.zeros((n, 3), np.int32),
+               "type": np.zeros(n, np.int32), "master": np.zeros(n, np.int32),
+               "vbar": np.zeros(n), "vcv": np.zeros(n), "sw": np.zeros(n), "S": np.zeros((n, 6))}
+        _lib3a().orc3a_leaves(self._h, *[_p(out[k]) for k in
+                                         ("lvl", "ijk", "type", "master", "vbar", "vcv", "sw", "S")])
+        return out
+
+    def faces(self):
+        out = {"ptr": np.zeros(self.nleaf + 1, np.int32), "nb": np.zeros(self.nface, np.int32),
+               "dir": np.zeros(self.nface, np.int32), "area": np.zeros(self.nface)}
+        _lib3a().orc3a_faces(self._h, *[_p(out[k]) for k in ("ptr", "nb", "dir", "area")])
+        return out
+
+    def init(self):
+        F = np.zeros((self.nleaf, self.nvel))
+        _lib3a().orc3a_init(self._h, _p(F))
+        return F
+
+    def merge(self, F):
+        F = np.ascontiguousarray(F, dtype=np.float64).copy()
+        _lib3a().orc3a_merge(self._h, _p(F))
+        return F
+
+    def step(self, F):
+        """One step; returns (F1, diag) with diag = (Fx, Fy, Fz, mass) of F^n."""
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        Fo = np.zeros_like(F)
+        d = np.zeros(4)
+        st = _lib3a().orc3a_step(self._h, _p(F), _p(Fo), _p(d))
+        if st != 0:
+            raise OracleError(f"oracle step failed with status {st}")
+        return Fo, d
+
+    def run(self, F, nsteps):
+        diags = []
+        for _ in range(nsteps):
+            F, d = self.step(F)
+            diags.append(d)
+        return F, np.array(diags).reshape(-1, 4)

@@ -683,3 +683,429 @@ void orc3d_moments(const orc3d *o, const double *F, double *out) {
 }
 
 void orc3d_velocity(const orc3d *o, double *v) { memcpy(v, o->v, o->N * sizeof(double)); }
+
+/* ================================================================== */
+/* Octree mesh (Section 5, octree procedure) around a fixed body        */
+/* ================================================================== */
+/* The coarse n[0] x n[1] x n[2] grid is refined near the boundary: a cell
+   of depth d is divided in 8 when its centre is closer to the boundary than
+   band * Delta x / 2^d and d < amr_depth.  READINGS: the distance is the
+   absolute value of the level set at the centre; Delta x is the largest
+   coarse spacing; "d <= d_max" is read as "a cell of depth d < d_max is
+   divided", so the finest depth is d_max (the paper's 50^3 coarse grid with
+   d_max = 2 then has the resolution of a 200^3 grid near the vanes); band =
+   2 sqrt 2 unless amr_band > 0.  The data structure: leaves in Z-order of
+   their lower corner (in finest-level units), and per leaf a list of faces
+   in the order x-, x+, y-, y+, z-, z+: the leaf across (same depth, one
+   coarser, or the four of the next finer depth) or the farfield (-1), with
+   the face's gas area.  Cut cells lie at the finest depth (the band is
+   wider than a cell's half-diagonal) and have the uniform grid's geometry
+   there; their control volumes follow the same master search, restricted to
+   leaves of the finest depth. */
+struct orc3a {
+  orc_cfg cfg;
+  orc3d vel;                      /* velocity grid, model and dt (helpers shared with orc3d) */
+  int n0[3], dmax, nleaf, nface;
+  double hf[3];                   /* finest spacing */
+  int *lvl, *ijk;                 /* depth and integer coordinates at that depth (3 per leaf) */
+  int *type, *master, *mptr, *midx;
+  int *fptr, *fnb, *fdir;
+  double *farea;
+  double *S6;                     /* 6 gas face areas per leaf */
+  double *vsum;                   /* sum of the 8 vertex values (centre test) */
+  double *sw, *nw3, *rw3, *vbar, *vcv;
+};
+
+typedef unsigned long long u64;
+typedef struct { u64 key; int idx; } keyidx3;
+
+static u64 cell_key3(int l, int i, int j, int k) {
+  return ((u64)l << 60) | ((u64)i << 40) | ((u64)j << 20) | (u64)k;
+}
+
+static u64 spread3(u64 x) {
+  u64 r = 0;
+  for (int b = 0; b < 21; ++b) r |= ((x >> b) & 1ULL) << (3 * b);
+  return r;
+}
+
+static int cmp_keyidx3(const void *a, const void *b) {
+  u64 x = ((const keyidx3 *)a)->key, y = ((const keyidx3 *)b)->key;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* leaf with this (depth, coordinates), or -1 */
+static int find_leaf3(const keyidx3 *tab, int n, int l, int i, int j, int k) {
+  if (l < 0 || i < 0 || j < 0 || k < 0) return -1;
+  u64 key = cell_key3(l, i, j, k);
+  int lo = 0, hi = n - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) / 2;
+    if (tab[mid].key == key) return tab[mid].idx;
+    if (tab[mid].key < key) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+void orc3a_destroy(orc3a *o);
+
+static int build3a(orc3a *o) {
+  const orc_cfg *cf = &o->cfg;
+  int D = o->dmax;
+  double h0[3];
+  for (int d = 0; d < 3; ++d) h0[d] = (cf->hi[d] - cf->lo[d]) / o->n0[d];
+  double Dx = mx(h0[0], mx(h0[1], h0[2]));
+  double band = cf->amr_band > 0.0 ? cf->amr_band : 2.0 * sqrt(2.0);
+  /* refinement by the criterion, depth first */
+  int cap = 1 << 16, nl = 0, sp = 0, scap = 1 << 12;
+  int *leaf = malloc((size_t)cap * 4 * sizeof(int));
+  int *st = malloc((size_t)scap * 4 * sizeof(int));
+  for (int k = o->n0[2] - 1; k >= 0; --k)
+    for (int j = o->n0[1] - 1; j >= 0; --j)
+      for (int i = o->n0[0] - 1; i >= 0; --i) {
+        if (sp == scap) { scap *= 2; st = realloc(st, (size_t)scap * 4 * sizeof(int)); }
+        st[4 * sp] = 0; st[4 * sp + 1] = i; st[4 * sp + 2] = j; st[4 * sp + 3] = k; ++sp;
+      }
+  while (sp > 0) {
+    --sp;
+    int l = st[4 * sp], i = st[4 * sp + 1], j = st[4 * sp + 2], k = st[4 * sp + 3];
+    double s = 1.0 / (double)(1 << l);
+    double cx = cf->lo[0] + (i + 0.5) * h0[0] * s, cy = cf->lo[1] + (j + 0.5) * h0[1] * s,
+           cz = cf->lo[2] + (k + 0.5) * h0[2] * s;
+    if (l < D && fabs(levelset3(cf, cx, cy, cz)) < band * Dx * s) {
+      for (int t = 7; t >= 0; --t) {
+        if (sp == scap) { scap *= 2; st = realloc(st, (size_t)scap * 4 * sizeof(int)); }
+        st[4 * sp] = l + 1;
+        st[4 * sp + 1] = 2 * i + (t & 1); st[4 * sp + 2] = 2 * j + ((t >> 1) & 1);
+        st[4 * sp + 3] = 2 * k + ((t >> 2) & 1);
+        ++sp;
+      }
+    } else {
+      if (nl == cap) { cap *= 2; leaf = realloc(leaf, (size_t)cap * 4 * sizeof(int)); }
+      memcpy(leaf + 4 * nl, st + 4 * sp, 4 * sizeof(int));
+      ++nl;
+    }
+  }
+  free(st);
+  /* Z-order of the lower corner in finest units */
+  keyidx3 *mz = malloc((size_t)nl * sizeof(keyidx3));
+  for (int q = 0; q < nl; ++q) {
+    int l = leaf[4 * q], sh = D - l;
+    u64 I = (u64)leaf[4 * q + 1] << sh, J = (u64)leaf[4 * q + 2] << sh, K = (u64)leaf[4 * q + 3] << sh;
+    mz[q].key = spread3(I) | (spread3(J) << 1) | (spread3(K) << 2);
+    mz[q].idx = q;
+  }
+  qsort(mz, nl, sizeof(keyidx3), cmp_keyidx3);
+  int n = o->nleaf = nl;
+  o->lvl = malloc(n * sizeof(int)); o->ijk = malloc((size_t)n * 3 * sizeof(int));
+  for (int q = 0; q < n; ++q) {
+    const int *c = leaf + 4 * mz[q].idx;
+    o->lvl[q] = c[0];
+    o->ijk[3 * q] = c[1]; o->ijk[3 * q + 1] = c[2]; o->ijk[3 * q + 2] = c[3];
+  }
+  free(mz); free(leaf);
+  keyidx3 *tab = malloc((size_t)n * sizeof(keyidx3));
+  for (int q = 0; q < n; ++q) {
+    tab[q].key = cell_key3(o->lvl[q], o->ijk[3 * q], o->ijk[3 * q + 1], o->ijk[3 * q + 2]);
+    tab[q].idx = q;
+  }
+  qsort(tab, n, sizeof(keyidx3), cmp_keyidx3);
+  /* geometry: vertex values (clamped as on the uniform grid) and the
+     uniform grid's per-cell construction at the leaf's own size */
+  o->type = calloc(n, sizeof(int)); o->master = calloc(n, sizeof(int));
+  o->mptr = calloc(n + 1, sizeof(int)); o->midx = calloc(n, sizeof(int));
+  o->S6 = calloc((size_t)n * 6, sizeof(double)); o->vsum = calloc(n, sizeof(double));
+  o->sw = calloc(n, sizeof(double)); o->nw3 = calloc((size_t)n * 3, sizeof(double));
+  o->rw3 = calloc((size_t)n * 3, sizeof(double));
+  o->vbar = calloc(n, sizeof(double)); o->vcv = calloc(n, sizeof(double));
+  double eps = 1e-10 * o->hf[0];
+  int bad = 0;
+  for (int q = 0; q < n; ++q) {
+    int l = o->lvl[q], sh = D - l;
+    int A0[3] = {o->ijk[3 * q] << sh, o->ijk[3 * q + 1] << sh, o->ijk[3 * q + 2] << sh};
+    double q8[8], h[3];
+    for (int d = 0; d < 3; ++d) h[d] = o->hf[d] * (double)(1 << sh);
+    for (int t = 0; t < 8; ++t) {
+      int a = A0[0] + ((t & 1) << sh), b = A0[1] + (((t >> 1) & 1) << sh), c = A0[2] + (((t >> 2) & 1) << sh);
+      double p = levelset3(cf, cf->lo[0] + a * o->hf[0], cf->lo[1] + b * o->hf[1], cf->lo[2] + c * o->hf[2]);
+      double sg = p >= 0.0 ? 1.0 : -1.0;
+      q8[t] = sg * mx(fabs(p), eps);
+    }
+    double vs = 0.0;
+    for (int t = 0; t < 8; ++t) vs += q8[t];
+    o->vsum[q] = vs;
+    double rl[3];
+    int type;
+    if (cell_geom3(q8, h, &type, o->S6 + 6 * q, &o->sw[q], o->nw3 + 3 * q, rl, &o->vbar[q])) bad = 1;
+    if (type == CUT && l < D) bad = 1;     /* a cut cell above the finest depth */
+    o->type[q] = type;
+    if (o->sw[q] > 0.0)
+      for (int d = 0; d < 3; ++d) o->rw3[3 * q + d] = cf->lo[d] + A0[d] * o->hf[d] + rl[d];
+  }
+  /* faces */
+  int fcap = 8 * n + 16;
+  o->fptr = calloc(n + 1, sizeof(int));
+  o->fnb = malloc((size_t)fcap * sizeof(int)); o->fdir = malloc((size_t)fcap * sizeof(int));
+  o->farea = malloc((size_t)fcap * sizeof(double));
+  int nf = 0;
+#define ADDF(nb_, t_, a_) do { if (nf == fcap) { fcap *= 2; \
+    o->fnb = realloc(o->fnb, (size_t)fcap * sizeof(int)); o->fdir = realloc(o->fdir, (size_t)fcap * sizeof(int)); \
+    o->farea = realloc(o->farea, (size_t)fcap * sizeof(double)); } \
+    o->fnb[nf] = (nb_); o->fdir[nf] = (t_); o->farea[nf] = (a_); ++nf; } while (0)
+  for (int q = 0; q < n; ++q) {
+    o->fptr[q] = nf;
+    if (o->type[q] == SOLID) continue;
+    int l = o->lvl[q];
+    for (int t = 0; t < 6; ++t) {
+      double A = o->S6[6 * q + t];
+      if (A == 0.0) continue;
+      int d = t >> 1, sd = t & 1, d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+      int g[3] = {o->ijk[3 * q], o->ijk[3 * q + 1], o->ijk[3 * q + 2]};
+      g[d] += sd ? 1 : -1;
+      if (g[d] < 0 || g[d] >= (o->n0[d] << l)) { ADDF(-1, t, A); continue; }
+      int x = find_leaf3(tab, n, l, g[0], g[1], g[2]);
+      if (x < 0) x = find_leaf3(tab, n, l - 1, g[0] >> 1, g[1] >> 1, g[2] >> 1);
+      if (x >= 0) { ADDF(x, t, A); continue; }
+      if (l == D) { bad = 1; continue; }
+      for (int b2 = 0; b2 < 2; ++b2)
+        for (int b1 = 0; b1 < 2; ++b1) {
+          int c[3];
+          c[d] = 2 * g[d] + (sd ? 0 : 1); c[d1] = 2 * g[d1] + b1; c[d2] = 2 * g[d2] + b2;
+          int y = find_leaf3(tab, n, l + 1, c[0], c[1], c[2]);
+          if (y < 0) { bad = 1; continue; }          /* more than one depth apart */
+          double Ay = o->S6[6 * y + (t ^ 1)];         /* the finer leaf's face toward this one */
+          if (Ay != 0.0) ADDF(y, t, Ay);
+        }
+    }
+  }
+  o->fptr[n] = nf;
+  o->nface = nf;
+#undef ADDF
+  /* masters (finest depth): centre in gas = mean of the 8 vertex values
+     > 1e-12 dx; hop across the largest face shared with a leaf of the same
+     depth, order x+, x-, y+, y-, z+, z- */
+  double thr = 1e-12 * o->hf[0];
+  const int order[6] = {1, 0, 3, 2, 5, 4};
+  for (int q = 0; q < n; ++q) {
+    if (o->type[q] == SOLID) { o->master[q] = -1; continue; }
+    int cur = q, hops = 0, seen[5];
+    seen[0] = q;
+    for (;;) {
+      if (o->vsum[cur] / 8.0 > thr) break;
+      int l = o->lvl[cur], nb6[6];
+      double L[6];
+      for (int u = 0; u < 6; ++u) {
+        int t = order[u], d = t >> 1;
+        int g[3] = {o->ijk[3 * cur], o->ijk[3 * cur + 1], o->ijk[3 * cur + 2]};
+        g[d] += (t & 1) ? 1 : -1;
+        nb6[u] = -1;
+        L[u] = 0.0;
+        if (g[d] < 0 || g[d] >= (o->n0[d] << l)) continue;
+        nb6[u] = find_leaf3(tab, n, l, g[0], g[1], g[2]);
+        L[u] = o->S6[6 * cur + t];
+      }
+      double M = 0.0;
+      for (int u = 0; u < 6; ++u) M = mx(M, L[u]);
+      if (!(M > 0.0) || hops == 4) { bad = 1; break; }
+      double tie = M * (1.0 - 1e-12);
+      int u = 0;
+      while (L[u] < tie) ++u;
+      if (nb6[u] < 0) { bad = 1; break; }       /* across a change of depth */
+      cur = nb6[u];
+      ++hops;
+      for (int hh = 0; hh < hops; ++hh) if (seen[hh] == cur) bad = 1;
+      if (bad) break;
+      seen[hops] = cur;
+    }
+    o->master[q] = cur;
+  }
+  free(tab);
+  if (bad) return -3;
+  memset(o->mptr, 0, (n + 1) * sizeof(int));
+  for (int c = 0; c < n; ++c) if (o->master[c] >= 0) o->mptr[o->master[c] + 1]++;
+  for (int c = 0; c < n; ++c) o->mptr[c + 1] += o->mptr[c];
+  int *fill = calloc(n, sizeof(int));
+  for (int c = 0; c < n; ++c) {
+    int m = o->master[c];
+    if (m >= 0) o->midx[o->mptr[m] + fill[m]++] = c;
+  }
+  free(fill);
+  for (int c = 0; c < n; ++c) {
+    o->vcv[c] = 0.0;
+    for (int q = o->mptr[c]; q < o->mptr[c + 1]; ++q) o->vcv[c] += o->vbar[o->midx[q]];
+  }
+  for (int c = 0; c < n; ++c) {
+    int m = o->master[c];
+    if (m >= 0 && o->master[m] != m) return -3;
+  }
+  return 0;
+}
+
+int orc3a_create(const orc_cfg *cfg, orc3a **out) {
+  if (!cfg || cfg->dim != 3 || cfg->n[0] < 1 || cfg->n[1] < 1 || cfg->n[2] < 1 || cfg->nv < 1 ||
+      !(cfg->vmax > cfg->vmin) || cfg->amr_depth < 0 || cfg->amr_depth > 8)
+    return -1;
+  for (int d = 0; d < 3; ++d)
+    if (((u64)cfg->n[d] << cfg->amr_depth) >= (1ULL << 20)) return -1;
+  orc3a *o = calloc(1, sizeof(orc3a));
+  o->cfg = *cfg;
+  o->dmax = cfg->amr_depth;
+  for (int d = 0; d < 3; ++d) {
+    o->n0[d] = cfg->n[d];
+    o->hf[d] = (cfg->hi[d] - cfg->lo[d]) / (double)(cfg->n[d] << o->dmax);
+  }
+  /* velocity grid, model and time step: the finest spacing sets dt */
+  orc3d *v = &o->vel;
+  v->cfg = *cfg;
+  v->N = cfg->nv; v->nvel = v->N * v->N * v->N;
+  v->dx = o->hf[0]; v->dy = o->hf[1]; v->dz = o->hf[2];
+  v->dv = (cfg->vmax - cfg->vmin) / v->N;
+  v->w = v->dv * v->dv * v->dv;
+  v->v = malloc(v->N * sizeof(double));
+  for (int p = 0; p < v->N; ++p) v->v[p] = cfg->vmin + (p + 0.5) * v->dv;
+  double vm = 0.0;
+  for (int p = 0; p < v->N; ++p) vm = mx(vm, fabs(v->v[p]));
+  v->dt = cfg->dt > 0.0 ? cfg->dt : cfg->cfl / (vm / v->dx + vm / v->dy + vm / v->dz);
+  int st = build3a(o);
+  if (st) { orc3a_destroy(o); return st; }
+  *out = o;
+  return 0;
+}
+
+void orc3a_destroy(orc3a *o) {
+  if (!o) return;
+  free(o->vel.v);
+  free(o->lvl); free(o->ijk); free(o->type); free(o->master); free(o->mptr); free(o->midx);
+  free(o->fptr); free(o->fnb); free(o->fdir); free(o->farea); free(o->S6); free(o->vsum);
+  free(o->sw); free(o->nw3); free(o->rw3); free(o->vbar); free(o->vcv);
+  free(o);
+}
+
+double orc3a_dt(const orc3a *o) { return o->vel.dt; }
+int orc3a_nleaf(const orc3a *o) { return o->nleaf; }
+int orc3a_nface(const orc3a *o) { return o->nface; }
+void orc3a_velocity(const orc3a *o, double *v) { memcpy(v, o->vel.v, o->vel.N * sizeof(double)); }
+
+void orc3a_leaves(const orc3a *o, int *lvl, int *ijk, int *type, int *master, double *vbar,
+                  double *vcv, double *sw, double *S6) {
+  int n = o->nleaf;
+  memcpy(lvl, o->lvl, n * sizeof(int));
+  memcpy(ijk, o->ijk, (size_t)n * 3 * sizeof(int));
+  memcpy(type, o->type, n * sizeof(int));
+  memcpy(master, o->master, n * sizeof(int));
+  memcpy(vbar, o->vbar, n * sizeof(double));
+  memcpy(vcv, o->vcv, n * sizeof(double));
+  memcpy(sw, o->sw, n * sizeof(double));
+  memcpy(S6, o->S6, (size_t)n * 6 * sizeof(double));
+}
+
+void orc3a_faces(const orc3a *o, int *fptr, int *fnb, int *fdir, double *farea) {
+  memcpy(fptr, o->fptr, (o->nleaf + 1) * sizeof(int));
+  memcpy(fnb, o->fnb, o->nface * sizeof(int));
+  memcpy(fdir, o->fdir, o->nface * sizeof(int));
+  memcpy(farea, o->farea, o->nface * sizeof(double));
+}
+
+void orc3a_init(const orc3a *o, double *F) {
+  const double *in = o->cfg.inflow;
+  double u[3] = {in[1], in[2], in[3]};
+  const orc3d *v = &o->vel;
+  int N = v->N, nvel = v->nvel;
+  for (int c = 0; c < o->nleaf; ++c)
+    for (int p = 0; p < nvel; ++p) {
+      double M = maxw3(in[0], u, in[4], v->v[p % N], v->v[(p / N) % N], v->v[p / (N * N)]);
+      F[(size_t)c * nvel + p] = o->type[c] == SOLID ? 0.0 : M;
+    }
+}
+
+static void merge3a(const orc3a *o, double *F) {
+  int nvel = o->vel.nvel;
+  double *acc = malloc(nvel * sizeof(double));
+  for (int m = 0; m < o->nleaf; ++m) {
+    if (o->master[m] != m || o->mptr[m + 1] - o->mptr[m] <= 1) continue;
+    for (int p = 0; p < nvel; ++p) acc[p] = 0.0;
+    for (int q = o->mptr[m]; q < o->mptr[m + 1]; ++q) {
+      int c = o->midx[q];
+      for (int p = 0; p < nvel; ++p) acc[p] += o->vbar[c] * F[(size_t)c * nvel + p];
+    }
+    for (int q = o->mptr[m]; q < o->mptr[m + 1]; ++q) {
+      int c = o->midx[q];
+      for (int p = 0; p < nvel; ++p) F[(size_t)c * nvel + p] = acc[p] / o->vcv[m];
+    }
+  }
+  free(acc);
+}
+
+void orc3a_merge(const orc3a *o, double *F) { merge3a(o, F); }
+
+/* eq. (eq-schema3D) for the control volume of master m: the fluxes of its
+   members' face lists and wall faces, then the update of the uniform grid */
+static void scheme3a(const orc3a *o, const double *Fm, int m, double *out) {
+  const orc3d *v = &o->vel;
+  int nvel = v->nvel, N = v->N;
+  const double *fc = Fm + (size_t)m * nvel;
+  const double *in = o->cfg.inflow;
+  double uin[3] = {in[1], in[2], in[3]};
+  double *R = calloc(nvel, sizeof(double));
+  double *fw = malloc(nvel * sizeof(double));
+  for (int q = o->mptr[m]; q < o->mptr[m + 1]; ++q) {
+    int k = o->midx[q];
+    const double *fk = Fm + (size_t)k * nvel;
+    int has_wall = o->sw[k] > 0.0;
+    if (has_wall) wall_values3(v, fc, o->nw3 + 3 * k, fw);
+    for (int p = 0; p < nvel; ++p) {
+      double vv[3] = {v->v[p % N], v->v[(p / N) % N], v->v[p / (N * N)]};
+      double r = 0.0;
+      for (int e = o->fptr[k]; e < o->fptr[k + 1]; ++e) {
+        double A = o->farea[e];
+        int f = o->fdir[e];
+        /* outward normal velocity of the face */
+        double c = (f & 1) ? vv[f / 2] : -vv[f / 2];
+        double fn = o->fnb[e] >= 0 ? Fm[(size_t)o->fnb[e] * nvel + p]
+                                   : maxw3(in[0], uin, in[4], vv[0], vv[1], vv[2]);
+        r += A * (mx(c, 0.0) * fk[p] + mn(c, 0.0) * fn);
+      }
+      if (has_wall) {
+        const double *nk = o->nw3 + 3 * k;
+        double cn = vv[0] * nk[0] + vv[1] * nk[1] + vv[2] * nk[2];
+        r += o->sw[k] * (mn(cn, 0.0) * fw[p] + mx(cn, 0.0) * fk[p]);
+      }
+      R[p] += r;
+    }
+  }
+  relax_update3(v, fc, R, o->vcv[m], out);
+  free(R); free(fw);
+}
+
+/* one step on the octree; diag (nullable) = Fx, Fy, Fz, mass of F^n */
+int orc3a_step(orc3a *o, const double *F, double *Fo, double *diag) {
+  int nvel = o->vel.nvel, n = o->nleaf;
+  size_t tot = (size_t)n * nvel;
+  double *Fm = malloc(tot * sizeof(double));
+  memcpy(Fm, F, tot * sizeof(double));
+  merge3a(o, Fm);
+  if (diag) {
+    double Fw[3] = {0, 0, 0}, mass = 0.0;
+    for (int k = 0; k < n; ++k)
+      if (o->sw[k] > 0.0) wall_force3(&o->vel, Fm + (size_t)o->master[k] * nvel, o->nw3 + 3 * k, o->sw[k], Fw);
+    for (int m = 0; m < n; ++m) {
+      if (o->master[m] != m) continue;
+      double sm = 0.0;
+      for (int p = 0; p < nvel; ++p) sm += Fm[(size_t)m * nvel + p] * o->vel.w;
+      mass += o->vcv[m] * sm;
+    }
+    diag[0] = Fw[0]; diag[1] = Fw[1]; diag[2] = Fw[2]; diag[3] = mass;
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int m = 0; m < n; ++m) {
+    if (o->master[m] != m) continue;
+    scheme3a(o, Fm, m, Fo + (size_t)m * nvel);
+  }
+  for (int c = 0; c < n; ++c) {
+    int m = o->master[c];
+    if (m < 0) memset(Fo + (size_t)c * nvel, 0, nvel * sizeof(double));
+    else if (m != c) memcpy(Fo + (size_t)c * nvel, Fo + (size_t)m * nvel, nvel * sizeof(double));
+  }
+  free(Fm);
+  return 0;
+}
