@@ -136,10 +136,16 @@ def workload(name: str, kn: float | None = None) -> Config:
                       inflow=_inflow(0.5),
                       body=Body("sphere", (0.5, 0.25, 0.25), (0.1, 0.1, 0.1)),
                       steps=500, name=name)
+    if name == "sphere_amr":   # 3D octree: 32x16x16 coarse, depth 2 (1/128 near the sphere), 16^3 velocities
+        return Config(dim=3, n=(32, 16, 16), lo=(0.0, 0.0, 0.0),
+                      hi=(1.0, 0.5, 0.5), nv=16, kn=0.1 if kn is None else kn,
+                      inflow=_inflow(0.5),
+                      body=Body("sphere", (0.5, 0.25, 0.25), (0.1, 0.1, 0.1)),
+                      steps=500, name=name, amr_depth=2)
     raise KeyError(name)
 
 
-WORKLOADS = ("cyl32", "cyl512", "ellipse256", "sphere128")
+WORKLOADS = ("cyl32", "cyl512", "ellipse256", "sphere128", "sphere_amr")
 
 BATCH_SEED = 20150316
 

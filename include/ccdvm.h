@@ -111,6 +111,9 @@ typedef struct {
                              no adjoint or batch) */
   int model;              /* CC_MODEL_BGK or CC_MODEL_SHAKHOV (no adjoint or batch) */
   double prandtl;         /* Shakhov: Prandtl number, finite and > 0 */
+  int amr_depth;          /* 3D octree mesh (Section 5): finest depth below the
+                             coarse grid n; 0 = uniform grid; at most 8 */
+  double amr_band;        /* refinement band in coarse spacings (<= 0: 2 sqrt 2) */
 } cc_config;
 
 /* Obstacle given by an analytic signed distance, gas side positive
@@ -215,6 +218,33 @@ cc_status cc_geometry_export3d(cc_ctx* ctx, int* type, int* master, double* sxm,
  * are cut cells or own merged cells) and of non-master non-solid cells. */
 cc_status cc_geometry_counts(cc_ctx* ctx, int* n_irregular, int* n_members,
                              int* n_solid);
+
+/* Octree mesh (3D, amr_depth > 0; Section 5, octree procedure).  The
+ * coarse grid n is refined near the boundary: a cell of depth d is divided
+ * in 8 while the distance from its centre to the boundary is below
+ * amr_band * dx / 2^d (dx = largest coarse spacing) and d < amr_depth.  The
+ * mesh is built on the host by cc_create (CC_EGEOM if a cut cell lies above
+ * the finest depth, neighbours differ by more than one depth, or the master
+ * search fails) and uploaded by cc_bind.  The cells of every other call are
+ * then the leaves, in Z-order of their lower corner: the state is
+ * F[leaf][p]; cc_moments, cc_geometry_counts and the diag rows of cc_step
+ * (force and mass of the state entering each step) work as on a uniform
+ * grid; cc_body_force and cc_geometry_export3d are not available.  The
+ * octree runs the explicit BGK scheme with the direct equilibrium; dt comes
+ * from the finest spacing.
+ * cc_amr_counts: leaves and face-list entries.
+ * cc_amr_export (host arrays, each nullable): per leaf its depth, its
+ * integer coordinates at that depth (3), type (0 gas, 1 cut, 2 solid),
+ * master leaf (-1 solid), gas volume, control-volume volume, wall area and
+ * the gas areas of its six faces (x-, x+, y-, y+, z-, z+).
+ * cc_amr_faces (host arrays): fptr (nleaf + 1) into the face entries, the
+ * leaf across each face (-1: farfield), its direction 0..5 and gas area
+ * (across a change of depth the finer leaf's face).
+ * All three return CC_EINVAL on a uniform grid. */
+cc_status cc_amr_counts(cc_ctx* ctx, int* nleaf, int* nface);
+cc_status cc_amr_export(cc_ctx* ctx, int* lvl, int* ijk, int* type, int* master, double* vbar,
+                        double* vcv, double* aw, double* S6);
+cc_status cc_amr_faces(cc_ctx* ctx, int* fptr, int* fnb, int* fdir, double* farea);
 
 /* Rows of cells per tile of the regular-cell pass (each tile is 4 adjacent
  * columns; one wave per column marches up the rows).  0 = automatic.

@@ -25,7 +25,7 @@ class cc_config(C.Structure):
                 ("vmax", C.c_double), ("kn", C.c_double), ("lref", C.c_double),
                 ("cfl", C.c_double), ("dt", C.c_double), ("inflow", C.c_double * 5),
                 ("maxwellian", C.c_int), ("scheme", C.c_int), ("model", C.c_int),
-                ("prandtl", C.c_double)]
+                ("prandtl", C.c_double), ("amr_depth", C.c_int), ("amr_band", C.c_double)]
 
 
 class cc_body(C.Structure):
@@ -55,6 +55,9 @@ SYMBOLS = {
     "cc_geometry_export": (C.c_int, [C.c_void_p] + [C.c_void_p] * 13),
     "cc_geometry_export3d": (C.c_int, [C.c_void_p] + [C.c_void_p] * 17),
     "cc_geometry_counts": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int)] * 3),
+    "cc_amr_counts": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int)] * 2),
+    "cc_amr_export": (C.c_int, [C.c_void_p] * 9),
+    "cc_amr_faces": (C.c_int, [C.c_void_p] * 5),
     "cc_set_tile_rows": (C.c_int, [C.c_void_p, C.c_int]),
     "cc_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "cc_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
@@ -103,6 +106,8 @@ def make_config(cfg) -> cc_config:
     c.scheme = {"explicit": 0, "imex": 1}[getattr(cfg, "scheme", "explicit")]
     c.model = {"bgk": 0, "shakhov": 1}[getattr(cfg, "model", "bgk")]
     c.prandtl = getattr(cfg, "prandtl", 2.0 / 3.0)
+    c.amr_depth = getattr(cfg, "amr_depth", 0)
+    c.amr_band = getattr(cfg, "amr_band", 0.0)
     return c
 
 

@@ -106,6 +106,21 @@ void layout_geo3d(cc_ctx* ctx, char* base, size_t* bytes) {
   *bytes = cv.off;
 }
 
+void layout_amr(cc_ctx* ctx, char* base, size_t* bytes) {
+  Carver cv{base};
+  const AmrHost& H = *ctx->amrh;
+  AmrDev& G = ctx->a3;
+  const size_t n = H.nleaf, nf = H.nface, ncv = H.cv.size();
+  G.nleaf = (int)n; G.ncv = (int)ncv;
+  G.type = cv.take<int>(n); G.master = cv.take<int>(n);
+  G.cv = cv.take<int>(ncv); G.cvptr = cv.take<int>(ncv + 1); G.cvmem = cv.take<int>(H.cvmem.size());
+  G.fptr = cv.take<int>(n + 1); G.fnb = cv.take<int>(nf); G.fdir = cv.take<int>(nf);
+  G.farea = cv.take<double>(nf); G.aw = cv.take<double>(n); G.nw = cv.take<double>(3 * n);
+  G.vbar = cv.take<double>(n); G.vcv = cv.take<double>(n);
+  G.ghost = cv.take<double>(ctx->nvel);
+  *bytes = cv.off;
+}
+
 void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
   Carver cv{base};
   size_t n = ctx->ncell;
@@ -223,6 +238,14 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
     return reject("the Shakhov model needs a finite Prandtl number > 0");
   if (c.scheme == CC_SCHEME_IMEX && body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_NONE)
     return reject("the semi-implicit scheme is available for fixed bodies");
+  if (c.amr_depth < 0 || c.amr_depth > 8) return reject("amr_depth must be in [0, 8]");
+  if (c.amr_depth > 0) {
+    if (c.dim != 3) return reject("the octree mesh is 3D");
+    for (int d = 0; d < 3; ++d)
+      if (((long long)c.n[d] << c.amr_depth) >= (1LL << 20)) return reject("octree too deep for the coarse grid");
+    if (c.model != CC_MODEL_BGK || c.maxwellian != CC_MAXW_DIRECT || c.scheme != CC_SCHEME_EXPLICIT)
+      return reject("the octree mesh runs the explicit BGK scheme with the direct equilibrium");
+  }
   ctx->dim = c.dim;
   ctx->nx = c.n[0]; ctx->ny = c.n[1]; ctx->nz = c.dim == 3 ? c.n[2] : 1;
   long long ncell = (long long)ctx->nx * ctx->ny * ctx->nz;
@@ -238,6 +261,21 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   ctx->dx = (c.hi[0] - c.lo[0]) / ctx->nx;
   ctx->dy = (c.hi[1] - c.lo[1]) / ctx->ny;
   ctx->dz = c.dim == 3 ? (c.hi[2] - c.lo[2]) / ctx->nz : 1.0;
+  if (c.amr_depth > 0) {
+    ctx->amr = true;
+    ctx->amrh = new (std::nothrow) AmrHost();
+    if (!ctx->amrh) { delete ctx; return CC_ENOMEM; }
+    std::string err;
+    if (!build_octree_3d(c, *body, *ctx->amrh, err)) {
+      fprintf(stderr, "ccdvm: %s\n", err.c_str());
+      delete ctx->amrh;
+      delete ctx;
+      return CC_EGEOM;
+    }
+    // the leaves are the cells; the finest spacing sets dt
+    ctx->ncell = ctx->amrh->nleaf;
+    ctx->dx = ctx->amrh->hf[0]; ctx->dy = ctx->amrh->hf[1]; ctx->dz = ctx->amrh->hf[2];
+  }
   ctx->dv = (c.vmax - c.vmin) / c.nv;
   double vm = 0.0;
   for (int p = 0; p < c.nv; ++p) vm = fmax(vm, fabs(c.vmin + (p + 0.5) * ctx->dv));
@@ -248,6 +286,7 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   size_t per = c.dim == 2 ? 16 : 8;
   ctx->state_bytes = align_up((size_t)ctx->ncell * ctx->nvel * per);
   if (c.dim == 2) layout_geo2d(ctx, nullptr, &ctx->geom_bytes);
+  else if (ctx->amr) layout_amr(ctx, nullptr, &ctx->geom_bytes);
   else layout_geo3d(ctx, nullptr, &ctx->geom_bytes);
   layout_scratch(ctx, nullptr, &ctx->scratch_bytes);
   ctx->body_state[0] = body->center[0];
@@ -268,6 +307,7 @@ void cc_destroy(cc_ctx* ctx) {
     for (hipEvent_t e : ctx->prof.start[k]) hipEventDestroy(e);
     for (hipEvent_t e : ctx->prof.stop[k]) hipEventDestroy(e);
   }
+  delete ctx->amrh;
   delete ctx;
 }
 
@@ -317,6 +357,7 @@ cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scr
   ctx->stream = (hipStream_t)hip_stream;
   size_t b;
   if (ctx->dim == 2) layout_geo2d(ctx, (char*)geom, &b);
+  else if (ctx->amr) layout_amr(ctx, (char*)geom, &b);
   else layout_geo3d(ctx, (char*)geom, &b);
   layout_scratch(ctx, (char*)scratch, &b);
   HIPCHK(ctx, hipMemsetAsync(scratch, 0, ctx->scratch_bytes, ctx->stream), "scratch clear");
@@ -326,6 +367,39 @@ cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scr
   HIPCHK(ctx, hipMemsetAsync(state1, 0, ctx->state_bytes, ctx->stream), "state clear");
   HIPCHK(ctx, hipMemcpyAsync(ctx->s.body, ctx->body_state, 6 * sizeof(double),
                              hipMemcpyHostToDevice, ctx->stream), "body state upload");
+  if (ctx->amr) {
+    const AmrHost& H = *ctx->amrh;
+    AmrDev& G = ctx->a3;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+      return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream) : hipSuccess;
+    };
+    const size_t n = H.nleaf;
+    hipError_t e = hipSuccess;
+    for (hipError_t x : {up(G.type, H.type.data(), n * sizeof(int)), up(G.master, H.master.data(), n * sizeof(int)),
+                         up(G.cv, H.cv.data(), H.cv.size() * sizeof(int)),
+                         up(G.cvptr, H.cvptr.data(), H.cvptr.size() * sizeof(int)),
+                         up(G.cvmem, H.cvmem.data(), H.cvmem.size() * sizeof(int)),
+                         up(G.fptr, H.fptr.data(), H.fptr.size() * sizeof(int)),
+                         up(G.fnb, H.fnb.data(), H.fnb.size() * sizeof(int)),
+                         up(G.fdir, H.fdir.data(), H.fdir.size() * sizeof(int)),
+                         up(G.farea, H.farea.data(), H.farea.size() * sizeof(double)),
+                         up(G.aw, H.aw.data(), n * sizeof(double)), up(G.nw, H.nw.data(), 3 * n * sizeof(double)),
+                         up(G.vbar, H.vbar.data(), n * sizeof(double)), up(G.vcv, H.vcv.data(), n * sizeof(double))})
+      if (x != hipSuccess) e = x;
+    if (e == hipSuccess) e = launch_amr_tables(ctx);
+    if (e != hipSuccess) return hip_fail(ctx, e, "octree upload");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "octree upload");
+    // the generic 3D moment and mass kernels see the leaves through g3
+    ctx->g3 = Geo3D{};
+    ctx->g3.ncell = H.nleaf; ctx->g3.N = ctx->N; ctx->g3.nvel = ctx->nvel;
+    ctx->g3.type = G.type; ctx->g3.master = G.master; ctx->g3.vcv = G.vcv;
+    ctx->n_irr = H.n_irr; ctx->n_members = H.n_members; ctx->n_solid = H.n_solid;
+    ctx->nstep = 0;
+    ctx->bound = true;
+    ctx->merged = false;
+    ctx->mom_valid = false;
+    return CC_OK;
+  }
   hipError_t e = ctx->dim == 2 ? build_geometry_2d(ctx, ctx->g2, ctx->s.body) : build_geometry_3d(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernels");
   if (ctx->dim == 2 && is_moving(ctx)) {
@@ -345,6 +419,18 @@ cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scr
 
 // make the current state ready for a step: moments valid, control volumes merged
 static cc_status prepare(cc_ctx* ctx) {
+  if (ctx->amr) {
+    if (!ctx->merged) {
+      HIPCHK(ctx, launch_amr_merge(ctx), "merge");
+      ctx->merged = true;
+      ctx->mom_valid = false;
+    }
+    if (!ctx->mom_valid) {
+      HIPCHK(ctx, launch_amr_moments(ctx), "moments");
+      ctx->mom_valid = true;
+    }
+    return CC_OK;
+  }
   if (ctx->dim == 3) {
     // 3D moment sums are taken of the merged control-volume values
     if (!ctx->merged) {
@@ -372,7 +458,8 @@ static cc_status prepare(cc_ctx* ctx) {
 cc_status cc_init_maxwellian(cc_ctx* ctx) {
   if (!ctx) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
-  HIPCHK(ctx, ctx->dim == 2 ? launch_init_maxwellian_2d(ctx) : launch_init_maxwellian_3d(ctx), "init");
+  HIPCHK(ctx, ctx->amr ? launch_amr_init(ctx, nullptr)
+                       : (ctx->dim == 2 ? launch_init_maxwellian_2d(ctx) : launch_init_maxwellian_3d(ctx)), "init");
   ctx->mom_valid = false;
   ctx->merged = false;
   return prepare(ctx);
@@ -382,7 +469,8 @@ cc_status cc_load_state(cc_ctx* ctx, const double* f, const double* g) {
   if (!ctx || !f) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   if (ctx->dim == 2 && !g) return fail(ctx, CC_EINVAL, "g is required in 2D");
-  HIPCHK(ctx, ctx->dim == 2 ? launch_load_state_2d(ctx, f, g) : launch_load_state_3d(ctx, f), "load");
+  HIPCHK(ctx, ctx->amr ? launch_amr_init(ctx, f)
+                       : (ctx->dim == 2 ? launch_load_state_2d(ctx, f, g) : launch_load_state_3d(ctx, f)), "load");
   ctx->mom_valid = false;
   ctx->merged = false;
   return prepare(ctx);
@@ -402,6 +490,13 @@ cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
   if (st != CC_OK) return st;
   if (nsteps == 0) return CC_OK;
   bool moving = ctx->body.motion != CC_MOTION_FIXED && ctx->body.kind != CC_BODY_NONE;
+  if (ctx->amr) {
+    for (int n = 0; n < nsteps; ++n) {
+      hipError_t e = launch_amr_step(ctx, diag ? diag + 4 * (size_t)n : nullptr);
+      if (e != hipSuccess) return hip_fail(ctx, e, "step");
+    }
+    return CC_OK;
+  }
   if (ctx->dim == 3) {
     // every step reduces its own force and mass rows
     for (int n = 0; n < nsteps; ++n) {
@@ -465,6 +560,7 @@ cc_status cc_moments(cc_ctx* ctx, double* out) {
 cc_status cc_body_force(cc_ctx* ctx, double out[4]) {
   if (!ctx || !out) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (ctx->amr) return fail(ctx, CC_EINVAL, "on the octree mesh the force comes with the diag rows of cc_step");
   cc_status st = prepare(ctx);
   if (st != CC_OK) return st;
   double* dev = ctx->s.red + 4 * 128 + 4;
@@ -531,7 +627,7 @@ cc_status cc_geometry_export3d(cc_ctx* ctx, int* type, int* master, double* sxm,
                                double* rwz, double* vbar, double* vcv) {
   if (!ctx) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
-  if (ctx->dim != 3) return fail(ctx, CC_EINVAL, "3D only");
+  if (ctx->dim != 3 || ctx->amr) return fail(ctx, CC_EINVAL, "uniform 3D grids only (octree: cc_amr_export)");
   const Geo3D& G = ctx->g3;
   size_t n = ctx->ncell;
   struct { void* dst; const void* src; size_t sz; } cp[] = {
@@ -542,6 +638,42 @@ cc_status cc_geometry_export3d(cc_ctx* ctx, int* type, int* master, double* sxm,
   for (auto& c : cp)
     if (c.dst) HIPCHK(ctx, hipMemcpyAsync(c.dst, c.src, n * c.sz, hipMemcpyDeviceToHost, ctx->stream), "export");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "export sync");
+  return CC_OK;
+}
+
+cc_status cc_amr_counts(cc_ctx* ctx, int* nleaf, int* nface) {
+  if (!ctx) return CC_EINVAL;
+  if (!ctx->amr) return fail(ctx, CC_EINVAL, "not an octree mesh");
+  if (nleaf) *nleaf = ctx->amrh->nleaf;
+  if (nface) *nface = ctx->amrh->nface;
+  return CC_OK;
+}
+
+cc_status cc_amr_export(cc_ctx* ctx, int* lvl, int* ijk, int* type, int* master, double* vbar, double* vcv,
+                        double* aw, double* S6) {
+  if (!ctx) return CC_EINVAL;
+  if (!ctx->amr) return fail(ctx, CC_EINVAL, "not an octree mesh");
+  const AmrHost& H = *ctx->amrh;
+  const size_t n = H.nleaf;
+  if (lvl) memcpy(lvl, H.lvl.data(), n * sizeof(int));
+  if (ijk) memcpy(ijk, H.ijk.data(), 3 * n * sizeof(int));
+  if (type) memcpy(type, H.type.data(), n * sizeof(int));
+  if (master) memcpy(master, H.master.data(), n * sizeof(int));
+  if (vbar) memcpy(vbar, H.vbar.data(), n * sizeof(double));
+  if (vcv) memcpy(vcv, H.vcv.data(), n * sizeof(double));
+  if (aw) memcpy(aw, H.aw.data(), n * sizeof(double));
+  if (S6) memcpy(S6, H.S6.data(), 6 * n * sizeof(double));
+  return CC_OK;
+}
+
+cc_status cc_amr_faces(cc_ctx* ctx, int* fptr, int* fnb, int* fdir, double* farea) {
+  if (!ctx) return CC_EINVAL;
+  if (!ctx->amr) return fail(ctx, CC_EINVAL, "not an octree mesh");
+  const AmrHost& H = *ctx->amrh;
+  if (fptr) memcpy(fptr, H.fptr.data(), H.fptr.size() * sizeof(int));
+  if (fnb) memcpy(fnb, H.fnb.data(), H.fnb.size() * sizeof(int));
+  if (fdir) memcpy(fdir, H.fdir.data(), H.fdir.size() * sizeof(int));
+  if (farea) memcpy(farea, H.farea.data(), H.farea.size() * sizeof(double));
   return CC_OK;
 }
 

@@ -97,6 +97,28 @@ struct Geo3D {
   double* ghost;     // nvel farfield values (F)
 };
 
+// Octree mesh (3D, amr_depth > 0): built on the host when the context is
+// created (octree3d.hip), uploaded to the geometry buffer when it is bound.
+struct AmrHost {
+  int n0[3];
+  double hf[3];                     // finest spacing
+  int nleaf = 0, nface = 0, n_irr = 0, n_members = 0, n_solid = 0;
+  std::vector<int> lvl, ijk, type, flags, master;
+  std::vector<double> S6, aw, nw, rw, vbar, vcv;
+  std::vector<int> fptr, fnb, fdir;  // per leaf, faces x-, x+, y-, y+, z-, z+ (leaf across or -1)
+  std::vector<double> farea;
+  std::vector<int> cv, cvptr, cvmem; // control volumes: master leaf, members (CSR)
+};
+
+struct AmrDev {
+  int nleaf, ncv;
+  int* type; int* master;
+  int* cv; int* cvptr; int* cvmem;
+  int* fptr; int* fnb; int* fdir;
+  double* farea; double* aw; double* nw; double* vbar; double* vcv;
+  double* ghost;                    // nvel farfield values
+};
+
 // Scratch layout (caller's scratch buffer).
 struct Scratch {
   // moving bodies: per-step dispatch and receiving control volumes
@@ -159,6 +181,9 @@ struct cc_ctx {
   ccdvm::Geo2D g2n;         // moving bodies: geometry at the next time level
   long long nstep = 0;      // steps taken since binding
   ccdvm::Geo3D g3;
+  bool amr = false;                 // 3D octree mesh
+  ccdvm::AmrHost* amrh = nullptr;
+  ccdvm::AmrDev a3{};
   ccdvm::Scratch s;
   int n_irr = 0, n_members = 0, n_solid = 0;
   // host mirror of the rigid body (kept in sync with the device copy)
@@ -225,6 +250,14 @@ hipError_t launch_step_3d(cc_ctx* ctx, double* force_row, double* mass_row);
 hipError_t launch_mass_3d(cc_ctx* ctx, double* mass_row);
 hipError_t launch_moments_out_3d(cc_ctx* ctx, double* out);
 int chunks3d(int N);   // velocity chunks of the 3D regular-cell pass (0: unsupported N)
+
+// octree mesh (octree3d.hip)
+bool build_octree_3d(const cc_config& cfg, const cc_body& body, AmrHost& H, std::string& err);
+hipError_t launch_amr_tables(cc_ctx* ctx);
+hipError_t launch_amr_init(cc_ctx* ctx, const double* f);   // f null: farfield Maxwellian
+hipError_t launch_amr_merge(cc_ctx* ctx);
+hipError_t launch_amr_moments(cc_ctx* ctx);
+hipError_t launch_amr_step(cc_ctx* ctx, double* row);
 
 // profiling hooks (capi.cpp)
 void prof_begin(cc_ctx* ctx, int k);

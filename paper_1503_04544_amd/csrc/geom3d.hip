@@ -24,16 +24,10 @@
 
 #pragma clang fp contract(off)
 
+#include "cellgeom3d.h"
+
 namespace ccdvm {
 namespace {
-
-__device__ inline double level_set_3d(const BodyDev& B, double x, double y, double z) {
-  if (B.kind == CC_BODY_SPHERE) {
-    const double a = x - B.cx, b = y - B.cy, c = z - B.cz;
-    return sqrt(a * a + b * b + c * c) - B.a;
-  }
-  return 1.0e300;
-}
 
 __global__ void k_phi3d(Geo3D G, BodyDev B) {
   const long long nvx = G.nx + 1, nvy = G.ny + 1, nvz = G.nz + 1;
@@ -52,110 +46,28 @@ __device__ inline double vtx(const Geo3D& G, int i, int j, int k, int bx, int by
   return G.phi[((long long)(k + bz) * nvy + (j + by)) * nvx + (i + bx)];
 }
 
-// gas polygon of a rectangle [0,h1]x[0,h2] with corner values q (corners in
-// the order (0,0), (h1,0), (h1,h2), (0,h2)): area, number of crossed edges
-__device__ inline double face_area(const double q[4], double h1, double h2, int* ncross) {
-  const double cs[4] = {0.0, h1, h1, 0.0}, ct[4] = {0.0, 0.0, h2, h2};
-  double ps[8], pt[8];
-  int np = 0, nc = 0;
-  for (int e = 0; e < 4; ++e) {
-    const int e1 = (e + 1) & 3;
-    const bool ga = q[e] > 0.0, gb = q[e1] > 0.0;
-    if (ga) { ps[np] = cs[e]; pt[np] = ct[e]; ++np; }
-    if (ga != gb) {
-      const double t = q[e] / (q[e] - q[e1]);
-      ps[np] = cs[e] + t * (cs[e1] - cs[e]);
-      pt[np] = ct[e] + t * (ct[e1] - ct[e]);
-      ++np;
-      ++nc;
-    }
-  }
-  double A = 0.0;
-  for (int k = 0; k < np; ++k) {
-    const int k1 = k + 1 == np ? 0 : k + 1;
-    A += ps[k] * pt[k1] - ps[k1] * pt[k];
-  }
-  *ncross = nc;
-  return 0.5 * A;
-}
-
 __global__ void k_cell3d(Geo3D G) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= G.ncell) return;
   const int i = t % G.nx, j = (t / G.nx) % G.ny, k = t / (G.nx * G.ny);
   double q8[8];
-  double mn = 1e300, mx = -1e300, sum = 0.0;
-  for (int b = 0; b < 8; ++b) {
-    q8[b] = vtx(G, i, j, k, b & 1, (b >> 1) & 1, (b >> 2) & 1);
-    mn = fmin(mn, q8[b]);
-    mx = fmax(mx, q8[b]);
-    sum += q8[b];
-  }
-  const int type = mn > 0.0 ? TYPE_GAS : (mx < 0.0 ? TYPE_SOLID : TYPE_CUT);
+  for (int b = 0; b < 8; ++b) q8[b] = vtx(G, i, j, k, b & 1, (b >> 1) & 1, (b >> 2) & 1);
   const double h[3] = {G.dx, G.dy, G.dz};
-  int flags = sum / 8.0 > 1e-12 * G.dx ? 1 : 0;
-  double S[6], Aw[3] = {0.0, 0.0, 0.0}, V = 0.0;
-  for (int d = 0; d < 3; ++d) {
-    const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-    for (int sd = 0; sd < 2; ++sd) {
-      double q[4];
-      for (int u = 0; u < 4; ++u) {
-        int idx[3];
-        idx[d] = sd;
-        idx[d1] = (u == 1 || u == 2) ? 1 : 0;
-        idx[d2] = u >= 2 ? 1 : 0;
-        q[u] = q8[idx[0] | (idx[1] << 1) | (idx[2] << 2)];
-      }
-      int nc;
-      const double area = face_area(q, h[d1], h[d2], &nc);
-      if (nc == 4) flags |= 2;
-      S[2 * d + sd] = type == TYPE_SOLID ? 0.0 : area;
-      const double sgn = sd ? 1.0 : -1.0;
-      Aw[d] -= sgn * area;
-      V += area * (sd ? h[d] : 0.0) / 3.0;
-    }
+  CellGeo3 c;
+  cell_geometry_3d(q8, h, 1e-12 * G.dx, c);
+  G.type[t] = c.type;
+  G.flags[t] = c.flags;
+  G.sxm[t] = c.S[0]; G.sxp[t] = c.S[1]; G.sym[t] = c.S[2];
+  G.syp[t] = c.S[3]; G.szm[t] = c.S[4]; G.szp[t] = c.S[5];
+  G.aw[t] = c.aw; G.nwx[t] = c.n[0]; G.nwy[t] = c.n[1]; G.nwz[t] = c.n[2];
+  if (c.aw > 0.0) {
+    G.rwx[t] = G.x0 + i * G.dx + c.r[0];
+    G.rwy[t] = G.y0 + j * G.dy + c.r[1];
+    G.rwz[t] = G.z0 + k * G.dz + c.r[2];
+  } else {
+    G.rwx[t] = 0.0; G.rwy[t] = 0.0; G.rwz[t] = 0.0;
   }
-  // mean of the crossings on the 12 edges
-  double rs[3] = {0.0, 0.0, 0.0};
-  int ncx = 0;
-  for (int d = 0; d < 3; ++d) {
-    const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-    for (int u = 0; u < 4; ++u) {
-      int i0[3], i1[3];
-      i0[d] = 0; i1[d] = 1;
-      i0[d1] = i1[d1] = u & 1;
-      i0[d2] = i1[d2] = (u >> 1) & 1;
-      const double qa = q8[i0[0] | (i0[1] << 1) | (i0[2] << 2)];
-      const double qb = q8[i1[0] | (i1[1] << 1) | (i1[2] << 2)];
-      if ((qa > 0.0) != (qb > 0.0)) {
-        const double tt = qa / (qa - qb);
-        double p3[3];
-        p3[d] = tt * h[d];
-        p3[d1] = i0[d1] * h[d1];
-        p3[d2] = i0[d2] * h[d2];
-        rs[0] += p3[0]; rs[1] += p3[1]; rs[2] += p3[2];
-        ++ncx;
-      }
-    }
-  }
-  const double Sw = sqrt(Aw[0] * Aw[0] + Aw[1] * Aw[1] + Aw[2] * Aw[2]);
-  double aw = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0, r0 = 0.0, r1 = 0.0, r2 = 0.0;
-  if (type == TYPE_CUT && ncx > 0 && Sw > 0.0) {
-    const double r[3] = {rs[0] / ncx, rs[1] / ncx, rs[2] / ncx};
-    aw = Sw;
-    n0 = Aw[0] / Sw; n1 = Aw[1] / Sw; n2 = Aw[2] / Sw;
-    V += (r[0] * Aw[0] + r[1] * Aw[1] + r[2] * Aw[2]) / 3.0;
-    r0 = G.x0 + i * G.dx + r[0];
-    r1 = G.y0 + j * G.dy + r[1];
-    r2 = G.z0 + k * G.dz + r[2];
-  }
-  G.type[t] = type;
-  G.flags[t] = flags;
-  G.sxm[t] = S[0]; G.sxp[t] = S[1]; G.sym[t] = S[2];
-  G.syp[t] = S[3]; G.szm[t] = S[4]; G.szp[t] = S[5];
-  G.aw[t] = aw; G.nwx[t] = n0; G.nwy[t] = n1; G.nwz[t] = n2;
-  G.rwx[t] = r0; G.rwy[t] = r1; G.rwz[t] = r2;
-  G.vbar[t] = type == TYPE_SOLID ? 0.0 : (type == TYPE_GAS ? G.dx * G.dy * G.dz : V);
+  G.vbar[t] = c.vbar;
 }
 
 // one hop across the largest face shared with a cell of the domain

@@ -1,0 +1,574 @@
+// Octree mesh around a fixed body in 3D (Section 5, octree procedure) and
+// its explicit step.
+//
+// Mesh (built once, on the host, when the context is created): the coarse
+// grid cfg.n is refined near the boundary; a cell of depth d is divided in 8
+// when the distance from its centre to the boundary (|level set|) is below
+// band * dx / 2^d, dx the largest coarse spacing, and d < amr_depth, so the
+// finest depth is amr_depth.  Leaves are stored in Z-order of their lower
+// corner (finest-level units), which keeps face neighbours close in memory.
+// Each leaf lists its faces in the order x-, x+, y-, y+, z-, z+: the leaf
+// across (same depth, one coarser, or the four of the next finer depth) or
+// the farfield, with the face's gas area (across a change of depth, the
+// finer leaf's face).  Cut cells lie at the finest depth, where the leaves
+// carry the uniform grid's cut-cell geometry (cellgeom3d.h) and master
+// search; depth jumps of more than one, cut cells above the finest depth or
+// a master search across a change of depth reject the mesh.
+//
+// Step (eq. eq-schema3D on the leaves): one wave per control volume reads
+// its value (members hold it), gathers the upwind fluxes of its members'
+// face lists and wall faces, relaxes toward the separable Maxwellian of the
+// moments it stored the step before, writes the new value to every member
+// and sums the moments of that value for the next step.  Velocities are
+// walked in passes of RC per lane so that one face's loads of a pass are
+// independent (memory-level parallelism on the gather).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "ccdvm_impl.h"
+
+#pragma clang fp contract(off)
+
+#include "cellgeom3d.h"
+
+namespace ccdvm {
+
+// ---------------------------------------------------------------------
+// host builder
+// ---------------------------------------------------------------------
+namespace {
+
+uint64_t spread_bits3(uint64_t x) {
+  uint64_t r = 0;
+  for (int b = 0; b < 21; ++b) r |= ((x >> b) & 1ULL) << (3 * b);
+  return r;
+}
+
+uint64_t leaf_key(int l, int i, int j, int k) {
+  return ((uint64_t)l << 60) | ((uint64_t)i << 40) | ((uint64_t)j << 20) | (uint64_t)k;
+}
+
+struct LeafTable {
+  std::vector<std::pair<uint64_t, int>> t;
+  int find(int l, int i, int j, int k) const {
+    if (l < 0 || i < 0 || j < 0 || k < 0) return -1;
+    const uint64_t key = leaf_key(l, i, j, k);
+    auto it = std::lower_bound(t.begin(), t.end(), std::make_pair(key, -1));
+    return it != t.end() && it->first == key ? it->second : -1;
+  }
+};
+
+}  // namespace
+
+bool build_octree_3d(const cc_config& cfg, const cc_body& body, AmrHost& H, std::string& err) {
+  const int D = cfg.amr_depth;
+  BodyDev B{};
+  B.kind = body.kind;
+  B.cx = body.center[0]; B.cy = body.center[1]; B.cz = body.center[2];
+  B.a = body.axes[0];
+  double h0[3];
+  for (int d = 0; d < 3; ++d) {
+    H.n0[d] = cfg.n[d];
+    h0[d] = (cfg.hi[d] - cfg.lo[d]) / cfg.n[d];
+    H.hf[d] = (cfg.hi[d] - cfg.lo[d]) / (double)(cfg.n[d] << D);
+  }
+  const double Dx = std::max(h0[0], std::max(h0[1], h0[2]));
+  const double band = cfg.amr_band > 0.0 ? cfg.amr_band : 2.0 * sqrt(2.0);
+  // refinement
+  struct C4 { int l, i, j, k; };
+  std::vector<C4> stack, leaves;
+  for (int k = cfg.n[2] - 1; k >= 0; --k)
+    for (int j = cfg.n[1] - 1; j >= 0; --j)
+      for (int i = cfg.n[0] - 1; i >= 0; --i) stack.push_back({0, i, j, k});
+  while (!stack.empty()) {
+    const C4 c = stack.back();
+    stack.pop_back();
+    const double s = 1.0 / (double)(1 << c.l);
+    const double x = cfg.lo[0] + (c.i + 0.5) * h0[0] * s, y = cfg.lo[1] + (c.j + 0.5) * h0[1] * s,
+                 z = cfg.lo[2] + (c.k + 0.5) * h0[2] * s;
+    if (c.l < D && fabs(level_set_3d(B, x, y, z)) < band * Dx * s) {
+      for (int t = 7; t >= 0; --t)
+        stack.push_back({c.l + 1, 2 * c.i + (t & 1), 2 * c.j + ((t >> 1) & 1), 2 * c.k + ((t >> 2) & 1)});
+    } else {
+      leaves.push_back(c);
+    }
+  }
+  const int n = (int)leaves.size();
+  std::vector<std::pair<uint64_t, int>> order(n);
+  for (int q = 0; q < n; ++q) {
+    const C4& c = leaves[q];
+    const int sh = D - c.l;
+    order[q] = {spread_bits3((uint64_t)c.i << sh) | (spread_bits3((uint64_t)c.j << sh) << 1) |
+                    (spread_bits3((uint64_t)c.k << sh) << 2),
+                q};
+  }
+  std::sort(order.begin(), order.end());
+  H.nleaf = n;
+  H.lvl.resize(n); H.ijk.resize(3 * (size_t)n);
+  for (int q = 0; q < n; ++q) {
+    const C4& c = leaves[order[q].second];
+    H.lvl[q] = c.l; H.ijk[3 * q] = c.i; H.ijk[3 * q + 1] = c.j; H.ijk[3 * q + 2] = c.k;
+  }
+  LeafTable T;
+  T.t.resize(n);
+  for (int q = 0; q < n; ++q) T.t[q] = {leaf_key(H.lvl[q], H.ijk[3 * q], H.ijk[3 * q + 1], H.ijk[3 * q + 2]), q};
+  std::sort(T.t.begin(), T.t.end());
+  // geometry of every leaf at its own size
+  H.type.assign(n, 0); H.flags.assign(n, 0); H.S6.assign(6 * (size_t)n, 0.0);
+  H.aw.assign(n, 0.0); H.nw.assign(3 * (size_t)n, 0.0); H.rw.assign(3 * (size_t)n, 0.0);
+  H.vbar.assign(n, 0.0);
+  bool saddle = false, coarse_cut = false;
+  for (int q = 0; q < n; ++q) {
+    const int sh = D - H.lvl[q];
+    const int A0[3] = {H.ijk[3 * q] << sh, H.ijk[3 * q + 1] << sh, H.ijk[3 * q + 2] << sh};
+    double q8[8], h[3];
+    for (int d = 0; d < 3; ++d) h[d] = H.hf[d] * (double)(1 << sh);
+    for (int t = 0; t < 8; ++t) {
+      const int a = A0[0] + ((t & 1) << sh), b = A0[1] + (((t >> 1) & 1) << sh),
+                c = A0[2] + (((t >> 2) & 1) << sh);
+      q8[t] = clamp_vertex(level_set_3d(B, cfg.lo[0] + a * H.hf[0], cfg.lo[1] + b * H.hf[1], cfg.lo[2] + c * H.hf[2]),
+                           H.hf[0]);
+    }
+    CellGeo3 g;
+    cell_geometry_3d(q8, h, 1e-12 * H.hf[0], g);
+    if (g.flags & 2) saddle = true;
+    if (g.type == TYPE_CUT && H.lvl[q] < D) coarse_cut = true;
+    H.type[q] = g.type;
+    H.flags[q] = g.flags;
+    for (int f = 0; f < 6; ++f) H.S6[6 * q + f] = g.S[f];
+    H.aw[q] = g.aw;
+    for (int d = 0; d < 3; ++d) {
+      H.nw[3 * q + d] = g.n[d];
+      H.rw[3 * q + d] = g.aw > 0.0 ? cfg.lo[d] + A0[d] * H.hf[d] + g.r[d] : 0.0;
+    }
+    H.vbar[q] = g.vbar;
+  }
+  if (saddle) { err = "a cell is cut twice by the boundary"; return false; }
+  if (coarse_cut) { err = "a cut cell above the finest depth (refinement band too narrow)"; return false; }
+  // face lists
+  H.fptr.assign(n + 1, 0);
+  H.fnb.clear(); H.fdir.clear(); H.farea.clear();
+  bool jump = false;
+  for (int q = 0; q < n; ++q) {
+    H.fptr[q] = (int)H.fnb.size();
+    if (H.type[q] == TYPE_SOLID) continue;
+    const int l = H.lvl[q];
+    for (int t = 0; t < 6; ++t) {
+      const double A = H.S6[6 * q + t];
+      if (A == 0.0) continue;
+      const int d = t >> 1, sd = t & 1, d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+      int g[3] = {H.ijk[3 * q], H.ijk[3 * q + 1], H.ijk[3 * q + 2]};
+      g[d] += sd ? 1 : -1;
+      auto add = [&](int nb, double area) {
+        H.fnb.push_back(nb); H.fdir.push_back(t); H.farea.push_back(area);
+      };
+      if (g[d] < 0 || g[d] >= (cfg.n[d] << l)) { add(-1, A); continue; }
+      int x = T.find(l, g[0], g[1], g[2]);
+      if (x < 0) x = T.find(l - 1, g[0] >> 1, g[1] >> 1, g[2] >> 1);
+      if (x >= 0) { add(x, A); continue; }
+      if (l == D) { jump = true; continue; }
+      for (int b2 = 0; b2 < 2; ++b2)
+        for (int b1 = 0; b1 < 2; ++b1) {
+          int c[3];
+          c[d] = 2 * g[d] + (sd ? 0 : 1); c[d1] = 2 * g[d1] + b1; c[d2] = 2 * g[d2] + b2;
+          const int y = T.find(l + 1, c[0], c[1], c[2]);
+          if (y < 0) { jump = true; continue; }
+          const double Ay = H.S6[6 * (size_t)y + (t ^ 1)];
+          if (Ay != 0.0) add(y, Ay);
+        }
+    }
+  }
+  H.fptr[n] = (int)H.fnb.size();
+  H.nface = H.fptr[n];
+  if (jump) { err = "neighbouring leaves differ by more than one depth"; return false; }
+  // masters: centre in gas, else hop across the largest face shared with a
+  // leaf of the same depth (order x+, x-, y+, y-, z+, z-), at most 4 hops
+  H.master.assign(n, -1);
+  const int dir_order[6] = {1, 0, 3, 2, 5, 4};
+  for (int q = 0; q < n; ++q) {
+    if (H.type[q] == TYPE_SOLID) continue;
+    int cur = q, hops = 0, seen[5] = {q, -1, -1, -1, -1};
+    bool ok = true;
+    while (!(H.flags[cur] & 1)) {
+      const int l = H.lvl[cur];
+      double L[6];
+      int nb[6];
+      for (int u = 0; u < 6; ++u) {
+        const int t = dir_order[u], d = t >> 1;
+        int g[3] = {H.ijk[3 * cur], H.ijk[3 * cur + 1], H.ijk[3 * cur + 2]};
+        g[d] += (t & 1) ? 1 : -1;
+        L[u] = 0.0; nb[u] = -1;
+        if (g[d] < 0 || g[d] >= (cfg.n[d] << l)) continue;
+        nb[u] = T.find(l, g[0], g[1], g[2]);
+        L[u] = H.S6[6 * (size_t)cur + t];
+      }
+      double M = 0.0;
+      for (int u = 0; u < 6; ++u) M = std::max(M, L[u]);
+      if (!(M > 0.0) || hops == 4) { ok = false; break; }
+      const double tie = M * (1.0 - 1e-12);
+      int u = 0;
+      while (L[u] < tie) ++u;
+      if (nb[u] < 0) { ok = false; break; }
+      cur = nb[u];
+      ++hops;
+      for (int h = 0; h < hops; ++h) if (seen[h] == cur) ok = false;
+      if (!ok) break;
+      seen[hops] = cur;
+    }
+    if (!ok) { err = "master search cycles, leaves the domain, crosses a change of depth or needs more than 4 hops"; return false; }
+    H.master[q] = cur;
+  }
+  for (int q = 0; q < n; ++q)
+    if (H.master[q] >= 0 && H.master[H.master[q]] != H.master[q]) { err = "a master is not its own master"; return false; }
+  // control volumes: masters in leaf order, members ascending
+  std::vector<int> cnt(n, 0);
+  for (int q = 0; q < n; ++q) if (H.master[q] >= 0) cnt[H.master[q]]++;
+  H.cv.clear(); H.cvptr.assign(1, 0); H.cvmem.clear();
+  std::vector<int> slot(n, -1);
+  for (int q = 0; q < n; ++q)
+    if (H.master[q] == q) {
+      if (cnt[q] > kMaxMembers) { err = "a control volume has more members than supported"; return false; }
+      slot[q] = (int)H.cv.size();
+      H.cv.push_back(q);
+      H.cvptr.push_back(H.cvptr.back() + cnt[q]);
+    }
+  H.cvmem.assign(H.cvptr.back(), 0);
+  std::vector<int> fill(H.cv.size(), 0);
+  for (int q = 0; q < n; ++q)
+    if (H.master[q] >= 0) {
+      const int s = slot[H.master[q]];
+      H.cvmem[H.cvptr[s] + fill[s]++] = q;
+    }
+  H.vcv.assign(n, 0.0);
+  for (size_t s = 0; s < H.cv.size(); ++s) {
+    double v = 0.0;
+    for (int e = H.cvptr[s]; e < H.cvptr[s + 1]; ++e) v += H.vbar[H.cvmem[e]];
+    H.vcv[H.cv[s]] = v;
+  }
+  H.n_irr = 0; H.n_members = 0; H.n_solid = 0;
+  for (size_t s = 0; s < H.cv.size(); ++s) {
+    const int nm = H.cvptr[s + 1] - H.cvptr[s];
+    bool wall = false;
+    for (int e = H.cvptr[s]; e < H.cvptr[s + 1]; ++e) wall = wall || H.aw[H.cvmem[e]] > 0.0;
+    if (nm > 1 || wall) ++H.n_irr;
+    H.n_members += nm - 1;
+  }
+  for (int q = 0; q < n; ++q) H.n_solid += H.type[q] == TYPE_SOLID;
+  return true;
+}
+
+// ---------------------------------------------------------------------
+// device
+// ---------------------------------------------------------------------
+namespace {
+
+constexpr int kWaveA = 64;
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWaveA);
+  return v;
+}
+
+__device__ inline double vnodeA(double vmin, double dv, int i) { return vmin + (i + 0.5) * dv; }
+
+struct AmrArgs {
+  const double* in;
+  double* out;
+  AmrDev G;
+  double* mom;        // 8 per leaf: A, ux, uy, uz, 1/(2T), dt/tau, rho, -
+  double* fslot;      // 3 per control volume: wall force of the state at t^n
+  double vmin, dv, w, dt, tau_coef, t_wall;
+};
+
+// record of the relaxation from the moment sums of one control volume
+__device__ inline void write_record(double* mom, const int* mem, int nm, const double s[5],
+                                    double w, double dt, double tau_coef) {
+  const double rho = s[0] * w;
+  const double ux = s[1] * w / rho, uy = s[2] * w / rho, uz = s[3] * w / rho;
+  const double en = 0.5 * s[4] * w;
+  const double T = (2.0 * en / rho - (ux * ux + uy * uy + uz * uz)) / 3.0;
+  const double rec[8] = {rho / pow(2.0 * M_PI * T, 1.5), ux, uy, uz, 0.5 / T,
+                         tau_coef > 0.0 ? dt * rho / tau_coef : 0.0, rho, 0.0};
+  for (int t = 0; t < nm; ++t)
+    for (int q = 0; q < 8; ++q) mom[8 * (size_t)mem[t] + q] = rec[q];
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
+  constexpr int NV = N * N * N;
+  constexpr int R = (NV + kWaveA - 1) / kWaveA;     // velocities per lane
+  constexpr int RC = R < 16 ? R : 16;                // per pass
+  constexpr int NP = (R + RC - 1) / RC;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (w >= A.G.ncv) return;
+  const AmrDev& G = A.G;
+  const int m = G.cv[w], b = G.cvptr[w], nm = G.cvptr[w + 1] - b;
+  const double* rec = A.mom + 8 * (size_t)m;
+  const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4], dtau = rec[5];
+  const double dtV = A.dt / G.vcv[m];
+  const double* own = A.in + (size_t)m * NV;
+  double tx = 0.0, ty = 0.0, tz = 0.0;
+  if (lane < N) {
+    const double v = vnodeA(A.vmin, A.dv, lane);
+    tx = exp(-(v - ux) * (v - ux) * inv2T);
+    ty = exp(-(v - uy) * (v - uy) * inv2T);
+    tz = exp(-(v - uz) * (v - uz) * inv2T);
+  }
+  // wall density of each member with a wall face (zero net mass flux)
+  const double Tw = A.t_wall, cw = 1.0 / pow(2.0 * M_PI * Tw, 1.5), i2Tw = 0.5 / Tw;
+  double phiw[kMaxMembers];
+  bool any_wall = false;
+  for (int t = 0; t < nm; ++t) {
+    const int k = G.cvmem[b + t];
+    phiw[t] = 0.0;
+    if (!(G.aw[k] > 0.0)) continue;
+    any_wall = true;
+    const double n0 = G.nw[3 * k], n1 = G.nw[3 * k + 1], n2 = G.nw[3 * k + 2];
+    double num = 0.0, den = 0.0;
+    for (int p = lane; p < NV; p += kWaveA) {
+      const double vx = vnodeA(A.vmin, A.dv, p % N), vy = vnodeA(A.vmin, A.dv, (p / N) % N),
+                   vz = vnodeA(A.vmin, A.dv, p / (N * N));
+      const double cn = vx * n0 + vy * n1 + vz * n2;
+      if (cn > 0.0) num += cn * own[p];
+      else if (cn < 0.0) den += cn * cw * exp(-(vx * vx + vy * vy + vz * vz) * i2Tw);
+    }
+    num = wsum(num);
+    den = wsum(den);
+    phiw[t] = den != 0.0 ? -num / den : 0.0;
+  }
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  for (int pass = 0; pass < NP; ++pass) {
+    double fo[RC], acc[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      const int p = (pass * RC + r) * kWaveA + lane;
+      fo[r] = p < NV ? own[p] : 0.0;
+      acc[r] = 0.0;
+    }
+    for (int t = 0; t < nm; ++t) {
+      const int k = G.cvmem[b + t];
+      for (int e = G.fptr[k]; e < G.fptr[k + 1]; ++e) {
+        const int nb = G.fnb[e], dir = G.fdir[e];
+        const double area = G.farea[e];
+        const double* nrow = nb >= 0 ? A.in + (size_t)nb * NV : G.ghost;
+        const int ax = dir >> 1;
+        const double sg = (dir & 1) ? 1.0 : -1.0;
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+          const int p = (pass * RC + r) * kWaveA + lane;
+          const int pc = ax == 0 ? p % N : (ax == 1 ? (p / N) % N : p / (N * N));
+          const double c = sg * vnodeA(A.vmin, A.dv, pc);   // outward normal velocity
+          const double fn = c < 0.0 && p < NV ? nrow[p] : 0.0;
+          acc[r] += area * (fmax(c, 0.0) * fo[r] + fmin(c, 0.0) * fn);
+        }
+      }
+      if (any_wall && G.aw[k] > 0.0) {
+        const double awk = G.aw[k], n0 = G.nw[3 * k], n1 = G.nw[3 * k + 1], n2 = G.nw[3 * k + 2];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+          const int p = (pass * RC + r) * kWaveA + lane;
+          if (p >= NV) continue;
+          const double vx = vnodeA(A.vmin, A.dv, p % N), vy = vnodeA(A.vmin, A.dv, (p / N) % N),
+                       vz = vnodeA(A.vmin, A.dv, p / (N * N));
+          const double cn = vx * n0 + vy * n1 + vz * n2;
+          const double fw = phiw[t] * cw * exp(-(vx * vx + vy * vy + vz * vz) * i2Tw);
+          acc[r] += awk * (fmin(cn, 0.0) * fw + fmax(cn, 0.0) * fo[r]);
+          const double fv = cn < 0.0 ? fw : (cn > 0.0 ? fo[r] : 0.0);
+          fx += awk * vx * cn * fv; fy += awk * vy * cn * fv; fz += awk * vz * cn * fv;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      const int p = (pass * RC + r) * kWaveA + lane;
+      if (p >= NV) continue;
+      const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
+      const double E = Am * __shfl(tx, p1, kWaveA) * __shfl(ty, p2, kWaveA) * __shfl(tz, p3, kWaveA);
+      const double f = fo[r];
+      const double fn = f - dtV * acc[r] + dtau * (E - f);
+      for (int t = 0; t < nm; ++t) A.out[(size_t)G.cvmem[b + t] * NV + p] = fn;
+      const double vx = vnodeA(A.vmin, A.dv, p1), vy = vnodeA(A.vmin, A.dv, p2), vz = vnodeA(A.vmin, A.dv, p3);
+      s[0] += fn; s[1] += vx * fn; s[2] += vy * fn; s[3] += vz * fn;
+      s[4] += (vx * vx + vy * vy + vz * vz) * fn;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) s[q] = wsum(s[q]);
+  if (any_wall) { fx = wsum(fx); fy = wsum(fy); fz = wsum(fz); }
+  if (lane == 0) {
+    write_record(A.mom, G.cvmem + b, nm, s, A.w, A.dt, A.tau_coef);
+    A.fslot[3 * w] = fx * A.w; A.fslot[3 * w + 1] = fy * A.w; A.fslot[3 * w + 2] = fz * A.w;
+  }
+}
+
+// record of every control volume from its current value (one wave each)
+template <int N>
+__global__ void __launch_bounds__(256) k_amr_mom(AmrArgs A) {
+  constexpr int NV = N * N * N;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (w >= A.G.ncv) return;
+  const int m = A.G.cv[w], b = A.G.cvptr[w], nm = A.G.cvptr[w + 1] - b;
+  const double* own = A.in + (size_t)m * NV;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int p = lane; p < NV; p += kWaveA) {
+    const double vx = vnodeA(A.vmin, A.dv, p % N), vy = vnodeA(A.vmin, A.dv, (p / N) % N),
+                 vz = vnodeA(A.vmin, A.dv, p / (N * N));
+    const double f = own[p];
+    s[0] += f; s[1] += vx * f; s[2] += vy * f; s[3] += vz * f;
+    s[4] += (vx * vx + vy * vy + vz * vz) * f;
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) s[q] = wsum(s[q]);
+  if (lane == 0) write_record(A.mom, A.G.cvmem + b, nm, s, A.w, A.dt, A.tau_coef);
+}
+
+// merge of the control volumes with several members: value = sum_k V_k F_k / V
+__global__ void __launch_bounds__(256) k_amr_merge(AmrDev G, double* __restrict__ st, int nvel) {
+  const int w = blockIdx.x;
+  const int m = G.cv[w], b = G.cvptr[w], nm = G.cvptr[w + 1] - b;
+  if (nm <= 1) return;
+  for (int p = threadIdx.x; p < nvel; p += blockDim.x) {
+    double acc = 0.0;
+    for (int t = 0; t < nm; ++t) {
+      const int k = G.cvmem[b + t];
+      acc += G.vbar[k] * st[(size_t)k * nvel + p];
+    }
+    const double v = acc / G.vcv[m];
+    for (int t = 0; t < nm; ++t) st[(size_t)G.cvmem[b + t] * nvel + p] = v;
+  }
+}
+
+__global__ void k_amr_init(AmrDev G, double* __restrict__ st, int nvel, int load, const double* __restrict__ f) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)G.nleaf * nvel) return;
+  const int c = (int)(t / nvel), p = (int)(t % nvel);
+  st[t] = G.type[c] == TYPE_SOLID ? 0.0 : (load ? f[t] : G.ghost[p]);
+}
+
+__global__ void k_amr_tables(AmrDev G, int N, double vmin, double dv, double rho, double ux, double uy,
+                             double uz, double T) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N * N * N) return;
+  const double vx = vmin + (p % N + 0.5) * dv, vy = vmin + ((p / N) % N + 0.5) * dv,
+               vz = vmin + (p / (N * N) + 0.5) * dv;
+  const double cx = vx - ux, cy = vy - uy, cz = vz - uz;
+  G.ghost[p] = rho / pow(2.0 * M_PI * T, 1.5) * exp(-(cx * cx + cy * cy + cz * cz) / (2.0 * T));
+}
+
+// mass of the state entering the step, before its records are overwritten
+__global__ void __launch_bounds__(256) k_amr_mass(AmrDev G, const double* __restrict__ mom, double* __restrict__ row) {
+  __shared__ double lds[4];
+  double a = 0.0;
+  for (int w = threadIdx.x; w < G.ncv; w += blockDim.x) a += G.vcv[G.cv[w]] * mom[8 * (size_t)G.cv[w] + 6];
+  a = wsum(a);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) row[3] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+}
+
+// force slots of the step into row[0..2]
+__global__ void __launch_bounds__(256) k_amr_force(AmrDev G, const double* __restrict__ fslot, double* __restrict__ row) {
+  __shared__ double lds[4][3];
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int w = threadIdx.x; w < G.ncv; w += blockDim.x) {
+    a[0] += fslot[3 * w]; a[1] += fslot[3 * w + 1]; a[2] += fslot[3 * w + 2];
+  }
+  for (int q = 0; q < 3; ++q) a[q] = wsum(a[q]);
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 3; ++q) lds[threadIdx.x >> 6][q] = a[q];
+  __syncthreads();
+  if (threadIdx.x < 3) row[threadIdx.x] = ((lds[0][threadIdx.x] + lds[1][threadIdx.x]) + lds[2][threadIdx.x]) +
+                                          lds[3][threadIdx.x];
+}
+
+AmrArgs amr_args(cc_ctx* ctx, const double* in, double* out) {
+  AmrArgs A;
+  A.in = in; A.out = out; A.G = ctx->a3;
+  A.mom = ctx->s.mom; A.fslot = ctx->s.fslot;
+  A.vmin = ctx->cfg.vmin; A.dv = ctx->dv; A.w = ctx->dv * ctx->dv * ctx->dv;
+  A.dt = ctx->dt;
+  A.tau_coef = ctx->cfg.kn > 0.0 ? sqrt(M_PI) / 2.0 * ctx->cfg.kn * ctx->cfg.lref / sqrt(2.0) : 0.0;
+  A.t_wall = ctx->body.t_wall;
+  return A;
+}
+
+typedef void (*amr_fn)(AmrArgs);
+
+bool pick_amr(int N, amr_fn* step, amr_fn* mom) {
+  switch (N) {
+    case 4: *step = k_amr_step<4>; *mom = k_amr_mom<4>; return true;
+    case 6: *step = k_amr_step<6>; *mom = k_amr_mom<6>; return true;
+    case 8: *step = k_amr_step<8>; *mom = k_amr_mom<8>; return true;
+    case 12: *step = k_amr_step<12>; *mom = k_amr_mom<12>; return true;
+    case 16: *step = k_amr_step<16>; *mom = k_amr_mom<16>; return true;
+    default: return false;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_amr_tables(cc_ctx* ctx) {
+  const double* in = ctx->cfg.inflow;
+  k_amr_tables<<<(ctx->nvel + 255) / 256, 256, 0, ctx->stream>>>(ctx->a3, ctx->N, ctx->cfg.vmin, ctx->dv, in[0],
+                                                                  in[1], in[2], in[3], in[4]);
+  return hipGetLastError();
+}
+
+hipError_t launch_amr_init(cc_ctx* ctx, const double* f) {
+  const size_t tot = (size_t)ctx->ncell * ctx->nvel;
+  k_amr_init<<<(unsigned)((tot + 255) / 256), 256, 0, ctx->stream>>>(ctx->a3, (double*)ctx->state[ctx->cur],
+                                                                     ctx->nvel, f ? 1 : 0, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_amr_merge(cc_ctx* ctx) {
+  if (ctx->a3.ncv == 0) return hipSuccess;
+  prof_begin(ctx, 3);
+  k_amr_merge<<<ctx->a3.ncv, 256, 0, ctx->stream>>>(ctx->a3, (double*)ctx->state[ctx->cur], ctx->nvel);
+  prof_end(ctx, 3);
+  return hipGetLastError();
+}
+
+hipError_t launch_amr_moments(cc_ctx* ctx) {
+  amr_fn step, mom;
+  if (!pick_amr(ctx->N, &step, &mom)) return hipErrorNotSupported;
+  const double* cur = (const double*)ctx->state[ctx->cur];
+  mom<<<(ctx->a3.ncv + 3) / 4, 256, 0, ctx->stream>>>(amr_args(ctx, cur, nullptr));
+  return hipGetLastError();
+}
+
+// one step state[cur] -> state[1-cur]; row (nullable) = force and mass of
+// the state entering the step
+hipError_t launch_amr_step(cc_ctx* ctx, double* row) {
+  amr_fn step, mom;
+  if (!pick_amr(ctx->N, &step, &mom)) return hipErrorNotSupported;
+  const double* in = (const double*)ctx->state[ctx->cur];
+  double* out = (double*)ctx->state[1 - ctx->cur];
+  if (row) k_amr_mass<<<1, 256, 0, ctx->stream>>>(ctx->a3, ctx->s.mom, row);
+  prof_begin(ctx, 0);
+  step<<<(ctx->a3.ncv + 3) / 4, 256, 0, ctx->stream>>>(amr_args(ctx, in, out));
+  prof_end(ctx, 0);
+  if (row) {
+    prof_begin(ctx, 2);
+    k_amr_force<<<1, 256, 0, ctx->stream>>>(ctx->a3, ctx->s.fslot, row);
+    prof_end(ctx, 2);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  ctx->cur = 1 - ctx->cur;
+  ctx->nstep += 1;
+  return hipSuccess;
+}
+
+}  // namespace ccdvm

@@ -34,6 +34,11 @@ class Solver:
         self._check(lib().cc_workspace_bytes(h, C.byref(sb), C.byref(gb), C.byref(xb)))
         self.dim = cfg.dim
         self.ncell = cfg.n[0] * cfg.n[1] * cfg.n[2]
+        self.amr = getattr(cfg, "amr_depth", 0) > 0
+        if self.amr:   # octree mesh: the cells are the leaves
+            nl, nf = C.c_int(), C.c_int()
+            self._check(lib().cc_amr_counts(h, C.byref(nl), C.byref(nf)))
+            self.ncell, self.nface = nl.value, nf.value
         self.nvel = cfg.nv ** cfg.dim
         with torch.cuda.device(self.device):
             # caller-owned device buffers (uint8 tensors; 256-byte aligned by the caching allocator)
@@ -143,6 +148,26 @@ class Solver:
         out["nw"] = np.stack([raw["nwx"], raw["nwy"], raw["nwz"]], axis=1)
         out["rw"] = np.stack([raw["rwx"], raw["rwy"], raw["rwz"]], axis=1)
         out["vbar"], out["vcv"] = raw["vbar"], raw["vcv"]
+        return out
+
+    def amr_leaves(self) -> dict:
+        """Octree leaves (host arrays): depth, coordinates at that depth,
+        type, master, gas volume, control-volume volume, wall area, face
+        gas areas (n, 6)."""
+        n = self.ncell
+        out = {"lvl": np.zeros(n, np.int32), "ijk": np.zeros((n, 3), np.int32),
+               "type": np.zeros(n, np.int32), "master": np.zeros(n, np.int32),
+               "vbar": np.zeros(n), "vcv": np.zeros(n), "sw": np.zeros(n), "S": np.zeros((n, 6))}
+        P = lambda a: a.ctypes.data_as(C.c_void_p)
+        self._check(lib().cc_amr_export(self._h, *[P(out[k]) for k in
+                                                   ("lvl", "ijk", "type", "master", "vbar", "vcv", "sw", "S")]))
+        return out
+
+    def amr_faces(self) -> dict:
+        out = {"ptr": np.zeros(self.ncell + 1, np.int32), "nb": np.zeros(self.nface, np.int32),
+               "dir": np.zeros(self.nface, np.int32), "area": np.zeros(self.nface)}
+        P = lambda a: a.ctypes.data_as(C.c_void_p)
+        self._check(lib().cc_amr_faces(self._h, *[P(out[k]) for k in ("ptr", "nb", "dir", "area")]))
         return out
 
     def counts(self):
