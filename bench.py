@@ -32,6 +32,9 @@ WORKLOAD_TEXT = {
     "cyl32": "cyl32: 2D 32x32 cells, 16x16 velocities, cylinder r=0.2, Kn {kn}, Mach 0.5",
     "sphere128": "sphere128: 3D 128x64x64 cells on [0,1]x[0,0.5]^2, 16^3 velocities on [-6,6]^3, "
                  "sphere r=0.1, Kn {kn}, Mach 0.5, T_w 1, CFL 0.5, force every step",
+    "sphere_amr": "sphere_amr: 3D octree, 32x16x16 coarse cells on [0,1]x[0,0.5]^2 refined twice near "
+                  "the sphere (1/128 there, as sphere128), 16^3 velocities, sphere r=0.1, Kn {kn}, "
+                  "Mach 0.5, T_w 1, CFL 0.5, force every step",
 }
 # committed rocprofv3 counter summaries: workload -> (kernel source, summary)
 TRAFFIC = {
@@ -138,9 +141,9 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kn", type=float, default=None)
-    ap.add_argument("--workload", default="cyl512", choices=["cyl512", "ellipse256", "cyl32", "sphere128", "batch"],
+    ap.add_argument("--workload", default="cyl512", choices=["cyl512", "ellipse256", "cyl32", "sphere128", "sphere_amr", "batch"],
                     help="cyl512 (default, the headline line) | ellipse256 (moving body) | cyl32 | "
-                         "sphere128 (3D)")
+                         "sphere128 (3D) | sphere_amr (3D octree)")
     ap.add_argument("--maxwellian", default="direct", choices=["direct", "conservative"],
                     help="equilibrium of the relaxation: direct moments (default) or the conservative "
                          "Newton triplet")
@@ -185,7 +188,7 @@ def main():
     torch.cuda.set_device(dev)
     s = Solver(cfg, device=dev)
     n_irr, n_mem, n_solid = s.counts()
-    active = cfg.ncell - n_solid
+    active = s.ncell - n_solid   # cells, or the leaves of an octree
     nvel = cfg.nv ** cfg.dim
     s.init_maxwellian()
     diag = torch.empty((max(args.steps, args.warmup, 1), 4), dtype=torch.float64, device=dev)
@@ -213,7 +216,10 @@ def main():
     mom_ms, mom_n = s.profile_read(4)
     rlx_ms, rlx_n = s.profile_read(5)
     s.profile_enable(False)
-    n_regular = active - n_irr - n_mem
+    amr = getattr(cfg, "amr_depth", 0) > 0
+    # the uniform kernels stream the regular cells (cut control volumes have
+    # their own kernel); the octree kernel updates every control volume
+    n_regular = active - n_mem if amr else active - n_irr - n_mem
     # read + write of the state, FP64: f,g in 2D (32 B), F in 3D (16 B)
     bytes_per_launch = n_regular * nvel * (32 if cfg.dim == 2 else 16)
     avg_s = reg_ms / max(reg_n, 1) / 1e3
@@ -234,11 +240,11 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload].format(kn=cfg.kn),
-                   "cells": cfg.ncell, "active_cells": active, "velocities": nvel,
+                   "cells": s.ncell, "active_cells": active, "velocities": nvel,
                    "cut_control_volumes": n_irr, "merged_cells": n_mem, "dt": s.dt,
                    "maxwellian": args.maxwellian, "scheme": args.scheme, "model": args.model,
                    "drag_last_step": drag_last},
-        "roofline": {"bound": "hbm", "kernel": "k_step2d" if cfg.dim == 2 else "k_step3d",
+        "roofline": {"bound": "hbm", "kernel": "k_step2d" if cfg.dim == 2 else ("k_amr_step" if amr else "k_step3d"),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "avg_launch_us": round(avg_s * 1e6, 2),

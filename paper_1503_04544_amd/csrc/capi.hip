@@ -111,7 +111,7 @@ void layout_amr(cc_ctx* ctx, char* base, size_t* bytes) {
   const AmrHost& H = *ctx->amrh;
   AmrDev& G = ctx->a3;
   const size_t n = H.nleaf, nf = H.nface, ncv = H.cv.size();
-  G.nleaf = (int)n; G.ncv = (int)ncv;
+  G.nleaf = (int)n; G.ncv = (int)ncv; G.nreg = H.nreg; G.nsimple = H.nsimple;
   G.type = cv.take<int>(n); G.master = cv.take<int>(n);
   G.cv = cv.take<int>(ncv); G.cvptr = cv.take<int>(ncv + 1); G.cvmem = cv.take<int>(H.cvmem.size());
   G.fptr = cv.take<int>(n + 1); G.fnb = cv.take<int>(nf); G.fdir = cv.take<int>(nf);
@@ -307,6 +307,9 @@ void cc_destroy(cc_ctx* ctx) {
     for (hipEvent_t e : ctx->prof.start[k]) hipEventDestroy(e);
     for (hipEvent_t e : ctx->prof.stop[k]) hipEventDestroy(e);
   }
+  if (ctx->fork) hipEventDestroy(ctx->fork);
+  if (ctx->join) hipEventDestroy(ctx->join);
+  if (ctx->side) hipStreamDestroy(ctx->side);
   delete ctx->amrh;
   delete ctx;
 }
@@ -388,6 +391,11 @@ cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scr
       if (x != hipSuccess) e = x;
     if (e == hipSuccess) e = launch_amr_tables(ctx);
     if (e != hipSuccess) return hip_fail(ctx, e, "octree upload");
+    if (!ctx->side) {   // default priority, like the caller's stream
+      HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "side stream");
+      HIPCHK(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming), "event");
+      HIPCHK(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming), "event");
+    }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "octree upload");
     // the generic 3D moment and mass kernels see the leaves through g3
     ctx->g3 = Geo3D{};

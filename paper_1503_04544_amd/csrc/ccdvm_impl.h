@@ -107,11 +107,13 @@ struct AmrHost {
   std::vector<double> S6, aw, nw, rw, vbar, vcv;
   std::vector<int> fptr, fnb, fdir;  // per leaf, faces x-, x+, y-, y+, z-, z+ (leaf across or -1)
   std::vector<double> farea;
-  std::vector<int> cv, cvptr, cvmem; // control volumes: master leaf, members (CSR)
+  std::vector<int> cv, cvptr, cvmem; // control volumes: master leaf, members (CSR); regular first
+  int nsimple = 0;                   // simple regular control volumes (one face entry per direction)
+  int nreg = 0;                      // regular control volumes (one member, no wall face), simple first
 };
 
 struct AmrDev {
-  int nleaf, ncv;
+  int nleaf, ncv, nreg, nsimple;
   int* type; int* master;
   int* cv; int* cvptr; int* cvmem;
   int* fptr; int* fnb; int* fdir;
@@ -184,6 +186,8 @@ struct cc_ctx {
   bool amr = false;                 // 3D octree mesh
   ccdvm::AmrHost* amrh = nullptr;
   ccdvm::AmrDev a3{};
+  hipStream_t side = nullptr;        // octree: cut control volumes run beside the others
+  hipEvent_t fork = nullptr, join = nullptr;
   ccdvm::Scratch s;
   int n_irr = 0, n_members = 0, n_solid = 0;
   // host mirror of the rigid body (kept in sync with the device copy)

@@ -227,18 +227,33 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, AmrHost& H, std:
   }
   for (int q = 0; q < n; ++q)
     if (H.master[q] >= 0 && H.master[H.master[q]] != H.master[q]) { err = "a master is not its own master"; return false; }
-  // control volumes: masters in leaf order, members ascending
+  // control volumes: first the regular ones (one member, no wall face),
+  // then the others, each in leaf order; members ascending
   std::vector<int> cnt(n, 0);
   for (int q = 0; q < n; ++q) if (H.master[q] >= 0) cnt[H.master[q]]++;
   H.cv.clear(); H.cvptr.assign(1, 0); H.cvmem.clear();
   std::vector<int> slot(n, -1);
-  for (int q = 0; q < n; ++q)
-    if (H.master[q] == q) {
-      if (cnt[q] > kMaxMembers) { err = "a control volume has more members than supported"; return false; }
-      slot[q] = (int)H.cv.size();
-      H.cv.push_back(q);
-      H.cvptr.push_back(H.cvptr.back() + cnt[q]);
-    }
+  // kinds: 0 simple (one member, no wall, one face entry per direction, in
+  // direction order), 1 other regular, 2 cut or merged
+  auto kind_of = [&](int q) {
+    if (cnt[q] != 1 || H.aw[q] > 0.0) return 2;
+    if (H.fptr[q + 1] - H.fptr[q] != 6) return 1;
+    for (int t = 0; t < 6; ++t) if (H.fdir[H.fptr[q] + t] != t) return 1;
+    return 0;
+  };
+  H.nsimple = 0; H.nreg = 0;
+  for (int pass = 0; pass < 3; ++pass)
+    for (int q = 0; q < n; ++q)
+      if (H.master[q] == q) {
+        if (cnt[q] > kMaxMembers) { err = "a control volume has more members than supported"; return false; }
+        const int kd = kind_of(q);
+        if (kd != pass) continue;
+        H.nsimple += kd == 0;
+        H.nreg += kd <= 1;
+        slot[q] = (int)H.cv.size();
+        H.cv.push_back(q);
+        H.cvptr.push_back(H.cvptr.back() + cnt[q]);
+      }
   H.cvmem.assign(H.cvptr.back(), 0);
   std::vector<int> fill(H.cv.size(), 0);
   for (int q = 0; q < n; ++q)
@@ -270,6 +285,12 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, AmrHost& H, std:
 namespace {
 
 constexpr int kWaveA = 64;
+#ifndef CCDVM_AMR_RC
+#define CCDVM_AMR_RC 4   // velocities per lane and pass of the general octree step
+#endif
+#ifndef CCDVM_AMR_RCS
+#define CCDVM_AMR_RCS 4  // velocities per lane and pass of the streaming octree step
+#endif
 
 __device__ inline double wsum(double v) {
 #pragma unroll
@@ -284,7 +305,8 @@ struct AmrArgs {
   double* out;
   AmrDev G;
   double* mom;        // 8 per leaf: A, ux, uy, uz, 1/(2T), dt/tau, rho, -
-  double* fslot;      // 3 per control volume: wall force of the state at t^n
+  double* part;       // 4 per block: wall force and mass of the state at t^n
+  int per_simple, per, per_irr;   // blocks per XCD of the three kinds of control volumes
   double vmin, dv, w, dt, tau_coef, t_wall;
 };
 
@@ -301,19 +323,30 @@ __device__ inline void write_record(double* mom, const int* mem, int nm, const d
     for (int q = 0; q < 8; ++q) mom[8 * (size_t)mem[t] + q] = rec[q];
 }
 
-template <int N>
+// IRR = false: control volumes [nsimple, nreg) (one member, no wall face,
+// a finer neighbour on some face); IRR = true: [nreg, ncv) (cut or merged)
+template <int N, bool IRR>
 __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
   constexpr int NV = N * N * N;
   constexpr int R = (NV + kWaveA - 1) / kWaveA;     // velocities per lane
-  constexpr int RC = R < 16 ? R : 16;                // per pass
+  constexpr int RC = R < CCDVM_AMR_RC ? R : CCDVM_AMR_RC;   // per pass
   constexpr int NP = (R + RC - 1) / RC;
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (w >= A.G.ncv) return;
+  __shared__ double lds[4][4];
+  // XCD-aware order: block b runs on XCD b % 8, and the blocks of one XCD
+  // take a contiguous range of control volumes (neighbours in Z-order share
+  // that XCD's L2)
+  const int per = IRR ? A.per_irr : A.per;
+  const int w0 = IRR ? A.G.nreg : A.G.nsimple, ncv = IRR ? A.G.ncv - A.G.nreg : A.G.nreg - A.G.nsimple;
+  const int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = w0 + blk * 4 + wave;
+  if (blk * 4 >= ncv) return;    // uniform over the block
+  const bool live = w < w0 + ncv;
   const AmrDev& G = A.G;
-  const int m = G.cv[w], b = G.cvptr[w], nm = G.cvptr[w + 1] - b;
+  const int m = live ? G.cv[w] : 0, b = live ? G.cvptr[w] : 0, nm = live ? G.cvptr[w + 1] - b : 0;
   const double* rec = A.mom + 8 * (size_t)m;
   const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4], dtau = rec[5];
+  const double mass_n = live ? G.vcv[m] * rec[6] : 0.0;   // before the record is overwritten
   const double dtV = A.dt / G.vcv[m];
   const double* own = A.in + (size_t)m * NV;
   double tx = 0.0, ty = 0.0, tz = 0.0;
@@ -325,9 +358,9 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
   }
   // wall density of each member with a wall face (zero net mass flux)
   const double Tw = A.t_wall, cw = 1.0 / pow(2.0 * M_PI * Tw, 1.5), i2Tw = 0.5 / Tw;
-  double phiw[kMaxMembers];
+  double phiw[IRR ? kMaxMembers : 1];
   bool any_wall = false;
-  for (int t = 0; t < nm; ++t) {
+  for (int t = 0; t < (IRR ? nm : 0); ++t) {
     const int k = G.cvmem[b + t];
     phiw[t] = 0.0;
     if (!(G.aw[k] > 0.0)) continue;
@@ -347,36 +380,46 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
   }
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  for (int pass = 0; pass < NP; ++pass) {
+  for (int pass = 0; pass < (live ? NP : 0); ++pass) {
+    // the lane id is laundered per pass so that the velocity constants of a
+    // pass are recomputed where used instead of being held across passes
+    int lv = lane;
+    asm volatile("" : "+v"(lv));
     double fo[RC], acc[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
-      const int p = (pass * RC + r) * kWaveA + lane;
+      const int p = (pass * RC + r) * kWaveA + lv;
       fo[r] = p < NV ? own[p] : 0.0;
       acc[r] = 0.0;
     }
-    for (int t = 0; t < nm; ++t) {
-      const int k = G.cvmem[b + t];
+    for (int t = 0; t < (IRR ? nm : 1); ++t) {
+      const int k = IRR ? G.cvmem[b + t] : m;
       for (int e = G.fptr[k]; e < G.fptr[k + 1]; ++e) {
         const int nb = G.fnb[e], dir = G.fdir[e];
         const double area = G.farea[e];
         const double* nrow = nb >= 0 ? A.in + (size_t)nb * NV : G.ghost;
-        const int ax = dir >> 1;
         const double sg = (dir & 1) ? 1.0 : -1.0;
+        // the face's axis is uniform over the wave: one loop per axis
+        auto gather = [&](auto comp) {
 #pragma unroll
-        for (int r = 0; r < RC; ++r) {
-          const int p = (pass * RC + r) * kWaveA + lane;
-          const int pc = ax == 0 ? p % N : (ax == 1 ? (p / N) % N : p / (N * N));
-          const double c = sg * vnodeA(A.vmin, A.dv, pc);   // outward normal velocity
-          const double fn = c < 0.0 && p < NV ? nrow[p] : 0.0;
-          acc[r] += area * (fmax(c, 0.0) * fo[r] + fmin(c, 0.0) * fn);
+          for (int r = 0; r < RC; ++r) {
+            const int p = (pass * RC + r) * kWaveA + lv;
+            const double c = sg * vnodeA(A.vmin, A.dv, comp(p));   // outward normal velocity
+            const double fn = c < 0.0 && p < NV ? nrow[p] : 0.0;
+            acc[r] += area * (fmax(c, 0.0) * fo[r] + fmin(c, 0.0) * fn);
+          }
+        };
+        switch (dir >> 1) {
+          case 0: gather([](int p) { return p % N; }); break;
+          case 1: gather([](int p) { return (p / N) % N; }); break;
+          default: gather([](int p) { return p / (N * N); }); break;
         }
       }
-      if (any_wall && G.aw[k] > 0.0) {
+      if (IRR && any_wall && G.aw[k] > 0.0) {
         const double awk = G.aw[k], n0 = G.nw[3 * k], n1 = G.nw[3 * k + 1], n2 = G.nw[3 * k + 2];
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
-          const int p = (pass * RC + r) * kWaveA + lane;
+          const int p = (pass * RC + r) * kWaveA + lv;
           if (p >= NV) continue;
           const double vx = vnodeA(A.vmin, A.dv, p % N), vy = vnodeA(A.vmin, A.dv, (p / N) % N),
                        vz = vnodeA(A.vmin, A.dv, p / (N * N));
@@ -390,13 +433,16 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
     }
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
-      const int p = (pass * RC + r) * kWaveA + lane;
+      const int p = (pass * RC + r) * kWaveA + lv;
       if (p >= NV) continue;
       const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
       const double E = Am * __shfl(tx, p1, kWaveA) * __shfl(ty, p2, kWaveA) * __shfl(tz, p3, kWaveA);
       const double f = fo[r];
       const double fn = f - dtV * acc[r] + dtau * (E - f);
-      for (int t = 0; t < nm; ++t) A.out[(size_t)G.cvmem[b + t] * NV + p] = fn;
+      if (IRR)
+        for (int t = 0; t < nm; ++t) A.out[(size_t)G.cvmem[b + t] * NV + p] = fn;
+      else
+        A.out[(size_t)m * NV + p] = fn;
       const double vx = vnodeA(A.vmin, A.dv, p1), vy = vnodeA(A.vmin, A.dv, p2), vz = vnodeA(A.vmin, A.dv, p3);
       s[0] += fn; s[1] += vx * fn; s[2] += vy * fn; s[3] += vz * fn;
       s[4] += (vx * vx + vy * vy + vz * vz) * fn;
@@ -404,11 +450,104 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) s[q] = wsum(s[q]);
-  if (any_wall) { fx = wsum(fx); fy = wsum(fy); fz = wsum(fz); }
+  if (IRR && any_wall) { fx = wsum(fx); fy = wsum(fy); fz = wsum(fz); }
   if (lane == 0) {
-    write_record(A.mom, G.cvmem + b, nm, s, A.w, A.dt, A.tau_coef);
-    A.fslot[3 * w] = fx * A.w; A.fslot[3 * w + 1] = fy * A.w; A.fslot[3 * w + 2] = fz * A.w;
+    if (live) write_record(A.mom, G.cvmem + b, nm, s, A.w, A.dt, A.tau_coef);
+    lds[wave][0] = fx * A.w; lds[wave][1] = fy * A.w; lds[wave][2] = fz * A.w; lds[wave][3] = mass_n;
   }
+  __syncthreads();
+  // block partials of the force and mass of t^n, in wave order (regular
+  // blocks first, then the others)
+  if (threadIdx.x < 4)
+    A.part[4 * ((size_t)blk + (A.G.nsimple + 3) / 4 + (IRR ? (A.G.nreg - A.G.nsimple + 3) / 4 : 0)) + threadIdx.x] =
+        ((lds[0][threadIdx.x] + lds[1][threadIdx.x]) + lds[2][threadIdx.x]) + lds[3][threadIdx.x];
+}
+
+// Control volumes [0, nsimple): gas leaves with one neighbour (or the
+// farfield) per face direction.  The upwind flux of an axis is then
+// A |v| (f - f_up) with f_up from the face's leaf on the upwind side, so
+// each velocity needs its own value and three upwind values, all
+// independent loads.
+template <int N>
+__global__ void __launch_bounds__(256) k_amr_simple(AmrArgs A) {
+  constexpr int NV = N * N * N;
+  constexpr int R = (NV + kWaveA - 1) / kWaveA;
+  constexpr int RC = R < CCDVM_AMR_RCS ? R : CCDVM_AMR_RCS;
+  constexpr int NP = (R + RC - 1) / RC;
+  __shared__ double lds[4][4];
+  const int per = A.per_simple, ncv = A.G.nsimple;
+  const int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = blk * 4 + wave;
+  if (blk * 4 >= ncv) return;    // uniform over the block
+  const bool live = w < ncv;
+  const AmrDev& G = A.G;
+  const int m = live ? G.cv[w] : 0;
+  const double* rec = A.mom + 8 * (size_t)m;
+  const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4], dtau = rec[5];
+  const double mass_n = live ? G.vcv[m] * rec[6] : 0.0;
+  const double dtV = A.dt / G.vcv[m];
+  const double* own = A.in + (size_t)m * NV;
+  const int e0 = G.fptr[m];
+  const double* row[6];
+  double ar[6];
+  for (int t = 0; t < 6; ++t) {
+    const int nb = live ? G.fnb[e0 + t] : -1;
+    row[t] = nb >= 0 ? A.in + (size_t)nb * NV : G.ghost;
+    ar[t] = live ? G.farea[e0 + t] : 0.0;
+  }
+  double tx = 0.0, ty = 0.0, tz = 0.0;
+  if (lane < N) {
+    const double v = vnodeA(A.vmin, A.dv, lane);
+    tx = exp(-(v - ux) * (v - ux) * inv2T);
+    ty = exp(-(v - uy) * (v - uy) * inv2T);
+    tz = exp(-(v - uz) * (v - uz) * inv2T);
+  }
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int pass = 0; pass < (live ? NP : 0); ++pass) {
+    int lv = lane;
+    asm volatile("" : "+v"(lv));
+    double fo[RC], fx[RC], fy[RC], fz[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      const int p = (pass * RC + r) * kWaveA + lv;
+      const bool in = p < NV;
+      const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
+      // upwind side: the x- face's leaf for v_x > 0, the x+ face's for v_x < 0
+      const bool px = vnodeA(A.vmin, A.dv, p1) > 0.0, py = vnodeA(A.vmin, A.dv, p2) > 0.0,
+                 pz = vnodeA(A.vmin, A.dv, p3) > 0.0;
+      fo[r] = in ? own[p] : 0.0;
+      fx[r] = in ? (px ? row[0] : row[1])[p] : 0.0;
+      fy[r] = in ? (py ? row[2] : row[3])[p] : 0.0;
+      fz[r] = in ? (pz ? row[4] : row[5])[p] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      const int p = (pass * RC + r) * kWaveA + lv;
+      if (p >= NV) continue;
+      const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
+      const double vx = vnodeA(A.vmin, A.dv, p1), vy = vnodeA(A.vmin, A.dv, p2), vz = vnodeA(A.vmin, A.dv, p3);
+      const double f = fo[r];
+      const double acc = (vx > 0.0 ? ar[0] : ar[1]) * fabs(vx) * (f - fx[r]) +
+                         (vy > 0.0 ? ar[2] : ar[3]) * fabs(vy) * (f - fy[r]) +
+                         (vz > 0.0 ? ar[4] : ar[5]) * fabs(vz) * (f - fz[r]);
+      const double E = Am * __shfl(tx, p1, kWaveA) * __shfl(ty, p2, kWaveA) * __shfl(tz, p3, kWaveA);
+      const double fn = f - dtV * acc + dtau * (E - f);
+      A.out[(size_t)m * NV + p] = fn;
+      s[0] += fn; s[1] += vx * fn; s[2] += vy * fn; s[3] += vz * fn;
+      s[4] += (vx * vx + vy * vy + vz * vz) * fn;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) s[q] = wsum(s[q]);
+  if (lane == 0) {
+    if (live) write_record(A.mom, &G.cv[w], 1, s, A.w, A.dt, A.tau_coef);
+    lds[wave][0] = 0.0; lds[wave][1] = 0.0; lds[wave][2] = 0.0; lds[wave][3] = mass_n;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4)
+    A.part[4 * (size_t)blk + threadIdx.x] =
+        ((lds[0][threadIdx.x] + lds[1][threadIdx.x]) + lds[2][threadIdx.x]) + lds[3][threadIdx.x];
 }
 
 // record of every control volume from its current value (one wave each)
@@ -466,36 +605,32 @@ __global__ void k_amr_tables(AmrDev G, int N, double vmin, double dv, double rho
   G.ghost[p] = rho / pow(2.0 * M_PI * T, 1.5) * exp(-(cx * cx + cy * cy + cz * cz) / (2.0 * T));
 }
 
-// mass of the state entering the step, before its records are overwritten
-__global__ void __launch_bounds__(256) k_amr_mass(AmrDev G, const double* __restrict__ mom, double* __restrict__ row) {
-  __shared__ double lds[4];
-  double a = 0.0;
-  for (int w = threadIdx.x; w < G.ncv; w += blockDim.x) a += G.vcv[G.cv[w]] * mom[8 * (size_t)G.cv[w] + 6];
-  a = wsum(a);
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = a;
-  __syncthreads();
-  if (threadIdx.x == 0) row[3] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
-}
-
-// force slots of the step into row[0..2]
-__global__ void __launch_bounds__(256) k_amr_force(AmrDev G, const double* __restrict__ fslot, double* __restrict__ row) {
-  __shared__ double lds[4][3];
-  double a[3] = {0.0, 0.0, 0.0};
-  for (int w = threadIdx.x; w < G.ncv; w += blockDim.x) {
-    a[0] += fslot[3 * w]; a[1] += fslot[3 * w + 1]; a[2] += fslot[3 * w + 2];
-  }
-  for (int q = 0; q < 3; ++q) a[q] = wsum(a[q]);
+// diag row from the block partials of the step (fixed order)
+__global__ void __launch_bounds__(1024) k_amr_reduce(const double* __restrict__ part, int nblk,
+                                                    double* __restrict__ row) {
+  __shared__ double lds[16][4];
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int t = threadIdx.x; t < nblk; t += blockDim.x)
+    for (int q = 0; q < 4; ++q) a[q] += part[4 * (size_t)t + q];
+  for (int q = 0; q < 4; ++q) a[q] = wsum(a[q]);
+  const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0)
-    for (int q = 0; q < 3; ++q) lds[threadIdx.x >> 6][q] = a[q];
+    for (int q = 0; q < 4; ++q) lds[wave][q] = a[q];
   __syncthreads();
-  if (threadIdx.x < 3) row[threadIdx.x] = ((lds[0][threadIdx.x] + lds[1][threadIdx.x]) + lds[2][threadIdx.x]) +
-                                          lds[3][threadIdx.x];
+  if (threadIdx.x < 4) {
+    double r = 0.0;
+    for (int v = 0; v < 16; ++v) r += lds[v][threadIdx.x];
+    row[threadIdx.x] = r;
+  }
 }
 
 AmrArgs amr_args(cc_ctx* ctx, const double* in, double* out) {
   AmrArgs A;
   A.in = in; A.out = out; A.G = ctx->a3;
-  A.mom = ctx->s.mom; A.fslot = ctx->s.fslot;
+  A.mom = ctx->s.mom; A.part = ctx->s.mpart;
+  A.per_simple = ((ctx->a3.nsimple + 3) / 4 + 7) / 8;
+  A.per = ((ctx->a3.nreg - ctx->a3.nsimple + 3) / 4 + 7) / 8;
+  A.per_irr = ((ctx->a3.ncv - ctx->a3.nreg + 3) / 4 + 7) / 8;
   A.vmin = ctx->cfg.vmin; A.dv = ctx->dv; A.w = ctx->dv * ctx->dv * ctx->dv;
   A.dt = ctx->dt;
   A.tau_coef = ctx->cfg.kn > 0.0 ? sqrt(M_PI) / 2.0 * ctx->cfg.kn * ctx->cfg.lref / sqrt(2.0) : 0.0;
@@ -505,13 +640,15 @@ AmrArgs amr_args(cc_ctx* ctx, const double* in, double* out) {
 
 typedef void (*amr_fn)(AmrArgs);
 
-bool pick_amr(int N, amr_fn* step, amr_fn* mom) {
+struct AmrFns { amr_fn simple, reg, irr, mom; };
+
+bool pick_amr(int N, AmrFns* f) {
   switch (N) {
-    case 4: *step = k_amr_step<4>; *mom = k_amr_mom<4>; return true;
-    case 6: *step = k_amr_step<6>; *mom = k_amr_mom<6>; return true;
-    case 8: *step = k_amr_step<8>; *mom = k_amr_mom<8>; return true;
-    case 12: *step = k_amr_step<12>; *mom = k_amr_mom<12>; return true;
-    case 16: *step = k_amr_step<16>; *mom = k_amr_mom<16>; return true;
+    case 4: *f = {k_amr_simple<4>, k_amr_step<4, false>, k_amr_step<4, true>, k_amr_mom<4>}; return true;
+    case 6: *f = {k_amr_simple<6>, k_amr_step<6, false>, k_amr_step<6, true>, k_amr_mom<6>}; return true;
+    case 8: *f = {k_amr_simple<8>, k_amr_step<8, false>, k_amr_step<8, true>, k_amr_mom<8>}; return true;
+    case 12: *f = {k_amr_simple<12>, k_amr_step<12, false>, k_amr_step<12, true>, k_amr_mom<12>}; return true;
+    case 16: *f = {k_amr_simple<16>, k_amr_step<16, false>, k_amr_step<16, true>, k_amr_mom<16>}; return true;
     default: return false;
   }
 }
@@ -541,30 +678,54 @@ hipError_t launch_amr_merge(cc_ctx* ctx) {
 }
 
 hipError_t launch_amr_moments(cc_ctx* ctx) {
-  amr_fn step, mom;
-  if (!pick_amr(ctx->N, &step, &mom)) return hipErrorNotSupported;
+  AmrFns f;
+  if (!pick_amr(ctx->N, &f)) return hipErrorNotSupported;
   const double* cur = (const double*)ctx->state[ctx->cur];
-  mom<<<(ctx->a3.ncv + 3) / 4, 256, 0, ctx->stream>>>(amr_args(ctx, cur, nullptr));
+  f.mom<<<(ctx->a3.ncv + 3) / 4, 256, 0, ctx->stream>>>(amr_args(ctx, cur, nullptr));
   return hipGetLastError();
 }
 
 // one step state[cur] -> state[1-cur]; row (nullable) = force and mass of
 // the state entering the step
 hipError_t launch_amr_step(cc_ctx* ctx, double* row) {
-  amr_fn step, mom;
-  if (!pick_amr(ctx->N, &step, &mom)) return hipErrorNotSupported;
+  AmrFns f;
+  if (!pick_amr(ctx->N, &f)) return hipErrorNotSupported;
   const double* in = (const double*)ctx->state[ctx->cur];
   double* out = (double*)ctx->state[1 - ctx->cur];
-  if (row) k_amr_mass<<<1, 256, 0, ctx->stream>>>(ctx->a3, ctx->s.mom, row);
+  const AmrArgs A = amr_args(ctx, in, out);
+  // the few cut control volumes (too few waves to hide their latency on
+  // their own) run on a side stream, overlapped with the streaming kernels
+  const bool overlap = A.per_irr > 0 && ctx->side && !ctx->prof.on;
+  hipError_t e = hipSuccess;
+  if (overlap) {
+    e = hipEventRecord(ctx->fork, ctx->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->fork, 0);
+    if (e != hipSuccess) return e;
+    f.irr<<<A.per_irr * 8, 256, 0, ctx->side>>>(A);
+    e = hipEventRecord(ctx->join, ctx->side);
+    if (e != hipSuccess) return e;
+  } else if (A.per_irr > 0) {
+    prof_begin(ctx, 1);
+    f.irr<<<A.per_irr * 8, 256, 0, ctx->stream>>>(A);
+    prof_end(ctx, 1);
+  }
   prof_begin(ctx, 0);
-  step<<<(ctx->a3.ncv + 3) / 4, 256, 0, ctx->stream>>>(amr_args(ctx, in, out));
+  if (A.per_simple > 0) f.simple<<<A.per_simple * 8, 256, 0, ctx->stream>>>(A);
+  if (A.per > 0) f.reg<<<A.per * 8, 256, 0, ctx->stream>>>(A);
   prof_end(ctx, 0);
+  if (overlap) {
+    e = hipStreamWaitEvent(ctx->stream, ctx->join, 0);
+    if (e != hipSuccess) return e;
+  }
   if (row) {
     prof_begin(ctx, 2);
-    k_amr_force<<<1, 256, 0, ctx->stream>>>(ctx->a3, ctx->s.fslot, row);
+    // blocks past the last control volume of each kind return at once and
+    // write nothing: the partials are the first ceil(n_kind / 4) of each kind
+    const int ns = ctx->a3.nsimple, nr = ctx->a3.nreg - ns, ni = ctx->a3.ncv - ctx->a3.nreg;
+    k_amr_reduce<<<1, 1024, 0, ctx->stream>>>(ctx->s.mpart, (ns + 3) / 4 + (nr + 3) / 4 + (ni + 3) / 4, row);
     prof_end(ctx, 2);
   }
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   ctx->cur = 1 - ctx->cur;
   ctx->nstep += 1;
