@@ -324,32 +324,42 @@ __device__ inline void write_record(double* mom, const int* mem, int nm, const d
 }
 
 // IRR = false: control volumes [nsimple, nreg) (one member, no wall face,
-// a finer neighbour on some face); IRR = true: [nreg, ncv) (cut or merged)
+// a finer neighbour on some face); IRR = true: [nreg, ncv) (cut or merged).
+// These are few, so each gets a 256-thread block (one wave each would leave
+// most of the GPU waiting on memory); the four waves split the velocities.
 template <int N, bool IRR>
 __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
   constexpr int NV = N * N * N;
-  constexpr int R = (NV + kWaveA - 1) / kWaveA;     // velocities per lane
+  constexpr int NT = 256;
+  constexpr int R = (NV + NT - 1) / NT;                      // velocities per thread
   constexpr int RC = R < CCDVM_AMR_RC ? R : CCDVM_AMR_RC;   // per pass
   constexpr int NP = (R + RC - 1) / RC;
-  __shared__ double lds[4][4];
+  __shared__ double lds[4][2];
   // XCD-aware order: block b runs on XCD b % 8, and the blocks of one XCD
   // take a contiguous range of control volumes (neighbours in Z-order share
   // that XCD's L2)
   const int per = IRR ? A.per_irr : A.per;
   const int w0 = IRR ? A.G.nreg : A.G.nsimple, ncv = IRR ? A.G.ncv - A.G.nreg : A.G.nreg - A.G.nsimple;
   const int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int w = w0 + blk * 4 + wave;
-  if (blk * 4 >= ncv) return;    // uniform over the block
-  const bool live = w < w0 + ncv;
+  if (blk >= ncv) return;    // uniform over the block
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const AmrDev& G = A.G;
-  const int m = live ? G.cv[w] : 0, b = live ? G.cvptr[w] : 0, nm = live ? G.cvptr[w + 1] - b : 0;
+  const int w = w0 + blk;
+  const int m = G.cv[w], b = G.cvptr[w], nm = G.cvptr[w + 1] - b;
   const double* rec = A.mom + 8 * (size_t)m;
   const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4], dtau = rec[5];
-  const double mass_n = live ? G.vcv[m] * rec[6] : 0.0;   // before the record is overwritten
+  const double mass_n = G.vcv[m] * rec[6];   // before the record is overwritten
   const double dtV = A.dt / G.vcv[m];
   const double* own = A.in + (size_t)m * NV;
-  double tx = 0.0, ty = 0.0, tz = 0.0;
+  // block sum (waves added in order); every thread gets the total
+  auto bsum = [&](double v) {
+    v = wsum(v);
+    __syncthreads();
+    if (lane == 0) lds[wave][0] = v;
+    __syncthreads();
+    return ((lds[0][0] + lds[1][0]) + lds[2][0]) + lds[3][0];
+  };
+  double tx = 0.0, ty = 0.0, tz = 0.0;   // per-axis factors of the Maxwellian, in every wave
   if (lane < N) {
     const double v = vnodeA(A.vmin, A.dv, lane);
     tx = exp(-(v - ux) * (v - ux) * inv2T);
@@ -367,28 +377,28 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
     any_wall = true;
     const double n0 = G.nw[3 * k], n1 = G.nw[3 * k + 1], n2 = G.nw[3 * k + 2];
     double num = 0.0, den = 0.0;
-    for (int p = lane; p < NV; p += kWaveA) {
+    for (int p = tid; p < NV; p += NT) {
       const double vx = vnodeA(A.vmin, A.dv, p % N), vy = vnodeA(A.vmin, A.dv, (p / N) % N),
                    vz = vnodeA(A.vmin, A.dv, p / (N * N));
       const double cn = vx * n0 + vy * n1 + vz * n2;
       if (cn > 0.0) num += cn * own[p];
       else if (cn < 0.0) den += cn * cw * exp(-(vx * vx + vy * vy + vz * vz) * i2Tw);
     }
-    num = wsum(num);
-    den = wsum(den);
+    num = bsum(num);
+    den = bsum(den);
     phiw[t] = den != 0.0 ? -num / den : 0.0;
   }
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  for (int pass = 0; pass < (live ? NP : 0); ++pass) {
-    // the lane id is laundered per pass so that the velocity constants of a
-    // pass are recomputed where used instead of being held across passes
-    int lv = lane;
+  for (int pass = 0; pass < NP; ++pass) {
+    // the thread id is laundered per pass so that the velocity constants of
+    // a pass are recomputed where used instead of being held across passes
+    int lv = tid;
     asm volatile("" : "+v"(lv));
     double fo[RC], acc[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
-      const int p = (pass * RC + r) * kWaveA + lv;
+      const int p = (pass * RC + r) * NT + lv;
       fo[r] = p < NV ? own[p] : 0.0;
       acc[r] = 0.0;
     }
@@ -399,11 +409,11 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
         const double area = G.farea[e];
         const double* nrow = nb >= 0 ? A.in + (size_t)nb * NV : G.ghost;
         const double sg = (dir & 1) ? 1.0 : -1.0;
-        // the face's axis is uniform over the wave: one loop per axis
+        // the face's axis is uniform over the block: one loop per axis
         auto gather = [&](auto comp) {
 #pragma unroll
           for (int r = 0; r < RC; ++r) {
-            const int p = (pass * RC + r) * kWaveA + lv;
+            const int p = (pass * RC + r) * NT + lv;
             const double c = sg * vnodeA(A.vmin, A.dv, comp(p));   // outward normal velocity
             const double fn = c < 0.0 && p < NV ? nrow[p] : 0.0;
             acc[r] += area * (fmax(c, 0.0) * fo[r] + fmin(c, 0.0) * fn);
@@ -419,7 +429,7 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
         const double awk = G.aw[k], n0 = G.nw[3 * k], n1 = G.nw[3 * k + 1], n2 = G.nw[3 * k + 2];
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
-          const int p = (pass * RC + r) * kWaveA + lv;
+          const int p = (pass * RC + r) * NT + lv;
           if (p >= NV) continue;
           const double vx = vnodeA(A.vmin, A.dv, p % N), vy = vnodeA(A.vmin, A.dv, (p / N) % N),
                        vz = vnodeA(A.vmin, A.dv, p / (N * N));
@@ -433,7 +443,7 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
     }
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
-      const int p = (pass * RC + r) * kWaveA + lv;
+      const int p = (pass * RC + r) * NT + lv;
       if (p >= NV) continue;
       const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
       const double E = Am * __shfl(tx, p1, kWaveA) * __shfl(ty, p2, kWaveA) * __shfl(tz, p3, kWaveA);
@@ -449,18 +459,17 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
     }
   }
 #pragma unroll
-  for (int q = 0; q < 5; ++q) s[q] = wsum(s[q]);
-  if (IRR && any_wall) { fx = wsum(fx); fy = wsum(fy); fz = wsum(fz); }
-  if (lane == 0) {
-    if (live) write_record(A.mom, G.cvmem + b, nm, s, A.w, A.dt, A.tau_coef);
-    lds[wave][0] = fx * A.w; lds[wave][1] = fy * A.w; lds[wave][2] = fz * A.w; lds[wave][3] = mass_n;
+  for (int q = 0; q < 5; ++q) s[q] = bsum(s[q]);
+  if (IRR && any_wall) { fx = bsum(fx); fy = bsum(fy); fz = bsum(fz); }
+  if (tid == 0) {
+    write_record(A.mom, G.cvmem + b, nm, s, A.w, A.dt, A.tau_coef);
+    // partials after the streaming kernel's blocks: one per control volume
+    const size_t slot = (size_t)(A.G.nsimple + 3) / 4 + (IRR ? A.G.nreg - A.G.nsimple : 0) + blk;
+    A.part[4 * slot + 0] = IRR ? fx * A.w : 0.0;
+    A.part[4 * slot + 1] = IRR ? fy * A.w : 0.0;
+    A.part[4 * slot + 2] = IRR ? fz * A.w : 0.0;
+    A.part[4 * slot + 3] = mass_n;
   }
-  __syncthreads();
-  // block partials of the force and mass of t^n, in wave order (regular
-  // blocks first, then the others)
-  if (threadIdx.x < 4)
-    A.part[4 * ((size_t)blk + (A.G.nsimple + 3) / 4 + (IRR ? (A.G.nreg - A.G.nsimple + 3) / 4 : 0)) + threadIdx.x] =
-        ((lds[0][threadIdx.x] + lds[1][threadIdx.x]) + lds[2][threadIdx.x]) + lds[3][threadIdx.x];
 }
 
 // Control volumes [0, nsimple): gas leaves with one neighbour (or the
@@ -629,8 +638,8 @@ AmrArgs amr_args(cc_ctx* ctx, const double* in, double* out) {
   A.in = in; A.out = out; A.G = ctx->a3;
   A.mom = ctx->s.mom; A.part = ctx->s.mpart;
   A.per_simple = ((ctx->a3.nsimple + 3) / 4 + 7) / 8;
-  A.per = ((ctx->a3.nreg - ctx->a3.nsimple + 3) / 4 + 7) / 8;
-  A.per_irr = ((ctx->a3.ncv - ctx->a3.nreg + 3) / 4 + 7) / 8;
+  A.per = (ctx->a3.nreg - ctx->a3.nsimple + 7) / 8;      // one block per control volume
+  A.per_irr = (ctx->a3.ncv - ctx->a3.nreg + 7) / 8;
   A.vmin = ctx->cfg.vmin; A.dv = ctx->dv; A.w = ctx->dv * ctx->dv * ctx->dv;
   A.dt = ctx->dt;
   A.tau_coef = ctx->cfg.kn > 0.0 ? sqrt(M_PI) / 2.0 * ctx->cfg.kn * ctx->cfg.lref / sqrt(2.0) : 0.0;
@@ -720,9 +729,10 @@ hipError_t launch_amr_step(cc_ctx* ctx, double* row) {
   if (row) {
     prof_begin(ctx, 2);
     // blocks past the last control volume of each kind return at once and
-    // write nothing: the partials are the first ceil(n_kind / 4) of each kind
+    // write nothing: the partials are ceil(n_simple / 4) blocks of the
+    // streaming kernel, then one per other control volume
     const int ns = ctx->a3.nsimple, nr = ctx->a3.nreg - ns, ni = ctx->a3.ncv - ctx->a3.nreg;
-    k_amr_reduce<<<1, 1024, 0, ctx->stream>>>(ctx->s.mpart, (ns + 3) / 4 + (nr + 3) / 4 + (ni + 3) / 4, row);
+    k_amr_reduce<<<1, 1024, 0, ctx->stream>>>(ctx->s.mpart, (ns + 3) / 4 + nr + ni, row);
     prof_end(ctx, 2);
   }
   e = hipGetLastError();
