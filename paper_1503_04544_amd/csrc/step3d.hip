@@ -967,7 +967,7 @@ __global__ void __launch_bounds__(256) k_mass3d(Geo3D G, const double* __restric
 // (chunk slot 0, the other slots zero).  One wave per cell; the separable
 // Maxwellian is tabulated per axis in the first N lanes when the velocity
 // count is a multiple of the wave.
-template <bool SK>
+template <int N, bool SK>
 __global__ void __launch_bounds__(256) k_relax3d(Geo3D G, double* __restrict__ st,
                                                 const double* __restrict__ mom,
                                                 const double* __restrict__ heat,
@@ -979,7 +979,7 @@ __global__ void __launch_bounds__(256) k_relax3d(Geo3D G, double* __restrict__ s
   if (c >= G.ncell) return;
   const int m = G.master[c];
   if (m < 0) return;
-  const int N = G.N, nvel = G.nvel;
+  constexpr int nvel = N * N * N;
   const double* rec = mom + 8 * (size_t)m;
   const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4], nu = rec[5];
   const double* qt = SK ? heat + 3 * (size_t)m : nullptr;
@@ -991,23 +991,36 @@ __global__ void __launch_bounds__(256) k_relax3d(Geo3D G, double* __restrict__ s
     ty = exp(-(v - uy) * (v - uy) * inv2T);
     tz = exp(-(v - uz) * (v - uz) * inv2T);
   }
-  const bool tables = nvel % kWave == 0;
+  constexpr bool tables = nvel % kWave == 0;
   double* row = st + (size_t)c * nvel;
   Sums3<SK> sm;
-  for (int p = lane; p < nvel; p += kWave) {
-    const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
-    const double vx = vnode3(vmin, dv, p1), vy = vnode3(vmin, dv, p2), vz = vnode3(vmin, dv, p3);
-    double E;
-    if (tables) {
-      E = Am * __shfl(tx, p1, kWave) * __shfl(ty, p2, kWave) * __shfl(tz, p3, kWave);
-    } else {
-      const double cx = vx - ux, cy = vy - uy, cz = vz - uz;
-      E = Am * exp(-(cx * cx + cy * cy + cz * cz) * inv2T);
+  // eight independent loads per lane in flight, then their updates
+  constexpr int B = 8;
+  for (int p0 = 0; p0 < nvel; p0 += B * kWave) {
+    double fv[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int p = p0 + u * kWave + lane;
+      fv[u] = p < nvel ? row[p] : 0.0;
     }
-    if (SK) E = shakhov3(qt, 2.0 * inv2T, vx - ux, vy - uy, vz - uz, E);
-    const double fn = (row[p] + nu * E) * sc;
-    row[p] = fn;
-    sm.add(vx, vy, vz, fn);
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int p = p0 + u * kWave + lane;
+      if (p >= nvel) continue;
+      const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
+      const double vx = vnode3(vmin, dv, p1), vy = vnode3(vmin, dv, p2), vz = vnode3(vmin, dv, p3);
+      double E;
+      if (tables) {
+        E = Am * __shfl(tx, p1, kWave) * __shfl(ty, p2, kWave) * __shfl(tz, p3, kWave);
+      } else {
+        const double cx = vx - ux, cy = vy - uy, cz = vz - uz;
+        E = Am * exp(-(cx * cx + cy * cy + cz * cz) * inv2T);
+      }
+      if (SK) E = shakhov3(qt, 2.0 * inv2T, vx - ux, vy - uy, vz - uz, E);
+      const double fn = (fv[u] + nu * E) * sc;
+      __builtin_nontemporal_store(fn, &row[p]);
+      sm.add(vx, vy, vz, fn);
+    }
   }
   if (c != m) return;
   sm.reduce([](double x) { return wave_sum3(x); });
@@ -1215,7 +1228,15 @@ hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
     e = run_mom3d(ctx, 2);
     if (e != hipSuccess) return e;
     prof_begin(ctx, 5);
-    auto rfn = ctx->cfg.model == CC_MODEL_SHAKHOV ? k_relax3d<true> : k_relax3d<false>;
+    const bool sk = ctx->cfg.model == CC_MODEL_SHAKHOV;
+    decltype(&k_relax3d<16, false>) rfn = nullptr;
+    switch (ctx->N) {
+      case 4: rfn = sk ? k_relax3d<4, true> : k_relax3d<4, false>; break;
+      case 6: rfn = sk ? k_relax3d<6, true> : k_relax3d<6, false>; break;
+      case 8: rfn = sk ? k_relax3d<8, true> : k_relax3d<8, false>; break;
+      case 12: rfn = sk ? k_relax3d<12, true> : k_relax3d<12, false>; break;
+      default: rfn = sk ? k_relax3d<16, true> : k_relax3d<16, false>; break;
+    }
     rfn<<<(ctx->ncell + 3) / 4, 256, 0, ctx->stream>>>(ctx->g3, out, ctx->s.mom, ctx->s.heat, ctx->s.part,
                                                        chunks3d(ctx->N), ctx->cfg.vmin, ctx->dv);
     prof_end(ctx, 5);
