@@ -240,7 +240,8 @@ hipError_t launch_store_state_2d(const cc_ctx* ctx, double* f, double* g);
 hipError_t launch_merge_2d(cc_ctx* ctx);
 hipError_t launch_moments_all_2d(cc_ctx* ctx);
 hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_force_row,
-                                double* cur_mass_row, bool record, bool relax = true);
+                                double* cur_mass_row, bool record, bool relax = true,
+                                bool implicit = false);
 hipError_t launch_step_2d_flush(cc_ctx* ctx, double* force_row, double* mass_row);
 hipError_t launch_mass_2d(cc_ctx* ctx, double* mass_row);
 hipError_t launch_moments_out_2d(cc_ctx* ctx, double* out);

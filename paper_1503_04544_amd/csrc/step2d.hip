@@ -50,6 +50,7 @@ struct StepParams {
   int moving;
   int write_state;        // 0: cut-cell kernel only computes the wall forces
   int shakhov;            // relaxation toward the Shakhov equilibria (eq. ShakhovDD)
+  int implicit;           // semi-implicit step: the cut-cell kernel transports only
   double sk_coef;         // (1 - Pr)/5
 };
 
@@ -168,7 +169,7 @@ __device__ void cut_cv(const Geo2D& G, const double2* __restrict__ in, double2* 
   const int N = G.N, nvel = G.nvel, nx = G.nx, ny = G.ny;
   const double rho = mom[4 * m + 0], ux = mom[4 * m + 1], uy = mom[4 * m + 2], T = mom[4 * m + 3];
   const double inv2T = 0.5 / T, A = rho / (2.0 * M_PI * T);
-  const double dtau = P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
+  const double dtau = P.tau_coef > 0.0 && !P.implicit ? P.dt * rho / P.tau_coef : 0.0;
   const double qx = SK ? heat[2 * m] : 0.0, qy = SK ? heat[2 * m + 1] : 0.0;
   const double ska = SK ? P.sk_coef / (rho * T * T) : 0.0;
   const double S = G.scv[m];
@@ -318,11 +319,16 @@ constexpr int kListBlocks = 512;   // grid of kernels that walk a list whose len
 #ifndef CCDVM_SK_REGS
 #define CCDVM_SK_REGS 40
 #endif
+// VGPRs per chunk the semi-implicit variant needs beyond the explicit one
+// (it holds the transported row until its relaxation)
+#ifndef CCDVM_IM_REGS
+#define CCDVM_IM_REGS 8
+#endif
 // Chunks loaded ahead of the one computed.  Each chunk in flight costs 16
 // VGPRs and the row window 8 per chunk; the depth is capped so that a wave
 // stays within 256 VGPRs (2 waves per SIMD) without spilling.
-constexpr int prefetch_depth(int nch, bool sk = false) {
-  int cap = (138 - (sk ? CCDVM_SK_REGS : 0) - 8 * nch) / 16;
+constexpr int prefetch_depth(int nch, bool sk = false, bool im = false) {
+  int cap = (138 - (sk ? CCDVM_SK_REGS : 0) - (im ? CCDVM_IM_REGS * nch : 0) - 8 * nch) / 16;
   int d = CCDVM_PREFETCH < cap ? CCDVM_PREFETCH : cap;
   d = d < 1 ? 1 : d;
   return d < nch - 1 ? d : (nch - 1 > 0 ? nch - 1 : 0);
@@ -410,7 +416,12 @@ __host__ __device__ inline TileArgs tile_args(const Geo2D& G, const FusedArgs& A
 // row earlier (as the y-upwind of the row below), so its lines have left L2
 // by the time the neighbours need them.  (The upper half is loaded by its
 // owner in the same row and comes through L2.)
-template <int NCH, bool SK>
+// IM: semi-implicit step (ImpSchemeDD, direct equilibrium).  The row's
+// transported value is written as usual, its moments give the equilibrium,
+// and the wave then reads the value back (its lines are still in L2),
+// relaxes it implicitly with dt/tau of the state entering the step, writes
+// it and sums the moments of the result.
+template <int NCH, bool SK, bool IM = false>
 __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, double* lds,
                              d2v* xlo = nullptr) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -427,11 +438,28 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
   if (i < nx && j0 < j1) {
     const double S = Ta.dx * Ta.dy;
     const double cxf = P.dt / S * Ta.dy, cyf = P.dt / S * Ta.dx;
-    d2v prevU[NCH], curL[NCH];
+    // IM: the lower halves live only in LDS, in two buffers (this row's,
+    // read by the wave and its x-neighbours; the next row's, written as it
+    // is loaded), which frees the registers for the transported row
+    d2v prevU[NCH], curL[IM ? 1 : NCH];
     load_half<NCH>(prevU, j0 > 0 ? in + (size_t)((j0 - 1) * nx + i) * nvel : ghost, lo_n, hi_n, lane);
-    load_half<NCH>(curL, in + (size_t)(j0 * nx + i) * nvel, 0, lo_n, lane);
+    if constexpr (IM) {
+      const d2v* r0 = in + (size_t)(j0 * nx + i) * nvel;
+#pragma unroll
+      for (int k = 0; k < NCH; ++k)
+        xlo[(wave * NCH + k) * kWave + lane] = k * 64 + lane < lo_n ? r0[k * 64 + lane] : d2v{0.0, 0.0};
+    } else {
+      load_half<NCH>(curL, in + (size_t)(j0 * nx + i) * nvel, 0, lo_n, lane);
+    }
     for (int j = j0; j < j1; ++j) {
-      if (xlo) {
+      d2v* xcur = xlo;
+      d2v* xnext = xlo;
+      if constexpr (IM) {
+        __syncthreads();   // row j's lower halves are complete, row j-1's are no longer read
+        const int par = (j - j0) & 1;
+        xcur = xlo + par * (kTileW * NCH * kWave);
+        xnext = xlo + (1 - par) * (kTileW * NCH * kWave);
+      } else if (xlo) {
         __syncthreads();   // every wave is done with the previous row's halves
 #pragma unroll
         for (int k = 0; k < NCH; ++k) xlo[(wave * NCH + k) * kWave + lane] = curL[k];
@@ -441,7 +469,7 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
       const d2v* row = in + (size_t)c * nvel;
       const d2v* nrow = j + 1 < ny ? row + (size_t)nx * nvel : ghost;
       const bool reg = Ta.kind[c] == KIND_REGULAR;   // uniform over the wave
-      double Am = 0.0, T = 1.0, dtau = 0.0, tx = 0.0, ty = 0.0;
+      double Am = 0.0, T = 1.0, dtau = 0.0, tx = 0.0, ty = 0.0, nu = 0.0;
       double ux = 0.0, uy = 0.0, qx = 0.0, qy = 0.0, ska = 0.0, invT = 1.0;   // SK only
       if (reg) {
         const double* mc = Ta.mom + 4 * c;
@@ -450,13 +478,14 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
         T = mc[3];
         const double inv2T = 0.5 / T;
         Am = rho / (2.0 * M_PI * T);
-        dtau = P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
+        dtau = P.tau_coef > 0.0 && !IM ? P.dt * rho / P.tau_coef : 0.0;
+        nu = IM && P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
         if (SK) {
           qx = Ta.heat[2 * c]; qy = Ta.heat[2 * c + 1];
           ska = P.sk_coef / (rho * T * T);
           invT = 1.0 / T;
         }
-        if (lane < N) {
+        if (!IM && lane < N) {
           const double v = vnode(P.vmin, P.dv, lane);
           tx = exp(-(v - ux) * (v - ux) * inv2T);
           ty = exp(-(v - uy) * (v - uy) * inv2T);
@@ -474,8 +503,9 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
       // across the row loop, which would cost ~10 VGPRs per chunk.
       int lv = lane;
       asm volatile("" : "+v"(lv));
-      constexpr int PD = prefetch_depth(NCH, SK);
+      constexpr int PD = prefetch_depth(NCH, SK, IM);
       d2v bN[NCH], bU[NCH], bXa[NCH], bXb[NCH];
+      d2v fsL[IM ? NCH : 1], fsU[IM ? NCH : 1];   // IM: the transported row
       // lanes whose x-upwind cell is another wave of this tile read its
       // lower half from xlo (v_x > 0: the wave to the left)
       auto xwave = [&](int k) {
@@ -500,7 +530,7 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
         const int o = k * 64 + lv;
         const int xw = xwave(k);
         const d2v nL = bN[k], cU = bU[k], xb = bXb[k];
-        const d2v xa = xw >= 0 && o < lo_n ? xlo[(xw * NCH + k) * kWave + lv] : bXa[k];
+        const d2v xa = xw >= 0 && o < lo_n ? xcur[(xw * NCH + k) * kWave + lv] : bXa[k];
         if (reg) {
           const int p1 = o % N, q2 = o / N;
           const double vx = vnode(P.vmin, P.dv, p1);
@@ -511,31 +541,96 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
           if (o < lo_n) {   // lower half: v_y < 0, y-upwind is the cell above
             const double vy = vnode(P.vmin, P.dv, q2);
             const double ay = cyf * fabs(vy);
-            double E = ex * tyl, Eg = 0.5 * T * E;
-            if (SK) shakhov2(ska, qx, qy, T, invT, vx - ux, vy - uy, ex * tyl, E, Eg);
-            const d2v own = curL[k];
-            const double fn = own.x - ax * (own.x - xa.x) - ay * (own.x - nL.x) + dtau * (E - own.x);
-            const double gn = own.y - ax * (own.y - xa.y) - ay * (own.y - nL.y) + dtau * (Eg - own.y);
-            __builtin_nontemporal_store(d2v{fn, gn}, &orow[o]);
+            d2v own;
+            if constexpr (IM) own = xcur[(wave * NCH + k) * kWave + lv];
+            else own = curL[k];
+            double fn = own.x - ax * (own.x - xa.x) - ay * (own.x - nL.x);
+            double gn = own.y - ax * (own.y - xa.y) - ay * (own.y - nL.y);
+            if (!IM) {
+              double E = ex * tyl, Eg = 0.5 * T * E;
+              if (SK) shakhov2(ska, qx, qy, T, invT, vx - ux, vy - uy, ex * tyl, E, Eg);
+              fn += dtau * (E - own.x);
+              gn += dtau * (Eg - own.y);
+            }
+            if (IM) fsL[k] = d2v{fn, gn};
+            else __builtin_nontemporal_store(d2v{fn, gn}, &orow[o]);
             sm.add(vx, vy, fn, gn);
           }
           if (o < hi_n) {   // upper half: v_y >= 0, y-upwind is the cell below
             const double vy = vnode(P.vmin, P.dv, split + q2);
             const double ay = cyf * fabs(vy);
-            double E = ex * tyu, Eg = 0.5 * T * E;
-            if (SK) shakhov2(ska, qx, qy, T, invT, vx - ux, vy - uy, ex * tyu, E, Eg);
             const d2v own = cU, yu = prevU[k];
-            const double fn = own.x - ax * (own.x - xb.x) - ay * (own.x - yu.x) + dtau * (E - own.x);
-            const double gn = own.y - ax * (own.y - xb.y) - ay * (own.y - yu.y) + dtau * (Eg - own.y);
-            __builtin_nontemporal_store(d2v{fn, gn}, &orow[lo_n + o]);
+            double fn = own.x - ax * (own.x - xb.x) - ay * (own.x - yu.x);
+            double gn = own.y - ax * (own.y - xb.y) - ay * (own.y - yu.y);
+            if (!IM) {
+              double E = ex * tyu, Eg = 0.5 * T * E;
+              if (SK) shakhov2(ska, qx, qy, T, invT, vx - ux, vy - uy, ex * tyu, E, Eg);
+              fn += dtau * (E - own.x);
+              gn += dtau * (Eg - own.y);
+            }
+            if (IM) fsU[k] = d2v{fn, gn};
+            else __builtin_nontemporal_store(d2v{fn, gn}, &orow[lo_n + o]);
             sm.add(vx, vy, fn, gn);
           }
         }
         prevU[k] = cU;
-        curL[k] = nL;
+        if constexpr (IM) xnext[(wave * NCH + k) * kWave + lv] = nL;
+        else curL[k] = nL;
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (reg) {
+      if (reg && IM) {
+        // implicit relaxation toward the equilibrium of the transported row
+        sm.reduce([](double v) { return wave_sum(v); });
+        double m1[4], h1[2];
+        sm.finish(P.w, m1, h1);          // every lane: the sums are wave totals
+        const double T1 = m1[3], i2T1 = 0.5 / T1, A1 = m1[0] / (2.0 * M_PI * T1);
+        const double sk1 = SK ? P.sk_coef / (m1[0] * T1 * T1) : 0.0, iT1 = 1.0 / T1;
+        const double sc = 1.0 / (1.0 + nu);
+        double t1x = 0.0, t1y = 0.0;
+        if (lane < N) {
+          const double v = vnode(P.vmin, P.dv, lane);
+          t1x = exp(-(v - m1[1]) * (v - m1[1]) * i2T1);
+          t1y = exp(-(v - m1[2]) * (v - m1[2]) * i2T1);
+        }
+        Sums2<SK> s2;
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+          const int o = k * 64 + lv;
+          const int p1 = o % N, q2 = o / N;
+          const double vx = vnode(P.vmin, P.dv, p1);
+          const double ex = A1 * __shfl(t1x, p1, 64);
+          const double tyl = __shfl(t1y, q2 < N ? q2 : 0, 64);
+          const double tyu = __shfl(t1y, split + q2 < N ? split + q2 : 0, 64);
+          if (o < lo_n) {
+            const double vy = vnode(P.vmin, P.dv, q2);
+            double E = ex * tyl, Eg = 0.5 * T1 * E;
+            if (SK) shakhov2(sk1, h1[0], h1[1], T1, iT1, vx - m1[1], vy - m1[2], ex * tyl, E, Eg);
+            const d2v fs = fsL[k];
+            const double fn = (fs.x + nu * E) * sc, gn = (fs.y + nu * Eg) * sc;
+            __builtin_nontemporal_store(d2v{fn, gn}, &orow[o]);
+            s2.add(vx, vy, fn, gn);
+          }
+          if (o < hi_n) {
+            const double vy = vnode(P.vmin, P.dv, split + q2);
+            double E = ex * tyu, Eg = 0.5 * T1 * E;
+            if (SK) shakhov2(sk1, h1[0], h1[1], T1, iT1, vx - m1[1], vy - m1[2], ex * tyu, E, Eg);
+            const d2v fs = fsU[k];
+            const double fn = (fs.x + nu * E) * sc, gn = (fs.y + nu * Eg) * sc;
+            __builtin_nontemporal_store(d2v{fn, gn}, &orow[lo_n + o]);
+            s2.add(vx, vy, fn, gn);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        s2.reduce([](double v) { return wave_sum(v); });
+        if (lane == 0) {
+          double mo[4], hq[2];
+          s2.finish(P.w, mo, hq);
+          double* dst = Ta.mom + 4 * c;
+          dst[0] = mo[0]; dst[1] = mo[1]; dst[2] = mo[2]; dst[3] = mo[3];
+          if (SK) { Ta.heat[2 * c] = hq[0]; Ta.heat[2 * c + 1] = hq[1]; }
+        }
+        msum += S * (s2.r * P.w);
+      } else if (reg) {
         sm.reduce([](double v) { return wave_sum(v); });
         if (lane == 0) {
           double mo[4], hq[2];
@@ -549,7 +644,10 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
     }
   }
   if (xlo && !(i < nx) && j0 < j1)   // columns past the grid still take part in the row barriers
-    for (int j = j0; j < j1; ++j) { __syncthreads(); __syncthreads(); }
+    for (int j = j0; j < j1; ++j) {
+      __syncthreads();
+      if (!IM) __syncthreads();
+    }
   __syncthreads();
   if (lane == 0) lds[wave] = msum;
   __syncthreads();
@@ -557,11 +655,14 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
 }
 
 // regular-cell tiles (+ block 0: deferred reduction of the previous step)
-template <int NCH, bool SK>
-__global__ void __launch_bounds__(256) k_step2d(Geo2D G, FusedArgs A, StepParams P) {
+template <int NCH, bool SK, bool IM>
+__device__ __forceinline__ void step_tiles(const Geo2D& G, const FusedArgs& A, const StepParams& P) {
   __shared__ double lds[8];
-  constexpr bool kX = CCDVM_XLDS && NCH <= 16;   // LDS lower halves (<= 64 KB per block)
-  __shared__ d2v xlo[kX ? kTileW * NCH * kWave : 1];
+  // LDS lower halves (<= 64 KB per block); the semi-implicit variant keeps
+  // two rows of them and needs them
+  constexpr bool kX = (CCDVM_XLDS || IM) && NCH <= 16;
+  static_assert(!IM || NCH <= 8, "semi-implicit tile: at most 8 chunks per half");
+  __shared__ d2v xlo[kX ? (IM ? 2 : 1) * kTileW * NCH * kWave : 1];
   const int bid = blockIdx.x;
   if (bid < A.tile_base) {
     if (bid == 0 && A.prev_mpart) deferred_reduce(G, A, lds);
@@ -573,7 +674,23 @@ __global__ void __launch_bounds__(256) k_step2d(Geo2D G, FusedArgs A, StepParams
   const int per = A.ntiles_pad / 8;
   const int tile = (b % 8) * per + b / 8;
   if (tile >= A.ntiles) return;
-  regular_tile<NCH, SK>(tile_args(G, A), P, tile, lds, kX ? xlo : nullptr);
+  regular_tile<NCH, SK, IM>(tile_args(G, A), P, tile, lds, kX ? xlo : nullptr);
+}
+
+template <int NCH, bool SK>
+__global__ void __launch_bounds__(256) k_step2d(Geo2D G, FusedArgs A, StepParams P) {
+  step_tiles<NCH, SK, false>(G, A, P);
+}
+
+// the semi-implicit variant is held to 2 waves per SIMD (its LDS allows 2
+// blocks per CU); a few spilled registers cost less than half the waves
+#ifndef CCDVM_IM_WPE
+#define CCDVM_IM_WPE 2
+#endif
+template <int NCH, bool SK>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCDVM_IM_WPE)))
+k_step2d_im(Geo2D G, FusedArgs A, StepParams P) {
+  step_tiles<NCH, SK, true>(G, A, P);
 }
 
 // cut / merged control volumes of one step, one 256-thread block each
@@ -875,6 +992,51 @@ __global__ void __launch_bounds__(256) k_relax2d(Geo2D G, double2* __restrict__ 
   else relax_cell2d<false>(G, st, mom, nullptr, nu, mom_next, nullptr, P, c, m, lane);
 }
 
+// Semi-implicit step, last part for cut and merged control volumes when the
+// regular cells are relaxed inside the streaming kernel: the transported
+// value (the same for every member) is relaxed toward the equilibrium of the
+// control volume's transported moments and written to every member, whose
+// moments (and heat flux) are then replaced in place by those of the new
+// value.  One 256-thread block per control volume.
+template <bool SK>
+__global__ void __launch_bounds__(256) k_relax_cut2d(Geo2D G, double2* __restrict__ st,
+                                                    double* __restrict__ mom,
+                                                    double* __restrict__ heat,
+                                                    const double* __restrict__ nu, StepParams P) {
+  __shared__ double lds[8];
+  const int q = blockIdx.x;
+  const int m = G.irr[q];
+  const int b = G.mptr[q], e = G.mptr[q + 1];
+  const int N = G.N, nvel = G.nvel;
+  const double rho = mom[4 * m], ux = mom[4 * m + 1], uy = mom[4 * m + 2], T = mom[4 * m + 3];
+  const double A = rho / (2.0 * M_PI * T), inv2T = 0.5 / T, invT = 1.0 / T;
+  const double qx = SK ? heat[2 * m] : 0.0, qy = SK ? heat[2 * m + 1] : 0.0;
+  const double ska = SK ? P.sk_coef / (rho * T * T) : 0.0;
+  const double nv = nu[m], sc = 1.0 / (1.0 + nv);
+  Sums2<SK> sm;
+  for (int p = threadIdx.x; p < nvel; p += blockDim.x) {
+    const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
+    const double cx = vx - ux, cy = vy - uy;
+    double E = A * exp(-(cx * cx + cy * cy) * inv2T), Eg = 0.5 * T * E;
+    if (SK) shakhov2(ska, qx, qy, T, invT, cx, cy, E, E, Eg);
+    const double2 o = st[(size_t)m * nvel + p];
+    const double fn = (o.x + nv * E) * sc;
+    const double gn = (o.y + nv * Eg) * sc;
+    for (int t = b; t < e; ++t) st[(size_t)G.mem[t] * nvel + p] = make_double2(fn, gn);
+    sm.add(vx, vy, fn, gn);
+  }
+  sm.reduce([&](double v) { return block_sum4(v, lds); });
+  if (threadIdx.x == 0) {
+    double mo[4], hq[2];
+    sm.finish(P.w, mo, hq);
+    for (int t = b; t < e; ++t) {
+      const int k = G.mem[t];
+      for (int i = 0; i < 4; ++i) mom[4 * k + i] = mo[i];
+      if (SK) { heat[2 * k] = hq[0]; heat[2 * k + 1] = hq[1]; }
+    }
+  }
+}
+
 StepParams params2d(const cc_ctx* ctx) {
   StepParams P;
   P.vmin = ctx->cfg.vmin;
@@ -886,6 +1048,7 @@ StepParams params2d(const cc_ctx* ctx) {
   P.moving = ctx->body.motion != CC_MOTION_FIXED && ctx->body.kind != CC_BODY_NONE;
   P.write_state = 1;
   P.shakhov = ctx->cfg.model == CC_MODEL_SHAKHOV;
+  P.implicit = 0;
   P.sk_coef = (1.0 - ctx->cfg.prandtl) / 5.0;
   return P;
 }
@@ -1236,7 +1399,7 @@ __global__ void __launch_bounds__(256) k_batch_tiles2d(const BatchInst* __restri
   const int2 it = items[w];
   const int inst = __builtin_amdgcn_readfirstlane(it.x);
   const int tile = __builtin_amdgcn_readfirstlane(it.y);
-  regular_tile<NCH, false>(D[inst].T, D[inst].P, tile, lds);
+  regular_tile<NCH, false, false>(D[inst].T, D[inst].P, tile, lds);
 }
 
 __global__ void __launch_bounds__(256) k_batch_cut2d(const BatchInst* __restrict__ D,
@@ -1283,39 +1446,58 @@ batch_tiles_fn pick_batch_tiles(int nch) {
 
 typedef void (*fused_fn)(const cc_ctx*, dim3, const FusedArgs&, const StepParams&);
 
-template <int NCH, bool SK>
+template <int NCH, bool SK, bool IM>
 void launch_fused(const cc_ctx* ctx, dim3 grid, const FusedArgs& A, const StepParams& P) {
-  k_step2d<NCH, SK><<<grid, 256, 0, ctx->stream>>>(ctx->g2, A, P);
+  if constexpr (IM) k_step2d_im<NCH, SK><<<grid, 256, 0, ctx->stream>>>(ctx->g2, A, P);
+  else k_step2d<NCH, SK><<<grid, 256, 0, ctx->stream>>>(ctx->g2, A, P);
+}
+
+// fused semi-implicit variants for the velocity grids of the workloads
+// (N <= 32); larger grids take the separate relaxation pass
+template <bool SK>
+fused_fn pick_fused_im(int nch) {
+  switch (nch) {
+    case 1: return launch_fused<1, SK, true>;
+    case 2: return launch_fused<2, SK, true>;
+    case 3: return launch_fused<3, SK, true>;
+    case 4: return launch_fused<4, SK, true>;
+    case 5: return launch_fused<5, SK, true>;
+    case 6: return launch_fused<6, SK, true>;
+    case 7: return launch_fused<7, SK, true>;
+    case 8: return launch_fused<8, SK, true>;
+    default: return nullptr;
+  }
 }
 
 template <bool SK>
 fused_fn pick_fused_sk(int nch) {
   switch (nch) {
-    case 1: return launch_fused<1, SK>;
-    case 2: return launch_fused<2, SK>;
-    case 3: return launch_fused<3, SK>;
-    case 4: return launch_fused<4, SK>;
-    case 5: return launch_fused<5, SK>;
-    case 6: return launch_fused<6, SK>;
-    case 7: return launch_fused<7, SK>;
-    case 8: return launch_fused<8, SK>;
-    case 9: return launch_fused<9, SK>;
-    case 10: return launch_fused<10, SK>;
-    case 11: return launch_fused<11, SK>;
-    case 12: return launch_fused<12, SK>;
-    case 13: return launch_fused<13, SK>;
-    case 14: return launch_fused<14, SK>;
-    case 16: return launch_fused<16, SK>;
-    case 18: return launch_fused<18, SK>;
-    case 20: return launch_fused<20, SK>;
-    case 24: return launch_fused<24, SK>;
-    case 28: return launch_fused<28, SK>;
-    case 32: return launch_fused<32, SK>;
+    case 1: return launch_fused<1, SK, false>;
+    case 2: return launch_fused<2, SK, false>;
+    case 3: return launch_fused<3, SK, false>;
+    case 4: return launch_fused<4, SK, false>;
+    case 5: return launch_fused<5, SK, false>;
+    case 6: return launch_fused<6, SK, false>;
+    case 7: return launch_fused<7, SK, false>;
+    case 8: return launch_fused<8, SK, false>;
+    case 9: return launch_fused<9, SK, false>;
+    case 10: return launch_fused<10, SK, false>;
+    case 11: return launch_fused<11, SK, false>;
+    case 12: return launch_fused<12, SK, false>;
+    case 13: return launch_fused<13, SK, false>;
+    case 14: return launch_fused<14, SK, false>;
+    case 16: return launch_fused<16, SK, false>;
+    case 18: return launch_fused<18, SK, false>;
+    case 20: return launch_fused<20, SK, false>;
+    case 24: return launch_fused<24, SK, false>;
+    case 28: return launch_fused<28, SK, false>;
+    case 32: return launch_fused<32, SK, false>;
     default: return nullptr;
   }
 }
 
-fused_fn pick_fused(int nch, bool sk = false) {
+fused_fn pick_fused(int nch, bool sk = false, bool im = false) {
+  if (im) return sk ? pick_fused_im<true>(nch) : pick_fused_im<false>(nch);
   return sk ? pick_fused_sk<true>(nch) : pick_fused_sk<false>(nch);
 }
 
@@ -1407,9 +1589,31 @@ hipError_t launch_imex_step_2d(cc_ctx* ctx, double* row) {
     k_reduce2d<<<kRedBlocks, 256, 0, s>>>(ctx->g2, ctx->s.mom, ctx->s.fslot, ctx->s.red, ticket,
                                           nullptr, row + 3);
   k_imex_nu2d<<<(ctx->ncell + 255) / 256, 256, 0, s>>>(ctx->g2, ctx->s.mom, ctx->s.nu, P.dt, P.tau_coef);
+  const int par = ctx->step_parity;
+  // Direct equilibrium: the streaming kernel relaxes the regular cells right
+  // after their transport; the cut kernel only transports, and the cut and
+  // merged control volumes are relaxed afterwards.
+  if (ctx->cfg.maxwellian != CC_MAXW_CONSERVATIVE && pick_fused(chunks_per_half(ctx), P.shakhov, true)) {
+    hipError_t e = launch_step_2d_fused(ctx, false, nullptr, nullptr, false, true, true);
+    if (e != hipSuccess) return e;
+    if (row) {
+      const double* fs = ctx->s.fslot + (par ? 3 * (size_t)ctx->ncell : 0);
+      k_reduce2d<<<kRedBlocks, 256, 0, s>>>(ctx->g2, ctx->s.mom, fs, ctx->s.red, ticket, row, nullptr);
+    }
+    if (ctx->n_irr > 0) {
+      prof_begin(ctx, 5);
+      if (P.shakhov)
+        k_relax_cut2d<true><<<ctx->n_irr, 256, 0, s>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
+                                                        ctx->s.heat, ctx->s.nu, P);
+      else
+        k_relax_cut2d<false><<<ctx->n_irr, 256, 0, s>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
+                                                         nullptr, ctx->s.nu, P);
+      prof_end(ctx, 5);
+    }
+    return hipGetLastError();
+  }
   // transport: the step kernels without relaxation (the force of t^n is
   // computed by the cut kernel into this parity's slots)
-  const int par = ctx->step_parity;
   hipError_t e = launch_step_2d_fused(ctx, false, nullptr, nullptr, false, false);
   if (e != hipSuccess) return e;
   if (row) {
@@ -1460,10 +1664,11 @@ int tile_rows(const cc_ctx* ctx) {
 // diag rows; the last step's are reduced by cc_step through
 // launch_step_2d_flush.
 hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_force_row,
-                                double* cur_mass_row, bool record, bool relax) {
+                                double* cur_mass_row, bool record, bool relax, bool implicit) {
   StepParams P = params2d(ctx);
   if (!relax) P.tau_coef = 0.0;   // transport only (first half of the semi-implicit step)
-  fused_fn fn = pick_fused(chunks_per_half(ctx), P.shakhov);
+  P.implicit = implicit;          // transport, then the implicit relaxation of the regular cells
+  fused_fn fn = pick_fused(chunks_per_half(ctx), P.shakhov, implicit);
   if (!fn) return hipErrorInvalidValue;
   const int par = ctx->step_parity;
   FusedArgs A;
@@ -1493,7 +1698,7 @@ hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_forc
   A.red_force = prev_force_row;
   A.red_mass = cur_mass_row;
   dim3 grid(A.tile_base + A.ntiles_pad);
-  if (relax && ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE) {
+  if (relax && !implicit && ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE) {
     prof_begin(ctx, 4);
     k_newton2d<<<(ctx->ncell + 255) / 256, 256, 0, ctx->stream>>>(ctx->g2, ctx->s.mom, P.vmin, P.dv);
     prof_end(ctx, 4);
