@@ -21,7 +21,7 @@ import numpy as np
 
 GAMMA = 5.0 / 3.0
 
-BODY_KINDS = ("none", "circle", "ellipse", "cavity", "halfplane", "sphere")
+BODY_KINDS = ("none", "circle", "ellipse", "cavity", "halfplane", "sphere", "vane")
 MOTIONS = ("fixed", "free_rotation", "imposed")
 
 
@@ -38,9 +38,12 @@ class Body:
               axes[0], axes[1], rotated by theta) | 'cavity' (gas inside a
               circle of radius axes[0]) | 'halfplane' (gas on the side of the
               unit normal (cos theta, sin theta) through center) | 'sphere'
-              (3D, axes[0] = radius)
+              (3D, axes[0] = radius) | 'vane' (3D plate with rounded edges:
+              the points within min(axes) of the box of half-sizes
+              axes - min(axes), turned by theta about the z axis)
     motion    'fixed' | 'free_rotation' (rotation about center driven by the
-              gas torque, translation off) | 'imposed' (constant vel/omega)
+              gas torque, translation off; in 3D about the z axis) |
+              'imposed' (constant vel/omega)
     """
     kind: str = "none"
     center: Tuple[float, float, float] = (0.5, 0.5, 0.5)
@@ -142,10 +145,18 @@ def workload(name: str, kn: float | None = None) -> Config:
                       inflow=_inflow(0.5),
                       body=Body("sphere", (0.5, 0.25, 0.25), (0.1, 0.1, 0.1)),
                       steps=500, name=name, amr_depth=2)
+    if name == "vane_amr":     # 3D octree, turning vane: 32x32x16 coarse, depth 2, 8^3 velocities
+        return Config(dim=3, n=(32, 32, 16), lo=(0.0, 0.0, 0.0),
+                      hi=(1.0, 1.0, 0.5), nv=8, kn=0.1 if kn is None else kn,
+                      inflow=_inflow(0.5),
+                      body=Body("vane", (0.5, 0.5, 0.25), (0.2, 0.03, 0.12),
+                                theta=math.pi / 8, inertia=0.002, motion="free_rotation",
+                                omega=2.0),
+                      steps=500, name=name, amr_depth=2)
     raise KeyError(name)
 
 
-WORKLOADS = ("cyl32", "cyl512", "ellipse256", "sphere128", "sphere_amr")
+WORKLOADS = ("cyl32", "cyl512", "ellipse256", "sphere128", "sphere_amr", "vane_amr")
 
 BATCH_SEED = 20150316
 

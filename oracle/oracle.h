@@ -30,7 +30,7 @@ typedef struct {
   double kn, lref;         /* Knudsen number (<= 0: collisionless), length */
   double cfl, dt;          /* dt <= 0: dt from cfl */
   double inflow[5];        /* rho, ux, uy, uz, T of the farfield Maxwellian */
-  int body_kind;           /* 0 none 1 circle 2 ellipse 3 cavity 4 halfplane 5 sphere */
+  int body_kind;           /* 0 none 1 circle 2 ellipse 3 cavity 4 halfplane 5 sphere 6 vane */
   double center[3], axes[3], theta, t_wall;
   double mass, inertia;
   int motion;              /* 0 fixed 1 free rotation 2 imposed */
@@ -112,8 +112,11 @@ int  orc3d_equilibrium(const orc3d *o, const double *F, double *out);
    2.1, or the Shakhov equilibrium given there */
 void orc3d_equilibrium_values(const orc3d *o, const double *F, double *Fe);
 
-/* 3D octree mesh around a fixed body (Section 5, octree procedure):
-   leaves in Z-order; state F[leaf][p] */
+/* 3D octree mesh (Section 5, octree procedure): leaves in Z-order; state
+   F[leaf][p].  A body with motion != 0 turns about the z axis through its
+   centre (pure rotation, Section 5 steps 1-7): orc3a_step then leaves the
+   state at t^{n+1} on the mesh of t^n, orc3a_adapt rebuilds the mesh for the
+   new angle and orc3a_remap carries the state over to it. */
 typedef struct orc3a orc3a;
 int  orc3a_create(const orc_cfg *cfg, orc3a **out);
 void orc3a_destroy(orc3a *o);
@@ -130,7 +133,13 @@ void orc3a_leaves(const orc3a *o, int *lvl, int *ijk, int *type, int *master, do
 void orc3a_faces(const orc3a *o, int *fptr, int *fnb, int *fdir, double *farea);
 void orc3a_init(const orc3a *o, double *F);
 void orc3a_merge(const orc3a *o, double *F);
+/* diag = Fx, Fy, Fz, mass of F^n (fixed body) or Fx, Fy, torque about
+   the z axis, mass (turning body) */
 int  orc3a_step(orc3a *o, const double *F, double *Fo, double *diag);
+int  orc3a_adapt(orc3a *o);
+void orc3a_remap(const orc3a *o, const double *Fold, double *Fnew);
+void orc3a_body(const orc3a *o, double *out);   /* angle, angular velocity */
+double orc3a_levelset(const orc3a *o, double th, double x, double y, double z);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,7 @@ import numpy as np
 
 from . import build as _build
 
-_BODY = {"none": 0, "circle": 1, "ellipse": 2, "cavity": 3, "halfplane": 4, "sphere": 5}
+_BODY = {"none": 0, "circle": 1, "ellipse": 2, "cavity": 3, "halfplane": 4, "sphere": 5, "vane": 6}
 _MOTION = {"fixed": 0, "free_rotation": 1, "imposed": 2}
 
 
@@ -354,13 +354,19 @@ def _lib3a():
         L.orc3a_init.argtypes = [P, P]
         L.orc3a_merge.argtypes = [P, P]
         L.orc3a_step.argtypes = [P, P, P, P]
+        L.orc3a_adapt.argtypes = [P]
+        L.orc3a_remap.argtypes = [P, P, P]
+        L.orc3a_body.argtypes = [P, P]
+        L.orc3a_levelset.argtypes = [P] + [C.c_double] * 4
+        L.orc3a_levelset.restype = C.c_double
         L._has3a = True
     return L
 
 
 class Oracle3A:
-    """3D octree mesh around a fixed body (Section 5): state F of shape
-    (nleaf, N**3), leaves in Z-order."""
+    """3D octree mesh (Section 5): state F of shape (nleaf, N**3), leaves in
+    Z-order.  With a turning body the mesh follows the body: every step
+    returns the state on the mesh of the new angle (nleaf may change)."""
 
     def __init__(self, cfg):
         assert cfg.dim == 3
@@ -416,14 +422,50 @@ class Oracle3A:
         _lib3a().orc3a_merge(self._h, _p(F))
         return F
 
-    def step(self, F):
-        """One step; returns (F1, diag) with diag = (Fx, Fy, Fz, mass) of F^n."""
+    @property
+    def moving(self) -> bool:
+        return self.cfg.body.motion != "fixed" and self.cfg.body.kind != "none"
+
+    def body(self):
+        """(angle, angular velocity) of the body."""
+        out = np.zeros(2)
+        _lib3a().orc3a_body(self._h, _p(out))
+        return out
+
+    def levelset(self, th, x, y, z) -> float:
+        """Signed distance to the body turned by th (gas side positive)."""
+        return _lib3a().orc3a_levelset(self._h, th, x, y, z)
+
+    def step_on_mesh(self, F):
+        """Section 5 steps 1-7 on the current mesh (no adaptation): the state
+        at t^{n+1} on the same leaves, and diag."""
         F = np.ascontiguousarray(F, dtype=np.float64)
         Fo = np.zeros_like(F)
         d = np.zeros(4)
         st = _lib3a().orc3a_step(self._h, _p(F), _p(Fo), _p(d))
         if st != 0:
             raise OracleError(f"oracle step failed with status {st}")
+        return Fo, d
+
+    def adapt(self, F):
+        """Rebuild the mesh for the current body angle and carry F over."""
+        st = _lib3a().orc3a_adapt(self._h)
+        if st != 0:
+            raise OracleError(f"oracle mesh adaptation failed with status {st}")
+        self.nleaf = _lib3a().orc3a_nleaf(self._h)
+        self.nface = _lib3a().orc3a_nface(self._h)
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        F1 = np.zeros((self.nleaf, self.nvel))
+        _lib3a().orc3a_remap(self._h, _p(F), _p(F1))
+        return F1
+
+    def step(self, F):
+        """One step; returns (F1, diag) with diag = (Fx, Fy, Fz, mass) of F^n
+        (turning body: (Fx, Fy, torque about z, mass), and F1 on the mesh
+        adapted to the new angle)."""
+        Fo, d = self.step_on_mesh(F)
+        if self.moving:
+            Fo = self.adapt(Fo)
         return Fo, d
 
     def run(self, F, nsteps):

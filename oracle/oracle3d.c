@@ -81,10 +81,28 @@ static void face_polygon(const double *q, double h1, double h2, double *area, do
   else { *cs = 0.0; *ct = 0.0; }
 }
 
-static double levelset3(const orc_cfg *cf, double x, double y, double z) {
-  if (cf->body_kind == 5) {
-    double a = x - cf->center[0], b = y - cf->center[1], c = z - cf->center[2];
-    return sqrt(a * a + b * b + c * c) - cf->axes[0];
+/* Signed distance to the body, gas side positive (Appendix A), with the
+   body turned by th about the z axis through its centre.
+   5 sphere: radius axes[0].
+   6 vane: the points within r = min(axes) of the box of half-sizes
+     axes - r (body frame), i.e. a plate with rounded edges; the body frame
+     is the frame turned by th.  Distance to the box: the length of the
+     positive part of q = |p| - (axes - r) outside, the largest component of
+     q inside; minus r. */
+static double levelset3(const orc_cfg *cf, double th, double x, double y, double z) {
+  double a = x - cf->center[0], b = y - cf->center[1], c = z - cf->center[2];
+  if (cf->body_kind == 5) return sqrt(a * a + b * b + c * c) - cf->axes[0];
+  if (cf->body_kind == 6) {
+    double ct = cos(th), st = sin(th);
+    double p[3] = {ct * a + st * b, -st * a + ct * b, c};
+    double r = mn(cf->axes[0], mn(cf->axes[1], cf->axes[2]));
+    double q[3], out2 = 0.0, qmax = -1e300;
+    for (int d = 0; d < 3; ++d) {
+      q[d] = fabs(p[d]) - (cf->axes[d] - r);
+      out2 += mx(q[d], 0.0) * mx(q[d], 0.0);
+      qmax = mx(qmax, q[d]);
+    }
+    return sqrt(out2) + mn(qmax, 0.0) - r;
   }
   return 1.0e300;
 }
@@ -168,7 +186,7 @@ static int build3(orc3d *o) {
   for (int c = 0; c <= nz; ++c)
     for (int b = 0; b <= ny; ++b)
       for (int a = 0; a <= nx; ++a) {
-        double p = levelset3(cf, cf->lo[0] + a * o->dx, cf->lo[1] + b * o->dy, cf->lo[2] + c * o->dz);
+        double p = levelset3(cf, cf->theta, cf->lo[0] + a * o->dx, cf->lo[1] + b * o->dy, cf->lo[2] + c * o->dz);
         double s = p >= 0.0 ? 1.0 : -1.0;
         o->phi[((size_t)c * vy + b) * vx + a] = s * mx(fabs(p), eps);
       }
@@ -701,12 +719,23 @@ void orc3d_velocity(const orc3d *o, double *v) { memcpy(v, o->v, o->N * sizeof(d
    the face's gas area.  Cut cells lie at the finest depth (the band is
    wider than a cell's half-diagonal) and have the uniform grid's geometry
    there; their control volumes follow the same master search, restricted to
-   leaves of the finest depth. */
+   leaves of the finest depth.
+
+   Rotating body (Section 5, steps 1-7, pure rotation about the z axis
+   through the body centre): a step on the mesh of t^n, then the mesh is
+   rebuilt for the body at t^{n+1} (the adaptation the paper makes at the
+   start of the next iteration) and the state is carried over by
+   restriction (gas-volume weighted mean of the old leaves inside a new one)
+   or prolongation (a new leaf inside an old one takes its value). */
+typedef unsigned long long u64;
+typedef struct { u64 key; int idx; } keyidx3;
+
 struct orc3a {
   orc_cfg cfg;
   orc3d vel;                      /* velocity grid, model and dt (helpers shared with orc3d) */
   int n0[3], dmax, nleaf, nface;
   double hf[3];                   /* finest spacing */
+  double th, om;                  /* body angle about z and angular velocity */
   int *lvl, *ijk;                 /* depth and integer coordinates at that depth (3 per leaf) */
   int *type, *master, *mptr, *midx;
   int *fptr, *fnb, *fdir;
@@ -714,10 +743,12 @@ struct orc3a {
   double *S6;                     /* 6 gas face areas per leaf */
   double *vsum;                   /* sum of the 8 vertex values (centre test) */
   double *sw, *nw3, *rw3, *vbar, *vcv;
+  keyidx3 *tab;                   /* (depth, coordinates) -> leaf, sorted by key */
+  double *vbar1;                  /* leaves' gas volumes with the body at t^{n+1} (last step) */
+  int pn, *plvl, *pijk;           /* previous mesh, kept by orc3a_adapt for orc3a_remap */
+  double *pvbar;                  /* its leaves' gas volumes at the new angle */
+  keyidx3 *ptab;
 };
-
-typedef unsigned long long u64;
-typedef struct { u64 key; int idx; } keyidx3;
 
 static u64 cell_key3(int l, int i, int j, int k) {
   return ((u64)l << 60) | ((u64)i << 40) | ((u64)j << 20) | (u64)k;
@@ -749,6 +780,41 @@ static int find_leaf3(const keyidx3 *tab, int n, int l, int i, int j, int k) {
 
 void orc3a_destroy(orc3a *o);
 
+/* geometry of leaf q with the body at angle th: the 8 vertex values clamped
+   as on the uniform grid, then the uniform grid's per-cell construction at
+   the leaf's own size.  Returns 1 for a saddle face. */
+static int leaf_geom3a(const orc3a *o, double th, int q, int *type, double *S6, double *sw, double *nw,
+                       double *rw, double *vbar, double *vsum) {
+  const orc_cfg *cf = &o->cfg;
+  int l = o->lvl[q], sh = o->dmax - l;
+  int A0[3] = {o->ijk[3 * q] << sh, o->ijk[3 * q + 1] << sh, o->ijk[3 * q + 2] << sh};
+  double q8[8], h[3], eps = 1e-10 * o->hf[0];
+  for (int d = 0; d < 3; ++d) h[d] = o->hf[d] * (double)(1 << sh);
+  for (int t = 0; t < 8; ++t) {
+    int a = A0[0] + ((t & 1) << sh), b = A0[1] + (((t >> 1) & 1) << sh), c = A0[2] + (((t >> 2) & 1) << sh);
+    double p = levelset3(cf, th, cf->lo[0] + a * o->hf[0], cf->lo[1] + b * o->hf[1], cf->lo[2] + c * o->hf[2]);
+    double sg = p >= 0.0 ? 1.0 : -1.0;
+    q8[t] = sg * mx(fabs(p), eps);
+  }
+  double vs = 0.0;
+  for (int t = 0; t < 8; ++t) vs += q8[t];
+  *vsum = vs;
+  double rl[3];
+  int bad = cell_geom3(q8, h, type, S6, sw, nw, rl, vbar);
+  for (int d = 0; d < 3; ++d) rw[d] = *sw > 0.0 ? cf->lo[d] + A0[d] * o->hf[d] + rl[d] : 0.0;
+  return bad;
+}
+
+static void free_mesh3a(orc3a *o) {
+  free(o->lvl); free(o->ijk); free(o->type); free(o->master); free(o->mptr); free(o->midx);
+  free(o->fptr); free(o->fnb); free(o->fdir); free(o->farea); free(o->S6); free(o->vsum);
+  free(o->sw); free(o->nw3); free(o->rw3); free(o->vbar); free(o->vcv); free(o->tab); free(o->vbar1);
+  o->lvl = o->ijk = o->type = o->master = o->mptr = o->midx = o->fptr = o->fnb = o->fdir = NULL;
+  o->farea = o->S6 = o->vsum = o->sw = o->nw3 = o->rw3 = o->vbar = o->vcv = o->vbar1 = NULL;
+  o->tab = NULL;
+}
+
+/* the mesh for the body at angle o->th */
 static int build3a(orc3a *o) {
   const orc_cfg *cf = &o->cfg;
   int D = o->dmax;
@@ -772,7 +838,7 @@ static int build3a(orc3a *o) {
     double s = 1.0 / (double)(1 << l);
     double cx = cf->lo[0] + (i + 0.5) * h0[0] * s, cy = cf->lo[1] + (j + 0.5) * h0[1] * s,
            cz = cf->lo[2] + (k + 0.5) * h0[2] * s;
-    if (l < D && fabs(levelset3(cf, cx, cy, cz)) < band * Dx * s) {
+    if (l < D && fabs(levelset3(cf, o->th, cx, cy, cz)) < band * Dx * s) {
       for (int t = 7; t >= 0; --t) {
         if (sp == scap) { scap *= 2; st = realloc(st, (size_t)scap * 4 * sizeof(int)); }
         st[4 * sp] = l + 1;
@@ -804,43 +870,26 @@ static int build3a(orc3a *o) {
     o->ijk[3 * q] = c[1]; o->ijk[3 * q + 1] = c[2]; o->ijk[3 * q + 2] = c[3];
   }
   free(mz); free(leaf);
-  keyidx3 *tab = malloc((size_t)n * sizeof(keyidx3));
+  keyidx3 *tab = o->tab = malloc((size_t)n * sizeof(keyidx3));
   for (int q = 0; q < n; ++q) {
     tab[q].key = cell_key3(o->lvl[q], o->ijk[3 * q], o->ijk[3 * q + 1], o->ijk[3 * q + 2]);
     tab[q].idx = q;
   }
   qsort(tab, n, sizeof(keyidx3), cmp_keyidx3);
-  /* geometry: vertex values (clamped as on the uniform grid) and the
-     uniform grid's per-cell construction at the leaf's own size */
   o->type = calloc(n, sizeof(int)); o->master = calloc(n, sizeof(int));
   o->mptr = calloc(n + 1, sizeof(int)); o->midx = calloc(n, sizeof(int));
   o->S6 = calloc((size_t)n * 6, sizeof(double)); o->vsum = calloc(n, sizeof(double));
   o->sw = calloc(n, sizeof(double)); o->nw3 = calloc((size_t)n * 3, sizeof(double));
   o->rw3 = calloc((size_t)n * 3, sizeof(double));
   o->vbar = calloc(n, sizeof(double)); o->vcv = calloc(n, sizeof(double));
-  double eps = 1e-10 * o->hf[0];
   int bad = 0;
   for (int q = 0; q < n; ++q) {
-    int l = o->lvl[q], sh = D - l;
-    int A0[3] = {o->ijk[3 * q] << sh, o->ijk[3 * q + 1] << sh, o->ijk[3 * q + 2] << sh};
-    double q8[8], h[3];
-    for (int d = 0; d < 3; ++d) h[d] = o->hf[d] * (double)(1 << sh);
-    for (int t = 0; t < 8; ++t) {
-      int a = A0[0] + ((t & 1) << sh), b = A0[1] + (((t >> 1) & 1) << sh), c = A0[2] + (((t >> 2) & 1) << sh);
-      double p = levelset3(cf, cf->lo[0] + a * o->hf[0], cf->lo[1] + b * o->hf[1], cf->lo[2] + c * o->hf[2]);
-      double sg = p >= 0.0 ? 1.0 : -1.0;
-      q8[t] = sg * mx(fabs(p), eps);
-    }
-    double vs = 0.0;
-    for (int t = 0; t < 8; ++t) vs += q8[t];
-    o->vsum[q] = vs;
-    double rl[3];
     int type;
-    if (cell_geom3(q8, h, &type, o->S6 + 6 * q, &o->sw[q], o->nw3 + 3 * q, rl, &o->vbar[q])) bad = 1;
-    if (type == CUT && l < D) bad = 1;     /* a cut cell above the finest depth */
+    if (leaf_geom3a(o, o->th, q, &type, o->S6 + 6 * q, &o->sw[q], o->nw3 + 3 * q, o->rw3 + 3 * q, &o->vbar[q],
+                    &o->vsum[q]))
+      bad = 1;
+    if (type == CUT && o->lvl[q] < D) bad = 1;     /* a cut cell above the finest depth */
     o->type[q] = type;
-    if (o->sw[q] > 0.0)
-      for (int d = 0; d < 3; ++d) o->rw3[3 * q + d] = cf->lo[d] + A0[d] * o->hf[d] + rl[d];
   }
   /* faces */
   int fcap = 8 * n + 16;
@@ -919,7 +968,6 @@ static int build3a(orc3a *o) {
     }
     o->master[q] = cur;
   }
-  free(tab);
   if (bad) return -3;
   memset(o->mptr, 0, (n + 1) * sizeof(int));
   for (int c = 0; c < n; ++c) if (o->master[c] >= 0) o->mptr[o->master[c] + 1]++;
@@ -945,11 +993,14 @@ int orc3a_create(const orc_cfg *cfg, orc3a **out) {
   if (!cfg || cfg->dim != 3 || cfg->n[0] < 1 || cfg->n[1] < 1 || cfg->n[2] < 1 || cfg->nv < 1 ||
       !(cfg->vmax > cfg->vmin) || cfg->amr_depth < 0 || cfg->amr_depth > 8)
     return -1;
+  if (cfg->motion != 0 && cfg->body_kind != 0 && cfg->motion == 1 && !(cfg->inertia > 0.0)) return -1;
   for (int d = 0; d < 3; ++d)
     if (((u64)cfg->n[d] << cfg->amr_depth) >= (1ULL << 20)) return -1;
   orc3a *o = calloc(1, sizeof(orc3a));
   o->cfg = *cfg;
   o->dmax = cfg->amr_depth;
+  o->th = cfg->theta;
+  o->om = cfg->motion != 0 ? cfg->omega : 0.0;
   for (int d = 0; d < 3; ++d) {
     o->n0[d] = cfg->n[d];
     o->hf[d] = (cfg->hi[d] - cfg->lo[d]) / (double)(cfg->n[d] << o->dmax);
@@ -975,9 +1026,8 @@ int orc3a_create(const orc_cfg *cfg, orc3a **out) {
 void orc3a_destroy(orc3a *o) {
   if (!o) return;
   free(o->vel.v);
-  free(o->lvl); free(o->ijk); free(o->type); free(o->master); free(o->mptr); free(o->midx);
-  free(o->fptr); free(o->fnb); free(o->fdir); free(o->farea); free(o->S6); free(o->vsum);
-  free(o->sw); free(o->nw3); free(o->rw3); free(o->vbar); free(o->vcv);
+  free_mesh3a(o);
+  free(o->plvl); free(o->pijk); free(o->pvbar); free(o->ptab);
   free(o);
 }
 
@@ -985,6 +1035,7 @@ double orc3a_dt(const orc3a *o) { return o->vel.dt; }
 int orc3a_nleaf(const orc3a *o) { return o->nleaf; }
 int orc3a_nface(const orc3a *o) { return o->nface; }
 void orc3a_velocity(const orc3a *o, double *v) { memcpy(v, o->vel.v, o->vel.N * sizeof(double)); }
+void orc3a_body(const orc3a *o, double *out) { out[0] = o->th; out[1] = o->om; }
 
 void orc3a_leaves(const orc3a *o, int *lvl, int *ijk, int *type, int *master, double *vbar,
                   double *vcv, double *sw, double *S6) {
@@ -1077,8 +1128,209 @@ static void scheme3a(const orc3a *o, const double *Fm, int m, double *out) {
   free(R); free(fw);
 }
 
-/* one step on the octree; diag (nullable) = Fx, Fy, Fz, mass of F^n */
+/* ---- rotating body ---- */
+
+/* velocity of the wall point r of a body turning at om about the z axis
+   through its centre (step 4): om e_z x (r - centre).  READING: the printed
+   r om (sin a, cos a, 0) is taken as this rigid rotation. */
+static void wall_velocity3(const orc3a *o, const double *r, double om, double *uw) {
+  uw[0] = -om * (r[1] - o->cfg.center[1]);
+  uw[1] = om * (r[0] - o->cfg.center[0]);
+  uw[2] = 0.0;
+}
+
+/* wall value of one wall face moving with uw (step 4): incoming and
+   outgoing sets and the density from the relative velocity v - uw */
+static void wall_values3m(const orc3d *o, const double *fc, const double *nwk, const double *uw, double *fw) {
+  int nvel = o->nvel, N = o->N;
+  double Tw = o->cfg.t_wall, num = 0.0, den = 0.0;
+  for (int p = 0; p < nvel; ++p) {
+    double vx = o->v[p % N], vy = o->v[(p / N) % N], vz = o->v[p / (N * N)];
+    double cn = (vx - uw[0]) * nwk[0] + (vy - uw[1]) * nwk[1] + (vz - uw[2]) * nwk[2];
+    if (cn > 0.0) num += cn * fc[p] * o->w;
+    else if (cn < 0.0) den += cn * maxw3(1.0, uw, Tw, vx, vy, vz) * o->w;
+  }
+  double phi = den != 0.0 ? -num / den : 0.0;
+  for (int p = 0; p < nvel; ++p)
+    fw[p] = phi * maxw3(1.0, uw, Tw, o->v[p % N], o->v[(p / N) % N], o->v[p / (N * N)]);
+}
+
+/* force of one moving wall face (step 5): the relative-velocity stress
+   (v - uw) ((v - uw).n) of the wall value on incoming and of the control
+   volume's value on outgoing velocities, times the face area */
+static void wall_force3m(const orc3d *o, const double *fc, const double *nwk, const double *uw, double swk,
+                         double *Fk) {
+  int nvel = o->nvel, N = o->N;
+  double *fw = malloc(nvel * sizeof(double));
+  wall_values3m(o, fc, nwk, uw, fw);
+  double s[3] = {0, 0, 0};
+  for (int p = 0; p < nvel; ++p) {
+    double c[3] = {o->v[p % N] - uw[0], o->v[(p / N) % N] - uw[1], o->v[p / (N * N)] - uw[2]};
+    double cn = c[0] * nwk[0] + c[1] * nwk[1] + c[2] * nwk[2];
+    double fv = cn < 0.0 ? fw[p] : (cn > 0.0 ? fc[p] : 0.0);
+    for (int d = 0; d < 3; ++d) s[d] += c[d] * cn * fv * o->w;
+  }
+  for (int d = 0; d < 3; ++d) Fk[d] = s[d] * swk;
+  free(fw);
+}
+
+/* eq. (eq-schema3D) with the volume ratio V^n / V^{n+1,*} for the control
+   volume of master m of t^n (vnew = its volume with the body at t^{n+1}),
+   walls moving at om */
+static void scheme3a_moving(const orc3a *o, const double *Fm, int m, double vnew, double om, double *out) {
+  const orc3d *v = &o->vel;
+  int nvel = v->nvel, N = v->N;
+  const double *fc = Fm + (size_t)m * nvel;
+  const double *in = o->cfg.inflow;
+  double uin[3] = {in[1], in[2], in[3]};
+  double *R = calloc(nvel, sizeof(double));
+  double *fw = malloc(nvel * sizeof(double));
+  for (int q = o->mptr[m]; q < o->mptr[m + 1]; ++q) {
+    int k = o->midx[q];
+    const double *fk = Fm + (size_t)k * nvel;
+    int has_wall = o->sw[k] > 0.0;
+    double uw[3] = {0, 0, 0};
+    if (has_wall) {
+      wall_velocity3(o, o->rw3 + 3 * k, om, uw);
+      wall_values3m(v, fc, o->nw3 + 3 * k, uw, fw);
+    }
+    for (int p = 0; p < nvel; ++p) {
+      double vv[3] = {v->v[p % N], v->v[(p / N) % N], v->v[p / (N * N)]};
+      double r = 0.0;
+      for (int e = o->fptr[k]; e < o->fptr[k + 1]; ++e) {
+        double A = o->farea[e];
+        int f = o->fdir[e];
+        double c = (f & 1) ? vv[f / 2] : -vv[f / 2];
+        double fn = o->fnb[e] >= 0 ? Fm[(size_t)o->fnb[e] * nvel + p]
+                                   : maxw3(in[0], uin, in[4], vv[0], vv[1], vv[2]);
+        r += A * (mx(c, 0.0) * fk[p] + mn(c, 0.0) * fn);
+      }
+      if (has_wall) {
+        const double *nk = o->nw3 + 3 * k;
+        double cn = (vv[0] - uw[0]) * nk[0] + (vv[1] - uw[1]) * nk[1] + (vv[2] - uw[2]) * nk[2];
+        r += o->sw[k] * (mn(cn, 0.0) * fw[p] + mx(cn, 0.0) * fk[p]);
+      }
+      R[p] += r;
+    }
+  }
+  relax3 tg;
+  relax_target3(v, fc, &tg);
+  int collide = o->cfg.kn > 0.0;
+  double tau = collide ? sqrt(M_PI) / 2.0 * (1.0 / tg.rho) * o->cfg.kn * o->cfg.lref / sqrt(2.0) : 1.0;
+  double ratio = o->vcv[m] / vnew;
+  for (int p = 0; p < nvel; ++p) {
+    double E = collide ? equilibrium_at3(v, &tg, v->v[p % N], v->v[(p / N) % N], v->v[p / (N * N)]) : 0.0;
+    double fnew = ratio * fc[p] - v->dt / vnew * R[p];
+    if (collide) fnew += ratio * (v->dt / tau) * (E - fc[p]);
+    out[p] = fnew;
+  }
+  free(R); free(fw);
+}
+
+/* one step with the body turning (Section 5, steps 1-7) on the current
+   mesh: Fo is the state at t^{n+1} on the same leaves, with the geometry of
+   the body at t^{n+1}.  diag = Fx, Fy, torque about the z axis, mass of F^n. */
+static int step3a_moving(orc3a *o, const double *F, double *Fo, double *diag) {
+  const orc3d *v = &o->vel;
+  int nvel = v->nvel, n = o->nleaf, D = o->dmax;
+  size_t tot = (size_t)n * nvel;
+  /* 1. angle at t^{n+1} (pure rotation, eq. motionDD_posit) */
+  double th1 = o->th + v->dt * o->om;
+  /* 2. merge over the control volumes of t^n */
+  double *Fm = malloc(tot * sizeof(double));
+  memcpy(Fm, F, tot * sizeof(double));
+  merge3a(o, Fm);
+  /* 3. the leaves with the body at t^{n+1}: types, gas volumes, faces */
+  int *type1 = malloc(n * sizeof(int)), *target = malloc(n * sizeof(int));
+  double *vbar1 = malloc(n * sizeof(double)), *S61 = malloc((size_t)n * 6 * sizeof(double));
+  int bad = 0;
+  for (int q = 0; q < n; ++q) {
+    double sw1, nw1[3], rw1[3], vs1;
+    if (leaf_geom3a(o, th1, q, &type1[q], S61 + 6 * q, &sw1, nw1, rw1, &vbar1[q], &vs1)) bad = 1;
+    if (type1[q] == CUT && o->lvl[q] < D) bad = 1;   /* the body moved past the refined band */
+    target[q] = o->master[q];
+  }
+  /* READING (as in 2D): a leaf solid at t^n and not at t^{n+1} joins the
+     control volume of t^n reached by hopping across its largest face at
+     t^{n+1} (same depth, order x+, x-, y+, y-, z+, z-, at most 4 hops) */
+  const int order[6] = {1, 0, 3, 2, 5, 4};
+  for (int q = 0; q < n && !bad; ++q) {
+    if (!(o->type[q] == SOLID && type1[q] != SOLID)) continue;
+    int cur = q, hops = 0;
+    while (o->master[cur] < 0 && hops < 4) {
+      int l = o->lvl[cur], nb = -1;
+      double M = 0.0, L[6];
+      int nb6[6];
+      for (int u = 0; u < 6; ++u) {
+        int t = order[u], d = t >> 1;
+        int g[3] = {o->ijk[3 * cur], o->ijk[3 * cur + 1], o->ijk[3 * cur + 2]};
+        g[d] += (t & 1) ? 1 : -1;
+        nb6[u] = -1; L[u] = 0.0;
+        if (g[d] < 0 || g[d] >= (o->n0[d] << l)) continue;
+        nb6[u] = find_leaf3(o->tab, n, l, g[0], g[1], g[2]);
+        L[u] = S61[6 * cur + t];
+        M = mx(M, L[u]);
+      }
+      if (!(M > 0.0)) break;
+      double tie = M * (1.0 - 1e-12);
+      int u = 0;
+      while (L[u] < tie) ++u;
+      nb = nb6[u];
+      if (nb < 0) break;
+      cur = nb;
+      ++hops;
+    }
+    if (o->master[cur] < 0) bad = 1;
+    else target[q] = o->master[cur];
+  }
+  if (bad) { free(Fm); free(type1); free(target); free(vbar1); free(S61); return -3; }
+  double *vnew = calloc(n, sizeof(double));
+  for (int q = 0; q < n; ++q)
+    if (target[q] >= 0) vnew[target[q]] += vbar1[q];
+  /* 4-5. wall condition, force and torque at t^n */
+  double Fw[3] = {0, 0, 0}, Tz = 0.0, mass = 0.0;
+  for (int k = 0; k < n; ++k) {
+    if (!(o->sw[k] > 0.0)) continue;
+    double uw[3], Fk[3];
+    wall_velocity3(o, o->rw3 + 3 * k, o->om, uw);
+    wall_force3m(v, Fm + (size_t)o->master[k] * nvel, o->nw3 + 3 * k, uw, o->sw[k], Fk);
+    for (int d = 0; d < 3; ++d) Fw[d] += Fk[d];
+    Tz += (o->rw3[3 * k] - o->cfg.center[0]) * Fk[1] - (o->rw3[3 * k + 1] - o->cfg.center[1]) * Fk[0];
+  }
+  for (int m = 0; m < n; ++m) {
+    if (o->master[m] != m) continue;
+    double sm = 0.0;
+    for (int p = 0; p < nvel; ++p) sm += Fm[(size_t)m * nvel + p] * v->w;
+    mass += o->vcv[m] * sm;
+  }
+  if (diag) { diag[0] = Fw[0]; diag[1] = Fw[1]; diag[2] = Tz; diag[3] = mass; }
+  /* 6. scheme on every control volume of t^n */
+  double *Fcv = malloc(tot * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int m = 0; m < n; ++m) {
+    if (o->master[m] != m || !(vnew[m] > 0.0)) continue;
+    scheme3a_moving(o, Fm, m, vnew[m], o->om, Fcv + (size_t)m * nvel);
+  }
+  /* 7. redistribution to the leaves of t^{n+1} */
+  for (int q = 0; q < n; ++q) {
+    int m = target[q];
+    double *dst = Fo + (size_t)q * nvel;
+    if (m < 0 || type1[q] == SOLID || !(vnew[m] > 0.0)) memset(dst, 0, nvel * sizeof(double));
+    else memcpy(dst, Fcv + (size_t)m * nvel, nvel * sizeof(double));
+  }
+  /* body: explicit Euler, torque of t^n (free rotation) */
+  if (o->cfg.motion == 1) o->om = o->om + v->dt * Tz / o->cfg.inertia;
+  o->th = th1;
+  free(o->vbar1);
+  o->vbar1 = vbar1;
+  free(Fm); free(Fcv); free(type1); free(target); free(S61); free(vnew);
+  return 0;
+}
+
+/* one step on the octree; diag (nullable) = Fx, Fy, Fz, mass of F^n (fixed
+   body) or Fx, Fy, torque about z, mass (turning body) */
 int orc3a_step(orc3a *o, const double *F, double *Fo, double *diag) {
+  if (o->cfg.motion != 0 && o->cfg.body_kind != 0) return step3a_moving(o, F, Fo, diag);
   int nvel = o->vel.nvel, n = o->nleaf;
   size_t tot = (size_t)n * nvel;
   double *Fm = malloc(tot * sizeof(double));
@@ -1108,4 +1360,51 @@ int orc3a_step(orc3a *o, const double *F, double *Fo, double *diag) {
   }
   free(Fm);
   return 0;
+}
+
+/* Mesh adaptation (Section 5): the mesh is rebuilt for the body at its
+   current angle; the old leaves, with their gas volumes at that angle, are
+   kept for orc3a_remap. */
+int orc3a_adapt(orc3a *o) {
+  free(o->plvl); free(o->pijk); free(o->pvbar); free(o->ptab);
+  o->pn = o->nleaf;
+  o->plvl = o->lvl; o->pijk = o->ijk; o->ptab = o->tab;
+  if (o->vbar1) { o->pvbar = o->vbar1; o->vbar1 = NULL; }
+  else { o->pvbar = malloc(o->nleaf * sizeof(double)); memcpy(o->pvbar, o->vbar, o->nleaf * sizeof(double)); }
+  o->lvl = NULL; o->ijk = NULL; o->tab = NULL;
+  free_mesh3a(o);
+  return build3a(o);
+}
+
+/* The state carried from the previous mesh to the current one: a leaf that
+   is also an old leaf keeps its value; a leaf inside an old leaf takes its
+   value (prolongation, 0th order); a leaf covering old leaves takes their
+   gas-volume weighted mean, summed in old-leaf order (restriction).  Solid
+   leaves are 0. */
+void orc3a_remap(const orc3a *o, const double *Fold, double *Fnew) {
+  int nvel = o->vel.nvel;
+  for (int q = 0; q < o->nleaf; ++q) {
+    double *dst = Fnew + (size_t)q * nvel;
+    if (o->type[q] == SOLID) { memset(dst, 0, nvel * sizeof(double)); continue; }
+    int l = o->lvl[q], i = o->ijk[3 * q], j = o->ijk[3 * q + 1], k = o->ijk[3 * q + 2];
+    int src = find_leaf3(o->ptab, o->pn, l, i, j, k);
+    for (int a = l - 1; src < 0 && a >= 0; --a)
+      src = find_leaf3(o->ptab, o->pn, a, i >> (l - a), j >> (l - a), k >> (l - a));
+    if (src >= 0) { memcpy(dst, Fold + (size_t)src * nvel, nvel * sizeof(double)); continue; }
+    double W = 0.0;
+    memset(dst, 0, nvel * sizeof(double));
+    for (int r = 0; r < o->pn; ++r) {
+      int sh = o->plvl[r] - l;
+      if (sh <= 0) continue;
+      if ((o->pijk[3 * r] >> sh) != i || (o->pijk[3 * r + 1] >> sh) != j || (o->pijk[3 * r + 2] >> sh) != k) continue;
+      W += o->pvbar[r];
+      for (int p = 0; p < nvel; ++p) dst[p] += o->pvbar[r] * Fold[(size_t)r * nvel + p];
+    }
+    for (int p = 0; p < nvel; ++p) dst[p] = W > 0.0 ? dst[p] / W : 0.0;
+  }
+}
+
+/* the body's signed distance at angle th (tests) */
+double orc3a_levelset(const orc3a *o, double th, double x, double y, double z) {
+  return levelset3(&o->cfg, th, x, y, z);
 }

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libccdvm.so")
 
 CC_STATUS = {0: "CC_OK", -1: "CC_EINVAL", -2: "CC_ENOMEM", -3: "CC_EGEOM", -4: "CC_ECFL",
              -5: "CC_EHIP", -6: "CC_ESTATE", -7: "CC_ENUMERIC"}
-BODY = {"none": 0, "circle": 1, "ellipse": 2, "cavity": 3, "halfplane": 4, "sphere": 5}
+BODY = {"none": 0, "circle": 1, "ellipse": 2, "cavity": 3, "halfplane": 4, "sphere": 5, "vane": 6}
 MOTION = {"fixed": 0, "free_rotation": 1, "imposed": 2}
 
 
