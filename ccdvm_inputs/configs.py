@@ -145,9 +145,9 @@ def workload(name: str, kn: float | None = None) -> Config:
                       inflow=_inflow(0.5),
                       body=Body("sphere", (0.5, 0.25, 0.25), (0.1, 0.1, 0.1)),
                       steps=500, name=name, amr_depth=2)
-    if name == "vane_amr":     # 3D octree, turning vane: 32x32x16 coarse, depth 2, 8^3 velocities
+    if name == "vane_amr":     # 3D octree, turning vane: 32x32x16 coarse, depth 2, 16^3 velocities
         return Config(dim=3, n=(32, 32, 16), lo=(0.0, 0.0, 0.0),
-                      hi=(1.0, 1.0, 0.5), nv=8, kn=0.1 if kn is None else kn,
+                      hi=(1.0, 1.0, 0.5), nv=16, kn=0.1 if kn is None else kn,
                       inflow=_inflow(0.5),
                       body=Body("vane", (0.5, 0.5, 0.25), (0.2, 0.03, 0.12),
                                 theta=math.pi / 8, inertia=0.002, motion="free_rotation",

@@ -62,7 +62,7 @@ typedef enum {
 } cc_status;
 
 enum { CC_BODY_NONE = 0, CC_BODY_CIRCLE = 1, CC_BODY_ELLIPSE = 2,
-       CC_BODY_CAVITY = 3, CC_BODY_HALFPLANE = 4, CC_BODY_SPHERE = 5 };
+       CC_BODY_CAVITY = 3, CC_BODY_HALFPLANE = 4, CC_BODY_SPHERE = 5, CC_BODY_VANE = 6 };
 enum { CC_MOTION_FIXED = 0, CC_MOTION_FREE_ROTATION = 1, CC_MOTION_IMPOSED = 2 };
 /* Equilibrium of the relaxation term: the Maxwellian of the directly
  * computed moments (eq. MacroscopicDDv), or the conservative one of

@@ -106,24 +106,39 @@ void layout_geo3d(cc_ctx* ctx, char* base, size_t* bytes) {
   *bytes = cv.off;
 }
 
+// leaves the buffers are sized for: the mesh, or with a turning body the
+// largest mesh expected
+size_t cell_capacity(const cc_ctx* ctx) {
+  return ctx->amr_turning ? (size_t)ctx->amrh->cap_leaf : (size_t)ctx->ncell;
+}
+
 void layout_amr(cc_ctx* ctx, char* base, size_t* bytes) {
   Carver cv{base};
   const AmrHost& H = *ctx->amrh;
   AmrDev& G = ctx->a3;
-  const size_t n = H.nleaf, nf = H.nface, ncv = H.cv.size();
-  G.nleaf = (int)n; G.ncv = (int)ncv; G.nreg = H.nreg; G.nsimple = H.nsimple;
+  const bool turn = ctx->amr_turning;
+  const size_t n = turn ? H.cap_leaf : H.nleaf, nf = turn ? H.cap_face : H.nface;
+  const size_t ncv = turn ? n : H.cv.size(), nmem = turn ? n : H.cvmem.size();
+  G.nleaf = H.nleaf; G.ncv = (int)H.cv.size(); G.nreg = H.nreg; G.nsimple = H.nsimple;
   G.type = cv.take<int>(n); G.master = cv.take<int>(n);
-  G.cv = cv.take<int>(ncv); G.cvptr = cv.take<int>(ncv + 1); G.cvmem = cv.take<int>(H.cvmem.size());
+  G.cv = cv.take<int>(ncv); G.cvptr = cv.take<int>(ncv + 1); G.cvmem = cv.take<int>(nmem);
   G.fptr = cv.take<int>(n + 1); G.fnb = cv.take<int>(nf); G.fdir = cv.take<int>(nf);
   G.farea = cv.take<double>(nf); G.aw = cv.take<double>(n); G.nw = cv.take<double>(3 * n);
   G.vbar = cv.take<double>(n); G.vcv = cv.take<double>(n);
   G.ghost = cv.take<double>(ctx->nvel);
+  G.rw = turn ? cv.take<double>(3 * n) : nullptr;
+  G.vnew = turn ? cv.take<double>(n) : nullptr;
+  G.rptr = turn ? cv.take<int>(n + 1) : nullptr;
+  G.rmem = turn ? cv.take<int>(n) : nullptr;
+  G.sptr = turn ? cv.take<int>(n + 1) : nullptr;
+  G.src = turn ? cv.take<int>(2 * n) : nullptr;
+  G.wgt = turn ? cv.take<double>(2 * n) : nullptr;
   *bytes = cv.off;
 }
 
 void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
   Carver cv{base};
-  size_t n = ctx->ncell;
+  size_t n = cell_capacity(ctx);
   int nm = ctx->dim == 2 ? 4 : 8;
   ctx->s.skind = cv.take<int>(n);
   ctx->s.target = cv.take<int>(n);
@@ -211,10 +226,13 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   if (!(c.cfl > 0.0) && !(c.dt > 0.0)) return reject("need cfl > 0 or dt > 0");
   if (!(c.inflow[0] > 0.0) || !(c.inflow[4] > 0.0)) return reject("inflow rho and T must be > 0");
   if (c.kn > 0.0 && !(c.lref > 0.0)) return reject("lref must be > 0");
-  if (body->kind < CC_BODY_NONE || body->kind > CC_BODY_SPHERE) return reject("unknown body kind");
-  if (c.dim == 2 && body->kind == CC_BODY_SPHERE) return reject("sphere is 3D only");
-  if (c.dim == 3 && body->kind != CC_BODY_SPHERE && body->kind != CC_BODY_NONE)
-    return reject("3D supports sphere or no body");
+  if (body->kind < CC_BODY_NONE || body->kind > CC_BODY_VANE) return reject("unknown body kind");
+  if (c.dim == 2 && (body->kind == CC_BODY_SPHERE || body->kind == CC_BODY_VANE))
+    return reject("sphere and vane are 3D only");
+  if (c.dim == 3 && body->kind != CC_BODY_SPHERE && body->kind != CC_BODY_VANE && body->kind != CC_BODY_NONE)
+    return reject("3D supports a sphere, a vane or no body");
+  if (body->kind == CC_BODY_VANE && !(body->axes[0] > 0.0 && body->axes[1] > 0.0 && body->axes[2] > 0.0))
+    return reject("vane half-sizes must be > 0");
   if (body->kind != CC_BODY_NONE && !(body->t_wall > 0.0)) return reject("t_wall must be > 0");
   if (body->kind == CC_BODY_ELLIPSE && !(body->axes[0] > 0.0 && body->axes[1] > 0.0))
     return reject("ellipse semi-axes must be > 0");
@@ -222,9 +240,12 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
       !(body->axes[0] > 0.0))
     return reject("radius must be > 0");
   if (body->motion < CC_MOTION_FIXED || body->motion > CC_MOTION_IMPOSED) return reject("unknown motion");
-  if (body->motion != CC_MOTION_FIXED && c.dim == 3) return reject("moving bodies are 2D only");
-  if (body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_CIRCLE && body->kind != CC_BODY_ELLIPSE &&
-      body->kind != CC_BODY_NONE)
+  // 3D: a body turning about the z axis through its centre (pure rotation)
+  const bool turning3 = c.dim == 3 && body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_NONE;
+  if (turning3 && (body->vel[0] != 0.0 || body->vel[1] != 0.0 || body->vel[2] != 0.0))
+    return reject("a 3D body only turns about the z axis through its centre (vel must be 0)");
+  if (c.dim == 2 && body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_CIRCLE &&
+      body->kind != CC_BODY_ELLIPSE && body->kind != CC_BODY_NONE)
     return reject("moving bodies must be circles or ellipses");
   if (body->motion == CC_MOTION_FREE_ROTATION && !(body->inertia > 0.0))
     return reject("inertia must be > 0");
@@ -239,7 +260,7 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   if (c.scheme == CC_SCHEME_IMEX && body->motion != CC_MOTION_FIXED && body->kind != CC_BODY_NONE)
     return reject("the semi-implicit scheme is available for fixed bodies");
   if (c.amr_depth < 0 || c.amr_depth > 8) return reject("amr_depth must be in [0, 8]");
-  if (c.amr_depth > 0) {
+  if (c.amr_depth > 0 || turning3) {
     if (c.dim != 3) return reject("the octree mesh is 3D");
     for (int d = 0; d < 3; ++d)
       if (((long long)c.n[d] << c.amr_depth) >= (1LL << 20)) return reject("octree too deep for the coarse grid");
@@ -261,16 +282,36 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   ctx->dx = (c.hi[0] - c.lo[0]) / ctx->nx;
   ctx->dy = (c.hi[1] - c.lo[1]) / ctx->ny;
   ctx->dz = c.dim == 3 ? (c.hi[2] - c.lo[2]) / ctx->nz : 1.0;
-  if (c.amr_depth > 0) {
+  if (c.amr_depth > 0 || turning3) {
+    // octree mesh (a turning body always runs on it; depth 0 is the uniform grid)
     ctx->amr = true;
+    ctx->amr_turning = turning3;
     ctx->amrh = new (std::nothrow) AmrHost();
     if (!ctx->amrh) { delete ctx; return CC_ENOMEM; }
     std::string err;
-    if (!build_octree_3d(c, *body, *ctx->amrh, err)) {
+    if (!build_octree_3d(c, *body, body->theta, *ctx->amrh, err)) {
       fprintf(stderr, "ccdvm: %s\n", err.c_str());
       delete ctx->amrh;
       delete ctx;
       return CC_EGEOM;
+    }
+    if (turning3) {
+      // buffers for the largest mesh over a half turn (16 angles; the vane
+      // and the sphere map onto themselves after half a turn), plus a margin
+      int ml = ctx->amrh->nleaf, mf = ctx->amrh->nface;
+      for (int k = 1; k < 16; ++k) {
+        AmrHost T;
+        if (!build_octree_3d(c, *body, body->theta + k * M_PI / 16.0, T, err)) {
+          fprintf(stderr, "ccdvm: %s (at a later angle)\n", err.c_str());
+          delete ctx->amrh;
+          delete ctx;
+          return CC_EGEOM;
+        }
+        ml = std::max(ml, T.nleaf);
+        mf = std::max(mf, T.nface);
+      }
+      ctx->amrh->cap_leaf = ml + ml / 4 + 64;
+      ctx->amrh->cap_face = mf + mf / 4 + 256;
     }
     // the leaves are the cells; the finest spacing sets dt
     ctx->ncell = ctx->amrh->nleaf;
@@ -284,7 +325,7 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   double rate = vm / ctx->dx + vm / ctx->dy + (c.dim == 3 ? vm / ctx->dz : 0.0);
   ctx->dt = c.dt > 0.0 ? c.dt : c.cfl / rate;
   size_t per = c.dim == 2 ? 16 : 8;
-  ctx->state_bytes = align_up((size_t)ctx->ncell * ctx->nvel * per);
+  ctx->state_bytes = align_up(cell_capacity(ctx) * ctx->nvel * per);
   if (c.dim == 2) layout_geo2d(ctx, nullptr, &ctx->geom_bytes);
   else if (ctx->amr) layout_amr(ctx, nullptr, &ctx->geom_bytes);
   else layout_geo3d(ctx, nullptr, &ctx->geom_bytes);
@@ -331,6 +372,53 @@ cc_status cc_dt(const cc_ctx* ctx, double* dt) {
   return CC_OK;
 }
 
+// host mesh -> device arrays (the host vectors stay unchanged until the
+// stream has been synchronised)
+static hipError_t upload_amr_mesh(cc_ctx* ctx) {
+  const AmrHost& H = *ctx->amrh;
+  AmrDev& G = ctx->a3;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream) : hipSuccess;
+  };
+  const size_t n = H.nleaf;
+  G.nleaf = H.nleaf; G.ncv = (int)H.cv.size(); G.nreg = H.nreg; G.nsimple = H.nsimple;
+  hipError_t e = hipSuccess;
+  for (hipError_t x : {up(G.type, H.type.data(), n * sizeof(int)), up(G.master, H.master.data(), n * sizeof(int)),
+                       up(G.cv, H.cv.data(), H.cv.size() * sizeof(int)),
+                       up(G.cvptr, H.cvptr.data(), H.cvptr.size() * sizeof(int)),
+                       up(G.cvmem, H.cvmem.data(), H.cvmem.size() * sizeof(int)),
+                       up(G.fptr, H.fptr.data(), H.fptr.size() * sizeof(int)),
+                       up(G.fnb, H.fnb.data(), H.fnb.size() * sizeof(int)),
+                       up(G.fdir, H.fdir.data(), H.fdir.size() * sizeof(int)),
+                       up(G.farea, H.farea.data(), H.farea.size() * sizeof(double)),
+                       up(G.aw, H.aw.data(), n * sizeof(double)), up(G.nw, H.nw.data(), 3 * n * sizeof(double)),
+                       up(G.vbar, H.vbar.data(), n * sizeof(double)), up(G.vcv, H.vcv.data(), n * sizeof(double)),
+                       G.rw ? up(G.rw, H.rw.data(), 3 * n * sizeof(double)) : hipSuccess})
+    if (x != hipSuccess) e = x;
+  ctx->g3.ncell = H.nleaf;
+  return e;
+}
+
+// the control volumes in this step's order, their volumes at t^{n+1} and
+// their receivers (turning body)
+static hipError_t upload_amr_plan(cc_ctx* ctx) {
+  const AmrHost& H = *ctx->amrh;
+  AmrDev& G = ctx->a3;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream) : hipSuccess;
+  };
+  G.ncv = (int)H.cv.size(); G.nreg = H.nreg; G.nsimple = H.nsimple;
+  hipError_t e = hipSuccess;
+  for (hipError_t x : {up(G.cv, H.cv.data(), H.cv.size() * sizeof(int)),
+                       up(G.cvptr, H.cvptr.data(), H.cvptr.size() * sizeof(int)),
+                       up(G.cvmem, H.cvmem.data(), H.cvmem.size() * sizeof(int)),
+                       up(G.vnew, H.vnew.data(), H.vnew.size() * sizeof(double)),
+                       up(G.rptr, H.rptr.data(), H.rptr.size() * sizeof(int)),
+                       up(G.rmem, H.rmem.data(), H.rmem.size() * sizeof(int))})
+    if (x != hipSuccess) e = x;
+  return e;
+}
+
 static cc_status read_geometry_status(cc_ctx* ctx) {
   int counts[4] = {0, 0, 0, 0};
   int* dcounts = ctx->dim == 2 ? ctx->g2.counts : ctx->g3.counts;
@@ -373,22 +461,7 @@ cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scr
   if (ctx->amr) {
     const AmrHost& H = *ctx->amrh;
     AmrDev& G = ctx->a3;
-    auto up = [&](void* dst, const void* src, size_t bytes) {
-      return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream) : hipSuccess;
-    };
-    const size_t n = H.nleaf;
-    hipError_t e = hipSuccess;
-    for (hipError_t x : {up(G.type, H.type.data(), n * sizeof(int)), up(G.master, H.master.data(), n * sizeof(int)),
-                         up(G.cv, H.cv.data(), H.cv.size() * sizeof(int)),
-                         up(G.cvptr, H.cvptr.data(), H.cvptr.size() * sizeof(int)),
-                         up(G.cvmem, H.cvmem.data(), H.cvmem.size() * sizeof(int)),
-                         up(G.fptr, H.fptr.data(), H.fptr.size() * sizeof(int)),
-                         up(G.fnb, H.fnb.data(), H.fnb.size() * sizeof(int)),
-                         up(G.fdir, H.fdir.data(), H.fdir.size() * sizeof(int)),
-                         up(G.farea, H.farea.data(), H.farea.size() * sizeof(double)),
-                         up(G.aw, H.aw.data(), n * sizeof(double)), up(G.nw, H.nw.data(), 3 * n * sizeof(double)),
-                         up(G.vbar, H.vbar.data(), n * sizeof(double)), up(G.vcv, H.vcv.data(), n * sizeof(double))})
-      if (x != hipSuccess) e = x;
+    hipError_t e = upload_amr_mesh(ctx);
     if (e == hipSuccess) e = launch_amr_tables(ctx);
     if (e != hipSuccess) return hip_fail(ctx, e, "octree upload");
     if (!ctx->side) {   // default priority, like the caller's stream
@@ -491,6 +564,67 @@ cc_status cc_store_state(const cc_ctx* ctx, double* f, double* g) {
   return e == hipSuccess ? CC_OK : CC_EHIP;
 }
 
+// One step of a body turning on the octree (Section 5, steps 1-7, then the
+// mesh adapted to the body).  The host plans the step on the mesh of t^n
+// (geometry at t^{n+1}, receiving control volumes), the kernels step the
+// state, the torque sets the angular velocity of t^{n+1} (one
+// synchronisation per step), the host builds the mesh of t^{n+1} and the
+// remap kernel carries the state over.  row (device, nullable) = Fx, Fy,
+// torque about the axis, mass of the state entering the step.
+static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
+  AmrHost& H = *ctx->amrh;
+  const double th = ctx->body_state[2], om = ctx->body_state[5];
+  const double th1 = th + ctx->dt * om;
+  std::string err;
+  if (!plan_amr_move(ctx->cfg, ctx->body, th1, H, err)) return fail(ctx, CC_EGEOM, err);
+  HIPCHK(ctx, upload_amr_plan(ctx), "step plan upload");
+  cc_status st = prepare(ctx);
+  if (st != CC_OK) return st;
+  double* drow = row ? row : ctx->s.red + 4 * 128 + 4;
+  HIPCHK(ctx, launch_amr_step(ctx, drow), "step");
+  double tq = 0.0;
+  HIPCHK(ctx, hipMemcpyAsync(&tq, drow + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "torque copy");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "step");
+  // explicit Euler for the body: angle with the old angular velocity, the
+  // angular velocity with the torque of t^n (free rotation)
+  ctx->body_state[2] = th1;
+  if (ctx->body.motion == CC_MOTION_FREE_ROTATION) ctx->body_state[5] = om + ctx->dt * tq / ctx->body.inertia;
+  // the mesh of t^{n+1} and the state carried over to it
+  AmrHost* N1 = new (std::nothrow) AmrHost();
+  if (!N1) return fail(ctx, CC_ENOMEM, "host allocation");
+  if (!build_octree_3d(ctx->cfg, ctx->body, th1, *N1, err)) { delete N1; return fail(ctx, CC_EGEOM, err); }
+  AmrRemap R;
+  build_amr_remap(H, *N1, ctx->cfg.amr_depth, R);
+  if (N1->nleaf > H.cap_leaf || N1->nface > H.cap_face || (long long)R.src.size() > 2LL * H.cap_leaf) {
+    delete N1;
+    return fail(ctx, CC_ENOMEM, "the adapted mesh outgrew the buffers sized at cc_create");
+  }
+  N1->cap_leaf = H.cap_leaf; N1->cap_face = H.cap_face;
+  AmrDev& G = ctx->a3;
+  HIPCHK(ctx, hipMemcpyAsync(G.sptr, R.sptr.data(), R.sptr.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream),
+         "remap upload");
+  if (!R.src.empty()) {
+    HIPCHK(ctx, hipMemcpyAsync(G.src, R.src.data(), R.src.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream),
+           "remap upload");
+    HIPCHK(ctx, hipMemcpyAsync(G.wgt, R.wgt.data(), R.wgt.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream),
+           "remap upload");
+  }
+  AmrHost* old = ctx->amrh;
+  ctx->amrh = N1;
+  ctx->ncell = N1->nleaf;
+  hipError_t e = upload_amr_mesh(ctx);
+  if (e == hipSuccess) e = launch_amr_remap(ctx, (const double*)ctx->state[ctx->cur], (double*)ctx->state[1 - ctx->cur]);
+  // the host vectors uploaded above must outlive the copies
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  delete old;
+  if (e != hipSuccess) return hip_fail(ctx, e, "mesh adaptation");
+  ctx->cur = 1 - ctx->cur;
+  ctx->n_irr = N1->n_irr; ctx->n_members = N1->n_members; ctx->n_solid = N1->n_solid;
+  ctx->merged = false;
+  ctx->mom_valid = false;
+  return CC_OK;
+}
+
 cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
   if (!ctx || nsteps < 0) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
@@ -498,6 +632,13 @@ cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
   if (st != CC_OK) return st;
   if (nsteps == 0) return CC_OK;
   bool moving = ctx->body.motion != CC_MOTION_FIXED && ctx->body.kind != CC_BODY_NONE;
+  if (ctx->amr_turning) {
+    for (int n = 0; n < nsteps; ++n) {
+      st = amr_turning_step(ctx, diag ? diag + 4 * (size_t)n : nullptr);
+      if (st != CC_OK) return st;
+    }
+    return CC_OK;
+  }
   if (ctx->amr) {
     for (int n = 0; n < nsteps; ++n) {
       hipError_t e = launch_amr_step(ctx, diag ? diag + 4 * (size_t)n : nullptr);
@@ -580,7 +721,7 @@ cc_status cc_body_force(cc_ctx* ctx, double out[4]) {
 
 cc_status cc_body_state(cc_ctx* ctx, double out[6]) {
   if (!ctx || !out) return CC_EINVAL;
-  if (!ctx->bound) {
+  if (!ctx->bound || ctx->amr_turning) {   // a turning body is advanced on the host
     memcpy(out, ctx->body_state, 6 * sizeof(double));
     return CC_OK;
   }

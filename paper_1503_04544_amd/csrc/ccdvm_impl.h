@@ -97,8 +97,10 @@ struct Geo3D {
   double* ghost;     // nvel farfield values (F)
 };
 
-// Octree mesh (3D, amr_depth > 0): built on the host when the context is
-// created (octree3d.hip), uploaded to the geometry buffer when it is bound.
+// Octree mesh (3D): built on the host when the context is created
+// (octree3d.hip), uploaded to the geometry buffer when it is bound.  With a
+// turning body the host plans every step on the mesh of t^n, then rebuilds
+// the mesh for t^{n+1} and the map that carries the state over.
 struct AmrHost {
   int n0[3];
   double hf[3];                     // finest spacing
@@ -110,6 +112,23 @@ struct AmrHost {
   std::vector<int> cv, cvptr, cvmem; // control volumes: master leaf, members (CSR); regular first
   int nsimple = 0;                   // simple regular control volumes (one face entry per direction)
   int nreg = 0;                      // regular control volumes (one member, no wall face), simple first
+  std::vector<std::pair<uint64_t, int>> table;   // (depth, coordinates) key -> leaf, sorted
+  std::vector<uint64_t> zkey;        // Z-order key of each leaf's lower corner (ascending)
+  // turning body, plan of the step from t^n (this mesh) to t^{n+1}
+  std::vector<int> type1;            // leaf types with the body at t^{n+1}
+  std::vector<double> vbar1;         // leaf gas volumes at t^{n+1}
+  std::vector<double> vnew;          // per master: its control volume's volume at t^{n+1}
+  std::vector<int> rptr, rmem;       // per control volume (cv order): leaves receiving its value
+  // capacities of the device arrays (the largest mesh a turning body is expected to need)
+  int cap_leaf = 0, cap_face = 0;
+};
+
+// State carried from the mesh of t^n to the mesh of t^{n+1}: new leaf q
+// takes sum_e wgt[e] F[src[e]] / sum_e wgt[e] over e in [sptr[q], sptr[q+1])
+// (0 with no entry).
+struct AmrRemap {
+  std::vector<int> sptr, src;
+  std::vector<double> wgt;
 };
 
 struct AmrDev {
@@ -119,6 +138,11 @@ struct AmrDev {
   int* fptr; int* fnb; int* fdir;
   double* farea; double* aw; double* nw; double* vbar; double* vcv;
   double* ghost;                    // nvel farfield values
+  // turning body
+  double* rw;                       // wall centres (3 per leaf)
+  double* vnew;                     // per master: volume at t^{n+1}
+  int* rptr; int* rmem;             // receivers per control volume
+  int* sptr; int* src; double* wgt; // remap to the next mesh
 };
 
 // Scratch layout (caller's scratch buffer).
@@ -184,6 +208,7 @@ struct cc_ctx {
   long long nstep = 0;      // steps taken since binding
   ccdvm::Geo3D g3;
   bool amr = false;                 // 3D octree mesh
+  bool amr_turning = false;         // octree with a body turning about the z axis
   ccdvm::AmrHost* amrh = nullptr;
   ccdvm::AmrDev a3{};
   hipStream_t side = nullptr;        // octree: cut control volumes run beside the others
@@ -257,7 +282,10 @@ hipError_t launch_moments_out_3d(cc_ctx* ctx, double* out);
 int chunks3d(int N);   // velocity chunks of the 3D regular-cell pass (0: unsupported N)
 
 // octree mesh (octree3d.hip)
-bool build_octree_3d(const cc_config& cfg, const cc_body& body, AmrHost& H, std::string& err);
+bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, AmrHost& H, std::string& err);
+bool plan_amr_move(const cc_config& cfg, const cc_body& body, double th1, AmrHost& H, std::string& err);
+void build_amr_remap(const AmrHost& old_mesh, const AmrHost& new_mesh, int depth, AmrRemap& R);
+hipError_t launch_amr_remap(cc_ctx* ctx, const double* from, double* to);
 hipError_t launch_amr_tables(cc_ctx* ctx);
 hipError_t launch_amr_init(cc_ctx* ctx, const double* f);   // f null: farfield Maxwellian
 hipError_t launch_amr_merge(cc_ctx* ctx);

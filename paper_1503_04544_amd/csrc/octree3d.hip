@@ -51,28 +51,92 @@ uint64_t spread_bits3(uint64_t x) {
   return r;
 }
 
+uint64_t morton3(uint64_t i, uint64_t j, uint64_t k) {
+  return spread_bits3(i) | (spread_bits3(j) << 1) | (spread_bits3(k) << 2);
+}
+
 uint64_t leaf_key(int l, int i, int j, int k) {
   return ((uint64_t)l << 60) | ((uint64_t)i << 40) | ((uint64_t)j << 20) | (uint64_t)k;
 }
 
-struct LeafTable {
-  std::vector<std::pair<uint64_t, int>> t;
-  int find(int l, int i, int j, int k) const {
-    if (l < 0 || i < 0 || j < 0 || k < 0) return -1;
-    const uint64_t key = leaf_key(l, i, j, k);
-    auto it = std::lower_bound(t.begin(), t.end(), std::make_pair(key, -1));
-    return it != t.end() && it->first == key ? it->second : -1;
-  }
-};
+int find_leaf(const std::vector<std::pair<uint64_t, int>>& t, int l, int i, int j, int k) {
+  if (l < 0 || i < 0 || j < 0 || k < 0) return -1;
+  const uint64_t key = leaf_key(l, i, j, k);
+  auto it = std::lower_bound(t.begin(), t.end(), std::make_pair(key, -1));
+  return it != t.end() && it->first == key ? it->second : -1;
+}
 
-}  // namespace
-
-bool build_octree_3d(const cc_config& cfg, const cc_body& body, AmrHost& H, std::string& err) {
-  const int D = cfg.amr_depth;
+BodyDev body_at(const cc_body& body, double theta) {
   BodyDev B{};
   B.kind = body.kind;
   B.cx = body.center[0]; B.cy = body.center[1]; B.cz = body.center[2];
-  B.a = body.axes[0];
+  B.a = body.axes[0]; B.b = body.axes[1]; B.c = body.axes[2];
+  B.theta = theta;
+  B.t_wall = body.t_wall;
+  return B;
+}
+
+// geometry of leaf q with the body B: its 8 vertex values (clamped as on
+// the uniform grid) and the uniform grid's per-cell construction at the
+// leaf's size; A0 = lower corner in finest units
+void leaf_geometry(const cc_config& cfg, const AmrHost& H, const BodyDev& B, int q, CellGeo3& g, int A0[3]) {
+  const int sh = cfg.amr_depth - H.lvl[q];
+  for (int d = 0; d < 3; ++d) A0[d] = H.ijk[3 * (size_t)q + d] << sh;
+  double q8[8], h[3];
+  for (int d = 0; d < 3; ++d) h[d] = H.hf[d] * (double)(1 << sh);
+  for (int t = 0; t < 8; ++t) {
+    const int a = A0[0] + ((t & 1) << sh), b = A0[1] + (((t >> 1) & 1) << sh), c = A0[2] + (((t >> 2) & 1) << sh);
+    q8[t] = clamp_vertex(level_set_3d(B, cfg.lo[0] + a * H.hf[0], cfg.lo[1] + b * H.hf[1], cfg.lo[2] + c * H.hf[2]),
+                         H.hf[0]);
+  }
+  cell_geometry_3d(q8, h, 1e-12 * H.hf[0], g);
+}
+
+// Control volumes in kernel order: first the regular ones (one member, no
+// wall face; simple ones, with one face entry per direction in direction
+// order, before the others), then the cut or merged ones, each group in
+// leaf order; with a turning body the control volumes marked in `changed`
+// (volume or receivers differ between t^n and t^{n+1}) join the last group.
+bool order_cvs(AmrHost& H, const std::vector<char>* changed, std::string& err) {
+  const int n = H.nleaf;
+  std::vector<int> cnt(n, 0);
+  for (int q = 0; q < n; ++q) if (H.master[q] >= 0) cnt[H.master[q]]++;
+  H.cv.clear(); H.cvptr.assign(1, 0); H.cvmem.clear();
+  std::vector<int> slot(n, -1);
+  auto kind_of = [&](int q) {
+    if (cnt[q] != 1 || H.aw[q] > 0.0 || (changed && (*changed)[q])) return 2;
+    if (H.fptr[q + 1] - H.fptr[q] != 6) return 1;
+    for (int t = 0; t < 6; ++t) if (H.fdir[H.fptr[q] + t] != t) return 1;
+    return 0;
+  };
+  H.nsimple = 0; H.nreg = 0;
+  for (int pass = 0; pass < 3; ++pass)
+    for (int q = 0; q < n; ++q)
+      if (H.master[q] == q) {
+        if (cnt[q] > kMaxMembers) { err = "a control volume has more members than supported"; return false; }
+        const int kd = kind_of(q);
+        if (kd != pass) continue;
+        H.nsimple += kd == 0;
+        H.nreg += kd <= 1;
+        slot[q] = (int)H.cv.size();
+        H.cv.push_back(q);
+        H.cvptr.push_back(H.cvptr.back() + cnt[q]);
+      }
+  H.cvmem.assign(H.cvptr.back(), 0);
+  std::vector<int> fill(H.cv.size(), 0);
+  for (int q = 0; q < n; ++q)
+    if (H.master[q] >= 0) {
+      const int s = slot[H.master[q]];
+      H.cvmem[H.cvptr[s] + fill[s]++] = q;
+    }
+  return true;
+}
+
+}  // namespace
+
+bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, AmrHost& H, std::string& err) {
+  const int D = cfg.amr_depth;
+  const BodyDev B = body_at(body, theta);
   double h0[3];
   for (int d = 0; d < 3; ++d) {
     H.n0[d] = cfg.n[d];
@@ -105,39 +169,30 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, AmrHost& H, std:
   for (int q = 0; q < n; ++q) {
     const C4& c = leaves[q];
     const int sh = D - c.l;
-    order[q] = {spread_bits3((uint64_t)c.i << sh) | (spread_bits3((uint64_t)c.j << sh) << 1) |
-                    (spread_bits3((uint64_t)c.k << sh) << 2),
-                q};
+    order[q] = {morton3((uint64_t)c.i << sh, (uint64_t)c.j << sh, (uint64_t)c.k << sh), q};
   }
   std::sort(order.begin(), order.end());
   H.nleaf = n;
-  H.lvl.resize(n); H.ijk.resize(3 * (size_t)n);
+  H.lvl.resize(n); H.ijk.resize(3 * (size_t)n); H.zkey.resize(n);
   for (int q = 0; q < n; ++q) {
     const C4& c = leaves[order[q].second];
     H.lvl[q] = c.l; H.ijk[3 * q] = c.i; H.ijk[3 * q + 1] = c.j; H.ijk[3 * q + 2] = c.k;
+    H.zkey[q] = order[q].first;
   }
-  LeafTable T;
-  T.t.resize(n);
-  for (int q = 0; q < n; ++q) T.t[q] = {leaf_key(H.lvl[q], H.ijk[3 * q], H.ijk[3 * q + 1], H.ijk[3 * q + 2]), q};
-  std::sort(T.t.begin(), T.t.end());
+  H.table.resize(n);
+  for (int q = 0; q < n; ++q)
+    H.table[q] = {leaf_key(H.lvl[q], H.ijk[3 * q], H.ijk[3 * q + 1], H.ijk[3 * q + 2]), q};
+  std::sort(H.table.begin(), H.table.end());
+  const auto& T = H.table;
   // geometry of every leaf at its own size
   H.type.assign(n, 0); H.flags.assign(n, 0); H.S6.assign(6 * (size_t)n, 0.0);
   H.aw.assign(n, 0.0); H.nw.assign(3 * (size_t)n, 0.0); H.rw.assign(3 * (size_t)n, 0.0);
   H.vbar.assign(n, 0.0);
   bool saddle = false, coarse_cut = false;
   for (int q = 0; q < n; ++q) {
-    const int sh = D - H.lvl[q];
-    const int A0[3] = {H.ijk[3 * q] << sh, H.ijk[3 * q + 1] << sh, H.ijk[3 * q + 2] << sh};
-    double q8[8], h[3];
-    for (int d = 0; d < 3; ++d) h[d] = H.hf[d] * (double)(1 << sh);
-    for (int t = 0; t < 8; ++t) {
-      const int a = A0[0] + ((t & 1) << sh), b = A0[1] + (((t >> 1) & 1) << sh),
-                c = A0[2] + (((t >> 2) & 1) << sh);
-      q8[t] = clamp_vertex(level_set_3d(B, cfg.lo[0] + a * H.hf[0], cfg.lo[1] + b * H.hf[1], cfg.lo[2] + c * H.hf[2]),
-                           H.hf[0]);
-    }
     CellGeo3 g;
-    cell_geometry_3d(q8, h, 1e-12 * H.hf[0], g);
+    int A0[3];
+    leaf_geometry(cfg, H, B, q, g, A0);
     if (g.flags & 2) saddle = true;
     if (g.type == TYPE_CUT && H.lvl[q] < D) coarse_cut = true;
     H.type[q] = g.type;
@@ -170,15 +225,15 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, AmrHost& H, std:
         H.fnb.push_back(nb); H.fdir.push_back(t); H.farea.push_back(area);
       };
       if (g[d] < 0 || g[d] >= (cfg.n[d] << l)) { add(-1, A); continue; }
-      int x = T.find(l, g[0], g[1], g[2]);
-      if (x < 0) x = T.find(l - 1, g[0] >> 1, g[1] >> 1, g[2] >> 1);
+      int x = find_leaf(T, l, g[0], g[1], g[2]);
+      if (x < 0) x = find_leaf(T, l - 1, g[0] >> 1, g[1] >> 1, g[2] >> 1);
       if (x >= 0) { add(x, A); continue; }
       if (l == D) { jump = true; continue; }
       for (int b2 = 0; b2 < 2; ++b2)
         for (int b1 = 0; b1 < 2; ++b1) {
           int c[3];
           c[d] = 2 * g[d] + (sd ? 0 : 1); c[d1] = 2 * g[d1] + b1; c[d2] = 2 * g[d2] + b2;
-          const int y = T.find(l + 1, c[0], c[1], c[2]);
+          const int y = find_leaf(T, l + 1, c[0], c[1], c[2]);
           if (y < 0) { jump = true; continue; }
           const double Ay = H.S6[6 * (size_t)y + (t ^ 1)];
           if (Ay != 0.0) add(y, Ay);
@@ -206,7 +261,7 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, AmrHost& H, std:
         g[d] += (t & 1) ? 1 : -1;
         L[u] = 0.0; nb[u] = -1;
         if (g[d] < 0 || g[d] >= (cfg.n[d] << l)) continue;
-        nb[u] = T.find(l, g[0], g[1], g[2]);
+        nb[u] = find_leaf(T, l, g[0], g[1], g[2]);
         L[u] = H.S6[6 * (size_t)cur + t];
       }
       double M = 0.0;
@@ -227,40 +282,7 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, AmrHost& H, std:
   }
   for (int q = 0; q < n; ++q)
     if (H.master[q] >= 0 && H.master[H.master[q]] != H.master[q]) { err = "a master is not its own master"; return false; }
-  // control volumes: first the regular ones (one member, no wall face),
-  // then the others, each in leaf order; members ascending
-  std::vector<int> cnt(n, 0);
-  for (int q = 0; q < n; ++q) if (H.master[q] >= 0) cnt[H.master[q]]++;
-  H.cv.clear(); H.cvptr.assign(1, 0); H.cvmem.clear();
-  std::vector<int> slot(n, -1);
-  // kinds: 0 simple (one member, no wall, one face entry per direction, in
-  // direction order), 1 other regular, 2 cut or merged
-  auto kind_of = [&](int q) {
-    if (cnt[q] != 1 || H.aw[q] > 0.0) return 2;
-    if (H.fptr[q + 1] - H.fptr[q] != 6) return 1;
-    for (int t = 0; t < 6; ++t) if (H.fdir[H.fptr[q] + t] != t) return 1;
-    return 0;
-  };
-  H.nsimple = 0; H.nreg = 0;
-  for (int pass = 0; pass < 3; ++pass)
-    for (int q = 0; q < n; ++q)
-      if (H.master[q] == q) {
-        if (cnt[q] > kMaxMembers) { err = "a control volume has more members than supported"; return false; }
-        const int kd = kind_of(q);
-        if (kd != pass) continue;
-        H.nsimple += kd == 0;
-        H.nreg += kd <= 1;
-        slot[q] = (int)H.cv.size();
-        H.cv.push_back(q);
-        H.cvptr.push_back(H.cvptr.back() + cnt[q]);
-      }
-  H.cvmem.assign(H.cvptr.back(), 0);
-  std::vector<int> fill(H.cv.size(), 0);
-  for (int q = 0; q < n; ++q)
-    if (H.master[q] >= 0) {
-      const int s = slot[H.master[q]];
-      H.cvmem[H.cvptr[s] + fill[s]++] = q;
-    }
+  if (!order_cvs(H, nullptr, err)) return false;
   H.vcv.assign(n, 0.0);
   for (size_t s = 0; s < H.cv.size(); ++s) {
     double v = 0.0;
@@ -276,7 +298,125 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, AmrHost& H, std:
     H.n_members += nm - 1;
   }
   for (int q = 0; q < n; ++q) H.n_solid += H.type[q] == TYPE_SOLID;
+  H.type1.clear(); H.vbar1.clear(); H.vnew.clear(); H.rptr.clear(); H.rmem.clear();
   return true;
+}
+
+// Turning body, the step from t^n to t^{n+1} on the mesh H of t^n
+// (Section 5, steps 3 and 7): the leaves' types and gas volumes with the
+// body at th1; the control volume of t^n each leaf receives from (its
+// master; a leaf solid at t^n and not at t^{n+1} hops across its largest
+// face at t^{n+1} to a leaf of the same depth, order x+, x-, y+, y-, z+,
+// z-, at most 4 hops, and takes that leaf's control volume); each control
+// volume's volume at t^{n+1} (the sum over its receivers, leaf order) and
+// its receivers (not solid at t^{n+1}).  Control volumes whose volume or
+// receivers change are ordered with the cut ones.
+bool plan_amr_move(const cc_config& cfg, const cc_body& body, double th1, AmrHost& H, std::string& err) {
+  const int n = H.nleaf, D = cfg.amr_depth;
+  const BodyDev B = body_at(body, th1);
+  H.type1.assign(n, 0); H.vbar1.assign(n, 0.0);
+  std::vector<double> S61(6 * (size_t)n);
+  bool saddle = false, coarse_cut = false;
+  for (int q = 0; q < n; ++q) {
+    CellGeo3 g;
+    int A0[3];
+    leaf_geometry(cfg, H, B, q, g, A0);
+    if (g.flags & 2) saddle = true;
+    if (g.type == TYPE_CUT && H.lvl[q] < D) coarse_cut = true;
+    H.type1[q] = g.type;
+    H.vbar1[q] = g.vbar;
+    for (int f = 0; f < 6; ++f) S61[6 * (size_t)q + f] = g.S[f];
+  }
+  if (saddle) { err = "a cell is cut twice by the boundary at the next time"; return false; }
+  if (coarse_cut) { err = "the body moved out of the refined band within one step"; return false; }
+  std::vector<int> target(H.master);
+  const int dir_order[6] = {1, 0, 3, 2, 5, 4};
+  for (int q = 0; q < n; ++q) {
+    if (!(H.type[q] == TYPE_SOLID && H.type1[q] != TYPE_SOLID)) continue;
+    int cur = q, hops = 0;
+    while (H.master[cur] < 0 && hops < 4) {
+      const int l = H.lvl[cur];
+      double L[6], M = 0.0;
+      int nb[6];
+      for (int u = 0; u < 6; ++u) {
+        const int t = dir_order[u], d = t >> 1;
+        int g[3] = {H.ijk[3 * cur], H.ijk[3 * cur + 1], H.ijk[3 * cur + 2]};
+        g[d] += (t & 1) ? 1 : -1;
+        nb[u] = -1; L[u] = 0.0;
+        if (g[d] < 0 || g[d] >= (cfg.n[d] << l)) continue;
+        nb[u] = find_leaf(H.table, l, g[0], g[1], g[2]);
+        L[u] = S61[6 * (size_t)cur + t];
+        M = std::max(M, L[u]);
+      }
+      if (!(M > 0.0)) break;
+      const double tie = M * (1.0 - 1e-12);
+      int u = 0;
+      while (L[u] < tie) ++u;
+      if (nb[u] < 0) break;
+      cur = nb[u];
+      ++hops;
+    }
+    if (H.master[cur] < 0) { err = "a leaf appearing at the next time found no control volume"; return false; }
+    target[q] = H.master[cur];
+  }
+  H.vnew.assign(n, 0.0);
+  std::vector<int> rcnt(n, 0);
+  for (int q = 0; q < n; ++q)
+    if (target[q] >= 0) {
+      H.vnew[target[q]] += H.vbar1[q];
+      if (H.type1[q] != TYPE_SOLID) rcnt[target[q]]++;
+    }
+  // receivers grouped by master (leaf order), compared with the members
+  std::vector<int> rstart(n + 1, 0);
+  for (int q = 0; q < n; ++q) rstart[q + 1] = rstart[q] + rcnt[q];
+  std::vector<int> rlist(rstart[n]), fill(n, 0);
+  for (int q = 0; q < n; ++q)
+    if (target[q] >= 0 && H.type1[q] != TYPE_SOLID) rlist[rstart[target[q]] + fill[target[q]]++] = q;
+  std::vector<char> changed(n, 0);
+  for (size_t s = 0; s < H.cv.size(); ++s) {
+    const int m = H.cv[s];
+    const int nm = H.cvptr[s + 1] - H.cvptr[s];
+    bool same = H.vnew[m] == H.vcv[m] && rcnt[m] == nm;
+    for (int e = 0; same && e < nm; ++e) same = rlist[rstart[m] + e] == H.cvmem[H.cvptr[s] + e];
+    changed[m] = !same;
+  }
+  if (!order_cvs(H, &changed, err)) return false;
+  H.rptr.assign(H.cv.size() + 1, 0);
+  H.rmem.clear();
+  for (size_t s = 0; s < H.cv.size(); ++s) {
+    const int m = H.cv[s];
+    for (int e = rstart[m]; e < rstart[m + 1]; ++e) H.rmem.push_back(rlist[e]);
+    H.rptr[s + 1] = (int)H.rmem.size();
+  }
+  return true;
+}
+
+// The state carried from the mesh of t^n (old, with its leaves' gas volumes
+// at t^{n+1}) to the mesh of t^{n+1} (Section 5, mesh adaptation): a leaf
+// that is also an old leaf, or lies inside one, takes its value (0th-order
+// prolongation); a leaf that covers old leaves takes their gas-volume
+// weighted mean (restriction), summed in old-leaf order; solid leaves are 0.
+// The old leaves inside a leaf are a contiguous range of the Z-order.
+void build_amr_remap(const AmrHost& O, const AmrHost& H, int depth, AmrRemap& R) {
+  const int n = H.nleaf;
+  R.sptr.assign(n + 1, 0);
+  R.src.clear(); R.wgt.clear();
+  for (int q = 0; q < n; ++q) {
+    R.sptr[q] = (int)R.src.size();
+    if (H.type[q] == TYPE_SOLID) continue;
+    const int l = H.lvl[q], i = H.ijk[3 * q], j = H.ijk[3 * q + 1], k = H.ijk[3 * q + 2];
+    int s = find_leaf(O.table, l, i, j, k);
+    for (int a = l - 1; s < 0 && a >= 0; --a) s = find_leaf(O.table, a, i >> (l - a), j >> (l - a), k >> (l - a));
+    if (s >= 0) { R.src.push_back(s); R.wgt.push_back(1.0); continue; }
+    const int sh = depth - l;
+    const uint64_t z0 = morton3((uint64_t)i << sh, (uint64_t)j << sh, (uint64_t)k << sh), z1 = z0 + (1ULL << (3 * sh));
+    for (size_t r = std::lower_bound(O.zkey.begin(), O.zkey.end(), z0) - O.zkey.begin();
+         r < O.zkey.size() && O.zkey[r] < z1; ++r) {
+      R.src.push_back((int)r);
+      R.wgt.push_back(O.vbar1[r]);
+    }
+  }
+  R.sptr[n] = (int)R.src.size();
 }
 
 // ---------------------------------------------------------------------
@@ -308,6 +448,7 @@ struct AmrArgs {
   double* part;       // 4 per block: wall force and mass of the state at t^n
   int per_simple, per, per_irr;   // blocks per XCD of the three kinds of control volumes
   double vmin, dv, w, dt, tau_coef, t_wall;
+  double om, cx, cy;              // turning body: angular velocity at t^n, axis (z) position
 };
 
 // record of the relaxation from the moment sums of one control volume
@@ -327,7 +468,12 @@ __device__ inline void write_record(double* mom, const int* mem, int nm, const d
 // a finer neighbour on some face); IRR = true: [nreg, ncv) (cut or merged).
 // These are few, so each gets a 256-thread block (one wave each would leave
 // most of the GPU waiting on memory); the four waves split the velocities.
-template <int N, bool IRR>
+// MV (with IRR): turning body.  The walls move with om e_z x (r - axis):
+// wall density, wall flux and stress use v - u_w; the update carries the
+// ratio V^n / V^{n+1,*} of eq. (eq-schema3D) and goes to the control
+// volume's receivers at t^{n+1}; the partials hold the torque about the
+// axis in place of Fz.
+template <int N, bool IRR, bool MV = false>
 __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
   constexpr int NV = N * N * N;
   constexpr int NT = 256;
@@ -350,6 +496,9 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
   const double Am = rec[0], ux = rec[1], uy = rec[2], uz = rec[3], inv2T = rec[4], dtau = rec[5];
   const double mass_n = G.vcv[m] * rec[6];   // before the record is overwritten
   const double dtV = A.dt / G.vcv[m];
+  const double vn = MV ? G.vnew[m] : 0.0;
+  const double ratio = MV && vn > 0.0 ? G.vcv[m] / vn : 1.0;
+  const double dtVn = MV ? (vn > 0.0 ? A.dt / vn : 0.0) : dtV;
   const double* own = A.in + (size_t)m * NV;
   // block sum (waves added in order); every thread gets the total
   auto bsum = [&](double v) {
@@ -369,16 +518,23 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
   // wall density of each member with a wall face (zero net mass flux)
   const double Tw = A.t_wall, cw = 1.0 / pow(2.0 * M_PI * Tw, 1.5), i2Tw = 0.5 / Tw;
   double phiw[IRR ? kMaxMembers : 1];
+  double uwx[MV ? kMaxMembers : 1], uwy[MV ? kMaxMembers : 1];
   bool any_wall = false;
   for (int t = 0; t < (IRR ? nm : 0); ++t) {
     const int k = G.cvmem[b + t];
     phiw[t] = 0.0;
+    if (MV) { uwx[t] = 0.0; uwy[t] = 0.0; }
     if (!(G.aw[k] > 0.0)) continue;
     any_wall = true;
     const double n0 = G.nw[3 * k], n1 = G.nw[3 * k + 1], n2 = G.nw[3 * k + 2];
+    if (MV) {
+      uwx[t] = -A.om * (G.rw[3 * k + 1] - A.cy);
+      uwy[t] = A.om * (G.rw[3 * k] - A.cx);
+    }
+    const double ux_ = MV ? uwx[t] : 0.0, uy_ = MV ? uwy[t] : 0.0;
     double num = 0.0, den = 0.0;
     for (int p = tid; p < NV; p += NT) {
-      const double vx = vnodeA(A.vmin, A.dv, p % N), vy = vnodeA(A.vmin, A.dv, (p / N) % N),
+      const double vx = vnodeA(A.vmin, A.dv, p % N) - ux_, vy = vnodeA(A.vmin, A.dv, (p / N) % N) - uy_,
                    vz = vnodeA(A.vmin, A.dv, p / (N * N));
       const double cn = vx * n0 + vy * n1 + vz * n2;
       if (cn > 0.0) num += cn * own[p];
@@ -389,7 +545,7 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
     phiw[t] = den != 0.0 ? -num / den : 0.0;
   }
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  double fx = 0.0, fy = 0.0, fz = 0.0;
+  double fx = 0.0, fy = 0.0, fz = 0.0;   // MV: fz holds the torque about the axis
   for (int pass = 0; pass < NP; ++pass) {
     // the thread id is laundered per pass so that the velocity constants of
     // a pass are recomputed where used instead of being held across passes
@@ -427,17 +583,22 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
       }
       if (IRR && any_wall && G.aw[k] > 0.0) {
         const double awk = G.aw[k], n0 = G.nw[3 * k], n1 = G.nw[3 * k + 1], n2 = G.nw[3 * k + 2];
+        const double ux_ = MV ? uwx[t] : 0.0, uy_ = MV ? uwy[t] : 0.0;
+        const double lx = MV ? G.rw[3 * k] - A.cx : 0.0, ly = MV ? G.rw[3 * k + 1] - A.cy : 0.0;
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
           const int p = (pass * RC + r) * NT + lv;
           if (p >= NV) continue;
-          const double vx = vnodeA(A.vmin, A.dv, p % N), vy = vnodeA(A.vmin, A.dv, (p / N) % N),
+          // velocity relative to the wall
+          const double vx = vnodeA(A.vmin, A.dv, p % N) - ux_, vy = vnodeA(A.vmin, A.dv, (p / N) % N) - uy_,
                        vz = vnodeA(A.vmin, A.dv, p / (N * N));
           const double cn = vx * n0 + vy * n1 + vz * n2;
           const double fw = phiw[t] * cw * exp(-(vx * vx + vy * vy + vz * vz) * i2Tw);
           acc[r] += awk * (fmin(cn, 0.0) * fw + fmax(cn, 0.0) * fo[r]);
           const double fv = cn < 0.0 ? fw : (cn > 0.0 ? fo[r] : 0.0);
-          fx += awk * vx * cn * fv; fy += awk * vy * cn * fv; fz += awk * vz * cn * fv;
+          fx += awk * vx * cn * fv; fy += awk * vy * cn * fv;
+          if (MV) fz += awk * (lx * vy - ly * vx) * cn * fv;
+          else fz += awk * vz * cn * fv;
         }
       }
     }
@@ -448,8 +609,10 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
       const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
       const double E = Am * __shfl(tx, p1, kWaveA) * __shfl(ty, p2, kWaveA) * __shfl(tz, p3, kWaveA);
       const double f = fo[r];
-      const double fn = f - dtV * acc[r] + dtau * (E - f);
-      if (IRR)
+      const double fn = MV ? ratio * f - dtVn * acc[r] + ratio * dtau * (E - f) : f - dtV * acc[r] + dtau * (E - f);
+      if (MV)
+        for (int e = G.rptr[w]; e < G.rptr[w + 1]; ++e) A.out[(size_t)G.rmem[e] * NV + p] = fn;
+      else if (IRR)
         for (int t = 0; t < nm; ++t) A.out[(size_t)G.cvmem[b + t] * NV + p] = fn;
       else
         A.out[(size_t)m * NV + p] = fn;
@@ -462,7 +625,7 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
   for (int q = 0; q < 5; ++q) s[q] = bsum(s[q]);
   if (IRR && any_wall) { fx = bsum(fx); fy = bsum(fy); fz = bsum(fz); }
   if (tid == 0) {
-    write_record(A.mom, G.cvmem + b, nm, s, A.w, A.dt, A.tau_coef);
+    if (!MV) write_record(A.mom, G.cvmem + b, nm, s, A.w, A.dt, A.tau_coef);
     // partials after the streaming kernel's blocks: one per control volume
     const size_t slot = (size_t)(A.G.nsimple + 3) / 4 + (IRR ? A.G.nreg - A.G.nsimple : 0) + blk;
     A.part[4 * slot + 0] = IRR ? fx * A.w : 0.0;
@@ -633,6 +796,23 @@ __global__ void __launch_bounds__(1024) k_amr_reduce(const double* __restrict__ 
   }
 }
 
+// state carried to the next mesh: new leaf q takes
+// sum_e wgt[e] F[src[e]] / sum_e wgt[e] (0 with no entry), one thread per
+// leaf and velocity
+__global__ void __launch_bounds__(256) k_amr_remap(const int* __restrict__ sptr, const int* __restrict__ src,
+                                                  const double* __restrict__ wgt, int nleaf, int nvel,
+                                                  const double* __restrict__ from, double* __restrict__ to) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)nleaf * nvel) return;
+  const int q = (int)(t / nvel), p = (int)(t % nvel);
+  double acc = 0.0, W = 0.0;
+  for (int e = sptr[q]; e < sptr[q + 1]; ++e) {
+    acc += wgt[e] * from[(size_t)src[e] * nvel + p];
+    W += wgt[e];
+  }
+  to[t] = W > 0.0 ? acc / W : 0.0;
+}
+
 AmrArgs amr_args(cc_ctx* ctx, const double* in, double* out) {
   AmrArgs A;
   A.in = in; A.out = out; A.G = ctx->a3;
@@ -644,20 +824,27 @@ AmrArgs amr_args(cc_ctx* ctx, const double* in, double* out) {
   A.dt = ctx->dt;
   A.tau_coef = ctx->cfg.kn > 0.0 ? sqrt(M_PI) / 2.0 * ctx->cfg.kn * ctx->cfg.lref / sqrt(2.0) : 0.0;
   A.t_wall = ctx->body.t_wall;
+  A.om = ctx->body_state[5];
+  A.cx = ctx->body.center[0]; A.cy = ctx->body.center[1];
   return A;
 }
 
 typedef void (*amr_fn)(AmrArgs);
 
-struct AmrFns { amr_fn simple, reg, irr, mom; };
+struct AmrFns { amr_fn simple, reg, irr, irr_mv, mom; };
+
+template <int N>
+AmrFns amr_fns() {
+  return {k_amr_simple<N>, k_amr_step<N, false>, k_amr_step<N, true>, k_amr_step<N, true, true>, k_amr_mom<N>};
+}
 
 bool pick_amr(int N, AmrFns* f) {
   switch (N) {
-    case 4: *f = {k_amr_simple<4>, k_amr_step<4, false>, k_amr_step<4, true>, k_amr_mom<4>}; return true;
-    case 6: *f = {k_amr_simple<6>, k_amr_step<6, false>, k_amr_step<6, true>, k_amr_mom<6>}; return true;
-    case 8: *f = {k_amr_simple<8>, k_amr_step<8, false>, k_amr_step<8, true>, k_amr_mom<8>}; return true;
-    case 12: *f = {k_amr_simple<12>, k_amr_step<12, false>, k_amr_step<12, true>, k_amr_mom<12>}; return true;
-    case 16: *f = {k_amr_simple<16>, k_amr_step<16, false>, k_amr_step<16, true>, k_amr_mom<16>}; return true;
+    case 4: *f = amr_fns<4>(); return true;
+    case 6: *f = amr_fns<6>(); return true;
+    case 8: *f = amr_fns<8>(); return true;
+    case 12: *f = amr_fns<12>(); return true;
+    case 16: *f = amr_fns<16>(); return true;
     default: return false;
   }
 }
@@ -710,12 +897,12 @@ hipError_t launch_amr_step(cc_ctx* ctx, double* row) {
     e = hipEventRecord(ctx->fork, ctx->stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->fork, 0);
     if (e != hipSuccess) return e;
-    f.irr<<<A.per_irr * 8, 256, 0, ctx->side>>>(A);
+    (ctx->amr_turning ? f.irr_mv : f.irr)<<<A.per_irr * 8, 256, 0, ctx->side>>>(A);
     e = hipEventRecord(ctx->join, ctx->side);
     if (e != hipSuccess) return e;
   } else if (A.per_irr > 0) {
     prof_begin(ctx, 1);
-    f.irr<<<A.per_irr * 8, 256, 0, ctx->stream>>>(A);
+    (ctx->amr_turning ? f.irr_mv : f.irr)<<<A.per_irr * 8, 256, 0, ctx->stream>>>(A);
     prof_end(ctx, 1);
   }
   prof_begin(ctx, 0);
@@ -740,6 +927,16 @@ hipError_t launch_amr_step(cc_ctx* ctx, double* row) {
   ctx->cur = 1 - ctx->cur;
   ctx->nstep += 1;
   return hipSuccess;
+}
+
+hipError_t launch_amr_remap(cc_ctx* ctx, const double* from, double* to) {
+  const size_t tot = (size_t)ctx->a3.nleaf * ctx->nvel;
+  if (tot == 0) return hipSuccess;
+  prof_begin(ctx, 4);
+  k_amr_remap<<<(unsigned)((tot + 255) / 256), 256, 0, ctx->stream>>>(ctx->a3.sptr, ctx->a3.src, ctx->a3.wgt,
+                                                                      ctx->a3.nleaf, ctx->nvel, from, to);
+  prof_end(ctx, 4);
+  return hipGetLastError();
 }
 
 }  // namespace ccdvm

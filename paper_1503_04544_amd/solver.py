@@ -34,11 +34,11 @@ class Solver:
         self._check(lib().cc_workspace_bytes(h, C.byref(sb), C.byref(gb), C.byref(xb)))
         self.dim = cfg.dim
         self.ncell = cfg.n[0] * cfg.n[1] * cfg.n[2]
-        self.amr = getattr(cfg, "amr_depth", 0) > 0
-        if self.amr:   # octree mesh: the cells are the leaves
-            nl, nf = C.c_int(), C.c_int()
-            self._check(lib().cc_amr_counts(h, C.byref(nl), C.byref(nf)))
-            self.ncell, self.nface = nl.value, nf.value
+        # octree mesh (also every 3D body that turns): the cells are the leaves
+        self.turning = cfg.dim == 3 and cfg.body.motion != "fixed" and cfg.body.kind != "none"
+        self.amr = getattr(cfg, "amr_depth", 0) > 0 or self.turning
+        if self.amr:
+            self._refresh_counts()
         self.nvel = cfg.nv ** cfg.dim
         with torch.cuda.device(self.device):
             # caller-owned device buffers (uint8 tensors; 256-byte aligned by the caching allocator)
@@ -48,6 +48,11 @@ class Solver:
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self._check(lib().cc_bind(h, _ptr(self.state[0]), _ptr(self.state[1]), _ptr(self.geom),
                                       _ptr(self.scratch), C.c_void_p(self.stream.cuda_stream)))
+
+    def _refresh_counts(self):
+        nl, nf = C.c_int(), C.c_int()
+        self._check(lib().cc_amr_counts(self._h, C.byref(nl), C.byref(nf)))
+        self.ncell, self.nface = nl.value, nf.value
 
     def _check(self, st):
         if st != 0:
@@ -94,13 +99,17 @@ class Solver:
     # ---------------------------------------------------------------- stepping
     def step(self, nsteps: int = 1, diag: torch.Tensor | bool | None = None):
         """Advance nsteps; with diag=True returns a (nsteps, 4) device tensor of
-        (Fx, Fy, torque, mass) of the state at the start of each step."""
+        (Fx, Fy, torque, mass) of the state at the start of each step (3D fixed
+        body: (Fx, Fy, Fz, mass)).  A turning 3D body adapts the mesh every
+        step, so ncell (the leaf count) may change."""
         d = None
         if diag is True:
             d = torch.empty((nsteps, 4), dtype=torch.float64, device=self.device)
         elif isinstance(diag, torch.Tensor):
             d = diag
         self._check(lib().cc_step(self._h, int(nsteps), _ptr(d)))
+        if self.turning:
+            self._refresh_counts()
         return d
 
     def moments(self) -> torch.Tensor:

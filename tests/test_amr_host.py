@@ -80,3 +80,54 @@ def test_octree_configurations_rejected():
     nl = C.c_int()
     assert lib().cc_amr_counts(h, C.byref(nl), None) != 0   # a uniform grid is no octree
     lib().cc_destroy(h)
+
+
+VANE = Body("vane", (0.5, 0.5, 0.25), (0.2, 0.06, 0.12), theta=0.0, inertia=0.01,
+            motion="free_rotation", omega=20.0)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3927, 1.1, 2.0, -0.7])
+def test_builder_equals_oracle_for_the_vane(theta):
+    from ccdvm_inputs.configs import Config, _inflow
+    body = Body("vane", VANE.center, VANE.axes, theta=theta, inertia=0.01, motion="free_rotation", omega=20.0)
+    cfg = Config(dim=3, n=(8, 8, 4), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 0.5), nv=4, kn=0.1, inflow=_inflow(0.5),
+                 body=body, amr_depth=2)
+    st, h = create(cfg)
+    assert st == 0
+    try:
+        L, F = export(h)
+    finally:
+        from paper_1503_04544_amd._capi import lib
+        lib().cc_destroy(h)
+    o = Oracle3A(cfg)
+    Lo, Fo = o.leaves(), o.faces()
+    for k in ("lvl", "ijk", "type", "master"):
+        assert np.array_equal(L[k], Lo[k]), k
+    for k in ("vbar", "vcv", "sw", "S"):
+        assert close(L[k], Lo[k]), k
+    for k in ("ptr", "nb", "dir"):
+        assert np.array_equal(F[k], Fo[k]), k
+    assert close(F["area"], Fo["area"])
+    assert np.sum(Lo["type"] == 1) > 50
+
+
+def test_turning_configurations():
+    from ccdvm_inputs.configs import Config, _inflow
+    from paper_1503_04544_amd._capi import lib
+
+    def cfg(**b):
+        kw = dict(center=VANE.center, axes=VANE.axes, inertia=0.01, motion="free_rotation", omega=1.0)
+        kw.update(b)
+        return Config(dim=3, n=(8, 8, 4), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 0.5), nv=4, kn=0.1,
+                      inflow=_inflow(0.5), body=Body("vane", **kw), amr_depth=2)
+    # a turning body runs on the octree, also at depth 0 (the uniform grid)
+    for c in (cfg(), cfg().with_(amr_depth=0, n=(32, 32, 16))):
+        st, h = create(c)
+        assert st == 0
+        nl = C.c_int()
+        assert lib().cc_amr_counts(h, C.byref(nl), None) == 0 and nl.value > 0
+        lib().cc_destroy(h)
+    for bad in (cfg(vel=(0.1, 0.0, 0.0)), cfg(inertia=0.0), cfg(axes=(0.2, 0.0, 0.1)),
+                cfg().with_(model="shakhov"), cfg().with_(scheme="imex")):
+        st, h = create(bad)
+        assert st != 0 and not h.value
