@@ -35,6 +35,10 @@ WORKLOAD_TEXT = {
     "sphere_amr": "sphere_amr: 3D octree, 32x16x16 coarse cells on [0,1]x[0,0.5]^2 refined twice near "
                   "the sphere (1/128 there, as sphere128), 16^3 velocities, sphere r=0.1, Kn {kn}, "
                   "Mach 0.5, T_w 1, CFL 0.5, force every step",
+    "vane_amr": "vane_amr: 3D octree, 32x32x16 coarse cells on [0,1]^2x[0,0.5] refined twice near a "
+                "vane (plate 0.4x0.06x0.24 with rounded edges) turning freely about z (J=0.002, "
+                "omega0=2, theta0=pi/8), mesh adapted every step, 16^3 velocities, Kn {kn}, Mach 0.5, "
+                "T_w 1, CFL 0.5, torque every step",
 }
 # committed rocprofv3 counter summaries: workload -> (kernel source, summary)
 TRAFFIC = {
@@ -141,9 +145,10 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kn", type=float, default=None)
-    ap.add_argument("--workload", default="cyl512", choices=["cyl512", "ellipse256", "cyl32", "sphere128", "sphere_amr", "batch"],
+    ap.add_argument("--workload", default="cyl512",
+                    choices=["cyl512", "ellipse256", "cyl32", "sphere128", "sphere_amr", "vane_amr", "batch"],
                     help="cyl512 (default, the headline line) | ellipse256 (moving body) | cyl32 | "
-                         "sphere128 (3D) | sphere_amr (3D octree)")
+                         "sphere128 (3D) | sphere_amr (3D octree) | vane_amr (3D octree, turning body)")
     ap.add_argument("--maxwellian", default="direct", choices=["direct", "conservative"],
                     help="equilibrium of the relaxation: direct moments (default) or the conservative "
                          "Newton triplet")
@@ -189,6 +194,7 @@ def main():
     s = Solver(cfg, device=dev)
     n_irr, n_mem, n_solid = s.counts()
     active = s.ncell - n_solid   # cells, or the leaves of an octree
+    ncell0 = s.ncell
     nvel = cfg.nv ** cfg.dim
     s.init_maxwellian()
     diag = torch.empty((max(args.steps, args.warmup, 1), 4), dtype=torch.float64, device=dev)
@@ -215,8 +221,10 @@ def main():
     mrg_ms, mrg_n = s.profile_read(3)
     mom_ms, mom_n = s.profile_read(4)
     rlx_ms, rlx_n = s.profile_read(5)
+    plan_ms, plan_n = s.profile_read(6)
+    adapt_ms, adapt_n = s.profile_read(7)
     s.profile_enable(False)
-    amr = getattr(cfg, "amr_depth", 0) > 0
+    amr = s.amr
     # the uniform kernels stream the regular cells (cut control volumes have
     # their own kernel); the octree kernel updates every control volume
     n_regular = active - n_mem if amr else active - n_irr - n_mem
@@ -246,7 +254,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload].format(kn=cfg.kn),
-                   "cells": s.ncell, "active_cells": active, "velocities": nvel,
+                   "cells": ncell0, "active_cells": active, "velocities": nvel,
                    "cut_control_volumes": n_irr, "merged_cells": n_mem, "dt": s.dt,
                    "maxwellian": args.maxwellian, "scheme": args.scheme, "model": args.model,
                    "drag_last_step": drag_last},
@@ -259,7 +267,14 @@ def main():
                      "reduce_kernel_avg_us": round(red_ms / max(red_n, 1) * 1e3, 2),
                      "merge_kernel_avg_us": round(mrg_ms / max(mrg_n, 1) * 1e3, 2)},
     }
-    if cfg.dim == 3 or args.maxwellian == "conservative":
+    if s.turning:
+        # turning body: the host plans each step and adapts the mesh; the
+        # remap kernel carries the state to the new mesh
+        out["roofline"]["remap_kernel_avg_us"] = round(mom_ms / max(mom_n, 1) * 1e3, 2)
+        out["host"] = {"plan_ms_per_step": round(plan_ms / max(plan_n, 1), 3),
+                       "adapt_ms_per_step": round(adapt_ms / max(adapt_n, 1), 3),
+                       "note": "cells and active_cells are those of the initial mesh"}
+    elif cfg.dim == 3 or args.maxwellian == "conservative":
         # 3D: moments from the chunk sums (and the Newton triplet);
         # 2D conservative: the Newton pass between steps
         out["roofline"]["between_steps_kernel_avg_us"] = round(mom_ms / max(mom_n, 1) * 1e3, 2)

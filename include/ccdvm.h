@@ -120,9 +120,14 @@ typedef struct {
  * (Appendix A).  circle: axes[0] = radius; ellipse: semi-axes axes[0],
  * axes[1], rotated by theta about center; cavity: gas inside a circle of
  * radius axes[0]; halfplane: gas where (x - center).(cos theta, sin theta) > 0;
- * sphere (3D): axes[0] = radius.  t_wall: wall temperature.  motion:
- * fixed, free rotation about the centre driven by the gas torque (inertia),
- * or imposed constant velocity vel / angular velocity omega. */
+ * sphere (3D): axes[0] = radius; vane (3D): the points within
+ * r = min(axes) of the box of half-sizes axes - r (a plate with rounded
+ * edges), turned by theta about the z axis through center (exact signed
+ * distance).  t_wall: wall temperature.  motion: fixed, free rotation about
+ * the centre driven by the gas torque (inertia), or imposed constant
+ * velocity vel / angular velocity omega.  In 3D a moving body turns about
+ * the z axis through its centre (pure rotation, Section 5: vel must be 0);
+ * its walls move with omega e_z x (x - center). */
 typedef struct {
   int kind;
   double center[3], axes[3], theta, t_wall;
@@ -134,8 +139,10 @@ typedef struct {
 /* Validates the set-up, computes dt and the sizes of the device buffers.
  * No device work.  *out receives a new context (free with cc_destroy).
  * Returns CC_EINVAL for an unsupported set-up; in 3D the velocity box must
- * be symmetric about 0 and N one of 4, 6, 8, 12, 16, and the body a fixed
- * sphere (or none). */
+ * be symmetric about 0 and N one of 4, 6, 8, 12, 16, and the body a sphere
+ * or a vane (or none).  A turning 3D body runs on the octree mesh (any
+ * amr_depth; 0 is the uniform grid), whose buffers are sized here for the
+ * largest mesh over a half turn plus a quarter. */
 cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out);
 void cc_destroy(cc_ctx* ctx);
 const char* cc_last_error(const cc_ctx* ctx);
@@ -168,9 +175,18 @@ cc_status cc_store_state(const cc_ctx* ctx, double* f, double* g);
 /* Advances nsteps time steps.  diag (nullable device pointer, nsteps*4
  * doubles) receives, for each step n, the force (Fx, Fy), the torque about
  * the body centre and the total mass, all of the state at t^n (eqs.
- * eq-force, eq-torque, def-masse); in 3D the entries are (Fx, Fy, Fz, mass).
- * Asynchronous for fixed bodies; for a moving body the rigid-body update of
- * every step runs on the device as well. */
+ * eq-force, eq-torque, def-masse); in 3D the entries are (Fx, Fy, Fz, mass),
+ * for a turning body (Fx, Fy, torque about the z axis through the centre,
+ * mass).  Asynchronous for fixed bodies; for a moving 2D body the
+ * rigid-body update of every step runs on the device as well.  A turning
+ * 3D body (Section 5, steps 1-7, then the mesh adapted to the body) is
+ * driven by the host: each step plans the step on the mesh of t^n, runs the
+ * kernels, reads the torque back (one synchronisation per step), builds the
+ * mesh of t^{n+1} and carries the state over to it (0th-order
+ * prolongation, gas-volume weighted restriction); the leaf count may
+ * change (cc_amr_counts).  CC_EGEOM when the body leaves the refined band
+ * within one step or a leaf appearing at t^{n+1} finds no control volume;
+ * CC_ENOMEM when the adapted mesh outgrows the buffers. */
 cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag);
 
 /* Moments of every cell of the current state, eq. (MacroscopicDDv):
@@ -184,7 +200,8 @@ cc_status cc_moments(cc_ctx* ctx, double* out);
 cc_status cc_body_force(cc_ctx* ctx, double out[4]);
 
 /* Rigid-body state at the current time (synchronous): centre x, y,
- * angle, velocity x, y, angular velocity. */
+ * angle, velocity x, y, angular velocity (a turning 3D body: its angle and
+ * angular velocity about the z axis). */
 cc_status cc_body_state(cc_ctx* ctx, double out[6]);
 
 /* Applies one explicit Euler update of the body velocity with a given
@@ -219,7 +236,8 @@ cc_status cc_geometry_export3d(cc_ctx* ctx, int* type, int* master, double* sxm,
 cc_status cc_geometry_counts(cc_ctx* ctx, int* n_irregular, int* n_members,
                              int* n_solid);
 
-/* Octree mesh (3D, amr_depth > 0; Section 5, octree procedure).  The
+/* Octree mesh (3D, amr_depth > 0 or a turning body; Section 5, octree
+ * procedure).  The
  * coarse grid n is refined near the boundary: a cell of depth d is divided
  * in 8 while the distance from its centre to the boundary is below
  * amr_band * dx / 2^d (dx = largest coarse spacing) and d < amr_depth.  The
@@ -232,6 +250,8 @@ cc_status cc_geometry_counts(cc_ctx* ctx, int* n_irregular, int* n_members,
  * grid; cc_body_force and cc_geometry_export3d are not available.  The
  * octree runs the explicit BGK scheme with the direct equilibrium; dt comes
  * from the finest spacing.
+ * With a turning body the mesh follows the body and these report the mesh
+ * of the current state.
  * cc_amr_counts: leaves and face-list entries.
  * cc_amr_export (host arrays, each nullable): per leaf its depth, its
  * integer coordinates at that depth (3), type (0 gas, 1 cut, 2 solid),
@@ -255,10 +275,14 @@ cc_status cc_set_tile_rows(cc_ctx* ctx, int rows);
  * cc_profile_enable(ctx, 1) starts recording (cleared); cc_profile_read
  * returns, for kernel id k (0 = regular-cell step kernel, 1 = cut-cell
  * kernel, 2 = force/mass reduction, 3 = merge, 4 = pass between steps:
- * 3D moments and the conservative Newton solve, 5 = implicit relaxation of
- * the semi-implicit scheme), the summed
- * milliseconds and the number of launches since enabling (at most 4096
- * launches per kernel are recorded).  Reading synchronises the stream. */
+ * 3D moments and the conservative Newton solve, or a turning body's remap
+ * to the adapted mesh, 5 = implicit relaxation of the semi-implicit
+ * scheme), the summed milliseconds and the number of launches since
+ * enabling (at most 4096 launches per kernel are recorded); ids 6 and 7
+ * return the host time of a turning body's steps: the step planning (with
+ * its upload), and the wall time from the launch of the step kernels to
+ * the remap map (the new mesh is built on the host while the device runs
+ * the step).  Reading synchronises the stream. */
 cc_status cc_profile_enable(cc_ctx* ctx, int on);
 cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launches);
 

@@ -8,6 +8,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <future>
 #include <new>
 #include <string>
 #include <vector>
@@ -576,23 +578,32 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
   const double th = ctx->body_state[2], om = ctx->body_state[5];
   const double th1 = th + ctx->dt * om;
   std::string err;
+  auto t0 = std::chrono::steady_clock::now();
   if (!plan_amr_move(ctx->cfg, ctx->body, th1, H, err)) return fail(ctx, CC_EGEOM, err);
   HIPCHK(ctx, upload_amr_plan(ctx), "step plan upload");
+  auto t1 = std::chrono::steady_clock::now();
   cc_status st = prepare(ctx);
   if (st != CC_OK) return st;
   double* drow = row ? row : ctx->s.red + 4 * 128 + 4;
   HIPCHK(ctx, launch_amr_step(ctx, drow), "step");
+  // the mesh of t^{n+1} depends only on the angle of t^{n+1}: it is built
+  // on the host while the device runs the step
+  auto t2 = std::chrono::steady_clock::now();
+  AmrHost* N1 = new (std::nothrow) AmrHost();
+  if (!N1) return fail(ctx, CC_ENOMEM, "host allocation");
+  std::string err1;
+  auto built = std::async(std::launch::async, [&] { return build_octree_3d(ctx->cfg, ctx->body, th1, *N1, err1); });
   double tq = 0.0;
-  HIPCHK(ctx, hipMemcpyAsync(&tq, drow + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "torque copy");
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "step");
+  hipError_t he = hipMemcpyAsync(&tq, drow + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+  const bool ok1 = built.get();
+  if (he != hipSuccess) { delete N1; return hip_fail(ctx, he, "step"); }
+  if (!ok1) { delete N1; return fail(ctx, CC_EGEOM, err1); }
   // explicit Euler for the body: angle with the old angular velocity, the
   // angular velocity with the torque of t^n (free rotation)
   ctx->body_state[2] = th1;
   if (ctx->body.motion == CC_MOTION_FREE_ROTATION) ctx->body_state[5] = om + ctx->dt * tq / ctx->body.inertia;
-  // the mesh of t^{n+1} and the state carried over to it
-  AmrHost* N1 = new (std::nothrow) AmrHost();
-  if (!N1) return fail(ctx, CC_ENOMEM, "host allocation");
-  if (!build_octree_3d(ctx->cfg, ctx->body, th1, *N1, err)) { delete N1; return fail(ctx, CC_EGEOM, err); }
+  // the state carried over to the mesh of t^{n+1}
   AmrRemap R;
   build_amr_remap(H, *N1, ctx->cfg.amr_depth, R);
   if (N1->nleaf > H.cap_leaf || N1->nface > H.cap_face || (long long)R.src.size() > 2LL * H.cap_leaf) {
@@ -608,6 +619,13 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
            "remap upload");
     HIPCHK(ctx, hipMemcpyAsync(G.wgt, R.wgt.data(), R.wgt.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream),
            "remap upload");
+  }
+  auto t3 = std::chrono::steady_clock::now();
+  if (ctx->prof.on) {
+    ctx->prof.host_ms[0] += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    ctx->prof.host_ms[1] += std::chrono::duration<double, std::milli>(t3 - t2).count();
+    ctx->prof.host_count[0] += 1;
+    ctx->prof.host_count[1] += 1;
   }
   AmrHost* old = ctx->amrh;
   ctx->amrh = N1;
@@ -850,12 +868,19 @@ cc_status cc_profile_enable(cc_ctx* ctx, int on) {
   }
   P.on = on != 0;
   for (int k = 0; k < kProfKernels; ++k) P.count[k] = 0;
+  for (int k = 0; k < 2; ++k) { P.host_ms[k] = 0.0; P.host_count[k] = 0; }
   return CC_OK;
 }
 
 cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launches) {
-  if (!ctx || kernel < 0 || kernel >= kProfKernels) return CC_EINVAL;
+  if (!ctx || kernel < 0 || kernel >= kProfKernels + 2) return CC_EINVAL;
   Prof& P = ctx->prof;
+  if (kernel >= kProfKernels) {   // host time of a turning body's step
+    const int k = kernel - kProfKernels;
+    if (total_ms) *total_ms = P.host_ms[k];
+    if (launches) *launches = P.host_count[k];
+    return CC_OK;
+  }
   double tot = 0.0;
   if (P.count[kernel] > 0) HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "profile sync");
   for (int e = 0; e < P.count[kernel]; ++e) {

@@ -34,6 +34,7 @@ struct BodyDev {
   double cx, cy, cz;
   double a, b, c;
   double theta;
+  double ct, st;     // cos and sin of theta (3D vane), evaluated once on the host
   double t_wall;
 };
 
@@ -112,7 +113,8 @@ struct AmrHost {
   std::vector<int> cv, cvptr, cvmem; // control volumes: master leaf, members (CSR); regular first
   int nsimple = 0;                   // simple regular control volumes (one face entry per direction)
   int nreg = 0;                      // regular control volumes (one member, no wall face), simple first
-  std::vector<std::pair<uint64_t, int>> table;   // (depth, coordinates) key -> leaf, sorted
+  int nf[3] = {0, 0, 0};             // finest-level cells per axis
+  std::vector<int> fine;             // leaf containing each finest-level cell
   std::vector<uint64_t> zkey;        // Z-order key of each leaf's lower corner (ascending)
   // turning body, plan of the step from t^n (this mesh) to t^{n+1}
   std::vector<int> type1;            // leaf types with the body at t^{n+1}
@@ -180,6 +182,8 @@ struct Prof {
   bool on = false;
   std::vector<hipEvent_t> start[kProfKernels], stop[kProfKernels];
   int count[kProfKernels] = {0, 0, 0, 0, 0, 0};
+  double host_ms[2] = {0.0, 0.0};   // turning body: host planning, host mesh adaptation
+  int host_count[2] = {0, 0};
 };
 
 }  // namespace ccdvm

@@ -22,14 +22,15 @@ namespace ccdvm {
 //   sphere: radius B.a.
 //   vane: the points within r = min(a, b, c) of the box of half-sizes
 //     (a, b, c) - r in the body frame, turned by B.theta about the z axis
-//     through the centre (a plate with rounded edges).  With q = |p| - (a - r)
+//     through the centre (a plate with rounded edges); B.ct, B.st hold
+//     cos and sin of B.theta.  With q = |p| - (a - r)
 //     in the body frame the distance to the box is |max(q, 0)| outside and
 //     the largest component of q inside.
 __host__ __device__ inline double level_set_3d(const BodyDev& B, double x, double y, double z) {
   const double a = x - B.cx, b = y - B.cy, c = z - B.cz;
   if (B.kind == CC_BODY_SPHERE) return sqrt(a * a + b * b + c * c) - B.a;
   if (B.kind == CC_BODY_VANE) {
-    const double ct = cos(B.theta), st = sin(B.theta);
+    const double ct = B.ct, st = B.st;
     const double p[3] = {ct * a + st * b, -st * a + ct * b, c};
     const double ax[3] = {B.a, B.b, B.c};
     const double r = B.a < (B.b < B.c ? B.b : B.c) ? B.a : (B.b < B.c ? B.b : B.c);

@@ -243,6 +243,7 @@ hipError_t build_geometry_3d(cc_ctx* ctx) {
   B.cx = ctx->body.center[0]; B.cy = ctx->body.center[1]; B.cz = ctx->body.center[2];
   B.a = ctx->body.axes[0]; B.b = ctx->body.axes[1]; B.c = ctx->body.axes[2];
   B.theta = ctx->body.theta;
+  B.ct = cos(B.theta); B.st = sin(B.theta);
   B.t_wall = ctx->body.t_wall;
   hipError_t e = hipMemsetAsync(G.counts, 0, 4 * sizeof(int), s);
   if (e != hipSuccess) return e;

@@ -1,0 +1,85 @@
+// A small pool of host threads for the per-leaf loops of the octree
+// builder (one pool per process, created on first use and never destroyed:
+// its threads end with the process).  run(n, fn) calls fn(begin, end) over
+// chunks of [0, n) of kChunk items, chunk c on participant c % P (the
+// calling thread is participant 0), and returns when every participant is
+// done.  Every worker takes part in every call, so a call cannot start
+// before all workers have finished the previous one; calls from several
+// threads are serialised.
+#pragma once
+
+#include <algorithm>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+namespace ccdvm {
+
+class HostPool {
+ public:
+  static constexpr int kChunk = 64;
+
+  static HostPool& get() {
+    static HostPool* p = new HostPool();
+    return *p;
+  }
+
+  int participants() const { return nw_ + 1; }
+
+  void run(int n, const std::function<void(int, int)>& fn) {
+    if (n <= 0) return;
+    if (nw_ == 0 || n <= 2 * kChunk) { fn(0, n); return; }
+    std::lock_guard<std::mutex> serial(call_);
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      fn_ = &fn; n_ = n; pending_ = nw_;
+      ++gen_;
+    }
+    cv_.notify_all();
+    slice(0, fn, n);
+    std::unique_lock<std::mutex> lk(m_);
+    fin_.wait(lk, [&] { return pending_ == 0; });
+    fn_ = nullptr;
+  }
+
+ private:
+  HostPool() {
+    const unsigned hw = std::thread::hardware_concurrency();
+    nw_ = (int)std::max(1u, std::min(hw, 16u)) - 1;
+    for (int t = 1; t <= nw_; ++t) std::thread([this, t] { loop(t); }).detach();
+  }
+
+  void slice(int id, const std::function<void(int, int)>& f, int n) const {
+    const int P = nw_ + 1;
+    for (long long c = id; c * kChunk < n; c += P) f((int)(c * kChunk), (int)std::min<long long>(n, (c + 1) * kChunk));
+  }
+
+  void loop(int id) {
+    unsigned long long seen = 0;
+    for (;;) {
+      const std::function<void(int, int)>* f;
+      int n;
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] { return gen_ != seen; });
+        seen = gen_;
+        f = fn_;
+        n = n_;
+      }
+      slice(id, *f, n);
+      std::lock_guard<std::mutex> lk(m_);
+      if (--pending_ == 0) fin_.notify_all();
+    }
+  }
+
+  int nw_ = 0;
+  std::mutex m_, call_;
+  std::condition_variable cv_, fin_;
+  const std::function<void(int, int)>* fn_ = nullptr;
+  int n_ = 0, pending_ = 0;
+  unsigned long long gen_ = 0;
+};
+
+}  // namespace ccdvm

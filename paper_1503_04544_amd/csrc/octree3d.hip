@@ -29,6 +29,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -37,6 +38,7 @@
 #pragma clang fp contract(off)
 
 #include "cellgeom3d.h"
+#include "hostpool.h"
 
 namespace ccdvm {
 
@@ -55,15 +57,20 @@ uint64_t morton3(uint64_t i, uint64_t j, uint64_t k) {
   return spread_bits3(i) | (spread_bits3(j) << 1) | (spread_bits3(k) << 2);
 }
 
-uint64_t leaf_key(int l, int i, int j, int k) {
-  return ((uint64_t)l << 60) | ((uint64_t)i << 40) | ((uint64_t)j << 20) | (uint64_t)k;
+// the leaf containing the lower corner of the depth-l cell (i, j, k), or -1
+// outside the domain (from the finest-level map)
+int leaf_at(const AmrHost& H, int D, int l, int i, int j, int k) {
+  if (l < 0 || i < 0 || j < 0 || k < 0) return -1;
+  const int sh = D - l;
+  const long long I = (long long)i << sh, J = (long long)j << sh, K = (long long)k << sh;
+  if (I >= H.nf[0] || J >= H.nf[1] || K >= H.nf[2]) return -1;
+  return H.fine[(size_t)((K * H.nf[1] + J) * H.nf[0] + I)];
 }
 
-int find_leaf(const std::vector<std::pair<uint64_t, int>>& t, int l, int i, int j, int k) {
-  if (l < 0 || i < 0 || j < 0 || k < 0) return -1;
-  const uint64_t key = leaf_key(l, i, j, k);
-  auto it = std::lower_bound(t.begin(), t.end(), std::make_pair(key, -1));
-  return it != t.end() && it->first == key ? it->second : -1;
+// the leaf of depth l at (i, j, k), or -1
+int find_leaf(const AmrHost& H, int D, int l, int i, int j, int k) {
+  const int y = leaf_at(H, D, l, i, j, k);
+  return y >= 0 && H.lvl[y] == l ? y : -1;
 }
 
 BodyDev body_at(const cc_body& body, double theta) {
@@ -72,18 +79,48 @@ BodyDev body_at(const cc_body& body, double theta) {
   B.cx = body.center[0]; B.cy = body.center[1]; B.cz = body.center[2];
   B.a = body.axes[0]; B.b = body.axes[1]; B.c = body.axes[2];
   B.theta = theta;
+  B.ct = cos(theta); B.st = sin(theta);
   B.t_wall = body.t_wall;
   return B;
 }
 
+// Geometry of a cell of depth l far from the boundary (all 8 vertices on
+// one side): the per-cell construction gives the same tables whatever the
+// vertex values, so it is computed once per depth and side.
+struct FarCells {
+  CellGeo3 g[9][2];
+  FarCells(const AmrHost& H, int D) {
+    for (int l = 0; l <= D; ++l)
+      for (int gas = 0; gas < 2; ++gas) {
+        double h[3], q8[8];
+        for (int d = 0; d < 3; ++d) h[d] = H.hf[d] * (double)(1 << (D - l));
+        for (int t = 0; t < 8; ++t) q8[t] = gas ? 1.0 : -1.0;
+        cell_geometry_3d(q8, h, 1e-12 * H.hf[0], g[l][gas]);
+      }
+  }
+  const CellGeo3& get(int l, bool gas) const { return g[l][gas]; }
+};
+
 // geometry of leaf q with the body B: its 8 vertex values (clamped as on
 // the uniform grid) and the uniform grid's per-cell construction at the
-// leaf's size; A0 = lower corner in finest units
-void leaf_geometry(const cc_config& cfg, const AmrHost& H, const BodyDev& B, int q, CellGeo3& g, int A0[3]) {
+// leaf's size; A0 = lower corner in finest units.  The level sets are
+// signed distances (1-Lipschitz): a leaf whose centre is farther from the
+// boundary than its half-diagonal (with a margin far above rounding) has
+// all vertices on the centre's side and takes the far-cell tables.
+void leaf_geometry(const cc_config& cfg, const AmrHost& H, const BodyDev& B, int q, CellGeo3& g, int A0[3],
+                   const FarCells& far) {
   const int sh = cfg.amr_depth - H.lvl[q];
   for (int d = 0; d < 3; ++d) A0[d] = H.ijk[3 * (size_t)q + d] << sh;
   double q8[8], h[3];
   for (int d = 0; d < 3; ++d) h[d] = H.hf[d] * (double)(1 << sh);
+  const double pc = level_set_3d(B, cfg.lo[0] + (A0[0] + 0.5 * (1 << sh)) * H.hf[0],
+                                 cfg.lo[1] + (A0[1] + 0.5 * (1 << sh)) * H.hf[1],
+                                 cfg.lo[2] + (A0[2] + 0.5 * (1 << sh)) * H.hf[2]);
+  const double hd = 0.5 * sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+  if (fabs(pc) > hd * (1.0 + 1e-9) + 1e-12 * H.hf[0]) {
+    g = far.get(H.lvl[q], pc > 0.0);
+    return;
+  }
   for (int t = 0; t < 8; ++t) {
     const int a = A0[0] + ((t & 1) << sh), b = A0[1] + (((t >> 1) & 1) << sh), c = A0[2] + (((t >> 2) & 1) << sh);
     q8[t] = clamp_vertex(level_set_3d(B, cfg.lo[0] + a * H.hf[0], cfg.lo[1] + b * H.hf[1], cfg.lo[2] + c * H.hf[2]),
@@ -145,32 +182,43 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
   }
   const double Dx = std::max(h0[0], std::max(h0[1], h0[2]));
   const double band = cfg.amr_band > 0.0 ? cfg.amr_band : 2.0 * sqrt(2.0);
-  // refinement
+  HostPool& pool = HostPool::get();
+  // refinement of every coarse cell by the criterion (coarse cells in
+  // parallel; the leaves are ordered by their Z-order key afterwards)
   struct C4 { int l, i, j, k; };
-  std::vector<C4> stack, leaves;
-  for (int k = cfg.n[2] - 1; k >= 0; --k)
-    for (int j = cfg.n[1] - 1; j >= 0; --j)
-      for (int i = cfg.n[0] - 1; i >= 0; --i) stack.push_back({0, i, j, k});
-  while (!stack.empty()) {
-    const C4 c = stack.back();
-    stack.pop_back();
-    const double s = 1.0 / (double)(1 << c.l);
-    const double x = cfg.lo[0] + (c.i + 0.5) * h0[0] * s, y = cfg.lo[1] + (c.j + 0.5) * h0[1] * s,
-                 z = cfg.lo[2] + (c.k + 0.5) * h0[2] * s;
-    if (c.l < D && fabs(level_set_3d(B, x, y, z)) < band * Dx * s) {
-      for (int t = 7; t >= 0; --t)
-        stack.push_back({c.l + 1, 2 * c.i + (t & 1), 2 * c.j + ((t >> 1) & 1), 2 * c.k + ((t >> 2) & 1)});
-    } else {
-      leaves.push_back(c);
+  const int n0 = cfg.n[0] * cfg.n[1] * cfg.n[2];
+  std::vector<std::vector<C4>> part((n0 + HostPool::kChunk - 1) / HostPool::kChunk);
+  pool.run(n0, [&](int b, int e) {
+    std::vector<C4>& out = part[b / HostPool::kChunk];
+    std::vector<C4> stack;
+    for (int c0 = b; c0 < e; ++c0) {
+      stack.push_back({0, c0 % cfg.n[0], (c0 / cfg.n[0]) % cfg.n[1], c0 / (cfg.n[0] * cfg.n[1])});
+      while (!stack.empty()) {
+        const C4 c = stack.back();
+        stack.pop_back();
+        const double s = 1.0 / (double)(1 << c.l);
+        const double x = cfg.lo[0] + (c.i + 0.5) * h0[0] * s, y = cfg.lo[1] + (c.j + 0.5) * h0[1] * s,
+                     z = cfg.lo[2] + (c.k + 0.5) * h0[2] * s;
+        if (c.l < D && fabs(level_set_3d(B, x, y, z)) < band * Dx * s) {
+          for (int t = 7; t >= 0; --t)
+            stack.push_back({c.l + 1, 2 * c.i + (t & 1), 2 * c.j + ((t >> 1) & 1), 2 * c.k + ((t >> 2) & 1)});
+        } else {
+          out.push_back(c);
+        }
+      }
     }
-  }
+  });
+  std::vector<C4> leaves;
+  for (auto& v : part) leaves.insert(leaves.end(), v.begin(), v.end());
   const int n = (int)leaves.size();
   std::vector<std::pair<uint64_t, int>> order(n);
-  for (int q = 0; q < n; ++q) {
-    const C4& c = leaves[q];
-    const int sh = D - c.l;
-    order[q] = {morton3((uint64_t)c.i << sh, (uint64_t)c.j << sh, (uint64_t)c.k << sh), q};
-  }
+  pool.run(n, [&](int b, int e) {
+    for (int q = b; q < e; ++q) {
+      const C4& c = leaves[q];
+      const int sh = D - c.l;
+      order[q] = {morton3((uint64_t)c.i << sh, (uint64_t)c.j << sh, (uint64_t)c.k << sh), q};
+    }
+  });
   std::sort(order.begin(), order.end());
   H.nleaf = n;
   H.lvl.resize(n); H.ijk.resize(3 * (size_t)n); H.zkey.resize(n);
@@ -179,75 +227,101 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
     H.lvl[q] = c.l; H.ijk[3 * q] = c.i; H.ijk[3 * q + 1] = c.j; H.ijk[3 * q + 2] = c.k;
     H.zkey[q] = order[q].first;
   }
-  H.table.resize(n);
-  for (int q = 0; q < n; ++q)
-    H.table[q] = {leaf_key(H.lvl[q], H.ijk[3 * q], H.ijk[3 * q + 1], H.ijk[3 * q + 2]), q};
-  std::sort(H.table.begin(), H.table.end());
-  const auto& T = H.table;
+  // finest-level map: the leaf containing each finest cell
+  for (int d = 0; d < 3; ++d) H.nf[d] = cfg.n[d] << D;
+  H.fine.resize((size_t)H.nf[0] * H.nf[1] * H.nf[2]);   // every entry is written below
+  pool.run(n, [&](int b, int e) {
+    for (int q = b; q < e; ++q) {
+      const int sh = D - H.lvl[q], w = 1 << sh;
+      const size_t i0 = (size_t)H.ijk[3 * q] << sh, j0 = (size_t)H.ijk[3 * q + 1] << sh,
+                   k0 = (size_t)H.ijk[3 * q + 2] << sh;
+      for (size_t kk = k0; kk < k0 + w; ++kk)
+        for (size_t jj = j0; jj < j0 + w; ++jj) {
+          int* row = H.fine.data() + (kk * H.nf[1] + jj) * H.nf[0] + i0;
+          for (int ii = 0; ii < w; ++ii) row[ii] = q;
+        }
+    }
+  });
   // geometry of every leaf at its own size
   H.type.assign(n, 0); H.flags.assign(n, 0); H.S6.assign(6 * (size_t)n, 0.0);
   H.aw.assign(n, 0.0); H.nw.assign(3 * (size_t)n, 0.0); H.rw.assign(3 * (size_t)n, 0.0);
   H.vbar.assign(n, 0.0);
-  bool saddle = false, coarse_cut = false;
-  for (int q = 0; q < n; ++q) {
-    CellGeo3 g;
-    int A0[3];
-    leaf_geometry(cfg, H, B, q, g, A0);
-    if (g.flags & 2) saddle = true;
-    if (g.type == TYPE_CUT && H.lvl[q] < D) coarse_cut = true;
-    H.type[q] = g.type;
-    H.flags[q] = g.flags;
-    for (int f = 0; f < 6; ++f) H.S6[6 * q + f] = g.S[f];
-    H.aw[q] = g.aw;
-    for (int d = 0; d < 3; ++d) {
-      H.nw[3 * q + d] = g.n[d];
-      H.rw[3 * q + d] = g.aw > 0.0 ? cfg.lo[d] + A0[d] * H.hf[d] + g.r[d] : 0.0;
+  std::atomic<bool> saddle{false}, coarse_cut{false};
+  const FarCells far(H, D);
+  pool.run(n, [&](int b, int e) {
+    for (int q = b; q < e; ++q) {
+      CellGeo3 g;
+      int A0[3];
+      leaf_geometry(cfg, H, B, q, g, A0, far);
+      if (g.flags & 2) saddle = true;
+      if (g.type == TYPE_CUT && H.lvl[q] < D) coarse_cut = true;
+      H.type[q] = g.type;
+      H.flags[q] = g.flags;
+      for (int f = 0; f < 6; ++f) H.S6[6 * q + f] = g.S[f];
+      H.aw[q] = g.aw;
+      for (int d = 0; d < 3; ++d) {
+        H.nw[3 * q + d] = g.n[d];
+        H.rw[3 * q + d] = g.aw > 0.0 ? cfg.lo[d] + A0[d] * H.hf[d] + g.r[d] : 0.0;
+      }
+      H.vbar[q] = g.vbar;
     }
-    H.vbar[q] = g.vbar;
-  }
+  });
   if (saddle) { err = "a cell is cut twice by the boundary"; return false; }
   if (coarse_cut) { err = "a cut cell above the finest depth (refinement band too narrow)"; return false; }
-  // face lists
-  H.fptr.assign(n + 1, 0);
-  H.fnb.clear(); H.fdir.clear(); H.farea.clear();
-  bool jump = false;
-  for (int q = 0; q < n; ++q) {
-    H.fptr[q] = (int)H.fnb.size();
-    if (H.type[q] == TYPE_SOLID) continue;
+  // face lists: per leaf, in the order x-, x+, y-, y+, z-, z+, the leaf
+  // across (same depth or one coarser), the four of the next finer depth,
+  // or the farfield (-1); counted, then written, leaves in parallel
+  std::atomic<bool> jump{false};
+  auto faces_of = [&](int q, auto&& emit) {
+    if (H.type[q] == TYPE_SOLID) return;
     const int l = H.lvl[q];
     for (int t = 0; t < 6; ++t) {
-      const double A = H.S6[6 * q + t];
+      const double A = H.S6[6 * (size_t)q + t];
       if (A == 0.0) continue;
       const int d = t >> 1, sd = t & 1, d1 = (d + 1) % 3, d2 = (d + 2) % 3;
       int g[3] = {H.ijk[3 * q], H.ijk[3 * q + 1], H.ijk[3 * q + 2]};
       g[d] += sd ? 1 : -1;
-      auto add = [&](int nb, double area) {
-        H.fnb.push_back(nb); H.fdir.push_back(t); H.farea.push_back(area);
-      };
-      if (g[d] < 0 || g[d] >= (cfg.n[d] << l)) { add(-1, A); continue; }
-      int x = find_leaf(T, l, g[0], g[1], g[2]);
-      if (x < 0) x = find_leaf(T, l - 1, g[0] >> 1, g[1] >> 1, g[2] >> 1);
-      if (x >= 0) { add(x, A); continue; }
-      if (l == D) { jump = true; continue; }
+      if (g[d] < 0 || g[d] >= (cfg.n[d] << l)) { emit(-1, t, A); continue; }
+      const int x = leaf_at(H, D, l, g[0], g[1], g[2]);
+      if (H.lvl[x] == l || H.lvl[x] == l - 1) { emit(x, t, A); continue; }
+      if (H.lvl[x] < l) { jump = true; continue; }
       for (int b2 = 0; b2 < 2; ++b2)
         for (int b1 = 0; b1 < 2; ++b1) {
           int c[3];
           c[d] = 2 * g[d] + (sd ? 0 : 1); c[d1] = 2 * g[d1] + b1; c[d2] = 2 * g[d2] + b2;
-          const int y = find_leaf(T, l + 1, c[0], c[1], c[2]);
+          const int y = find_leaf(H, D, l + 1, c[0], c[1], c[2]);
           if (y < 0) { jump = true; continue; }
           const double Ay = H.S6[6 * (size_t)y + (t ^ 1)];
-          if (Ay != 0.0) add(y, Ay);
+          if (Ay != 0.0) emit(y, t, Ay);
         }
     }
-  }
-  H.fptr[n] = (int)H.fnb.size();
+  };
+  std::vector<int> fcount(n);
+  pool.run(n, [&](int b, int e) {
+    for (int q = b; q < e; ++q) {
+      int c = 0;
+      faces_of(q, [&](int, int, double) { ++c; });
+      fcount[q] = c;
+    }
+  });
+  H.fptr.assign(n + 1, 0);
+  for (int q = 0; q < n; ++q) H.fptr[q + 1] = H.fptr[q] + fcount[q];
   H.nface = H.fptr[n];
+  H.fnb.resize(H.nface); H.fdir.resize(H.nface); H.farea.resize(H.nface);
+  pool.run(n, [&](int b, int e) {
+    for (int q = b; q < e; ++q) {
+      int at = H.fptr[q];
+      faces_of(q, [&](int nb, int t, double A) { H.fnb[at] = nb; H.fdir[at] = t; H.farea[at] = A; ++at; });
+    }
+  });
   if (jump) { err = "neighbouring leaves differ by more than one depth"; return false; }
   // masters: centre in gas, else hop across the largest face shared with a
   // leaf of the same depth (order x+, x-, y+, y-, z+, z-), at most 4 hops
   H.master.assign(n, -1);
   const int dir_order[6] = {1, 0, 3, 2, 5, 4};
-  for (int q = 0; q < n; ++q) {
+  std::atomic<bool> master_bad{false};
+  pool.run(n, [&](int qb, int qe) {
+  for (int q = qb; q < qe; ++q) {
     if (H.type[q] == TYPE_SOLID) continue;
     int cur = q, hops = 0, seen[5] = {q, -1, -1, -1, -1};
     bool ok = true;
@@ -261,7 +335,7 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
         g[d] += (t & 1) ? 1 : -1;
         L[u] = 0.0; nb[u] = -1;
         if (g[d] < 0 || g[d] >= (cfg.n[d] << l)) continue;
-        nb[u] = find_leaf(T, l, g[0], g[1], g[2]);
+        nb[u] = find_leaf(H, D, l, g[0], g[1], g[2]);
         L[u] = H.S6[6 * (size_t)cur + t];
       }
       double M = 0.0;
@@ -277,9 +351,11 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
       if (!ok) break;
       seen[hops] = cur;
     }
-    if (!ok) { err = "master search cycles, leaves the domain, crosses a change of depth or needs more than 4 hops"; return false; }
+    if (!ok) { master_bad = true; continue; }
     H.master[q] = cur;
   }
+  });
+  if (master_bad) { err = "master search cycles, leaves the domain, crosses a change of depth or needs more than 4 hops"; return false; }
   for (int q = 0; q < n; ++q)
     if (H.master[q] >= 0 && H.master[H.master[q]] != H.master[q]) { err = "a master is not its own master"; return false; }
   if (!order_cvs(H, nullptr, err)) return false;
@@ -316,17 +392,20 @@ bool plan_amr_move(const cc_config& cfg, const cc_body& body, double th1, AmrHos
   const BodyDev B = body_at(body, th1);
   H.type1.assign(n, 0); H.vbar1.assign(n, 0.0);
   std::vector<double> S61(6 * (size_t)n);
-  bool saddle = false, coarse_cut = false;
-  for (int q = 0; q < n; ++q) {
-    CellGeo3 g;
-    int A0[3];
-    leaf_geometry(cfg, H, B, q, g, A0);
-    if (g.flags & 2) saddle = true;
-    if (g.type == TYPE_CUT && H.lvl[q] < D) coarse_cut = true;
-    H.type1[q] = g.type;
-    H.vbar1[q] = g.vbar;
-    for (int f = 0; f < 6; ++f) S61[6 * (size_t)q + f] = g.S[f];
-  }
+  std::atomic<bool> saddle{false}, coarse_cut{false};
+  const FarCells far(H, D);
+  HostPool::get().run(n, [&](int b, int e) {
+    for (int q = b; q < e; ++q) {
+      CellGeo3 g;
+      int A0[3];
+      leaf_geometry(cfg, H, B, q, g, A0, far);
+      if (g.flags & 2) saddle = true;
+      if (g.type == TYPE_CUT && H.lvl[q] < D) coarse_cut = true;
+      H.type1[q] = g.type;
+      H.vbar1[q] = g.vbar;
+      for (int f = 0; f < 6; ++f) S61[6 * (size_t)q + f] = g.S[f];
+    }
+  });
   if (saddle) { err = "a cell is cut twice by the boundary at the next time"; return false; }
   if (coarse_cut) { err = "the body moved out of the refined band within one step"; return false; }
   std::vector<int> target(H.master);
@@ -344,7 +423,7 @@ bool plan_amr_move(const cc_config& cfg, const cc_body& body, double th1, AmrHos
         g[d] += (t & 1) ? 1 : -1;
         nb[u] = -1; L[u] = 0.0;
         if (g[d] < 0 || g[d] >= (cfg.n[d] << l)) continue;
-        nb[u] = find_leaf(H.table, l, g[0], g[1], g[2]);
+        nb[u] = find_leaf(H, D, l, g[0], g[1], g[2]);
         L[u] = S61[6 * (size_t)cur + t];
         M = std::max(M, L[u]);
       }
@@ -405,9 +484,9 @@ void build_amr_remap(const AmrHost& O, const AmrHost& H, int depth, AmrRemap& R)
     R.sptr[q] = (int)R.src.size();
     if (H.type[q] == TYPE_SOLID) continue;
     const int l = H.lvl[q], i = H.ijk[3 * q], j = H.ijk[3 * q + 1], k = H.ijk[3 * q + 2];
-    int s = find_leaf(O.table, l, i, j, k);
-    for (int a = l - 1; s < 0 && a >= 0; --a) s = find_leaf(O.table, a, i >> (l - a), j >> (l - a), k >> (l - a));
-    if (s >= 0) { R.src.push_back(s); R.wgt.push_back(1.0); continue; }
+    // the old leaf at this leaf's corner: the same leaf or one containing it
+    const int s = leaf_at(O, depth, l, i, j, k);
+    if (O.lvl[s] <= l) { R.src.push_back(s); R.wgt.push_back(1.0); continue; }
     const int sh = depth - l;
     const uint64_t z0 = morton3((uint64_t)i << sh, (uint64_t)j << sh, (uint64_t)k << sh), z1 = z0 + (1ULL << (3 * sh));
     for (size_t r = std::lower_bound(O.zkey.begin(), O.zkey.end(), z0) - O.zkey.begin();
@@ -797,20 +876,27 @@ __global__ void __launch_bounds__(1024) k_amr_reduce(const double* __restrict__ 
 }
 
 // state carried to the next mesh: new leaf q takes
-// sum_e wgt[e] F[src[e]] / sum_e wgt[e] (0 with no entry), one thread per
-// leaf and velocity
+// sum_e wgt[e] F[src[e]] / sum_e wgt[e] (0 with no entry); one block per
+// leaf, its threads over the velocities (the entries are uniform over the
+// block)
 __global__ void __launch_bounds__(256) k_amr_remap(const int* __restrict__ sptr, const int* __restrict__ src,
-                                                  const double* __restrict__ wgt, int nleaf, int nvel,
+                                                  const double* __restrict__ wgt, int nvel,
                                                   const double* __restrict__ from, double* __restrict__ to) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)nleaf * nvel) return;
-  const int q = (int)(t / nvel), p = (int)(t % nvel);
-  double acc = 0.0, W = 0.0;
-  for (int e = sptr[q]; e < sptr[q + 1]; ++e) {
-    acc += wgt[e] * from[(size_t)src[e] * nvel + p];
-    W += wgt[e];
+  const int q = blockIdx.x;
+  const int e0 = sptr[q], e1 = sptr[q + 1];
+  double* dst = to + (size_t)q * nvel;
+  if (e1 - e0 == 1 && wgt[e0] == 1.0) {   // the same leaf, or one containing it: a copy
+    const double* a = from + (size_t)src[e0] * nvel;
+    for (int p = threadIdx.x; p < nvel; p += blockDim.x) dst[p] = 0.0 + 1.0 * a[p];
+    return;
   }
-  to[t] = W > 0.0 ? acc / W : 0.0;
+  double W = 0.0;
+  for (int e = e0; e < e1; ++e) W += wgt[e];
+  for (int p = threadIdx.x; p < nvel; p += blockDim.x) {
+    double acc = 0.0;
+    for (int e = e0; e < e1; ++e) acc += wgt[e] * from[(size_t)src[e] * nvel + p];
+    dst[p] = W > 0.0 ? acc / W : 0.0;
+  }
 }
 
 AmrArgs amr_args(cc_ctx* ctx, const double* in, double* out) {
@@ -930,11 +1016,9 @@ hipError_t launch_amr_step(cc_ctx* ctx, double* row) {
 }
 
 hipError_t launch_amr_remap(cc_ctx* ctx, const double* from, double* to) {
-  const size_t tot = (size_t)ctx->a3.nleaf * ctx->nvel;
-  if (tot == 0) return hipSuccess;
+  if (ctx->a3.nleaf == 0) return hipSuccess;
   prof_begin(ctx, 4);
-  k_amr_remap<<<(unsigned)((tot + 255) / 256), 256, 0, ctx->stream>>>(ctx->a3.sptr, ctx->a3.src, ctx->a3.wgt,
-                                                                      ctx->a3.nleaf, ctx->nvel, from, to);
+  k_amr_remap<<<ctx->a3.nleaf, 256, 0, ctx->stream>>>(ctx->a3.sptr, ctx->a3.src, ctx->a3.wgt, ctx->nvel, from, to);
   prof_end(ctx, 4);
   return hipGetLastError();
 }
