@@ -508,7 +508,10 @@ constexpr int kWaveA = 64;
 #define CCDVM_AMR_RC 4   // velocities per lane and pass of the general octree step
 #endif
 #ifndef CCDVM_AMR_RCS
-#define CCDVM_AMR_RCS 4  // velocities per lane and pass of the streaming octree step
+#define CCDVM_AMR_RCS 2  // velocities per lane and pass of the streaming octree step
+#endif
+#ifndef CCDVM_AMR_PIPE
+#define CCDVM_AMR_PIPE 2 // streaming octree step: passes of loads issued ahead of the computed one
 #endif
 
 __device__ inline double wsum(double v) {
@@ -755,10 +758,15 @@ __global__ void __launch_bounds__(256) k_amr_simple(AmrArgs A) {
     tz = exp(-(v - uz) * (v - uz) * inv2T);
   }
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int pass = 0; pass < (live ? NP : 0); ++pass) {
+  // passes of RC velocities per lane; the loads of pass k + CCDVM_AMR_PIPE
+  // are issued before pass k is computed (CCDVM_AMR_PIPE + 1 stages)
+  constexpr int ST = CCDVM_AMR_PIPE + 1;
+  double fo[ST][RC], fx[ST][RC], fy[ST][RC], fz[ST][RC];
+  auto load = [&](int pass, int st) {
+    // the lane id is laundered per pass so that the velocity constants of a
+    // pass are recomputed where used instead of being held across passes
     int lv = lane;
     asm volatile("" : "+v"(lv));
-    double fo[RC], fx[RC], fy[RC], fz[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
       const int p = (pass * RC + r) * kWaveA + lv;
@@ -767,27 +775,40 @@ __global__ void __launch_bounds__(256) k_amr_simple(AmrArgs A) {
       // upwind side: the x- face's leaf for v_x > 0, the x+ face's for v_x < 0
       const bool px = vnodeA(A.vmin, A.dv, p1) > 0.0, py = vnodeA(A.vmin, A.dv, p2) > 0.0,
                  pz = vnodeA(A.vmin, A.dv, p3) > 0.0;
-      fo[r] = in ? own[p] : 0.0;
-      fx[r] = in ? (px ? row[0] : row[1])[p] : 0.0;
-      fy[r] = in ? (py ? row[2] : row[3])[p] : 0.0;
-      fz[r] = in ? (pz ? row[4] : row[5])[p] : 0.0;
+      fo[st][r] = in ? own[p] : 0.0;
+      fx[st][r] = in ? (px ? row[0] : row[1])[p] : 0.0;
+      fy[st][r] = in ? (py ? row[2] : row[3])[p] : 0.0;
+      fz[st][r] = in ? (pz ? row[4] : row[5])[p] : 0.0;
     }
+  };
+  if (live) {
+#pragma unroll
+    for (int k = 0; k < ST - 1 && k < NP; ++k) load(k, k);
+  }
+#pragma unroll
+  for (int pass = 0; pass < NP; ++pass) {
+    if (!live) break;
+    const int st = pass % ST;
+    if (ST > 1 && pass + ST - 1 < NP) load(pass + ST - 1, (pass + ST - 1) % ST);
+    int lv = lane;
+    asm volatile("" : "+v"(lv));
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
       const int p = (pass * RC + r) * kWaveA + lv;
       if (p >= NV) continue;
       const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
       const double vx = vnodeA(A.vmin, A.dv, p1), vy = vnodeA(A.vmin, A.dv, p2), vz = vnodeA(A.vmin, A.dv, p3);
-      const double f = fo[r];
-      const double acc = (vx > 0.0 ? ar[0] : ar[1]) * fabs(vx) * (f - fx[r]) +
-                         (vy > 0.0 ? ar[2] : ar[3]) * fabs(vy) * (f - fy[r]) +
-                         (vz > 0.0 ? ar[4] : ar[5]) * fabs(vz) * (f - fz[r]);
+      const double f = fo[st][r];
+      const double acc = (vx > 0.0 ? ar[0] : ar[1]) * fabs(vx) * (f - fx[st][r]) +
+                         (vy > 0.0 ? ar[2] : ar[3]) * fabs(vy) * (f - fy[st][r]) +
+                         (vz > 0.0 ? ar[4] : ar[5]) * fabs(vz) * (f - fz[st][r]);
       const double E = Am * __shfl(tx, p1, kWaveA) * __shfl(ty, p2, kWaveA) * __shfl(tz, p3, kWaveA);
       const double fn = f - dtV * acc + dtau * (E - f);
       A.out[(size_t)m * NV + p] = fn;
       s[0] += fn; s[1] += vx * fn; s[2] += vy * fn; s[3] += vz * fn;
       s[4] += (vx * vx + vy * vy + vz * vz) * fn;
     }
+    if (ST == 1 && pass + 1 < NP) load(pass + 1, 0);
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) s[q] = wsum(s[q]);
