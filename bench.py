@@ -223,6 +223,7 @@ def main():
     rlx_ms, rlx_n = s.profile_read(5)
     plan_ms, plan_n = s.profile_read(6)
     adapt_ms, adapt_n = s.profile_read(7)
+    build_ms, build_n = s.profile_read(8)
     s.profile_enable(False)
     amr = s.amr
     # the uniform kernels stream the regular cells (cut control volumes have
@@ -273,6 +274,7 @@ def main():
         out["roofline"]["remap_kernel_avg_us"] = round(mom_ms / max(mom_n, 1) * 1e3, 2)
         out["host"] = {"plan_ms_per_step": round(plan_ms / max(plan_n, 1), 3),
                        "adapt_ms_per_step": round(adapt_ms / max(adapt_n, 1), 3),
+                       "mesh_build_ms_per_step": round(build_ms / max(build_n, 1), 3),
                        "note": "cells and active_cells are those of the initial mesh"}
     elif cfg.dim == 3 or args.maxwellian == "conservative":
         # 3D: moments from the chunk sums (and the Newton triplet);

@@ -278,11 +278,12 @@ cc_status cc_set_tile_rows(cc_ctx* ctx, int rows);
  * 3D moments and the conservative Newton solve, or a turning body's remap
  * to the adapted mesh, 5 = implicit relaxation of the semi-implicit
  * scheme), the summed milliseconds and the number of launches since
- * enabling (at most 4096 launches per kernel are recorded); ids 6 and 7
- * return the host time of a turning body's steps: the step planning (with
- * its upload), and the wall time from the launch of the step kernels to
- * the remap map (the new mesh is built on the host while the device runs
- * the step).  Reading synchronises the stream. */
+ * enabling (at most 4096 launches per kernel are recorded); ids 6, 7 and
+ * 8 return the host time of a turning body's steps: the step planning
+ * (with its upload), the wall time from the launch of the step kernels to
+ * the remap map, and the build of the new mesh alone (it runs on a host
+ * thread while the device runs the step).  Reading synchronises the
+ * stream. */
 cc_status cc_profile_enable(cc_ctx* ctx, int on);
 cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launches);
 

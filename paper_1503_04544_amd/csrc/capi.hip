@@ -28,6 +28,8 @@ hipError_t launch_moving_init_2d(cc_ctx* ctx);
 size_t adjoint_workspace_bytes(const cc_ctx* ctx, int nsteps, int K);
 hipError_t adjoint_run_2d(cc_ctx* ctx, int nsteps, int K, int objective, char* pool, double* out);
 hipError_t launch_imex_step_2d(cc_ctx* ctx, double* row);
+bool imex_fused_2d(const cc_ctx* ctx);
+hipError_t launch_imex_fused_2d(cc_ctx* ctx, bool reduce_prev, double* prev_force_row, double* cur_mass_row);
 }  // namespace ccdvm
 
 static bool is_moving(const cc_ctx* ctx) {
@@ -592,7 +594,13 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
   AmrHost* N1 = new (std::nothrow) AmrHost();
   if (!N1) return fail(ctx, CC_ENOMEM, "host allocation");
   std::string err1;
-  auto built = std::async(std::launch::async, [&] { return build_octree_3d(ctx->cfg, ctx->body, th1, *N1, err1); });
+  double build_ms = 0.0;
+  auto built = std::async(std::launch::async, [&] {
+    auto b0 = std::chrono::steady_clock::now();
+    const bool ok = build_octree_3d(ctx->cfg, ctx->body, th1, *N1, err1);
+    build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - b0).count();
+    return ok;
+  });
   double tq = 0.0;
   hipError_t he = hipMemcpyAsync(&tq, drow + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
@@ -624,16 +632,17 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
   if (ctx->prof.on) {
     ctx->prof.host_ms[0] += std::chrono::duration<double, std::milli>(t1 - t0).count();
     ctx->prof.host_ms[1] += std::chrono::duration<double, std::milli>(t3 - t2).count();
-    ctx->prof.host_count[0] += 1;
-    ctx->prof.host_count[1] += 1;
+    ctx->prof.host_ms[2] += build_ms;
+    for (int k = 0; k < 3; ++k) ctx->prof.host_count[k] += 1;
   }
   AmrHost* old = ctx->amrh;
   ctx->amrh = N1;
   ctx->ncell = N1->nleaf;
+  // copies from pageable host memory return once the data is staged, so
+  // the host vectors may change afterwards; the next step's planning on
+  // the host then overlaps the remap on the device
   hipError_t e = upload_amr_mesh(ctx);
   if (e == hipSuccess) e = launch_amr_remap(ctx, (const double*)ctx->state[ctx->cur], (double*)ctx->state[1 - ctx->cur]);
-  // the host vectors uploaded above must outlive the copies
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   delete old;
   if (e != hipSuccess) return hip_fail(ctx, e, "mesh adaptation");
   ctx->cur = 1 - ctx->cur;
@@ -670,6 +679,19 @@ cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
       hipError_t e = launch_step_3d(ctx, diag ? diag + 4 * (size_t)n : nullptr, nullptr);
       if (e != hipSuccess) return hip_fail(ctx, e, "step");
     }
+    return CC_OK;
+  }
+  if (ctx->cfg.scheme == CC_SCHEME_IMEX && imex_fused_2d(ctx)) {
+    // fused semi-implicit step; the force/mass partials of step n are
+    // reduced by step n+1, as in the explicit step
+    if (diag) HIPCHK(ctx, launch_mass_2d(ctx, diag + 3), "mass");
+    for (int n = 0; n < nsteps; ++n) {
+      bool red = diag && n > 0;
+      hipError_t e = launch_imex_fused_2d(ctx, red, red ? diag + 4 * (size_t)(n - 1) : nullptr,
+                                          red ? diag + 4 * (size_t)n + 3 : nullptr);
+      if (e != hipSuccess) return hip_fail(ctx, e, "step");
+    }
+    if (diag) HIPCHK(ctx, launch_step_2d_flush(ctx, diag + 4 * (size_t)(nsteps - 1), nullptr), "reduce");
     return CC_OK;
   }
   if (ctx->cfg.scheme == CC_SCHEME_IMEX) {
@@ -868,12 +890,12 @@ cc_status cc_profile_enable(cc_ctx* ctx, int on) {
   }
   P.on = on != 0;
   for (int k = 0; k < kProfKernels; ++k) P.count[k] = 0;
-  for (int k = 0; k < 2; ++k) { P.host_ms[k] = 0.0; P.host_count[k] = 0; }
+  for (int k = 0; k < 3; ++k) { P.host_ms[k] = 0.0; P.host_count[k] = 0; }
   return CC_OK;
 }
 
 cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launches) {
-  if (!ctx || kernel < 0 || kernel >= kProfKernels + 2) return CC_EINVAL;
+  if (!ctx || kernel < 0 || kernel >= kProfKernels + 3) return CC_EINVAL;
   Prof& P = ctx->prof;
   if (kernel >= kProfKernels) {   // host time of a turning body's step
     const int k = kernel - kProfKernels;

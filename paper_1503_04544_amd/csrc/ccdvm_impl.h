@@ -182,8 +182,8 @@ struct Prof {
   bool on = false;
   std::vector<hipEvent_t> start[kProfKernels], stop[kProfKernels];
   int count[kProfKernels] = {0, 0, 0, 0, 0, 0};
-  double host_ms[2] = {0.0, 0.0};   // turning body: host planning, host mesh adaptation
-  int host_count[2] = {0, 0};
+  double host_ms[3] = {0.0, 0.0, 0.0};   // turning body: planning, launch to remap map, mesh build
+  int host_count[3] = {0, 0, 0};
 };
 
 }  // namespace ccdvm

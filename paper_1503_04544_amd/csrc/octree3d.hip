@@ -47,10 +47,15 @@ namespace ccdvm {
 // ---------------------------------------------------------------------
 namespace {
 
+// bit b of x (b < 21) to bit 3b
 uint64_t spread_bits3(uint64_t x) {
-  uint64_t r = 0;
-  for (int b = 0; b < 21; ++b) r |= ((x >> b) & 1ULL) << (3 * b);
-  return r;
+  x &= 0x1fffffULL;
+  x = (x | x << 32) & 0x1f00000000ffffULL;
+  x = (x | x << 16) & 0x1f0000ff0000ffULL;
+  x = (x | x << 8) & 0x100f00f00f00f00fULL;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+  x = (x | x << 2) & 0x1249249249249249ULL;
+  return x;
 }
 
 uint64_t morton3(uint64_t i, uint64_t j, uint64_t k) {
@@ -183,15 +188,21 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
   const double Dx = std::max(h0[0], std::max(h0[1], h0[2]));
   const double band = cfg.amr_band > 0.0 ? cfg.amr_band : 2.0 * sqrt(2.0);
   HostPool& pool = HostPool::get();
-  // refinement of every coarse cell by the criterion (coarse cells in
-  // parallel; the leaves are ordered by their Z-order key afterwards)
+  // refinement of every coarse cell by the criterion, coarse cells in
+  // parallel and in Z-order, each walked depth first with the children in
+  // Z-order: the leaves come out in the Z-order of their lower corners
   struct C4 { int l, i, j, k; };
   const int n0 = cfg.n[0] * cfg.n[1] * cfg.n[2];
+  std::vector<std::pair<uint64_t, int>> corder(n0);
+  for (int c0 = 0; c0 < n0; ++c0)
+    corder[c0] = {morton3(c0 % cfg.n[0], (c0 / cfg.n[0]) % cfg.n[1], c0 / (cfg.n[0] * cfg.n[1])), c0};
+  std::sort(corder.begin(), corder.end());
   std::vector<std::vector<C4>> part((n0 + HostPool::kChunk - 1) / HostPool::kChunk);
   pool.run(n0, [&](int b, int e) {
     std::vector<C4>& out = part[b / HostPool::kChunk];
     std::vector<C4> stack;
-    for (int c0 = b; c0 < e; ++c0) {
+    for (int z0 = b; z0 < e; ++z0) {
+      const int c0 = corder[z0].second;
       stack.push_back({0, c0 % cfg.n[0], (c0 / cfg.n[0]) % cfg.n[1], c0 / (cfg.n[0] * cfg.n[1])});
       while (!stack.empty()) {
         const C4 c = stack.back();
@@ -208,25 +219,20 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
       }
     }
   });
-  std::vector<C4> leaves;
-  for (auto& v : part) leaves.insert(leaves.end(), v.begin(), v.end());
-  const int n = (int)leaves.size();
-  std::vector<std::pair<uint64_t, int>> order(n);
-  pool.run(n, [&](int b, int e) {
-    for (int q = b; q < e; ++q) {
-      const C4& c = leaves[q];
-      const int sh = D - c.l;
-      order[q] = {morton3((uint64_t)c.i << sh, (uint64_t)c.j << sh, (uint64_t)c.k << sh), q};
-    }
-  });
-  std::sort(order.begin(), order.end());
+  std::vector<int> pstart(part.size() + 1, 0);
+  for (size_t c = 0; c < part.size(); ++c) pstart[c + 1] = pstart[c] + (int)part[c].size();
+  const int n = pstart.back();
   H.nleaf = n;
   H.lvl.resize(n); H.ijk.resize(3 * (size_t)n); H.zkey.resize(n);
-  for (int q = 0; q < n; ++q) {
-    const C4& c = leaves[order[q].second];
-    H.lvl[q] = c.l; H.ijk[3 * q] = c.i; H.ijk[3 * q + 1] = c.j; H.ijk[3 * q + 2] = c.k;
-    H.zkey[q] = order[q].first;
-  }
+  pool.run((int)part.size(), [&](int b, int e) {
+    for (int c = b; c < e; ++c)
+      for (size_t t = 0; t < part[c].size(); ++t) {
+        const C4& l = part[c][t];
+        const int q = pstart[c] + (int)t, sh = D - l.l;
+        H.lvl[q] = l.l; H.ijk[3 * q] = l.i; H.ijk[3 * q + 1] = l.j; H.ijk[3 * q + 2] = l.k;
+        H.zkey[q] = morton3((uint64_t)l.i << sh, (uint64_t)l.j << sh, (uint64_t)l.k << sh);
+      }
+  });
   // finest-level map: the leaf containing each finest cell
   for (int d = 0; d < 3; ++d) H.nf[d] = cfg.n[d] << D;
   H.fine.resize((size_t)H.nf[0] * H.nf[1] * H.nf[2]);   // every entry is written below
@@ -296,22 +302,29 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
         }
     }
   };
-  std::vector<int> fcount(n);
+  // one pass into per-chunk lists (chunks are ranges of leaves), then
+  // concatenated in leaf order
+  struct FaceChunk { std::vector<int> nb, dir; std::vector<double> area; };
+  std::vector<FaceChunk> fch((n + HostPool::kChunk - 1) / HostPool::kChunk);
+  H.fptr.assign(n + 1, 0);
   pool.run(n, [&](int b, int e) {
+    FaceChunk& F = fch[b / HostPool::kChunk];
+    F.nb.reserve(7 * (size_t)(e - b)); F.dir.reserve(7 * (size_t)(e - b)); F.area.reserve(7 * (size_t)(e - b));
     for (int q = b; q < e; ++q) {
-      int c = 0;
-      faces_of(q, [&](int, int, double) { ++c; });
-      fcount[q] = c;
+      const size_t before = F.nb.size();
+      faces_of(q, [&](int nb, int t, double A) { F.nb.push_back(nb); F.dir.push_back(t); F.area.push_back(A); });
+      H.fptr[q + 1] = (int)(F.nb.size() - before);
     }
   });
-  H.fptr.assign(n + 1, 0);
-  for (int q = 0; q < n; ++q) H.fptr[q + 1] = H.fptr[q] + fcount[q];
+  for (int q = 0; q < n; ++q) H.fptr[q + 1] += H.fptr[q];
   H.nface = H.fptr[n];
   H.fnb.resize(H.nface); H.fdir.resize(H.nface); H.farea.resize(H.nface);
-  pool.run(n, [&](int b, int e) {
-    for (int q = b; q < e; ++q) {
-      int at = H.fptr[q];
-      faces_of(q, [&](int nb, int t, double A) { H.fnb[at] = nb; H.fdir[at] = t; H.farea[at] = A; ++at; });
+  pool.run((int)fch.size(), [&](int b, int e) {
+    for (int c = b; c < e; ++c) {
+      const int at = H.fptr[c * HostPool::kChunk];
+      std::copy(fch[c].nb.begin(), fch[c].nb.end(), H.fnb.begin() + at);
+      std::copy(fch[c].dir.begin(), fch[c].dir.end(), H.fdir.begin() + at);
+      std::copy(fch[c].area.begin(), fch[c].area.end(), H.farea.begin() + at);
     }
   });
   if (jump) { err = "neighbouring leaves differ by more than one depth"; return false; }
@@ -479,23 +492,44 @@ bool plan_amr_move(const cc_config& cfg, const cc_body& body, double th1, AmrHos
 void build_amr_remap(const AmrHost& O, const AmrHost& H, int depth, AmrRemap& R) {
   const int n = H.nleaf;
   R.sptr.assign(n + 1, 0);
-  R.src.clear(); R.wgt.clear();
-  for (int q = 0; q < n; ++q) {
-    R.sptr[q] = (int)R.src.size();
-    if (H.type[q] == TYPE_SOLID) continue;
-    const int l = H.lvl[q], i = H.ijk[3 * q], j = H.ijk[3 * q + 1], k = H.ijk[3 * q + 2];
-    // the old leaf at this leaf's corner: the same leaf or one containing it
-    const int s = leaf_at(O, depth, l, i, j, k);
-    if (O.lvl[s] <= l) { R.src.push_back(s); R.wgt.push_back(1.0); continue; }
-    const int sh = depth - l;
-    const uint64_t z0 = morton3((uint64_t)i << sh, (uint64_t)j << sh, (uint64_t)k << sh), z1 = z0 + (1ULL << (3 * sh));
-    for (size_t r = std::lower_bound(O.zkey.begin(), O.zkey.end(), z0) - O.zkey.begin();
-         r < O.zkey.size() && O.zkey[r] < z1; ++r) {
-      R.src.push_back((int)r);
-      R.wgt.push_back(O.vbar1[r]);
+  // entries of each chunk of new leaves (chunks are leaf ranges), then
+  // concatenated in leaf order
+  struct Chunk { std::vector<int> src; std::vector<double> wgt; };
+  std::vector<Chunk> ch((n + HostPool::kChunk - 1) / HostPool::kChunk);
+  HostPool& pool = HostPool::get();
+  pool.run(n, [&](int b, int e) {
+    Chunk& C = ch[b / HostPool::kChunk];
+    for (int q = b; q < e; ++q) {
+      const size_t before = C.src.size();
+      if (H.type[q] != TYPE_SOLID) {
+        const int l = H.lvl[q], i = H.ijk[3 * q], j = H.ijk[3 * q + 1], k = H.ijk[3 * q + 2];
+        // the old leaf at this leaf's corner: the same leaf or one containing it
+        const int s = leaf_at(O, depth, l, i, j, k);
+        if (O.lvl[s] <= l) {
+          C.src.push_back(s); C.wgt.push_back(1.0);
+        } else {
+          const int sh = depth - l;
+          const uint64_t z0 = morton3((uint64_t)i << sh, (uint64_t)j << sh, (uint64_t)k << sh),
+                         z1 = z0 + (1ULL << (3 * sh));
+          for (size_t r = std::lower_bound(O.zkey.begin(), O.zkey.end(), z0) - O.zkey.begin();
+               r < O.zkey.size() && O.zkey[r] < z1; ++r) {
+            C.src.push_back((int)r);
+            C.wgt.push_back(O.vbar1[r]);
+          }
+        }
+      }
+      R.sptr[q + 1] = (int)(C.src.size() - before);
     }
-  }
-  R.sptr[n] = (int)R.src.size();
+  });
+  for (int q = 0; q < n; ++q) R.sptr[q + 1] += R.sptr[q];
+  R.src.resize(R.sptr[n]); R.wgt.resize(R.sptr[n]);
+  pool.run((int)ch.size(), [&](int b, int e) {
+    for (int c = b; c < e; ++c) {
+      const int at = R.sptr[c * HostPool::kChunk];
+      std::copy(ch[c].src.begin(), ch[c].src.end(), R.src.begin() + at);
+      std::copy(ch[c].wgt.begin(), ch[c].wgt.end(), R.wgt.begin() + at);
+    }
+  });
 }
 
 // ---------------------------------------------------------------------

@@ -1002,7 +1002,8 @@ template <bool SK>
 __global__ void __launch_bounds__(256) k_relax_cut2d(Geo2D G, double2* __restrict__ st,
                                                     double* __restrict__ mom,
                                                     double* __restrict__ heat,
-                                                    const double* __restrict__ nu, StepParams P) {
+                                                    const double* __restrict__ nu,
+                                                    double* __restrict__ mpart, StepParams P) {
   __shared__ double lds[8];
   const int q = blockIdx.x;
   const int m = G.irr[q];
@@ -1034,6 +1035,7 @@ __global__ void __launch_bounds__(256) k_relax_cut2d(Geo2D G, double2* __restric
       for (int i = 0; i < 4; ++i) mom[4 * k + i] = mo[i];
       if (SK) { heat[2 * k] = hq[0]; heat[2 * k + 1] = hq[1]; }
     }
+    mpart[q] = G.scv[m] * mo[0];   // mass of the new value (replaces the transported one)
   }
 }
 
@@ -1590,28 +1592,6 @@ hipError_t launch_imex_step_2d(cc_ctx* ctx, double* row) {
                                           nullptr, row + 3);
   k_imex_nu2d<<<(ctx->ncell + 255) / 256, 256, 0, s>>>(ctx->g2, ctx->s.mom, ctx->s.nu, P.dt, P.tau_coef);
   const int par = ctx->step_parity;
-  // Direct equilibrium: the streaming kernel relaxes the regular cells right
-  // after their transport; the cut kernel only transports, and the cut and
-  // merged control volumes are relaxed afterwards.
-  if (ctx->cfg.maxwellian != CC_MAXW_CONSERVATIVE && pick_fused(chunks_per_half(ctx), P.shakhov, true)) {
-    hipError_t e = launch_step_2d_fused(ctx, false, nullptr, nullptr, false, true, true);
-    if (e != hipSuccess) return e;
-    if (row) {
-      const double* fs = ctx->s.fslot + (par ? 3 * (size_t)ctx->ncell : 0);
-      k_reduce2d<<<kRedBlocks, 256, 0, s>>>(ctx->g2, ctx->s.mom, fs, ctx->s.red, ticket, row, nullptr);
-    }
-    if (ctx->n_irr > 0) {
-      prof_begin(ctx, 5);
-      if (P.shakhov)
-        k_relax_cut2d<true><<<ctx->n_irr, 256, 0, s>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
-                                                        ctx->s.heat, ctx->s.nu, P);
-      else
-        k_relax_cut2d<false><<<ctx->n_irr, 256, 0, s>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
-                                                         nullptr, ctx->s.nu, P);
-      prof_end(ctx, 5);
-    }
-    return hipGetLastError();
-  }
   // transport: the step kernels without relaxation (the force of t^n is
   // computed by the cut kernel into this parity's slots)
   hipError_t e = launch_step_2d_fused(ctx, false, nullptr, nullptr, false, false);
@@ -1638,6 +1618,39 @@ hipError_t launch_imex_step_2d(cc_ctx* ctx, double* row) {
   }
   return hipMemcpyAsync(ctx->s.mom, ctx->s.mom2, (size_t)ctx->ncell * 4 * sizeof(double),
                         hipMemcpyDeviceToDevice, s);
+}
+
+bool imex_fused_2d(const cc_ctx* ctx) {
+  return ctx->cfg.maxwellian != CC_MAXW_CONSERVATIVE &&
+         pick_fused(chunks_per_half(ctx), ctx->cfg.model == CC_MODEL_SHAKHOV, true) != nullptr;
+}
+
+// One semi-implicit step with the direct equilibrium (ImpSchemeDD): the
+// streaming kernel relaxes the regular cells right after their transport;
+// the cut kernel only transports, and the cut and merged control volumes
+// are relaxed afterwards (their mass partials replaced by those of the new
+// value).  The force and mass rows are reduced as in the explicit step:
+// by block 0 of the next step's streaming kernel, and by
+// launch_step_2d_flush after the last one.
+hipError_t launch_imex_fused_2d(cc_ctx* ctx, bool reduce_prev, double* prev_force_row, double* cur_mass_row) {
+  hipStream_t s = ctx->stream;
+  StepParams P = params2d(ctx);
+  k_imex_nu2d<<<(ctx->ncell + 255) / 256, 256, 0, s>>>(ctx->g2, ctx->s.mom, ctx->s.nu, P.dt, P.tau_coef);
+  hipError_t e = launch_step_2d_fused(ctx, reduce_prev, prev_force_row, cur_mass_row, true, true, true);
+  if (e != hipSuccess) return e;
+  if (ctx->n_irr > 0) {
+    const int par = 1 - ctx->step_parity;   // parity of the step just launched
+    double* mp = ctx->s.mpart + (par ? (size_t)ctx->s.mpart_cap : 0) + ctx->last_args_ntiles;
+    prof_begin(ctx, 5);
+    if (P.shakhov)
+      k_relax_cut2d<true><<<ctx->n_irr, 256, 0, s>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
+                                                      ctx->s.heat, ctx->s.nu, mp, P);
+    else
+      k_relax_cut2d<false><<<ctx->n_irr, 256, 0, s>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
+                                                       nullptr, ctx->s.nu, mp, P);
+    prof_end(ctx, 5);
+  }
+  return hipGetLastError();
 }
 
 // mass of the current state into mass_row (no force)
