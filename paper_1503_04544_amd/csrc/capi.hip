@@ -356,6 +356,7 @@ void cc_destroy(cc_ctx* ctx) {
   if (ctx->join) hipEventDestroy(ctx->join);
   if (ctx->side) hipStreamDestroy(ctx->side);
   delete ctx->amrh;
+  delete ctx->amr_spare;
   delete ctx;
 }
 
@@ -591,13 +592,15 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
   // the mesh of t^{n+1} depends only on the angle of t^{n+1}: it is built
   // on the host while the device runs the step
   auto t2 = std::chrono::steady_clock::now();
-  AmrHost* N1 = new (std::nothrow) AmrHost();
+  // the mesh of two steps ago is recycled (its vectors keep their capacity)
+  AmrHost* N1 = ctx->amr_spare ? ctx->amr_spare : new (std::nothrow) AmrHost();
+  ctx->amr_spare = nullptr;
   if (!N1) return fail(ctx, CC_ENOMEM, "host allocation");
   std::string err1;
   double build_ms = 0.0;
   auto built = std::async(std::launch::async, [&] {
     auto b0 = std::chrono::steady_clock::now();
-    const bool ok = build_octree_3d(ctx->cfg, ctx->body, th1, *N1, err1);
+    const bool ok = build_octree_3d(ctx->cfg, ctx->body, th1, *N1, err1, &H);
     build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - b0).count();
     return ok;
   });
@@ -643,7 +646,7 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
   // the host then overlaps the remap on the device
   hipError_t e = upload_amr_mesh(ctx);
   if (e == hipSuccess) e = launch_amr_remap(ctx, (const double*)ctx->state[ctx->cur], (double*)ctx->state[1 - ctx->cur]);
-  delete old;
+  ctx->amr_spare = old;
   if (e != hipSuccess) return hip_fail(ctx, e, "mesh adaptation");
   ctx->cur = 1 - ctx->cur;
   ctx->n_irr = N1->n_irr; ctx->n_members = N1->n_members; ctx->n_solid = N1->n_solid;

@@ -119,6 +119,8 @@ struct AmrHost {
   // turning body, plan of the step from t^n (this mesh) to t^{n+1}
   std::vector<int> type1;            // leaf types with the body at t^{n+1}
   std::vector<double> vbar1;         // leaf gas volumes at t^{n+1}
+  std::vector<int> flags1;           // the rest of the leaves' geometry at t^{n+1}, reused by
+  std::vector<double> S61, aw1, nw1, r1;   // the build of the mesh of t^{n+1}
   std::vector<double> vnew;          // per master: its control volume's volume at t^{n+1}
   std::vector<int> rptr, rmem;       // per control volume (cv order): leaves receiving its value
   // capacities of the device arrays (the largest mesh a turning body is expected to need)
@@ -214,6 +216,7 @@ struct cc_ctx {
   bool amr = false;                 // 3D octree mesh
   bool amr_turning = false;         // octree with a body turning about the z axis
   ccdvm::AmrHost* amrh = nullptr;
+  ccdvm::AmrHost* amr_spare = nullptr;   // turning body: the previous mesh, rebuilt into next step
   ccdvm::AmrDev a3{};
   hipStream_t side = nullptr;        // octree: cut control volumes run beside the others
   hipEvent_t fork = nullptr, join = nullptr;
@@ -286,7 +289,10 @@ hipError_t launch_moments_out_3d(cc_ctx* ctx, double* out);
 int chunks3d(int N);   // velocity chunks of the 3D regular-cell pass (0: unsupported N)
 
 // octree mesh (octree3d.hip)
-bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, AmrHost& H, std::string& err);
+// prev (nullable): a mesh whose plan holds the geometry of its leaves at the
+// same angle, reused for the leaves both meshes share
+bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, AmrHost& H, std::string& err,
+                     const AmrHost* prev = nullptr);
 bool plan_amr_move(const cc_config& cfg, const cc_body& body, double th1, AmrHost& H, std::string& err);
 void build_amr_remap(const AmrHost& old_mesh, const AmrHost& new_mesh, int depth, AmrRemap& R);
 hipError_t launch_amr_remap(cc_ctx* ctx, const double* from, double* to);

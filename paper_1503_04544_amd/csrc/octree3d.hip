@@ -151,13 +151,22 @@ bool order_cvs(AmrHost& H, const std::vector<char>* changed, std::string& err) {
     for (int t = 0; t < 6; ++t) if (H.fdir[H.fptr[q] + t] != t) return 1;
     return 0;
   };
+  // kind of every master (-1 for other leaves), leaves in parallel
+  std::vector<signed char> kind(n);
+  std::atomic<bool> too_many{false};
+  HostPool::get().run(n, [&](int b, int e) {
+    for (int q = b; q < e; ++q) {
+      kind[q] = H.master[q] == q ? (signed char)kind_of(q) : (signed char)-1;
+      if (H.master[q] == q && cnt[q] > kMaxMembers) too_many = true;
+    }
+  });
+  if (too_many) { err = "a control volume has more members than supported"; return false; }
   H.nsimple = 0; H.nreg = 0;
+  H.cv.reserve(n); H.cvptr.reserve(n + 1);
   for (int pass = 0; pass < 3; ++pass)
     for (int q = 0; q < n; ++q)
-      if (H.master[q] == q) {
-        if (cnt[q] > kMaxMembers) { err = "a control volume has more members than supported"; return false; }
-        const int kd = kind_of(q);
-        if (kd != pass) continue;
+      if (kind[q] == pass) {
+        const int kd = pass;
         H.nsimple += kd == 0;
         H.nreg += kd <= 1;
         slot[q] = (int)H.cv.size();
@@ -176,7 +185,8 @@ bool order_cvs(AmrHost& H, const std::vector<char>* changed, std::string& err) {
 
 }  // namespace
 
-bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, AmrHost& H, std::string& err) {
+bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, AmrHost& H, std::string& err,
+                     const AmrHost* prev) {
   const int D = cfg.amr_depth;
   const BodyDev B = body_at(body, theta);
   double h0[3];
@@ -249,16 +259,28 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
     }
   });
   // geometry of every leaf at its own size
-  H.type.assign(n, 0); H.flags.assign(n, 0); H.S6.assign(6 * (size_t)n, 0.0);
-  H.aw.assign(n, 0.0); H.nw.assign(3 * (size_t)n, 0.0); H.rw.assign(3 * (size_t)n, 0.0);
-  H.vbar.assign(n, 0.0);
+  // (every entry is written below; a recycled mesh keeps its capacity)
+  H.type.resize(n); H.flags.resize(n); H.S6.resize(6 * (size_t)n);
+  H.aw.resize(n); H.nw.resize(3 * (size_t)n); H.rw.resize(3 * (size_t)n);
+  H.vbar.resize(n);
   std::atomic<bool> saddle{false}, coarse_cut{false};
   const FarCells far(H, D);
   pool.run(n, [&](int b, int e) {
     for (int q = b; q < e; ++q) {
       CellGeo3 g;
       int A0[3];
-      leaf_geometry(cfg, H, B, q, g, A0, far);
+      // a leaf of the previous mesh planned at this angle: its geometry
+      // is already known (same construction, same inputs)
+      const int r = prev ? find_leaf(*prev, D, H.lvl[q], H.ijk[3 * q], H.ijk[3 * q + 1], H.ijk[3 * q + 2]) : -1;
+      if (r >= 0) {
+        const int sh = D - H.lvl[q];
+        for (int d = 0; d < 3; ++d) A0[d] = H.ijk[3 * (size_t)q + d] << sh;
+        g.type = prev->type1[r]; g.flags = prev->flags1[r]; g.aw = prev->aw1[r]; g.vbar = prev->vbar1[r];
+        for (int f = 0; f < 6; ++f) g.S[f] = prev->S61[6 * (size_t)r + f];
+        for (int d = 0; d < 3; ++d) { g.n[d] = prev->nw1[3 * (size_t)r + d]; g.r[d] = prev->r1[3 * (size_t)r + d]; }
+      } else {
+        leaf_geometry(cfg, H, B, q, g, A0, far);
+      }
       if (g.flags & 2) saddle = true;
       if (g.type == TYPE_CUT && H.lvl[q] < D) coarse_cut = true;
       H.type[q] = g.type;
@@ -306,7 +328,8 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
   // concatenated in leaf order
   struct FaceChunk { std::vector<int> nb, dir; std::vector<double> area; };
   std::vector<FaceChunk> fch((n + HostPool::kChunk - 1) / HostPool::kChunk);
-  H.fptr.assign(n + 1, 0);
+  H.fptr.resize(n + 1);
+  H.fptr[0] = 0;
   pool.run(n, [&](int b, int e) {
     FaceChunk& F = fch[b / HostPool::kChunk];
     F.nb.reserve(7 * (size_t)(e - b)); F.dir.reserve(7 * (size_t)(e - b)); F.area.reserve(7 * (size_t)(e - b));
@@ -330,11 +353,12 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
   if (jump) { err = "neighbouring leaves differ by more than one depth"; return false; }
   // masters: centre in gas, else hop across the largest face shared with a
   // leaf of the same depth (order x+, x-, y+, y-, z+, z-), at most 4 hops
-  H.master.assign(n, -1);
+  H.master.resize(n);
   const int dir_order[6] = {1, 0, 3, 2, 5, 4};
   std::atomic<bool> master_bad{false};
   pool.run(n, [&](int qb, int qe) {
   for (int q = qb; q < qe; ++q) {
+    H.master[q] = -1;
     if (H.type[q] == TYPE_SOLID) continue;
     int cur = q, hops = 0, seen[5] = {q, -1, -1, -1, -1};
     bool ok = true;
@@ -372,7 +396,8 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
   for (int q = 0; q < n; ++q)
     if (H.master[q] >= 0 && H.master[H.master[q]] != H.master[q]) { err = "a master is not its own master"; return false; }
   if (!order_cvs(H, nullptr, err)) return false;
-  H.vcv.assign(n, 0.0);
+  H.vcv.resize(n);
+  pool.run(n, [&](int b, int e) { std::fill(H.vcv.begin() + b, H.vcv.begin() + e, 0.0); });
   for (size_t s = 0; s < H.cv.size(); ++s) {
     double v = 0.0;
     for (int e = H.cvptr[s]; e < H.cvptr[s + 1]; ++e) v += H.vbar[H.cvmem[e]];
@@ -387,7 +412,8 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
     H.n_members += nm - 1;
   }
   for (int q = 0; q < n; ++q) H.n_solid += H.type[q] == TYPE_SOLID;
-  H.type1.clear(); H.vbar1.clear(); H.vnew.clear(); H.rptr.clear(); H.rmem.clear();
+  H.type1.clear(); H.vbar1.clear(); H.flags1.clear(); H.S61.clear(); H.aw1.clear(); H.nw1.clear(); H.r1.clear();
+  H.vnew.clear(); H.rptr.clear(); H.rmem.clear();
   return true;
 }
 
@@ -403,8 +429,9 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
 bool plan_amr_move(const cc_config& cfg, const cc_body& body, double th1, AmrHost& H, std::string& err) {
   const int n = H.nleaf, D = cfg.amr_depth;
   const BodyDev B = body_at(body, th1);
-  H.type1.assign(n, 0); H.vbar1.assign(n, 0.0);
-  std::vector<double> S61(6 * (size_t)n);
+  H.type1.resize(n); H.vbar1.resize(n); H.flags1.resize(n); H.S61.resize(6 * (size_t)n);
+  H.aw1.resize(n); H.nw1.resize(3 * (size_t)n); H.r1.resize(3 * (size_t)n);
+  std::vector<double>& S61 = H.S61;
   std::atomic<bool> saddle{false}, coarse_cut{false};
   const FarCells far(H, D);
   HostPool::get().run(n, [&](int b, int e) {
@@ -416,7 +443,10 @@ bool plan_amr_move(const cc_config& cfg, const cc_body& body, double th1, AmrHos
       if (g.type == TYPE_CUT && H.lvl[q] < D) coarse_cut = true;
       H.type1[q] = g.type;
       H.vbar1[q] = g.vbar;
+      H.flags1[q] = g.flags;
+      H.aw1[q] = g.aw;
       for (int f = 0; f < 6; ++f) S61[6 * (size_t)q + f] = g.S[f];
+      for (int d = 0; d < 3; ++d) { H.nw1[3 * (size_t)q + d] = g.n[d]; H.r1[3 * (size_t)q + d] = g.r[d]; }
     }
   });
   if (saddle) { err = "a cell is cut twice by the boundary at the next time"; return false; }
