@@ -98,6 +98,15 @@ struct Geo3D {
   double* ghost;     // nvel farfield values (F)
 };
 
+// Scratch of the octree builder, kept with a mesh so that a rebuild into it
+// reuses the allocations.
+struct AmrBuildScratch {
+  std::vector<std::pair<uint64_t, int>> corder;     // coarse cells in Z-order
+  std::vector<std::vector<int>> part;               // leaves (depth, i, j, k) per chunk of coarse cells
+  std::vector<std::vector<int>> fnb, fdir;          // face entries per chunk of leaves
+  std::vector<std::vector<double>> farea;
+};
+
 // Octree mesh (3D): built on the host when the context is created
 // (octree3d.hip), uploaded to the geometry buffer when it is bound.  With a
 // turning body the host plans every step on the mesh of t^n, then rebuilds
@@ -125,6 +134,7 @@ struct AmrHost {
   std::vector<int> rptr, rmem;       // per control volume (cv order): leaves receiving its value
   // capacities of the device arrays (the largest mesh a turning body is expected to need)
   int cap_leaf = 0, cap_face = 0;
+  AmrBuildScratch scratch;
 };
 
 // State carried from the mesh of t^n to the mesh of t^{n+1}: new leaf q

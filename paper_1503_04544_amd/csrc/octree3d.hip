@@ -203,13 +203,19 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
   // Z-order: the leaves come out in the Z-order of their lower corners
   struct C4 { int l, i, j, k; };
   const int n0 = cfg.n[0] * cfg.n[1] * cfg.n[2];
-  std::vector<std::pair<uint64_t, int>> corder(n0);
-  for (int c0 = 0; c0 < n0; ++c0)
-    corder[c0] = {morton3(c0 % cfg.n[0], (c0 / cfg.n[0]) % cfg.n[1], c0 / (cfg.n[0] * cfg.n[1])), c0};
-  std::sort(corder.begin(), corder.end());
-  std::vector<std::vector<C4>> part((n0 + HostPool::kChunk - 1) / HostPool::kChunk);
+  AmrBuildScratch& X = H.scratch;
+  std::vector<std::pair<uint64_t, int>>& corder = X.corder;
+  if ((int)corder.size() != n0) {
+    corder.resize(n0);
+    for (int c0 = 0; c0 < n0; ++c0)
+      corder[c0] = {morton3(c0 % cfg.n[0], (c0 / cfg.n[0]) % cfg.n[1], c0 / (cfg.n[0] * cfg.n[1])), c0};
+    std::sort(corder.begin(), corder.end());
+  }
+  std::vector<std::vector<int>>& part = X.part;
+  part.resize((n0 + HostPool::kChunk - 1) / HostPool::kChunk);
   pool.run(n0, [&](int b, int e) {
-    std::vector<C4>& out = part[b / HostPool::kChunk];
+    std::vector<int>& out = part[b / HostPool::kChunk];
+    out.clear();
     std::vector<C4> stack;
     for (int z0 = b; z0 < e; ++z0) {
       const int c0 = corder[z0].second;
@@ -224,23 +230,23 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
           for (int t = 7; t >= 0; --t)
             stack.push_back({c.l + 1, 2 * c.i + (t & 1), 2 * c.j + ((t >> 1) & 1), 2 * c.k + ((t >> 2) & 1)});
         } else {
-          out.push_back(c);
+          out.push_back(c.l); out.push_back(c.i); out.push_back(c.j); out.push_back(c.k);
         }
       }
     }
   });
   std::vector<int> pstart(part.size() + 1, 0);
-  for (size_t c = 0; c < part.size(); ++c) pstart[c + 1] = pstart[c] + (int)part[c].size();
+  for (size_t c = 0; c < part.size(); ++c) pstart[c + 1] = pstart[c] + (int)part[c].size() / 4;
   const int n = pstart.back();
   H.nleaf = n;
   H.lvl.resize(n); H.ijk.resize(3 * (size_t)n); H.zkey.resize(n);
   pool.run((int)part.size(), [&](int b, int e) {
     for (int c = b; c < e; ++c)
-      for (size_t t = 0; t < part[c].size(); ++t) {
-        const C4& l = part[c][t];
-        const int q = pstart[c] + (int)t, sh = D - l.l;
-        H.lvl[q] = l.l; H.ijk[3 * q] = l.i; H.ijk[3 * q + 1] = l.j; H.ijk[3 * q + 2] = l.k;
-        H.zkey[q] = morton3((uint64_t)l.i << sh, (uint64_t)l.j << sh, (uint64_t)l.k << sh);
+      for (size_t t = 0; 4 * t < part[c].size(); ++t) {
+        const int* l = &part[c][4 * t];
+        const int q = pstart[c] + (int)t, sh = D - l[0];
+        H.lvl[q] = l[0]; H.ijk[3 * q] = l[1]; H.ijk[3 * q + 1] = l[2]; H.ijk[3 * q + 2] = l[3];
+        H.zkey[q] = morton3((uint64_t)l[1] << sh, (uint64_t)l[2] << sh, (uint64_t)l[3] << sh);
       }
   });
   // finest-level map: the leaf containing each finest cell
@@ -326,28 +332,31 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
   };
   // one pass into per-chunk lists (chunks are ranges of leaves), then
   // concatenated in leaf order
-  struct FaceChunk { std::vector<int> nb, dir; std::vector<double> area; };
-  std::vector<FaceChunk> fch((n + HostPool::kChunk - 1) / HostPool::kChunk);
+  const size_t nch = (n + HostPool::kChunk - 1) / HostPool::kChunk;
+  X.fnb.resize(nch); X.fdir.resize(nch); X.farea.resize(nch);
   H.fptr.resize(n + 1);
   H.fptr[0] = 0;
   pool.run(n, [&](int b, int e) {
-    FaceChunk& F = fch[b / HostPool::kChunk];
-    F.nb.reserve(7 * (size_t)(e - b)); F.dir.reserve(7 * (size_t)(e - b)); F.area.reserve(7 * (size_t)(e - b));
+    const int c = b / HostPool::kChunk;
+    std::vector<int>& Fnb = X.fnb[c];
+    std::vector<int>& Fdir = X.fdir[c];
+    std::vector<double>& Farea = X.farea[c];
+    Fnb.clear(); Fdir.clear(); Farea.clear();
     for (int q = b; q < e; ++q) {
-      const size_t before = F.nb.size();
-      faces_of(q, [&](int nb, int t, double A) { F.nb.push_back(nb); F.dir.push_back(t); F.area.push_back(A); });
-      H.fptr[q + 1] = (int)(F.nb.size() - before);
+      const size_t before = Fnb.size();
+      faces_of(q, [&](int nb, int t, double A) { Fnb.push_back(nb); Fdir.push_back(t); Farea.push_back(A); });
+      H.fptr[q + 1] = (int)(Fnb.size() - before);
     }
   });
   for (int q = 0; q < n; ++q) H.fptr[q + 1] += H.fptr[q];
   H.nface = H.fptr[n];
   H.fnb.resize(H.nface); H.fdir.resize(H.nface); H.farea.resize(H.nface);
-  pool.run((int)fch.size(), [&](int b, int e) {
+  pool.run((int)nch, [&](int b, int e) {
     for (int c = b; c < e; ++c) {
       const int at = H.fptr[c * HostPool::kChunk];
-      std::copy(fch[c].nb.begin(), fch[c].nb.end(), H.fnb.begin() + at);
-      std::copy(fch[c].dir.begin(), fch[c].dir.end(), H.fdir.begin() + at);
-      std::copy(fch[c].area.begin(), fch[c].area.end(), H.farea.begin() + at);
+      std::copy(X.fnb[c].begin(), X.fnb[c].end(), H.fnb.begin() + at);
+      std::copy(X.fdir[c].begin(), X.fdir[c].end(), H.fdir.begin() + at);
+      std::copy(X.farea[c].begin(), X.farea[c].end(), H.farea.begin() + at);
     }
   });
   if (jump) { err = "neighbouring leaves differ by more than one depth"; return false; }
