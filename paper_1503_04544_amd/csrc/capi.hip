@@ -506,15 +506,19 @@ cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scr
 // make the current state ready for a step: moments valid, control volumes merged
 static cc_status prepare(cc_ctx* ctx) {
   if (ctx->amr) {
+    // after a remap only the control volumes with several members (all
+    // among the last group) need the merge and new records
+    const int from = ctx->amr_leaf_records ? ctx->a3.nreg : 0;
     if (!ctx->merged) {
-      HIPCHK(ctx, launch_amr_merge(ctx), "merge");
+      HIPCHK(ctx, launch_amr_merge(ctx, from), "merge");
       ctx->merged = true;
       ctx->mom_valid = false;
     }
     if (!ctx->mom_valid) {
-      HIPCHK(ctx, launch_amr_moments(ctx), "moments");
+      HIPCHK(ctx, launch_amr_moments(ctx, from), "moments");
       ctx->mom_valid = true;
     }
+    ctx->amr_leaf_records = false;
     return CC_OK;
   }
   if (ctx->dim == 3) {
@@ -548,6 +552,7 @@ cc_status cc_init_maxwellian(cc_ctx* ctx) {
                        : (ctx->dim == 2 ? launch_init_maxwellian_2d(ctx) : launch_init_maxwellian_3d(ctx)), "init");
   ctx->mom_valid = false;
   ctx->merged = false;
+  ctx->amr_leaf_records = false;
   return prepare(ctx);
 }
 
@@ -559,6 +564,7 @@ cc_status cc_load_state(cc_ctx* ctx, const double* f, const double* g) {
                        : (ctx->dim == 2 ? launch_load_state_2d(ctx, f, g) : launch_load_state_3d(ctx, f)), "load");
   ctx->mom_valid = false;
   ctx->merged = false;
+  ctx->amr_leaf_records = false;
   return prepare(ctx);
 }
 
@@ -652,6 +658,7 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
   ctx->n_irr = N1->n_irr; ctx->n_members = N1->n_members; ctx->n_solid = N1->n_solid;
   ctx->merged = false;
   ctx->mom_valid = false;
+  ctx->amr_leaf_records = true;
   return CC_OK;
 }
 

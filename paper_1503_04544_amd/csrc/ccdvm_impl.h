@@ -225,6 +225,8 @@ struct cc_ctx {
   ccdvm::Geo3D g3;
   bool amr = false;                 // 3D octree mesh
   bool amr_turning = false;         // octree with a body turning about the z axis
+  bool amr_leaf_records = false;    // the remap wrote every leaf's record: only control
+                                    // volumes with several members need merge and moments
   ccdvm::AmrHost* amrh = nullptr;
   ccdvm::AmrHost* amr_spare = nullptr;   // turning body: the previous mesh, rebuilt into next step
   ccdvm::AmrDev a3{};
@@ -308,8 +310,10 @@ void build_amr_remap(const AmrHost& old_mesh, const AmrHost& new_mesh, int depth
 hipError_t launch_amr_remap(cc_ctx* ctx, const double* from, double* to);
 hipError_t launch_amr_tables(cc_ctx* ctx);
 hipError_t launch_amr_init(cc_ctx* ctx, const double* f);   // f null: farfield Maxwellian
-hipError_t launch_amr_merge(cc_ctx* ctx);
-hipError_t launch_amr_moments(cc_ctx* ctx);
+// from: first control volume (the others are single members whose
+// records are already valid)
+hipError_t launch_amr_merge(cc_ctx* ctx, int from = 0);
+hipError_t launch_amr_moments(cc_ctx* ctx, int from = 0);
 hipError_t launch_amr_step(cc_ctx* ctx, double* row);
 
 // profiling hooks (capi.cpp)

@@ -604,6 +604,7 @@ struct AmrArgs {
   int per_simple, per, per_irr;   // blocks per XCD of the three kinds of control volumes
   double vmin, dv, w, dt, tau_coef, t_wall;
   double om, cx, cy;              // turning body: angular velocity at t^n, axis (z) position
+  int w0;                         // first control volume of the moment pass
 };
 
 // record of the relaxation from the moment sums of one control volume
@@ -899,7 +900,7 @@ __global__ void __launch_bounds__(256) k_amr_simple(AmrArgs A) {
 template <int N>
 __global__ void __launch_bounds__(256) k_amr_mom(AmrArgs A) {
   constexpr int NV = N * N * N;
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int w = A.w0 + blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (w >= A.G.ncv) return;
   const int m = A.G.cv[w], b = A.G.cvptr[w], nm = A.G.cvptr[w + 1] - b;
@@ -918,8 +919,8 @@ __global__ void __launch_bounds__(256) k_amr_mom(AmrArgs A) {
 }
 
 // merge of the control volumes with several members: value = sum_k V_k F_k / V
-__global__ void __launch_bounds__(256) k_amr_merge(AmrDev G, double* __restrict__ st, int nvel) {
-  const int w = blockIdx.x;
+__global__ void __launch_bounds__(256) k_amr_merge(AmrDev G, double* __restrict__ st, int nvel, int w0) {
+  const int w = w0 + blockIdx.x;
   const int m = G.cv[w], b = G.cvptr[w], nm = G.cvptr[w + 1] - b;
   if (nm <= 1) return;
   for (int p = threadIdx.x; p < nvel; p += blockDim.x) {
@@ -972,24 +973,49 @@ __global__ void __launch_bounds__(1024) k_amr_reduce(const double* __restrict__ 
 // state carried to the next mesh: new leaf q takes
 // sum_e wgt[e] F[src[e]] / sum_e wgt[e] (0 with no entry); one block per
 // leaf, its threads over the velocities (the entries are uniform over the
-// block)
+// block).  The moment sums of the new value give the leaf's relaxation
+// record (that of its control volume when it is the only member; the
+// moment pass redoes the control volumes with several members after their
+// merge).
+template <int N>
 __global__ void __launch_bounds__(256) k_amr_remap(const int* __restrict__ sptr, const int* __restrict__ src,
-                                                  const double* __restrict__ wgt, int nvel,
-                                                  const double* __restrict__ from, double* __restrict__ to) {
+                                                  const double* __restrict__ wgt, const double* __restrict__ from,
+                                                  double* __restrict__ to, AmrArgs A) {
+  constexpr int NV = N * N * N;
+  __shared__ double lds[4][5];
   const int q = blockIdx.x;
   const int e0 = sptr[q], e1 = sptr[q + 1];
-  double* dst = to + (size_t)q * nvel;
-  if (e1 - e0 == 1 && wgt[e0] == 1.0) {   // the same leaf, or one containing it: a copy
-    const double* a = from + (size_t)src[e0] * nvel;
-    for (int p = threadIdx.x; p < nvel; p += blockDim.x) dst[p] = 0.0 + 1.0 * a[p];
-    return;
-  }
+  double* dst = to + (size_t)q * NV;
+  const bool copy = e1 - e0 == 1 && wgt[e0] == 1.0;   // the same leaf, or one containing it
   double W = 0.0;
   for (int e = e0; e < e1; ++e) W += wgt[e];
-  for (int p = threadIdx.x; p < nvel; p += blockDim.x) {
-    double acc = 0.0;
-    for (int e = e0; e < e1; ++e) acc += wgt[e] * from[(size_t)src[e] * nvel + p];
-    dst[p] = W > 0.0 ? acc / W : 0.0;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int p = threadIdx.x; p < NV; p += 256) {
+    double v;
+    if (copy) {
+      v = 0.0 + 1.0 * from[(size_t)src[e0] * NV + p];
+    } else {
+      double acc = 0.0;
+      for (int e = e0; e < e1; ++e) acc += wgt[e] * from[(size_t)src[e] * NV + p];
+      v = W > 0.0 ? acc / W : 0.0;
+    }
+    dst[p] = v;
+    const double vx = vnodeA(A.vmin, A.dv, p % N), vy = vnodeA(A.vmin, A.dv, (p / N) % N),
+                 vz = vnodeA(A.vmin, A.dv, p / (N * N));
+    s[0] += v; s[1] += vx * v; s[2] += vy * v; s[3] += vz * v;
+    s[4] += (vx * vx + vy * vy + vz * vz) * v;
+  }
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double t = wsum(s[k]);
+    if ((threadIdx.x & 63) == 0) lds[wave][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && W > 0.0) {
+    double t[5];
+    for (int k = 0; k < 5; ++k) t[k] = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
+    if (t[0] > 0.0) write_record(A.mom, &q, 1, t, A.w, A.dt, A.tau_coef);
   }
 }
 
@@ -1006,16 +1032,20 @@ AmrArgs amr_args(cc_ctx* ctx, const double* in, double* out) {
   A.t_wall = ctx->body.t_wall;
   A.om = ctx->body_state[5];
   A.cx = ctx->body.center[0]; A.cy = ctx->body.center[1];
+  A.w0 = 0;
   return A;
 }
 
 typedef void (*amr_fn)(AmrArgs);
 
-struct AmrFns { amr_fn simple, reg, irr, irr_mv, mom; };
+typedef void (*remap_fn)(const int*, const int*, const double*, const double*, double*, AmrArgs);
+
+struct AmrFns { amr_fn simple, reg, irr, irr_mv, mom; remap_fn remap; };
 
 template <int N>
 AmrFns amr_fns() {
-  return {k_amr_simple<N>, k_amr_step<N, false>, k_amr_step<N, true>, k_amr_step<N, true, true>, k_amr_mom<N>};
+  return {k_amr_simple<N>, k_amr_step<N, false>, k_amr_step<N, true>, k_amr_step<N, true, true>, k_amr_mom<N>,
+          k_amr_remap<N>};
 }
 
 bool pick_amr(int N, AmrFns* f) {
@@ -1045,19 +1075,22 @@ hipError_t launch_amr_init(cc_ctx* ctx, const double* f) {
   return hipGetLastError();
 }
 
-hipError_t launch_amr_merge(cc_ctx* ctx) {
-  if (ctx->a3.ncv == 0) return hipSuccess;
+hipError_t launch_amr_merge(cc_ctx* ctx, int from) {
+  if (ctx->a3.ncv <= from) return hipSuccess;
   prof_begin(ctx, 3);
-  k_amr_merge<<<ctx->a3.ncv, 256, 0, ctx->stream>>>(ctx->a3, (double*)ctx->state[ctx->cur], ctx->nvel);
+  k_amr_merge<<<ctx->a3.ncv - from, 256, 0, ctx->stream>>>(ctx->a3, (double*)ctx->state[ctx->cur], ctx->nvel, from);
   prof_end(ctx, 3);
   return hipGetLastError();
 }
 
-hipError_t launch_amr_moments(cc_ctx* ctx) {
+hipError_t launch_amr_moments(cc_ctx* ctx, int from) {
   AmrFns f;
   if (!pick_amr(ctx->N, &f)) return hipErrorNotSupported;
+  if (ctx->a3.ncv <= from) return hipSuccess;
   const double* cur = (const double*)ctx->state[ctx->cur];
-  f.mom<<<(ctx->a3.ncv + 3) / 4, 256, 0, ctx->stream>>>(amr_args(ctx, cur, nullptr));
+  AmrArgs A = amr_args(ctx, cur, nullptr);
+  A.w0 = from;
+  f.mom<<<(ctx->a3.ncv - from + 3) / 4, 256, 0, ctx->stream>>>(A);
   return hipGetLastError();
 }
 
@@ -1110,9 +1143,12 @@ hipError_t launch_amr_step(cc_ctx* ctx, double* row) {
 }
 
 hipError_t launch_amr_remap(cc_ctx* ctx, const double* from, double* to) {
+  AmrFns f;
+  if (!pick_amr(ctx->N, &f)) return hipErrorNotSupported;
   if (ctx->a3.nleaf == 0) return hipSuccess;
   prof_begin(ctx, 4);
-  k_amr_remap<<<ctx->a3.nleaf, 256, 0, ctx->stream>>>(ctx->a3.sptr, ctx->a3.src, ctx->a3.wgt, ctx->nvel, from, to);
+  f.remap<<<ctx->a3.nleaf, 256, 0, ctx->stream>>>(ctx->a3.sptr, ctx->a3.src, ctx->a3.wgt, from, to,
+                                                   amr_args(ctx, nullptr, nullptr));
   prof_end(ctx, 4);
   return hipGetLastError();
 }
