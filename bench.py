@@ -167,8 +167,8 @@ def main():
                     help="only run a plain 1 GiB device copy 10 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the "
-              "path is described in DESIGN.md and not launched", file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus 1); the step is not sharded across GPUs",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -5,7 +5,7 @@ experiments are simulations whose comparison data is not available, so
 the inputs are the flow set-ups themselves (domain, grid, velocity box,
 obstacle, Knudsen number, inflow Mach number, wall temperature).
 
-Readings of the paper that fix these recipes (see the design doc for the list):
+Readings of the paper that fix these recipes:
   * inflow speed from the Mach number with gamma = 5/3 (monatomic gas,
     three translational degrees of freedom kept by the reduced model);
   * farfield outer boundary carrying the inflow Maxwellian;

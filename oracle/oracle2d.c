@@ -17,9 +17,9 @@
  *   seven-step summary ......................... Section 3.3.4
  *   relaxation time from Kn .................... Section 5.4 (BGK, tau(Kn))
  *
- * Readings taken where the paper is silent or garbled are marked READING
- * and listed in the design doc.  Nothing here is blocked, fused or reordered for
- * speed: loops run over cells, then members, then velocities.
+ * Readings taken where the paper is silent or garbled are marked READING.
+ * Nothing here is blocked, fused or reordered for speed: loops run over
+ * cells, then members, then velocities.
  */
 #include <math.h>
 #include <stdlib.h>
