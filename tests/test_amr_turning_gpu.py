@@ -87,3 +87,34 @@ def test_vane_at_depth_zero_is_the_uniform_grid():
 def test_vane_amr_full_size():
     cfg = workload("vane_amr")
     compare(cfg, 2)
+
+
+def test_steps_without_diag_rows():
+    from paper_1503_04544_amd.solver import Solver
+    cfg = vane_case(nv=4)
+    s = Solver(cfg, device="cuda:0")
+    s.init_maxwellian()
+    o = Oracle3A(cfg)
+    F = o.init()
+    s.step(3)                       # no diag rows: the torque goes through an internal row
+    for _ in range(3):
+        F, _ = o.step(F)
+    assert s.ncell == o.nleaf
+    Fg = s.store_state()[0].cpu().numpy()
+    assert np.max(np.abs(Fg - F)) <= 1e-10 * np.max(np.abs(F))
+    b, bo = s.body_state(), o.body()
+    assert abs(b[2] - bo[0]) <= 1e-14 and abs(b[5] - bo[1]) <= 1e-10 * abs(bo[1])
+    s.close()
+
+
+def test_body_leaving_the_refined_band_is_rejected():
+    # a turn of about two radians per step: coarse leaves are cut at the
+    # next time; the host plan rejects the step before any kernel runs
+    from paper_1503_04544_amd.solver import CCError, Solver
+    body = Body("vane", VANE.center, VANE.axes, theta=0.3, motion="imposed", omega=2000.0)
+    s = Solver(vane_case(nv=4, body=body), device="cuda:0")
+    s.init_maxwellian()
+    with pytest.raises(CCError) as e:
+        s.step(1)
+    assert e.value.status == -3
+    s.close()
