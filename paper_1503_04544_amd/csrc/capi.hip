@@ -463,17 +463,19 @@ cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scr
   HIPCHK(ctx, hipMemsetAsync(state1, 0, ctx->state_bytes, ctx->stream), "state clear");
   HIPCHK(ctx, hipMemcpyAsync(ctx->s.body, ctx->body_state, 6 * sizeof(double),
                              hipMemcpyHostToDevice, ctx->stream), "body state upload");
+  // a second stream for the cut control volumes, run beside the streaming
+  // kernel (default priority, like the caller's stream)
+  if (!ctx->side) {
+    HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "side stream");
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming), "event");
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming), "event");
+  }
   if (ctx->amr) {
     const AmrHost& H = *ctx->amrh;
     AmrDev& G = ctx->a3;
     hipError_t e = upload_amr_mesh(ctx);
     if (e == hipSuccess) e = launch_amr_tables(ctx);
     if (e != hipSuccess) return hip_fail(ctx, e, "octree upload");
-    if (!ctx->side) {   // default priority, like the caller's stream
-      HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "side stream");
-      HIPCHK(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming), "event");
-      HIPCHK(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming), "event");
-    }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "octree upload");
     // the generic 3D moment and mass kernels see the leaves through g3
     ctx->g3 = Geo3D{};

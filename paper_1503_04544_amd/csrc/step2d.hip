@@ -1716,7 +1716,17 @@ hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_forc
     k_newton2d<<<(ctx->ncell + 255) / 256, 256, 0, ctx->stream>>>(ctx->g2, ctx->s.mom, P.vmin, P.dv);
     prof_end(ctx, 4);
   }
-  if (A.n_cut > 0) {
+  // the cut control volumes (disjoint cells, their own partial slots) run on
+  // a side stream beside the streaming kernel; serial while profiling
+  const bool overlap = A.n_cut > 0 && ctx->side && !ctx->prof.on;
+  if (overlap) {
+    hipError_t e = hipEventRecord(ctx->fork, ctx->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->fork, 0);
+    if (e != hipSuccess) return e;
+    k_cutstep2d<<<A.n_cut, 256, 0, ctx->side>>>(ctx->g2, A, P);
+    e = hipEventRecord(ctx->join, ctx->side);
+    if (e != hipSuccess) return e;
+  } else if (A.n_cut > 0) {
     prof_begin(ctx, 1);
     k_cutstep2d<<<A.n_cut, 256, 0, ctx->stream>>>(ctx->g2, A, P);
     prof_end(ctx, 1);
@@ -1724,6 +1734,10 @@ hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_forc
   prof_begin(ctx, 0);
   fn(ctx, grid, A, P);
   prof_end(ctx, 0);
+  if (overlap) {
+    hipError_t e = hipStreamWaitEvent(ctx->stream, ctx->join, 0);
+    if (e != hipSuccess) return e;
+  }
   ctx->last_args_ntiles = A.ntiles;
   ctx->cur = 1 - ctx->cur;
   ctx->step_parity = 1 - par;

@@ -1212,6 +1212,22 @@ hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
   A.dv = ctx->dv;
   A.cxf = ctx->dt / ctx->dx; A.cyf = ctx->dt / ctx->dy; A.czf = ctx->dt / ctx->dz;
   A.relax = imex ? 0 : 1;
+  // the cut control volumes and the force/mass reduction (disjoint cells,
+  // their own slots) run on a side stream beside the streaming kernel;
+  // serial while profiling
+  const bool overlap = ctx->side && !ctx->prof.on;
+  if (overlap) {
+    e = hipEventRecord(ctx->fork, ctx->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->fork, 0);
+    if (e != hipSuccess) return e;
+    hipStream_t main = ctx->stream;
+    ctx->stream = ctx->side;
+    e = cut_and_reduce(ctx, in, out, 1, row, imex ? 0 : 1);
+    ctx->stream = main;
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ctx->join, ctx->side);
+    if (e != hipSuccess) return e;
+  }
   prof_begin(ctx, 0);
   for (int l = 0; l < nlaunch; ++l) {
     A.ch0 = l;
@@ -1220,7 +1236,11 @@ hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
   prof_end(ctx, 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = cut_and_reduce(ctx, in, out, 1, row, imex ? 0 : 1);
+  if (overlap) {
+    e = hipStreamWaitEvent(ctx->stream, ctx->join, 0);
+  } else {
+    e = cut_and_reduce(ctx, in, out, 1, row, imex ? 0 : 1);
+  }
   if (e != hipSuccess) return e;
   if (imex) {
     // semi-implicit step (ImpSchemeDD): equilibrium of the transported
