@@ -52,7 +52,8 @@ typedef struct cc_ctx cc_ctx;
 typedef enum {
   CC_OK = 0,
   CC_EINVAL = -1,     /* bad argument or unsupported size */
-  CC_ENOMEM = -2,     /* host allocation failed or a workspace is too small */
+  CC_ENOMEM = -2,     /* host allocation failed (no entry point lets an
+                         exception out) or a workspace is too small */
   CC_EGEOM = -3,      /* geometry rejected: a cell cut twice by the boundary,
                          a master search that cycles or needs more than 4 hops */
   CC_ECFL = -4,       /* positivity condition (eq-CFL) violated in strict mode */

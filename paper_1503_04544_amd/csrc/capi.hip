@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <future>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -204,9 +205,58 @@ void prof_end(cc_ctx* ctx, int k) {
 
 }  // namespace ccdvm
 
-extern "C" {
+// Exceptions do not cross the C interface: a host allocation that fails,
+// or a host thread that cannot start, ends the call with CC_ENOMEM and the
+// reason in the object's last error (when there is an object to hold it).
+template <class F>
+cc_status no_throw(std::string* err, F&& f) noexcept {
+  const char* why = "unexpected host error";
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    why = "host allocation failed";
+  } catch (const std::exception& e) {
+    if (err) {
+      try { *err = std::string("host error: ") + e.what(); } catch (...) {}
+    }
+    return CC_ENOMEM;
+  } catch (...) {
+  }
+  if (err) {
+    try { *err = why; } catch (...) {}
+  }
+  return CC_ENOMEM;
+}
 
-cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
+namespace {
+
+
+// The octree of the initial angle; for a turning body also the capacities
+// of the device arrays: the largest mesh over a half turn (16 angles; the
+// vane and the sphere map onto themselves after half a turn), plus a margin.
+cc_status build_first_mesh(const cc_config& c, const cc_body& body, bool turning, AmrHost& H) {
+  std::string err;
+  if (!build_octree_3d(c, body, body.theta, H, err)) {
+    fprintf(stderr, "ccdvm: %s\n", err.c_str());
+    return CC_EGEOM;
+  }
+  if (!turning) return CC_OK;
+  int ml = H.nleaf, mf = H.nface;
+  for (int k = 1; k < 16; ++k) {
+    AmrHost T;
+    if (!build_octree_3d(c, body, body.theta + k * M_PI / 16.0, T, err)) {
+      fprintf(stderr, "ccdvm: %s (at a later angle)\n", err.c_str());
+      return CC_EGEOM;
+    }
+    ml = std::max(ml, T.nleaf);
+    mf = std::max(mf, T.nface);
+  }
+  H.cap_leaf = ml + ml / 4 + 64;
+  H.cap_face = mf + mf / 4 + 256;
+  return CC_OK;
+}
+
+cc_status create_impl(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   if (!cfg || !body || !out) return CC_EINVAL;
   *out = nullptr;
   cc_ctx* ctx = new (std::nothrow) cc_ctx();
@@ -214,8 +264,8 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   ctx->cfg = *cfg;
   ctx->body = *body;
   const cc_config& c = *cfg;
-  auto reject = [&](const std::string& msg) {
-    fprintf(stderr, "ccdvm: %s\n", msg.c_str());
+  auto reject = [&](const char* msg) {
+    fprintf(stderr, "ccdvm: %s\n", msg);
     delete ctx;
     return CC_EINVAL;
   };
@@ -292,30 +342,12 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
     ctx->amr_turning = turning3;
     ctx->amrh = new (std::nothrow) AmrHost();
     if (!ctx->amrh) { delete ctx; return CC_ENOMEM; }
-    std::string err;
-    if (!build_octree_3d(c, *body, body->theta, *ctx->amrh, err)) {
-      fprintf(stderr, "ccdvm: %s\n", err.c_str());
+    const cc_status st = no_throw(nullptr, [&] { return build_first_mesh(c, *body, turning3, *ctx->amrh); });
+    if (st != CC_OK) {
+      if (st == CC_ENOMEM) fprintf(stderr, "ccdvm: host allocation failed while building the octree\n");
       delete ctx->amrh;
       delete ctx;
-      return CC_EGEOM;
-    }
-    if (turning3) {
-      // buffers for the largest mesh over a half turn (16 angles; the vane
-      // and the sphere map onto themselves after half a turn), plus a margin
-      int ml = ctx->amrh->nleaf, mf = ctx->amrh->nface;
-      for (int k = 1; k < 16; ++k) {
-        AmrHost T;
-        if (!build_octree_3d(c, *body, body->theta + k * M_PI / 16.0, T, err)) {
-          fprintf(stderr, "ccdvm: %s (at a later angle)\n", err.c_str());
-          delete ctx->amrh;
-          delete ctx;
-          return CC_EGEOM;
-        }
-        ml = std::max(ml, T.nleaf);
-        mf = std::max(mf, T.nface);
-      }
-      ctx->amrh->cap_leaf = ml + ml / 4 + 64;
-      ctx->amrh->cap_face = mf + mf / 4 + 256;
+      return st;
     }
     // the leaves are the cells; the finest spacing sets dt
     ctx->ncell = ctx->amrh->nleaf;
@@ -346,24 +378,8 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   return CC_OK;
 }
 
-void cc_destroy(cc_ctx* ctx) {
-  if (!ctx) return;
-  for (int k = 0; k < kProfKernels; ++k) {
-    for (hipEvent_t e : ctx->prof.start[k]) hipEventDestroy(e);
-    for (hipEvent_t e : ctx->prof.stop[k]) hipEventDestroy(e);
-  }
-  if (ctx->fork) hipEventDestroy(ctx->fork);
-  if (ctx->join) hipEventDestroy(ctx->join);
-  if (ctx->side) hipStreamDestroy(ctx->side);
-  delete ctx->amrh;
-  delete ctx->amr_spare;
-  delete ctx;
-}
-
-const char* cc_last_error(const cc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
-
-cc_status cc_workspace_bytes(const cc_ctx* ctx, size_t* state_bytes, size_t* geom_bytes,
-                             size_t* scratch_bytes) {
+cc_status workspace_bytes_impl(const cc_ctx* ctx, size_t* state_bytes, size_t* geom_bytes,
+                               size_t* scratch_bytes) {
   if (!ctx) return CC_EINVAL;
   if (state_bytes) *state_bytes = ctx->state_bytes;
   if (geom_bytes) *geom_bytes = ctx->geom_bytes;
@@ -371,7 +387,7 @@ cc_status cc_workspace_bytes(const cc_ctx* ctx, size_t* state_bytes, size_t* geo
   return CC_OK;
 }
 
-cc_status cc_dt(const cc_ctx* ctx, double* dt) {
+cc_status dt_impl(const cc_ctx* ctx, double* dt) {
   if (!ctx || !dt) return CC_EINVAL;
   *dt = ctx->dt;
   return CC_OK;
@@ -439,8 +455,8 @@ static cc_status read_geometry_status(cc_ctx* ctx) {
   return CC_OK;
 }
 
-cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scratch,
-                  void* hip_stream) {
+cc_status bind_impl(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scratch,
+                    void* hip_stream) {
   if (!ctx) return CC_EINVAL;
   if (!state0 || !state1 || !geom || !scratch) return fail(ctx, CC_EINVAL, "null buffer");
   for (void* p : {state0, state1, geom, scratch})
@@ -547,7 +563,7 @@ static cc_status prepare(cc_ctx* ctx) {
   return CC_OK;
 }
 
-cc_status cc_init_maxwellian(cc_ctx* ctx) {
+cc_status init_maxwellian_impl(cc_ctx* ctx) {
   if (!ctx) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   HIPCHK(ctx, ctx->amr ? launch_amr_init(ctx, nullptr)
@@ -558,7 +574,7 @@ cc_status cc_init_maxwellian(cc_ctx* ctx) {
   return prepare(ctx);
 }
 
-cc_status cc_load_state(cc_ctx* ctx, const double* f, const double* g) {
+cc_status load_state_impl(cc_ctx* ctx, const double* f, const double* g) {
   if (!ctx || !f) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   if (ctx->dim == 2 && !g) return fail(ctx, CC_EINVAL, "g is required in 2D");
@@ -570,7 +586,7 @@ cc_status cc_load_state(cc_ctx* ctx, const double* f, const double* g) {
   return prepare(ctx);
 }
 
-cc_status cc_store_state(const cc_ctx* ctx, double* f, double* g) {
+cc_status store_state_impl(const cc_ctx* ctx, double* f, double* g) {
   if (!ctx || !f) return CC_EINVAL;
   if (!ctx->bound) return CC_ESTATE;
   hipError_t e = ctx->dim == 2 ? launch_store_state_2d(ctx, f, g) : launch_store_state_3d(ctx, f);
@@ -664,7 +680,7 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
   return CC_OK;
 }
 
-cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
+cc_status step_impl(cc_ctx* ctx, int nsteps, double* diag) {
   if (!ctx || nsteps < 0) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   cc_status st = prepare(ctx);
@@ -745,20 +761,20 @@ cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
   return CC_OK;
 }
 
-cc_status cc_set_tile_rows(cc_ctx* ctx, int rows) {
+cc_status set_tile_rows_impl(cc_ctx* ctx, int rows) {
   if (!ctx || rows < 0) return CC_EINVAL;
   ctx->seglen = rows;
   return CC_OK;
 }
 
-cc_status cc_moments(cc_ctx* ctx, double* out) {
+cc_status moments_impl(cc_ctx* ctx, double* out) {
   if (!ctx || !out) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   HIPCHK(ctx, ctx->dim == 2 ? launch_moments_out_2d(ctx, out) : launch_moments_out_3d(ctx, out), "moments");
   return CC_OK;
 }
 
-cc_status cc_body_force(cc_ctx* ctx, double out[4]) {
+cc_status body_force_impl(cc_ctx* ctx, double out[4]) {
   if (!ctx || !out) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   if (ctx->amr) return fail(ctx, CC_EINVAL, "on the octree mesh the force comes with the diag rows of cc_step");
@@ -771,7 +787,7 @@ cc_status cc_body_force(cc_ctx* ctx, double out[4]) {
   return CC_OK;
 }
 
-cc_status cc_body_state(cc_ctx* ctx, double out[6]) {
+cc_status body_state_impl(cc_ctx* ctx, double out[6]) {
   if (!ctx || !out) return CC_EINVAL;
   if (!ctx->bound || ctx->amr_turning) {   // a turning body is advanced on the host
     memcpy(out, ctx->body_state, 6 * sizeof(double));
@@ -784,7 +800,7 @@ cc_status cc_body_state(cc_ctx* ctx, double out[6]) {
   return CC_OK;
 }
 
-cc_status cc_rigid_update(cc_ctx* ctx, const double force[3], double torque) {
+cc_status rigid_update_impl(cc_ctx* ctx, const double force[3], double torque) {
   if (!ctx || !force) return CC_EINVAL;
   double s[6];
   cc_status st = cc_body_state(ctx, s);
@@ -804,9 +820,9 @@ cc_status cc_rigid_update(cc_ctx* ctx, const double force[3], double torque) {
   return CC_OK;
 }
 
-cc_status cc_geometry_export(cc_ctx* ctx, int* type, int* master, double* lxm, double* lxp,
-                             double* lym, double* lyp, double* lw, double* nwx, double* nwy,
-                             double* rwx, double* rwy, double* sbar, double* scv) {
+cc_status geometry_export_impl(cc_ctx* ctx, int* type, int* master, double* lxm, double* lxp,
+                               double* lym, double* lyp, double* lw, double* nwx, double* nwy,
+                               double* rwx, double* rwy, double* sbar, double* scv) {
   if (!ctx) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   if (ctx->dim != 2) return fail(ctx, CC_EINVAL, "2D only");
@@ -822,10 +838,10 @@ cc_status cc_geometry_export(cc_ctx* ctx, int* type, int* master, double* lxm, d
   return CC_OK;
 }
 
-cc_status cc_geometry_export3d(cc_ctx* ctx, int* type, int* master, double* sxm, double* sxp,
-                               double* sym, double* syp, double* szm, double* szp, double* aw,
-                               double* nwx, double* nwy, double* nwz, double* rwx, double* rwy,
-                               double* rwz, double* vbar, double* vcv) {
+cc_status geometry_export3d_impl(cc_ctx* ctx, int* type, int* master, double* sxm, double* sxp,
+                                 double* sym, double* syp, double* szm, double* szp, double* aw,
+                                 double* nwx, double* nwy, double* nwz, double* rwx, double* rwy,
+                                 double* rwz, double* vbar, double* vcv) {
   if (!ctx) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   if (ctx->dim != 3 || ctx->amr) return fail(ctx, CC_EINVAL, "uniform 3D grids only (octree: cc_amr_export)");
@@ -842,7 +858,7 @@ cc_status cc_geometry_export3d(cc_ctx* ctx, int* type, int* master, double* sxm,
   return CC_OK;
 }
 
-cc_status cc_amr_counts(cc_ctx* ctx, int* nleaf, int* nface) {
+cc_status amr_counts_impl(cc_ctx* ctx, int* nleaf, int* nface) {
   if (!ctx) return CC_EINVAL;
   if (!ctx->amr) return fail(ctx, CC_EINVAL, "not an octree mesh");
   if (nleaf) *nleaf = ctx->amrh->nleaf;
@@ -850,8 +866,8 @@ cc_status cc_amr_counts(cc_ctx* ctx, int* nleaf, int* nface) {
   return CC_OK;
 }
 
-cc_status cc_amr_export(cc_ctx* ctx, int* lvl, int* ijk, int* type, int* master, double* vbar, double* vcv,
-                        double* aw, double* S6) {
+cc_status amr_export_impl(cc_ctx* ctx, int* lvl, int* ijk, int* type, int* master, double* vbar, double* vcv,
+                          double* aw, double* S6) {
   if (!ctx) return CC_EINVAL;
   if (!ctx->amr) return fail(ctx, CC_EINVAL, "not an octree mesh");
   const AmrHost& H = *ctx->amrh;
@@ -867,7 +883,7 @@ cc_status cc_amr_export(cc_ctx* ctx, int* lvl, int* ijk, int* type, int* master,
   return CC_OK;
 }
 
-cc_status cc_amr_faces(cc_ctx* ctx, int* fptr, int* fnb, int* fdir, double* farea) {
+cc_status amr_faces_impl(cc_ctx* ctx, int* fptr, int* fnb, int* fdir, double* farea) {
   if (!ctx) return CC_EINVAL;
   if (!ctx->amr) return fail(ctx, CC_EINVAL, "not an octree mesh");
   const AmrHost& H = *ctx->amrh;
@@ -878,7 +894,7 @@ cc_status cc_amr_faces(cc_ctx* ctx, int* fptr, int* fnb, int* fdir, double* fare
   return CC_OK;
 }
 
-cc_status cc_geometry_counts(cc_ctx* ctx, int* n_irregular, int* n_members, int* n_solid) {
+cc_status geometry_counts_impl(cc_ctx* ctx, int* n_irregular, int* n_members, int* n_solid) {
   if (!ctx) return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
   if (n_irregular) *n_irregular = ctx->n_irr;
@@ -887,7 +903,7 @@ cc_status cc_geometry_counts(cc_ctx* ctx, int* n_irregular, int* n_members, int*
   return CC_OK;
 }
 
-cc_status cc_profile_enable(cc_ctx* ctx, int on) {
+cc_status profile_enable_impl(cc_ctx* ctx, int on) {
   if (!ctx) return CC_EINVAL;
   Prof& P = ctx->prof;
   if (on && P.start[0].empty()) {
@@ -906,7 +922,7 @@ cc_status cc_profile_enable(cc_ctx* ctx, int on) {
   return CC_OK;
 }
 
-cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launches) {
+cc_status profile_read_impl(cc_ctx* ctx, int kernel, double* total_ms, int* launches) {
   if (!ctx || kernel < 0 || kernel >= kProfKernels + 3) return CC_EINVAL;
   Prof& P = ctx->prof;
   if (kernel >= kProfKernels) {   // host time of a turning body's step
@@ -932,14 +948,14 @@ cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launch
 // ---------------------------------------------------------------------
 static const double kGamma = 5.0 / 3.0;
 
-cc_status cc_adjoint_workspace_bytes(const cc_ctx* ctx, int nsteps, int ckpt_every, size_t* bytes) {
+cc_status adjoint_workspace_bytes_impl(const cc_ctx* ctx, int nsteps, int ckpt_every, size_t* bytes) {
   if (!ctx || !bytes || nsteps < 1 || ckpt_every < 1) return CC_EINVAL;
   if (ctx->dim != 2 || is_moving(ctx)) return CC_EINVAL;
   *bytes = adjoint_workspace_bytes(ctx, nsteps, ckpt_every);
   return CC_OK;
 }
 
-cc_status cc_adjoint(cc_ctx* ctx, int nsteps, int ckpt_every, int objective, void* pool, double out[4]) {
+cc_status adjoint_impl(cc_ctx* ctx, int nsteps, int ckpt_every, int objective, void* pool, double out[4]) {
   if (!ctx || !out || !pool || nsteps < 1 || ckpt_every < 1 || (objective != 0 && objective != 1))
     return CC_EINVAL;
   if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
@@ -1025,10 +1041,12 @@ static cc_status batch_upload_and_capture(cc_batch* b) {
   return CC_OK;
 }
 
-cc_status cc_batch_create(cc_ctx* const* ctxs, int n, cc_batch** out) {
+cc_status batch_create_impl(cc_ctx* const* ctxs, int n, cc_batch** out) {
   if (!ctxs || n < 1 || !out) return CC_EINVAL;
   *out = nullptr;
-  cc_batch* b = new (std::nothrow) cc_batch();
+  // held until it is handed out, so that an exception does not leak it
+  std::unique_ptr<cc_batch> hold(new (std::nothrow) cc_batch());
+  cc_batch* b = hold.get();
   if (!b) return CC_ENOMEM;
   for (int i = 0; i < n; ++i) {
     cc_ctx* c = ctxs[i];
@@ -1040,7 +1058,6 @@ cc_status cc_batch_create(cc_ctx* const* ctxs, int n, cc_batch** out) {
     if (!ok) {
       fprintf(stderr, "ccdvm: batch instance %d must be a distinct bound 2D fixed-body context "
                       "(explicit, direct equilibrium) on the stream of instance 0\n", i);
-      delete b;
       return CC_EINVAL;
     }
     b->ctx.push_back(c);
@@ -1058,17 +1075,17 @@ cc_status cc_batch_create(cc_ctx* const* ctxs, int n, cc_batch** out) {
   }
   size_t desc = align_up(n * batch_desc_bytes());
   b->dev_bytes = 2 * desc + align_up(b->tile_cap * sizeof(int2)) + align_up((b->cut_cap + 1) * sizeof(int2));
-  *out = b;
+  *out = hold.release();
   return CC_OK;
 }
 
-cc_status cc_batch_workspace_bytes(const cc_batch* b, size_t* bytes) {
+cc_status batch_workspace_bytes_impl(const cc_batch* b, size_t* bytes) {
   if (!b || !bytes) return CC_EINVAL;
   *bytes = b->dev_bytes;
   return CC_OK;
 }
 
-cc_status cc_batch_bind(cc_batch* b, void* workspace) {
+cc_status batch_bind_impl(cc_batch* b, void* workspace) {
   if (!b || !workspace) return CC_EINVAL;
   if ((uintptr_t)workspace % kAlign) return batch_fail(b, CC_EINVAL, "workspace must be 256-byte aligned");
   b->dev = (char*)workspace;
@@ -1087,7 +1104,7 @@ cc_status cc_batch_bind(cc_batch* b, void* workspace) {
   return CC_OK;
 }
 
-cc_status cc_batch_autotune(cc_batch* b, int trial_steps, int* rows_out) {
+cc_status batch_autotune_impl(cc_batch* b, int trial_steps, int* rows_out) {
   if (!b || trial_steps < 1) return CC_EINVAL;
   if (!b->bound) return batch_fail(b, CC_ESTATE, "cc_batch_bind first");
   hipEvent_t e0, e1;
@@ -1124,7 +1141,7 @@ cc_status cc_batch_autotune(cc_batch* b, int trial_steps, int* rows_out) {
   return batch_upload_and_capture(b);
 }
 
-cc_status cc_batch_groups(const cc_batch* b, int* ngroups, int* chunks, int* rows) {
+cc_status batch_groups_impl(const cc_batch* b, int* ngroups, int* chunks, int* rows) {
   if (!b || !ngroups) return CC_EINVAL;
   *ngroups = (int)b->group_nch.size();
   for (size_t g = 0; g < b->group_nch.size(); ++g) {
@@ -1134,7 +1151,7 @@ cc_status cc_batch_groups(const cc_batch* b, int* ngroups, int* chunks, int* row
   return CC_OK;
 }
 
-cc_status cc_batch_step(cc_batch* b, int nsteps) {
+cc_status batch_step_impl(cc_batch* b, int nsteps) {
   if (!b || nsteps < 0) return CC_EINVAL;
   if (!b->bound) return batch_fail(b, CC_ESTATE, "cc_batch_bind first");
   bool stale = false;
@@ -1159,6 +1176,159 @@ cc_status cc_batch_step(cc_batch* b, int nsteps) {
   }
   return CC_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+cc_status cc_create(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
+  return no_throw(nullptr, [&] { return create_impl(cfg, body, out); });
+}
+
+cc_status cc_workspace_bytes(const cc_ctx* ctx, size_t* state_bytes, size_t* geom_bytes,
+                             size_t* scratch_bytes) {
+  return no_throw(nullptr, [&] { return workspace_bytes_impl(ctx, state_bytes, geom_bytes, scratch_bytes); });
+}
+
+cc_status cc_dt(const cc_ctx* ctx, double* dt) {
+  return no_throw(nullptr, [&] { return dt_impl(ctx, dt); });
+}
+
+cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scratch, void* hip_stream) {
+  return no_throw(ctx ? &ctx->err : nullptr,
+                  [&] { return bind_impl(ctx, state0, state1, geom, scratch, hip_stream); });
+}
+
+cc_status cc_init_maxwellian(cc_ctx* ctx) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] { return init_maxwellian_impl(ctx); });
+}
+
+cc_status cc_load_state(cc_ctx* ctx, const double* f, const double* g) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] { return load_state_impl(ctx, f, g); });
+}
+
+cc_status cc_store_state(const cc_ctx* ctx, double* f, double* g) {
+  return no_throw(nullptr, [&] { return store_state_impl(ctx, f, g); });
+}
+
+cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] { return step_impl(ctx, nsteps, diag); });
+}
+
+cc_status cc_set_tile_rows(cc_ctx* ctx, int rows) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] { return set_tile_rows_impl(ctx, rows); });
+}
+
+cc_status cc_moments(cc_ctx* ctx, double* out) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] { return moments_impl(ctx, out); });
+}
+
+cc_status cc_body_force(cc_ctx* ctx, double out[4]) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] { return body_force_impl(ctx, out); });
+}
+
+cc_status cc_body_state(cc_ctx* ctx, double out[6]) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] { return body_state_impl(ctx, out); });
+}
+
+cc_status cc_rigid_update(cc_ctx* ctx, const double force[3], double torque) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] { return rigid_update_impl(ctx, force, torque); });
+}
+
+cc_status cc_geometry_export(cc_ctx* ctx, int* type, int* master, double* lxm, double* lxp, double* lym,
+                             double* lyp, double* lw, double* nwx, double* nwy, double* rwx, double* rwy,
+                             double* sbar, double* scv) {
+  return no_throw(ctx ? &ctx->err : nullptr,
+                  [&] { return geometry_export_impl(ctx, type, master, lxm, lxp, lym, lyp, lw, nwx, nwy, rwx,
+                                                    rwy, sbar, scv); });
+}
+
+cc_status cc_geometry_export3d(cc_ctx* ctx, int* type, int* master, double* sxm, double* sxp, double* sym,
+                               double* syp, double* szm, double* szp, double* aw, double* nwx, double* nwy,
+                               double* nwz, double* rwx, double* rwy, double* rwz, double* vbar,
+                               double* vcv) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] {
+    return geometry_export3d_impl(ctx, type, master, sxm, sxp, sym, syp, szm, szp, aw, nwx, nwy, nwz, rwx,
+                                  rwy, rwz, vbar, vcv);
+  });
+}
+
+cc_status cc_amr_counts(cc_ctx* ctx, int* nleaf, int* nface) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] { return amr_counts_impl(ctx, nleaf, nface); });
+}
+
+cc_status cc_amr_export(cc_ctx* ctx, int* lvl, int* ijk, int* type, int* master, double* vbar, double* vcv,
+                        double* aw, double* S6) {
+  return no_throw(ctx ? &ctx->err : nullptr,
+                  [&] { return amr_export_impl(ctx, lvl, ijk, type, master, vbar, vcv, aw, S6); });
+}
+
+cc_status cc_amr_faces(cc_ctx* ctx, int* fptr, int* fnb, int* fdir, double* farea) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] { return amr_faces_impl(ctx, fptr, fnb, fdir, farea); });
+}
+
+cc_status cc_geometry_counts(cc_ctx* ctx, int* n_irregular, int* n_members, int* n_solid) {
+  return no_throw(ctx ? &ctx->err : nullptr,
+                  [&] { return geometry_counts_impl(ctx, n_irregular, n_members, n_solid); });
+}
+
+cc_status cc_profile_enable(cc_ctx* ctx, int on) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] { return profile_enable_impl(ctx, on); });
+}
+
+cc_status cc_profile_read(cc_ctx* ctx, int kernel, double* total_ms, int* launches) {
+  return no_throw(ctx ? &ctx->err : nullptr,
+                  [&] { return profile_read_impl(ctx, kernel, total_ms, launches); });
+}
+
+cc_status cc_adjoint_workspace_bytes(const cc_ctx* ctx, int nsteps, int ckpt_every, size_t* bytes) {
+  return no_throw(nullptr, [&] { return adjoint_workspace_bytes_impl(ctx, nsteps, ckpt_every, bytes); });
+}
+
+cc_status cc_adjoint(cc_ctx* ctx, int nsteps, int ckpt_every, int objective, void* pool, double out[4]) {
+  return no_throw(ctx ? &ctx->err : nullptr,
+                  [&] { return adjoint_impl(ctx, nsteps, ckpt_every, objective, pool, out); });
+}
+
+cc_status cc_batch_create(cc_ctx* const* ctxs, int n, cc_batch** out) {
+  return no_throw(nullptr, [&] { return batch_create_impl(ctxs, n, out); });
+}
+
+cc_status cc_batch_workspace_bytes(const cc_batch* b, size_t* bytes) {
+  return no_throw(nullptr, [&] { return batch_workspace_bytes_impl(b, bytes); });
+}
+
+cc_status cc_batch_bind(cc_batch* b, void* workspace) {
+  return no_throw(b ? &b->err : nullptr, [&] { return batch_bind_impl(b, workspace); });
+}
+
+cc_status cc_batch_autotune(cc_batch* b, int trial_steps, int* rows_out) {
+  return no_throw(b ? &b->err : nullptr, [&] { return batch_autotune_impl(b, trial_steps, rows_out); });
+}
+
+cc_status cc_batch_groups(const cc_batch* b, int* ngroups, int* chunks, int* rows) {
+  return no_throw(nullptr, [&] { return batch_groups_impl(b, ngroups, chunks, rows); });
+}
+
+cc_status cc_batch_step(cc_batch* b, int nsteps) {
+  return no_throw(b ? &b->err : nullptr, [&] { return batch_step_impl(b, nsteps); });
+}
+
+void cc_destroy(cc_ctx* ctx) {
+  if (!ctx) return;
+  for (int k = 0; k < kProfKernels; ++k) {
+    for (hipEvent_t e : ctx->prof.start[k]) hipEventDestroy(e);
+    for (hipEvent_t e : ctx->prof.stop[k]) hipEventDestroy(e);
+  }
+  if (ctx->fork) hipEventDestroy(ctx->fork);
+  if (ctx->join) hipEventDestroy(ctx->join);
+  if (ctx->side) hipStreamDestroy(ctx->side);
+  delete ctx->amrh;
+  delete ctx->amr_spare;
+  delete ctx;
+}
+
+const char* cc_last_error(const cc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 const char* cc_batch_last_error(const cc_batch* b) { return b ? b->err.c_str() : "null batch"; }
 
