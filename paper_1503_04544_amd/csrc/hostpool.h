@@ -5,11 +5,14 @@
 // calling thread is participant 0), and returns when every participant is
 // done.  Every worker takes part in every call, so a call cannot start
 // before all workers have finished the previous one; calls from several
-// threads are serialised.
+// threads are serialised.  An exception thrown by fn on any participant
+// (the first one caught) is rethrown by run on the calling thread once
+// every participant is done.
 #pragma once
 
 #include <algorithm>
 #include <condition_variable>
+#include <exception>
 #include <functional>
 #include <mutex>
 #include <thread>
@@ -35,6 +38,7 @@ class HostPool {
     {
       std::lock_guard<std::mutex> lk(m_);
       fn_ = &fn; n_ = n; pending_ = nw_;
+      error_ = nullptr;
       ++gen_;
     }
     cv_.notify_all();
@@ -42,18 +46,39 @@ class HostPool {
     std::unique_lock<std::mutex> lk(m_);
     fin_.wait(lk, [&] { return pending_ == 0; });
     fn_ = nullptr;
+    if (error_) {
+      std::exception_ptr e = error_;
+      error_ = nullptr;
+      std::rethrow_exception(e);
+    }
   }
 
  private:
   HostPool() {
     const unsigned hw = std::thread::hardware_concurrency();
-    nw_ = (int)std::max(1u, std::min(hw, 16u)) - 1;
-    for (int t = 1; t <= nw_; ++t) std::thread([this, t] { loop(t); }).detach();
+    const int want = (int)std::max(1u, std::min(hw, 16u)) - 1;
+    // the workers that could be started (a thread that cannot start leaves
+    // the pool smaller, not broken); they first read nw_ in a call
+    for (int t = 1; t <= want; ++t) {
+      try {
+        std::thread([this, t] { loop(t); }).detach();
+      } catch (...) {
+        break;
+      }
+      nw_ = t;
+    }
   }
 
-  void slice(int id, const std::function<void(int, int)>& f, int n) const {
+  // the participant's chunks; it stops at the first exception and keeps it
+  void slice(int id, const std::function<void(int, int)>& f, int n) {
     const int P = nw_ + 1;
-    for (long long c = id; c * kChunk < n; c += P) f((int)(c * kChunk), (int)std::min<long long>(n, (c + 1) * kChunk));
+    try {
+      for (long long c = id; c * kChunk < n; c += P)
+        f((int)(c * kChunk), (int)std::min<long long>(n, (c + 1) * kChunk));
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(m_);
+      if (!error_) error_ = std::current_exception();
+    }
   }
 
   void loop(int id) {
@@ -79,6 +104,7 @@ class HostPool {
   std::condition_variable cv_, fin_;
   const std::function<void(int, int)>* fn_ = nullptr;
   int n_ = 0, pending_ = 0;
+  std::exception_ptr error_;
   unsigned long long gen_ = 0;
 };
 
