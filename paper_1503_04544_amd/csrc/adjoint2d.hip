@@ -396,15 +396,20 @@ __global__ void k_fill0(double* __restrict__ p, size_t n) {
     p[t] = 0.0;
 }
 
-// fixed-order sum of the partial arrays into out[4]
-__global__ void __launch_bounds__(256) k_adj_sum(const double* __restrict__ part, int nparts,
+// fixed-order sum of the partial arrays into out[4], in two passes: block b
+// of the first sums the partials [b*span, (b+1)*span) into mid[b] (kSumBlocks
+// blocks), one block then sums mid in block order
+constexpr int kSumBlocks = 256;
+
+__global__ void __launch_bounds__(256) k_adj_sum(const double* __restrict__ part, int nparts, int span,
                                                  double* __restrict__ out) {
   __shared__ double lds[8];
+  const int t0 = blockIdx.x * span, t1 = min(nparts, t0 + span);
   for (int r = 0; r < 4; ++r) {
     double s = 0.0;
-    for (int t = threadIdx.x; t < nparts; t += blockDim.x) s += part[4 * (size_t)t + r];
+    for (int t = t0 + threadIdx.x; t < t1; t += blockDim.x) s += part[4 * (size_t)t + r];
     s = bsum(s, lds);
-    if (threadIdx.x == 0) out[r] = s;
+    if (threadIdx.x == 0) out[4 * (size_t)blockIdx.x + r] = s;
   }
 }
 
@@ -429,7 +434,7 @@ AdjParams adj_params(const cc_ctx* ctx, int objective) {
 
 // Pool layout for the adjoint of nsteps steps with a checkpoint every K.
 struct AdjLayout {
-  size_t ckpt, ckmom, seg, segmom, mu0, mu1, part, out, total;
+  size_t ckpt, ckmom, seg, segmom, mu0, mu1, part, mid, out, total;
   int nckpt, K, nparts, nreg_blocks;
 };
 
@@ -445,11 +450,12 @@ static AdjLayout adj_layout(const cc_ctx* ctx, int nsteps, int K) {
   size_t off = 0;
   L.ckpt = off; off += st * (size_t)L.nckpt;
   L.ckmom = off; off += mb * (size_t)L.nckpt;
-  L.seg = off; off += st * (size_t)K;
+  L.seg = off; off += st * (size_t)(K - 1);   // states 1 .. K-1 of a segment (state 0 is its checkpoint)
   L.segmom = off; off += mb * (size_t)K;
   L.mu0 = off; off += st;
   L.mu1 = off; off += st;
   L.part = off; off += al256((size_t)L.nparts * 4 * sizeof(double));
+  L.mid = off; off += al256((size_t)kSumBlocks * 4 * sizeof(double));
   L.out = off; off += 256;
   L.total = off;
   return L;
@@ -511,10 +517,10 @@ hipError_t adjoint_run_2d(cc_ctx* ctx, int nsteps, int K, int objective, char* p
   // backward over the segments
   for (int sg = L.nckpt - 1; sg >= 0; --sg) {
     const int n0 = sg * K, n1 = nsteps < n0 + K ? nsteps : n0 + K, len = n1 - n0;
-    char* seg = pool + L.seg;
+    // state i of the segment: its checkpoint for i = 0 (read in place, never
+    // written), else slot i-1 of the segment buffer
+    auto state = [&](int i) { return i == 0 ? pool + L.ckpt + st * (size_t)sg : pool + L.seg + st * (size_t)(i - 1); };
     char* segmom = pool + L.segmom;
-    e = hipMemcpyAsync(seg, pool + L.ckpt + st * (size_t)sg, st, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
     e = hipMemcpyAsync(segmom, pool + L.ckmom + mb * (size_t)sg, (size_t)ctx->ncell * 4 * sizeof(double),
                        hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
@@ -522,27 +528,47 @@ hipError_t adjoint_run_2d(cc_ctx* ctx, int nsteps, int K, int objective, char* p
       e = hipMemcpyAsync(segmom + mb * (i + 1), segmom + mb * i, (size_t)ctx->ncell * 4 * sizeof(double),
                          hipMemcpyDeviceToDevice, s);
       if (e != hipSuccess) return e;
-      e = launch_step_2d_ptrs(ctx, (const double2*)(seg + st * i), (double2*)(seg + st * (i + 1)),
+      e = launch_step_2d_ptrs(ctx, (const double2*)state(i), (double2*)state(i + 1),
                               (double*)(segmom + mb * (i + 1)));
       if (e != hipSuccess) return e;
     }
     for (int i = len - 1; i >= 0; --i) {
-      B.x = (const double2*)(seg + st * i);
+      B.x = (const double2*)state(i);
       B.mom = (const double*)(segmom + mb * i);
       B.mu_in = (const double2*)mu[cur_mu];
       B.mu_out = (double2*)mu[1 - cur_mu];
-      prof_begin(ctx, 1);
-      if (ctx->n_irr > 0) k_adj_cut2d<<<ctx->n_irr, 256, 0, s>>>(ctx->g2, B, P, cut_base);
-      prof_end(ctx, 1);
+      // cut control volumes and regular cells write disjoint cells and
+      // partial slots: the former run on the side stream beside the latter
+      // (one after the other while profiling)
+      const bool overlap = ctx->n_irr > 0 && ctx->side && !ctx->prof.on;
+      if (overlap) {
+        e = hipEventRecord(ctx->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->fork, 0);
+        if (e != hipSuccess) return e;
+        k_adj_cut2d<<<ctx->n_irr, 256, 0, ctx->side>>>(ctx->g2, B, P, cut_base);
+        e = hipEventRecord(ctx->join, ctx->side);
+        if (e != hipSuccess) return e;
+      } else if (ctx->n_irr > 0) {
+        prof_begin(ctx, 1);
+        k_adj_cut2d<<<ctx->n_irr, 256, 0, s>>>(ctx->g2, B, P, cut_base);
+        prof_end(ctx, 1);
+      }
       prof_begin(ctx, 0);
       k_adj_regular2d<<<L.nreg_blocks, 256, 0, s>>>(ctx->g2, B, P);
       prof_end(ctx, 0);
+      if (overlap) {
+        e = hipStreamWaitEvent(s, ctx->join, 0);
+        if (e != hipSuccess) return e;
+      }
       cur_mu = 1 - cur_mu;
     }
   }
   B.mu_in = (const double2*)mu[cur_mu];
   k_adj_initial2d<<<ctx->ncell, 256, 0, s>>>(ctx->g2, B, P, L.nreg_blocks + 2 * ctx->ncell);
-  k_adj_sum<<<1, 256, 0, s>>>(part, L.nparts, dev_out + 4);
+  double* mid = (double*)(pool + L.mid);
+  const int span = (L.nparts + kSumBlocks - 1) / kSumBlocks;
+  k_adj_sum<<<kSumBlocks, 256, 0, s>>>(part, L.nparts, span, mid);
+  k_adj_sum<<<1, 256, 0, s>>>(mid, kSumBlocks, kSumBlocks, dev_out + 4);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   double h[8];

@@ -2001,8 +2001,23 @@ hipError_t launch_step_2d_ptrs(cc_ctx* ctx, const double2* in, double2* out, dou
   A.prev_mpart = nullptr;
   A.red_force = nullptr;
   A.red_mass = nullptr;
-  if (A.n_cut > 0) k_cutstep2d<<<A.n_cut, 256, 0, ctx->stream>>>(ctx->g2, A, P);
+  // the cut control volumes beside the streaming kernel, as in the forward step
+  const bool overlap = A.n_cut > 0 && ctx->side && !ctx->prof.on;
+  if (overlap) {
+    hipError_t e = hipEventRecord(ctx->fork, ctx->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->fork, 0);
+    if (e != hipSuccess) return e;
+    k_cutstep2d<<<A.n_cut, 256, 0, ctx->side>>>(ctx->g2, A, P);
+    e = hipEventRecord(ctx->join, ctx->side);
+    if (e != hipSuccess) return e;
+  } else if (A.n_cut > 0) {
+    k_cutstep2d<<<A.n_cut, 256, 0, ctx->stream>>>(ctx->g2, A, P);
+  }
   fn(ctx, dim3(A.tile_base + A.ntiles_pad), A, P);
+  if (overlap) {
+    hipError_t e = hipStreamWaitEvent(ctx->stream, ctx->join, 0);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 
