@@ -105,6 +105,8 @@ struct AmrBuildScratch {
   std::vector<std::vector<int>> part;               // leaves (depth, i, j, k) per chunk of coarse cells
   std::vector<std::vector<int>> fnb, fdir;          // face entries per chunk of leaves
   std::vector<std::vector<double>> farea;
+  std::vector<int> chunk_faces;                     // entries used in each chunk's lists
+  std::vector<int> counts;                          // per chunk: irregular CVs, members, solid leaves
 };
 
 // Octree mesh (3D): built on the host when the context is created

@@ -141,45 +141,101 @@ void leaf_geometry(const cc_config& cfg, const AmrHost& H, const BodyDev& B, int
 // (volume or receivers differ between t^n and t^{n+1}) join the last group.
 bool order_cvs(AmrHost& H, const std::vector<char>* changed, std::string& err) {
   const int n = H.nleaf;
-  std::vector<int> cnt(n, 0);
-  for (int q = 0; q < n; ++q) if (H.master[q] >= 0) cnt[H.master[q]]++;
-  H.cv.clear(); H.cvptr.assign(1, 0); H.cvmem.clear();
-  std::vector<int> slot(n, -1);
+  HostPool& pool = HostPool::get();
+  const int C = HostPool::kChunk;
+  const int nchunk = (n + C - 1) / C;
+  // members per master: the master itself (leaves in parallel), then the
+  // other members ("foreign", few), gathered per chunk and added in leaf order
+  std::vector<int> cnt(n);
+  std::vector<std::vector<int>> foreign(nchunk);
+  pool.run(n, [&](int b, int e) {
+    std::vector<int>& f = foreign[b / C];
+    for (int q = b; q < e; ++q) {
+      const int m = H.master[q];
+      cnt[q] = m == q ? 1 : 0;
+      if (m >= 0 && m != q) f.push_back(q);
+    }
+  });
+  std::vector<int> fq;
+  for (const std::vector<int>& f : foreign) fq.insert(fq.end(), f.begin(), f.end());
+  for (int q : fq) cnt[H.master[q]]++;
   auto kind_of = [&](int q) {
     if (cnt[q] != 1 || H.aw[q] > 0.0 || (changed && (*changed)[q])) return 2;
     if (H.fptr[q + 1] - H.fptr[q] != 6) return 1;
     for (int t = 0; t < 6; ++t) if (H.fdir[H.fptr[q] + t] != t) return 1;
     return 0;
   };
-  // kind of every master (-1 for other leaves), leaves in parallel
+  // kind of every master (-1 for other leaves) and the count of each kind
+  // per chunk, leaves in parallel
   std::vector<signed char> kind(n);
+  std::vector<int> kc(3 * (size_t)nchunk, 0);
   std::atomic<bool> too_many{false};
-  HostPool::get().run(n, [&](int b, int e) {
+  pool.run(n, [&](int b, int e) {
+    int k3[3] = {0, 0, 0};
     for (int q = b; q < e; ++q) {
-      kind[q] = H.master[q] == q ? (signed char)kind_of(q) : (signed char)-1;
+      const int kd = H.master[q] == q ? kind_of(q) : -1;
+      kind[q] = (signed char)kd;
+      if (kd >= 0) k3[kd]++;
       if (H.master[q] == q && cnt[q] > kMaxMembers) too_many = true;
     }
+    for (int t = 0; t < 3; ++t) kc[3 * (size_t)(b / C) + t] = k3[t];
   });
   if (too_many) { err = "a control volume has more members than supported"; return false; }
-  H.nsimple = 0; H.nreg = 0;
-  H.cv.reserve(n); H.cvptr.reserve(n + 1);
-  for (int pass = 0; pass < 3; ++pass)
-    for (int q = 0; q < n; ++q)
-      if (kind[q] == pass) {
-        const int kd = pass;
-        H.nsimple += kd == 0;
-        H.nreg += kd <= 1;
-        slot[q] = (int)H.cv.size();
-        H.cv.push_back(q);
-        H.cvptr.push_back(H.cvptr.back() + cnt[q]);
-      }
-  H.cvmem.assign(H.cvptr.back(), 0);
-  std::vector<int> fill(H.cv.size(), 0);
-  for (int q = 0; q < n; ++q)
-    if (H.master[q] >= 0) {
-      const int s = slot[H.master[q]];
-      H.cvmem[H.cvptr[s] + fill[s]++] = q;
+  // control volumes in kind order, each kind in leaf order: chunk c's
+  // masters of kind t start at the kinds before t plus chunks before c
+  std::vector<int> start(3 * (size_t)nchunk);
+  int at = 0;
+  for (int t = 0; t < 3; ++t) {
+    if (t == 1) H.nsimple = at;
+    if (t == 2) H.nreg = at;
+    for (int c = 0; c < nchunk; ++c) { start[3 * (size_t)c + t] = at; at += kc[3 * (size_t)c + t]; }
+  }
+  const int ncv = at;
+  H.cv.resize(ncv);
+  std::vector<int> slot(n);
+  pool.run(n, [&](int b, int e) {
+    int pos[3];
+    for (int t = 0; t < 3; ++t) pos[t] = start[3 * (size_t)(b / C) + t];
+    for (int q = b; q < e; ++q) {
+      const int kd = kind[q];
+      slot[q] = kd >= 0 ? pos[kd] : -1;
+      if (kd >= 0) H.cv[pos[kd]++] = q;
     }
+  });
+  // member offsets: a prefix sum over the control volumes, chunks in parallel
+  const int ncc = (ncv + C - 1) / C;
+  std::vector<int> csum(ncc + 1, 0);
+  pool.run(ncv, [&](int b, int e) {
+    int sum = 0;
+    for (int s = b; s < e; ++s) sum += cnt[H.cv[s]];
+    csum[b / C + 1] = sum;
+  });
+  for (int c = 0; c < ncc; ++c) csum[c + 1] += csum[c];
+  H.cvptr.resize(ncv + 1);
+  H.cvptr[0] = 0;
+  pool.run(ncv, [&](int b, int e) {
+    int off = csum[b / C];
+    for (int s = b; s < e; ++s) { off += cnt[H.cv[s]]; H.cvptr[s + 1] = off; }
+  });
+  // members in leaf order: a lone master is its only member; a master with
+  // foreign members takes its place among them
+  H.cvmem.resize(ncv ? H.cvptr[ncv] : 0);
+  pool.run(ncv, [&](int b, int e) {
+    for (int s = b; s < e; ++s) H.cvmem[H.cvptr[s]] = H.cv[s];
+  });
+  if (!fq.empty()) {
+    std::vector<int> fill(ncv, 0), touched;
+    std::vector<char> placed(ncv, 0);
+    for (int q : fq) {   // ascending
+      const int m = H.master[q], sl = slot[m];
+      if (fill[sl] == 0 && !placed[sl]) touched.push_back(sl);
+      if (!placed[sl] && m < q) { H.cvmem[H.cvptr[sl] + fill[sl]++] = m; placed[sl] = 1; }
+      H.cvmem[H.cvptr[sl] + fill[sl]++] = q;
+    }
+    // a master above all its foreign members comes last
+    for (int sl : touched)
+      if (!placed[sl]) H.cvmem[H.cvptr[sl] + fill[sl]++] = H.cv[sl];
+  }
   return true;
 }
 
@@ -330,33 +386,40 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
         }
     }
   };
-  // one pass into per-chunk lists (chunks are ranges of leaves), then
+  // one pass into per-chunk lists (chunks are ranges of leaves, each list
+  // sized once for the most entries a chunk can have: 24 per leaf), then
   // concatenated in leaf order
+  constexpr int kMaxFaces = 24;
   const size_t nch = (n + HostPool::kChunk - 1) / HostPool::kChunk;
   X.fnb.resize(nch); X.fdir.resize(nch); X.farea.resize(nch);
+  std::vector<int>& chunk_faces = X.chunk_faces;
+  chunk_faces.resize(nch);
   H.fptr.resize(n + 1);
   H.fptr[0] = 0;
   pool.run(n, [&](int b, int e) {
     const int c = b / HostPool::kChunk;
-    std::vector<int>& Fnb = X.fnb[c];
-    std::vector<int>& Fdir = X.fdir[c];
-    std::vector<double>& Farea = X.farea[c];
-    Fnb.clear(); Fdir.clear(); Farea.clear();
+    const size_t cap = (size_t)kMaxFaces * HostPool::kChunk;
+    if (X.fnb[c].size() != cap) { X.fnb[c].resize(cap); X.fdir[c].resize(cap); X.farea[c].resize(cap); }
+    int* Fnb = X.fnb[c].data();
+    int* Fdir = X.fdir[c].data();
+    double* Farea = X.farea[c].data();
+    int k = 0;
     for (int q = b; q < e; ++q) {
-      const size_t before = Fnb.size();
-      faces_of(q, [&](int nb, int t, double A) { Fnb.push_back(nb); Fdir.push_back(t); Farea.push_back(A); });
-      H.fptr[q + 1] = (int)(Fnb.size() - before);
+      const int before = k;
+      faces_of(q, [&](int nb, int t, double A) { Fnb[k] = nb; Fdir[k] = t; Farea[k] = A; ++k; });
+      H.fptr[q + 1] = k - before;
     }
+    chunk_faces[c] = k;
   });
   for (int q = 0; q < n; ++q) H.fptr[q + 1] += H.fptr[q];
   H.nface = H.fptr[n];
   H.fnb.resize(H.nface); H.fdir.resize(H.nface); H.farea.resize(H.nface);
   pool.run((int)nch, [&](int b, int e) {
     for (int c = b; c < e; ++c) {
-      const int at = H.fptr[c * HostPool::kChunk];
-      std::copy(X.fnb[c].begin(), X.fnb[c].end(), H.fnb.begin() + at);
-      std::copy(X.fdir[c].begin(), X.fdir[c].end(), H.fdir.begin() + at);
-      std::copy(X.farea[c].begin(), X.farea[c].end(), H.farea.begin() + at);
+      const int at = H.fptr[c * HostPool::kChunk], m = chunk_faces[c];
+      std::copy(X.fnb[c].begin(), X.fnb[c].begin() + m, H.fnb.begin() + at);
+      std::copy(X.fdir[c].begin(), X.fdir[c].begin() + m, H.fdir.begin() + at);
+      std::copy(X.farea[c].begin(), X.farea[c].begin() + m, H.farea.begin() + at);
     }
   });
   if (jump) { err = "neighbouring leaves differ by more than one depth"; return false; }
@@ -402,27 +465,48 @@ bool build_octree_3d(const cc_config& cfg, const cc_body& body, double theta, Am
   }
   });
   if (master_bad) { err = "master search cycles, leaves the domain, crosses a change of depth or needs more than 4 hops"; return false; }
-  for (int q = 0; q < n; ++q)
-    if (H.master[q] >= 0 && H.master[H.master[q]] != H.master[q]) { err = "a master is not its own master"; return false; }
+  std::atomic<bool> not_own{false};
+  pool.run(n, [&](int b, int e) {
+    for (int q = b; q < e; ++q)
+      if (H.master[q] >= 0 && H.master[H.master[q]] != H.master[q]) not_own = true;
+  });
+  if (not_own) { err = "a master is not its own master"; return false; }
   if (!order_cvs(H, nullptr, err)) return false;
+  // control-volume volumes (members in order) and the counts, per chunk
   H.vcv.resize(n);
   pool.run(n, [&](int b, int e) { std::fill(H.vcv.begin() + b, H.vcv.begin() + e, 0.0); });
-  for (size_t s = 0; s < H.cv.size(); ++s) {
-    double v = 0.0;
-    for (int e = H.cvptr[s]; e < H.cvptr[s + 1]; ++e) v += H.vbar[H.cvmem[e]];
-    H.vcv[H.cv[s]] = v;
-  }
+  const int ncv = (int)H.cv.size();
+  std::vector<int>& cnt3 = X.counts;
+  cnt3.assign(3 * (size_t)((std::max(ncv, n) + HostPool::kChunk - 1) / HostPool::kChunk), 0);
+  pool.run(ncv, [&](int b, int e) {
+    int irr = 0, mem = 0;
+    for (int s = b; s < e; ++s) {
+      double v = 0.0;
+      bool wall = false;
+      for (int k = H.cvptr[s]; k < H.cvptr[s + 1]; ++k) {
+        v += H.vbar[H.cvmem[k]];
+        wall = wall || H.aw[H.cvmem[k]] > 0.0;
+      }
+      H.vcv[H.cv[s]] = v;
+      const int nm = H.cvptr[s + 1] - H.cvptr[s];
+      irr += nm > 1 || wall;
+      mem += nm - 1;
+    }
+    cnt3[3 * (size_t)(b / HostPool::kChunk)] = irr;
+    cnt3[3 * (size_t)(b / HostPool::kChunk) + 1] = mem;
+  });
+  pool.run(n, [&](int b, int e) {
+    int sol = 0;
+    for (int q = b; q < e; ++q) sol += H.type[q] == TYPE_SOLID;
+    cnt3[3 * (size_t)(b / HostPool::kChunk) + 2] = sol;
+  });
   H.n_irr = 0; H.n_members = 0; H.n_solid = 0;
-  for (size_t s = 0; s < H.cv.size(); ++s) {
-    const int nm = H.cvptr[s + 1] - H.cvptr[s];
-    bool wall = false;
-    for (int e = H.cvptr[s]; e < H.cvptr[s + 1]; ++e) wall = wall || H.aw[H.cvmem[e]] > 0.0;
-    if (nm > 1 || wall) ++H.n_irr;
-    H.n_members += nm - 1;
+  for (size_t c = 0; 3 * c < cnt3.size(); ++c) {
+    H.n_irr += cnt3[3 * c]; H.n_members += cnt3[3 * c + 1]; H.n_solid += cnt3[3 * c + 2];
   }
-  for (int q = 0; q < n; ++q) H.n_solid += H.type[q] == TYPE_SOLID;
-  H.type1.clear(); H.vbar1.clear(); H.flags1.clear(); H.S61.clear(); H.aw1.clear(); H.nw1.clear(); H.r1.clear();
-  H.vnew.clear(); H.rptr.clear(); H.rmem.clear();
+  // the plan arrays (type1 .. rmem) keep their stale contents and sizes: the
+  // plan of a step writes every entry, and resizing a recycled mesh's arrays
+  // to about the same size then costs no fill
   return true;
 }
 
