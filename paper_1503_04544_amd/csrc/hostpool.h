@@ -5,12 +5,16 @@
 // calling thread is participant 0), and returns when every participant is
 // done.  Every worker takes part in every call, so a call cannot start
 // before all workers have finished the previous one; calls from several
-// threads are serialised.  An exception thrown by fn on any participant
+// threads are serialised.  A waiting thread spins for a few tens of
+// microseconds before it sleeps (a mesh build makes a few dozen calls in a
+// row).  An exception thrown by fn on any participant
 // (the first one caught) is rethrown by run on the calling thread once
 // every participant is done.
 #pragma once
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <exception>
 #include <functional>
@@ -37,15 +41,18 @@ class HostPool {
     std::lock_guard<std::mutex> serial(call_);
     {
       std::lock_guard<std::mutex> lk(m_);
-      fn_ = &fn; n_ = n; pending_ = nw_;
+      fn_ = &fn; n_ = n;
       error_ = nullptr;
-      ++gen_;
+      pending_.store(nw_, std::memory_order_relaxed);
+      gen_.store(gen_.load(std::memory_order_relaxed) + 1, std::memory_order_release);
     }
     cv_.notify_all();
     slice(0, fn, n);
-    std::unique_lock<std::mutex> lk(m_);
-    fin_.wait(lk, [&] { return pending_ == 0; });
-    fn_ = nullptr;
+    spin_until([&] { return pending_.load(std::memory_order_acquire) == 0; });
+    if (pending_.load(std::memory_order_acquire) != 0) {
+      std::unique_lock<std::mutex> lk(m_);
+      fin_.wait(lk, [&] { return pending_.load(std::memory_order_acquire) == 0; });
+    }
     if (error_) {
       std::exception_ptr e = error_;
       error_ = nullptr;
@@ -54,10 +61,22 @@ class HostPool {
   }
 
  private:
+  static constexpr std::chrono::microseconds kSpin{50};
+
+  template <class Pred>
+  static void spin_until(Pred&& done) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int k = 1; !done(); ++k) {
+      __builtin_ia32_pause();
+      if ((k & 63) == 0 && std::chrono::steady_clock::now() - t0 > kSpin) return;
+    }
+  }
+
   HostPool() {
     // at most 12 participants: with the 16 host CPUs one GPU gets, the rest
     // is left to the thread that drives the device, the concurrent mesh
-    // build's caller and the HIP runtime (12 measured faster than 8 or 16)
+    // build's caller and the HIP runtime (12 measured faster than 8 or 16,
+    // and leaves room for the spinning)
     const unsigned hw = std::thread::hardware_concurrency();
     const int want = (int)std::max(1u, std::min(hw, 12u)) - 1;
     // the workers that could be started (a thread that cannot start leaves
@@ -84,21 +103,23 @@ class HostPool {
     }
   }
 
+  // fn_ and n_ are written before the release store of gen_ and read after
+  // the acquire load that sees it; a call cannot start before every worker
+  // has finished the previous one, so no generation is skipped
   void loop(int id) {
     unsigned long long seen = 0;
     for (;;) {
-      const std::function<void(int, int)>* f;
-      int n;
-      {
+      spin_until([&] { return gen_.load(std::memory_order_acquire) != seen; });
+      if (gen_.load(std::memory_order_acquire) == seen) {
         std::unique_lock<std::mutex> lk(m_);
-        cv_.wait(lk, [&] { return gen_ != seen; });
-        seen = gen_;
-        f = fn_;
-        n = n_;
+        cv_.wait(lk, [&] { return gen_.load(std::memory_order_acquire) != seen; });
       }
-      slice(id, *f, n);
-      std::lock_guard<std::mutex> lk(m_);
-      if (--pending_ == 0) fin_.notify_all();
+      seen = gen_.load(std::memory_order_acquire);
+      slice(id, *fn_, n_);
+      if (pending_.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+        std::lock_guard<std::mutex> lk(m_);
+        fin_.notify_all();
+      }
     }
   }
 
@@ -106,9 +127,10 @@ class HostPool {
   std::mutex m_, call_;
   std::condition_variable cv_, fin_;
   const std::function<void(int, int)>* fn_ = nullptr;
-  int n_ = 0, pending_ = 0;
+  int n_ = 0;
+  std::atomic<int> pending_{0};
   std::exception_ptr error_;
-  unsigned long long gen_ = 0;
+  std::atomic<unsigned long long> gen_{0};
 };
 
 }  // namespace ccdvm
