@@ -1394,6 +1394,9 @@ __global__ void __launch_bounds__(256) k_batch_tiles2d(const BatchInst* __restri
                                                        const int2* __restrict__ items, int nitems,
                                                        int nitems_pad) {
   __shared__ double lds[8];
+  // the lower halves exchanged through LDS as in the single-instance kernel
+  constexpr bool kX = CCDVM_XLDS && NCH <= 16;
+  __shared__ d2v xlo[kX ? kTileW * NCH * kWave : 1];
   const int b = blockIdx.x;
   const int per = nitems_pad / 8;
   const int w = (b % 8) * per + b / 8;
@@ -1401,7 +1404,7 @@ __global__ void __launch_bounds__(256) k_batch_tiles2d(const BatchInst* __restri
   const int2 it = items[w];
   const int inst = __builtin_amdgcn_readfirstlane(it.x);
   const int tile = __builtin_amdgcn_readfirstlane(it.y);
-  regular_tile<NCH, false, false>(D[inst].T, D[inst].P, tile, lds);
+  regular_tile<NCH, false, false>(D[inst].T, D[inst].P, tile, lds, kX ? xlo : nullptr);
 }
 
 __global__ void __launch_bounds__(256) k_batch_cut2d(const BatchInst* __restrict__ D,
