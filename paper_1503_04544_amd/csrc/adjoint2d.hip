@@ -483,21 +483,35 @@ hipError_t adjoint_run_2d(cc_ctx* ctx, int nsteps, int K, int objective, char* p
   k_fill0<<<512, 256, 0, s>>>(part, (size_t)L.nparts * 4);
   k_fill0<<<1024, 256, 0, s>>>((double*)(pool + L.mu0), st / 8);
   k_fill0<<<1024, 256, 0, s>>>((double*)(pool + L.mu1), st / 8);
-  // forward with checkpoints
+  // forward with checkpoints: the state entering step n (n % K == 0) and the
+  // moments it uses, so that the recomputation replays the forward bit for
+  // bit.  The step before a checkpoint writes its output straight into the
+  // checkpoint buffer (the context's output slot points there for that
+  // step), and the next step reads it from there; only the first state is
+  // copied.  The slots get their own buffers back on every exit.
+  struct Slots {
+    cc_ctx* c;
+    void* own[2];
+    ~Slots() { c->state[0] = own[0]; c->state[1] = own[1]; }
+  } slots{ctx, {ctx->state[0], ctx->state[1]}};
   for (int n = 0; n < nsteps; ++n) {
-    if (n % K == 0) {
-      // the state and the moments the next step will use, so that the
-      // recomputation replays the forward bit for bit
-      e = hipMemcpyAsync(pool + L.ckpt + st * (size_t)(n / K), ctx->state[ctx->cur], st,
-                         hipMemcpyDeviceToDevice, s);
+    if (n == 0) {
+      e = hipMemcpyAsync(pool + L.ckpt, ctx->state[ctx->cur], st, hipMemcpyDeviceToDevice, s);
       if (e != hipSuccess) return e;
+    }
+    if (n % K == 0) {
       e = hipMemcpyAsync(pool + L.ckmom + mb * (size_t)(n / K), ctx->s.mom,
                          (size_t)ctx->ncell * 4 * sizeof(double), hipMemcpyDeviceToDevice, s);
       if (e != hipSuccess) return e;
     }
+    const int out = 1 - ctx->cur;
+    ctx->state[out] = (n + 1) % K == 0 && n + 1 < nsteps ? pool + L.ckpt + st * (size_t)((n + 1) / K)
+                                                        : slots.own[out];
     e = launch_step_2d_fused(ctx, false, nullptr, nullptr, false);
     if (e != hipSuccess) return e;
   }
+  // the final state (written to its own slot) is the current one
+  ctx->state[1 - ctx->cur] = slots.own[1 - ctx->cur];
   // objective value and its sensitivity mu^N
   double* dev_out = (double*)(pool + L.out);
   e = launch_force_only_2d(ctx, dev_out);
