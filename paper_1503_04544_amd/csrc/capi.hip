@@ -205,6 +205,8 @@ void prof_end(cc_ctx* ctx, int k) {
 
 }  // namespace ccdvm
 
+namespace {
+
 // Exceptions do not cross the C interface: a host allocation that fails,
 // or a host thread that cannot start, ends the call with CC_ENOMEM and the
 // reason in the object's last error (when there is an object to hold it).
@@ -227,9 +229,6 @@ cc_status no_throw(std::string* err, F&& f) noexcept {
   }
   return CC_ENOMEM;
 }
-
-namespace {
-
 
 // The octree of the initial angle; for a turning body also the capacities
 // of the device arrays: the largest mesh over a half turn (16 angles; the
