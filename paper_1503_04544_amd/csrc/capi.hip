@@ -616,8 +616,12 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
   // on the host while the device runs the step
   auto t2 = std::chrono::steady_clock::now();
   // the mesh of two steps ago is recycled (its vectors keep their capacity)
-  AmrHost* N1 = ctx->amr_spare ? ctx->amr_spare : new (std::nothrow) AmrHost();
+  // held until the context takes it over, so that every early return
+  // (including an exception) frees it; the build's future is destroyed
+  // first and waits for the build to end
+  std::unique_ptr<AmrHost> hold(ctx->amr_spare ? ctx->amr_spare : new (std::nothrow) AmrHost());
   ctx->amr_spare = nullptr;
+  AmrHost* N1 = hold.get();
   if (!N1) return fail(ctx, CC_ENOMEM, "host allocation");
   std::string err1;
   double build_ms = 0.0;
@@ -631,19 +635,13 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
   hipError_t he = hipMemcpyAsync(&tq, drow + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
   const bool ok1 = built.get();
-  if (he != hipSuccess) { delete N1; return hip_fail(ctx, he, "step"); }
-  if (!ok1) { delete N1; return fail(ctx, CC_EGEOM, err1); }
-  // explicit Euler for the body: angle with the old angular velocity, the
-  // angular velocity with the torque of t^n (free rotation)
-  ctx->body_state[2] = th1;
-  if (ctx->body.motion == CC_MOTION_FREE_ROTATION) ctx->body_state[5] = om + ctx->dt * tq / ctx->body.inertia;
+  if (he != hipSuccess) return hip_fail(ctx, he, "step");
+  if (!ok1) return fail(ctx, CC_EGEOM, err1);
   // the state carried over to the mesh of t^{n+1}
   AmrRemap R;
   build_amr_remap(H, *N1, ctx->cfg.amr_depth, R);
-  if (N1->nleaf > H.cap_leaf || N1->nface > H.cap_face || (long long)R.src.size() > 2LL * H.cap_leaf) {
-    delete N1;
+  if (N1->nleaf > H.cap_leaf || N1->nface > H.cap_face || (long long)R.src.size() > 2LL * H.cap_leaf)
     return fail(ctx, CC_ENOMEM, "the adapted mesh outgrew the buffers sized at cc_create");
-  }
   N1->cap_leaf = H.cap_leaf; N1->cap_face = H.cap_face;
   AmrDev& G = ctx->a3;
   HIPCHK(ctx, hipMemcpyAsync(G.sptr, R.sptr.data(), R.sptr.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream),
@@ -661,8 +659,12 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
     ctx->prof.host_ms[2] += build_ms;
     for (int k = 0; k < 3; ++k) ctx->prof.host_count[k] += 1;
   }
+  // explicit Euler for the body: angle with the old angular velocity, the
+  // angular velocity with the torque of t^n (free rotation)
+  ctx->body_state[2] = th1;
+  if (ctx->body.motion == CC_MOTION_FREE_ROTATION) ctx->body_state[5] = om + ctx->dt * tq / ctx->body.inertia;
   AmrHost* old = ctx->amrh;
-  ctx->amrh = N1;
+  ctx->amrh = hold.release();
   ctx->ncell = N1->nleaf;
   // copies from pageable host memory return once the data is staged, so
   // the host vectors may change afterwards; the next step's planning on
