@@ -36,6 +36,10 @@ def relerr(a, b):
 I = "imex"
 CASES2 = {
     "cyl32_n8_kn001": small_2d(32, 32, 8, kn=0.01, mach=0.9, scheme=I),
+    # 32^2 velocities: eight chunks per half, the instantiation of the fused
+    # kernel that the 512x256 benchmark runs (ragged grid, several tiles)
+    "n32_ragged": small_2d(42, 26, 32, kn=0.01, mach=0.8, body=Body("circle", (0.48, 0.5, 0), (0.2, 0.2, 0)), scheme=I),
+    "n32_shakhov": small_2d(36, 20, 32, kn=0.02, mach=0.6, scheme=I, model="shakhov"),
     "tiny6_merge": small_2d(6, 6, 4, kn=0.002, mach=0.4, body=Body("circle", (0.5, 0.52, 0), (0.19, 0.19, 0)), scheme=I),
     "ragged_n12_cons": small_2d(20, 14, 12, kn=0.005, mach=0.6, body=Body("circle", (0.45, 0.5, 0), (0.22, 0.22, 0), t_wall=1.4),
                                 scheme=I, maxwellian="conservative"),
@@ -64,8 +68,9 @@ def test_one_step_2d(name):
     assert abs(d[0, 3] - do[3]) <= 1e-12 * abs(do[3])
 
 
-def test_twenty_steps_2d():
-    cfg = CASES2["cyl32_n8_kn001"]
+@pytest.mark.parametrize("name", ["cyl32_n8_kn001", "n32_ragged"])
+def test_twenty_steps_2d(name):
+    cfg = CASES2[name]
     s = solver(cfg)
     s.init_maxwellian()
     d = s.step(20, diag=True).cpu().numpy()
