@@ -61,6 +61,37 @@ def test_batch_equals_sequential_and_oracle():
     assert np.max(np.abs(got[1][0] - fo)) / np.max(fo) < 1e-10
 
 
+def test_batch_benchmark_velocity_grids():
+    """The velocity grids of the benchmark recipe (N = 16, 24, 32: one, five
+    and eight chunks per half-row, tiles of several columns with the lower
+    halves exchanged in LDS) on ragged grids: batched = alone, bitwise, and
+    the N = 24 instance = the oracle."""
+    from paper_1503_04544_amd.solver import Batch
+    cfgs = [
+        small_2d(30, 22, 24, kn=0.05, mach=0.7, body=Body("circle", (0.5, 0.45, 0), (0.2, 0.2, 0), t_wall=1.3)),
+        small_2d(26, 34, 32, kn=0.2, mach=0.4, body=Body("circle", (0.55, 0.5, 0), (0.22, 0.22, 0))),
+        small_2d(36, 18, 16, kn=0.01, mach=0.9, body=Body("circle", (0.5, 0.5, 0), (0.18, 0.18, 0), t_wall=0.6)),
+        small_2d(18, 26, 32, kn=1.0, mach=0.3, body=Body("ellipse", (0.5, 0.5, 0), (0.3, 0.08, 0), theta=0.4)),
+    ]
+    stream = torch.cuda.Stream()
+    seq = _solvers(cfgs, stream)
+    for s in seq:
+        s.step(10)
+    ref = _states(seq)
+    bat = _solvers(cfgs, stream)
+    b = Batch(bat)
+    assert len(b.groups()) == 3
+    b.autotune(2)
+    b.step(10)
+    got = _states(bat)
+    for (f0, g0), (f1, g1) in zip(ref, got):
+        assert np.array_equal(f0, f1) and np.array_equal(g0, g1)
+    o = Oracle2D(cfgs[0])
+    fo, go, _ = o.run(*o.init(), 10)
+    assert np.max(np.abs(got[0][0] - fo)) / np.max(fo) < 1e-10
+    assert np.max(np.abs(got[0][1] - go)) / np.max(go) < 1e-10
+
+
 def test_batch_autotune_and_interleaving_keep_results():
     from paper_1503_04544_amd.solver import Batch
     cfgs = _cfgs()
