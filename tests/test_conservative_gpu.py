@@ -37,6 +37,8 @@ CASES2 = {
     "cyl32_n8": small_2d(32, 32, 8, kn=0.1, mach=0.9, maxwellian=C),
     "tiny6_merge": small_2d(6, 6, 4, kn=0.07, mach=0.4, body=Body("circle", (0.5, 0.52, 0), (0.19, 0.19, 0)), maxwellian=C),
     "ragged_n12": small_2d(20, 14, 12, kn=0.3, mach=0.6, body=Body("circle", (0.45, 0.5, 0), (0.22, 0.22, 0), t_wall=1.4), maxwellian=C),
+    # 32^2 velocities, as the 512x256 benchmark: the Newton solve over 32 nodes per axis
+    "n32_ragged": small_2d(34, 22, 32, kn=0.05, mach=0.8, body=Body("circle", (0.5, 0.48, 0), (0.2, 0.2, 0)), maxwellian=C),
 }
 CASES3 = {
     "n16": small_3d(16, 8, 8, nv=16, kn=0.1, mach=0.5, maxwellian=C),
