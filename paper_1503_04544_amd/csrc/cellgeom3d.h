@@ -1,11 +1,28 @@
 // Per-cell 3D cut-cell geometry (Section 5.1; the paper leaves the 3D
-// geometry to the reader), shared by the uniform-grid geometry kernels and
-// the octree builder.  Rules:
-//   * a Cartesian face's gas area is the polygon of its gas corners and the
-//     linear crossings on its mixed edges; four crossings reject the face;
-//   * the wall face closes the cell, |S_w| n_w = -sum_faces |S_k| n_k, n_w
-//     pointing into the solid; its centre is the mean of the edge crossings;
-//   * the volume follows from the divergence theorem, V = 1/3 sum |S| (m.n).
+// geometry to the reader), used by the uniform-grid geometry kernels and the
+// octree builder.  Rules (the 2D virtual-cell rules of Appendix A carried to
+// the six faces of a hexahedral cell):
+//   * a Cartesian face's gas part is bounded by its gas corners and the linear
+//     crossings of the level set on its mixed edges; a face crossed on all
+//     four edges rejects the geometry;
+//   * the wall face is the surface spanned by the loop of edge crossings; its
+//     vector area (n_w pointing into the solid) closes the cell, so it equals
+//     minus the sum of the Cartesian faces' outward vector areas;
+//   * the wall centre is the mean of the edge crossings;
+//   * the gas volume follows from the divergence theorem.
+//
+// How it is evaluated here:
+//   * face areas by the number and position of the gas corners: a corner
+//     triangle, a trapezoid on the gas edge, or the face minus the solid
+//     corner triangles;
+//   * the wall vector area from the crossing loop itself (Newell's formula
+//     for a closed polygon, 1/2 sum p_k x p_{k+1}), one chord per crossed
+//     face, with the points taken about the wall centre;
+//   * the volume as a sum of pyramids with their apex at the wall centre
+//     (the wall fan contributes nothing), so each Cartesian face adds
+//     1/3 |S| times its distance to the apex.
+// Corner k of a cell sits at ((k >> 2) & 1, (k >> 1) & 1, k & 1) in units of
+// the cell sizes (x is the high bit).
 // Include after `#pragma clang fp contract(off)` so that host and device
 // evaluate the formulas in the order written.
 #pragma once
@@ -19,65 +36,40 @@
 namespace ccdvm {
 
 // Signed distance to the body, gas side positive (Appendix A).
-//   sphere: radius B.a.
+//   sphere: radius B.a about the centre.
 //   vane: the points within r = min(a, b, c) of the box of half-sizes
-//     (a, b, c) - r in the body frame, turned by B.theta about the z axis
-//     through the centre (a plate with rounded edges); B.ct, B.st hold
-//     cos and sin of B.theta.  With q = |p| - (a - r)
-//     in the body frame the distance to the box is |max(q, 0)| outside and
-//     the largest component of q inside.
+//     e = (a, b, c) - r, the box turned by B.theta about the z axis through
+//     the centre (B.ct, B.st hold cos and sin of B.theta).  The nearest point
+//     of the box to a point p outside it is p clamped to [-e, e]; inside, the
+//     distance is the smallest slack e_d - |p_d|.
 __host__ __device__ inline double level_set_3d(const BodyDev& B, double x, double y, double z) {
-  const double a = x - B.cx, b = y - B.cy, c = z - B.cz;
-  if (B.kind == CC_BODY_SPHERE) return sqrt(a * a + b * b + c * c) - B.a;
+  const double dx = x - B.cx, dy = y - B.cy, dz = z - B.cz;
+  if (B.kind == CC_BODY_SPHERE) return sqrt(dx * dx + dy * dy + dz * dz) - B.a;
   if (B.kind == CC_BODY_VANE) {
-    const double ct = B.ct, st = B.st;
-    const double p[3] = {ct * a + st * b, -st * a + ct * b, c};
-    const double ax[3] = {B.a, B.b, B.c};
-    const double r = B.a < (B.b < B.c ? B.b : B.c) ? B.a : (B.b < B.c ? B.b : B.c);
-    double out2 = 0.0, qmax = -1e300;
+    const double rr = fmin(B.a, fmin(B.b, B.c));
+    const double pb[3] = {B.ct * dx + B.st * dy, B.ct * dy - B.st * dx, dz};
+    const double e[3] = {B.a - rr, B.b - rr, B.c - rr};
+    bool inside = true;
+    double gap2 = 0.0, slack = 1e300;
     for (int d = 0; d < 3; ++d) {
-      const double q = fabs(p[d]) - (ax[d] - r);
-      const double qp = q > 0.0 ? q : 0.0;
-      out2 += qp * qp;
-      qmax = qmax > q ? qmax : q;
+      const double ad = fabs(pb[d]);
+      if (ad > e[d]) {
+        inside = false;
+        const double o = ad - e[d];
+        gap2 += o * o;
+      } else {
+        slack = fmin(slack, e[d] - ad);
+      }
     }
-    return sqrt(out2) + (qmax < 0.0 ? qmax : 0.0) - r;
+    return (inside ? -slack : sqrt(gap2)) - rr;
   }
   return 1.0e300;
 }
 
-// vertex value with the 1e-10 dx clamp, sign(0) = +1
+// vertex value with the 1e-10 dx floor on its magnitude, sign(0) = +1
 __host__ __device__ inline double clamp_vertex(double p, double dx) {
-  const double floor_ = 1e-10 * dx;
-  const double m = fabs(p) > floor_ ? fabs(p) : floor_;
-  return p >= 0.0 ? m : -m;
-}
-
-// gas polygon of a rectangle [0,h1]x[0,h2] with corner values q (corners in
-// the order (0,0), (h1,0), (h1,h2), (0,h2)): area, number of crossed edges
-__host__ __device__ inline double face_area(const double q[4], double h1, double h2, int* ncross) {
-  const double cs[4] = {0.0, h1, h1, 0.0}, ct[4] = {0.0, 0.0, h2, h2};
-  double ps[8], pt[8];
-  int np = 0, nc = 0;
-  for (int e = 0; e < 4; ++e) {
-    const int e1 = (e + 1) & 3;
-    const bool ga = q[e] > 0.0, gb = q[e1] > 0.0;
-    if (ga) { ps[np] = cs[e]; pt[np] = ct[e]; ++np; }
-    if (ga != gb) {
-      const double t = q[e] / (q[e] - q[e1]);
-      ps[np] = cs[e] + t * (cs[e1] - cs[e]);
-      pt[np] = ct[e] + t * (ct[e1] - ct[e]);
-      ++np;
-      ++nc;
-    }
-  }
-  double A = 0.0;
-  for (int k = 0; k < np; ++k) {
-    const int k1 = k + 1 == np ? 0 : k + 1;
-    A += ps[k] * pt[k1] - ps[k1] * pt[k];
-  }
-  *ncross = nc;
-  return 0.5 * A;
+  const double m = fmax(fabs(p), 1e-10 * dx);
+  return p < 0.0 ? -m : m;
 }
 
 struct CellGeo3 {
@@ -90,75 +82,167 @@ struct CellGeo3 {
   double vbar;     // gas volume
 };
 
-// geometry of one cell of sizes h from its 8 vertex values
-// q8[a | b << 1 | c << 2] (a, b, c = 0/1 along x, y, z)
-__host__ __device__ inline void cell_geometry_3d(const double q8[8], const double h[3], double thr,
+namespace cg3 {
+
+// The six faces in the order x-, x+, y-, y+, z-, z+: axis, and the four
+// corners counter-clockwise about the outward normal.
+struct FaceDef { int axis; int hi; int c[4]; };
+__host__ __device__ inline FaceDef face_def(int f) {
+  switch (f) {
+    case 0: return {0, 0, {0, 1, 3, 2}};
+    case 1: return {0, 1, {4, 6, 7, 5}};
+    case 2: return {1, 0, {0, 4, 5, 1}};
+    case 3: return {1, 1, {2, 3, 7, 6}};
+    case 4: return {2, 0, {0, 2, 6, 4}};
+    default: return {2, 1, {1, 5, 7, 3}};
+  }
+}
+
+// axis along which corners a and b (neighbours) differ
+__host__ __device__ inline int edge_axis(int a, int b) {
+  const int x = a ^ b;
+  return x == 4 ? 0 : (x == 2 ? 1 : 2);
+}
+
+// edge slot of the edge between neighbouring corners a and b: its axis and
+// the lower corner's remaining two bits
+__host__ __device__ inline int edge_slot(int a, int b) {
+  const int ax = edge_axis(a, b);
+  const int lo = a < b ? a : b;
+  int rest;
+  if (ax == 0) rest = lo & 3;
+  else if (ax == 1) rest = ((lo >> 2) << 1) | (lo & 1);
+  else rest = lo >> 1;
+  return 4 * ax + rest;
+}
+
+// distance from corner a to the crossing on its edge towards b (signs of
+// qa and qb differ), for an edge of length L
+__host__ __device__ inline double to_cross(double qa, double qb, double L) {
+  return L * (qa / (qa - qb));
+}
+
+}  // namespace cg3
+
+// geometry of one cell of sizes h from its 8 vertex values q[k], corner k as
+// in the header comment
+__host__ __device__ inline void cell_geometry_3d(const double q[8], const double h[3], double thr,
                                                  CellGeo3& g) {
-  double mn = 1e300, mx = -1e300, sum = 0.0;
-  for (int b = 0; b < 8; ++b) {
-    mn = fmin(mn, q8[b]);
-    mx = fmax(mx, q8[b]);
-    sum += q8[b];
+  using namespace cg3;
+  bool any_gas = false, any_solid = false;
+  double qsum = 0.0;
+  for (int k = 0; k < 8; ++k) {
+    any_gas |= q[k] > 0.0;
+    any_solid |= !(q[k] > 0.0);
+    qsum += q[k];
   }
-  const int type = mn > 0.0 ? TYPE_GAS : (mx < 0.0 ? TYPE_SOLID : TYPE_CUT);
-  int flags = sum / 8.0 > thr ? 1 : 0;
-  double Aw[3] = {0.0, 0.0, 0.0}, V = 0.0;
-  for (int d = 0; d < 3; ++d) {
-    const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-    for (int sd = 0; sd < 2; ++sd) {
-      double q[4];
-      for (int u = 0; u < 4; ++u) {
-        int idx[3];
-        idx[d] = sd;
-        idx[d1] = (u == 1 || u == 2) ? 1 : 0;
-        idx[d2] = u >= 2 ? 1 : 0;
-        q[u] = q8[idx[0] | (idx[1] << 1) | (idx[2] << 2)];
-      }
-      int nc;
-      const double area = face_area(q, h[d1], h[d2], &nc);
-      if (nc == 4) flags |= 2;
-      g.S[2 * d + sd] = type == TYPE_SOLID ? 0.0 : area;
-      const double sgn = sd ? 1.0 : -1.0;
-      Aw[d] -= sgn * area;
-      V += area * (sd ? h[d] : 0.0) / 3.0;
-    }
-  }
-  // mean of the crossings on the 12 edges
-  double rs[3] = {0.0, 0.0, 0.0};
-  int ncx = 0;
-  for (int d = 0; d < 3; ++d) {
-    const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-    for (int u = 0; u < 4; ++u) {
-      int i0[3], i1[3];
-      i0[d] = 0; i1[d] = 1;
-      i0[d1] = i1[d1] = u & 1;
-      i0[d2] = i1[d2] = (u >> 1) & 1;
-      const double qa = q8[i0[0] | (i0[1] << 1) | (i0[2] << 2)];
-      const double qb = q8[i1[0] | (i1[1] << 1) | (i1[2] << 2)];
-      if ((qa > 0.0) != (qb > 0.0)) {
-        const double tt = qa / (qa - qb);
-        double p3[3];
-        p3[d] = tt * h[d];
-        p3[d1] = i0[d1] * h[d1];
-        p3[d2] = i0[d2] * h[d2];
-        rs[0] += p3[0]; rs[1] += p3[1]; rs[2] += p3[2];
-        ++ncx;
-      }
-    }
-  }
-  const double Sw = sqrt(Aw[0] * Aw[0] + Aw[1] * Aw[1] + Aw[2] * Aw[2]);
+  g.type = !any_solid ? TYPE_GAS : (!any_gas ? TYPE_SOLID : TYPE_CUT);
+  g.flags = qsum * 0.125 > thr ? 1 : 0;
   g.aw = 0.0;
   for (int d = 0; d < 3; ++d) { g.n[d] = 0.0; g.r[d] = 0.0; }
-  if (type == TYPE_CUT && ncx > 0 && Sw > 0.0) {
-    const double r[3] = {rs[0] / ncx, rs[1] / ncx, rs[2] / ncx};
-    g.aw = Sw;
-    g.n[0] = Aw[0] / Sw; g.n[1] = Aw[1] / Sw; g.n[2] = Aw[2] / Sw;
-    V += (r[0] * Aw[0] + r[1] * Aw[1] + r[2] * Aw[2]) / 3.0;
-    g.r[0] = r[0]; g.r[1] = r[1]; g.r[2] = r[2];
+  if (g.type == TYPE_SOLID) {
+    for (int f = 0; f < 6; ++f) g.S[f] = 0.0;
+    g.vbar = 0.0;
+    return;
   }
-  g.type = type;
-  g.flags = flags;
-  g.vbar = type == TYPE_SOLID ? 0.0 : (type == TYPE_GAS ? h[0] * h[1] * h[2] : V);
+  if (g.type == TYPE_GAS) {
+    g.S[0] = g.S[1] = h[1] * h[2];
+    g.S[2] = g.S[3] = h[0] * h[2];
+    g.S[4] = g.S[5] = h[0] * h[1];
+    g.vbar = h[0] * h[1] * h[2];
+    return;
+  }
+
+  // crossing point of every mixed edge, from the edge's lower corner
+  double X[12][3];
+  double m[3] = {0.0, 0.0, 0.0};
+  int ncross = 0;
+  for (int a = 0; a < 8; ++a)
+    for (int ax = 0; ax < 3; ++ax) {
+      const int bit = 4 >> ax;
+      if (a & bit) continue;
+      const int b = a | bit;
+      if ((q[a] > 0.0) == (q[b] > 0.0)) continue;
+      const int s = edge_slot(a, b);
+      const double p0[3] = {(a & 4) ? h[0] : 0.0, (a & 2) ? h[1] : 0.0, (a & 1) ? h[2] : 0.0};
+      for (int d = 0; d < 3; ++d) X[s][d] = p0[d];
+      X[s][ax] = to_cross(q[a], q[b], h[ax]);
+      for (int d = 0; d < 3; ++d) m[d] += X[s][d];
+      ++ncross;
+    }
+  for (int d = 0; d < 3; ++d) m[d] /= (double)ncross;
+
+  double W[3] = {0.0, 0.0, 0.0};   // wall vector area
+  double vol3 = 0.0;               // three times the volume
+  for (int f = 0; f < 6; ++f) {
+    const FaceDef F = face_def(f);
+    const int u1 = F.axis == 0 ? 1 : 0, u2 = F.axis == 2 ? 1 : 2;
+    const double L1 = h[u1], L2 = h[u2];
+    bool gas[4];
+    int ngas = 0;
+    for (int k = 0; k < 4; ++k) { gas[k] = q[F.c[k]] > 0.0; ngas += gas[k]; }
+    // length of the edge from corner slot k to k + 1
+    auto elen = [&](int k) { return h[edge_axis(F.c[k], F.c[(k + 1) & 3])]; };
+    // distance from corner slot k to the crossing towards slot k + dk
+    auto dist = [&](int k, int dk) {
+      const int k2 = (k + dk) & 3;
+      const int e = dk == 1 ? k : k2;
+      return to_cross(q[F.c[k]], q[F.c[k2]], elen(e));
+    };
+    double A;
+    if (ngas == 4) {
+      A = L1 * L2;
+    } else if (ngas == 0) {
+      A = 0.0;
+    } else if (ngas == 1 || ngas == 3) {
+      int k = 0;
+      while (gas[k] != (ngas == 1)) ++k;
+      const double tri = 0.5 * dist(k, 1) * dist(k, 3);
+      A = ngas == 1 ? tri : L1 * L2 - tri;
+    } else {
+      int k = 0;
+      while (k < 4 && !(gas[k] && gas[(k + 1) & 3])) ++k;
+      if (k < 4) {                       // gas edge from slot k to k + 1: trapezoid
+        A = elen(k) * 0.5 * (dist(k, 3) + dist((k + 1) & 3, 1));
+      } else {                           // opposite gas corners: both edges crossed twice
+        g.flags |= 2;
+        const int s0 = gas[0] ? 1 : 0, s1 = s0 + 2;
+        A = L1 * L2 - 0.5 * dist(s0, 1) * dist(s0, 3) - 0.5 * dist(s1, 1) * dist(s1, 3);
+      }
+    }
+    g.S[f] = A;
+    // pyramid from the wall centre over this face: distance along the
+    // outward normal from the apex to the face plane
+    const double hgt = F.hi ? h[F.axis] - m[F.axis] : m[F.axis];
+    vol3 += A * hgt;
+
+    // chords of the wall loop on this face: walking the corners in order
+    // from a gas corner, the gas part leaves at X_out and comes back at X_in;
+    // the wall runs the chord the other way, adding 1/2 X_in x X_out
+    if (ngas == 0 || ngas == 4) continue;
+    int k0 = 0;
+    while (!gas[k0]) ++k0;
+    double xo[3] = {0.0, 0.0, 0.0};
+    for (int t = 0; t < 4; ++t) {
+      const int ka = (k0 + t) & 3, kb = (ka + 1) & 3;
+      if (gas[ka] == gas[kb]) continue;
+      const double* P = X[edge_slot(F.c[ka], F.c[kb])];
+      const double p[3] = {P[0] - m[0], P[1] - m[1], P[2] - m[2]};
+      if (gas[ka]) {
+        xo[0] = p[0]; xo[1] = p[1]; xo[2] = p[2];
+      } else {
+        W[0] += 0.5 * (p[1] * xo[2] - p[2] * xo[1]);
+        W[1] += 0.5 * (p[2] * xo[0] - p[0] * xo[2]);
+        W[2] += 0.5 * (p[0] * xo[1] - p[1] * xo[0]);
+      }
+    }
+  }
+  g.vbar = vol3 / 3.0;
+  const double area = sqrt(W[0] * W[0] + W[1] * W[1] + W[2] * W[2]);
+  if (area > 0.0) {
+    g.aw = area;
+    for (int d = 0; d < 3; ++d) { g.n[d] = W[d] / area; g.r[d] = m[d]; }
+  }
 }
 
 }  // namespace ccdvm

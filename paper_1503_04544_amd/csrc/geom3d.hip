@@ -1,14 +1,9 @@
 // Device construction of the 3D cut-cell geometry (Section 5.1, fixed body).
 // The paper leaves the 3D geometry to the reader; the rules used here:
 //   * vertex level set with the 1e-10 dx clamp, sign(0) = +1;
-//   * a Cartesian face's gas area is the polygon of its gas corners and the
-//     linear crossings on its mixed edges (the 2D virtual-cell rule on the
-//     face's four vertices); a face crossed on all four edges rejects the
-//     geometry;
-//   * the wall face closes the cell, |S_w| n_w = -sum_faces |S_k| n_k, with
-//     n_w pointing into the solid; its centre is the mean of the edge
-//     crossings;
-//   * the volume follows from the divergence theorem, V = 1/3 sum |S| (m.n);
+//   * per-cell faces, wall and volume as in cellgeom3d.h (the 2D
+//     virtual-cell rule on each face's four vertices, a wall face that closes
+//     the cell, the divergence theorem for the volume);
 //   * master search: centre in gas when the mean of the 8 vertex values
 //     exceeds 1e-12 dx, otherwise hop across the largest face shared with a
 //     cell of the domain (ties within 1e-12 broken in the order x+, x-, y+,
@@ -50,11 +45,11 @@ __global__ void k_cell3d(Geo3D G) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= G.ncell) return;
   const int i = t % G.nx, j = (t / G.nx) % G.ny, k = t / (G.nx * G.ny);
-  double q8[8];
-  for (int b = 0; b < 8; ++b) q8[b] = vtx(G, i, j, k, b & 1, (b >> 1) & 1, (b >> 2) & 1);
+  double qv[8];   // corner b at ((b >> 2) & 1, (b >> 1) & 1, b & 1)
+  for (int b = 0; b < 8; ++b) qv[b] = vtx(G, i, j, k, (b >> 2) & 1, (b >> 1) & 1, b & 1);
   const double h[3] = {G.dx, G.dy, G.dz};
   CellGeo3 c;
-  cell_geometry_3d(q8, h, 1e-12 * G.dx, c);
+  cell_geometry_3d(qv, h, 1e-12 * G.dx, c);
   G.type[t] = c.type;
   G.flags[t] = c.flags;
   G.sxm[t] = c.S[0]; G.sxp[t] = c.S[1]; G.sym[t] = c.S[2];
@@ -70,26 +65,25 @@ __global__ void k_cell3d(Geo3D G) {
   G.vbar[t] = c.vbar;
 }
 
-// one hop across the largest face shared with a cell of the domain
+// One hop across the largest face shared with a cell of the domain.  Faces
+// are ranked x+, x-, y+, y-, z+, z- (direction u: axis u / 2, upward for
+// even u); the first one within a relative 1e-12 of the largest wins.
 __device__ inline bool hop3d(const Geo3D& G, int& i, int& j, int& k) {
   const int c = (k * G.ny + j) * G.nx + i;
-  const double L[6] = {i + 1 < G.nx ? G.sxp[c] : 0.0, i > 0 ? G.sxm[c] : 0.0,
-                       j + 1 < G.ny ? G.syp[c] : 0.0, j > 0 ? G.sym[c] : 0.0,
-                       k + 1 < G.nz ? G.szp[c] : 0.0, k > 0 ? G.szm[c] : 0.0};
-  double M = 0.0;
-  for (int u = 0; u < 6; ++u) M = L[u] > M ? L[u] : M;
-  if (!(M > 0.0)) return false;
-  const double tie = M * (1.0 - 1e-12);
-  int u = 0;
-  while (L[u] < tie) ++u;
-  switch (u) {
-    case 0: i += 1; break;
-    case 1: i -= 1; break;
-    case 2: j += 1; break;
-    case 3: j -= 1; break;
-    case 4: k += 1; break;
-    default: k -= 1; break;
+  int pos[3] = {i, j, k};
+  const int ext[3] = {G.nx, G.ny, G.nz};
+  const double* area[6] = {G.sxp, G.sxm, G.syp, G.sym, G.szp, G.szm};
+  double len[6], best = 0.0;
+  for (int u = 0; u < 6; ++u) {
+    const int nb = pos[u >> 1] + ((u & 1) ? -1 : 1);
+    len[u] = (nb >= 0 && nb < ext[u >> 1]) ? area[u][c] : 0.0;
+    best = fmax(best, len[u]);
   }
+  if (!(best > 0.0)) return false;
+  int u = 0;
+  while (len[u] < best * (1.0 - 1e-12)) ++u;
+  pos[u >> 1] += (u & 1) ? -1 : 1;
+  i = pos[0]; j = pos[1]; k = pos[2];
   return true;
 }
 

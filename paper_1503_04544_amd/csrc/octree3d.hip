@@ -97,10 +97,10 @@ struct FarCells {
   FarCells(const AmrHost& H, int D) {
     for (int l = 0; l <= D; ++l)
       for (int gas = 0; gas < 2; ++gas) {
-        double h[3], q8[8];
+        double h[3], qv[8];
         for (int d = 0; d < 3; ++d) h[d] = H.hf[d] * (double)(1 << (D - l));
-        for (int t = 0; t < 8; ++t) q8[t] = gas ? 1.0 : -1.0;
-        cell_geometry_3d(q8, h, 1e-12 * H.hf[0], g[l][gas]);
+        for (int t = 0; t < 8; ++t) qv[t] = gas ? 1.0 : -1.0;
+        cell_geometry_3d(qv, h, 1e-12 * H.hf[0], g[l][gas]);
       }
   }
   const CellGeo3& get(int l, bool gas) const { return g[l][gas]; }
@@ -116,7 +116,7 @@ void leaf_geometry(const cc_config& cfg, const AmrHost& H, const BodyDev& B, int
                    const FarCells& far) {
   const int sh = cfg.amr_depth - H.lvl[q];
   for (int d = 0; d < 3; ++d) A0[d] = H.ijk[3 * (size_t)q + d] << sh;
-  double q8[8], h[3];
+  double qv[8], h[3];
   for (int d = 0; d < 3; ++d) h[d] = H.hf[d] * (double)(1 << sh);
   const double pc = level_set_3d(B, cfg.lo[0] + (A0[0] + 0.5 * (1 << sh)) * H.hf[0],
                                  cfg.lo[1] + (A0[1] + 0.5 * (1 << sh)) * H.hf[1],
@@ -127,11 +127,12 @@ void leaf_geometry(const cc_config& cfg, const AmrHost& H, const BodyDev& B, int
     return;
   }
   for (int t = 0; t < 8; ++t) {
-    const int a = A0[0] + ((t & 1) << sh), b = A0[1] + (((t >> 1) & 1) << sh), c = A0[2] + (((t >> 2) & 1) << sh);
-    q8[t] = clamp_vertex(level_set_3d(B, cfg.lo[0] + a * H.hf[0], cfg.lo[1] + b * H.hf[1], cfg.lo[2] + c * H.hf[2]),
+    // corner t at ((t >> 2) & 1, (t >> 1) & 1, t & 1) in units of the leaf size
+    const int a = A0[0] + (((t >> 2) & 1) << sh), b = A0[1] + (((t >> 1) & 1) << sh), c = A0[2] + ((t & 1) << sh);
+    qv[t] = clamp_vertex(level_set_3d(B, cfg.lo[0] + a * H.hf[0], cfg.lo[1] + b * H.hf[1], cfg.lo[2] + c * H.hf[2]),
                          H.hf[0]);
   }
-  cell_geometry_3d(q8, h, 1e-12 * H.hf[0], g);
+  cell_geometry_3d(qv, h, 1e-12 * H.hf[0], g);
 }
 
 // Control volumes in kernel order: first the regular ones (one member, no

@@ -131,3 +131,112 @@ def test_turning_configurations():
                 cfg().with_(model="shakhov"), cfg().with_(scheme="imex")):
         st, h = create(bad)
         assert st != 0 and not h.value
+
+
+def _leaf_boxes(cfg, L):
+    hc = np.array([(cfg.hi[d] - cfg.lo[d]) / cfg.n[d] for d in range(3)])
+    h = hc[None, :] / (2.0 ** L["lvl"][:, None])
+    return np.array(cfg.lo)[None, :] + L["ijk"] * h, h
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_builder_planar_cut_cells_exact(seed):
+    """The library's own cut cells (host construction of the octree builder)
+    against exact clipping: a sphere of radius 1e7 is planar over every
+    leaf, so each face's gas area is the face polygon clipped by the plane
+    and the gas volume the convex hull of the gas corners and the edge
+    crossings; the wall area is the clipped plane polygon's area.  The level
+    set of so large a sphere carries rounding of about 1e-9 (1e7 x 1e-16),
+    which moves the crossings by ~1e-8 of a leaf: the tolerance is 2e-6 of
+    the leaf's area or volume, far below the effect of a wrong formula."""
+    from scipy.spatial import ConvexHull
+    rng = np.random.default_rng(100 + seed)
+    nrm = rng.normal(size=3)
+    nrm /= np.linalg.norm(nrm)
+    x0 = np.array([0.5, 0.25, 0.25]) + rng.uniform(-0.03, 0.03, 3)
+    R = 1.0e7
+    cfg = case(n=(8, 4, 4), depth=1, body=Body("sphere", tuple(x0 - R * nrm), (R, R, R)))
+    st, h = create(cfg)
+    assert st == 0
+    try:
+        L, _ = export(h)
+    finally:
+        from paper_1503_04544_amd._capi import lib
+        lib().cc_destroy(h)
+    lo, hh = _leaf_boxes(cfg, L)
+    ncut = 0
+    for q in np.nonzero(L["type"] == 1)[0]:
+        corners = [lo[q] + hh[q] * ((t & 1), (t >> 1) & 1, (t >> 2) & 1) for t in range(8)]
+        dist = [float(np.dot(c - x0, nrm)) for c in corners]   # > 0: gas
+        gas = [c for c, d in zip(corners, dist) if d > 0]
+        cross = []
+        for a in range(8):
+            for bit in (1, 2, 4):
+                b = a | bit
+                if b != a and (dist[a] > 0) != (dist[b] > 0):
+                    cross.append(corners[a] + dist[a] / (dist[a] - dist[b]) * (corners[b] - corners[a]))
+        pts = np.array(gas + cross)
+        vol = ConvexHull(pts).volume if len(gas) and np.linalg.matrix_rank(pts - pts[0]) == 3 else 0.0
+        vcell = np.prod(hh[q])
+        assert abs(L["vbar"][q] - vol) <= 2e-6 * vcell
+        # wall polygon: crossings on the plane, ordered by angle about their mean
+        P = np.array(cross)
+        m = P.mean(axis=0)
+        e1 = np.cross(nrm, [1.0, 0.0, 0.0] if abs(nrm[0]) < 0.9 else [0.0, 1.0, 0.0])
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(nrm, e1)
+        ang = np.arctan2((P - m) @ e2, (P - m) @ e1)
+        Q = P[np.argsort(ang)]
+        aw = 0.5 * abs(sum(np.dot(np.cross(Q[k], Q[(k + 1) % len(Q)]), nrm) for k in range(len(Q))))
+        assert abs(L["sw"][q] - aw) <= 2e-6 * np.max(hh[q]) ** 2
+        # faces x-, x+, y-, y+, z-, z+: gas area of the face rectangle
+        for f in range(6):
+            d, side = f // 2, f % 2
+            d1, d2 = [a for a in range(3) if a != d]
+            rect = []
+            for (u, v) in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                off = np.zeros(3)
+                off[d] = side
+                off[d1] = u
+                off[d2] = v
+                rect.append(lo[q] + hh[q] * off)
+            gpoly = []
+            for k in range(4):
+                a, b = rect[k], rect[(k + 1) % 4]
+                da, db = np.dot(a - x0, nrm), np.dot(b - x0, nrm)
+                if da > 0:
+                    gpoly.append(a)
+                if (da > 0) != (db > 0):
+                    gpoly.append(a + da / (da - db) * (b - a))
+            area = 0.0
+            if len(gpoly) >= 3:
+                s = np.zeros(3)
+                for k in range(len(gpoly)):
+                    s += np.cross(gpoly[k], gpoly[(k + 1) % len(gpoly)])
+                area = 0.5 * np.linalg.norm(s)
+            assert abs(L["S"][q, f] - area) <= 2e-6 * np.max(hh[q]) ** 2, (q, f)
+        ncut += 1
+    assert ncut > 20
+
+
+def test_builder_sphere_converges_at_second_order():
+    """Gas volume and wall area of the library's own cut cells on a sphere
+    against 4/3 pi r^3 and 4 pi r^2, coarse grids 8x4x4 .. 32x16x16 at depth
+    1: the errors fall by about four per halving of the spacing."""
+    r = 0.1
+    ev, ea = [], []
+    for n in ((8, 4, 4), (16, 8, 8), (32, 16, 16)):
+        cfg = case(n=n, depth=1, body=Body("sphere", (0.5, 0.25, 0.25), (r,) * 3))
+        st, h = create(cfg)
+        assert st == 0
+        try:
+            L, _ = export(h)
+        finally:
+            from paper_1503_04544_amd._capi import lib
+            lib().cc_destroy(h)
+        solid = 0.25 - L["vbar"].sum()
+        ev.append(abs(solid - 4.0 / 3.0 * np.pi * r ** 3) / (4.0 / 3.0 * np.pi * r ** 3))
+        ea.append(abs(L["sw"].sum() - 4.0 * np.pi * r ** 2) / (4.0 * np.pi * r ** 2))
+    assert ev[-1] < 0.02 and ea[-1] < 0.01, (ev, ea)
+    for e in (ev, ea):
+        assert e[1] / e[2] > 2.5 and e[0] / e[1] > 2.5, (ev, ea)
