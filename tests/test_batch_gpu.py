@@ -65,7 +65,7 @@ def test_batch_benchmark_velocity_grids():
     """The velocity grids of the benchmark recipe (N = 16, 24, 32: one, five
     and eight chunks per half-row, tiles of several columns with the lower
     halves exchanged in LDS) on ragged grids: batched = alone, bitwise, and
-    the N = 24 instance = the oracle."""
+    the N = 24 and N = 32 instances = the oracle."""
     from paper_1503_04544_amd.solver import Batch
     cfgs = [
         small_2d(30, 22, 24, kn=0.05, mach=0.7, body=Body("circle", (0.5, 0.45, 0), (0.2, 0.2, 0), t_wall=1.3)),
@@ -86,10 +86,12 @@ def test_batch_benchmark_velocity_grids():
     got = _states(bat)
     for (f0, g0), (f1, g1) in zip(ref, got):
         assert np.array_equal(f0, f1) and np.array_equal(g0, g1)
-    o = Oracle2D(cfgs[0])
-    fo, go, _ = o.run(*o.init(), 10)
-    assert np.max(np.abs(got[0][0] - fo)) / np.max(fo) < 1e-10
-    assert np.max(np.abs(got[0][1] - go)) / np.max(go) < 1e-10
+    # the N = 24 and both N = 32 instances against the oracle
+    for k in (0, 1, 3):
+        o = Oracle2D(cfgs[k])
+        fo, go, _ = o.run(*o.init(), 10)
+        assert np.max(np.abs(got[k][0] - fo)) / np.max(fo) < 1e-10, k
+        assert np.max(np.abs(got[k][1] - go)) / np.max(go) < 1e-10, k
 
 
 def test_batch_autotune_and_interleaving_keep_results():

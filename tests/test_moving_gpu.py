@@ -36,6 +36,9 @@ MOVING = {
         inertia=0.002)),
     "translating_circle": small_2d(48, 48, 8, kn=0.2, mach=0.3, body=Body(
         "circle", (0.45, 0.5, 0), (0.15, 0.15, 0), motion="imposed", vel=(1.0, 0.3, 0.0), t_wall=1.3)),
+    # the free-molecular torque pin's set-up: a circle spinning in a gas at rest
+    "spinning_circle": small_2d(48, 48, 16, kn=0.1, mach=0.0, body=Body(
+        "circle", (0.5, 0.5, 0), (0.25, 0.25, 0), motion="imposed", omega=3.0)),
 }
 
 

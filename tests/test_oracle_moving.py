@@ -75,3 +75,39 @@ def test_free_rotation_is_explicit_euler_on_the_torque():
         assert omegas[n + 1] - omegas[n] == pytest.approx(o.dt * torques[n] / 0.05, rel=1e-12)
         # the difference of two angles ~0.4 carries their rounding (~1e-16)
         assert thetas[n + 1] - thetas[n] == pytest.approx(o.dt * omegas[n], rel=1e-12, abs=2e-16)
+
+
+def test_spinning_circle_torque_is_the_free_molecular_torque():
+    """A circle of radius R spinning at imposed angular velocity omega in a
+    gas at rest (rho = 1, T = 1) with an isothermal diffuse wall
+    (eqs. uwDD, BoundaryDDv, StressTensorDD, eq-torque).  In the first step
+    the incident molecules carry no tangential momentum, and the re-emitted
+    ones leave at the incident mass flux m = int_{c_n > 0} c_n M dc_n with
+    the wall's tangential velocity omega R, so the gas pulls the wall back
+    with the shear m omega R per unit length: torque -2 pi R^2 m omega R per
+    unit length of cylinder (m is integrated numerically here).  The
+    oracle's first-step torque must have that sign and scale, converge to it
+    in the grid spacing, and be odd in omega with no net force.  A reversed
+    wall velocity (r - c)^perp or a wrong torque orientation flips the sign;
+    a wall velocity left out of the re-emitted Maxwellian gives zero."""
+    from scipy.integrate import quad
+    R = 0.25
+    m, _ = quad(lambda c: c * math.exp(-0.5 * c * c) / math.sqrt(2.0 * math.pi), 0.0, math.inf)
+    errs = []
+    for n in (32, 64, 128):
+        torques = []
+        for omega in (1.0, -1.0):
+            cfg = small_2d(n, n, 24, kn=0.1, mach=0.0,
+                           body=Body("circle", (0.5, 0.5, 0), (R, R, 0), motion="imposed", omega=omega))
+            o = Oracle2D(cfg)
+            f, g = o.init()
+            _, _, d = o.step(f, g)
+            exact = -2.0 * math.pi * R * R * m * omega * R
+            assert d[2] * exact > 0.0
+            assert abs(d[0]) < 1e-14 and abs(d[1]) < 1e-14
+            torques.append(d[2])
+            if omega > 0:
+                errs.append(abs(d[2] - exact) / abs(exact))
+        assert torques[0] == pytest.approx(-torques[1], rel=1e-13)
+    assert errs[0] < 7e-3 and errs[1] < 1.5e-3 and errs[2] < 6e-4, errs
+    assert errs[2] < errs[1] < errs[0]

@@ -190,3 +190,46 @@ def test_first_step_drag_tends_to_free_molecular():
         assert abs(d[1]) < 1e-12
     assert errs[0] < 5e-3 and errs[-1] < 3e-4
     assert errs[2] < errs[1] < errs[0]
+
+
+def test_relaxation_time_is_mean_free_path_over_mean_speed():
+    """tau(Kn) (Section 5.3): Kn = lambda / L_ref is the mean free path of the
+    reference state in units of L_ref, and the BGK collision time is the time
+    a molecule of mean speed cbar = int |c| M(c) d^3c (3D Maxwellian at T0,
+    integrated numerically here) takes to cross it, with lambda scaling as
+    rho0 / rho.  Measured from the oracle: interior cells of a uniform state
+    see no net transport, so f^{n+1} - f^n = (dt / tau)(E - f^n); the
+    least-squares ratio gives dt / tau, which must equal
+    dt cbar rho / (Kn L_ref rho0) for two densities and two Knudsen numbers."""
+    from scipy.integrate import quad
+    cbar, _ = quad(lambda c: 4.0 * math.pi * c ** 3 * math.exp(-0.5 * c * c) / (2.0 * math.pi) ** 1.5,
+                   0.0, math.inf)
+    nx = ny = 5
+    for kn, rho in ((0.05, 1.0), (0.05, 1.7), (0.3, 0.6)):
+        cfg = Config(dim=2, n=(nx, ny, 1), lo=(0, 0, 0), hi=(1, 1, 1), nv=24, kn=kn,
+                     body=Body("none"), inflow=(1.0, 0.3, -0.2, 0.0, 1.1))
+        o = Oracle2D(cfg)
+        v = o.velocity()
+        vx, vy = np.tile(v, 24), np.repeat(v, 24)
+        w = (12.0 / 24) ** 2
+
+        def gauss(ax, ay, T):
+            return np.exp(-((vx - ax) ** 2 + (vy - ay) ** 2) / (2 * T)) / (2 * np.pi * T)
+        f0 = rho * (0.6 * gauss(0.9, 0.2, 0.5) + 0.4 * gauss(-0.7, -0.4, 0.7))
+        g0 = 0.4 * f0 + 0.2 * rho * gauss(0.0, 0.3, 0.9)
+        f = np.repeat(f0[None], nx * ny, axis=0)
+        g = np.repeat(g0[None], nx * ny, axis=0)
+        f1, g1, _ = o.step(f, g)
+        c = 2 * nx + 2
+        # equilibrium of the cell's discrete moments (eqs. MacroscopicDDv, BGKDD)
+        r = f0.sum() * w
+        ux, uy = (vx * f0).sum() * w / r, (vy * f0).sum() * w / r
+        E = (0.5 * (vx ** 2 + vy ** 2) * f0 + g0).sum() * w
+        T = (2.0 * E / r - ux * ux - uy * uy) / 3.0
+        Ef = r * np.exp(-((vx - ux) ** 2 + (vy - uy) ** 2) / (2 * T)) / (2 * np.pi * T)
+        Eg = 0.5 * T * Ef
+        a = np.concatenate([Ef - f0, Eg - g0])
+        b = np.concatenate([f1[c] - f0, g1[c] - g0])
+        nu = float(a @ b / (a @ a))
+        assert np.max(np.abs(b - nu * a)) < 1e-12 * np.max(np.abs(b))
+        assert nu == pytest.approx(o.dt * cbar * r / (kn * 1.0 * 1.0), rel=1e-9)

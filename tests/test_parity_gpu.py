@@ -166,3 +166,38 @@ def test_deterministic_replay():
         out.append((f.cpu().numpy(), d.cpu().numpy()))
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_hundred_steps_at_32_squared_velocities():
+    """The instantiation the cyl512 benchmark times (32^2 velocities,
+    explicit BGK, direct equilibrium) over 100 steps from the inflow
+    Maxwellian on a 72 x 40 grid: several tiles and row segments, ragged
+    edges, cut and merged cells.  Every step after the first relaxes with the
+    moments the streaming kernel summed in its own epilogue, so those sums
+    are checked against the oracle here, as are the drag rows."""
+    cfg = small_2d(72, 40, 32, kn=0.1, mach=0.8, body=Body("circle", (0.45, 0.47, 0), (0.17, 0.17, 0)))
+    print("parity: 72x40, 32^2 velocities, 100 steps", flush=True)
+    s = solver(cfg)
+    s.init_maxwellian()
+    d = s.step(100, diag=True).cpu().numpy()
+    f1, g1 = (t.cpu().numpy() for t in s.store_state())
+    o = Oracle2D(cfg)
+    f, g = o.init()
+    fo, go, do = o.run(f, g, 100)
+    assert relerr(f1, fo) < 1e-9
+    assert relerr(g1, go) < 1e-9
+    fs = np.max(np.abs(do[:, :2]))
+    assert np.max(np.abs(d[:, :3] - do[:, :3])) < 1e-9 * fs
+    assert np.max(np.abs(d[:, 0] - do[:, 0]) / np.abs(do[:, 0])) < 1e-9
+    assert np.max(np.abs(d[:, 3] - do[:, 3]) / do[:, 3]) < 1e-12
+
+
+def test_saddle_geometry_rejected_by_bind():
+    """A thin ellipse along a diagonal puts two boundary pieces in a cell:
+    the device geometry build reports CC_EGEOM from cc_bind, as the oracle
+    rejects it."""
+    from paper_1503_04544_amd._capi import CCError
+    cfg = small_2d(32, 32, 2, body=Body("ellipse", (0.5, 0.5, 0.0), (0.1, 0.004, 0.0), theta=math.pi / 4))
+    with pytest.raises(CCError) as e:
+        solver(cfg)
+    assert e.value.status == -3
