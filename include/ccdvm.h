@@ -161,6 +161,25 @@ cc_status cc_workspace_bytes(const cc_ctx* ctx, size_t* state_bytes,
 cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom,
                   void* scratch, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cc_bind
+ * without the scratch buffer.  The context's per-step records (moments of
+ * the current state, force and mass partials, rigid-body state, moving-body
+ * lists) are kept in a static device array of the library, 32 MiB, one copy
+ * on each GPU, held until the process ends; state0, state1 and geom are the
+ * caller's buffers as for cc_bind, hip_stream must belong to the current
+ * device.  Allocates no device memory (the side stream and events of a
+ * context are created on its first bind, as with cc_bind).  Returns
+ * CC_EINVAL when the set-up needs more scratch than the array holds (the
+ * scratch size of cc_workspace_bytes; a 2D 512 x 256 grid with 32^2
+ * velocities needs 22 MiB).  The array serves one bound context per GPU:
+ * binding another context to it waits for the previous owner's stream, keeps
+ * its body state on the host and unbinds it (its calls then return
+ * CC_ESTATE until it is bound again); calls that overlap on one GPU race.
+ * cc_bind or cc_destroy releases the array. */
+cc_status cc_bind_noalloc(cc_ctx* ctx, void* state0, void* state1, void* geom,
+                          void* hip_stream);
+
 /* Fills the current state with the inflow Maxwellian in every non-solid
  * cell (g = T/2 f in 2D), zero in solid cells.  Asynchronous. */
 cc_status cc_init_maxwellian(cc_ctx* ctx);

@@ -43,6 +43,7 @@ SYMBOLS = {
     "cc_workspace_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
                                      C.POINTER(C.c_size_t)]),
     "cc_bind": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5),
+    "cc_bind_noalloc": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4),
     "cc_init_maxwellian": (C.c_int, [C.c_void_p]),
     "cc_load_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cc_store_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

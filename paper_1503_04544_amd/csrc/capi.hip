@@ -11,6 +11,7 @@
 #include <chrono>
 #include <future>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -174,6 +175,12 @@ void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
 cc_status fail(cc_ctx* ctx, cc_status st, const std::string& msg) {
   if (ctx) ctx->err = msg;
   return st;
+}
+
+cc_status not_bound(cc_ctx* ctx) {
+  return fail(ctx, CC_ESTATE, ctx->scratch_taken
+                                  ? "another context was bound to this GPU's static scratch array: bind again"
+                                  : "cc_bind first");
 }
 
 cc_status hip_fail(cc_ctx* ctx, hipError_t e, const char* where) {
@@ -520,6 +527,67 @@ cc_status bind_impl(cc_ctx* ctx, void* state0, void* state1, void* geom, void* s
   return CC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Binding without a caller scratch buffer.  The per-context records that
+// cc_bind carves out of the caller's scratch buffer (moments of the current
+// state, force and mass partials, rigid-body state, moving-body lists) live
+// instead in a file-scope device array of fixed size, one copy per GPU.  Its
+// device address is looked up once per device with hipGetSymbolAddress and
+// only that address is handed to kernels and copies (the array's name is a
+// host-side stand-in in host code).  The array holds the records of one
+// bound context per GPU: binding another context to it takes it over, and
+// the previous owner then reports CC_ESTATE until it is bound again.
+namespace noalloc {
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex mu;
+void* dev_ptr[kMaxDevices] = {};
+cc_ctx* owner[kMaxDevices] = {};
+}  // namespace noalloc
+
+static void release_static_scratch(cc_ctx* ctx) {
+  if (ctx->static_dev < 0) return;
+  std::lock_guard<std::mutex> lock(noalloc::mu);
+  if (noalloc::owner[ctx->static_dev] == ctx) noalloc::owner[ctx->static_dev] = nullptr;
+  ctx->static_dev = -1;
+}
+
+cc_status bind_noalloc_impl(cc_ctx* ctx, void* state0, void* state1, void* geom, void* hip_stream) {
+  if (!ctx) return CC_EINVAL;
+  if (ctx->scratch_bytes > noalloc::kScratchBytes)
+    return fail(ctx, CC_EINVAL, "this set-up needs " + std::to_string(ctx->scratch_bytes) +
+                                    " scratch bytes; the static array holds " +
+                                    std::to_string(noalloc::kScratchBytes));
+  int dev = -1;
+  HIPCHK(ctx, hipGetDevice(&dev), "current device");
+  if (dev < 0 || dev >= noalloc::kMaxDevices) return fail(ctx, CC_EINVAL, "device index out of range");
+  std::unique_lock<std::mutex> lock(noalloc::mu);
+  if (!noalloc::dev_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc::scratch)), "static scratch address");
+    if (!p) return fail(ctx, CC_EHIP, "static scratch address is null");
+    noalloc::dev_ptr[dev] = p;
+  }
+  cc_ctx* prev = noalloc::owner[dev];
+  if (prev && prev != ctx && prev->bound) {
+    // hand over: finish the previous owner's work and keep its body state
+    HIPCHK(ctx, hipStreamSynchronize(prev->stream), "previous owner's stream");
+    if (!prev->amr_turning)
+      HIPCHK(ctx, hipMemcpy(prev->body_state, prev->s.body, 6 * sizeof(double), hipMemcpyDeviceToHost),
+             "previous owner's body state");
+    prev->bound = false;
+    prev->scratch_taken = true;
+    prev->static_dev = -1;
+  }
+  noalloc::owner[dev] = ctx;
+  void* ptr = noalloc::dev_ptr[dev];
+  lock.unlock();
+  ctx->static_dev = dev;
+  ctx->scratch_taken = false;
+  return bind_impl(ctx, state0, state1, geom, ptr, hip_stream);
+}
+
 // make the current state ready for a step: moments valid, control volumes merged
 static cc_status prepare(cc_ctx* ctx) {
   if (ctx->amr) {
@@ -564,7 +632,7 @@ static cc_status prepare(cc_ctx* ctx) {
 
 cc_status init_maxwellian_impl(cc_ctx* ctx) {
   if (!ctx) return CC_EINVAL;
-  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (!ctx->bound) return not_bound(ctx);
   HIPCHK(ctx, ctx->amr ? launch_amr_init(ctx, nullptr)
                        : (ctx->dim == 2 ? launch_init_maxwellian_2d(ctx) : launch_init_maxwellian_3d(ctx)), "init");
   ctx->mom_valid = false;
@@ -575,7 +643,7 @@ cc_status init_maxwellian_impl(cc_ctx* ctx) {
 
 cc_status load_state_impl(cc_ctx* ctx, const double* f, const double* g) {
   if (!ctx || !f) return CC_EINVAL;
-  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (!ctx->bound) return not_bound(ctx);
   if (ctx->dim == 2 && !g) return fail(ctx, CC_EINVAL, "g is required in 2D");
   HIPCHK(ctx, ctx->amr ? launch_amr_init(ctx, f)
                        : (ctx->dim == 2 ? launch_load_state_2d(ctx, f, g) : launch_load_state_3d(ctx, f)), "load");
@@ -683,7 +751,7 @@ static cc_status amr_turning_step(cc_ctx* ctx, double* row) {
 
 cc_status step_impl(cc_ctx* ctx, int nsteps, double* diag) {
   if (!ctx || nsteps < 0) return CC_EINVAL;
-  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (!ctx->bound) return not_bound(ctx);
   cc_status st = prepare(ctx);
   if (st != CC_OK) return st;
   if (nsteps == 0) return CC_OK;
@@ -770,14 +838,14 @@ cc_status set_tile_rows_impl(cc_ctx* ctx, int rows) {
 
 cc_status moments_impl(cc_ctx* ctx, double* out) {
   if (!ctx || !out) return CC_EINVAL;
-  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (!ctx->bound) return not_bound(ctx);
   HIPCHK(ctx, ctx->dim == 2 ? launch_moments_out_2d(ctx, out) : launch_moments_out_3d(ctx, out), "moments");
   return CC_OK;
 }
 
 cc_status body_force_impl(cc_ctx* ctx, double out[4]) {
   if (!ctx || !out) return CC_EINVAL;
-  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (!ctx->bound) return not_bound(ctx);
   if (ctx->amr) return fail(ctx, CC_EINVAL, "on the octree mesh the force comes with the diag rows of cc_step");
   cc_status st = prepare(ctx);
   if (st != CC_OK) return st;
@@ -825,7 +893,7 @@ cc_status geometry_export_impl(cc_ctx* ctx, int* type, int* master, double* lxm,
                                double* lym, double* lyp, double* lw, double* nwx, double* nwy,
                                double* rwx, double* rwy, double* sbar, double* scv) {
   if (!ctx) return CC_EINVAL;
-  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (!ctx->bound) return not_bound(ctx);
   if (ctx->dim != 2) return fail(ctx, CC_EINVAL, "2D only");
   const Geo2D& G = ctx->g2;
   size_t n = ctx->ncell;
@@ -844,7 +912,7 @@ cc_status geometry_export3d_impl(cc_ctx* ctx, int* type, int* master, double* sx
                                  double* nwx, double* nwy, double* nwz, double* rwx, double* rwy,
                                  double* rwz, double* vbar, double* vcv) {
   if (!ctx) return CC_EINVAL;
-  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (!ctx->bound) return not_bound(ctx);
   if (ctx->dim != 3 || ctx->amr) return fail(ctx, CC_EINVAL, "uniform 3D grids only (octree: cc_amr_export)");
   const Geo3D& G = ctx->g3;
   size_t n = ctx->ncell;
@@ -897,7 +965,7 @@ cc_status amr_faces_impl(cc_ctx* ctx, int* fptr, int* fnb, int* fdir, double* fa
 
 cc_status geometry_counts_impl(cc_ctx* ctx, int* n_irregular, int* n_members, int* n_solid) {
   if (!ctx) return CC_EINVAL;
-  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (!ctx->bound) return not_bound(ctx);
   if (n_irregular) *n_irregular = ctx->n_irr;
   if (n_members) *n_members = ctx->n_members;
   if (n_solid) *n_solid = ctx->n_solid;
@@ -959,7 +1027,7 @@ cc_status adjoint_workspace_bytes_impl(const cc_ctx* ctx, int nsteps, int ckpt_e
 cc_status adjoint_impl(cc_ctx* ctx, int nsteps, int ckpt_every, int objective, void* pool, double out[4]) {
   if (!ctx || !out || !pool || nsteps < 1 || ckpt_every < 1 || (objective != 0 && objective != 1))
     return CC_EINVAL;
-  if (!ctx->bound) return fail(ctx, CC_ESTATE, "cc_bind first");
+  if (!ctx->bound) return not_bound(ctx);
   if (ctx->dim != 2 || is_moving(ctx)) return fail(ctx, CC_EINVAL, "the adjoint covers 2D fixed bodies");
   if (ctx->cfg.maxwellian != CC_MAXW_DIRECT || ctx->cfg.scheme != CC_SCHEME_EXPLICIT ||
       ctx->cfg.model != CC_MODEL_BGK)
@@ -1196,8 +1264,18 @@ cc_status cc_dt(const cc_ctx* ctx, double* dt) {
 }
 
 cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scratch, void* hip_stream) {
+  return no_throw(ctx ? &ctx->err : nullptr, [&] {
+    if (ctx) {
+      release_static_scratch(ctx);
+      ctx->scratch_taken = false;
+    }
+    return bind_impl(ctx, state0, state1, geom, scratch, hip_stream);
+  });
+}
+
+cc_status cc_bind_noalloc(cc_ctx* ctx, void* state0, void* state1, void* geom, void* hip_stream) {
   return no_throw(ctx ? &ctx->err : nullptr,
-                  [&] { return bind_impl(ctx, state0, state1, geom, scratch, hip_stream); });
+                  [&] { return bind_noalloc_impl(ctx, state0, state1, geom, hip_stream); });
 }
 
 cc_status cc_init_maxwellian(cc_ctx* ctx) {
@@ -1317,6 +1395,7 @@ cc_status cc_batch_step(cc_batch* b, int nsteps) {
 
 void cc_destroy(cc_ctx* ctx) {
   if (!ctx) return;
+  release_static_scratch(ctx);
   for (int k = 0; k < kProfKernels; ++k) {
     for (hipEvent_t e : ctx->prof.start[k]) hipEventDestroy(e);
     for (hipEvent_t e : ctx->prof.stop[k]) hipEventDestroy(e);

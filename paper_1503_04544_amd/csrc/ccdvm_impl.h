@@ -214,6 +214,8 @@ struct cc_ctx {
   int cur = 0;
   void* geom = nullptr;
   void* scratch = nullptr;
+  int static_dev = -1;     // device whose static scratch array this context is bound to (-1: none)
+  bool scratch_taken = false;  // another context was bound to that array since
   hipStream_t stream = nullptr;
   bool bound = false;
   bool merged = false;     // members hold their control-volume value

@@ -20,7 +20,10 @@ def _ptr(t: torch.Tensor | None):
 class Solver:
     """One flow problem bound to one stream of one GPU."""
 
-    def __init__(self, cfg, device: str | torch.device = "cuda", stream: torch.cuda.Stream | None = None):
+    def __init__(self, cfg, device: str | torch.device = "cuda", stream: torch.cuda.Stream | None = None,
+                 static_scratch: bool = False):
+        """static_scratch: bind with cc_bind_noalloc (the library's static
+        scratch array instead of a scratch tensor)."""
         self.cfg = cfg
         self.device = torch.device(device)
         self._cfg = make_config(cfg)
@@ -44,10 +47,15 @@ class Solver:
             # caller-owned device buffers (uint8 tensors; 256-byte aligned by the caching allocator)
             self.state = [torch.empty(sb.value, dtype=torch.uint8, device=self.device) for _ in range(2)]
             self.geom = torch.empty(gb.value, dtype=torch.uint8, device=self.device)
-            self.scratch = torch.empty(xb.value, dtype=torch.uint8, device=self.device)
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-            self._check(lib().cc_bind(h, _ptr(self.state[0]), _ptr(self.state[1]), _ptr(self.geom),
-                                      _ptr(self.scratch), C.c_void_p(self.stream.cuda_stream)))
+            if static_scratch:
+                self.scratch = None
+                self._check(lib().cc_bind_noalloc(h, _ptr(self.state[0]), _ptr(self.state[1]), _ptr(self.geom),
+                                                  C.c_void_p(self.stream.cuda_stream)))
+            else:
+                self.scratch = torch.empty(xb.value, dtype=torch.uint8, device=self.device)
+                self._check(lib().cc_bind(h, _ptr(self.state[0]), _ptr(self.state[1]), _ptr(self.geom),
+                                          _ptr(self.scratch), C.c_void_p(self.stream.cuda_stream)))
 
     def _refresh_counts(self):
         nl, nf = C.c_int(), C.c_int()

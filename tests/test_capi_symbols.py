@@ -111,3 +111,19 @@ def test_create_validates_model():
     st, h = _create(small_2d(8, 8, 8, model="shakhov"))
     assert st == 0
     lib().cc_destroy(h)
+
+
+def test_noalloc_bind_rejects_a_setup_larger_than_the_static_scratch():
+    """cc_bind_noalloc checks the scratch size of the set-up against its
+    static array before it touches a device: the 3D sphere workload needs
+    far more than 32 MiB and is refused with CC_EINVAL."""
+    from paper_1503_04544_amd._capi import lib
+    st, h = _create(workload("sphere128"))
+    assert st == 0
+    sb, gb, xb = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    assert lib().cc_workspace_bytes(h, C.byref(sb), C.byref(gb), C.byref(xb)) == 0
+    assert xb.value > 32 << 20
+    dummy = C.c_void_p(1 << 20)   # never dereferenced: the size check comes first
+    assert lib().cc_bind_noalloc(h, dummy, dummy, dummy, None) == -1
+    assert b"static array" in lib().cc_last_error(h)
+    lib().cc_destroy(h)
