@@ -72,31 +72,162 @@ def measured_traffic(workload):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, nsteps):
-    """The oracle as it stands, on the host cores: nsteps full steps of the
-    same workload from the inflow-Maxwellian state."""
+def cpu_baseline(cfg, nsteps, threads=None):
+    """The oracle as it stands, on the host cores (or `threads` of them):
+    nsteps full steps of the same workload from the inflow-Maxwellian state."""
     import oracle
-    o = oracle.Oracle2D(cfg)
-    f, g = o.init()
-    t0 = time.perf_counter()
-    for _ in range(nsteps):
-        f, g, _ = o.step(f, g)
-    dt = time.perf_counter() - t0
+    prev = oracle.threads()
+    if threads:
+        oracle.set_threads(threads)
+    try:
+        o = oracle.Oracle2D(cfg)
+        f, g = o.init()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            f, g, _ = o.step(f, g)
+        dt = time.perf_counter() - t0
+        used = oracle.threads()
+    finally:
+        if threads:
+            oracle.set_threads(prev)
     geo = o.geometry()
     nupd = int((geo["type"] != 2).sum()) * cfg.nv ** 2 * nsteps
     return {"value": nupd / dt / 1e9, "unit": "G cell-velocity updates/s",
-            "cores": oracle.threads(), "kind": "oracle",
+            "cores": used, "kind": "oracle",
             "sample": f"{nsteps} full steps of the 512x256x32^2 workload from the inflow "
                       f"Maxwellian ({dt:.1f} s)"}
 
 
-def bench_batch(args):
+def measure(cfg, name, steps, warmup, args):
+    """Time `steps` steps of one workload after `warmup` untimed ones, then
+    the same steps again with per-kernel HIP events on the solver's stream."""
+    import torch
+    from paper_1503_04544_amd.solver import Solver
+    dev = torch.device("cuda:0")
+    s = Solver(cfg, device=dev)
+    n_irr, n_mem, n_solid = s.counts()
+    active = s.ncell - n_solid   # cells, or the leaves of an octree
+    ncell0 = s.ncell
+    nvel = cfg.nv ** cfg.dim
+    s.init_maxwellian()
+    diag = torch.empty((max(steps, warmup, 1), 4), dtype=torch.float64, device=dev)
+    log(f"bench {name}: warmup {warmup} steps")
+    if warmup:
+        s.step(warmup, diag=diag[:warmup])
+    torch.cuda.synchronize()
+    log(f"bench {name}: timing {steps} steps")
+    t0 = time.perf_counter()
+    s.step(steps, diag=diag[:steps])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / steps * 1e3
+    value = active * nvel * steps / elapsed / 1e9
+    drag_last = float(diag[steps - 1, 0].item())
+
+    # live per-kernel durations (HIP events on the solver's stream), same steps
+    log(f"bench {name}: per-kernel event timing")
+    s.profile_enable(True)
+    s.step(steps, diag=diag[:steps])
+    reg_ms, reg_n = s.profile_read(0)
+    cut_ms, cut_n = s.profile_read(1)
+    red_ms, red_n = s.profile_read(2)
+    mrg_ms, mrg_n = s.profile_read(3)
+    mom_ms, mom_n = s.profile_read(4)
+    rlx_ms, rlx_n = s.profile_read(5)
+    plan_ms, plan_n = s.profile_read(6)
+    adapt_ms, adapt_n = s.profile_read(7)
+    build_ms, build_n = s.profile_read(8)
+    s.profile_enable(False)
+    amr = s.amr
+    # the uniform kernels stream the regular cells (cut control volumes have
+    # their own kernel); the octree kernel updates every control volume
+    n_regular = active - n_mem if amr else active - n_irr - n_mem
+    # read + write of the state, FP64: f,g in 2D (32 B), F in 3D (16 B)
+    bytes_per_launch = n_regular * nvel * (32 if cfg.dim == 2 else 16)
+    avg_s = reg_ms / max(reg_n, 1) / 1e3
+    achieved = bytes_per_launch / avg_s / 1e9
+    traffic = measured_traffic(name)
+
+    # 2D semi-implicit with the direct equilibrium: the relaxation runs inside
+    # the streaming kernel (its own instantiation) for up to 8 chunks per half
+    im_fused = (cfg.dim == 2 and cfg.scheme == "imex" and cfg.maxwellian == "direct"
+                and ((cfg.nv + 1) // 2 * cfg.nv + 63) // 64 <= 8)
+    kernel_name = ("k_step2d_im" if im_fused else "k_step2d") if cfg.dim == 2 else \
+        ("k_amr_step" if amr else "k_step3d")
+    out = {
+        "metric": "cell-velocity updates/s",
+        "value": round(value, 3),
+        "unit": "G cell-velocity updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[name].format(kn=cfg.kn),
+                   "cells": ncell0, "active_cells": active, "velocities": nvel,
+                   "cut_control_volumes": n_irr, "merged_cells": n_mem, "dt": s.dt,
+                   "maxwellian": cfg.maxwellian, "scheme": cfg.scheme, "model": cfg.model,
+                   "drag_last_step": drag_last, "positivity_number": s.cfl_number()},
+        "roofline": {"bound": "hbm", "kernel": kernel_name,
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "avg_launch_us": round(avg_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "cut_kernel_avg_us": round(cut_ms / max(cut_n, 1) * 1e3, 2),
+                     "reduce_kernel_avg_us": round(red_ms / max(red_n, 1) * 1e3, 2),
+                     "merge_kernel_avg_us": round(mrg_ms / max(mrg_n, 1) * 1e3, 2)},
+    }
+    if s.turning:
+        # turning body: the host plans each step and adapts the mesh; the
+        # remap kernel carries the state to the new mesh
+        out["roofline"]["remap_kernel_avg_us"] = round(mom_ms / max(mom_n, 1) * 1e3, 2)
+        out["host"] = {"plan_ms_per_step": round(plan_ms / max(plan_n, 1), 3),
+                       "adapt_ms_per_step": round(adapt_ms / max(adapt_n, 1), 3),
+                       "mesh_build_ms_per_step": round(build_ms / max(build_n, 1), 3),
+                       "note": "cells and active_cells are those of the initial mesh"}
+    elif cfg.dim == 2 and cfg.body.motion != "fixed":
+        # moving 2D body: the geometry of t^{n+1} is rebuilt every step
+        geo_ms = mom_ms / max(mom_n, 1)
+        out["roofline"]["geometry_rebuild_avg_us"] = round(geo_ms * 1e3, 2)
+        out["ms_per_step_without_geometry_rebuild"] = round(ms_per_step - geo_ms, 4)
+    elif cfg.dim == 3 or cfg.maxwellian == "conservative":
+        # 3D: moments from the chunk sums (and the Newton triplet);
+        # 2D conservative: the Newton pass between steps
+        out["roofline"]["between_steps_kernel_avg_us"] = round(mom_ms / max(mom_n, 1) * 1e3, 2)
+    if cfg.scheme == "imex":
+        out["roofline"]["relax_kernel_avg_us"] = round(rlx_ms / max(rlx_n, 1) * 1e3, 2)
+    return s, out
+
+
+def summary(line):
+    """The figures of another workload's line carried in the headline line."""
+    r = line["roofline"]
+    keep = {"ms_per_step": line["ms_per_step"], "value": line["value"], "unit": line["unit"],
+            "steps": line["steps"], "kernel": r["kernel"], "kernel_avg_us": r["avg_launch_us"],
+            "achieved_GBs": r["achieved"], "frac": r["frac"], "traffic": r["traffic"],
+            "workload": line["config"]["workload"]}
+    for k in ("ms_per_step_without_geometry_rebuild",):
+        if k in line:
+            keep[k] = line[k]
+    if "geometry_rebuild_avg_us" in r:
+        keep["geometry_rebuild_avg_us"] = r["geometry_rebuild_avg_us"]
+    return keep
+
+
+def bench_batch(args, steps=None, warmup=None, quiet=False):
     """64 heterogeneous 2D fixed-cylinder instances (seeded recipe): batched
     step (one graph launch per step) against the same instances stepped one
-    after the other with their own launches."""
+    after the other with their own launches.  quiet: return the figures
+    instead of printing a line."""
     import torch
     from ccdvm_inputs import batch_instances
     from paper_1503_04544_amd.solver import Batch, Solver
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(dev)
     cfgs = batch_instances()
@@ -106,10 +237,9 @@ def bench_batch(args):
         s.init_maxwellian()
         solvers.append(s)
     upd = sum((c.ncell - s.counts()[2]) * c.nv ** 2 for c, s in zip(cfgs, solvers))
-    steps = args.steps
     log(f"bench batch: {len(cfgs)} instances, {upd / 1e6:.1f} M cell-velocity updates per step")
     for s in solvers:
-        s.step(args.warmup)
+        s.step(warmup)
     stream.synchronize()
     t0 = time.perf_counter()
     for s in solvers:
@@ -118,23 +248,36 @@ def bench_batch(args):
     t_seq = time.perf_counter() - t0
     b = Batch(solvers)
     rows = b.autotune(5)
-    b.step(args.warmup)
+    b.step(warmup)
     stream.synchronize()
     t0 = time.perf_counter()
     b.step(steps)
     stream.synchronize()
     t_bat = time.perf_counter() - t0
+    fig = {"ms_per_step": round(t_bat / steps * 1e3, 4),
+           "value": round(upd * steps / t_bat / 1e9, 3), "unit": "G cell-velocity updates/s",
+           "steps": steps, "updates_per_step": upd,
+           "achieved_GBs": round(upd * 32 * steps / t_bat / 1e9, 1),
+           "frac": round(upd * 32 * steps / t_bat / 1e9 / HBM_PEAK_GBS, 4),
+           "sequential_ms_per_step": round(t_seq / steps * 1e3, 4),
+           "batched_over_sequential": round(t_seq / t_bat, 3),
+           "groups_chunks_rows": b.groups(), "autotuned_rows": rows,
+           "workload": "batch: 64 2D fixed-cylinder instances, n in {64,128,256}^2, N in {16,24,32}^2, "
+                       "Kn 10^U(-2,0), T_w U(0.5,2), Mach U(0.3,1), seed 20150316"}
+    b.close()
+    for s in solvers:
+        s.close()
+    if quiet:
+        return fig
     out = {
-        "metric": "cell-velocity updates/s", "value": round(upd * steps / t_bat / 1e9, 3),
-        "unit": "G cell-velocity updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
-        "ms_per_step": round(t_bat / steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "metric": "cell-velocity updates/s", "value": fig["value"],
+        "unit": "G cell-velocity updates/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": fig["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "batch: 64 2D fixed-cylinder instances, n in {64,128,256}^2, "
-                               "N in {16,24,32}^2, Kn 10^U(-2,0), T_w U(0.5,2), Mach U(0.3,1), seed 20150316",
-                   "updates_per_step": upd,
-                   "sequential_ms_per_step": round(t_seq / steps * 1e3, 4),
-                   "batched_over_sequential": round(t_seq / t_bat, 3),
-                   "groups_chunks_rows": b.groups(), "autotuned_rows": rows},
+        "config": {"workload": fig["workload"], "updates_per_step": upd,
+                   "sequential_ms_per_step": fig["sequential_ms_per_step"],
+                   "batched_over_sequential": fig["batched_over_sequential"],
+                   "groups_chunks_rows": fig["groups_chunks_rows"], "autotuned_rows": rows},
     }
     print(json.dumps(out), flush=True)
 
@@ -163,6 +306,10 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=40,
                     help="steps of the adjoint/forward time ratio measurement (0: skip)")
     ap.add_argument("--adjoint-ckpt", type=int, default=8)
+    ap.add_argument("--extra-steps", type=int, default=20,
+                    help="timed steps of each other workload carried in the cyl512 line")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="cyl512 line without the other workloads")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -191,97 +338,7 @@ def main():
                                                     prandtl=args.prandtl)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    s = Solver(cfg, device=dev)
-    n_irr, n_mem, n_solid = s.counts()
-    active = s.ncell - n_solid   # cells, or the leaves of an octree
-    ncell0 = s.ncell
-    nvel = cfg.nv ** cfg.dim
-    s.init_maxwellian()
-    diag = torch.empty((max(args.steps, args.warmup, 1), 4), dtype=torch.float64, device=dev)
-    log(f"bench: warmup {args.warmup} steps")
-    if args.warmup:
-        s.step(args.warmup, diag=diag[: args.warmup])
-    torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} steps")
-    t0 = time.perf_counter()
-    s.step(args.steps, diag=diag[: args.steps])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed / args.steps * 1e3
-    value = active * nvel * args.steps / elapsed / 1e9
-    drag_last = float(diag[args.steps - 1, 0].item())
-
-    # live per-kernel durations (HIP events on the solver's stream), same steps
-    log("bench: per-kernel event timing")
-    s.profile_enable(True)
-    s.step(args.steps, diag=diag[: args.steps])
-    reg_ms, reg_n = s.profile_read(0)
-    cut_ms, cut_n = s.profile_read(1)
-    red_ms, red_n = s.profile_read(2)
-    mrg_ms, mrg_n = s.profile_read(3)
-    mom_ms, mom_n = s.profile_read(4)
-    rlx_ms, rlx_n = s.profile_read(5)
-    plan_ms, plan_n = s.profile_read(6)
-    adapt_ms, adapt_n = s.profile_read(7)
-    build_ms, build_n = s.profile_read(8)
-    s.profile_enable(False)
-    amr = s.amr
-    # the uniform kernels stream the regular cells (cut control volumes have
-    # their own kernel); the octree kernel updates every control volume
-    n_regular = active - n_mem if amr else active - n_irr - n_mem
-    # read + write of the state, FP64: f,g in 2D (32 B), F in 3D (16 B)
-    bytes_per_launch = n_regular * nvel * (32 if cfg.dim == 2 else 16)
-    avg_s = reg_ms / max(reg_n, 1) / 1e3
-    achieved = bytes_per_launch / avg_s / 1e9
-    traffic = measured_traffic(args.workload)
-
-    # 2D semi-implicit with the direct equilibrium: the relaxation runs inside
-    # the streaming kernel (its own instantiation) for up to 8 chunks per half
-    im_fused = (cfg.dim == 2 and args.scheme == "imex" and args.maxwellian == "direct"
-                and ((cfg.nv + 1) // 2 * cfg.nv + 63) // 64 <= 8)
-    kernel_name = ("k_step2d_im" if im_fused else "k_step2d") if cfg.dim == 2 else \
-        ("k_amr_step" if amr else "k_step3d")
-    out = {
-        "metric": "cell-velocity updates/s",
-        "value": round(value, 3),
-        "unit": "G cell-velocity updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT[args.workload].format(kn=cfg.kn),
-                   "cells": ncell0, "active_cells": active, "velocities": nvel,
-                   "cut_control_volumes": n_irr, "merged_cells": n_mem, "dt": s.dt,
-                   "maxwellian": args.maxwellian, "scheme": args.scheme, "model": args.model,
-                   "drag_last_step": drag_last},
-        "roofline": {"bound": "hbm", "kernel": kernel_name,
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "avg_launch_us": round(avg_s * 1e6, 2),
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "cut_kernel_avg_us": round(cut_ms / max(cut_n, 1) * 1e3, 2),
-                     "reduce_kernel_avg_us": round(red_ms / max(red_n, 1) * 1e3, 2),
-                     "merge_kernel_avg_us": round(mrg_ms / max(mrg_n, 1) * 1e3, 2)},
-    }
-    if s.turning:
-        # turning body: the host plans each step and adapts the mesh; the
-        # remap kernel carries the state to the new mesh
-        out["roofline"]["remap_kernel_avg_us"] = round(mom_ms / max(mom_n, 1) * 1e3, 2)
-        out["host"] = {"plan_ms_per_step": round(plan_ms / max(plan_n, 1), 3),
-                       "adapt_ms_per_step": round(adapt_ms / max(adapt_n, 1), 3),
-                       "mesh_build_ms_per_step": round(build_ms / max(build_n, 1), 3),
-                       "note": "cells and active_cells are those of the initial mesh"}
-    elif cfg.dim == 3 or args.maxwellian == "conservative":
-        # 3D: moments from the chunk sums (and the Newton triplet);
-        # 2D conservative: the Newton pass between steps
-        out["roofline"]["between_steps_kernel_avg_us"] = round(mom_ms / max(mom_n, 1) * 1e3, 2)
-    if args.scheme == "imex":
-        out["roofline"]["relax_kernel_avg_us"] = round(rlx_ms / max(rlx_n, 1) * 1e3, 2)
+    s, out = measure(cfg, args.workload, args.steps, args.warmup, args)
     if (args.workload == "cyl512" and args.adjoint_steps > 0 and args.maxwellian == "direct"
             and args.scheme == "explicit" and args.model == "bgk"):
         # adjoint over the same workload: forward alone vs forward with
@@ -305,9 +362,30 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
+    if args.workload == "cyl512" and not args.no_extra:
+        # the other full-size workloads, timed in the same run: 3D sphere,
+        # moving ellipse (geometry rebuilt every step), and the batch
+        extra = {}
+        for name, steps, warmup in (("sphere128", args.extra_steps, 3),
+                                    ("ellipse256", 2 * args.extra_steps, 5)):
+            s2, line = measure(workload(name), name, steps, warmup, args)
+            s2.close()
+            del s2
+            torch.cuda.empty_cache()
+            extra[name] = summary(line)
+        extra["batch"] = bench_batch(args, steps=args.extra_steps, warmup=3, quiet=True)
+        torch.cuda.empty_cache()
+        out["other_workloads"] = extra
     if not args.no_cpu and args.workload == "cyl512":
         log(f"bench: oracle on the host, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+        log("bench: oracle on one host thread, 1 step")
+        out["cpu_baseline"]["one_thread"] = cpu_baseline(cfg, 1, threads=1)
+        out["paper_context"] = {
+            "note": "the paper reports no timing of this 2D step; its one figure is the 3D Crookes "
+                    "radiometer on an octree (240 000 cells) in under 12 h on 240 MPI processes "
+                    "(CPU model not stated), velocity grid and step count not stated",
+            "implied_G_updates_per_s": ">= ~1.5 only if 30^3 velocities and 1e4 steps (assumed)"}
     print(json.dumps(out), flush=True)
 
 

@@ -80,6 +80,7 @@ class Config:
     prandtl: float = 2.0 / 3.0  # Prandtl number of the Shakhov model
     amr_depth: int = 0          # 3D octree: finest depth below the coarse grid n (0: uniform)
     amr_band: float = 0.0       # octree refinement band in coarse spacings (<= 0: 2 sqrt 2)
+    cfl_strict: int = 0         # 1: binding fails when the positivity number exceeds 1
 
     @property
     def ncell(self) -> int:

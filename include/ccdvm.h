@@ -58,8 +58,7 @@ typedef enum {
                          a master search that cycles or needs more than 4 hops */
   CC_ECFL = -4,       /* positivity condition (eq-CFL) violated in strict mode */
   CC_EHIP = -5,       /* a HIP runtime call failed */
-  CC_ESTATE = -6,     /* call out of order (e.g. cc_step before cc_bind) */
-  CC_ENUMERIC = -7    /* non-finite or negative value detected by a check */
+  CC_ESTATE = -6      /* call out of order (e.g. cc_step before cc_bind) */
 } cc_status;
 
 enum { CC_BODY_NONE = 0, CC_BODY_CIRCLE = 1, CC_BODY_ELLIPSE = 2,
@@ -78,9 +77,10 @@ enum { CC_MAXW_DIRECT = 0, CC_MAXW_CONSERVATIVE = 1 };
  * scheme of eq. ImpSchemeDD: explicit transport, then the relaxation taken
  * implicitly toward the equilibrium of the transported value,
  * f^{n+1} = (f* + (dt/tau^n) E*)/(1 + dt/tau^n), tau^n from the density of
- * the state at t^n.  The semi-implicit step reads and writes the state
- * twice (about twice the time of an explicit step) and is stable for
- * dt >> tau. */
+ * the state at t^n.  Stable for dt >> tau.  In 2D with the direct
+ * equilibrium and up to 8 velocity chunks per half-row the relaxation runs
+ * inside the streaming kernel, which then reads and writes the state once,
+ * as the explicit step does; otherwise a second pass relaxes in place. */
 enum { CC_SCHEME_EXPLICIT = 0, CC_SCHEME_IMEX = 1 };
 /* Relaxation model: BGK (eq. BGKDD; 3D: the Maxwellian) or the Shakhov
  * model (eq. ShakhovDD; 3D: the Shakhov equilibrium of Section 2.1), whose
@@ -115,6 +115,8 @@ typedef struct {
   int amr_depth;          /* 3D octree mesh (Section 5): finest depth below the
                              coarse grid n; 0 = uniform grid; at most 8 */
   double amr_band;        /* refinement band in coarse spacings (<= 0: 2 sqrt 2) */
+  int cfl_strict;         /* 1: cc_bind returns CC_ECFL when the positivity number of
+                             eq. eq-CFL exceeds 1 (0: it only warns on stderr) */
 } cc_config;
 
 /* Obstacle given by an analytic signed distance, gas side positive
@@ -179,6 +181,20 @@ cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom,
  * cc_bind or cc_destroy releases the array. */
 cc_status cc_bind_noalloc(cc_ctx* ctx, void* state0, void* state1, void* geom,
                           void* hip_stream);
+
+/* Positivity condition of the explicit scheme (Section 3.4.1, eqs. eq-CFL
+ * and phiCFL), evaluated by cc_bind on the bound geometry:
+ *   out[0] = dt max_{CV, p} phi_{CV,p} / S_CV, phi the outflow rate of a
+ *            control volume at velocity p summed over its members' Cartesian
+ *            and wall edges (faces in 3D) as printed, with the wall velocity
+ *            of the initial body state;
+ *   out[1] = dt max 1/tau at the inflow density (the state is not known at
+ *            bind; 0 without collisions and for the semi-implicit scheme,
+ *            whose condition does not involve tau);
+ *   out[2] = out[0] + out[1], the number that must not exceed 1.
+ * phi is convex in v, so its largest value on the velocity grid is taken at
+ * one of the grid's corner nodes.  CC_ESTATE before cc_bind. */
+cc_status cc_cfl_number(const cc_ctx* ctx, double out[3]);
 
 /* Fills the current state with the inflow Maxwellian in every non-solid
  * cell (g = T/2 f in 2D), zero in solid cells.  Asynchronous. */
@@ -295,8 +311,10 @@ cc_status cc_set_tile_rows(cc_ctx* ctx, int rows);
  * cc_profile_enable(ctx, 1) starts recording (cleared); cc_profile_read
  * returns, for kernel id k (0 = regular-cell step kernel, 1 = cut-cell
  * kernel, 2 = force/mass reduction, 3 = merge, 4 = pass between steps:
- * 3D moments and the conservative Newton solve, or a turning body's remap
- * to the adapted mesh, 5 = implicit relaxation of the semi-implicit
+ * 3D moments and the conservative Newton solve, a turning body's remap
+ * to the adapted mesh, or a moving 2D body's geometry rebuild (pose, level
+ * set, cells, masters, control volumes and step lists of t^{n+1}),
+ * 5 = implicit relaxation of the semi-implicit
  * scheme), the summed milliseconds and the number of launches since
  * enabling (at most 4096 launches per kernel are recorded); ids 6, 7 and
  * 8 return the host time of a turning body's steps: the step planning

@@ -3,4 +3,4 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The solver library never does.
 """
-from .oracle import Oracle2D, OracleError, cfg_struct, threads  # noqa: F401
+from .oracle import Oracle2D, OracleError, cfg_struct, set_threads, threads  # noqa: F401

@@ -85,6 +85,7 @@ int  orc2d_equilibrium(const orc2d *o, const double *f, const double *g, double 
 void orc2d_equilibrium_values(const orc2d *o, const double *f, const double *g, double *fe,
                               double *ge);
 int  orc_threads(void);
+void orc_set_threads(int n);
 
 typedef struct orc3d orc3d;
 int  orc3d_create(const orc_cfg *cfg, orc3d **out);

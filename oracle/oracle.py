@@ -81,6 +81,8 @@ def lib():
         _lib.orc2d_force.argtypes = [P, P, P, P]
         _lib.orc2d_moments.argtypes = [P, P, P, P]
         _lib.orc_threads.restype = C.c_int
+        _lib.orc_set_threads.argtypes = [C.c_int]
+        _lib.orc_set_threads.restype = None
         _lib.orc2d_adjoint.argtypes = [P, C.c_int, C.c_int, P]
         _lib.orc2d_equilibrium.argtypes = [P, P, P, P]
         _lib.orc2d_equilibrium_values.argtypes = [P, P, P, P, P]
@@ -89,6 +91,10 @@ def lib():
 
 def threads() -> int:
     return lib().orc_threads()
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
 
 
 def _p(a):

@@ -922,6 +922,15 @@ int orc_threads(void) {
 #endif
 }
 
+/* threads for the parallel loops from now on (the single-thread baseline) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Adjoint of the fixed-geometry step (not in the paper: the transpose  */
 /* of the scheme above, written out term by term).                     */

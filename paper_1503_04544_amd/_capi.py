@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libccdvm.so")
 
 CC_STATUS = {0: "CC_OK", -1: "CC_EINVAL", -2: "CC_ENOMEM", -3: "CC_EGEOM", -4: "CC_ECFL",
-             -5: "CC_EHIP", -6: "CC_ESTATE", -7: "CC_ENUMERIC"}
+             -5: "CC_EHIP", -6: "CC_ESTATE"}
 BODY = {"none": 0, "circle": 1, "ellipse": 2, "cavity": 3, "halfplane": 4, "sphere": 5, "vane": 6}
 MOTION = {"fixed": 0, "free_rotation": 1, "imposed": 2}
 
@@ -25,7 +25,8 @@ class cc_config(C.Structure):
                 ("vmax", C.c_double), ("kn", C.c_double), ("lref", C.c_double),
                 ("cfl", C.c_double), ("dt", C.c_double), ("inflow", C.c_double * 5),
                 ("maxwellian", C.c_int), ("scheme", C.c_int), ("model", C.c_int),
-                ("prandtl", C.c_double), ("amr_depth", C.c_int), ("amr_band", C.c_double)]
+                ("prandtl", C.c_double), ("amr_depth", C.c_int), ("amr_band", C.c_double),
+                ("cfl_strict", C.c_int)]
 
 
 class cc_body(C.Structure):
@@ -44,6 +45,7 @@ SYMBOLS = {
                                      C.POINTER(C.c_size_t)]),
     "cc_bind": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5),
     "cc_bind_noalloc": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4),
+    "cc_cfl_number": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "cc_init_maxwellian": (C.c_int, [C.c_void_p]),
     "cc_load_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cc_store_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -109,6 +111,7 @@ def make_config(cfg) -> cc_config:
     c.prandtl = getattr(cfg, "prandtl", 2.0 / 3.0)
     c.amr_depth = getattr(cfg, "amr_depth", 0)
     c.amr_band = getattr(cfg, "amr_band", 0.0)
+    c.cfl_strict = int(getattr(cfg, "cfl_strict", 0))
     return c
 
 

@@ -262,6 +262,8 @@ cc_status build_first_mesh(const cc_config& c, const cc_body& body, bool turning
   return CC_OK;
 }
 
+static cc_status check_cfl(cc_ctx* ctx, bool report);
+
 cc_status create_impl(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
   if (!cfg || !body || !out) return CC_EINVAL;
   *out = nullptr;
@@ -380,6 +382,8 @@ cc_status create_impl(const cc_config* cfg, const cc_body* body, cc_ctx** out) {
     ctx->body_state[4] = body->vel[1];
     ctx->body_state[5] = body->omega;
   }
+  // the octree is built on the host: its positivity number is known now
+  if (ctx->amr) check_cfl(ctx, false);
   *out = ctx;
   return CC_OK;
 }
@@ -446,6 +450,89 @@ static hipError_t upload_amr_plan(cc_ctx* ctx) {
   return e;
 }
 
+// Outflow rate per unit volume of eq. (phiCFL) over the control volumes of
+// an octree mesh (members' face entries, the farfield included, and wall
+// faces), maximised over the eight corner nodes of the velocity grid (phi is
+// convex in v).  A turning body's walls move with omega e_z x (r - centre).
+static double cfl_rate_amr(const AmrHost& H, double vlo, double vhi, double omega, const double* centre) {
+  double best = 0.0;
+  const int ncv = (int)H.cv.size();
+  for (int q = 0; q < ncv; ++q) {
+    const int m = H.cv[q];
+    for (int corner = 0; corner < 8; ++corner) {
+      const double v[3] = {(corner & 1) ? vhi : vlo, (corner & 2) ? vhi : vlo, (corner & 4) ? vhi : vlo};
+      double phi = 0.0;
+      for (int e = H.cvptr[q]; e < H.cvptr[q + 1]; ++e) {
+        const int k = H.cvmem[e];
+        for (int f = H.fptr[k]; f < H.fptr[k + 1]; ++f) {
+          const int d = H.fdir[f];
+          const double vn = (d & 1) ? v[d >> 1] : -v[d >> 1];
+          phi += H.farea[f] * fmax(vn, 0.0);
+        }
+        if (H.aw[k] > 0.0) {
+          const double* n = &H.nw[3 * (size_t)k];
+          double uwx = 0.0, uwy = 0.0;
+          if (omega != 0.0) {
+            const double* r = &H.rw[3 * (size_t)k];
+            uwx = -omega * (r[1] - centre[1]);
+            uwy = omega * (r[0] - centre[0]);
+          }
+          phi += H.aw[k] * fmax((v[0] - uwx) * n[0] + (v[1] - uwy) * n[1] + v[2] * n[2], 0.0);
+        }
+      }
+      best = fmax(best, phi / H.vcv[m]);
+    }
+  }
+  return best;
+}
+
+// Positivity number of eq. (eq-CFL) on the bound geometry: dt times the
+// largest outflow rate per unit area (volume) of a control volume, and dt
+// times the largest collision frequency 1/tau at the inflow density
+// (explicit scheme only).  Regular cells: phi / S = sum_d |v_d| / dx_d,
+// largest at the grid's extreme nodes.  Warns above 1, or fails with
+// CC_ECFL when cfl_strict is set.
+static cc_status check_cfl(cc_ctx* ctx, bool report) {
+  const cc_config& c = ctx->cfg;
+  const double vlo = c.vmin + 0.5 * ctx->dv, vhi = c.vmin + (c.nv - 0.5) * ctx->dv;
+  const double vm = ctx->vmax_abs;
+  double rate = 0.0;
+  if (ctx->amr) {
+    rate = cfl_rate_amr(*ctx->amrh, vlo, vhi, ctx->amr_turning ? ctx->body_state[5] : 0.0, ctx->body.center);
+  } else if (!ctx->bound_geometry) {
+    return CC_OK;   // uniform grids: the geometry is built on the device by cc_bind
+  } else {
+    rate = vm / ctx->dx + vm / ctx->dy + (ctx->dim == 3 ? vm / ctx->dz : 0.0);
+    double irr = 0.0;
+    const hipError_t e = ctx->dim == 2 ? cfl_rate_2d(ctx, vlo, vhi, ctx->body_state, &irr)
+                                       : cfl_rate_3d(ctx, vlo, vhi, &irr);
+    if (e != hipSuccess) return hip_fail(ctx, e, "positivity check");
+    rate = fmax(rate, irr);
+  }
+  ctx->cfl[0] = ctx->dt * rate;
+  const double tau_coef = sqrt(M_PI) / 2.0 * c.kn * c.lref / sqrt(2.0);
+  ctx->cfl[1] = c.kn > 0.0 && c.scheme == CC_SCHEME_EXPLICIT ? ctx->dt * c.inflow[0] / tau_coef : 0.0;
+  const double num = ctx->cfl[0] + ctx->cfl[1];
+  if (report && num > 1.0) {
+    char msg[200];
+    snprintf(msg, sizeof(msg),
+             "positivity condition eq-CFL: dt (max 1/tau + max phi/S) = %.4g > 1 (transport %.4g, collisions %.4g)",
+             num, ctx->cfl[0], ctx->cfl[1]);
+    if (c.cfl_strict) return fail(ctx, CC_ECFL, msg);
+    fprintf(stderr, "ccdvm: warning: %s\n", msg);
+  }
+  return CC_OK;
+}
+
+cc_status cfl_number_impl(const cc_ctx* ctx, double* out) {
+  if (!ctx || !out) return CC_EINVAL;
+  if (!ctx->bound && !ctx->amr) return CC_ESTATE;
+  out[0] = ctx->cfl[0];
+  out[1] = ctx->cfl[1];
+  out[2] = ctx->cfl[0] + ctx->cfl[1];
+  return CC_OK;
+}
+
 static cc_status read_geometry_status(cc_ctx* ctx) {
   int counts[4] = {0, 0, 0, 0};
   int* dcounts = ctx->dim == 2 ? ctx->g2.counts : ctx->g3.counts;
@@ -504,6 +591,8 @@ cc_status bind_impl(cc_ctx* ctx, void* state0, void* state1, void* geom, void* s
     ctx->g3.ncell = H.nleaf; ctx->g3.N = ctx->N; ctx->g3.nvel = ctx->nvel;
     ctx->g3.type = G.type; ctx->g3.master = G.master; ctx->g3.vcv = G.vcv;
     ctx->n_irr = H.n_irr; ctx->n_members = H.n_members; ctx->n_solid = H.n_solid;
+    cc_status cst = check_cfl(ctx, true);
+    if (cst != CC_OK) return cst;
     ctx->nstep = 0;
     ctx->bound = true;
     ctx->merged = false;
@@ -519,6 +608,9 @@ cc_status bind_impl(cc_ctx* ctx, void* state0, void* state1, void* geom, void* s
     if (e != hipSuccess) return hip_fail(ctx, e, "moving init");
   }
   cc_status st = read_geometry_status(ctx);
+  if (st != CC_OK) return st;
+  ctx->bound_geometry = true;
+  st = check_cfl(ctx, true);
   if (st != CC_OK) return st;
   ctx->nstep = 0;
   ctx->bound = true;
@@ -1276,6 +1368,10 @@ cc_status cc_bind(cc_ctx* ctx, void* state0, void* state1, void* geom, void* scr
 cc_status cc_bind_noalloc(cc_ctx* ctx, void* state0, void* state1, void* geom, void* hip_stream) {
   return no_throw(ctx ? &ctx->err : nullptr,
                   [&] { return bind_noalloc_impl(ctx, state0, state1, geom, hip_stream); });
+}
+
+cc_status cc_cfl_number(const cc_ctx* ctx, double out[3]) {
+  return no_throw(nullptr, [&] { return cfl_number_impl(ctx, out); });
 }
 
 cc_status cc_init_maxwellian(cc_ctx* ctx) {

@@ -216,6 +216,8 @@ struct cc_ctx {
   void* scratch = nullptr;
   int static_dev = -1;     // device whose static scratch array this context is bound to (-1: none)
   bool scratch_taken = false;  // another context was bound to that array since
+  double cfl[2] = {0.0, 0.0};  // positivity number of eq. eq-CFL: transport, collisions
+  bool bound_geometry = false;  // a uniform grid's geometry has been built on the device
   hipStream_t stream = nullptr;
   bool bound = false;
   bool merged = false;     // members hold their control-volume value
@@ -273,6 +275,11 @@ size_t batch_desc_bytes();
 void batch_fill(cc_batch* B, std::vector<char>& desc0, std::vector<char>& desc1,
                 std::vector<int2>& tiles, std::vector<int2>& cuts);
 hipError_t batch_launch_step(cc_batch* B, int par, hipStream_t* side, int nside);
+hipError_t batch_launch_desc(cc_batch* B, const void* D, hipStream_t* side, int nside);
+void batch_desc_patch(void* desc, const double2* in, double2* out, double* mom);
+// batched adjoint (adjoint2d.hip)
+size_t batch_adjoint_workspace_bytes(const cc_batch* B, int nsteps, int K);
+hipError_t batch_adjoint_run_2d(cc_batch* B, int nsteps, int K, int objective, char* ws, double* out);
 hipError_t batch_launch_group(cc_batch* B, int g);
 int tile_rows(const cc_ctx* ctx);
 
@@ -280,6 +287,10 @@ int tile_rows(const cc_ctx* ctx);
 hipError_t build_geometry_2d(cc_ctx* ctx, Geo2D& G, const double* pose);
 hipError_t build_geometry_box_2d(cc_ctx* ctx, Geo2D& G, const double* pose, Box2D bx);
 hipError_t build_geometry_3d(cc_ctx* ctx);
+// largest outflow rate per unit area (volume) of the cut and merged control
+// volumes, eq. phiCFL (geom2d.hip / geom3d.hip); synchronise the stream
+hipError_t cfl_rate_2d(cc_ctx* ctx, double vlo, double vhi, const double* body_state, double* rate);
+hipError_t cfl_rate_3d(cc_ctx* ctx, double vlo, double vhi, double* rate);
 
 // step and helpers (step2d.hip / step3d.hip)
 hipError_t launch_init_maxwellian_2d(cc_ctx* ctx);

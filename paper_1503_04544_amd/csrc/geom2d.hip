@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <string.h>
 
 #include "ccdvm_impl.h"
 
@@ -307,7 +308,60 @@ __global__ void k_tables2d(Geo2D G, double vmin, double dv, double rho, double u
   G.ghost[p] = make_double2(f, 0.5 * T * f);
 }
 
+// Outflow rate phi of eq. (phiCFL) of each cut or merged control volume
+// divided by its area, maximised over the velocity grid.  phi is a sum of
+// terms of the form |L| max(a . v + b, 0), convex in v, so its largest value
+// on the grid is taken at one of the four corner nodes (vlo|vhi, vlo|vhi).
+// The wall velocity is the rigid motion u_w = (ux, uy) + om (r - c)^perp of
+// eq. (uwDD).  The maximum over the control volumes is folded into *out as
+// the bit pattern of a non-negative double (order-preserving).
+__global__ void k_cfl2d(Geo2D G, int nirr, double vlo, double vhi, double ux, double uy, double om,
+                        double cx, double cy, unsigned long long* out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nirr) return;
+  const int m = G.irr[q];
+  double best = 0.0;
+  for (int corner = 0; corner < 4; ++corner) {
+    const double v1 = (corner & 1) ? vhi : vlo, v2 = (corner & 2) ? vhi : vlo;
+    double phi = 0.0;
+    for (int e = G.mptr[q]; e < G.mptr[q + 1]; ++e) {
+      const int k = G.mem[e];
+      phi += G.lxp[k] * fmax(v1, 0.0) - G.lxm[k] * fmin(v1, 0.0) + G.lyp[k] * fmax(v2, 0.0) -
+             G.lym[k] * fmin(v2, 0.0);
+      if (G.lw[k] > 0.0) {
+        const double uwx = ux - om * (G.rwy[k] - cy), uwy = uy + om * (G.rwx[k] - cx);
+        phi += G.lw[k] * fmax((v1 - uwx) * G.nwx[k] + (v2 - uwy) * G.nwy[k], 0.0);
+      }
+    }
+    best = fmax(best, phi / G.scv[m]);
+  }
+  atomicMax(out, (unsigned long long)__double_as_longlong(best));
+}
+
 }  // namespace
+
+// Largest outflow rate per unit area of eq. (eq-CFL) over the cut and merged
+// control volumes of the current geometry (velocity extremes vlo, vhi; body
+// state s = cx, cy, theta, ux, uy, omega); synchronises the stream.  `word`
+// is a device word of scratch memory.
+hipError_t cfl_rate_2d(cc_ctx* ctx, double vlo, double vhi, const double* s, double* rate) {
+  const Geo2D& G = ctx->g2;
+  unsigned long long* word = reinterpret_cast<unsigned long long*>(ctx->s.red);
+  hipError_t e = hipMemsetAsync(word, 0, sizeof(unsigned long long), ctx->stream);
+  if (e != hipSuccess) return e;
+  if (ctx->n_irr > 0)
+    k_cfl2d<<<(ctx->n_irr + 127) / 128, 128, 0, ctx->stream>>>(G, ctx->n_irr, vlo, vhi, s[3], s[4], s[5], s[0],
+                                                               s[1], word);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  unsigned long long bits = 0;
+  e = hipMemcpyAsync(&bits, word, sizeof(bits), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  double r;
+  memcpy(&r, &bits, sizeof(r));
+  *rate = r;
+  return e;
+}
 
 BodyDev body_dev(const cc_ctx* ctx) {
   BodyDev B{};

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <string.h>
 
 #include "ccdvm_impl.h"
 
@@ -227,7 +228,47 @@ __global__ void k_tables3d(Geo3D G, double vmin, double dv, double rho, double u
   G.ghost[p] = rho / pow(2.0 * M_PI * T, 1.5) * exp(-(cx * cx + cy * cy + cz * cz) / (2.0 * T));
 }
 
+// Outflow rate of eq. (phiCFL), in its 3D form (six faces and the wall),
+// of each cut or merged control volume divided by its volume, maximised over
+// the velocity grid: convex in v, so the largest value is at one of the
+// eight corner nodes.  Fixed wall (u_w = 0).
+__global__ void k_cfl3d(Geo3D G, int nirr, double vlo, double vhi, unsigned long long* out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nirr) return;
+  const int m = G.irr[q];
+  double best = 0.0;
+  for (int corner = 0; corner < 8; ++corner) {
+    const double v1 = (corner & 1) ? vhi : vlo, v2 = (corner & 2) ? vhi : vlo, v3 = (corner & 4) ? vhi : vlo;
+    double phi = 0.0;
+    for (int e = G.mptr[q]; e < G.mptr[q + 1]; ++e) {
+      const int k = G.mem[e];
+      phi += G.sxp[k] * fmax(v1, 0.0) - G.sxm[k] * fmin(v1, 0.0) + G.syp[k] * fmax(v2, 0.0) -
+             G.sym[k] * fmin(v2, 0.0) + G.szp[k] * fmax(v3, 0.0) - G.szm[k] * fmin(v3, 0.0);
+      if (G.aw[k] > 0.0) phi += G.aw[k] * fmax(v1 * G.nwx[k] + v2 * G.nwy[k] + v3 * G.nwz[k], 0.0);
+    }
+    best = fmax(best, phi / G.vcv[m]);
+  }
+  atomicMax(out, (unsigned long long)__double_as_longlong(best));
+}
+
 }  // namespace
+
+hipError_t cfl_rate_3d(cc_ctx* ctx, double vlo, double vhi, double* rate) {
+  unsigned long long* word = reinterpret_cast<unsigned long long*>(ctx->s.red);
+  hipError_t e = hipMemsetAsync(word, 0, sizeof(unsigned long long), ctx->stream);
+  if (e != hipSuccess) return e;
+  if (ctx->n_irr > 0)
+    k_cfl3d<<<(ctx->n_irr + 127) / 128, 128, 0, ctx->stream>>>(ctx->g3, ctx->n_irr, vlo, vhi, word);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  unsigned long long bits = 0;
+  e = hipMemcpyAsync(&bits, word, sizeof(bits), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  double r;
+  memcpy(&r, &bits, sizeof(r));
+  *rate = r;
+  return e;
+}
 
 hipError_t build_geometry_3d(cc_ctx* ctx) {
   Geo3D& G = ctx->g3;

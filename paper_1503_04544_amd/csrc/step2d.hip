@@ -1792,22 +1792,26 @@ hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_ro
   if (!fn) return hipErrorInvalidValue;
   hipStream_t st = ctx->stream;
   const int par = ctx->step_parity;
-  // 1. pose at t^{n+1}; 3. geometry at t^{n+1} inside the box
+  // 1. pose at t^{n+1}; 3. geometry at t^{n+1} inside the box and the
+  // step lists (profiling slot 4: the geometry rebuild)
+  prof_begin(ctx, 4);
   k_pose_next2d<<<1, 64, 0, st>>>(ctx->s.body, ctx->s.pose, ctx->dt);
   Box2D bx = moving_box(ctx);
   hipError_t e = build_geometry_box_2d(ctx, ctx->g2n, ctx->s.pose, bx);
   if (e != hipSuccess) return e;
-  // 2. merge over the control volumes of t^n
-  prof_begin(ctx, 3);
-  k_merge2d<<<kListBlocks, 64, 0, st>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
-                                        ctx->s.heat, P);
-  prof_end(ctx, 3);
   MoveArgs M;
   M.G0 = ctx->g2; M.G1 = ctx->g2n;
   M.skind = ctx->s.skind; M.target = ctx->s.target; M.rcnt = ctx->s.rcnt; M.age = ctx->s.age;
   M.gl = ctx->s.gl; M.gptr = ctx->s.gptr; M.gmem = ctx->s.gmem; M.gcount = ctx->s.gcount;
   M.bx = bx;
   k_steplist2d<<<1, 1024, 0, st>>>(M);
+  prof_end(ctx, 4);
+  // 2. merge over the control volumes of t^n (independent of the new
+  // geometry and of the step lists)
+  prof_begin(ctx, 3);
+  k_merge2d<<<kListBlocks, 64, 0, st>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
+                                        ctx->s.heat, P);
+  prof_end(ctx, 3);
   FusedArgs A;
   A.kind = ctx->s.skind;
   A.in = (const double2*)ctx->state[ctx->cur];
@@ -1928,7 +1932,12 @@ void batch_fill(cc_batch* B, std::vector<char>& desc0, std::vector<char>& desc1,
 // streams (graph capture), the cut-cell kernel and each group's tile kernel
 // are recorded on their own branch so the graph may run them concurrently
 hipError_t batch_launch_step(cc_batch* B, int par, hipStream_t* side, int nside) {
-  const BatchInst* D = (const BatchInst*)(par ? B->d_desc1 : B->d_desc0);
+  return batch_launch_desc(B, par ? B->d_desc1 : B->d_desc0, side, nside);
+}
+
+// one batched step with the descriptor table D (device)
+hipError_t batch_launch_desc(cc_batch* B, const void* Dv, hipStream_t* side, int nside) {
+  const BatchInst* D = (const BatchInst*)Dv;
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> joins;
   if (nside > 0) {
@@ -1966,6 +1975,16 @@ hipError_t batch_launch_step(cc_batch* B, int par, hipStream_t* side, int nside)
   for (hipEvent_t j : joins) hipEventDestroy(j);
   if (fork) hipEventDestroy(fork);
   return e;
+}
+
+// Redirects a host image of an instance's descriptor to other state and
+// moment buffers (the steps of the batched adjoint).
+void batch_desc_patch(void* desc, const double2* in, double2* out, double* mom) {
+  BatchInst& d = *(BatchInst*)desc;
+  d.A.in = in;
+  d.A.out = out;
+  d.A.mom = mom;
+  d.T = tile_args(d.G, d.A);
 }
 
 // tile kernel of one group only (autotuning)

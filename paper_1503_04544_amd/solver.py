@@ -86,6 +86,12 @@ class Solver:
         self._check(lib().cc_dt(self._h, C.byref(d)))
         return d.value
 
+    def cfl_number(self) -> list:
+        """Positivity number of eq. eq-CFL: [transport part, collision part, sum]."""
+        out = (C.c_double * 3)()
+        self._check(lib().cc_cfl_number(self._h, out))
+        return [float(x) for x in out]
+
     def init_maxwellian(self):
         self._check(lib().cc_init_maxwellian(self._h))
 

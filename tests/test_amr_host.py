@@ -240,3 +240,32 @@ def test_builder_sphere_converges_at_second_order():
     assert ev[-1] < 0.02 and ea[-1] < 0.01, (ev, ea)
     for e in (ev, ea):
         assert e[1] / e[2] > 2.5 and e[0] / e[1] > 2.5, (ev, ea)
+
+
+def test_octree_positivity_number_on_the_host():
+    """eq. eq-CFL on an octree (built on the host by cc_create): the regular
+    leaves of the finest depth give phi / V = sum_d |v_d| / h_d at the
+    grid's extreme nodes, which is what sets dt, so the transport part is at
+    least the CFL number; cut control volumes may raise it but stay below
+    1 at CFL 0.5 here.  The collision part is dt / tau at the inflow density,
+    tau = mean free path Kn L_ref over the mean molecular speed (numerically
+    integrated here).  A uniform grid has no number before cc_bind."""
+    import math
+    from scipy.integrate import quad
+    from paper_1503_04544_amd._capi import lib
+    cbar, _ = quad(lambda c: 4.0 * math.pi * c ** 3 * math.exp(-0.5 * c * c) / (2.0 * math.pi) ** 1.5, 0, math.inf)
+    cfg = case(n=(16, 8, 8), depth=2, nv=4)
+    st, h = create(cfg)
+    assert st == 0
+    out = (C.c_double * 3)()
+    assert lib().cc_cfl_number(h, out) == 0
+    d = C.c_double()
+    assert lib().cc_dt(h, C.byref(d)) == 0
+    assert 0.5 * (1 - 1e-14) <= out[0] < 1.0
+    assert out[1] == pytest.approx(d.value * cbar * cfg.inflow[0] / cfg.kn, rel=1e-12)
+    assert out[2] == pytest.approx(out[0] + out[1], rel=1e-15)
+    lib().cc_destroy(h)
+    st, h = create(small_3d(8, 4, 4, nv=4))
+    assert st == 0
+    assert lib().cc_cfl_number(h, out) == -6
+    lib().cc_destroy(h)
