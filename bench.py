@@ -254,6 +254,37 @@ def bench_batch(args, steps=None, warmup=None, quiet=False):
     b.step(steps)
     stream.synchronize()
     t_bat = time.perf_counter() - t0
+    groups = b.groups()
+    b.close()
+    # forward + adjoint (drag of the final state, gradient w.r.t. T_w, Kn,
+    # Ma) of a subset of the instances: every cc_adjoint in turn, then one
+    # cc_batch_adjoint over the same instances
+    nadj = min(args.batch_adjoint_instances, len(solvers))
+    na, ka = args.batch_adjoint_steps, args.batch_adjoint_ckpt
+    adj = None
+    if nadj > 0 and na > 0:
+        sub = solvers[:nadj]
+        log(f"bench batch: adjoint of {nadj} instances, {na} steps, checkpoint every {ka}")
+        sub[0].adjoint(na, ka, "drag")        # warm-up (pool allocation)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        seq = [s.adjoint(na, ka, "drag") for s in sub]
+        stream.synchronize()
+        t_seq_adj = time.perf_counter() - t0
+        b2 = Batch(sub)
+        b2.adjoint(na, ka, "drag")            # warm-up
+        stream.synchronize()
+        t0 = time.perf_counter()
+        J, G = b2.adjoint(na, ka, "drag")
+        stream.synchronize()
+        t_bat_adj = time.perf_counter() - t0
+        b2.close()
+        same = all(J[i] == seq[i][0] and (G[i] == seq[i][1]).all() for i in range(nadj))
+        adj = {"instances": nadj, "steps": na, "ckpt_every": ka,
+               "sequential_s": round(t_seq_adj, 4), "batched_s": round(t_bat_adj, 4),
+               "batched_over_sequential": round(t_seq_adj / t_bat_adj, 3),
+               "bitwise_equal_to_sequential": bool(same)}
+        torch.cuda.empty_cache()
     fig = {"ms_per_step": round(t_bat / steps * 1e3, 4),
            "value": round(upd * steps / t_bat / 1e9, 3), "unit": "G cell-velocity updates/s",
            "steps": steps, "updates_per_step": upd,
@@ -261,10 +292,10 @@ def bench_batch(args, steps=None, warmup=None, quiet=False):
            "frac": round(upd * 32 * steps / t_bat / 1e9 / HBM_PEAK_GBS, 4),
            "sequential_ms_per_step": round(t_seq / steps * 1e3, 4),
            "batched_over_sequential": round(t_seq / t_bat, 3),
-           "groups_chunks_rows": b.groups(), "autotuned_rows": rows,
+           "groups_chunks_rows": groups, "autotuned_rows": rows,
+           "forward_adjoint": adj,
            "workload": "batch: 64 2D fixed-cylinder instances, n in {64,128,256}^2, N in {16,24,32}^2, "
                        "Kn 10^U(-2,0), T_w U(0.5,2), Mach U(0.3,1), seed 20150316"}
-    b.close()
     for s in solvers:
         s.close()
     if quiet:
@@ -277,7 +308,8 @@ def bench_batch(args, steps=None, warmup=None, quiet=False):
         "config": {"workload": fig["workload"], "updates_per_step": upd,
                    "sequential_ms_per_step": fig["sequential_ms_per_step"],
                    "batched_over_sequential": fig["batched_over_sequential"],
-                   "groups_chunks_rows": fig["groups_chunks_rows"], "autotuned_rows": rows},
+                   "groups_chunks_rows": fig["groups_chunks_rows"], "autotuned_rows": rows,
+                   "forward_adjoint": adj},
     }
     print(json.dumps(out), flush=True)
 
@@ -306,6 +338,10 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=40,
                     help="steps of the adjoint/forward time ratio measurement (0: skip)")
     ap.add_argument("--adjoint-ckpt", type=int, default=8)
+    ap.add_argument("--batch-adjoint-instances", type=int, default=32,
+                    help="instances of the batch recipe whose forward + adjoint is timed (0: skip)")
+    ap.add_argument("--batch-adjoint-steps", type=int, default=20)
+    ap.add_argument("--batch-adjoint-ckpt", type=int, default=5)
     ap.add_argument("--extra-steps", type=int, default=20,
                     help="timed steps of each other workload carried in the cyl512 line")
     ap.add_argument("--no-extra", action="store_true",

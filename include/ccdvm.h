@@ -12,7 +12,7 @@
  * redistribution to the virtual cells (eq. UpdateDD); the force and torque
  * on the body from the wall stress (eqs. eq-force, eq-torque,
  * StressTensorDD); the rigid-body update (eqs. motionDD_posit, motionDD_vit,
- * uwDD).  The 3D variant follows Section 5.1 (eq. eq-schema3D).
+ * uwDD).  The 3D variant follows Section 5 (eq. eq-schema3D).
  *
  * Units: nondimensional, R = T0 = rho0 = 1.  All floating point is FP64.
  *
@@ -112,7 +112,7 @@ typedef struct {
                              no adjoint or batch) */
   int model;              /* CC_MODEL_BGK or CC_MODEL_SHAKHOV (no adjoint or batch) */
   double prandtl;         /* Shakhov: Prandtl number, finite and > 0 */
-  int amr_depth;          /* 3D octree mesh (Section 5): finest depth below the
+  int amr_depth;          /* 3D octree mesh (Section 5.1): finest depth below the
                              coarse grid n; 0 = uniform grid; at most 8 */
   double amr_band;        /* refinement band in coarse spacings (<= 0: 2 sqrt 2) */
   int cfl_strict;         /* 1: cc_bind returns CC_ECFL when the positivity number of
@@ -257,7 +257,7 @@ cc_status cc_geometry_export(cc_ctx* ctx, int* type, int* master,
                              double* lw, double* nwx, double* nwy, double* rwx,
                              double* rwy, double* sbar, double* scv);
 
-/* 3D geometry tables (Section 5.1 with the face, wall and volume rules
+/* 3D geometry tables (Section 5 with the face, wall and volume rules
  * stated in the library's geometry source) to host arrays of ncell entries
  * each (any pointer may be NULL): type, master, gas areas of the faces x-,
  * x+, y-, y+, z-, z+, wall area, wall normal (into the solid), wall centre,
@@ -272,7 +272,7 @@ cc_status cc_geometry_export3d(cc_ctx* ctx, int* type, int* master, double* sxm,
 cc_status cc_geometry_counts(cc_ctx* ctx, int* n_irregular, int* n_members,
                              int* n_solid);
 
-/* Octree mesh (3D, amr_depth > 0 or a turning body; Section 5, octree
+/* Octree mesh (3D, amr_depth > 0 or a turning body; Section 5.1, octree
  * procedure).  The
  * coarse grid n is refined near the boundary: a cell of depth d is divided
  * in 8 while the distance from its centre to the boundary is below
@@ -370,6 +370,21 @@ cc_status cc_batch_groups(const cc_batch* b, int* ngroups, int* chunks, int* row
 /* Advances every instance by nsteps (asynchronous).  Stepping an instance
  * on its own in between is allowed; the tables are rebuilt when needed. */
 cc_status cc_batch_step(cc_batch* b, int nsteps);
+/* Adjoint of every instance at once: what cc_adjoint returns for each
+ * context (from the inflow Maxwellian, nsteps steps, J = drag or torque of
+ * the final state, checkpoint every ckpt_every steps), with each step of
+ * each phase one launch over all instances (forward steps and segment
+ * recomputations through the batched step kernels, adjoint steps through
+ * batched adjoint kernels, checkpoint copies through one copy kernel).
+ * Results are bitwise those of cc_adjoint on each context.  out: n x 4
+ * doubles {J, dJ/dT_w, dJ/dKn, dJ/dMa} per instance, in the batch order.
+ * workspace: caller-owned 256-byte aligned device buffer of
+ * cc_batch_adjoint_workspace_bytes bytes (every instance's adjoint pool and
+ * the step tables).  Leaves every context at its final state.
+ * Synchronous. */
+cc_status cc_batch_adjoint_workspace_bytes(const cc_batch* b, int nsteps, int ckpt_every, size_t* bytes);
+cc_status cc_batch_adjoint(cc_batch* b, int nsteps, int ckpt_every, int objective, void* workspace,
+                           double* out);
 const char* cc_batch_last_error(const cc_batch* b);
 void cc_batch_destroy(cc_batch* b);
 

@@ -113,7 +113,7 @@ int  orc3d_equilibrium(const orc3d *o, const double *F, double *out);
    2.1, or the Shakhov equilibrium given there */
 void orc3d_equilibrium_values(const orc3d *o, const double *F, double *Fe);
 
-/* 3D octree mesh (Section 5, octree procedure): leaves in Z-order; state
+/* 3D octree mesh (Section 5.1, octree procedure): leaves in Z-order; state
    F[leaf][p].  A body with motion != 0 turns about the z axis through its
    centre (pure rotation, Section 5 steps 1-7): orc3a_step then leaves the
    state at t^{n+1} on the mesh of t^n, orc3a_adapt rebuilds the mesh for the

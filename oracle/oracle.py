@@ -370,7 +370,7 @@ def _lib3a():
 
 
 class Oracle3A:
-    """3D octree mesh (Section 5): state F of shape (nleaf, N**3), leaves in
+    """3D octree mesh (Section 5.1): state F of shape (nleaf, N**3), leaves in
     Z-order.  With a turning body the mesh follows the body: every step
     returns the state on the mesh of the new angle (nleaf may change)."""
 

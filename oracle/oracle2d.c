@@ -15,7 +15,7 @@
  *                                                (eq-torque), (StressTensorDD), (uwDD)
  *   rigid-body update .......................... eqs. (motionDD_posit), (motionDD_vit)
  *   seven-step summary ......................... Section 3.3.4
- *   relaxation time from Kn .................... Section 5.4 (BGK, tau(Kn))
+ *   relaxation time from Kn .................... Section 5.3 (BGK, tau(Kn))
  *
  * Readings taken where the paper is silent or garbled are marked READING.
  * Nothing here is blocked, fused or reordered for speed: loops run over

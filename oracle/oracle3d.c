@@ -1,12 +1,12 @@
 /* Oracle, three-dimensional model (F) -- TEST INFRASTRUCTURE ONLY.
  *
  * Plain serial-order FP64 implementation of the 3D cut-cell method of
- * Dechriste & Mieussens (2015), Section 5.1 (fixed body):
+ * Dechriste & Mieussens (2015), Section 5 (fixed body):
  *   moments and Maxwellian ........................ Section 2.1, eqs. (MacroscopicTD), (MaxwellianTD)
  *   Shakhov equilibrium ........................... Section 2.1
- *   diffuse wall with zero net mass flux ........... Section 5.1 step 4
+ *   diffuse wall with zero net mass flux ........... Section 5 step 4
  *   explicit scheme with seven virtual faces ....... eq. (eq-schema3D)
- *   control volumes, merge, redistribution ......... Section 5.1 steps 2, 6, 7
+ *   control volumes, merge, redistribution ......... Section 5 steps 2, 6, 7
  * READING (the paper leaves the 3D geometry "to the reader"): the gas area
  * of a Cartesian face is the 2D virtual-cell polygon of that face's four
  * vertices (linear crossings on mixed edges); the wall face closes the cell,
@@ -543,7 +543,7 @@ static void relax_update3(const orc3d *o, const double *fc, const double *R, dou
   }
 }
 
-/* Diffuse wall of zero net mass flux (Section 5.1 step 4), fixed wall
+/* Diffuse wall of zero net mass flux (Section 5 step 4), fixed wall
    u_w = 0, normal nwk into the solid: fw = phi_w M[1, 0, T_w] at every
    velocity, phi_w from the outgoing flux of the control-volume value fc. */
 static void wall_values3(const orc3d *o, const double *fc, const double *nwk, double *fw) {
@@ -602,7 +602,7 @@ static void scheme3(const orc3d *o, const double *Fm, int m, double *out) {
 }
 
 /* wall stress of one wall face (normal nwk into the solid, area swk) from
-   the control-volume value fc, added to the force F (Section 5.1 step 5) */
+   the control-volume value fc, added to the force F (Section 5 step 5) */
 static void wall_force3(const orc3d *o, const double *fc, const double *nwk, double swk, double *F) {
   int nvel = o->nvel, N = o->N;
   double Tw = o->cfg.t_wall, zero[3] = {0, 0, 0};
@@ -703,7 +703,7 @@ void orc3d_moments(const orc3d *o, const double *F, double *out) {
 void orc3d_velocity(const orc3d *o, double *v) { memcpy(v, o->v, o->N * sizeof(double)); }
 
 /* ================================================================== */
-/* Octree mesh (Section 5, octree procedure) around a fixed body        */
+/* Octree mesh (Section 5.1, octree procedure) around a fixed body        */
 /* ================================================================== */
 /* The coarse n[0] x n[1] x n[2] grid is refined near the boundary: a cell
    of depth d is divided in 8 when its centre is closer to the boundary than
@@ -1362,7 +1362,7 @@ int orc3a_step(orc3a *o, const double *F, double *Fo, double *diag) {
   return 0;
 }
 
-/* Mesh adaptation (Section 5): the mesh is rebuilt for the body at its
+/* Mesh adaptation (Section 5.1): the mesh is rebuilt for the body at its
    current angle; the old leaves, with their gas volumes at that angle, are
    kept for orc3a_remap. */
 int orc3a_adapt(orc3a *o) {

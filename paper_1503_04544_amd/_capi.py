@@ -72,6 +72,8 @@ SYMBOLS = {
     "cc_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "cc_batch_groups": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "cc_batch_step": (C.c_int, [C.c_void_p, C.c_int]),
+    "cc_batch_adjoint_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
+    "cc_batch_adjoint": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
     "cc_batch_last_error": (C.c_char_p, [C.c_void_p]),
     "cc_batch_destroy": (None, [C.c_void_p]),
 }

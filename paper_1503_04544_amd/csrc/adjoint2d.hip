@@ -18,8 +18,17 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <string.h>
+
+#include <vector>
 
 #include "ccdvm_impl.h"
+
+// Contraction off: the adjoint kernel bodies are inlined into the
+// single-instance and the batched kernels, and each expression must round
+// the same way in both, so that a batched gradient equals the
+// single-instance one bit for bit.
+#pragma clang fp contract(off)
 
 namespace ccdvm {
 namespace {
@@ -97,10 +106,11 @@ __device__ inline BgkSums chain(double rho, double ux, double uy, double T, cons
 // ---------------------------------------------------------------------
 // regular gas cells: one wave per cell
 // ---------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_adj_regular2d(Geo2D G, AdjBufs B, AdjParams P) {
-  __shared__ double lds[4][4];
+// blk: the block's index among the instance's regular blocks (4 cells each)
+__device__ inline void adj_regular_body(const Geo2D& G, const AdjBufs& B, const AdjParams& P, int blk,
+                                        double (*lds)[4]) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = blockIdx.x * 4 + wave;
+  const int c = blk * 4 + wave;
   double pk = 0.0, pux = 0.0, puy = 0.0;
   if (c < G.ncell && G.kind[c] == KIND_REGULAR) {
     const int nx = G.nx, ny = G.ny, N = G.N, nvel = G.nvel;
@@ -164,19 +174,25 @@ __global__ void __launch_bounds__(256) k_adj_regular2d(Geo2D G, AdjBufs B, AdjPa
   if (lane == 0) { lds[wave][0] = pk; lds[wave][1] = pux; lds[wave][2] = puy; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double* pt = B.part + 4 * (size_t)blockIdx.x;
+    double* pt = B.part + 4 * (size_t)blk;
     pt[1] += ((lds[0][0] + lds[1][0]) + lds[2][0]) + lds[3][0];
     pt[2] += ((lds[0][1] + lds[1][1]) + lds[2][1]) + lds[3][1];
     pt[3] += ((lds[0][2] + lds[1][2]) + lds[2][2]) + lds[3][2];
   }
 }
 
+__global__ void __launch_bounds__(256) k_adj_regular2d(Geo2D G, AdjBufs B, AdjParams P) {
+  __shared__ double lds[4][4];
+  adj_regular_body(G, B, P, blockIdx.x, lds);
+}
+
 // ---------------------------------------------------------------------
 // cut / merged control volumes: one 256-thread block each
 // ---------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_adj_cut2d(Geo2D G, AdjBufs B, AdjParams P, int part_base) {
-  __shared__ double lds[8];
-  const int q = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
+// q: the control volume's slot in the instance's list of cut/merged volumes
+__device__ inline void adj_cut_body(const Geo2D& G, const AdjBufs& B, const AdjParams& P, int part_base, int q,
+                                    double* lds) {
+  const int tid = threadIdx.x, nth = blockDim.x;
   const int m = G.irr[q];
   const int b0 = G.mptr[q];
   const int nm = min(G.mptr[q + 1] - b0, kMaxMembers);
@@ -296,6 +312,11 @@ __global__ void __launch_bounds__(256) k_adj_cut2d(Geo2D G, AdjBufs B, AdjParams
     pt[2] += pux;
     pt[3] += puy;
   }
+}
+
+__global__ void __launch_bounds__(256) k_adj_cut2d(Geo2D G, AdjBufs B, AdjParams P, int part_base) {
+  __shared__ double lds[8];
+  adj_cut_body(G, B, P, part_base, blockIdx.x, lds);
 }
 
 // objective (drag or torque of the final state): mu^N at the members of every
@@ -595,6 +616,363 @@ hipError_t adjoint_run_2d(cc_ctx* ctx, int nsteps, int K, int objective, char* p
   host_j[2] = h[5];
   host_j[3] = h[6];
   host_j[4] = h[7];
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------
+// Batched adjoint: the instances of a batch run the same sequence as
+// adjoint_run_2d in lock step (they share nsteps and K, hence the segment
+// structure), each on its own pool, and every step of every phase is one
+// launch over all instances: the forward steps (with checkpoints) and the
+// segment recomputations through the batched step kernels with per-step
+// descriptor tables, the adjoint steps through k_batch_adj_regular2d /
+// k_batch_adj_cut2d with per-step buffer tables, the checkpoint and moment
+// copies through one copy kernel.  Each instance's partial sums land in its
+// own slots in the same order as alone, so its gradient is the same bit for
+// bit as cc_adjoint's.  All tables are built on the host and uploaded once.
+// ---------------------------------------------------------------------
+namespace {
+
+struct AdjInst {
+  Geo2D G;
+  AdjParams P;
+  int cut_base;
+};
+
+__global__ void __launch_bounds__(256) k_batch_adj_regular2d(const AdjInst* __restrict__ I,
+                                                             const AdjBufs* __restrict__ Bs,
+                                                             const int2* __restrict__ items, int n, int npad) {
+  __shared__ double lds[4][4];
+  // blocks of one XCD take a contiguous range of the item list
+  const int b = blockIdx.x, per = npad / 8;
+  const int w = (b % 8) * per + b / 8;
+  if (w >= n) return;
+  const int2 it = items[w];
+  const int inst = __builtin_amdgcn_readfirstlane(it.x);
+  const int blk = __builtin_amdgcn_readfirstlane(it.y);
+  adj_regular_body(I[inst].G, Bs[inst], I[inst].P, blk, lds);
+}
+
+__global__ void __launch_bounds__(256) k_batch_adj_cut2d(const AdjInst* __restrict__ I,
+                                                         const AdjBufs* __restrict__ Bs,
+                                                         const int2* __restrict__ items, int n) {
+  __shared__ double lds[8];
+  if ((int)blockIdx.x >= n) return;
+  const int2 it = items[blockIdx.x];
+  const int inst = __builtin_amdgcn_readfirstlane(it.x);
+  const int q = __builtin_amdgcn_readfirstlane(it.y);
+  adj_cut_body(I[inst].G, Bs[inst], I[inst].P, I[inst].cut_base, q, lds);
+}
+
+struct CopyItem {
+  const double* src;
+  double* dst;
+  size_t n;
+};
+
+// copy list blockIdx.y: src -> dst, n doubles
+__global__ void k_copy_items(const CopyItem* __restrict__ items) {
+  const CopyItem c = items[blockIdx.y];
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < c.n; t += (size_t)gridDim.x * blockDim.x)
+    c.dst[t] = c.src[t];
+}
+
+struct BatchAdjPlan {
+  std::vector<AdjLayout> L;
+  std::vector<size_t> pool;          // offset of each instance's pool in the workspace
+  size_t inst, bufs, fwd, copies, adj_items, cut_items, total;
+  int nfwd, nbufs, ncopies, nadj_items, ncut_items;
+};
+
+BatchAdjPlan batch_adj_plan(const cc_batch* B, int nsteps, int K) {
+  BatchAdjPlan X;
+  const int n = (int)B->ctx.size();
+  size_t off = 0;
+  X.nadj_items = 0;
+  X.ncut_items = 0;
+  for (cc_ctx* c : B->ctx) {
+    X.L.push_back(adj_layout(c, nsteps, K));
+    X.pool.push_back(off);
+    off += al256(X.L.back().total);
+    X.nadj_items += X.L.back().nreg_blocks;
+    X.ncut_items += c->n_irr;
+  }
+  const int nckpt = (nsteps + K - 1) / K;
+  X.nfwd = nsteps + (nsteps - nckpt);       // forward steps, then the segment recomputations
+  X.nbufs = nsteps;                         // adjoint steps
+  X.ncopies = 1 + 2 * nckpt + (nsteps - nckpt);
+  X.inst = off; off += al256(n * sizeof(AdjInst));
+  X.bufs = off; off += al256((size_t)X.nbufs * n * sizeof(AdjBufs));
+  X.fwd = off; off += al256((size_t)X.nfwd * n * batch_desc_bytes());
+  X.copies = off; off += al256((size_t)X.ncopies * n * sizeof(CopyItem));
+  X.adj_items = off; off += al256((size_t)(X.nadj_items + 8) * sizeof(int2));
+  X.cut_items = off; off += al256((size_t)(X.ncut_items + 1) * sizeof(int2));
+  X.total = off;
+  return X;
+}
+
+}  // namespace
+
+size_t batch_adjoint_workspace_bytes(const cc_batch* B, int nsteps, int K) {
+  return batch_adj_plan(B, nsteps, K).total;
+}
+
+// out (host, 5 per instance) = J, dJ/dT_w, dJ/dKn, dJ/du_x, dJ/du_y
+hipError_t batch_adjoint_run_2d(cc_batch* Bt, int nsteps, int K, int objective, char* ws, double* out) {
+  const int n = (int)Bt->ctx.size();
+  const BatchAdjPlan X = batch_adj_plan(Bt, nsteps, K);
+  hipStream_t s = Bt->stream;
+  hipError_t e;
+  const size_t dsz = batch_desc_bytes();
+  // descriptor images of every instance (their tile and cut lists are
+  // uploaded again, for the group tile heights in force now)
+  std::vector<char> d0, d1;
+  std::vector<int2> tiles, cuts;
+  batch_fill(Bt, d0, d1, tiles, cuts);
+  if (tiles.size() > Bt->tile_cap || cuts.size() > Bt->cut_cap) return hipErrorInvalidValue;
+  Bt->ncut = (int)cuts.size();
+  if (!tiles.empty() && (e = hipMemcpyAsync(Bt->d_tiles, tiles.data(), tiles.size() * sizeof(int2),
+                                            hipMemcpyHostToDevice, s)) != hipSuccess)
+    return e;
+  if (!cuts.empty() && (e = hipMemcpyAsync(Bt->d_cuts, cuts.data(), cuts.size() * sizeof(int2),
+                                           hipMemcpyHostToDevice, s)) != hipSuccess)
+    return e;
+
+  // ---- host tables
+  std::vector<char> tab(X.total - X.inst, 0);
+  auto at = [&](size_t off) { return tab.data() + (off - X.inst); };
+  std::vector<int2> adj_items, cut_items;
+  std::vector<char*> pool(n);
+  std::vector<AdjParams> P(n);
+  for (int i = 0; i < n; ++i) {
+    cc_ctx* c = Bt->ctx[i];
+    pool[i] = ws + X.pool[i];
+    P[i] = adj_params(c, objective);
+    AdjInst a;
+    a.G = c->g2;
+    a.P = P[i];
+    a.cut_base = X.L[i].nreg_blocks;
+    memcpy(at(X.inst) + i * sizeof(AdjInst), &a, sizeof(a));
+    for (int b = 0; b < X.L[i].nreg_blocks; ++b) adj_items.push_back(make_int2(i, b));
+    for (int q = 0; q < c->n_irr; ++q) cut_items.push_back(make_int2(i, q));
+  }
+  memcpy(at(X.adj_items), adj_items.data(), adj_items.size() * sizeof(int2));
+  memcpy(at(X.cut_items), cut_items.data(), cut_items.size() * sizeof(int2));
+  const int nadj_pad = (X.nadj_items + 7) / 8 * 8;
+
+  // the control flow of adjoint_run_2d, recorded as a list of operations
+  enum { OP_COPY, OP_FWD, OP_ADJ };
+  struct Op { int kind, idx; };
+  std::vector<Op> ops;
+  int nf = 0, nb = 0, nc = 0;
+  auto add_copy = [&](auto&& item_of) {
+    CopyItem* list = (CopyItem*)(at(X.copies)) + (size_t)nc * n;
+    for (int i = 0; i < n; ++i) list[i] = item_of(i);
+    ops.push_back({OP_COPY, nc++});
+  };
+  auto add_fwd = [&](auto&& ptrs_of) {
+    char* set = at(X.fwd) + (size_t)nf * n * dsz;
+    for (int i = 0; i < n; ++i) {
+      memcpy(set + i * dsz, d0.data() + i * dsz, dsz);
+      const double2* in;
+      double2* o;
+      double* mom;
+      ptrs_of(i, in, o, mom);
+      batch_desc_patch(set + i * dsz, in, o, mom);
+    }
+    ops.push_back({OP_FWD, nf++});
+  };
+  std::vector<size_t> st(n), mb(n);
+  std::vector<int> cur(n);
+  std::vector<char*> own0(n), own1(n), where(n);
+  for (int i = 0; i < n; ++i) {
+    cc_ctx* c = Bt->ctx[i];
+    st[i] = c->state_bytes;
+    mb[i] = al256((size_t)c->ncell * 4 * sizeof(double));
+    cur[i] = c->cur;
+    own0[i] = (char*)c->state[0];
+    own1[i] = (char*)c->state[1];
+    where[i] = (char*)c->state[c->cur];
+  }
+  auto own = [&](int i, int k) { return k ? own1[i] : own0[i]; };
+  // forward with checkpoints
+  for (int step = 0; step < nsteps; ++step) {
+    if (step == 0)
+      add_copy([&](int i) {
+        return CopyItem{(const double*)where[i], (double*)(pool[i] + X.L[i].ckpt), st[i] / 8};
+      });
+    if (step % K == 0)
+      add_copy([&](int i) {
+        cc_ctx* c = Bt->ctx[i];
+        return CopyItem{c->s.mom, (double*)(pool[i] + X.L[i].ckmom + mb[i] * (size_t)(step / K)),
+                        (size_t)c->ncell * 4};
+      });
+    add_fwd([&](int i, const double2*& in, double2*& o, double*& mom) {
+      const int outk = 1 - cur[i];
+      char* dst = (step + 1) % K == 0 && step + 1 < nsteps ? pool[i] + X.L[i].ckpt + st[i] * (size_t)((step + 1) / K)
+                                                           : own(i, outk);
+      in = (const double2*)where[i];
+      o = (double2*)dst;
+      mom = Bt->ctx[i]->s.mom;
+      cur[i] = outk;
+      where[i] = dst;
+    });
+  }
+  // backward over the segments
+  const int nckpt = (nsteps + K - 1) / K;
+  int cur_mu = 0;
+  std::vector<int> bw_order;
+  for (int sg = nckpt - 1; sg >= 0; --sg) {
+    const int n0 = sg * K, n1 = nsteps < n0 + K ? nsteps : n0 + K, len = n1 - n0;
+    auto state = [&](int i, int k) -> char* {
+      return k == 0 ? pool[i] + X.L[i].ckpt + st[i] * (size_t)sg : pool[i] + X.L[i].seg + st[i] * (size_t)(k - 1);
+    };
+    add_copy([&](int i) {
+      return CopyItem{(const double*)(pool[i] + X.L[i].ckmom + mb[i] * (size_t)sg),
+                      (double*)(pool[i] + X.L[i].segmom), (size_t)Bt->ctx[i]->ncell * 4};
+    });
+    for (int k = 0; k + 1 < len; ++k) {
+      add_copy([&](int i) {
+        char* sm = pool[i] + X.L[i].segmom;
+        return CopyItem{(const double*)(sm + mb[i] * k), (double*)(sm + mb[i] * (k + 1)),
+                        (size_t)Bt->ctx[i]->ncell * 4};
+      });
+      add_fwd([&](int i, const double2*& in, double2*& o, double*& mom) {
+        in = (const double2*)state(i, k);
+        o = (double2*)state(i, k + 1);
+        mom = (double*)(pool[i] + X.L[i].segmom + mb[i] * (k + 1));
+      });
+    }
+    for (int k = len - 1; k >= 0; --k) {
+      AdjBufs* set = (AdjBufs*)(at(X.bufs)) + (size_t)nb * n;
+      for (int i = 0; i < n; ++i) {
+        char* mu[2] = {pool[i] + X.L[i].mu0, pool[i] + X.L[i].mu1};
+        AdjBufs b;
+        b.x = (const double2*)state(i, k);
+        b.mom = (const double*)(pool[i] + X.L[i].segmom + mb[i] * k);
+        b.mu_in = (const double2*)mu[cur_mu];
+        b.mu_out = (double2*)mu[1 - cur_mu];
+        b.part = (double*)(pool[i] + X.L[i].part);
+        b.body = Bt->ctx[i]->s.body;
+        set[i] = b;
+      }
+      ops.push_back({OP_ADJ, nb++});
+      cur_mu = 1 - cur_mu;
+    }
+  }
+  if (nf != X.nfwd || nb != X.nbufs || nc != X.ncopies) return hipErrorInvalidValue;
+  e = hipMemcpyAsync(ws + X.inst, tab.data(), tab.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+
+  // ---- device work
+  for (int i = 0; i < n; ++i) {
+    const AdjLayout& L = X.L[i];
+    k_fill0<<<512, 256, 0, s>>>((double*)(pool[i] + L.part), (size_t)L.nparts * 4);
+    k_fill0<<<1024, 256, 0, s>>>((double*)(pool[i] + L.mu0), st[i] / 8);
+    k_fill0<<<1024, 256, 0, s>>>((double*)(pool[i] + L.mu1), st[i] / 8);
+  }
+  const AdjInst* dI = (const AdjInst*)(ws + X.inst);
+  const int2* dadj = (const int2*)(ws + X.adj_items);
+  const int2* dcut = (const int2*)(ws + X.cut_items);
+  hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr, join = nullptr;
+  struct Cleanup {
+    hipStream_t* side;
+    hipEvent_t* fork;
+    hipEvent_t* join;
+    ~Cleanup() {
+      for (int k = 0; k < 4; ++k)
+        if (side[k]) hipStreamDestroy(side[k]);
+      if (*fork) hipEventDestroy(*fork);
+      if (*join) hipEventDestroy(*join);
+    }
+  } cleanup{side, &fork, &join};
+  for (int k = 0; k < 4; ++k)
+    if ((e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&join, hipEventDisableTiming)) != hipSuccess) return e;
+  auto run = [&](const Op& op) -> hipError_t {
+    if (op.kind == OP_COPY) {
+      k_copy_items<<<dim3(1024, n), 256, 0, s>>>((const CopyItem*)(ws + X.copies) + (size_t)op.idx * n);
+    } else if (op.kind == OP_FWD) {
+      return batch_launch_desc(Bt, ws + X.fwd + (size_t)op.idx * n * dsz, side, 4);
+    } else {
+      const AdjBufs* set = (const AdjBufs*)(ws + X.bufs) + (size_t)op.idx * n;
+      // cut control volumes beside the regular cells (disjoint cells and slots)
+      if (X.ncut_items > 0) {
+        hipError_t r = hipEventRecord(fork, s);
+        if (r == hipSuccess) r = hipStreamWaitEvent(side[0], fork, 0);
+        if (r != hipSuccess) return r;
+        k_batch_adj_cut2d<<<X.ncut_items, 256, 0, side[0]>>>(dI, set, dcut, X.ncut_items);
+        if ((r = hipEventRecord(join, side[0])) != hipSuccess) return r;
+      }
+      k_batch_adj_regular2d<<<nadj_pad, 256, 0, s>>>(dI, set, dadj, X.nadj_items, nadj_pad);
+      if (X.ncut_items > 0) return hipStreamWaitEvent(s, join, 0);
+    }
+    return hipGetLastError();
+  };
+  // forward phase: operations up to the first adjoint step's segment start
+  // are recorded in order; the objective sits between the forward and the
+  // backward operations
+  size_t k = 0;
+  const size_t nforward_ops = 1 + (size_t)nckpt + (size_t)nsteps;   // initial copy, moment copies, steps
+  for (; k < nforward_ops; ++k)
+    if ((e = run(ops[k])) != hipSuccess) return e;
+  // instance state after the forward: the final state is current
+  for (int i = 0; i < n; ++i) {
+    cc_ctx* c = Bt->ctx[i];
+    const int steps_parity = nsteps & 1;
+    c->cur = cur[i];
+    c->step_parity ^= steps_parity;
+    (void)steps_parity;
+  }
+  std::vector<double> hout(8 * (size_t)n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    cc_ctx* c = Bt->ctx[i];
+    double* dev_out = (double*)(pool[i] + X.L[i].out);
+    if ((e = launch_force_only_2d(c, dev_out)) != hipSuccess) return e;
+    AdjBufs b;
+    b.body = c->s.body;
+    b.part = (double*)(pool[i] + X.L[i].part);
+    b.x = (const double2*)c->state[c->cur];
+    b.mom = c->s.mom;
+    b.mu_in = nullptr;
+    b.mu_out = (double2*)(pool[i] + X.L[i].mu0);
+    if (c->n_irr > 0)
+      k_adj_objective2d<<<c->n_irr, 256, 0, s>>>(c->g2, b, P[i], X.L[i].nreg_blocks + c->ncell);
+  }
+  for (; k < ops.size(); ++k)
+    if ((e = run(ops[k])) != hipSuccess) return e;
+  for (int i = 0; i < n; ++i) {
+    cc_ctx* c = Bt->ctx[i];
+    const AdjLayout& L = X.L[i];
+    AdjBufs b;
+    b.body = c->s.body;
+    b.part = (double*)(pool[i] + L.part);
+    b.x = nullptr;
+    b.mom = nullptr;
+    b.mu_in = (const double2*)(cur_mu ? pool[i] + L.mu1 : pool[i] + L.mu0);
+    b.mu_out = nullptr;
+    k_adj_initial2d<<<c->ncell, 256, 0, s>>>(c->g2, b, P[i], L.nreg_blocks + 2 * c->ncell);
+    double* mid = (double*)(pool[i] + L.mid);
+    double* dev_out = (double*)(pool[i] + L.out);
+    const int span = (L.nparts + kSumBlocks - 1) / kSumBlocks;
+    k_adj_sum<<<kSumBlocks, 256, 0, s>>>(b.part, L.nparts, span, mid);
+    k_adj_sum<<<1, 256, 0, s>>>(mid, kSumBlocks, kSumBlocks, dev_out + 4);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(hout.data() + 8 * (size_t)i, dev_out, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess)
+      return e;
+  }
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  for (int i = 0; i < n; ++i) {
+    const double* h = hout.data() + 8 * (size_t)i;
+    out[5 * i + 0] = objective == 0 ? h[0] : h[2];
+    out[5 * i + 1] = h[4];
+    out[5 * i + 2] = h[5];
+    out[5 * i + 3] = h[6];
+    out[5 * i + 4] = h[7];
+  }
   return hipSuccess;
 }
 

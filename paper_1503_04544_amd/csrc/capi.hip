@@ -1338,6 +1338,39 @@ cc_status batch_step_impl(cc_batch* b, int nsteps) {
   return CC_OK;
 }
 
+cc_status batch_adjoint_workspace_bytes_impl(const cc_batch* b, int nsteps, int K, size_t* bytes) {
+  if (!b || !bytes || nsteps < 1 || K < 1) return CC_EINVAL;
+  *bytes = batch_adjoint_workspace_bytes(b, nsteps, K);
+  return CC_OK;
+}
+
+cc_status batch_adjoint_impl(cc_batch* b, int nsteps, int K, int objective, void* ws, double* out) {
+  if (!b || !ws || !out || nsteps < 1 || K < 1 || (objective != 0 && objective != 1)) return CC_EINVAL;
+  if (!b->bound) return batch_fail(b, CC_ESTATE, "cc_batch_bind first");
+  if ((uintptr_t)ws % kAlign) return batch_fail(b, CC_EINVAL, "workspace must be 256-byte aligned");
+  for (cc_ctx* c : b->ctx) {
+    if (!c->bound) return batch_fail(b, CC_ESTATE, "an instance is no longer bound");
+    if (c->cfg.model != CC_MODEL_BGK)
+      return batch_fail(b, CC_EINVAL, "the adjoint is written for the BGK model");
+    cc_status st = cc_init_maxwellian(c);
+    if (st != CC_OK) return batch_fail(b, st, "instance initialisation failed: " + c->err);
+  }
+  std::vector<double> r(5 * b->ctx.size());
+  hipError_t e = batch_adjoint_run_2d(b, nsteps, K, objective, (char*)ws, r.data());
+  if (e != hipSuccess) return batch_fail(b, CC_EHIP, std::string("batched adjoint: ") + hipGetErrorString(e));
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    const cc_ctx* c = b->ctx[i];
+    // Mach number along the inflow direction, as cc_adjoint
+    const double ux = c->cfg.inflow[1], uy = c->cfg.inflow[2], un = sqrt(ux * ux + uy * uy);
+    const double ex = un > 0.0 ? ux / un : 1.0, ey = un > 0.0 ? uy / un : 0.0;
+    out[4 * i + 0] = r[5 * i + 0];
+    out[4 * i + 1] = r[5 * i + 1];
+    out[4 * i + 2] = r[5 * i + 2];
+    out[4 * i + 3] = sqrt(kGamma * c->cfg.inflow[4]) * (ex * r[5 * i + 3] + ey * r[5 * i + 4]);
+  }
+  return CC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1505,6 +1538,16 @@ void cc_destroy(cc_ctx* ctx) {
 }
 
 const char* cc_last_error(const cc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+cc_status cc_batch_adjoint_workspace_bytes(const cc_batch* b, int nsteps, int ckpt_every, size_t* bytes) {
+  return no_throw(nullptr, [&] { return batch_adjoint_workspace_bytes_impl(b, nsteps, ckpt_every, bytes); });
+}
+
+cc_status cc_batch_adjoint(cc_batch* b, int nsteps, int ckpt_every, int objective, void* workspace,
+                           double* out) {
+  return no_throw(b ? &b->err : nullptr,
+                  [&] { return batch_adjoint_impl(b, nsteps, ckpt_every, objective, workspace, out); });
+}
 
 const char* cc_batch_last_error(const cc_batch* b) { return b ? b->err.c_str() : "null batch"; }
 

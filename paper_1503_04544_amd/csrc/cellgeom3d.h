@@ -1,5 +1,5 @@
-// Per-cell 3D cut-cell geometry (Section 5.1; the paper leaves the 3D
-// geometry to the reader), used by the uniform-grid geometry kernels and the
+// Per-cell 3D cut-cell geometry (Section 5; Appendix A leaves
+// its extension to 3D to the reader), used by the uniform-grid geometry kernels and the
 // octree builder.  Rules (the 2D virtual-cell rules of Appendix A carried to
 // the six faces of a hexahedral cell):
 //   * a Cartesian face's gas part is bounded by its gas corners and the linear

@@ -1,4 +1,4 @@
-// Device construction of the 3D cut-cell geometry (Section 5.1, fixed body).
+// Device construction of the 3D cut-cell geometry (Section 5, fixed body).
 // The paper leaves the 3D geometry to the reader; the rules used here:
 //   * vertex level set with the 1e-10 dx clamp, sign(0) = +1;
 //   * per-cell faces, wall and volume as in cellgeom3d.h (the 2D

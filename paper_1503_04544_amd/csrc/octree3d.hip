@@ -1,4 +1,4 @@
-// Octree mesh around a fixed body in 3D (Section 5, octree procedure) and
+// Octree mesh around a fixed body in 3D (Section 5.1, octree procedure) and
 // its explicit step.
 //
 // Mesh (built once, on the host, when the context is created): the coarse
@@ -608,7 +608,7 @@ bool plan_amr_move(const cc_config& cfg, const cc_body& body, double th1, AmrHos
 }
 
 // The state carried from the mesh of t^n (old, with its leaves' gas volumes
-// at t^{n+1}) to the mesh of t^{n+1} (Section 5, mesh adaptation): a leaf
+// at t^{n+1}) to the mesh of t^{n+1} (Section 5.1, mesh adaptation): a leaf
 // that is also an old leaf, or lies inside one, takes its value (0th-order
 // prolongation); a leaf that covers old leaves takes their gas-volume
 // weighted mean (restriction), summed in old-leaf order; solid leaves are 0.
@@ -662,15 +662,9 @@ void build_amr_remap(const AmrHost& O, const AmrHost& H, int depth, AmrRemap& R)
 namespace {
 
 constexpr int kWaveA = 64;
-#ifndef CCDVM_AMR_RC
-#define CCDVM_AMR_RC 4   // velocities per lane and pass of the general octree step
-#endif
-#ifndef CCDVM_AMR_RCS
-#define CCDVM_AMR_RCS 2  // velocities per lane and pass of the streaming octree step
-#endif
-#ifndef CCDVM_AMR_PIPE
-#define CCDVM_AMR_PIPE 2 // streaming octree step: passes of loads issued ahead of the computed one
-#endif
+constexpr int kAmrRC = 4;    // velocities per lane and pass of the general octree step
+constexpr int kAmrRCS = 2;   // velocities per lane and pass of the streaming octree step
+constexpr int kAmrPipe = 2;  // streaming octree step: passes of loads issued ahead of the computed one
 
 __device__ inline double wsum(double v) {
 #pragma unroll
@@ -719,7 +713,7 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
   constexpr int NV = N * N * N;
   constexpr int NT = 256;
   constexpr int R = (NV + NT - 1) / NT;                      // velocities per thread
-  constexpr int RC = R < CCDVM_AMR_RC ? R : CCDVM_AMR_RC;   // per pass
+  constexpr int RC = R < kAmrRC ? R : kAmrRC;   // per pass
   constexpr int NP = (R + RC - 1) / RC;
   __shared__ double lds[4][2];
   // XCD-aware order: block b runs on XCD b % 8, and the blocks of one XCD
@@ -885,7 +879,7 @@ template <int N>
 __global__ void __launch_bounds__(256) k_amr_simple(AmrArgs A) {
   constexpr int NV = N * N * N;
   constexpr int R = (NV + kWaveA - 1) / kWaveA;
-  constexpr int RC = R < CCDVM_AMR_RCS ? R : CCDVM_AMR_RCS;
+  constexpr int RC = R < kAmrRCS ? R : kAmrRCS;
   constexpr int NP = (R + RC - 1) / RC;
   __shared__ double lds[4][4];
   const int per = A.per_simple, ncv = A.G.nsimple;
@@ -917,9 +911,9 @@ __global__ void __launch_bounds__(256) k_amr_simple(AmrArgs A) {
     tz = exp(-(v - uz) * (v - uz) * inv2T);
   }
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  // passes of RC velocities per lane; the loads of pass k + CCDVM_AMR_PIPE
-  // are issued before pass k is computed (CCDVM_AMR_PIPE + 1 stages)
-  constexpr int ST = CCDVM_AMR_PIPE + 1;
+  // passes of RC velocities per lane; the loads of pass k + kAmrPipe
+  // are issued before pass k is computed (kAmrPipe + 1 stages)
+  constexpr int ST = kAmrPipe + 1;
   double fo[ST][RC], fx[ST][RC], fy[ST][RC], fz[ST][RC];
   auto load = [&](int pass, int st) {
     // the lane id is laundered per pass so that the velocity constants of a

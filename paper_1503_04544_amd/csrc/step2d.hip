@@ -308,28 +308,19 @@ __global__ void __launch_bounds__(256) k_cut_force2d(Geo2D G, const double2* __r
 // ---------------------------------------------------------------------
 constexpr int kTileW = 4;   // columns (waves) per tile
 constexpr int kListBlocks = 512;   // grid of kernels that walk a list whose length is on the device
-#ifndef CCDVM_PREFETCH
-#define CCDVM_PREFETCH 4
-#endif
-#ifndef CCDVM_XLDS
-#define CCDVM_XLDS 1
-#endif
+constexpr int kPrefetch = 4;       // chunks loaded ahead of the one computed, at most
 // VGPRs the Shakhov variant needs beyond the BGK one (heat-flux sums, q and
 // the velocity offsets), taken from the prefetch budget
-#ifndef CCDVM_SK_REGS
-#define CCDVM_SK_REGS 40
-#endif
+constexpr int kSkRegs = 40;
 // VGPRs per chunk the semi-implicit variant needs beyond the explicit one
 // (it holds the transported row until its relaxation)
-#ifndef CCDVM_IM_REGS
-#define CCDVM_IM_REGS 8
-#endif
+constexpr int kImRegs = 8;
 // Chunks loaded ahead of the one computed.  Each chunk in flight costs 16
 // VGPRs and the row window 8 per chunk; the depth is capped so that a wave
 // stays within 256 VGPRs (2 waves per SIMD) without spilling.
 constexpr int prefetch_depth(int nch, bool sk = false, bool im = false) {
-  int cap = (138 - (sk ? CCDVM_SK_REGS : 0) - (im ? CCDVM_IM_REGS * nch : 0) - 8 * nch) / 16;
-  int d = CCDVM_PREFETCH < cap ? CCDVM_PREFETCH : cap;
+  int cap = (138 - (sk ? kSkRegs : 0) - (im ? kImRegs * nch : 0) - 8 * nch) / 16;
+  int d = kPrefetch < cap ? kPrefetch : cap;
   d = d < 1 ? 1 : d;
   return d < nch - 1 ? d : (nch - 1 > 0 ? nch - 1 : 0);
 }
@@ -660,7 +651,7 @@ __device__ __forceinline__ void step_tiles(const Geo2D& G, const FusedArgs& A, c
   __shared__ double lds[8];
   // LDS lower halves (<= 64 KB per block); the semi-implicit variant keeps
   // two rows of them and needs them
-  constexpr bool kX = (CCDVM_XLDS || IM) && NCH <= 16;
+  constexpr bool kX = NCH <= 16;
   static_assert(!IM || NCH <= 8, "semi-implicit tile: at most 8 chunks per half");
   __shared__ d2v xlo[kX ? (IM ? 2 : 1) * kTileW * NCH * kWave : 1];
   const int bid = blockIdx.x;
@@ -684,11 +675,8 @@ __global__ void __launch_bounds__(256) k_step2d(Geo2D G, FusedArgs A, StepParams
 
 // the semi-implicit variant is held to 2 waves per SIMD (its LDS allows 2
 // blocks per CU); a few spilled registers cost less than half the waves
-#ifndef CCDVM_IM_WPE
-#define CCDVM_IM_WPE 2
-#endif
 template <int NCH, bool SK>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCDVM_IM_WPE)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_step2d_im(Geo2D G, FusedArgs A, StepParams P) {
   step_tiles<NCH, SK, true>(G, A, P);
 }
@@ -1395,7 +1383,7 @@ __global__ void __launch_bounds__(256) k_batch_tiles2d(const BatchInst* __restri
                                                        int nitems_pad) {
   __shared__ double lds[8];
   // the lower halves exchanged through LDS as in the single-instance kernel
-  constexpr bool kX = CCDVM_XLDS && NCH <= 16;
+  constexpr bool kX = NCH <= 16;
   __shared__ d2v xlo[kX ? kTileW * NCH * kWave : 1];
   const int b = blockIdx.x;
   const int per = nitems_pad / 8;

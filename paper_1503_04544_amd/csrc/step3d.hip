@@ -1,4 +1,4 @@
-// Device step of the 3D cut-cell scheme (Section 5.1, eq. eq-schema3D, fixed
+// Device step of the 3D cut-cell scheme (Section 5, eq. eq-schema3D, fixed
 // body) with the BGK relaxation (eq. MaxwellianTD, tau = (sqrt(pi)/2) Kn
 // L_ref / (sqrt(2) rho)) and the diffuse wall of zero net mass flux.
 //
@@ -32,24 +32,13 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kTY = 4, kTZ = 4, kTileWaves = kTY * kTZ;
-#ifndef CCDVM_PD3
-#define CCDVM_PD3 2
-#endif
-#ifndef CCDVM_CHUNK_LAUNCH
-#define CCDVM_CHUNK_LAUNCH 0
-#endif
-#ifndef CCDVM_R16
-#define CCDVM_R16 4   // velocities per lane of the N = 16 kernel: 4 or 8
-#endif
-#ifndef CCDVM_HALO_PD
-#define CCDVM_HALO_PD 0
-#endif
 // Own cells are loaded kPD3 + 2 x-steps before they are updated, halo cells
 // kHaloPD x-steps before.  Vector-memory completions are waited for in issue
 // order, so each x-step issues the halo loads (needed soonest) before the own
 // prefetch.
-constexpr int kPD3 = CCDVM_PD3;
-constexpr int kHaloPD = CCDVM_HALO_PD;
+constexpr int kPD3 = 2;
+constexpr int kHaloPD = 0;
+constexpr int kR16 = 4;   // velocities per lane of the N = 16 kernel
 
 __device__ inline double wave_sum3(double v) {
 #pragma unroll
@@ -113,7 +102,7 @@ struct Chunk3 {
   static constexpr int H = N / 2;                 // p2 (or p3) values of one sign
   static constexpr int E1 = H * N;                // velocities of one (p3, half of p2)
   // p3 per chunk (N = 16: as the dedicated kernel's chunks)
-  static constexpr int G3 = N == 16 ? CCDVM_R16 / 2 : ((H % 2 == 0) ? 2 : (H % 3 == 0 ? 3 : 1));
+  static constexpr int G3 = N == 16 ? kR16 / 2 : ((H % 2 == 0) ? 2 : (H % 3 == 0 ? 3 : 1));
   static constexpr int CH = G3 * E1;              // velocities per chunk
   static constexpr int R = (CH + kWave - 1) / kWave;
   static constexpr int NCH = 4 * H / G3;          // chunks
@@ -294,8 +283,8 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A, const int* _
 }
 
 // ---------------------------------------------------------------------
-// N = 16 regular-cell kernel.  Same chunks as Chunk3<16> (R = 4 or 8 slots
-// per lane, 16 or 8 chunks of 64 R velocities), with the index structure made
+// N = 16 regular-cell kernel.  Same chunks as Chunk3<16> (R = 4 slots per
+// lane, 16 chunks of 256 velocities), with the index structure made
 // explicit: slot r of lane l holds p1 = l % 16, p2 = 8 sy + l / 16 +
 // 4 (r & 1), p3 = p3b + r / 2, at offset (p3b + r/2) 256 + 128 sy +
 // 64 (r & 1) + l in the cell.  Per x-step and wave: one exp per lane (lanes
@@ -308,7 +297,6 @@ __global__ void __launch_bounds__(1024) k_step3d(const Step3Args A, const int* _
 // two register slots (next, in flight) and the x loop is unrolled by two.
 // Halo cells of the next x-step are requested after the update.
 // ---------------------------------------------------------------------
-constexpr int kR16 = CCDVM_R16;          // slots per lane: 4 or 8
 constexpr int kG16 = kR16 / 2;           // p3 values per chunk
 constexpr int kNCH16 = 2 * 16 / kG16;    // chunks
 
@@ -739,7 +727,7 @@ __device__ inline double maxw3(double rho, double ux, double uy, double uz, doub
 }
 
 // One control volume that is cut or owns merged cells: wall density of each
-// wall face (zero net mass flux, Section 5.1), fluxes through the six
+// wall face (zero net mass flux, Section 5), fluxes through the six
 // Cartesian faces and the wall face of every member, explicit update with
 // relaxation toward the Maxwellian of the control volume's record (built by
 // k_mom3d), redistribution to the members, the moment sums of the new value
@@ -868,7 +856,7 @@ __global__ void __launch_bounds__(256) k_reduce3d(const double* __restrict__ fsl
   }
 }
 
-// merge over the control volumes with more than one member (Section 5.1
+// merge over the control volumes with more than one member (Section 5
 // step 2): value = sum_k Vbar_k F_k / V, written to every member
 __global__ void __launch_bounds__(256) k_merge3d(Geo3D G, double* __restrict__ st) {
   const int q = blockIdx.x;
@@ -1197,16 +1185,7 @@ hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
   A.nx = ctx->nx; A.ny = ctx->ny; A.nz = ctx->nz; A.nvel = ctx->nvel;
   A.ntj = (ctx->ny + kTY - 1) / kTY;
   A.ntiles = A.ntj * ((ctx->nz + kTZ - 1) / kTZ);
-#if CCDVM_CHUNK_LAUNCH
-  // one launch per velocity chunk: the tiles of a chunk run together and
-  // march along x in step, so that the edge cells a tile reads from its
-  // neighbours (same XCD, adjacent in the tile order) are still in L2
-  A.nblk = A.ntiles;
-  const int nlaunch = chunks3d(ctx->N);
-#else
   A.nblk = A.ntiles * chunks3d(ctx->N);
-  const int nlaunch = 1;
-#endif
   A.per = (A.nblk + 7) / 8;
   A.vmin = ctx->cfg.vmin;
   A.dv = ctx->dv;
@@ -1229,10 +1208,8 @@ hipError_t launch_step_3d(cc_ctx* ctx, double* row, double*) {
     if (e != hipSuccess) return e;
   }
   prof_begin(ctx, 0);
-  for (int l = 0; l < nlaunch; ++l) {
-    A.ch0 = l;
-    fn<<<A.per * 8, 1024, 0, ctx->stream>>>(A, A.kind, A.mom);
-  }
+  A.ch0 = 0;
+  fn<<<A.per * 8, 1024, 0, ctx->stream>>>(A, A.kind, A.mom);
   prof_end(ctx, 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -261,6 +261,21 @@ class Batch:
     def step(self, nsteps: int = 1):
         self._check(lib().cc_batch_step(self._h, int(nsteps)))
 
+    def adjoint(self, nsteps: int, ckpt_every: int = 16, objective: str = "drag"):
+        """Solver.adjoint for every instance at once (cc_batch_adjoint):
+        J (n,) and dJ/d(T_w, Kn, Ma) (n, 3), each instance from its inflow
+        Maxwellian."""
+        nb = C.c_size_t()
+        self._check(lib().cc_batch_adjoint_workspace_bytes(self._h, int(nsteps), int(ckpt_every), C.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.solvers[0].device)
+        n = len(self.solvers)
+        out = (C.c_double * (4 * n))()
+        self._check(lib().cc_batch_adjoint(self._h, int(nsteps), int(ckpt_every),
+                                           0 if objective == "drag" else 1, _ptr(ws), out))
+        del ws
+        a = np.array(out[:]).reshape(n, 4)
+        return a[:, 0].copy(), a[:, 1:].copy()
+
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:

@@ -1,4 +1,4 @@
-"""Pins of the 3D oracle (Section 5.1) against what geometry and mathematics fix.
+"""Pins of the 3D oracle (Section 5) against what geometry and mathematics fix.
 
 * A body whose surface is planar over every cell (a sphere of radius 1e6)
   gives exact cut cells: the gas polygon of each face, the planar wall

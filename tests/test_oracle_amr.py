@@ -1,4 +1,4 @@
-"""Pins of the oracle's octree mesh (Section 5, octree procedure) around a
+"""Pins of the oracle's octree mesh (Section 5.1, octree procedure) around a
 fixed sphere:
 
 * with no refinement it is the uniform 3D oracle (bitwise, leaves permuted);
