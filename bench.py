@@ -190,10 +190,12 @@ def measure(cfg, name, steps, warmup, args):
                        "mesh_build_ms_per_step": round(build_ms / max(build_n, 1), 3),
                        "note": "cells and active_cells are those of the initial mesh"}
     elif cfg.dim == 2 and cfg.body.motion != "fixed":
-        # moving 2D body: the geometry of t^{n+1} is rebuilt every step
+        # moving 2D body: the geometry of t^{n+1} is rebuilt every step, beside
+        # the streaming kernel of the step before (timed alone while profiling)
         geo_ms = mom_ms / max(mom_n, 1)
         out["roofline"]["geometry_rebuild_avg_us"] = round(geo_ms * 1e3, 2)
-        out["ms_per_step_without_geometry_rebuild"] = round(ms_per_step - geo_ms, 4)
+        out["roofline"]["general_cv_kernel_avg_us"] = round(cut_ms / max(cut_n, 1) * 1e3, 2)
+        out["roofline"]["geometry_overlapped"] = True
     elif cfg.dim == 3 or cfg.maxwellian == "conservative":
         # 3D: moments from the chunk sums (and the Newton triplet);
         # 2D conservative: the Newton pass between steps
@@ -210,11 +212,9 @@ def summary(line):
             "steps": line["steps"], "kernel": r["kernel"], "kernel_avg_us": r["avg_launch_us"],
             "achieved_GBs": r["achieved"], "frac": r["frac"], "traffic": r["traffic"],
             "workload": line["config"]["workload"]}
-    for k in ("ms_per_step_without_geometry_rebuild",):
-        if k in line:
-            keep[k] = line[k]
-    if "geometry_rebuild_avg_us" in r:
-        keep["geometry_rebuild_avg_us"] = r["geometry_rebuild_avg_us"]
+    for k in ("geometry_rebuild_avg_us", "general_cv_kernel_avg_us", "geometry_overlapped"):
+        if k in r:
+            keep[k] = r[k]
     return keep
 
 

@@ -25,7 +25,8 @@ bool regular_supported_2d(int nvel);
 bool regular_supported_3d(int nvel);
 hipError_t launch_force_only_2d(cc_ctx* ctx, double* out4);
 hipError_t launch_force_only_3d(cc_ctx* ctx, double* out4);
-hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_row);
+hipError_t launch_moving_prologue_2d(cc_ctx* ctx);
+hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_row, bool next);
 hipError_t launch_moving_init_2d(cc_ctx* ctx);
 size_t adjoint_workspace_bytes(const cc_ctx* ctx, int nsteps, int K);
 hipError_t adjoint_run_2d(cc_ctx* ctx, int nsteps, int K, int objective, char* pool, double* out);
@@ -147,13 +148,14 @@ void layout_scratch(cc_ctx* ctx, char* base, size_t* bytes) {
   size_t n = cell_capacity(ctx);
   int nm = ctx->dim == 2 ? 4 : 8;
   ctx->s.skind = cv.take<int>(n);
+  ctx->s.skind2 = cv.take<int>(n);
   ctx->s.target = cv.take<int>(n);
   ctx->s.rcnt = cv.take<int>(n);
   ctx->s.age = cv.take<int>(n);
   ctx->s.gl = cv.take<int>(n);
   ctx->s.gptr = cv.take<int>(n + 1);
   ctx->s.gmem = cv.take<int>(n);
-  ctx->s.gcount = cv.take<int>(4);
+  ctx->s.gcount = cv.take<int>(8);
   ctx->s.pose = cv.take<double>(4);
   ctx->s.mom = cv.take<double>(n * nm);
   ctx->s.mom2 = cv.take<double>(ctx->dim == 2 ? n * 4 : 0);
@@ -902,10 +904,11 @@ cc_status step_impl(cc_ctx* ctx, int nsteps, double* diag) {
     if (diag) HIPCHK(ctx, launch_step_2d_flush(ctx, diag + 4 * (size_t)(nsteps - 1), nullptr), "reduce");
     return CC_OK;
   }
+  if (nsteps > 0) HIPCHK(ctx, launch_moving_prologue_2d(ctx), "moving geometry");
   for (int n = 0; n < nsteps; ++n) {
     double* frow = diag ? diag + 4 * (size_t)n : nullptr;
     double* mrow = (diag && n + 1 < nsteps) ? diag + 4 * (size_t)(n + 1) + 3 : nullptr;
-    hipError_t e = launch_moving_step_2d(ctx, frow, mrow);
+    hipError_t e = launch_moving_step_2d(ctx, frow, mrow, n + 1 < nsteps);
     if (e != hipSuccess) return hip_fail(ctx, e, "step");
   }
   if (moving) {

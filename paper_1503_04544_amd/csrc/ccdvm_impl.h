@@ -164,14 +164,16 @@ struct AmrDev {
 // Scratch layout (caller's scratch buffer).
 struct Scratch {
   // moving bodies: per-step dispatch and receiving control volumes
-  int* skind;        // per-cell kind for this step
+  int* skind;        // per-cell kind of the steps of parity 0
+  int* skind2;       // per-cell kind of the steps of parity 1
   int* target;       // per cell: master at t^n of the control volume it receives from, -1 none
   int* rcnt;         // per master: receivers other than itself
   int* age;          // consecutive time levels a cell has been solid (saturates at 2)
   int* gl;           // general control volumes (master) or -1-c (cell to zero)
   int* gptr;         // receivers CSR pointers
   int* gmem;         // receivers
-  int* gcount;       // [0] entries in gl, [1] error bits
+  int* gcount;       // [0] entries in gl, [1] error bits, [2] general control volumes,
+                     // [4 + parity] entries of the step of that parity (its mass row)
   double* pose;      // pose at t^{n+1}: cx, cy, theta
   double* mom;       // 2D: ncell * 4 (rho, ux, uy, T); 3D: ncell * 8 (Maxwellian factor, u,
                      // 1/(2T), dt/tau, rho)

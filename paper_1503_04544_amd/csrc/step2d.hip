@@ -1335,31 +1335,44 @@ __global__ void __launch_bounds__(256) k_genstep2d(MoveArgs M, const double2* __
   }
 }
 
-// Force, torque (t^n) and mass (t^{n+1}) in fixed order; then the rigid
-// body: pose at t^{n+1} and, for free rotation, the angular velocity at
-// t^{n+1} from the torque of t^n (eq. motionDD_vit).
-__global__ void __launch_bounds__(256) k_rigid2d(const int* __restrict__ gcount,
+// Force and torque of t^n in fixed order (the general control volumes'
+// slots), then the rigid body: pose at t^{n+1} and, for free rotation, the
+// angular velocity at t^{n+1} from the torque of t^n (eq. motionDD_vit).
+// The number of general entries of this step is kept in gcount[4 + par]
+// for the mass row, since the step lists of the next step may be built
+// before that row is reduced.
+__global__ void __launch_bounds__(256) k_rigid2d(int* __restrict__ gcount, int par,
                                                  const double* __restrict__ fslot,
-                                                 const double* __restrict__ mpart, int ntiles,
                                                  double* __restrict__ body,
                                                  const double* __restrict__ pose, double dt,
                                                  double inv_inertia, int free_rotation,
-                                                 double* force_row, double* mass_row) {
+                                                 double* force_row) {
   __shared__ double lds[8];
   const int ng = gcount[0];
-  double ms = 0.0, fx = 0.0, fy = 0.0, tq = 0.0;
-  for (int t = threadIdx.x; t < ntiles + ng; t += blockDim.x) ms += mpart[t];
+  double fx = 0.0, fy = 0.0, tq = 0.0;
   for (int q = threadIdx.x; q < ng; q += blockDim.x) {
     fx += fslot[3 * q]; fy += fslot[3 * q + 1]; tq += fslot[3 * q + 2];
   }
-  ms = block_sum4(ms, lds); fx = block_sum4(fx, lds);
+  fx = block_sum4(fx, lds);
   fy = block_sum4(fy, lds); tq = block_sum4(tq, lds);
   if (threadIdx.x == 0) {
     if (force_row) { force_row[0] = fx; force_row[1] = fy; force_row[2] = tq; }
-    if (mass_row) mass_row[0] = ms;
     body[0] = pose[0]; body[1] = pose[1]; body[2] = pose[2];
     if (free_rotation) body[5] = body[5] + dt * tq * inv_inertia;
+    gcount[4 + par] = ng;
   }
+}
+
+// mass of t^{n+1}: the regular tiles' partials, then the general entries'
+__global__ void __launch_bounds__(256) k_moving_mass2d(const int* __restrict__ gcount, int par,
+                                                       const double* __restrict__ mpart, int ntiles,
+                                                       double* mass_row) {
+  __shared__ double lds[8];
+  const int ng = gcount[4 + par];
+  double ms = 0.0;
+  for (int t = threadIdx.x; t < ntiles + ng; t += blockDim.x) ms += mpart[t];
+  ms = block_sum4(ms, lds);
+  if (threadIdx.x == 0) mass_row[0] = ms;
 }
 
 
@@ -1736,28 +1749,29 @@ hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_forc
   return hipGetLastError();
 }
 
-__global__ void k_moving_init2d(Geo2D G, int* __restrict__ skind, int* __restrict__ target,
-                                int* __restrict__ age) {
+__global__ void k_moving_init2d(Geo2D G, int* __restrict__ skind0, int* __restrict__ skind1,
+                                int* __restrict__ target, int* __restrict__ age) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= G.ncell) return;
-  skind[c] = G.kind[c];
+  skind0[c] = G.kind[c];
+  skind1[c] = G.kind[c];
   target[c] = G.master[c];
   age[c] = G.type[c] == TYPE_SOLID ? 2 : 0;
 }
 
 hipError_t launch_moving_init_2d(cc_ctx* ctx) {
-  k_moving_init2d<<<(ctx->ncell + 255) / 256, 256, 0, ctx->stream>>>(ctx->g2, ctx->s.skind,
+  k_moving_init2d<<<(ctx->ncell + 255) / 256, 256, 0, ctx->stream>>>(ctx->g2, ctx->s.skind, ctx->s.skind2,
                                                                       ctx->s.target, ctx->s.age);
   return hipGetLastError();
 }
 
 // Box of cells that can change between t^n and t^{n+1}: the body's extent
 // at both times plus a margin covering master searches and receivers.
-Box2D moving_box(const cc_ctx* ctx) {
+Box2D moving_box(const cc_ctx* ctx, long long n) {
   const cc_body& b = ctx->body;
   double R = b.axes[0] > b.axes[1] ? b.axes[0] : b.axes[1];
   if (b.kind == CC_BODY_CIRCLE) R = b.axes[0];
-  double t0 = ctx->nstep * ctx->dt, t1 = t0 + ctx->dt;
+  double t0 = n * ctx->dt, t1 = t0 + ctx->dt;
   double vx = b.motion == CC_MOTION_IMPOSED ? b.vel[0] : 0.0;
   double vy = b.motion == CC_MOTION_IMPOSED ? b.vel[1] : 0.0;
   double xa = b.center[0] + vx * t0, xb = b.center[0] + vx * t1;
@@ -1774,34 +1788,68 @@ Box2D moving_box(const cc_ctx* ctx) {
   return Box2D{i0, j0, i1 - i0, j1 - j0};
 }
 
-hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_row) {
+// Geometry of the time level after step n (body pose from the body state
+// of t^n), built into G1 inside the box of step n, and the step lists of
+// step n against G0 (the geometry of t^n), written with parity par: the
+// per-cell kinds of that parity, the receivers, the general list.
+static hipError_t moving_lists_2d(cc_ctx* ctx, hipStream_t st, const Geo2D& G0, Geo2D& G1, long long n,
+                                  int par) {
+  k_pose_next2d<<<1, 64, 0, st>>>(ctx->s.body, ctx->s.pose, ctx->dt);
+  const Box2D bx = moving_box(ctx, n);
+  hipStream_t keep = ctx->stream;
+  ctx->stream = st;
+  hipError_t e = build_geometry_box_2d(ctx, G1, ctx->s.pose, bx);
+  ctx->stream = keep;
+  if (e != hipSuccess) return e;
+  MoveArgs M;
+  M.G0 = G0; M.G1 = G1;
+  M.skind = par ? ctx->s.skind2 : ctx->s.skind;
+  M.target = ctx->s.target; M.rcnt = ctx->s.rcnt; M.age = ctx->s.age;
+  M.gl = ctx->s.gl; M.gptr = ctx->s.gptr; M.gmem = ctx->s.gmem; M.gcount = ctx->s.gcount;
+  M.bx = bx;
+  k_steplist2d<<<1, 1024, 0, st>>>(M);
+  return hipGetLastError();
+}
+
+// Before the first step of a call: the geometry of t^{n+1} and the step
+// lists of step n (profiling slot 4: the geometry rebuild).
+hipError_t launch_moving_prologue_2d(cc_ctx* ctx) {
+  prof_begin(ctx, 4);
+  hipError_t e = moving_lists_2d(ctx, ctx->stream, ctx->g2, ctx->g2n, ctx->nstep, ctx->step_parity);
+  prof_end(ctx, 4);
+  return e;
+}
+
+// One step of a moving body (Section 3.3.4) whose geometry of t^{n+1} and
+// step lists were built before.  Main stream: merge over the control volumes
+// of t^n, the streaming kernel over the regular cells, the mass of t^{n+1}.
+// Beside it (side stream, after the merge): the general control volumes
+// (wall condition, area ratio, receivers), the force and torque of t^n and
+// the rigid body, then, when another step follows, the geometry of t^{n+2}
+// (into the buffer of t^n, which only the general control volumes read) and
+// the step lists of step n+1 (the other parity of the kind array).  While
+// profiling everything runs on the main stream in the same order.
+hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_row, bool next) {
   StepParams P = params2d(ctx);
   fused_fn fn = pick_fused(chunks_per_half(ctx), P.shakhov);
   if (!fn) return hipErrorInvalidValue;
   hipStream_t st = ctx->stream;
+  const bool overlap = ctx->side && !ctx->prof.on;
+  hipStream_t sd = overlap ? ctx->side : st;
   const int par = ctx->step_parity;
-  // 1. pose at t^{n+1}; 3. geometry at t^{n+1} inside the box and the
-  // step lists (profiling slot 4: the geometry rebuild)
-  prof_begin(ctx, 4);
-  k_pose_next2d<<<1, 64, 0, st>>>(ctx->s.body, ctx->s.pose, ctx->dt);
-  Box2D bx = moving_box(ctx);
-  hipError_t e = build_geometry_box_2d(ctx, ctx->g2n, ctx->s.pose, bx);
-  if (e != hipSuccess) return e;
   MoveArgs M;
   M.G0 = ctx->g2; M.G1 = ctx->g2n;
-  M.skind = ctx->s.skind; M.target = ctx->s.target; M.rcnt = ctx->s.rcnt; M.age = ctx->s.age;
+  M.skind = par ? ctx->s.skind2 : ctx->s.skind;
+  M.target = ctx->s.target; M.rcnt = ctx->s.rcnt; M.age = ctx->s.age;
   M.gl = ctx->s.gl; M.gptr = ctx->s.gptr; M.gmem = ctx->s.gmem; M.gcount = ctx->s.gcount;
-  M.bx = bx;
-  k_steplist2d<<<1, 1024, 0, st>>>(M);
-  prof_end(ctx, 4);
-  // 2. merge over the control volumes of t^n (independent of the new
-  // geometry and of the step lists)
+  M.bx = moving_box(ctx, ctx->nstep);
+  // 2. merge over the control volumes of t^n
   prof_begin(ctx, 3);
   k_merge2d<<<kListBlocks, 64, 0, st>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
                                         ctx->s.heat, P);
   prof_end(ctx, 3);
   FusedArgs A;
-  A.kind = ctx->s.skind;
+  A.kind = M.skind;
   A.in = (const double2*)ctx->state[ctx->cur];
   A.out = (double2*)ctx->state[1 - ctx->cur];
   A.mom = ctx->s.mom;
@@ -1824,20 +1872,38 @@ hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_ro
   A.prev_mpart = nullptr;
   A.red_force = nullptr;
   A.red_mass = nullptr;
-  // 4-6. wall condition, scheme and redistribution
+  hipError_t e;
+  if (overlap) {
+    if ((e = hipEventRecord(ctx->fork, st)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(sd, ctx->fork, 0)) != hipSuccess) return e;
+  }
+  // 4-6. wall condition, scheme and redistribution of the general control
+  // volumes; 5/1. force and torque of t^n, body velocity and pose at t^{n+1}
   prof_begin(ctx, 1);
-  k_genstep2d<<<kListBlocks, 256, 0, st>>>(M, A.in, A.out, A.mom, A.heat, fs, mp, A.ntiles, ctx->s.body, P);
+  k_genstep2d<<<kListBlocks, 256, 0, sd>>>(M, A.in, A.out, A.mom, A.heat, fs, mp, A.ntiles, ctx->s.body, P);
   prof_end(ctx, 1);
+  const bool free_rot = ctx->body.motion == CC_MOTION_FREE_ROTATION;
+  prof_begin(ctx, 2);
+  k_rigid2d<<<1, 256, 0, sd>>>(ctx->s.gcount, par, fs, ctx->s.body, ctx->s.pose, ctx->dt,
+                               free_rot ? 1.0 / ctx->body.inertia : 0.0, free_rot ? 1 : 0, force_row);
+  prof_end(ctx, 2);
+  if (overlap && next) {
+    // the next step's geometry and lists beside the streaming kernel
+    if ((e = moving_lists_2d(ctx, sd, ctx->g2n, ctx->g2, ctx->nstep + 1, 1 - par)) != hipSuccess) return e;
+  }
+  if (overlap && (e = hipEventRecord(ctx->join, sd)) != hipSuccess) return e;
+  // 6. scheme and redistribution of every other (regular) cell
   prof_begin(ctx, 0);
   fn(ctx, dim3(A.tile_base + A.ntiles_pad), A, P);
   prof_end(ctx, 0);
-  // 5/1. force and torque of t^n, body velocity and pose at t^{n+1}
-  const bool free_rot = ctx->body.motion == CC_MOTION_FREE_ROTATION;
-  prof_begin(ctx, 2);
-  k_rigid2d<<<1, 256, 0, st>>>(ctx->s.gcount, fs, mp, A.ntiles, ctx->s.body, ctx->s.pose, ctx->dt,
-                               free_rot ? 1.0 / ctx->body.inertia : 0.0, free_rot ? 1 : 0,
-                               force_row, mass_row);
-  prof_end(ctx, 2);
+  if (overlap && (e = hipStreamWaitEvent(st, ctx->join, 0)) != hipSuccess) return e;
+  if (mass_row) k_moving_mass2d<<<1, 256, 0, st>>>(ctx->s.gcount, par, mp, A.ntiles, mass_row);
+  if (!overlap && next) {
+    prof_begin(ctx, 4);
+    e = moving_lists_2d(ctx, st, ctx->g2n, ctx->g2, ctx->nstep + 1, 1 - par);
+    prof_end(ctx, 4);
+    if (e != hipSuccess) return e;
+  }
   e = hipGetLastError();
   Geo2D tmp = ctx->g2; ctx->g2 = ctx->g2n; ctx->g2n = tmp;
   ctx->cur = 1 - ctx->cur;
