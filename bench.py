@@ -40,20 +40,29 @@ WORKLOAD_TEXT = {
                 "omega0=2, theta0=pi/8), mesh adapted every step, 16^3 velocities, Kn {kn}, Mach 0.5, "
                 "T_w 1, CFL 0.5, torque every step",
 }
-# committed rocprofv3 counter summaries: workload -> (kernel source, summary)
+# committed rocprofv3 counter summaries: workload -> (kernel source, summary);
+# a summary holds for the kernel source and the headers it includes
 TRAFFIC = {
     "cyl512": ("step2d.hip", "traffic_regular2d_cyl512.json"),
     "sphere128": ("step3d.hip", "traffic_regular3d_sphere128.json"),
 }
+KERNEL_HEADERS = ("ccdvm_impl.h", "equilibrium.h")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def src_hash(path):
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def src_hash(src):
+    """sha256[:16] of a kernel source file followed by the library headers it
+    includes (csrc/ccdvm_impl.h, csrc/equilibrium.h, include/ccdvm.h)."""
+    csrc = os.path.join(ROOT, "paper_1503_04544_amd", "csrc")
+    h = hashlib.sha256()
+    for path in [os.path.join(csrc, src)] + [os.path.join(csrc, x) for x in KERNEL_HEADERS] + \
+            [os.path.join(ROOT, "include", "ccdvm.h")]:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload):
@@ -67,7 +76,7 @@ def measured_traffic(workload):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != src_hash(os.path.join(ROOT, "paper_1503_04544_amd", "csrc", src)):
+    if t.get("kernel_sources_sha256_16") != src_hash(src):
         return None
     return t.get("bytes_per_launch")
 

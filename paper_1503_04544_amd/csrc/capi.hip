@@ -1172,12 +1172,21 @@ static cc_status batch_upload_and_capture(cc_batch* b) {
     return batch_fail(b, CC_EHIP, std::string("batch upload: ") + hipGetErrorString(e));
   // one step per ping-pong parity, recorded on a private capture stream with
   // side streams for the independent kernels (all at the default priority)
-  hipStream_t cap, side[4];
-  if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess)
+  // the capture stream and the side streams are destroyed on every exit
+  struct Streams {
+    hipStream_t cap = nullptr, side[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~Streams() {
+      if (cap) hipStreamDestroy(cap);
+      for (hipStream_t s : side)
+        if (s) hipStreamDestroy(s);
+    }
+  } ss;
+  if ((e = hipStreamCreateWithFlags(&ss.cap, hipStreamNonBlocking)) != hipSuccess)
     return batch_fail(b, CC_EHIP, "capture stream");
   for (int k = 0; k < 4; ++k)
-    if ((e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking)) != hipSuccess)
+    if ((e = hipStreamCreateWithFlags(&ss.side[k], hipStreamNonBlocking)) != hipSuccess)
       return batch_fail(b, CC_EHIP, "capture stream");
+  hipStream_t cap = ss.cap;
   hipStream_t user = b->stream;
   for (int par = 0; par < 2; ++par) {
     if (b->exec[par]) { hipGraphExecDestroy(b->exec[par]); b->exec[par] = nullptr; }
@@ -1185,20 +1194,14 @@ static cc_status batch_upload_and_capture(cc_batch* b) {
     b->stream = cap;
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t le = batch_launch_step(b, par, side, 4);
+      hipError_t le = batch_launch_step(b, par, ss.side, 4);
       e = hipStreamEndCapture(cap, &b->graph[par]);
       if (le != hipSuccess) e = le;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[par], b->graph[par], nullptr, nullptr, 0);
     b->stream = user;
-    if (e != hipSuccess) {
-      hipStreamDestroy(cap);
-      for (int k = 0; k < 4; ++k) hipStreamDestroy(side[k]);
-      return batch_fail(b, CC_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-    }
+    if (e != hipSuccess) return batch_fail(b, CC_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
   }
-  hipStreamDestroy(cap);
-  for (int k = 0; k < 4; ++k) hipStreamDestroy(side[k]);
   b->base_cur.resize(b->ctx.size());
   for (size_t i = 0; i < b->ctx.size(); ++i) b->base_cur[i] = b->ctx[i]->cur;
   b->steps = 0;
