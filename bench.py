@@ -53,15 +53,25 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _code_only(text):
+    """C/C++ source without comments and blank lines (so that a change of a
+    comment does not invalidate a counter summary, a change of code does)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def src_hash(src):
-    """sha256[:16] of a kernel source file followed by the library headers it
-    includes (csrc/ccdvm_impl.h, csrc/equilibrium.h, include/ccdvm.h)."""
+    """sha256[:16] of the code of a kernel source file followed by the
+    library headers it includes (csrc/ccdvm_impl.h, csrc/equilibrium.h,
+    include/ccdvm.h), comments stripped."""
     csrc = os.path.join(ROOT, "paper_1503_04544_amd", "csrc")
     h = hashlib.sha256()
     for path in [os.path.join(csrc, src)] + [os.path.join(csrc, x) for x in KERNEL_HEADERS] + \
             [os.path.join(ROOT, "include", "ccdvm.h")]:
-        with open(path, "rb") as fh:
-            h.update(fh.read())
+        with open(path, encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -231,8 +231,12 @@ cc_status cc_step(cc_ctx* ctx, int nsteps, double* diag);
  * Solid cells get zeros.  out is a device pointer.  Asynchronous. */
 cc_status cc_moments(cc_ctx* ctx, double* out);
 
-/* Force and torque on the body for the current state (synchronous):
- * out[0..3] = Fx, Fy, torque, mass (2D) or Fx, Fy, Fz, mass (3D). */
+/* Force and torque on the body for the current state (synchronous), from
+ * the wall stress of eq. (StressTensorDD) summed over every wall edge (face)
+ * of every virtual cell, eqs. (eq-force) and (eq-torque), the wall density
+ * of eq. (BoundaryDDv) taken from the current state: out[0..3] = Fx, Fy,
+ * torque about the body centre (counter-clockwise positive), mass
+ * sum_CV S_CV rho (2D) or Fx, Fy, Fz, mass (3D, Section 5). */
 cc_status cc_body_force(cc_ctx* ctx, double out[4]);
 
 /* Rigid-body state at the current time (synchronous): centre x, y,
