@@ -71,6 +71,7 @@ void layout_geo2d_one(cc_ctx* ctx, Geo2D& G, char* base, size_t* bytes) {
   G.rwx = cv.take<double>(n); G.rwy = cv.take<double>(n);
   G.sbar = cv.take<double>(n); G.scv = cv.take<double>(n);
   G.irr = cv.take<int>(n); G.mptr = cv.take<int>(n + 1); G.mem = cv.take<int>(n);
+  G.aux = cv.take<int>(n);
   G.counts = cv.take<int>(4);
   G.vnode = cv.take<double>(ctx->N);
   G.ghost = cv.take<double2>(ctx->nvel);
@@ -1299,11 +1300,12 @@ cc_status batch_autotune_impl(cc_batch* b, int trial_steps, int* rows_out) {
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   // the trials advanced the regular cells of the ping-pong targets only, but
-  // rewrote the stored moments: recompute them from the current states
-  for (cc_ctx* c : b->ctx) c->mom_valid = false;
+  // rewrote the regular cells' stored moments: recompute those from the
+  // current states (the cut and merged control volumes keep theirs)
   for (cc_ctx* c : b->ctx) {
     cc_status st = prepare(c);
     if (st != CC_OK) return batch_fail(b, st, "instance preparation failed");
+    if (launch_moments_all_2d(c, true) != hipSuccess) return batch_fail(b, CC_EHIP, "moments");
   }
   return batch_upload_and_capture(b);
 }

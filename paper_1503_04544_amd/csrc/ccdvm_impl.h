@@ -63,7 +63,55 @@ struct Geo2D {
   double* vnode;     // N velocity nodes
   double2* ghost;    // nvel farfield values (f, g)
   double* wden;      // per irregular-list slot and member: wall-density denominator
+  int* aux;          // per cell: scratch of the list builder (member counts, then fill cursors)
 };
+
+// Sorts a list of at most kMaxMembers distinct cell indices in place into
+// ascending order, each value written at its rank (longer lists, which the
+// geometry checks reject, are left as they are).
+__device__ inline void sort_cells(int* a, int n) {
+  if (n < 2 || n > kMaxMembers) return;
+  int v[kMaxMembers];
+#pragma unroll
+  for (int e = 0; e < kMaxMembers; ++e) v[e] = e < n ? a[e] : 0x7fffffff;
+#pragma unroll
+  for (int e = 0; e < kMaxMembers; ++e) {
+    int r = 0;
+#pragma unroll
+    for (int f = 0; f < kMaxMembers; ++f) r += v[f] < v[e];
+    if (e < n) a[r] = v[e];
+  }
+}
+
+// Exclusive prefix sum of one int per thread over the block (a multiple of
+// 64 threads, at most 1024): a shuffle scan inside each wave, then the wave
+// totals through sh (16 ints), two barriers in all.  *total receives the
+// block's sum; sh may be reused as soon as the call returns.
+__device__ inline int block_scan_excl(int v, int* sh, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int sw = sh[w];
+    before += w < wave ? sw : 0;
+    tot += sw;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + x - v;
+}
+
+// an int that other threads update with atomics, read at L2
+__device__ inline int load_l2(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // One hop of the master search (algorithm (fusion), Appendix A.3) from cell
 // (i, j): across the largest gas edge shared with a cell of the domain, ties
@@ -299,7 +347,8 @@ hipError_t launch_init_maxwellian_2d(cc_ctx* ctx);
 hipError_t launch_load_state_2d(cc_ctx* ctx, const double* f, const double* g);
 hipError_t launch_store_state_2d(const cc_ctx* ctx, double* f, double* g);
 hipError_t launch_merge_2d(cc_ctx* ctx);
-hipError_t launch_moments_all_2d(cc_ctx* ctx);
+// moments of every gas cell, or (regular_only) of the regular cells only
+hipError_t launch_moments_all_2d(cc_ctx* ctx, bool regular_only = false);
 hipError_t launch_step_2d_fused(cc_ctx* ctx, bool reduce_prev, double* prev_force_row,
                                 double* cur_mass_row, bool record, bool relax = true,
                                 bool implicit = false);

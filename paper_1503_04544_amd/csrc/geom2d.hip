@@ -226,74 +226,66 @@ __global__ void k_cv2d(Geo2D G, Box2D bx) {
   if (cnt > kMaxMembers) atomicOr(&G.counts[3], 4);
 }
 
-// Block-wide exclusive scan of 1024 ints held one per thread; returns the
-// exclusive prefix and writes the block total to *total.
-__device__ int block_exclusive_scan(int v, int* sh, int* total) {
-  int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    int add = t >= off ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
-  }
-  int incl = sh[t];
-  *total = sh[blockDim.x - 1];
-  __syncthreads();
-  return incl - v;
-}
-
 // Single-block deterministic compaction: list of irregular masters in
-// ascending cell order, CSR of their members, population counts.
+// ascending cell order, CSR of their members (ascending), population counts.
+// The box cells are taken one per thread and round (coalesced), the list by
+// a block scan per round.  Members are counted and placed through integer
+// atomics on the per-cell scratch, and every member list is then sorted, so
+// the result does not depend on the order of the atomics.
 __global__ void __launch_bounds__(1024) k_compact2d(Geo2D G, Box2D bx) {
   __shared__ int sh[1024];
-  int t = threadIdx.x;
+  const int t = threadIdx.x, nth = blockDim.x;
   const int nbox = bx.ni * bx.nj;
-  int per = (nbox + blockDim.x - 1) / blockDim.x;
-  int b = t * per, e = min(b + per, nbox);
   // box index -> cell index, ascending in the cell order
   auto cell = [&](int u) { return (bx.j0 + u / bx.ni) * G.nx + bx.i0 + u % bx.ni; };
-  int nirr = 0, nmem = 0, nsol = 0;
-  for (int u = b; u < e; ++u) {
-    int k = G.kind[cell(u)];
-    nirr += k == KIND_IRREGULAR;
+  // a listed master: irregular and inside the box
+  auto listed = [&](int m) {
+    if (m < 0) return false;
+    const int i = m % G.nx - bx.i0, j = m / G.nx - bx.j0;
+    return i >= 0 && i < bx.ni && j >= 0 && j < bx.nj && G.kind[m] == KIND_IRREGULAR;
+  };
+  int carry = 0, nmem = 0, nsol = 0;
+  for (int base = 0; base < nbox; base += nth) {
+    const int u = base + t;
+    int k = -1, c = 0;
+    if (u < nbox) { c = cell(u); k = G.kind[c]; }
     nmem += k == KIND_MEMBER;
     nsol += k == KIND_SOLID;
-  }
-  int tot_irr, tot_mem, tot_sol;
-  int off = block_exclusive_scan(nirr, sh, &tot_irr);
-  block_exclusive_scan(nmem, sh, &tot_mem);
-  block_exclusive_scan(nsol, sh, &tot_sol);
-  for (int u = b; u < e; ++u)
-    if (G.kind[cell(u)] == KIND_IRREGULAR) G.irr[off++] = cell(u);
-  if (t == 0) { G.counts[0] = tot_irr; G.counts[1] = tot_mem; G.counts[2] = tot_sol; }
-  __syncthreads();
-  // member counts per listed master, then CSR pointers by a chunked scan
-  int carry = 0;
-  for (int base = 0; base < tot_irr; base += blockDim.x) {
-    int q = base + t, cnt = 0;
-    if (q < tot_irr) {
-      int m = G.irr[q], i = m % G.nx, j = m / G.nx;
-      for (int jj = max(j - kHopCap, 0); jj <= min(j + kHopCap, G.ny - 1); ++jj)
-        for (int ii = max(i - kHopCap, 0); ii <= min(i + kHopCap, G.nx - 1); ++ii)
-          cnt += G.master[jj * G.nx + ii] == m;
-    }
     int tot;
-    int ex = block_exclusive_scan(cnt, sh, &tot);
-    if (q < tot_irr) G.mptr[q] = carry + ex;
+    const int ex = block_scan_excl(k == KIND_IRREGULAR ? 1 : 0, sh, &tot);
+    if (k == KIND_IRREGULAR) { G.irr[carry + ex] = c; G.aux[c] = 0; }
+    carry += tot;
+  }
+  const int tot_irr = carry;
+  int tot_mem, tot_sol;
+  block_scan_excl(nmem, sh, &tot_mem);
+  block_scan_excl(nsol, sh, &tot_sol);
+  if (t == 0) { G.counts[0] = tot_irr; G.counts[1] = tot_mem; G.counts[2] = tot_sol; }
+  // member counts of the listed masters
+  for (int u = t; u < nbox; u += nth) {
+    const int m = G.master[cell(u)];
+    if (listed(m)) atomicAdd(&G.aux[m], 1);
+  }
+  __syncthreads();
+  // CSR pointers by a chunked scan; each count becomes its list's cursor
+  carry = 0;
+  for (int base = 0; base < tot_irr; base += nth) {
+    const int q = base + t;
+    int cnt = 0, m = 0;
+    if (q < tot_irr) { m = G.irr[q]; cnt = load_l2(&G.aux[m]); }
+    int tot;
+    const int ex = block_scan_excl(cnt, sh, &tot);
+    if (q < tot_irr) { G.mptr[q] = carry + ex; G.aux[m] = carry + ex; }
     carry += tot;
   }
   if (t == 0) G.mptr[tot_irr] = carry;
   __syncthreads();
-  for (int q = t; q < tot_irr; q += blockDim.x) {
-    int m = G.irr[q], i = m % G.nx, j = m / G.nx, w = G.mptr[q];
-    for (int jj = max(j - kHopCap, 0); jj <= min(j + kHopCap, G.ny - 1); ++jj)
-      for (int ii = max(i - kHopCap, 0); ii <= min(i + kHopCap, G.nx - 1); ++ii) {
-        int k = jj * G.nx + ii;
-        if (G.master[k] == m) G.mem[w++] = k;
-      }
+  for (int u = t; u < nbox; u += nth) {
+    const int c = cell(u), m = G.master[c];
+    if (listed(m)) G.mem[atomicAdd(&G.aux[m], 1)] = c;
   }
+  __syncthreads();
+  for (int q = t; q < tot_irr; q += nth) sort_cells(G.mem + G.mptr[q], G.mptr[q + 1] - G.mptr[q]);
 }
 
 // velocity nodes (midpoints of the velocity box) and farfield table

@@ -153,22 +153,6 @@ __global__ void k_cv3d(Geo3D G) {
   if (cnt > kMaxMembers) atomicOr(&G.counts[3], 4);
 }
 
-__device__ int block_scan(int v, int* sh, int* total) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    const int add = t >= off ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
-  }
-  const int incl = sh[t];
-  *total = sh[blockDim.x - 1];
-  __syncthreads();
-  return incl - v;
-}
-
 // single-block deterministic compaction: irregular masters in ascending
 // order, CSR of their members (ascending), population counts
 __global__ void __launch_bounds__(1024) k_compact3d(Geo3D G) {
@@ -184,9 +168,9 @@ __global__ void __launch_bounds__(1024) k_compact3d(Geo3D G) {
     nsol += kd == KIND_SOLID;
   }
   int tot_irr, tot_mem, tot_sol;
-  int off = block_scan(nirr, sh, &tot_irr);
-  block_scan(nmem, sh, &tot_mem);
-  block_scan(nsol, sh, &tot_sol);
+  int off = block_scan_excl(nirr, sh, &tot_irr);
+  block_scan_excl(nmem, sh, &tot_mem);
+  block_scan_excl(nsol, sh, &tot_sol);
   for (int u = b; u < e; ++u)
     if (G.kind[u] == KIND_IRREGULAR) G.irr[off++] = u;
   if (t == 0) { G.counts[0] = tot_irr; G.counts[1] = tot_mem; G.counts[2] = tot_sol; }
@@ -200,7 +184,7 @@ __global__ void __launch_bounds__(1024) k_compact3d(Geo3D G) {
       for_window(G, m, [&](int c) { cnt += G.master[c] == m; });
     }
     int tot;
-    const int ex = block_scan(cnt, sh, &tot);
+    const int ex = block_scan_excl(cnt, sh, &tot);
     if (q < tot_irr) G.mptr[q] = carry + ex;
     carry += tot;
   }

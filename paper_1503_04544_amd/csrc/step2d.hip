@@ -119,24 +119,6 @@ __device__ inline void shakhov2(double a, double qx, double qy, double T, double
   Eg = 0.5 * T * M * (1.0 + s * (c2T - 2.0));
 }
 
-// Block-wide exclusive scan of one int per thread (any block size up to
-// 1024); returns the exclusive prefix and the block total.
-__device__ int block_exclusive_scan_int(int v, int* sh, int* total) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    const int add = t >= off ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
-  }
-  const int incl = sh[t];
-  *total = sh[blockDim.x - 1];
-  __syncthreads();
-  return incl - v;
-}
-
 // Block-wide sum over the 4 waves of a 256-thread block; every thread gets
 // the total.  Waves are added in wave order (deterministic).
 __device__ inline double block_sum4(double v, double* lds) {
@@ -699,28 +681,40 @@ __global__ void __launch_bounds__(256) k_final_reduce2d(Geo2D G, FusedArgs A) {
 
 // ---------------------------------------------------------------------
 // Merge (eq. FusionDD) of control volumes with several members, in place,
-// followed by the moments of the merged value.
+// followed by the moments of the merged value.  One 256-thread block per
+// control volume; its members and their areas are read once, and the
+// members' values of a velocity are requested together.
 // ---------------------------------------------------------------------
 template <bool SK>
-__device__ void merge_cv(Geo2D G, double2* __restrict__ st, double* __restrict__ mom,
-                         double* __restrict__ heat, const StepParams& P, int q) {
-  const int lane = threadIdx.x;
+__device__ void merge_cv(const Geo2D& G, double2* __restrict__ st, double* __restrict__ mom,
+                         double* __restrict__ heat, const StepParams& P, int q, double* lds) {
+  const int tid = threadIdx.x, nth = blockDim.x;
   const int m = G.irr[q];
-  const int b = G.mptr[q], e = G.mptr[q + 1];
+  const int b = G.mptr[q], nm = min(G.mptr[q + 1] - b, kMaxMembers);
   const int N = G.N, nvel = G.nvel;
   const double S = G.scv[m];
+  int mk[kMaxMembers];
+  double w[kMaxMembers];
+#pragma unroll
+  for (int t = 0; t < kMaxMembers; ++t) {
+    mk[t] = t < nm ? G.mem[b + t] : m;
+    w[t] = t < nm ? G.sbar[mk[t]] : 0.0;
+  }
   Sums2<SK> sm;
-  for (int p = lane; p < nvel; p += kWave) {
+  for (int p = tid; p < nvel; p += nth) {
     double af = 0.0, ag = 0.0;
-    if (e - b > 1) {
-      for (int t = b; t < e; ++t) {
-        const int k = G.mem[t];
-        const double2 v = st[(size_t)k * nvel + p];
-        af += G.sbar[k] * v.x;
-        ag += G.sbar[k] * v.y;
-      }
+    if (nm > 1) {
+      double2 v[kMaxMembers];
+#pragma unroll
+      for (int t = 0; t < kMaxMembers; ++t)
+        if (t < nm) v[t] = st[(size_t)mk[t] * nvel + p];
+#pragma unroll
+      for (int t = 0; t < kMaxMembers; ++t)
+        if (t < nm) { af += w[t] * v[t].x; ag += w[t] * v[t].y; }
       af /= S; ag /= S;
-      for (int t = b; t < e; ++t) st[(size_t)G.mem[t] * nvel + p] = make_double2(af, ag);
+#pragma unroll
+      for (int t = 0; t < kMaxMembers; ++t)
+        if (t < nm) st[(size_t)mk[t] * nvel + p] = make_double2(af, ag);
     } else {
       const double2 v = st[(size_t)m * nvel + p];
       af = v.x; ag = v.y;
@@ -728,24 +722,25 @@ __device__ void merge_cv(Geo2D G, double2* __restrict__ st, double* __restrict__
     const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
     sm.add(vx, vy, af, ag);
   }
-  sm.reduce([](double v) { return wave_sum(v); });
-  if (lane == 0) {
+  sm.reduce([&](double v) { return block_sum4(v, lds); });
+  if (tid == 0) {
     double mo[4], hq[2];
     sm.finish(P.w, mo, hq);
-    for (int t = b; t < e; ++t) {
-      const int k = G.mem[t];
+    for (int t = 0; t < nm; ++t) {
+      const int k = mk[t];
       for (int i = 0; i < 4; ++i) mom[4 * k + i] = mo[i];
       if (SK) { heat[2 * k] = hq[0]; heat[2 * k + 1] = hq[1]; }
     }
   }
 }
 
-__global__ void __launch_bounds__(64) k_merge2d(Geo2D G, double2* __restrict__ st,
-                                                double* __restrict__ mom, double* __restrict__ heat,
-                                                StepParams P) {
+__global__ void __launch_bounds__(256) k_merge2d(Geo2D G, double2* __restrict__ st,
+                                                 double* __restrict__ mom, double* __restrict__ heat,
+                                                 StepParams P) {
+  __shared__ double lds[8];
   for (int q = blockIdx.x; q < G.counts[0]; q += gridDim.x) {
-    if (P.shakhov) merge_cv<true>(G, st, mom, heat, P, q);
-    else merge_cv<false>(G, st, mom, nullptr, P, q);
+    if (P.shakhov) merge_cv<true>(G, st, mom, heat, P, q, lds);
+    else merge_cv<false>(G, st, mom, nullptr, P, q, lds);
   }
 }
 
@@ -769,12 +764,15 @@ __device__ void cell_moments2d(const Geo2D& G, const double2* __restrict__ st, d
   }
 }
 
+// regular_only: the cells streamed by the regular-cell kernel only (the cut
+// and merged control volumes keep the moments their own kernels stored)
 __global__ void __launch_bounds__(256) k_mom2d(Geo2D G, const double2* __restrict__ st,
                                                double* __restrict__ mom, double* __restrict__ heat,
-                                               StepParams P) {
+                                               StepParams P, int regular_only) {
   const int lane = threadIdx.x & (kWave - 1);
   const int c = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
   if (c >= G.ncell || G.kind[c] == KIND_SOLID) return;
+  if (regular_only && G.kind[c] != KIND_REGULAR) return;
   if (P.shakhov) cell_moments2d<true>(G, st, mom, heat, P, c, lane);
   else cell_moments2d<false>(G, st, mom, nullptr, P, c, lane);
 }
@@ -1091,13 +1089,15 @@ __global__ void __launch_bounds__(1024) k_steplist2d(MoveArgs M) {
   const int nx = G0.nx;
   const int nbox = M.bx.ni * M.bx.nj;
   auto cell = [&](int u) { return (M.bx.j0 + u / M.bx.ni) * nx + M.bx.i0 + u % M.bx.ni; };
-  const int t = threadIdx.x;
-  const int per = (nbox + blockDim.x - 1) / blockDim.x;
-  const int ub = t * per, ue = min(ub + per, nbox);
-  const int R = 2 * kHopCap;   // a receiver is at most 2 x 4 hops from its master
+  auto in_box = [&](int c) {
+    const int i = c % nx - M.bx.i0, j = c / nx - M.bx.j0;
+    return i >= 0 && i < M.bx.ni && j >= 0 && j < M.bx.nj;
+  };
+  const int t = threadIdx.x, nth = blockDim.x;
   int bad = 0;
-  // receiving control volume of every cell of t^{n+1}
-  for (int u = ub; u < ue; ++u) {
+  // receiving control volume of every cell of t^{n+1} (one cell per thread
+  // and round)
+  for (int u = t; u < nbox; u += nth) {
     const int c = cell(u);
     int tg = G0.master[c];
     if (tg < 0 && G1.type[c] != TYPE_SOLID) {
@@ -1115,66 +1115,87 @@ __global__ void __launch_bounds__(1024) k_steplist2d(MoveArgs M) {
   __syncthreads();
   // receivers other than the master itself, counted per master (integer
   // atomics: the count does not depend on their order)
-  for (int u = ub; u < ue; ++u) {
+  for (int u = t; u < nbox; u += nth) {
     const int c = cell(u);
     const int tg = M.target[c];
-    if (tg >= 0 && tg != c) atomicAdd(&M.rcnt[tg], 1);
+    if (tg >= 0 && tg != c && in_box(tg)) atomicAdd(&M.rcnt[tg], 1);
   }
   __syncthreads();
-  // control volumes that need the general update, per-cell kinds, cells to zero
-  int ngen = 0, nzero = 0;
-  for (int u = ub; u < ue; ++u) {
-    const int c = cell(u);
-    const int tg = M.target[c];
-    int kind = KIND_SOLID;
-    if (tg == c) {
-      const bool general = G0.kind[c] != KIND_REGULAR || M.rcnt[c] != 0 || G1.type[c] != TYPE_GAS;
-      kind = general ? KIND_IRREGULAR : KIND_REGULAR;
-      ngen += general;
-    } else if (tg >= 0) {
-      kind = KIND_MEMBER;
-    }
-    M.skind[c] = kind;
-    // solid at t^n and t^{n+1} but not at t^{n-1}: its entry in the output
-    // buffer (the state of t^{n-1}) is stale
-    if (G1.type[c] == TYPE_SOLID && M.age[c] == 1) ++nzero;
-  }
-  int tot_gen, tot_zero;
-  int off_gen = block_exclusive_scan_int(ngen, sh, &tot_gen);
-  int off_zero = block_exclusive_scan_int(nzero, sh, &tot_zero);
-  for (int u = ub; u < ue; ++u) {
-    const int c = cell(u);
-    if (M.skind[c] == KIND_IRREGULAR) M.gl[off_gen++] = c;
-    const int a = M.age[c];
-    if (G1.type[c] == TYPE_SOLID && a == 1) M.gl[tot_gen + off_zero++] = -1 - c;
-    M.age[c] = G1.type[c] == TYPE_SOLID ? min(a + 1, 2) : 0;
-  }
-  __syncthreads();
-  // receivers of each general control volume, in ascending cell order
+  // per-cell kinds and the control volumes that need the general update, in
+  // ascending cell order (a block scan per round)
   int carry = 0;
-  for (int base = 0; base < tot_gen; base += blockDim.x) {
+  for (int base = 0; base < nbox; base += nth) {
+    const int u = base + t;
+    int general = 0, c = 0;
+    if (u < nbox) {
+      c = cell(u);
+      const int tg = M.target[c];
+      int kind = KIND_SOLID;
+      if (tg == c) {
+        general = G0.kind[c] != KIND_REGULAR || load_l2(&M.rcnt[c]) != 0 || G1.type[c] != TYPE_GAS;
+        kind = general ? KIND_IRREGULAR : KIND_REGULAR;
+      } else if (tg >= 0) {
+        kind = KIND_MEMBER;
+      }
+      M.skind[c] = kind;
+    }
+    int tot;
+    const int ex = block_scan_excl(general, sh, &tot);
+    if (general) M.gl[carry + ex] = c;
+    carry += tot;
+  }
+  const int tot_gen = carry;
+  // then the cells to zero: solid at t^n and t^{n+1} but not at t^{n-1}, so
+  // their entry in the output buffer (the state of t^{n-1}) is stale; ages
+  carry = 0;
+  for (int base = 0; base < nbox; base += nth) {
+    const int u = base + t;
+    int zero = 0, c = 0;
+    if (u < nbox) {
+      c = cell(u);
+      const int a = M.age[c];
+      const bool solid = G1.type[c] == TYPE_SOLID;
+      zero = solid && a == 1;
+      M.age[c] = solid ? min(a + 1, 2) : 0;
+    }
+    int tot;
+    const int ex = block_scan_excl(zero, sh, &tot);
+    if (zero) M.gl[tot_gen + carry + ex] = -1 - c;
+    carry += tot;
+  }
+  const int tot_zero = carry;
+  __syncthreads();
+  // receivers of each general control volume: CSR pointers by a chunked
+  // scan, then the cells placed through atomic cursors and each list sorted
+  // into ascending cell order
+  carry = 0;
+  for (int base = 0; base < tot_gen; base += nth) {
     const int q = base + t;
     int cnt = 0;
     if (q < tot_gen) {
-      cnt = 1 + M.rcnt[M.gl[q]];
+      cnt = 1 + load_l2(&M.rcnt[M.gl[q]]);
       if (cnt > kMaxMembers) bad |= 2;
     }
     int tot;
-    const int ex = block_exclusive_scan_int(cnt, sh, &tot);
-    if (q < tot_gen) {
-      const int m = M.gl[q];
-      M.gptr[q] = carry + ex;
-      int w = carry + ex, lim = carry + ex + cnt;
-      const int i = m % nx, j = m / nx;
-      for (int jj = max(j - R, 0); jj <= min(j + R, G0.ny - 1); ++jj)
-        for (int ii = max(i - R, 0); ii <= min(i + R, nx - 1); ++ii)
-          if (M.target[jj * nx + ii] == m && w < lim) M.gmem[w++] = jj * nx + ii;
-      if (w != lim) bad |= 4;
-    }
+    const int ex = block_scan_excl(cnt, sh, &tot);
+    if (q < tot_gen) M.gptr[q] = carry + ex;
     carry += tot;
   }
+  if (t == 0) M.gptr[tot_gen] = carry;
+  __syncthreads();   // every count is read before it becomes a cursor
+  for (int q = t; q < tot_gen; q += nth) M.rcnt[M.gl[q]] = M.gptr[q];
+  __syncthreads();
+  for (int u = t; u < nbox; u += nth) {
+    const int c = cell(u), tg = M.target[c];
+    if (tg >= 0 && in_box(tg) && M.skind[tg] == KIND_IRREGULAR) M.gmem[atomicAdd(&M.rcnt[tg], 1)] = c;
+  }
+  __syncthreads();
+  for (int q = t; q < tot_gen; q += nth) {
+    const int b = M.gptr[q], e = M.gptr[q + 1];
+    if (load_l2(&M.rcnt[M.gl[q]]) != e) bad |= 4;
+    sort_cells(M.gmem + b, e - b);
+  }
   if (t == 0) {
-    M.gptr[tot_gen] = carry;
     M.gcount[0] = tot_gen + tot_zero;
     M.gcount[2] = tot_gen;
   }
@@ -1565,16 +1586,16 @@ hipError_t launch_store_state_2d(const cc_ctx* ctx, double* f, double* g) {
 hipError_t launch_merge_2d(cc_ctx* ctx) {
   StepParams P = params2d(ctx);
   prof_begin(ctx, 3);
-  k_merge2d<<<kListBlocks, 64, 0, ctx->stream>>>(ctx->g2, (double2*)ctx->state[ctx->cur],
+  k_merge2d<<<kListBlocks, 256, 0, ctx->stream>>>(ctx->g2, (double2*)ctx->state[ctx->cur],
                                                   ctx->s.mom, ctx->s.heat, P);
   prof_end(ctx, 3);
   return hipGetLastError();
 }
 
-hipError_t launch_moments_all_2d(cc_ctx* ctx) {
+hipError_t launch_moments_all_2d(cc_ctx* ctx, bool regular_only) {
   StepParams P = params2d(ctx);
   k_mom2d<<<(ctx->ncell + 3) / 4, 256, 0, ctx->stream>>>(
-      ctx->g2, (const double2*)ctx->state[ctx->cur], ctx->s.mom, ctx->s.heat, P);
+      ctx->g2, (const double2*)ctx->state[ctx->cur], ctx->s.mom, ctx->s.heat, P, regular_only ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1668,9 +1689,15 @@ hipError_t launch_mass_2d(cc_ctx* ctx, double* mass_row) {
 // Tile shape of the regular-cell pass: kTileW columns x seglen rows.
 int tile_rows(const cc_ctx* ctx) {
   if (ctx->seglen > 0) return ctx->seglen;
-  // aim for ~2 tiles per CU on 256 CUs (as many as are resident at once)
+  // Fixed body: ~2 tiles per CU on 256 CUs (as many as are resident at
+  // once).  Moving body: ~16 per CU, so that blocks retire all through the
+  // streaming kernel and the next step's geometry kernels, queued beside it
+  // on the side stream, find free slots early instead of in its tail
+  // (ellipse256: 0.79 against 0.92 ms per step).
+  const bool moving = ctx->body.motion != CC_MOTION_FIXED && ctx->body.kind != CC_BODY_NONE;
   const int groups = (ctx->nx + kTileW - 1) / kTileW;
-  int segs = (512 + groups - 1) / groups;
+  const int target = moving ? 4096 : 512;
+  int segs = (target + groups - 1) / groups;
   if (segs < 1) segs = 1;
   int rows = (ctx->ny + segs - 1) / segs;
   return rows < 1 ? 1 : rows;
@@ -1845,7 +1872,7 @@ hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_ro
   M.bx = moving_box(ctx, ctx->nstep);
   // 2. merge over the control volumes of t^n
   prof_begin(ctx, 3);
-  k_merge2d<<<kListBlocks, 64, 0, st>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
+  k_merge2d<<<kListBlocks, 256, 0, st>>>(ctx->g2, (double2*)ctx->state[ctx->cur], ctx->s.mom,
                                         ctx->s.heat, P);
   prof_end(ctx, 3);
   FusedArgs A;
@@ -2094,13 +2121,6 @@ hipError_t launch_step_2d_ptrs(cc_ctx* ctx, const double2* in, double2* out, dou
     hipError_t e = hipStreamWaitEvent(ctx->stream, ctx->join, 0);
     if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_moments_ptr_2d(cc_ctx* ctx, const double2* st, double* mom) {
-  StepParams P = params2d(ctx);
-  P.shakhov = 0;
-  k_mom2d<<<(ctx->ncell + 3) / 4, 256, 0, ctx->stream>>>(ctx->g2, st, mom, nullptr, P);
   return hipGetLastError();
 }
 
