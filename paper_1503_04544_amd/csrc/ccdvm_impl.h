@@ -83,6 +83,9 @@ __device__ inline void sort_cells(int* a, int n) {
   }
 }
 
+// consecutive cells per thread and round in the single-block list builders
+constexpr int kScanPer = 4;
+
 // Exclusive prefix sum of one int per thread over the block (a multiple of
 // 64 threads, at most 1024): a shuffle scan inside each wave, then the wave
 // totals through sh (16 ints), two barriers in all.  *total receives the

@@ -228,8 +228,8 @@ __global__ void k_cv2d(Geo2D G, Box2D bx) {
 
 // Single-block deterministic compaction: list of irregular masters in
 // ascending cell order, CSR of their members (ascending), population counts.
-// The box cells are taken one per thread and round (coalesced), the list by
-// a block scan per round.  Members are counted and placed through integer
+// The box cells are taken kScanPer consecutive ones per thread and round,
+// the list by a block scan per round.  Members are counted and placed through integer
 // atomics on the per-cell scratch, and every member list is then sorted, so
 // the result does not depend on the order of the atomics.
 __global__ void __launch_bounds__(1024) k_compact2d(Geo2D G, Box2D bx) {
@@ -245,15 +245,23 @@ __global__ void __launch_bounds__(1024) k_compact2d(Geo2D G, Box2D bx) {
     return i >= 0 && i < bx.ni && j >= 0 && j < bx.nj && G.kind[m] == KIND_IRREGULAR;
   };
   int carry = 0, nmem = 0, nsol = 0;
-  for (int base = 0; base < nbox; base += nth) {
-    const int u = base + t;
-    int k = -1, c = 0;
-    if (u < nbox) { c = cell(u); k = G.kind[c]; }
-    nmem += k == KIND_MEMBER;
-    nsol += k == KIND_SOLID;
+  for (int base = 0; base < nbox; base += nth * kScanPer) {
+    int c[kScanPer], k[kScanPer], cnt = 0;
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+      const int u = base + t * kScanPer + e;
+      c[e] = 0;
+      k[e] = -1;
+      if (u < nbox) { c[e] = cell(u); k[e] = G.kind[c[e]]; }
+      nmem += k[e] == KIND_MEMBER;
+      nsol += k[e] == KIND_SOLID;
+      cnt += k[e] == KIND_IRREGULAR;
+    }
     int tot;
-    const int ex = block_scan_excl(k == KIND_IRREGULAR ? 1 : 0, sh, &tot);
-    if (k == KIND_IRREGULAR) { G.irr[carry + ex] = c; G.aux[c] = 0; }
+    int w = carry + block_scan_excl(cnt, sh, &tot);
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e)
+      if (k[e] == KIND_IRREGULAR) { G.irr[w++] = c[e]; G.aux[c[e]] = 0; }
     carry += tot;
   }
   const int tot_irr = carry;

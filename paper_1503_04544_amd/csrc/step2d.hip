@@ -1122,45 +1122,62 @@ __global__ void __launch_bounds__(1024) k_steplist2d(MoveArgs M) {
   }
   __syncthreads();
   // per-cell kinds and the control volumes that need the general update, in
-  // ascending cell order (a block scan per round)
+  // ascending cell order (kScanPer consecutive cells per thread, a block scan
+  // per round)
   int carry = 0;
-  for (int base = 0; base < nbox; base += nth) {
-    const int u = base + t;
-    int general = 0, c = 0;
-    if (u < nbox) {
-      c = cell(u);
-      const int tg = M.target[c];
-      int kind = KIND_SOLID;
-      if (tg == c) {
-        general = G0.kind[c] != KIND_REGULAR || load_l2(&M.rcnt[c]) != 0 || G1.type[c] != TYPE_GAS;
-        kind = general ? KIND_IRREGULAR : KIND_REGULAR;
-      } else if (tg >= 0) {
-        kind = KIND_MEMBER;
+  for (int base = 0; base < nbox; base += nth * kScanPer) {
+    int c[kScanPer], general[kScanPer], cnt = 0;
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+      const int u = base + t * kScanPer + e;
+      c[e] = 0;
+      general[e] = 0;
+      if (u < nbox) {
+        c[e] = cell(u);
+        const int tg = M.target[c[e]];
+        int kind = KIND_SOLID;
+        if (tg == c[e]) {
+          general[e] = G0.kind[tg] != KIND_REGULAR || load_l2(&M.rcnt[tg]) != 0 || G1.type[tg] != TYPE_GAS;
+          kind = general[e] ? KIND_IRREGULAR : KIND_REGULAR;
+        } else if (tg >= 0) {
+          kind = KIND_MEMBER;
+        }
+        M.skind[c[e]] = kind;
       }
-      M.skind[c] = kind;
+      cnt += general[e];
     }
     int tot;
-    const int ex = block_scan_excl(general, sh, &tot);
-    if (general) M.gl[carry + ex] = c;
+    int w = carry + block_scan_excl(cnt, sh, &tot);
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e)
+      if (general[e]) M.gl[w++] = c[e];
     carry += tot;
   }
   const int tot_gen = carry;
   // then the cells to zero: solid at t^n and t^{n+1} but not at t^{n-1}, so
   // their entry in the output buffer (the state of t^{n-1}) is stale; ages
   carry = 0;
-  for (int base = 0; base < nbox; base += nth) {
-    const int u = base + t;
-    int zero = 0, c = 0;
-    if (u < nbox) {
-      c = cell(u);
-      const int a = M.age[c];
-      const bool solid = G1.type[c] == TYPE_SOLID;
-      zero = solid && a == 1;
-      M.age[c] = solid ? min(a + 1, 2) : 0;
+  for (int base = 0; base < nbox; base += nth * kScanPer) {
+    int c[kScanPer], zero[kScanPer], cnt = 0;
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+      const int u = base + t * kScanPer + e;
+      c[e] = 0;
+      zero[e] = 0;
+      if (u < nbox) {
+        c[e] = cell(u);
+        const int a = M.age[c[e]];
+        const bool solid = G1.type[c[e]] == TYPE_SOLID;
+        zero[e] = solid && a == 1;
+        M.age[c[e]] = solid ? min(a + 1, 2) : 0;
+      }
+      cnt += zero[e];
     }
     int tot;
-    const int ex = block_scan_excl(zero, sh, &tot);
-    if (zero) M.gl[tot_gen + carry + ex] = -1 - c;
+    int w = tot_gen + carry + block_scan_excl(cnt, sh, &tot);
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e)
+      if (zero[e]) M.gl[w++] = -1 - c[e];
     carry += tot;
   }
   const int tot_zero = carry;
