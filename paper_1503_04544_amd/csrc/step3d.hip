@@ -720,12 +720,6 @@ struct Cut3Params {
   int relax;            // 0: transport only (semi-implicit step)
 };
 
-__device__ inline double maxw3(double rho, double ux, double uy, double uz, double T, double vx,
-                               double vy, double vz) {
-  const double ex = vx - ux, ey = vy - uy, ez = vz - uz;
-  return rho / pow(2.0 * M_PI * T, 1.5) * exp(-(ex * ex + ey * ey + ez * ez) / (2.0 * T));
-}
-
 // One control volume that is cut or owns merged cells: wall density of each
 // wall face (zero net mass flux, Section 5), fluxes through the six
 // Cartesian faces and the wall face of every member, explicit update with
@@ -733,6 +727,10 @@ __device__ inline double maxw3(double rho, double ux, double uy, double uz, doub
 // k_mom3d), redistribution to the members, the moment sums of the new value
 // (chunk slot 0) for the next record; wall stress -> force of the state at
 // t^n.  write_state == 0: force only.
+// Both Maxwellians are separable: their per-axis factors (N exponentials
+// each) and the members' faces are set up in LDS once per block, so the
+// velocity loops read tables instead of evaluating exponentials.
+constexpr int kMaxN3 = 16;   // largest velocity nodes per axis of the 3D kernels
 template <bool SK>
 __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict__ in,
                                               double* __restrict__ out, double* __restrict__ fslot,
@@ -740,10 +738,15 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
                                               double* __restrict__ part, int nch, Cut3Params P) {
   constexpr int K = Sums3<SK>::K;
   __shared__ double lds[4];
+  __shared__ double wf[kMaxN3];                  // exp(-v^2 / (2 T_w))
+  __shared__ double ef[3][kMaxN3];               // exp(-(v - u_d)^2 / (2 T))
+  __shared__ double mS[kMaxMembers][6];          // members' Cartesian face areas
+  __shared__ long long mnb[kMaxMembers][6];      // upwind neighbour's cell, -1: farfield
+  __shared__ double mw[kMaxMembers][5];          // wall area, normal, density
   const int tid = threadIdx.x, nth = blockDim.x;
   const int q = blockIdx.x;
   const int m = G.irr[q];
-  const int b = G.mptr[q], nm = G.mptr[q + 1] - b;
+  const int b = G.mptr[q], nm = min(G.mptr[q + 1] - b, kMaxMembers);
   const int N = G.N, nvel = G.nvel, nx = G.nx, ny = G.ny, nz = G.nz;
   const double* own = in + (size_t)m * nvel;
   const double* rec = mom + 8 * (size_t)m;
@@ -752,60 +755,82 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
   const double* qt = SK ? heat + 3 * (size_t)m : nullptr;
   const double V = G.vcv[m];
   const double Tw = P.t_wall;
-  double phiw[kMaxMembers];
+  const double cw = 1.0 / pow(2.0 * M_PI * Tw, 1.5);   // wall Maxwellian of unit density
+  if (tid < N) {
+    const double v = vnode3(P.vmin, P.dv, tid);
+    wf[tid] = exp(-(v * v) / (2.0 * Tw));
+    ef[0][tid] = exp(-(v - ux) * (v - ux) * inv2T);
+    ef[1][tid] = exp(-(v - uy) * (v - uy) * inv2T);
+    ef[2][tid] = exp(-(v - uz) * (v - uz) * inv2T);
+  }
+  if (tid < nm) {
+    const int k = G.mem[b + tid];
+    const int i = k % nx, j = (k / nx) % ny, kk = k / (nx * ny);
+    const bool inside[6] = {i > 0, i + 1 < nx, j > 0, j + 1 < ny, kk > 0, kk + 1 < nz};
+    const long long stride[3] = {1, nx, (long long)nx * ny};
+    const double S[6] = {G.sxm[k], G.sxp[k], G.sym[k], G.syp[k], G.szm[k], G.szp[k]};
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      mS[tid][f] = S[f];
+      mnb[tid][f] = inside[f] ? k + ((f & 1) ? stride[f >> 1] : -stride[f >> 1]) : -1;
+    }
+    mw[tid][0] = G.aw[k];
+    mw[tid][1] = G.nwx[k];
+    mw[tid][2] = G.nwy[k];
+    mw[tid][3] = G.nwz[k];
+    mw[tid][4] = 0.0;
+  }
+  __syncthreads();
   for (int t = 0; t < nm; ++t) {
-    const int k = G.mem[b + t];
-    phiw[t] = 0.0;
-    if (!(G.aw[k] > 0.0)) continue;
-    const double n0 = G.nwx[k], n1 = G.nwy[k], n2 = G.nwz[k];
+    if (!(mw[t][0] > 0.0)) continue;
+    const double n0 = mw[t][1], n1 = mw[t][2], n2 = mw[t][3];
     double num = 0.0, den = 0.0;
     for (int p = tid; p < nvel; p += nth) {
-      const double vx = vnode3(P.vmin, P.dv, p % N), vy = vnode3(P.vmin, P.dv, (p / N) % N),
-                   vz = vnode3(P.vmin, P.dv, p / (N * N));
+      const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
+      const double vx = vnode3(P.vmin, P.dv, p1), vy = vnode3(P.vmin, P.dv, p2), vz = vnode3(P.vmin, P.dv, p3);
       const double cn = vx * n0 + vy * n1 + vz * n2;
       if (cn > 0.0) num += cn * own[p];
-      else if (cn < 0.0) den += cn * maxw3(1.0, 0.0, 0.0, 0.0, Tw, vx, vy, vz);
+      else if (cn < 0.0) den += cn * (cw * (wf[p1] * wf[p2] * wf[p3]));
     }
     num = block_sum(num, lds);
     den = block_sum(den, lds);
-    phiw[t] = den != 0.0 ? -num / den : 0.0;
+    if (tid == 0) mw[t][4] = den != 0.0 ? -num / den : 0.0;
   }
-  double sx[kMaxMembers], sy[kMaxMembers], sz[kMaxMembers];
-  for (int t = 0; t < kMaxMembers; ++t) { sx[t] = 0.0; sy[t] = 0.0; sz[t] = 0.0; }
+  __syncthreads();
+  double Fx = 0.0, Fy = 0.0, Fz = 0.0;
   Sums3<SK> sm;
   for (int p = tid; p < nvel; p += nth) {
-    const double v[3] = {vnode3(P.vmin, P.dv, p % N), vnode3(P.vmin, P.dv, (p / N) % N),
-                         vnode3(P.vmin, P.dv, p / (N * N))};
+    const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
+    const double v[3] = {vnode3(P.vmin, P.dv, p1), vnode3(P.vmin, P.dv, p2), vnode3(P.vmin, P.dv, p3)};
     const double fo = own[p];
+    const double Mw = cw * (wf[p1] * wf[p2] * wf[p3]);
     double Rs = 0.0;
     for (int t = 0; t < nm; ++t) {
-      const int k = G.mem[b + t];
-      const int i = k % nx, j = (k / nx) % ny, kk = k / (nx * ny);
-      const double S[6] = {G.sxm[k], G.sxp[k], G.sym[k], G.syp[k], G.szm[k], G.szp[k]};
-      const bool inside[6] = {i > 0, i + 1 < nx, j > 0, j + 1 < ny, kk > 0, kk + 1 < nz};
-      const long long stride[3] = {1, nx, (long long)nx * ny};
+#pragma unroll
       for (int f = 0; f < 6; ++f) {
-        if (!(S[f] > 0.0)) continue;
+        const double S = mS[t][f];
+        if (!(S > 0.0)) continue;
         const int d = f >> 1;
         const double cvel = (f & 1) ? v[d] : -v[d];   // outward normal velocity
-        const double fn = inside[f] ? in[(size_t)(k + ((f & 1) ? stride[d] : -stride[d])) * nvel + p]
-                                    : G.ghost[p];
-        Rs += S[f] * (fmax(cvel, 0.0) * fo + fmin(cvel, 0.0) * fn);
+        const long long nb = mnb[t][f];
+        const double fn = nb >= 0 ? in[(size_t)nb * nvel + p] : G.ghost[p];
+        Rs += S * (fmax(cvel, 0.0) * fo + fmin(cvel, 0.0) * fn);
       }
-      const double aw = G.aw[k];
+      const double aw = mw[t][0];
       if (aw > 0.0) {
-        const double cn = v[0] * G.nwx[k] + v[1] * G.nwy[k] + v[2] * G.nwz[k];
-        const double fw = phiw[t] * maxw3(1.0, 0.0, 0.0, 0.0, Tw, v[0], v[1], v[2]);
+        const double cn = v[0] * mw[t][1] + v[1] * mw[t][2] + v[2] * mw[t][3];
+        const double fw = mw[t][4] * Mw;
         Rs += aw * (fmin(cn, 0.0) * fw + fmax(cn, 0.0) * fo);
         const double fv = cn < 0.0 ? fw : (cn > 0.0 ? fo : 0.0);
-        sx[t] += v[0] * cn * fv;
-        sy[t] += v[1] * cn * fv;
-        sz[t] += v[2] * cn * fv;
+        const double s = aw * cn * fv;
+        Fx += v[0] * s;
+        Fy += v[1] * s;
+        Fz += v[2] * s;
       }
     }
     if (P.write_state) {
       const double cx = v[0] - ux, cy = v[1] - uy, cz = v[2] - uz;
-      double E = nu != 0.0 ? Am * exp(-(cx * cx + cy * cy + cz * cz) * inv2T) : 0.0;
+      double E = nu != 0.0 ? Am * (ef[0][p1] * ef[1][p2] * ef[2][p3]) : 0.0;
       if (SK && nu != 0.0) E = shakhov3(qt, 2.0 * inv2T, cx, cy, cz, E);
       const double fn = fo - P.dt / V * Rs + nu * (E - fo);
       for (int t = 0; t < nm; ++t) out[(size_t)G.mem[b + t] * nvel + p] = fn;
@@ -820,16 +845,9 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
     if (tid == 0)
       for (int k = 0; k < K; ++k) pp[k] = sm.s[k];
   }
-  double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-  for (int t = 0; t < nm; ++t) {
-    const int k = G.mem[b + t];
-    if (!(G.aw[k] > 0.0)) continue;
-    const double ax = block_sum(sx[t], lds) * P.w, ay = block_sum(sy[t], lds) * P.w,
-                 az = block_sum(sz[t], lds) * P.w;
-    Fx += ax * G.aw[k];
-    Fy += ay * G.aw[k];
-    Fz += az * G.aw[k];
-  }
+  Fx = block_sum(Fx, lds) * P.w;
+  Fy = block_sum(Fy, lds) * P.w;
+  Fz = block_sum(Fz, lds) * P.w;
   if (tid == 0) {
     fslot[3 * q + 0] = Fx;
     fslot[3 * q + 1] = Fy;
