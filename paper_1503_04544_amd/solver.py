@@ -198,17 +198,27 @@ class Solver:
         self._check(lib().cc_geometry_counts(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
 
-    def adjoint(self, nsteps: int, ckpt_every: int = 16, objective: str = "drag"):
+    def adjoint(self, nsteps: int, ckpt_every: int = 16, objective: str = "drag", pool=None):
         """J and dJ/d(T_w, Kn, Ma) of the drag or torque after nsteps from the
-        inflow Maxwellian (hand-written adjoint with checkpointing)."""
+        inflow Maxwellian (hand-written adjoint with checkpointing).  pool: a
+        device uint8 tensor of at least adjoint_workspace_bytes() bytes to
+        use, else one is allocated for the call."""
         nb = C.c_size_t()
         self._check(lib().cc_adjoint_workspace_bytes(self._h, int(nsteps), int(ckpt_every), C.byref(nb)))
-        pool = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        if pool is None:
+            pool = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        elif pool.numel() < nb.value:
+            raise ValueError(f"adjoint pool of {pool.numel()} bytes, {nb.value} needed")
         out = (C.c_double * 4)()
         self._check(lib().cc_adjoint(self._h, int(nsteps), int(ckpt_every),
                                      0 if objective == "drag" else 1, _ptr(pool), out))
-        del pool
         return out[0], np.array(out[1:])
+
+    def adjoint_workspace_bytes(self, nsteps: int, ckpt_every: int = 16) -> int:
+        """Bytes of the device pool adjoint() allocates (cc_adjoint_workspace_bytes)."""
+        nb = C.c_size_t()
+        self._check(lib().cc_adjoint_workspace_bytes(self._h, int(nsteps), int(ckpt_every), C.byref(nb)))
+        return nb.value
 
     def set_tile_rows(self, rows: int):
         self._check(lib().cc_set_tile_rows(self._h, int(rows)))
@@ -261,18 +271,25 @@ class Batch:
     def step(self, nsteps: int = 1):
         self._check(lib().cc_batch_step(self._h, int(nsteps)))
 
-    def adjoint(self, nsteps: int, ckpt_every: int = 16, objective: str = "drag"):
-        """Solver.adjoint for every instance at once (cc_batch_adjoint):
-        J (n,) and dJ/d(T_w, Kn, Ma) (n, 3), each instance from its inflow
-        Maxwellian."""
+    def adjoint_workspace_bytes(self, nsteps: int, ckpt_every: int = 16) -> int:
         nb = C.c_size_t()
         self._check(lib().cc_batch_adjoint_workspace_bytes(self._h, int(nsteps), int(ckpt_every), C.byref(nb)))
-        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.solvers[0].device)
+        return nb.value
+
+    def adjoint(self, nsteps: int, ckpt_every: int = 16, objective: str = "drag", workspace=None):
+        """Solver.adjoint for every instance at once (cc_batch_adjoint):
+        J (n,) and dJ/d(T_w, Kn, Ma) (n, 3), each instance from its inflow
+        Maxwellian.  workspace: a device uint8 tensor of at least
+        adjoint_workspace_bytes() bytes to use, else one is allocated."""
+        nb = self.adjoint_workspace_bytes(nsteps, ckpt_every)
+        if workspace is None:
+            workspace = torch.empty(nb, dtype=torch.uint8, device=self.solvers[0].device)
+        elif workspace.numel() < nb:
+            raise ValueError(f"batched adjoint workspace of {workspace.numel()} bytes, {nb} needed")
         n = len(self.solvers)
         out = (C.c_double * (4 * n))()
         self._check(lib().cc_batch_adjoint(self._h, int(nsteps), int(ckpt_every),
-                                           0 if objective == "drag" else 1, _ptr(ws), out))
-        del ws
+                                           0 if objective == "drag" else 1, _ptr(workspace), out))
         a = np.array(out[:]).reshape(n, 4)
         return a[:, 0].copy(), a[:, 1:].copy()
 
