@@ -201,3 +201,24 @@ def test_saddle_geometry_rejected_by_bind():
     with pytest.raises(CCError) as e:
         solver(cfg)
     assert e.value.status == -3
+
+
+@pytest.mark.parametrize("nv,model,steps", [(40, "bgk", 20), (48, "bgk", 8), (40, "shakhov", 8)])
+def test_two_waves_per_tile_column(nv, model, steps):
+    """Velocity grids with more than 8 chunks per half-row, streamed by two
+    waves per tile column (the second handing its moment sums to the first
+    through LDS at the next row barrier; N = 48 also without the LDS
+    exchange of the lower halves): several steps from the inflow Maxwellian
+    on a ragged grid, state and drag rows against the oracle."""
+    cfg = small_2d(22, 18, nv, kn=0.08, mach=0.6,
+                   body=Body("circle", (0.47, 0.52, 0), (0.21, 0.21, 0), t_wall=1.2)).with_(model=model)
+    s = solver(cfg)
+    s.init_maxwellian()
+    d = s.step(steps, diag=True).cpu().numpy()
+    f1, g1 = (t.cpu().numpy() for t in s.store_state())
+    o = Oracle2D(cfg)
+    fo, go, do = o.run(*o.init(), steps)
+    assert relerr(f1, fo) < 1e-10
+    assert relerr(g1, go) < 1e-10
+    assert np.max(np.abs(d[:, 0] - do[:, 0]) / np.abs(do[:, 0])) < 1e-9
+    assert np.max(np.abs(d[:, 3] - do[:, 3]) / np.abs(do[:, 3])) < 1e-10
