@@ -204,12 +204,12 @@ def test_saddle_geometry_rejected_by_bind():
 
 
 @pytest.mark.parametrize("nv,model,steps", [(40, "bgk", 20), (48, "bgk", 8), (40, "shakhov", 8)])
-def test_two_waves_per_tile_column(nv, model, steps):
-    """Velocity grids with more than 8 chunks per half-row, streamed by two
-    waves per tile column (the second handing its moment sums to the first
-    through LDS at the next row barrier; N = 48 also without the LDS
-    exchange of the lower halves): several steps from the inflow Maxwellian
-    on a ragged grid, state and drag rows against the oracle."""
+def test_velocity_grids_above_eight_chunks(nv, model, steps):
+    """Velocity grids with more than 8 chunks of 64 velocities per half-row
+    (N = 40: 13 chunks, prefetch 2 deep; N = 48: 18 chunks, without the LDS
+    exchange of the lower halves; Shakhov at N = 40): several steps from the
+    inflow Maxwellian on a ragged grid, state and drag rows against the
+    oracle."""
     cfg = small_2d(22, 18, nv, kn=0.08, mach=0.6,
                    body=Body("circle", (0.47, 0.52, 0), (0.21, 0.21, 0), t_wall=1.2)).with_(model=model)
     s = solver(cfg)
