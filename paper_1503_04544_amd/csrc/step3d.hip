@@ -789,7 +789,8 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
       const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
       const double vx = vnode3(P.vmin, P.dv, p1), vy = vnode3(P.vmin, P.dv, p2), vz = vnode3(P.vmin, P.dv, p3);
       const double cn = vx * n0 + vy * n1 + vz * n2;
-      if (cn > 0.0) num += cn * own[p];
+      const double o = own[p];
+      if (cn > 0.0) num += cn * o;
       else if (cn < 0.0) den += cn * (cw * (wf[p1] * wf[p2] * wf[p3]));
     }
     num = block_sum(num, lds);
@@ -806,15 +807,21 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
     const double Mw = cw * (wf[p1] * wf[p2] * wf[p3]);
     double Rs = 0.0;
     for (int t = 0; t < nm; ++t) {
+      // the six faces' upwind values are requested together (a closed face
+      // reads the cell's own value and adds a zero term)
+      double fn[6];
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
-        const double S = mS[t][f];
-        if (!(S > 0.0)) continue;
+        const long long nb = mnb[t][f];
+        const double* src = !(mS[t][f] > 0.0) ? own : (nb >= 0 ? in + (size_t)nb * nvel : G.ghost);
+        fn[f] = src[p];
+      }
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        const double S = mS[t][f] > 0.0 ? mS[t][f] : 0.0;
         const int d = f >> 1;
         const double cvel = (f & 1) ? v[d] : -v[d];   // outward normal velocity
-        const long long nb = mnb[t][f];
-        const double fn = nb >= 0 ? in[(size_t)nb * nvel + p] : G.ghost[p];
-        Rs += S * (fmax(cvel, 0.0) * fo + fmin(cvel, 0.0) * fn);
+        Rs += S * (fmax(cvel, 0.0) * fo + fmin(cvel, 0.0) * fn[f]);
       }
       const double aw = mw[t][0];
       if (aw > 0.0) {
