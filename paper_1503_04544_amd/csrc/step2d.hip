@@ -61,10 +61,7 @@ __device__ inline void wall_velocity(const double* body, double rx, double ry, d
   *uwy = body[4] + (rx - body[0]) * body[5];
 }
 
-__device__ inline double maxw_wall(double vx, double vy, double uwx, double uwy, double Tw) {
-  double ex = vx - uwx, ey = vy - uwy;
-  return exp(-(ex * ex + ey * ey) / (2.0 * Tw)) / (2.0 * M_PI * Tw);
-}
+constexpr int kMaxN2 = 64;  // largest number of velocity nodes per axis
 
 // Velocity sums of one control volume's (f, g), from which eq.
 // (MacroscopicDDv) gives rho, u, T and, with SK, the heat flux.  q is
@@ -130,54 +127,121 @@ __device__ inline double block_sum4(double v, double* lds) {
   return ((lds[0] + lds[1]) + lds[2]) + lds[3];
 }
 
+// Block-wide sums of two values at once (same order as block_sum4).
+__device__ inline void block_sum4x2(double& a, double& b, double* lds) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { lds[wave] = a; lds[4 + wave] = b; }
+  __syncthreads();
+  a = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+  b = ((lds[4] + lds[5]) + lds[6]) + lds[7];
+}
+
+// One control volume's members, staged in LDS by the block that updates
+// it: the rows read through each member's four edges (the volume's own row
+// where an edge is closed; its open length is then 0), the rows it writes,
+// and its wall edges with the per-axis factors of their Maxwellians
+// (exp(-(v - u_w)^2 / 2T_w) along each axis, so M_w = c_w fx[p1] fy[p2]).
+struct CvStage {
+  const double2* src[kMaxMembers][4];   // +x, -x, +y, -y
+  double len[kMaxMembers][4];
+  double2* dst[kMaxMembers];            // nullptr: not written
+  int live[kMaxMembers];                // 0: written as zero (cell now solid)
+  double wall[kMaxMembers][8];          // L_w, n_w, u_w, r_w - centre, phi_w
+  double wfx[kMaxMembers][kMaxN2], wfy[kMaxMembers][kMaxN2];
+  double eqx[kMaxN2], eqy[kMaxN2];      // per-axis factors of the volume's Maxwellian
+  double red[8];
+  int nwall;
+};
+
 // ---------------------------------------------------------------------
-// One control volume that is cut or owns merged cells, by a block of 256
-// threads (velocities strided over the block).  Wall density of each wall
-// edge (eq. BoundaryDDv), fluxes of all members' edges (eq. FluxDD), the
-// explicit update with relaxation (eq. ExSchemeDD), redistribution to all
-// members (eq. UpdateDD), wall stress -> force and torque of the state at
-// t^n (eqs. StressTensorDD, eq-force, eq-torque), moments and mass of the
-// new value.  With write_state == 0 only the force is produced.
+// The update of one control volume that is cut or owns merged cells, by a
+// block of 256 threads (velocities strided over the block).  Wall density
+// of each wall edge (eq. BoundaryDDv), fluxes of all members' edges (eq.
+// FluxDD), the explicit update with relaxation (eq. ExSchemeDD; ratio and
+// dts carry the area change of a moving body, eq. UpdateDD-m), the new
+// value written to every member (eq. UpdateDD), the wall stress of the
+// state at t^n summed into force and torque (eqs. StressTensorDD,
+// eq-force, eq-torque) and the velocity sums of the new value.  The
+// caller has staged dst and live of each member.
 // ---------------------------------------------------------------------
 template <bool SK>
-__device__ void cut_cv(const Geo2D& G, const double2* __restrict__ in, double2* __restrict__ out,
-                       double* __restrict__ mom, double* __restrict__ heat, double* __restrict__ fslot,
-                       double* __restrict__ mpart, const double* __restrict__ body,
-                       const StepParams& P, int q, double* lds) {
+__device__ void cv_update(CvStage& cs, const Geo2D& G, const int* __restrict__ mem, int nm,
+                          const double2* __restrict__ in, const double2* __restrict__ own,
+                          const double* __restrict__ body, const StepParams& P, double rho,
+                          double ux, double uy, double T, double qx, double qy, double dtau,
+                          double ratio, double dts,
+                          Sums2<SK>& sm, double& Fx, double& Fy, double& Tq) {
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int m = G.irr[q];
-  const int b = G.mptr[q], e = G.mptr[q + 1];
-  const int nm = e - b;
   const int N = G.N, nvel = G.nvel, nx = G.nx, ny = G.ny;
-  const double rho = mom[4 * m + 0], ux = mom[4 * m + 1], uy = mom[4 * m + 2], T = mom[4 * m + 3];
   const double inv2T = 0.5 / T, A = rho / (2.0 * M_PI * T);
-  const double dtau = P.tau_coef > 0.0 && !P.implicit ? P.dt * rho / P.tau_coef : 0.0;
-  const double qx = SK ? heat[2 * m] : 0.0, qy = SK ? heat[2 * m + 1] : 0.0;
   const double ska = SK ? P.sk_coef / (rho * T * T) : 0.0;
-  const double S = G.scv[m];
-  const double2* own = in + (size_t)m * nvel;
-  const double Tw = P.t_wall;
-  double phiw[kMaxMembers], uwx[kMaxMembers], uwy[kMaxMembers];
-  for (int t = 0; t < nm; ++t) {
-    const int k = G.mem[b + t];
-    phiw[t] = 0.0; uwx[t] = 0.0; uwy[t] = 0.0;
-    if (!(G.lw[k] > 0.0)) continue;
-    wall_velocity(body, G.rwx[k], G.rwy[k], &uwx[t], &uwy[t]);
-    const double nwx = G.nwx[k], nwy = G.nwy[k];
+  const double Tw = P.t_wall, cw = 1.0 / (2.0 * M_PI * Tw), inv2Tw = 0.5 / Tw;
+  if (tid < kWave) {
+    const int t = tid;
+    const int k = t < nm ? mem[t] : 0;
+    const bool isw = t < nm && G.lw[k] > 0.0;
+    const unsigned long long wm = __ballot(isw);
+    if (t < nm) {
+      const int i = k % nx, j = k / nx;
+      const double Lr = G.lxp[k], Ll = G.lxm[k], Lt = G.lyp[k], Lb = G.lym[k];
+      cs.src[t][0] = Lr > 0.0 ? (i + 1 < nx ? in + (size_t)(k + 1) * nvel : G.ghost) : own;
+      cs.src[t][1] = Ll > 0.0 ? (i > 0 ? in + (size_t)(k - 1) * nvel : G.ghost) : own;
+      cs.src[t][2] = Lt > 0.0 ? (j + 1 < ny ? in + (size_t)(k + nx) * nvel : G.ghost) : own;
+      cs.src[t][3] = Lb > 0.0 ? (j > 0 ? in + (size_t)(k - nx) * nvel : G.ghost) : own;
+      cs.len[t][0] = Lr > 0.0 ? Lr : 0.0;
+      cs.len[t][1] = Ll > 0.0 ? Ll : 0.0;
+      cs.len[t][2] = Lt > 0.0 ? Lt : 0.0;
+      cs.len[t][3] = Lb > 0.0 ? Lb : 0.0;
+    }
+    if (isw) {
+      const int u = __popcll(wm & ((1ull << t) - 1));
+      double uwx, uwy;
+      const double rx = G.rwx[k], ry = G.rwy[k];
+      wall_velocity(body, rx, ry, &uwx, &uwy);
+      double* wd = cs.wall[u];
+      wd[0] = G.lw[k]; wd[1] = G.nwx[k]; wd[2] = G.nwy[k];
+      wd[3] = uwx; wd[4] = uwy; wd[5] = rx - body[0]; wd[6] = ry - body[1];
+    }
+    if (t == 0) cs.nwall = __popcll(wm);
+  }
+  __syncthreads();
+  const int nwall = cs.nwall;
+  for (int a = tid; a < nwall * N; a += nth) {
+    const int u = a / N, c = a % N;
+    const double v = vnode(P.vmin, P.dv, c);
+    const double ex = v - cs.wall[u][3], ey = v - cs.wall[u][4];
+    cs.wfx[u][c] = exp(-ex * ex * inv2Tw);
+    cs.wfy[u][c] = exp(-ey * ey * inv2Tw);
+  }
+  if (dtau != 0.0)
+    for (int a = tid; a < N; a += nth) {
+      const double v = vnode(P.vmin, P.dv, a);
+      const double ex = v - ux, ey = v - uy;
+      cs.eqx[a] = exp(-ex * ex * inv2T);
+      cs.eqy[a] = exp(-ey * ey * inv2T);
+    }
+  __syncthreads();
+  // wall density of each wall edge: no net mass through it (eq. BoundaryDDv)
+  for (int u = 0; u < nwall; ++u) {
+    const double nwx = cs.wall[u][1], nwy = cs.wall[u][2], uwx = cs.wall[u][3], uwy = cs.wall[u][4];
     double num = 0.0, den = 0.0;
     for (int p = tid; p < nvel; p += nth) {
-      const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
-      const double cn = (vx - uwx[t]) * nwx + (vy - uwy[t]) * nwy;
-      if (cn > 0.0) num += cn * own[p].x;
-      else if (cn < 0.0) den += cn * maxw_wall(vx, vy, uwx[t], uwy[t], Tw);
+      const int p1 = p % N, p2 = p / N;
+      const double vx = vnode(P.vmin, P.dv, p1), vy = vnode(P.vmin, P.dv, p2);
+      const double cn = (vx - uwx) * nwx + (vy - uwy) * nwy;
+      const double fo = own[p].x;
+      const double Mw = cw * cs.wfx[u][p1] * cs.wfy[u][p2];
+      num += cn > 0.0 ? cn * fo : 0.0;
+      den += cn < 0.0 ? cn * Mw : 0.0;
     }
-    num = block_sum4(num, lds);
-    den = block_sum4(den, lds);
-    phiw[t] = den != 0.0 ? -num / den : 0.0;
+    block_sum4x2(num, den, cs.red);
+    if (tid == 0) cs.wall[u][7] = den != 0.0 ? -num / den : 0.0;
   }
-  double sx[kMaxMembers], sy[kMaxMembers];
-  for (int t = 0; t < kMaxMembers; ++t) { sx[t] = 0.0; sy[t] = 0.0; }
-  Sums2<SK> sm;
+  __syncthreads();
+  double fx = 0.0, fy = 0.0, tq = 0.0;
   for (int p = tid; p < nvel; p += nth) {
     const int p1 = p % N, p2 = p / N;
     const double vx = vnode(P.vmin, P.dv, p1), vy = vnode(P.vmin, P.dv, p2);
@@ -186,65 +250,78 @@ __device__ void cut_cv(const Geo2D& G, const double2* __restrict__ in, double2* 
     const double2 o = own[p];
     double Rf = 0.0, Rg = 0.0;
     for (int t = 0; t < nm; ++t) {
-      const int k = G.mem[b + t];
-      const int i = k % nx, j = k / nx;
-      const double Lr = G.lxp[k], Ll = G.lxm[k], Lt = G.lyp[k], Lb = G.lym[k];
-      if (Lr > 0.0) {
-        const double2 nb = i + 1 < nx ? in[(size_t)(k + 1) * nvel + p] : G.ghost[p];
-        Rf += Lr * (vxm * nb.x + vxp * o.x);
-        Rg += Lr * (vxm * nb.y + vxp * o.y);
-      }
-      if (Ll > 0.0) {
-        const double2 nb = i > 0 ? in[(size_t)(k - 1) * nvel + p] : G.ghost[p];
-        Rf -= Ll * (vxm * o.x + vxp * nb.x);
-        Rg -= Ll * (vxm * o.y + vxp * nb.y);
-      }
-      if (Lt > 0.0) {
-        const double2 nb = j + 1 < ny ? in[(size_t)(k + nx) * nvel + p] : G.ghost[p];
-        Rf += Lt * (vym * nb.x + vyp * o.x);
-        Rg += Lt * (vym * nb.y + vyp * o.y);
-      }
-      if (Lb > 0.0) {
-        const double2 nb = j > 0 ? in[(size_t)(k - nx) * nvel + p] : G.ghost[p];
-        Rf -= Lb * (vym * o.x + vyp * nb.x);
-        Rg -= Lb * (vym * o.y + vyp * nb.y);
-      }
-      const double Lw = G.lw[k];
-      if (Lw > 0.0) {
-        const double cx_ = vx - uwx[t], cy_ = vy - uwy[t];
-        const double cn = cx_ * G.nwx[k] + cy_ * G.nwy[k];
-        const double Mw = maxw_wall(vx, vy, uwx[t], uwy[t], Tw);
-        const double fw = phiw[t] * Mw, gw = phiw[t] * 0.5 * Tw * Mw;
-        Rf += Lw * (fmin(cn, 0.0) * fw + fmax(cn, 0.0) * o.x);
-        Rg += Lw * (fmin(cn, 0.0) * gw + fmax(cn, 0.0) * o.y);
-        const double fv = cn < 0.0 ? fw : (cn > 0.0 ? o.x : 0.0);
-        sx[t] += cx_ * cn * fv;
-        sy[t] += cy_ * cn * fv;
-      }
+      const double2 nr = cs.src[t][0][p], nl = cs.src[t][1][p];
+      const double2 nt = cs.src[t][2][p], nb = cs.src[t][3][p];
+      const double wr = cs.len[t][0], wl = cs.len[t][1], wt = cs.len[t][2], wb = cs.len[t][3];
+      Rf += wr * (vxm * nr.x + vxp * o.x);
+      Rg += wr * (vxm * nr.y + vxp * o.y);
+      Rf -= wl * (vxm * o.x + vxp * nl.x);
+      Rg -= wl * (vxm * o.y + vxp * nl.y);
+      Rf += wt * (vym * nt.x + vyp * o.x);
+      Rg += wt * (vym * nt.y + vyp * o.y);
+      Rf -= wb * (vym * o.x + vyp * nb.x);
+      Rg -= wb * (vym * o.y + vyp * nb.y);
+    }
+    for (int u = 0; u < nwall; ++u) {
+      const double* wd = cs.wall[u];
+      const double Lw = wd[0];
+      const double cx_ = vx - wd[3], cy_ = vy - wd[4];
+      const double cn = cx_ * wd[1] + cy_ * wd[2];
+      const double Mw = cw * cs.wfx[u][p1] * cs.wfy[u][p2];
+      const double fw = wd[7] * Mw, gw = wd[7] * 0.5 * Tw * Mw;
+      Rf += Lw * (fmin(cn, 0.0) * fw + fmax(cn, 0.0) * o.x);
+      Rg += Lw * (fmin(cn, 0.0) * gw + fmax(cn, 0.0) * o.y);
+      const double fv = cn < 0.0 ? fw : (cn > 0.0 ? o.x : 0.0);
+      const double sw = Lw * cn * fv;
+      fx += cx_ * sw;
+      fy += cy_ * sw;
+      tq += (wd[5] * cy_ - wd[6] * cx_) * sw;
     }
     double E = 0.0, Eg = 0.0;
     if (dtau != 0.0) {
-      const double ex = vx - ux, ey = vy - uy;
-      E = A * exp(-ex * ex * inv2T) * exp(-ey * ey * inv2T);
-      if (SK) shakhov2(ska, qx, qy, T, 1.0 / T, ex, ey, E, E, Eg);
+      E = A * cs.eqx[p1] * cs.eqy[p2];
+      if (SK) shakhov2(ska, qx, qy, T, 1.0 / T, vx - ux, vy - uy, E, E, Eg);
       else Eg = 0.5 * T * E;
     }
-    const double fn = o.x - P.dt / S * Rf + dtau * (E - o.x);
-    const double gn = o.y - P.dt / S * Rg + dtau * (Eg - o.y);
-    if (P.write_state)
-      for (int t = 0; t < nm; ++t) out[(size_t)G.mem[b + t] * nvel + p] = make_double2(fn, gn);
+    const double fn = ratio * o.x - dts * Rf + ratio * dtau * (E - o.x);
+    const double gn = ratio * o.y - dts * Rg + ratio * dtau * (Eg - o.y);
+    for (int t = 0; t < nm; ++t) {
+      double2* d = cs.dst[t];
+      if (d) d[p] = cs.live[t] ? make_double2(fn, gn) : make_double2(0.0, 0.0);
+    }
     sm.add(vx, vy, fn, gn);
   }
-  double Fx = 0.0, Fy = 0.0, Tq = 0.0;
-  for (int t = 0; t < nm; ++t) {
-    const int k = G.mem[b + t];
-    if (!(G.lw[k] > 0.0)) continue;
-    const double ax = block_sum4(sx[t], lds) * P.w, ay = block_sum4(sy[t], lds) * P.w;
-    Fx += ax * G.lw[k];
-    Fy += ay * G.lw[k];
-    Tq += ((G.rwx[k] - body[0]) * ay - (G.rwy[k] - body[1]) * ax) * G.lw[k];
+  Fx = block_sum4(fx, cs.red) * P.w;
+  Fy = block_sum4(fy, cs.red) * P.w;
+  Tq = block_sum4(tq, cs.red) * P.w;
+  sm.reduce([&](double v) { return block_sum4(v, cs.red); });
+}
+
+// A cut or merged control volume of a fixed geometry.  With write_state ==
+// 0 only the force is produced.
+template <bool SK>
+__device__ void cut_cv(const Geo2D& G, const double2* __restrict__ in, double2* __restrict__ out,
+                       double* __restrict__ mom, double* __restrict__ heat, double* __restrict__ fslot,
+                       double* __restrict__ mpart, const double* __restrict__ body,
+                       const StepParams& P, int q, CvStage& cs) {
+  const int tid = threadIdx.x;
+  const int m = G.irr[q];
+  const int b = G.mptr[q];
+  // more members than supported is reported by the list builder; never index past the arrays
+  const int nm = min(G.mptr[q + 1] - b, kMaxMembers);
+  const int nvel = G.nvel;
+  const double rho = mom[4 * m + 0], ux = mom[4 * m + 1], uy = mom[4 * m + 2], T = mom[4 * m + 3];
+  const double dtau = P.tau_coef > 0.0 && !P.implicit ? P.dt * rho / P.tau_coef : 0.0;
+  const double qx = SK ? heat[2 * m] : 0.0, qy = SK ? heat[2 * m + 1] : 0.0;
+  const double S = G.scv[m];
+  if (tid < nm) {
+    cs.dst[tid] = P.write_state ? out + (size_t)G.mem[b + tid] * nvel : nullptr;
+    cs.live[tid] = 1;
   }
-  sm.reduce([&](double v) { return block_sum4(v, lds); });
+  Sums2<SK> sm;
+  double Fx, Fy, Tq;
+  cv_update<SK>(cs, G, G.mem + b, nm, in, in + (size_t)m * nvel, body, P, rho, ux, uy, T, qx, qy,
+                dtau, 1.0, P.dt / S, sm, Fx, Fy, Tq);
   if (tid == 0) {
     double mo[4], hq[2];
     sm.finish(P.w, mo, hq);
@@ -266,9 +343,9 @@ __global__ void __launch_bounds__(256) k_cut_force2d(Geo2D G, const double2* __r
                                                      double* __restrict__ fslot,
                                                      const double* __restrict__ body,
                                                      StepParams P) {
-  __shared__ double lds[8];
+  __shared__ CvStage cs;
   for (int q = blockIdx.x; q < G.counts[0]; q += gridDim.x)
-    cut_cv<false>(G, in, nullptr, mom, nullptr, fslot, nullptr, body, P, q, lds);
+    cut_cv<false>(G, in, nullptr, mom, nullptr, fslot, nullptr, body, P, q, cs);
 }
 
 // ---------------------------------------------------------------------
@@ -665,12 +742,12 @@ k_step2d_im(Geo2D G, FusedArgs A, StepParams P) {
 
 // cut / merged control volumes of one step, one 256-thread block each
 __global__ void __launch_bounds__(256) k_cutstep2d(Geo2D G, FusedArgs A, StepParams P) {
-  __shared__ double lds[8];
+  __shared__ CvStage cs;
   const int q = blockIdx.x;
   if (P.shakhov)
-    cut_cv<true>(G, A.in, A.out, A.mom, A.heat, A.fslot, A.mpart + A.ntiles + q, A.body, P, q, lds);
+    cut_cv<true>(G, A.in, A.out, A.mom, A.heat, A.fslot, A.mpart + A.ntiles + q, A.body, P, q, cs);
   else
-    cut_cv<false>(G, A.in, A.out, A.mom, nullptr, A.fslot, A.mpart + A.ntiles + q, A.body, P, q, lds);
+    cut_cv<false>(G, A.in, A.out, A.mom, nullptr, A.fslot, A.mpart + A.ntiles + q, A.body, P, q, cs);
 }
 
 // final reduction of the last step of a call (same code as the deferred one)
@@ -1225,11 +1302,11 @@ __device__ void general_cv(const MoveArgs& M, const double2* __restrict__ in,
                            double2* __restrict__ out, double* __restrict__ mom, double* __restrict__ heat,
                            double* __restrict__ fslot, double* __restrict__ mpart,
                            const double* __restrict__ body, const StepParams& P, int q,
-                           double* lds) {
+                           CvStage& cs) {
   const Geo2D& G0 = M.G0;
   const Geo2D& G1 = M.G1;
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int N = G0.N, nvel = G0.nvel, nx = G0.nx, ny = G0.ny;
+  const int nvel = G0.nvel;
   const int e0 = M.gl[q];
   if (e0 < 0) {
     const int c = -1 - e0;
@@ -1242,107 +1319,22 @@ __device__ void general_cv(const MoveArgs& M, const double2* __restrict__ in,
   // more receivers than supported is reported by k_steplist2d; never index past the arrays
   const int nm = min(M.gptr[q + 1] - b, kMaxMembers);
   const double rho = mom[4 * m + 0], ux = mom[4 * m + 1], uy = mom[4 * m + 2], T = mom[4 * m + 3];
-  const double inv2T = 0.5 / T, A = rho / (2.0 * M_PI * T);
   const double dtau = P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
   const double qx = SK ? heat[2 * m] : 0.0, qy = SK ? heat[2 * m + 1] : 0.0;
-  const double ska = SK ? P.sk_coef / (rho * T * T) : 0.0;
   const double Sn = G0.scv[m];
   double Snew = 0.0;
   for (int t = 0; t < nm; ++t) Snew += G1.sbar[M.gmem[b + t]];
-  const double2* own = in + (size_t)m * nvel;
-  const double Tw = P.t_wall;
-  double phiw[kMaxMembers], uwx[kMaxMembers], uwy[kMaxMembers];
-  for (int t = 0; t < nm; ++t) {
-    const int k = M.gmem[b + t];
-    phiw[t] = 0.0; uwx[t] = 0.0; uwy[t] = 0.0;
-    if (!(G0.lw[k] > 0.0)) continue;
-    wall_velocity(body, G0.rwx[k], G0.rwy[k], &uwx[t], &uwy[t]);
-    const double nwx = G0.nwx[k], nwy = G0.nwy[k];
-    double num = 0.0, den = 0.0;
-    for (int p = tid; p < nvel; p += nth) {
-      const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
-      const double cn = (vx - uwx[t]) * nwx + (vy - uwy[t]) * nwy;
-      if (cn > 0.0) num += cn * own[p].x;
-      else if (cn < 0.0) den += cn * maxw_wall(vx, vy, uwx[t], uwy[t], Tw);
-    }
-    num = block_sum4(num, lds);
-    den = block_sum4(den, lds);
-    phiw[t] = den != 0.0 ? -num / den : 0.0;
+  if (tid < nm) {
+    const int k = M.gmem[b + tid];
+    cs.dst[tid] = out + (size_t)k * nvel;
+    cs.live[tid] = G1.type[k] != TYPE_SOLID && Snew > 0.0;
   }
-  double sx[kMaxMembers], sy[kMaxMembers];
-  for (int t = 0; t < kMaxMembers; ++t) { sx[t] = 0.0; sy[t] = 0.0; }
-  Sums2<SK> sm;
   const double ratio = Snew > 0.0 ? Sn / Snew : 0.0;
   const double dts = Snew > 0.0 ? P.dt / Snew : 0.0;
-  for (int p = tid; p < nvel; p += nth) {
-    const double vx = vnode(P.vmin, P.dv, p % N), vy = vnode(P.vmin, P.dv, p / N);
-    const double vxm = fmin(vx, 0.0), vxp = fmax(vx, 0.0);
-    const double vym = fmin(vy, 0.0), vyp = fmax(vy, 0.0);
-    const double2 o = own[p];
-    double Rf = 0.0, Rg = 0.0;
-    for (int t = 0; t < nm; ++t) {
-      const int k = M.gmem[b + t];
-      const int i = k % nx, j = k / nx;
-      const double Lr = G0.lxp[k], Ll = G0.lxm[k], Lt = G0.lyp[k], Lb = G0.lym[k];
-      if (Lr > 0.0) {
-        const double2 nb = i + 1 < nx ? in[(size_t)(k + 1) * nvel + p] : G0.ghost[p];
-        Rf += Lr * (vxm * nb.x + vxp * o.x);
-        Rg += Lr * (vxm * nb.y + vxp * o.y);
-      }
-      if (Ll > 0.0) {
-        const double2 nb = i > 0 ? in[(size_t)(k - 1) * nvel + p] : G0.ghost[p];
-        Rf -= Ll * (vxm * o.x + vxp * nb.x);
-        Rg -= Ll * (vxm * o.y + vxp * nb.y);
-      }
-      if (Lt > 0.0) {
-        const double2 nb = j + 1 < ny ? in[(size_t)(k + nx) * nvel + p] : G0.ghost[p];
-        Rf += Lt * (vym * nb.x + vyp * o.x);
-        Rg += Lt * (vym * nb.y + vyp * o.y);
-      }
-      if (Lb > 0.0) {
-        const double2 nb = j > 0 ? in[(size_t)(k - nx) * nvel + p] : G0.ghost[p];
-        Rf -= Lb * (vym * o.x + vyp * nb.x);
-        Rg -= Lb * (vym * o.y + vyp * nb.y);
-      }
-      const double Lw = G0.lw[k];
-      if (Lw > 0.0) {
-        const double cx_ = vx - uwx[t], cy_ = vy - uwy[t];
-        const double cn = cx_ * G0.nwx[k] + cy_ * G0.nwy[k];
-        const double Mw = maxw_wall(vx, vy, uwx[t], uwy[t], Tw);
-        const double fw = phiw[t] * Mw, gw = phiw[t] * 0.5 * Tw * Mw;
-        Rf += Lw * (fmin(cn, 0.0) * fw + fmax(cn, 0.0) * o.x);
-        Rg += Lw * (fmin(cn, 0.0) * gw + fmax(cn, 0.0) * o.y);
-        const double fv = cn < 0.0 ? fw : (cn > 0.0 ? o.x : 0.0);
-        sx[t] += cx_ * cn * fv;
-        sy[t] += cy_ * cn * fv;
-      }
-    }
-    double E = 0.0, Eg = 0.0;
-    if (dtau != 0.0) {
-      const double ex = vx - ux, ey = vy - uy;
-      E = A * exp(-ex * ex * inv2T) * exp(-ey * ey * inv2T);
-      if (SK) shakhov2(ska, qx, qy, T, 1.0 / T, ex, ey, E, E, Eg);
-      else Eg = 0.5 * T * E;
-    }
-    const double fn = ratio * o.x - dts * Rf + ratio * dtau * (E - o.x);
-    const double gn = ratio * o.y - dts * Rg + ratio * dtau * (Eg - o.y);
-    for (int t = 0; t < nm; ++t) {
-      const int k = M.gmem[b + t];
-      const bool live = G1.type[k] != TYPE_SOLID && Snew > 0.0;
-      out[(size_t)k * nvel + p] = live ? make_double2(fn, gn) : make_double2(0.0, 0.0);
-    }
-    sm.add(vx, vy, fn, gn);
-  }
-  double Fx = 0.0, Fy = 0.0, Tq = 0.0;
-  for (int t = 0; t < nm; ++t) {
-    const int k = M.gmem[b + t];
-    if (!(G0.lw[k] > 0.0)) continue;
-    const double ax = block_sum4(sx[t], lds) * P.w, ay = block_sum4(sy[t], lds) * P.w;
-    Fx += ax * G0.lw[k];
-    Fy += ay * G0.lw[k];
-    Tq += ((G0.rwx[k] - body[0]) * ay - (G0.rwy[k] - body[1]) * ax) * G0.lw[k];
-  }
-  sm.reduce([&](double v) { return block_sum4(v, lds); });
+  Sums2<SK> sm;
+  double Fx, Fy, Tq;
+  cv_update<SK>(cs, G0, M.gmem + b, nm, in, in + (size_t)m * nvel, body, P, rho, ux, uy, T, qx, qy,
+                dtau, ratio, dts, sm, Fx, Fy, Tq);
   if (tid == 0) {
     double mo[4], hq[2];
     sm.finish(P.w, mo, hq);
@@ -1365,11 +1357,11 @@ __global__ void __launch_bounds__(256) k_genstep2d(MoveArgs M, const double2* __
                                                    double* __restrict__ fslot,
                                                    double* __restrict__ mpart, int ntiles,
                                                    const double* __restrict__ body, StepParams P) {
-  __shared__ double lds[8];
+  __shared__ CvStage cs;
   const int cnt = M.gcount[0];
   for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
-    if (P.shakhov) general_cv<true>(M, in, out, mom, heat, fslot, mpart + ntiles + q, body, P, q, lds);
-    else general_cv<false>(M, in, out, mom, nullptr, fslot, mpart + ntiles + q, body, P, q, lds);
+    if (P.shakhov) general_cv<true>(M, in, out, mom, heat, fslot, mpart + ntiles + q, body, P, q, cs);
+    else general_cv<false>(M, in, out, mom, nullptr, fslot, mpart + ntiles + q, body, P, q, cs);
   }
 }
 
@@ -1448,7 +1440,7 @@ __global__ void __launch_bounds__(256) k_batch_tiles2d(const BatchInst* __restri
 
 __global__ void __launch_bounds__(256) k_batch_cut2d(const BatchInst* __restrict__ D,
                                                      const int2* __restrict__ items, int nitems) {
-  __shared__ double lds[8];
+  __shared__ CvStage cs;
   const int w = blockIdx.x;
   if (w >= nitems) return;
   const int2 it = items[w];
@@ -1456,7 +1448,7 @@ __global__ void __launch_bounds__(256) k_batch_cut2d(const BatchInst* __restrict
   const int q = __builtin_amdgcn_readfirstlane(it.y);
   const Geo2D G = D[inst].G;
   const FusedArgs A = D[inst].A;
-  cut_cv<false>(G, A.in, A.out, A.mom, nullptr, A.fslot, A.mpart + A.ntiles + q, A.body, D[inst].P, q, lds);
+  cut_cv<false>(G, A.in, A.out, A.mom, nullptr, A.fslot, A.mpart + A.ntiles + q, A.body, D[inst].P, q, cs);
 }
 
 typedef void (*batch_tiles_fn)(hipStream_t, const BatchInst*, const int2*, int);
