@@ -161,7 +161,7 @@ struct CvStage {
 // block of 256 threads (velocities strided over the block).  Wall density
 // of each wall edge (eq. BoundaryDDv), fluxes of all members' edges (eq.
 // FluxDD), the explicit update with relaxation (eq. ExSchemeDD; ratio and
-// dts carry the area change of a moving body, eq. UpdateDD-m), the new
+// dts carry the area change S^n / S^{n+1,*} of a moving body, eq. SchemeDD), the new
 // value written to every member (eq. UpdateDD), the wall stress of the
 // state at t^n summed into force and torque (eqs. StressTensorDD,
 // eq-force, eq-torque) and the velocity sums of the new value.  The
