@@ -307,31 +307,58 @@ __device__ inline double readlane_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Cross-lane steps of the butterflies below, without the LDS crossbar.
+// pl32_sum(a, b): lanes 0-31 get a(l) + a(l + 32), lanes 32-63 get
+// b(l - 32) + b(l), from one swap of the upper half of a with the lower half
+// of b per dword (v_permlane32_swap).  pl16_sum does the same within each
+// 32-lane half with 16-lane rows (odd rows of a with even rows of b).
+__device__ inline double pl32_sum(double a, double b) {
+  const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((int)ia, (int)ib, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((int)(ia >> 32), (int)(ib >> 32), false, false);
+  const double an = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]);
+  const double bn = __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+  return an + bn;
+}
+
+__device__ inline double pl16_sum(double a, double b) {
+  const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((int)ia, (int)ib, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((int)(ia >> 32), (int)(ib >> 32), false, false);
+  const double an = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]);
+  const double bn = __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+  return an + bn;
+}
+
+// value of a partner lane inside a 16-lane row (DPP): kMirror16 pairs lane
+// i with 15 - i, kMirror8 i with 7 - i in each half row, kSwap2 / kSwap1
+// i with i ^ 2 / i ^ 1 in each quad
+constexpr int kMirror16 = 0x140, kMirror8 = 0x141, kSwap2 = 0x4E, kSwap1 = 0xB1;
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Sums of v[0..4] over the wave: on return lanes 8q .. 8q+7 hold the sum
-// of quantity q (q < 5).
+// of quantity q (q < 5).  Each level halves the quantities a lane keeps and
+// adds its partner's copy of them; the last three levels sum within 8 lanes.
 __device__ inline double reduce5(const double (&v)[5], int lv) {
-  const bool b5 = lv & 32, b4 = lv & 16, b3 = lv & 8;
+  const bool b3 = lv & 8;
   double w[4];
+  w[0] = pl32_sum(v[0], v[4]);   // lower half: quantity 0, upper half: 4
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double a = v[k], b = k == 0 ? v[4] : 0.0;   // quantities k and k+4
-    const double keep = b5 ? b : a, send = b5 ? a : b;
-    w[k] = keep + __shfl_xor(send, 32, kWave);
-  }
+  for (int k = 1; k < 4; ++k) w[k] = pl32_sum(v[k], 0.0);
   double x[2];
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const double keep = b4 ? w[k + 2] : w[k], send = b4 ? w[k] : w[k + 2];
-    x[k] = keep + __shfl_xor(send, 16, kWave);
-  }
-  double y;
-  {
-    const double keep = b3 ? x[1] : x[0], send = b3 ? x[0] : x[1];
-    y = keep + __shfl_xor(send, 8, kWave);
-  }
-  y += __shfl_xor(y, 4, kWave);
-  y += __shfl_xor(y, 2, kWave);
-  y += __shfl_xor(y, 1, kWave);
+  for (int k = 0; k < 2; ++k) x[k] = pl16_sum(w[k], w[k + 2]);
+  const double keep = b3 ? x[1] : x[0], send = b3 ? x[0] : x[1];
+  double y = keep + dpp_d<kMirror16>(send);
+  y += dpp_d<kMirror8>(y);
+  y += dpp_d<kSwap2>(y);
+  y += dpp_d<kSwap1>(y);
   return y;
 }
 
@@ -339,29 +366,23 @@ __device__ inline double reduce5(const double (&v)[5], int lv) {
 // of quantity q.  Each level halves the quantities a lane keeps and adds its
 // partner's copy of them.
 __device__ inline double reduce16(const double (&v)[16], int lv) {
-  const bool b5 = lv & 32, b4 = lv & 16, b3 = lv & 8, b2 = lv & 4;
+  const bool b3 = lv & 8, b2 = lv & 4;
   double a[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const double keep = b5 ? v[k + 8] : v[k], send = b5 ? v[k] : v[k + 8];
-    a[k] = keep + __shfl_xor(send, 32, kWave);
-  }
+  for (int k = 0; k < 8; ++k) a[k] = pl32_sum(v[k], v[k + 8]);
   double b[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double keep = b4 ? a[k + 4] : a[k], send = b4 ? a[k] : a[k + 4];
-    b[k] = keep + __shfl_xor(send, 16, kWave);
-  }
+  for (int k = 0; k < 4; ++k) b[k] = pl16_sum(a[k], a[k + 4]);
   double c[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const double keep = b3 ? b[k + 2] : b[k], send = b3 ? b[k] : b[k + 2];
-    c[k] = keep + __shfl_xor(send, 8, kWave);
+    c[k] = keep + dpp_d<kMirror16>(send);
   }
   const double keep = b2 ? c[1] : c[0], send = b2 ? c[0] : c[1];
-  double d = keep + __shfl_xor(send, 4, kWave);
-  d += __shfl_xor(d, 2, kWave);
-  d += __shfl_xor(d, 1, kWave);
+  double d = keep + dpp_d<kMirror8>(send);
+  d += dpp_d<kSwap2>(d);
+  d += dpp_d<kSwap1>(d);
   return d;
 }
 
