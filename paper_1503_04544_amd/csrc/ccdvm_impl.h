@@ -111,6 +111,53 @@ __device__ inline int block_scan_excl(int v, int* sh, int* total) {
   return before + x - v;
 }
 
+// Cross-lane steps of wave reductions without the LDS crossbar.
+// pl32_sum(a, b): lanes 0-31 get a(l) + a(l + 32), lanes 32-63 get
+// b(l - 32) + b(l), from one swap of the upper half of a with the lower half
+// of b per dword (v_permlane32_swap).  pl16_sum does the same within each
+// 32-lane half with 16-lane rows (odd rows of a with even rows of b).
+__device__ inline double pl32_sum(double a, double b) {
+  const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((int)ia, (int)ib, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((int)(ia >> 32), (int)(ib >> 32), false, false);
+  const double an = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]);
+  const double bn = __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+  return an + bn;
+}
+
+__device__ inline double pl16_sum(double a, double b) {
+  const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((int)ia, (int)ib, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((int)(ia >> 32), (int)(ib >> 32), false, false);
+  const double an = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]);
+  const double bn = __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+  return an + bn;
+}
+
+// value of a partner lane inside a 16-lane row (DPP): kMirror16 pairs lane
+// i with 15 - i, kMirror8 i with 7 - i in each half row, kSwap2 / kSwap1
+// i with i ^ 2 / i ^ 1 in each quad
+constexpr int kMirror16 = 0x140, kMirror8 = 0x141, kSwap2 = 0x4E, kSwap1 = 0xB1;
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave (every lane active); every lane gets the
+// same bits, since each step adds the same two operands in both partners.
+__device__ inline double wave_allsum(double v) {
+  v = pl32_sum(v, v);
+  v = pl16_sum(v, v);
+  v += dpp_d<kMirror16>(v);
+  v += dpp_d<kMirror8>(v);
+  v += dpp_d<kSwap2>(v);
+  v += dpp_d<kSwap1>(v);
+  return v;
+}
+
 // an int that other threads update with atomics, read at L2
 __device__ inline int load_l2(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

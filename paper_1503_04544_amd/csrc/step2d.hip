@@ -34,11 +34,7 @@ namespace {
 
 constexpr int kWave = 64;
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
+__device__ inline double wave_sum(double v) { return wave_allsum(v); }
 
 __device__ inline double vnode(double vmin, double dv, int idx) { return vmin + (idx + 0.5) * dv; }
 
