@@ -141,8 +141,9 @@ constexpr int kMirror16 = 0x140, kMirror8 = 0x141, kSwap2 = 0x4E, kSwap1 = 0xB1;
 template <int CTRL>
 __device__ inline double dpp_d(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  // every lane reads a lane of its own row, so no old value is needed
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 

@@ -493,8 +493,6 @@ __device__ __forceinline__ void step16(const Step3Args& A, const int* __restrict
       m[2] = vya * Aa + vyb * Ab;
       m[3] = m3;
       m[4] = vx * vx * s0 + (vya * vya * Aa + vyb * vyb * Ab) + m4z;
-      // halos of cell i+1 before the reduction
-      load_halos16(X, i + 1, nx, lb, hy, hz);
       const double tot = reduce5(m, lv);
       if ((lv & 7) == 0 && lv < 40) A.part[((size_t)c * kNCH16 + X.ch) * kSums5 + (lv >> 3)] = tot;
     } else {
@@ -530,14 +528,13 @@ __device__ __forceinline__ void step16(const Step3Args& A, const int* __restrict
       m[13] = vx2 * m3 + z3y + z3;
       m[14] = 0.0;
       m[15] = 0.0;
-      load_halos16(X, i + 1, nx, lb, hy, hz);
       const double tot = reduce16(m, lv);
       if ((lv & 3) == 0 && lv < 4 * kSumsSK)
         A.part[((size_t)c * kNCH16 + X.ch) * kSumsSK + (lv >> 2)] = tot;
     }
-  } else {
-    load_halos16(X, i + 1, nx, lb, hy, hz);
   }
+  // halos of cell i+1, once hy and hz are no longer read
+  load_halos16(X, i + 1, nx, lb, hy, hz);
 }
 
 template <bool SK>
