@@ -415,10 +415,16 @@ __device__ void deferred_reduce(const Geo2D& G, const FusedArgs& A, double* lds)
 }
 
 typedef double d2v __attribute__((ext_vector_type(2)));
+// a type in the global address space: pointers read from memory (the
+// batched kernels' descriptor tables) carry no address space, and the
+// compiler then issues flat operations, which count on both the vector
+// memory and the LDS counters, so that every wait drains both
+template <class T>
+using glob = __attribute__((address_space(1))) T;
 
 // load one velocity half of a cell row (or of the farfield table)
 template <int NCH>
-__device__ inline void load_half(d2v (&dst)[NCH], const d2v* __restrict__ row, int base,
+__device__ inline void load_half(d2v (&dst)[NCH], const glob<d2v>* __restrict__ row, int base,
                                  int count, int lane) {
 #pragma unroll
   for (int k = 0; k < NCH; ++k) {
@@ -477,9 +483,12 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
   const int j0 = seg * Ta.seglen, j1 = min(j0 + Ta.seglen, ny);
   const int split = Ta.split;
   const int lo_n = split * N, hi_n = nvel - lo_n;   // sizes of the two halves
-  const d2v* in = reinterpret_cast<const d2v*>(Ta.in);
-  d2v* out = reinterpret_cast<d2v*>(Ta.out);
-  const d2v* ghost = reinterpret_cast<const d2v*>(Ta.ghost);
+  const glob<d2v>* in = (const glob<d2v>*)Ta.in;
+  glob<d2v>* out = (glob<d2v>*)Ta.out;
+  const glob<d2v>* ghost = (const glob<d2v>*)Ta.ghost;
+  const glob<int>* kind = (const glob<int>*)Ta.kind;
+  glob<double>* mom = (glob<double>*)Ta.mom;
+  glob<double>* heat = (glob<double>*)Ta.heat;
   double msum = 0.0;
   if (i < nx && j0 < j1) {
     const double S = Ta.dx * Ta.dy;
@@ -490,7 +499,7 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
     d2v prevU[NCH], curL[IM ? 1 : NCH];
     load_half<NCH>(prevU, j0 > 0 ? in + (size_t)((j0 - 1) * nx + i) * nvel : ghost, lo_n, hi_n, lane);
     if constexpr (IM) {
-      const d2v* r0 = in + (size_t)(j0 * nx + i) * nvel;
+      const glob<d2v>* r0 = in + (size_t)(j0 * nx + i) * nvel;
 #pragma unroll
       for (int k = 0; k < NCH; ++k)
         xlo[(wave * NCH + k) * kWave + lane] = k * 64 + lane < lo_n ? r0[k * 64 + lane] : d2v{0.0, 0.0};
@@ -512,13 +521,13 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
         __syncthreads();
       }
       const int c = j * nx + i;
-      const d2v* row = in + (size_t)c * nvel;
-      const d2v* nrow = j + 1 < ny ? row + (size_t)nx * nvel : ghost;
-      const bool reg = Ta.kind[c] == KIND_REGULAR;   // uniform over the wave
+      const glob<d2v>* row = in + (size_t)c * nvel;
+      const glob<d2v>* nrow = j + 1 < ny ? row + (size_t)nx * nvel : ghost;
+      const bool reg = kind[c] == KIND_REGULAR;   // uniform over the wave
       double Am = 0.0, T = 1.0, dtau = 0.0, tx = 0.0, ty = 0.0, nu = 0.0;
       double ux = 0.0, uy = 0.0, qx = 0.0, qy = 0.0, ska = 0.0, invT = 1.0;   // SK only
       if (reg) {
-        const double* mc = Ta.mom + 4 * c;
+        const glob<double>* mc = mom + 4 * c;
         const double rho = mc[0];
         ux = mc[1]; uy = mc[2];
         T = mc[3];
@@ -527,7 +536,7 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
         dtau = P.tau_coef > 0.0 && !IM ? P.dt * rho / P.tau_coef : 0.0;
         nu = IM && P.tau_coef > 0.0 ? P.dt * rho / P.tau_coef : 0.0;
         if (SK) {
-          qx = Ta.heat[2 * c]; qy = Ta.heat[2 * c + 1];
+          qx = heat[2 * c]; qy = heat[2 * c + 1];
           ska = P.sk_coef / (rho * T * T);
           invT = 1.0 / T;
         }
@@ -537,9 +546,9 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
           ty = exp(-(v - uy) * (v - uy) * inv2T);
         }
       }
-      const d2v* xl = i > 0 ? row - nvel : ghost;        // x-upwind for v_x > 0
-      const d2v* xr = i + 1 < nx ? row + nvel : ghost;   // x-upwind for v_x < 0
-      d2v* orow = out + (size_t)c * nvel;
+      const glob<d2v>* xl = i > 0 ? row - nvel : ghost;        // x-upwind for v_x > 0
+      const glob<d2v>* xr = i + 1 < nx ? row + nvel : ghost;   // x-upwind for v_x < 0
+      glob<d2v>* orow = out + (size_t)c * nvel;
       Sums2<SK> sm;
       // software pipeline over the chunks: the loads of chunk k+PD are issued
       // before chunk k is computed; a scheduling barrier between chunks keeps
@@ -559,14 +568,21 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
         const bool in_tile = pos ? wave > 0 : (wave + 1 < kTileW && i + 1 < nx);
         return xlo && in_tile ? (pos ? wave - 1 : wave + 1) : -1;
       };
+      // Every lane issues the same loads for every chunk and row (lanes past
+      // a half read its first element, lanes whose x-upwind lower half comes
+      // from xlo read the x-upwind upper half, which the bXb load brings
+      // in), so the loads carry no branch: the compiler then waits for each
+      // chunk's loads alone instead of draining the whole prefetch window.
+      // Values of such lanes are never used.
       auto issue = [&](int k) {
         const int o = k * 64 + lv;
         const int lp1 = o % N;
-        const d2v* xrow = vnode(P.vmin, P.dv, lp1) > 0.0 ? xl : xr;
-        bN[k] = o < lo_n ? nrow[o] : d2v{0.0, 0.0};
-        bU[k] = o < hi_n ? row[lo_n + o] : d2v{0.0, 0.0};
-        bXa[k] = reg && o < lo_n && xwave(k) < 0 ? xrow[o] : d2v{0.0, 0.0};
-        bXb[k] = reg && o < hi_n ? xrow[lo_n + o] : d2v{0.0, 0.0};
+        const glob<d2v>* xrow = vnode(P.vmin, P.dv, lp1) > 0.0 ? xl : xr;
+        const int oa = o < lo_n ? o : 0, ob = o < hi_n ? o : 0;
+        bN[k] = nrow[oa];
+        bU[k] = row[lo_n + ob];
+        bXa[k] = xrow[xwave(k) < 0 ? oa : lo_n + ob];
+        bXb[k] = xrow[lo_n + ob];
       };
 #pragma unroll
       for (int k = 0; k < PD; ++k) issue(k);
@@ -576,7 +592,11 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
         const int o = k * 64 + lv;
         const int xw = xwave(k);
         const d2v nL = bN[k], cU = bU[k], xb = bXb[k];
-        const d2v xa = xw >= 0 && o < lo_n ? xcur[(xw * NCH + k) * kWave + lv] : bXa[k];
+        // the LDS value is read by every lane (from its own slot where it is
+        // not used) and selected as a value: a select of the two sources'
+        // addresses would put bXa in scratch and read both through flat loads
+        const d2v xs = xlo ? xcur[((xw >= 0 ? xw : wave) * NCH + k) * kWave + lv] : d2v{0.0, 0.0};
+        const d2v xa = xw >= 0 && o < lo_n ? xs : bXa[k];
         if (reg) {
           const int p1 = o % N, q2 = o / N;
           const double vx = vnode(P.vmin, P.dv, p1);
@@ -584,7 +604,8 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
           const double ex = Am * __shfl(tx, p1, 64);
           const double tyl = __shfl(ty, q2 < N ? q2 : 0, 64);
           const double tyu = __shfl(ty, split + q2 < N ? split + q2 : 0, 64);
-          if (o < lo_n) {   // lower half: v_y < 0, y-upwind is the cell above
+          {   // lower half: v_y < 0, y-upwind is the cell above
+            const bool va = o < lo_n;
             const double vy = vnode(P.vmin, P.dv, q2);
             const double ay = cyf * fabs(vy);
             d2v own;
@@ -599,10 +620,11 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
               gn += dtau * (Eg - own.y);
             }
             if (IM) fsL[k] = d2v{fn, gn};
-            else __builtin_nontemporal_store(d2v{fn, gn}, &orow[o]);
-            sm.add(vx, vy, fn, gn);
+            else if (va) __builtin_nontemporal_store(d2v{fn, gn}, &orow[o]);
+            sm.add(vx, vy, va ? fn : 0.0, va ? gn : 0.0);
           }
-          if (o < hi_n) {   // upper half: v_y >= 0, y-upwind is the cell below
+          {   // upper half: v_y >= 0, y-upwind is the cell below
+            const bool vb = o < hi_n;
             const double vy = vnode(P.vmin, P.dv, split + q2);
             const double ay = cyf * fabs(vy);
             const d2v own = cU, yu = prevU[k];
@@ -615,8 +637,8 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
               gn += dtau * (Eg - own.y);
             }
             if (IM) fsU[k] = d2v{fn, gn};
-            else __builtin_nontemporal_store(d2v{fn, gn}, &orow[lo_n + o]);
-            sm.add(vx, vy, fn, gn);
+            else if (vb) __builtin_nontemporal_store(d2v{fn, gn}, &orow[lo_n + o]);
+            sm.add(vx, vy, vb ? fn : 0.0, vb ? gn : 0.0);
           }
         }
         prevU[k] = cU;
@@ -671,9 +693,9 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
         if (lane == 0) {
           double mo[4], hq[2];
           s2.finish(P.w, mo, hq);
-          double* dst = Ta.mom + 4 * c;
+          glob<double>* dst = mom + 4 * c;
           dst[0] = mo[0]; dst[1] = mo[1]; dst[2] = mo[2]; dst[3] = mo[3];
-          if (SK) { Ta.heat[2 * c] = hq[0]; Ta.heat[2 * c + 1] = hq[1]; }
+          if (SK) { heat[2 * c] = hq[0]; heat[2 * c + 1] = hq[1]; }
         }
         msum += S * (s2.r * P.w);
       } else if (reg) {
@@ -681,9 +703,9 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
         if (lane == 0) {
           double mo[4], hq[2];
           sm.finish(P.w, mo, hq);
-          double* dst = Ta.mom + 4 * c;
+          glob<double>* dst = mom + 4 * c;
           dst[0] = mo[0]; dst[1] = mo[1]; dst[2] = mo[2]; dst[3] = mo[3];
-          if (SK) { Ta.heat[2 * c] = hq[0]; Ta.heat[2 * c + 1] = hq[1]; }
+          if (SK) { heat[2 * c] = hq[0]; heat[2 * c + 1] = hq[1]; }
         }
         msum += S * (sm.r * P.w);
       }
@@ -697,7 +719,7 @@ __device__ void regular_tile(const TileArgs Ta, const StepParams P, int tile, do
   __syncthreads();
   if (lane == 0) lds[wave] = msum;
   __syncthreads();
-  if (threadIdx.x == 0) Ta.mpart[tile] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+  if (threadIdx.x == 0) ((glob<double>*)Ta.mpart)[tile] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
 }
 
 // regular-cell tiles (+ block 0: deferred reduction of the previous step)
