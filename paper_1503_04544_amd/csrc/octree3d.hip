@@ -915,6 +915,13 @@ __global__ void __launch_bounds__(256) k_amr_simple(AmrArgs A) {
   // are issued before pass k is computed (kAmrPipe + 1 stages)
   constexpr int ST = kAmrPipe + 1;
   double fo[ST][RC], fx[ST][RC], fy[ST][RC], fz[ST][RC];
+  // Every lane issues every load (lanes past the last velocity read the
+  // first one; their values are not used), and the whole pipeline sits
+  // under one branch on the wave, so that no branch splits the loads and
+  // the compiler waits for each pass's loads only, not for the whole
+  // window.  in_v is decided from the plain lane id, so that it folds to
+  // true where NV is a multiple of the wave.
+  auto in_v = [&](int pass, int r) { return (pass * RC + r) * kWaveA + lane < NV; };
   auto load = [&](int pass, int st) {
     // the lane id is laundered per pass so that the velocity constants of a
     // pass are recomputed where used instead of being held across passes
@@ -922,46 +929,47 @@ __global__ void __launch_bounds__(256) k_amr_simple(AmrArgs A) {
     asm volatile("" : "+v"(lv));
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
-      const int p = (pass * RC + r) * kWaveA + lv;
-      const bool in = p < NV;
+      const int p0 = (pass * RC + r) * kWaveA + lv;
+      const int p = in_v(pass, r) ? p0 : lv;
       const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
       // upwind side: the x- face's leaf for v_x > 0, the x+ face's for v_x < 0
       const bool px = vnodeA(A.vmin, A.dv, p1) > 0.0, py = vnodeA(A.vmin, A.dv, p2) > 0.0,
                  pz = vnodeA(A.vmin, A.dv, p3) > 0.0;
-      fo[st][r] = in ? own[p] : 0.0;
-      fx[st][r] = in ? (px ? row[0] : row[1])[p] : 0.0;
-      fy[st][r] = in ? (py ? row[2] : row[3])[p] : 0.0;
-      fz[st][r] = in ? (pz ? row[4] : row[5])[p] : 0.0;
+      fo[st][r] = own[p];
+      fx[st][r] = (px ? row[0] : row[1])[p];
+      fy[st][r] = (py ? row[2] : row[3])[p];
+      fz[st][r] = (pz ? row[4] : row[5])[p];
     }
   };
   if (live) {
 #pragma unroll
     for (int k = 0; k < ST - 1 && k < NP; ++k) load(k, k);
-  }
 #pragma unroll
-  for (int pass = 0; pass < NP; ++pass) {
-    if (!live) break;
-    const int st = pass % ST;
-    if (ST > 1 && pass + ST - 1 < NP) load(pass + ST - 1, (pass + ST - 1) % ST);
-    int lv = lane;
-    asm volatile("" : "+v"(lv));
+    for (int pass = 0; pass < NP; ++pass) {
+      const int st = pass % ST;
+      if (ST > 1 && pass + ST - 1 < NP) load(pass + ST - 1, (pass + ST - 1) % ST);
+      int lv = lane;
+      asm volatile("" : "+v"(lv));
 #pragma unroll
-    for (int r = 0; r < RC; ++r) {
-      const int p = (pass * RC + r) * kWaveA + lv;
-      if (p >= NV) continue;
-      const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
-      const double vx = vnodeA(A.vmin, A.dv, p1), vy = vnodeA(A.vmin, A.dv, p2), vz = vnodeA(A.vmin, A.dv, p3);
-      const double f = fo[st][r];
-      const double acc = (vx > 0.0 ? ar[0] : ar[1]) * fabs(vx) * (f - fx[st][r]) +
-                         (vy > 0.0 ? ar[2] : ar[3]) * fabs(vy) * (f - fy[st][r]) +
-                         (vz > 0.0 ? ar[4] : ar[5]) * fabs(vz) * (f - fz[st][r]);
-      const double E = Am * __shfl(tx, p1, kWaveA) * __shfl(ty, p2, kWaveA) * __shfl(tz, p3, kWaveA);
-      const double fn = f - dtV * acc + dtau * (E - f);
-      A.out[(size_t)m * NV + p] = fn;
-      s[0] += fn; s[1] += vx * fn; s[2] += vy * fn; s[3] += vz * fn;
-      s[4] += (vx * vx + vy * vy + vz * vz) * fn;
+      for (int r = 0; r < RC; ++r) {
+        const bool in = in_v(pass, r);
+        const int p0 = (pass * RC + r) * kWaveA + lv;
+        const int p = in ? p0 : lv;
+        const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
+        const double vx = vnodeA(A.vmin, A.dv, p1), vy = vnodeA(A.vmin, A.dv, p2), vz = vnodeA(A.vmin, A.dv, p3);
+        const double f = fo[st][r];
+        const double acc = (vx > 0.0 ? ar[0] : ar[1]) * fabs(vx) * (f - fx[st][r]) +
+                           (vy > 0.0 ? ar[2] : ar[3]) * fabs(vy) * (f - fy[st][r]) +
+                           (vz > 0.0 ? ar[4] : ar[5]) * fabs(vz) * (f - fz[st][r]);
+        const double E = Am * __shfl(tx, p1, kWaveA) * __shfl(ty, p2, kWaveA) * __shfl(tz, p3, kWaveA);
+        const double fn = f - dtV * acc + dtau * (E - f);
+        if (in) A.out[(size_t)m * NV + p] = fn;
+        const double fv = in ? fn : 0.0;
+        s[0] += fv; s[1] += vx * fv; s[2] += vy * fv; s[3] += vz * fv;
+        s[4] += (vx * vx + vy * vy + vz * vz) * fv;
+      }
+      if (ST == 1 && pass + 1 < NP) load(pass + 1, 0);
     }
-    if (ST == 1 && pass + 1 < NP) load(pass + 1, 0);
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) s[q] = wsum(s[q]);
