@@ -800,12 +800,12 @@ __device__ void merge_cv(const Geo2D& G, double2* __restrict__ st, double* __res
     double af = 0.0, ag = 0.0;
     if (nm > 1) {
       double2 v[kMaxMembers];
+      // every member slot is loaded (past the members the master's row,
+      // with weight 0), so that no branch splits the loads
 #pragma unroll
-      for (int t = 0; t < kMaxMembers; ++t)
-        if (t < nm) v[t] = st[(size_t)mk[t] * nvel + p];
+      for (int t = 0; t < kMaxMembers; ++t) v[t] = st[(size_t)mk[t] * nvel + p];
 #pragma unroll
-      for (int t = 0; t < kMaxMembers; ++t)
-        if (t < nm) { af += w[t] * v[t].x; ag += w[t] * v[t].y; }
+      for (int t = 0; t < kMaxMembers; ++t) { af += w[t] * v[t].x; ag += w[t] * v[t].y; }
       af /= S; ag /= S;
 #pragma unroll
       for (int t = 0; t < kMaxMembers; ++t)
@@ -1951,7 +1951,19 @@ hipError_t launch_moving_step_2d(cc_ctx* ctx, double* force_row, double* mass_ro
   fn(ctx, dim3(A.tile_base + A.ntiles_pad), A, P);
   prof_end(ctx, 0);
   if (overlap && (e = hipStreamWaitEvent(st, ctx->join, 0)) != hipSuccess) return e;
-  if (mass_row) k_moving_mass2d<<<1, 256, 0, st>>>(ctx->s.gcount, par, mp, A.ntiles, mass_row);
+  if (mass_row) {
+    // the mass row off the solver stream: on the side stream once this
+    // step's streaming kernel is done (the next step's side work queues
+    // behind it; a call's last step, which has no mass row, joins the side
+    // stream back before the call returns)
+    hipStream_t sm = st;
+    if (overlap && next) {
+      if ((e = hipEventRecord(ctx->fork, st)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(sd, ctx->fork, 0)) != hipSuccess) return e;
+      sm = sd;
+    }
+    k_moving_mass2d<<<1, 256, 0, sm>>>(ctx->s.gcount, par, mp, A.ntiles, mass_row);
+  }
   if (!overlap && next) {
     prof_begin(ctx, 4);
     e = moving_lists_2d(ctx, st, ctx->g2n, ctx->g2, ctx->nstep + 1, 1 - par);
