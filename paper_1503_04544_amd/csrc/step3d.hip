@@ -675,21 +675,38 @@ struct Mom3Params {
 //   q = 1/2 [S3 - 2 S2 u - u tr S2 + 2 rho |u|^2 u],
 // S2 = sum v v^T F w, S3 = sum |v|^2 v F w, stored as
 // (1 - Pr) q / (5 rho T^2) with the triplet of the record
+// Four lanes per control volume: lane j of a quad sums the chunks j, j + 4,
+// ... (every chunk count is a multiple of 4), the quad adds its four sums
+// through lane swaps (each lane ends with the same bits) and the record's
+// slots are stored by the quad's lanes in turn, so a wave reads the sums of
+// 16 consecutive control volumes and writes their records as whole rows.
 template <bool CONS, bool SK>
 __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict__ part,
                                               double* __restrict__ mom, double* __restrict__ heat,
                                               double* __restrict__ mpart, Mom3Params P) {
   constexpr int K = Sums3<SK>::K;
   __shared__ double lds[4];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = t >> 2, j = t & 3;
+  // the sums are requested together with the kind (from the last control
+  // volume for the lanes past the end); those of other kinds are not used
+  const int cc = c < G.ncell ? c : G.ncell - 1;
+  const int kd = c < G.ncell ? G.kind[cc] : KIND_SOLID;
+  double s[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) s[q] = 0.0;
+  const double* pp = part + (size_t)cc * P.nch * K;
+  for (int ch = j; ch < P.nch; ch += 4)
+#pragma unroll
+    for (int q = 0; q < K; ++q) s[q] += pp[K * ch + q];
+  const bool live = kd == KIND_REGULAR || kd == KIND_IRREGULAR;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    s[q] += dpp_d<kSwap1>(s[q]);
+    s[q] += dpp_d<kSwap2>(s[q]);
+  }
   double ms = 0.0;
-  const int kd = c < G.ncell ? G.kind[c] : KIND_SOLID;
-  if (kd == KIND_REGULAR || kd == KIND_IRREGULAR) {
-    double s[K];
-    for (int q = 0; q < K; ++q) s[q] = 0.0;
-    const double* pp = part + (size_t)c * P.nch * K;
-    for (int ch = 0; ch < P.nch; ++ch)
-      for (int q = 0; q < K; ++q) s[q] += pp[K * ch + q];
+  if (live) {
     const double rho = s[0] * P.w;
     const double ux = s[1] * P.w / rho, uy = s[2] * P.w / rho, uz = s[3] * P.w / rho;
     const double en = 0.5 * s[4] * P.w;
@@ -701,26 +718,27 @@ __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict
         x[0] = rho; x[1] = ux; x[2] = uy; x[3] = uz; x[4] = T;
       }
     }
+    // record slots: 0 density factor, 1-3 velocity, 4 1/(2T), 5 dt/tau, 6 rho
+    const double r0 = x[0] / pow(2.0 * M_PI * x[4], 1.5);
+    const double r5 = P.tau_coef > 0.0 ? P.dt * (P.mode == 1 ? rho : x[0]) / P.tau_coef : 0.0;
     double* mo = mom + 8 * (size_t)c;
-    mo[0] = x[0] / pow(2.0 * M_PI * x[4], 1.5);
-    mo[1] = x[1]; mo[2] = x[2]; mo[3] = x[3];
-    mo[4] = 0.5 / x[4];
-    if (P.mode != 2) mo[5] = P.tau_coef > 0.0 ? P.dt * (P.mode == 1 ? rho : x[0]) / P.tau_coef : 0.0;
-    mo[6] = rho;
+    mo[j] = j == 0 ? r0 : (j == 1 ? x[1] : (j == 2 ? x[2] : x[3]));
+    if (j < 3 && (j != 1 || P.mode != 2)) mo[4 + j] = j == 0 ? 0.5 / x[4] : (j == 1 ? r5 : rho);
     if (SK) {
-      const double w = P.w, u[3] = {ux, uy, uz}, u2 = ux * ux + uy * uy + uz * uz;
-      const double S2[3][3] = {{s[5] * w, s[6] * w, s[7] * w},
-                               {s[6] * w, s[8] * w, s[9] * w},
-                               {s[7] * w, s[9] * w, s[10] * w}};
-      const double tr = S2[0][0] + S2[1][1] + S2[2][2];
+      // heat flux component d = j (lanes 0-2) from the row d of S2
+      const double w = P.w, u2 = ux * ux + uy * uy + uz * uz;
+      const double tr = s[5] * w + s[8] * w + s[10] * w;
       const double a = P.sk_coef / (x[0] * x[4] * x[4]);
-      for (int d = 0; d < 3; ++d) {
-        const double S2u = S2[d][0] * ux + S2[d][1] * uy + S2[d][2] * uz;
-        const double qd = 0.5 * (s[11 + d] * w - 2.0 * S2u - u[d] * tr + 2.0 * rho * u2 * u[d]);
-        heat[3 * (size_t)c + d] = a * qd;
-      }
+      const double r0x = j == 0 ? s[5] : (j == 1 ? s[6] : s[7]);
+      const double r1x = j == 0 ? s[6] : (j == 1 ? s[8] : s[9]);
+      const double r2x = j == 0 ? s[7] : (j == 1 ? s[9] : s[10]);
+      const double s3 = j == 0 ? s[11] : (j == 1 ? s[12] : s[13]);
+      const double ud = j == 0 ? ux : (j == 1 ? uy : uz);
+      const double S2u = (r0x * w) * ux + (r1x * w) * uy + (r2x * w) * uz;
+      const double qd = 0.5 * (s3 * w - 2.0 * S2u - ud * tr + 2.0 * rho * u2 * ud);
+      if (j < 3) heat[3 * (size_t)c + j] = a * qd;
     }
-    ms = (kd == KIND_REGULAR ? P.vol : G.vcv[c]) * rho;
+    if (j == 0) ms = (kd == KIND_REGULAR ? P.vol : G.vcv[c]) * rho;
   }
   ms = block_sum(ms, lds);
   if (threadIdx.x == 0) mpart[blockIdx.x] = ms;
@@ -885,7 +903,17 @@ __global__ void __launch_bounds__(256) k_reduce3d(const double* __restrict__ fsl
   for (int t = threadIdx.x; t < ncv; t += blockDim.x) {
     fx += fslot[3 * t]; fy += fslot[3 * t + 1]; fz += fslot[3 * t + 2];
   }
-  for (int t = threadIdx.x; t < nmp; t += blockDim.x) ms += mpart[t];
+  {
+    // four partials in flight per thread
+    const int bd = blockDim.x;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    int t = threadIdx.x;
+    for (; t + 3 * bd < nmp; t += 4 * bd) {
+      m0 += mpart[t]; m1 += mpart[t + bd]; m2 += mpart[t + 2 * bd]; m3 += mpart[t + 3 * bd];
+    }
+    for (; t < nmp; t += bd) m0 += mpart[t];
+    ms = (m0 + m1) + (m2 + m3);
+  }
   fx = block_sum(fx, lds); fy = block_sum(fy, lds); fz = block_sum(fz, lds);
   ms = block_sum(ms, lds);
   if (threadIdx.x == 0) {
@@ -1098,7 +1126,7 @@ double tau_coef(const cc_ctx* ctx) {
 
 double weight3(const cc_ctx* ctx) { return ctx->dv * ctx->dv * ctx->dv; }
 
-int mom_blocks(const cc_ctx* ctx) { return (ctx->ncell + 255) / 256; }
+int mom_blocks(const cc_ctx* ctx) { return (ctx->ncell + 63) / 64; }
 
 hipError_t run_mom3d(cc_ctx* ctx, int mode = 0) {
   Mom3Params P;
