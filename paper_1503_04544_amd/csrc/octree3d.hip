@@ -665,6 +665,7 @@ constexpr int kWaveA = 64;
 constexpr int kAmrRC = 4;    // velocities per lane and pass of the general octree step
 constexpr int kAmrRCS = 2;   // velocities per lane and pass of the streaming octree step
 constexpr int kAmrPipe = 2;  // streaming octree step: passes of loads issued ahead of the computed one
+constexpr int kAmrFU = 2;    // general octree step: faces whose loads are requested together
 
 __device__ inline double wsum(double v) {
 #pragma unroll
@@ -795,25 +796,67 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
     }
     for (int t = 0; t < (IRR ? nm : 1); ++t) {
       const int k = IRR ? G.cvmem[b + t] : m;
-      for (int e = G.fptr[k]; e < G.fptr[k + 1]; ++e) {
-        const int nb = G.fnb[e], dir = G.fdir[e];
-        const double area = G.farea[e];
-        const double* nrow = nb >= 0 ? A.in + (size_t)nb * NV : G.ghost;
-        const double sg = (dir & 1) ? 1.0 : -1.0;
-        // the face's axis is uniform over the block: one loop per axis
-        auto gather = [&](auto comp) {
+      if constexpr (IRR) {
+        // the cut kernels take the faces one by one: their registers decide
+        // how many of their blocks fit beside the streaming kernel
+        for (int e = G.fptr[k]; e < G.fptr[k + 1]; ++e) {
+          const int nb = G.fnb[e], dir = G.fdir[e];
+          const double area = G.farea[e];
+          const double* nrow = nb >= 0 ? A.in + (size_t)nb * NV : G.ghost;
+          const double sg = (dir & 1) ? 1.0 : -1.0;
+          // the face's axis is uniform over the block: one loop per axis
+          auto gather = [&](auto comp) {
 #pragma unroll
-          for (int r = 0; r < RC; ++r) {
-            const int p = (pass * RC + r) * NT + lv;
-            const double c = sg * vnodeA(A.vmin, A.dv, comp(p));   // outward normal velocity
-            const double fn = c < 0.0 && p < NV ? nrow[p] : 0.0;
-            acc[r] += area * (fmax(c, 0.0) * fo[r] + fmin(c, 0.0) * fn);
+            for (int r = 0; r < RC; ++r) {
+              const int p = (pass * RC + r) * NT + lv;
+              const double c = sg * vnodeA(A.vmin, A.dv, comp(p));   // outward normal velocity
+              const double fn = c < 0.0 && p < NV ? nrow[p] : 0.0;
+              acc[r] += area * (fmax(c, 0.0) * fo[r] + fmin(c, 0.0) * fn);
+            }
+          };
+          switch (dir >> 1) {
+            case 0: gather([](int p) { return p % N; }); break;
+            case 1: gather([](int p) { return (p / N) % N; }); break;
+            default: gather([](int p) { return p / (N * N); }); break;
           }
-        };
-        switch (dir >> 1) {
-          case 0: gather([](int p) { return p % N; }); break;
-          case 1: gather([](int p) { return (p / N) % N; }); break;
-          default: gather([](int p) { return p / (N * N); }); break;
+        }
+      } else {
+        // faces in groups of kAmrFU, the group's loads requested together;
+        // a lane whose velocity leaves through a face (or lies past the last
+        // velocity) reads its own value there, already in the cache, and
+        // the group's missing faces have zero area
+        constexpr int FU = kAmrFU;
+        const int e0 = G.fptr[k], e1 = G.fptr[k + 1];
+        for (int e = e0; e < e1; e += FU) {
+          const double* nrow[FU];
+          double area[FU], sg[FU];
+          int ax[FU];
+#pragma unroll
+          for (int j = 0; j < FU; ++j) {
+            const bool ok = e + j < e1;
+            const int ej = ok ? e + j : e;
+            const int nb = G.fnb[ej], dir = G.fdir[ej];
+            area[j] = ok ? G.farea[ej] : 0.0;
+            nrow[j] = nb >= 0 ? A.in + (size_t)nb * NV : G.ghost;
+            sg[j] = (dir & 1) ? 1.0 : -1.0;
+            ax[j] = dir >> 1;
+          }
+          double c[FU][RC], fn[FU][RC];
+#pragma unroll
+          for (int j = 0; j < FU; ++j)
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+              const int p0 = (pass * RC + r) * NT + lv;
+              const int p = p0 < NV ? p0 : 0;
+              const int pa = ax[j] == 0 ? p % N : (ax[j] == 1 ? (p / N) % N : p / (N * N));
+              c[j][r] = sg[j] * vnodeA(A.vmin, A.dv, pa);   // outward normal velocity
+              fn[j][r] = (c[j][r] < 0.0 && p0 < NV ? nrow[j] : own)[p];
+            }
+#pragma unroll
+          for (int j = 0; j < FU; ++j)
+#pragma unroll
+            for (int r = 0; r < RC; ++r)
+              acc[r] += area[j] * (fmax(c[j][r], 0.0) * fo[r] + fmin(c[j][r], 0.0) * fn[j][r]);
         }
       }
       if (IRR && any_wall && G.aw[k] > 0.0) {
