@@ -756,6 +756,16 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
   double phiw[IRR ? kMaxMembers : 1];
   double uwx[MV ? kMaxMembers : 1], uwy[MV ? kMaxMembers : 1];
   bool any_wall = false;
+  // the control volume's values of the thread's velocities, requested
+  // together (no per-lane condition), for the wall densities
+  double fw0[IRR ? R : 1];
+  if (IRR) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int p = i * NT + tid;
+      fw0[i] = own[p < NV ? p : 0];
+    }
+  }
   for (int t = 0; t < (IRR ? nm : 0); ++t) {
     const int k = G.cvmem[b + t];
     phiw[t] = 0.0;
@@ -769,11 +779,14 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
     }
     const double ux_ = MV ? uwx[t] : 0.0, uy_ = MV ? uwy[t] : 0.0;
     double num = 0.0, den = 0.0;
-    for (int p = tid; p < NV; p += NT) {
+#pragma unroll
+    for (int i = 0; i < (IRR ? R : 1); ++i) {
+      const int p = i * NT + tid;
+      if (p >= NV) continue;
       const double vx = vnodeA(A.vmin, A.dv, p % N) - ux_, vy = vnodeA(A.vmin, A.dv, (p / N) % N) - uy_,
                    vz = vnodeA(A.vmin, A.dv, p / (N * N));
       const double cn = vx * n0 + vy * n1 + vz * n2;
-      if (cn > 0.0) num += cn * own[p];
+      if (cn > 0.0) num += cn * fw0[i];
       else if (cn < 0.0) den += cn * cw * exp(-(vx * vx + vy * vy + vz * vz) * i2Tw);
     }
     num = bsum(num);

@@ -816,13 +816,25 @@ __global__ void __launch_bounds__(256) k_cut3d(Geo3D G, const double* __restrict
     if (!(mw[t][0] > 0.0)) continue;
     const double n0 = mw[t][1], n1 = mw[t][2], n2 = mw[t][3];
     double num = 0.0, den = 0.0;
-    for (int p = tid; p < nvel; p += nth) {
-      const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
-      const double vx = vnode3(P.vmin, P.dv, p1), vy = vnode3(P.vmin, P.dv, p2), vz = vnode3(P.vmin, P.dv, p3);
-      const double cn = vx * n0 + vy * n1 + vz * n2;
-      const double o = own[p];
-      if (cn > 0.0) num += cn * o;
-      else if (cn < 0.0) den += cn * (cw * (wf[p1] * wf[p2] * wf[p3]));
+    // four velocities per thread at a time, their values requested together
+    // (past the last velocity the thread's first one is read and not used)
+    for (int p0 = tid; p0 < nvel; p0 += 4 * nth) {
+      double o[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = p0 + u * nth;
+        o[u] = own[p < nvel ? p : p0];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = p0 + u * nth;
+        if (p >= nvel) continue;
+        const int p1 = p % N, p2 = (p / N) % N, p3 = p / (N * N);
+        const double vx = vnode3(P.vmin, P.dv, p1), vy = vnode3(P.vmin, P.dv, p2), vz = vnode3(P.vmin, P.dv, p3);
+        const double cn = vx * n0 + vy * n1 + vz * n2;
+        if (cn > 0.0) num += cn * o[u];
+        else if (cn < 0.0) den += cn * (cw * (wf[p1] * wf[p2] * wf[p3]));
+      }
     }
     num = block_sum(num, lds);
     den = block_sum(den, lds);
