@@ -680,14 +680,17 @@ struct Mom3Params {
 // through lane swaps (each lane ends with the same bits) and the record's
 // slots are stored by the quad's lanes in turn, so a wave reads the sums of
 // 16 consecutive control volumes and writes their records as whole rows.
+// With the conservative triplet one thread per control volume: the Newton
+// solve would otherwise run in all four lanes of the quad.
 template <bool CONS, bool SK>
 __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict__ part,
                                               double* __restrict__ mom, double* __restrict__ heat,
                                               double* __restrict__ mpart, Mom3Params P) {
   constexpr int K = Sums3<SK>::K;
+  constexpr int CPT = CONS ? 1 : 4;   // threads per control volume
   __shared__ double lds[4];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = t >> 2, j = t & 3;
+  const int c = t / CPT, j = t % CPT;
   // the sums are requested together with the kind (from the last control
   // volume for the lanes past the end); those of other kinds are not used
   const int cc = c < G.ncell ? c : G.ncell - 1;
@@ -696,14 +699,16 @@ __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict
 #pragma unroll
   for (int q = 0; q < K; ++q) s[q] = 0.0;
   const double* pp = part + (size_t)cc * P.nch * K;
-  for (int ch = j; ch < P.nch; ch += 4)
+  for (int ch = j; ch < P.nch; ch += CPT)
 #pragma unroll
     for (int q = 0; q < K; ++q) s[q] += pp[K * ch + q];
   const bool live = kd == KIND_REGULAR || kd == KIND_IRREGULAR;
+  if (CPT == 4) {
 #pragma unroll
-  for (int q = 0; q < K; ++q) {
-    s[q] += dpp_d<kSwap1>(s[q]);
-    s[q] += dpp_d<kSwap2>(s[q]);
+    for (int q = 0; q < K; ++q) {
+      s[q] += dpp_d<kSwap1>(s[q]);
+      s[q] += dpp_d<kSwap2>(s[q]);
+    }
   }
   double ms = 0.0;
   if (live) {
@@ -722,21 +727,27 @@ __global__ void __launch_bounds__(256) k_mom3d(Geo3D G, const double* __restrict
     const double r0 = x[0] / pow(2.0 * M_PI * x[4], 1.5);
     const double r5 = P.tau_coef > 0.0 ? P.dt * (P.mode == 1 ? rho : x[0]) / P.tau_coef : 0.0;
     double* mo = mom + 8 * (size_t)c;
-    mo[j] = j == 0 ? r0 : (j == 1 ? x[1] : (j == 2 ? x[2] : x[3]));
-    if (j < 3 && (j != 1 || P.mode != 2)) mo[4 + j] = j == 0 ? 0.5 / x[4] : (j == 1 ? r5 : rho);
+#pragma unroll
+    for (int sl = j; sl < 4; sl += CPT) mo[sl] = sl == 0 ? r0 : (sl == 1 ? x[1] : (sl == 2 ? x[2] : x[3]));
+#pragma unroll
+    for (int sl = j; sl < 3; sl += CPT)
+      if (sl != 1 || P.mode != 2) mo[4 + sl] = sl == 0 ? 0.5 / x[4] : (sl == 1 ? r5 : rho);
     if (SK) {
-      // heat flux component d = j (lanes 0-2) from the row d of S2
+      // heat flux component d from the row d of S2
       const double w = P.w, u2 = ux * ux + uy * uy + uz * uz;
       const double tr = s[5] * w + s[8] * w + s[10] * w;
       const double a = P.sk_coef / (x[0] * x[4] * x[4]);
-      const double r0x = j == 0 ? s[5] : (j == 1 ? s[6] : s[7]);
-      const double r1x = j == 0 ? s[6] : (j == 1 ? s[8] : s[9]);
-      const double r2x = j == 0 ? s[7] : (j == 1 ? s[9] : s[10]);
-      const double s3 = j == 0 ? s[11] : (j == 1 ? s[12] : s[13]);
-      const double ud = j == 0 ? ux : (j == 1 ? uy : uz);
-      const double S2u = (r0x * w) * ux + (r1x * w) * uy + (r2x * w) * uz;
-      const double qd = 0.5 * (s3 * w - 2.0 * S2u - ud * tr + 2.0 * rho * u2 * ud);
-      if (j < 3) heat[3 * (size_t)c + j] = a * qd;
+#pragma unroll
+      for (int d = j; d < 3; d += CPT) {
+        const double r0x = d == 0 ? s[5] : (d == 1 ? s[6] : s[7]);
+        const double r1x = d == 0 ? s[6] : (d == 1 ? s[8] : s[9]);
+        const double r2x = d == 0 ? s[7] : (d == 1 ? s[9] : s[10]);
+        const double s3 = d == 0 ? s[11] : (d == 1 ? s[12] : s[13]);
+        const double ud = d == 0 ? ux : (d == 1 ? uy : uz);
+        const double S2u = (r0x * w) * ux + (r1x * w) * uy + (r2x * w) * uz;
+        const double qd = 0.5 * (s3 * w - 2.0 * S2u - ud * tr + 2.0 * rho * u2 * ud);
+        heat[3 * (size_t)c + d] = a * qd;
+      }
     }
     if (j == 0) ms = (kd == KIND_REGULAR ? P.vol : G.vcv[c]) * rho;
   }
@@ -1138,7 +1149,11 @@ double tau_coef(const cc_ctx* ctx) {
 
 double weight3(const cc_ctx* ctx) { return ctx->dv * ctx->dv * ctx->dv; }
 
-int mom_blocks(const cc_ctx* ctx) { return (ctx->ncell + 63) / 64; }
+// blocks of the moment pass: 64 control volumes per block (four threads
+// each), 256 with the conservative triplet (one thread each)
+int mom_blocks(const cc_ctx* ctx) {
+  return ctx->cfg.maxwellian == CC_MAXW_CONSERVATIVE ? (ctx->ncell + 255) / 256 : (ctx->ncell + 63) / 64;
+}
 
 hipError_t run_mom3d(cc_ctx* ctx, int mode = 0) {
   Mom3Params P;
