@@ -452,10 +452,12 @@ def main():
     torch.cuda.empty_cache()
     if args.workload == "cyl512" and not args.no_extra:
         # the other full-size workloads, timed in the same run: 3D sphere,
-        # moving ellipse (geometry rebuilt every step), and the batch
+        # moving ellipse (geometry rebuilt every step), the fixed sphere on
+        # the octree, and the batch
         extra = {}
         for name, steps, warmup in (("sphere128", args.extra_steps, 3),
-                                    ("ellipse256", 2 * args.extra_steps, 5)):
+                                    ("ellipse256", 2 * args.extra_steps, 5),
+                                    ("sphere_amr", 2 * args.extra_steps, 5)):
             s2, line = measure(workload(name), name, steps, warmup, args)
             s2.close()
             del s2
