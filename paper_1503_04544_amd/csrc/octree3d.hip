@@ -823,7 +823,7 @@ __global__ void __launch_bounds__(256) k_amr_step(AmrArgs A) {
             for (int r = 0; r < RC; ++r) {
               const int p = (pass * RC + r) * NT + lv;
               const double c = sg * vnodeA(A.vmin, A.dv, comp(p));   // outward normal velocity
-              const double fn = c < 0.0 && p < NV ? nrow[p] : 0.0;
+              const double fn = nrow[p < NV ? p : 0];   // no per-lane condition on the load
               acc[r] += area * (fmax(c, 0.0) * fo[r] + fmin(c, 0.0) * fn);
             }
           };
